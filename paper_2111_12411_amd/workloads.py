@@ -1,0 +1,96 @@
+"""Seeded synthetic workloads (particle initial conditions).
+
+This module draws inputs only; it holds none of the method's arithmetic, so both
+the oracle tests and the GPU path can be fed from it.  Shapes follow the beam and
+plasma set-ups of the paper's results section (beam drift of order 0.1-0.2 c,
+beam radius about 0.4 of the cavity radius) on a cube of side L with PEC walls.
+
+Every draw uses numpy's PCG64 with seed 1000*config + 7 unless a seed is given.
+"""
+import numpy as np
+
+C_LIGHT = 299792458.0
+MU0 = 1.25663706212e-6
+EPS0 = 1.0 / (MU0 * C_LIGHT ** 2)
+Q_E = 1.602176634e-19
+M_E = 9.1093837015e-31
+
+# (mesh N, order, particles, kind, steps, dt / dt_cfl, precision)
+CONFIGS = {
+    1: dict(N=4, order=1, n=1000, kind="thermal", vth=0.01, steps=100, cfl=5.0, precision="fp64"),
+    2: dict(N=20, order=2, n=1_000_000, kind="beam", vth=0.005, drift=0.1, steps=200, cfl=10.0, precision="fp64"),
+    3: dict(N=40, order=2, n=16_000_000, kind="oscillation", vth=0.02, steps=500, cfl=10.0, precision="mixed"),
+    5: dict(N=56, order=2, n=64_000_000, kind="two_stream", vth=0.01, drift=0.2, steps=1000, cfl=10.0,
+            precision="mixed"),
+}
+
+_EDGE = 1e-9  # keep initial positions off the walls
+
+
+def _clip(x):
+    return np.clip(x, _EDGE, 1.0 - _EDGE)
+
+
+def particles(kind, n, seed, L=1.0, vth=0.01, drift=0.1):
+    """Positions (n,3) and velocities (n,3) in SI units."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = C_LIGHT
+    if kind == "thermal":
+        pos = _clip(rng.random((n, 3)))
+        vel = rng.normal(0.0, vth * c, (n, 3))
+    elif kind == "beam":
+        pos = np.empty((n, 3))
+        for ax in (0, 1):
+            v = rng.normal(0.5, 0.15, n)
+            bad = (v <= 0.0) | (v >= 1.0)
+            while bad.any():
+                v[bad] = rng.normal(0.5, 0.15, bad.sum())
+                bad = (v <= 0.0) | (v >= 1.0)
+            pos[:, ax] = v
+        pos[:, 2] = rng.random(n)
+        pos = _clip(pos)
+        vel = rng.normal(0.0, vth * c, (n, 3))
+        vel[:, 2] += drift * c
+    elif kind == "oscillation":
+        # density proportional to 1 + 0.01 sin(2 pi x): invert the CDF by Newton
+        u = rng.random(n)
+        x = u.copy()
+        amp = 0.01
+        for _ in range(30):
+            F = x + amp * (1.0 - np.cos(2 * np.pi * x)) / (2 * np.pi) - u
+            dF = 1.0 + amp * np.sin(2 * np.pi * x)
+            x = x - F / dF
+        pos = _clip(np.stack([x, rng.random(n), rng.random(n)], axis=1))
+        vel = rng.normal(0.0, vth * c, (n, 3))
+    elif kind == "two_stream":
+        half = n // 2
+        pos = rng.random((n, 3))
+        pos[:half, 0] *= 0.5
+        pos[half:, 0] = 0.5 + 0.5 * pos[half:, 0]
+        pos = _clip(pos)
+        vel = rng.normal(0.0, vth * c, (n, 3))
+        vel[:half, 2] += drift * c
+        vel[half:, 2] -= drift * c
+    else:
+        raise ValueError(kind)
+    return pos * L, vel
+
+
+def plasma_weight(n, dt, L=1.0, omega_dt=0.1):
+    """Macro-particle weight so that the electron plasma frequency at the mean
+    density satisfies omega_p dt = omega_dt (omega_p^2 = n_e e^2 / (eps0 m_e))."""
+    vol = L ** 3
+    return (omega_dt / dt) ** 2 * EPS0 * M_E * vol / (n * Q_E ** 2)
+
+
+def config_particles(cfg_id, n=None, seed=None, L=1.0):
+    cfg = CONFIGS[cfg_id]
+    n = cfg["n"] if n is None else n
+    seed = 1000 * cfg_id + 7 if seed is None else seed
+    return particles(cfg["kind"], n, seed, L=L, vth=cfg["vth"], drift=cfg.get("drift", 0.0))
+
+
+def random_fields(n1, n2, seed, e_scale=1.0e3, b_scale=1.0e-5):
+    """Random field coefficient vectors (for gather/push parity at full size)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(0.0, e_scale, n1), rng.normal(0.0, b_scale, n2)
