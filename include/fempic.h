@@ -1,0 +1,229 @@
+/*
+ * fempic.h - C ABI of the MI355X (gfx950) higher-order charge-conserving
+ * electromagnetic finite-element particle-in-cell hot path.
+ *
+ * Method: Crawford, Ramachandran, O'Connor, Luginsland, Shanker, "Higher Order
+ * Charge Conserving Electromagnetic Finite Element Particle in Cell Method"
+ * (arXiv 2111.12411).  Section references below are to that paper.
+ *
+ * Conventions for every function:
+ *   - returns FEMPIC_OK (0) or a negative fempic status;
+ *   - no C++ exception crosses the boundary; the message of the last failure on
+ *     the calling thread is returned by fempic_last_error();
+ *   - every pointer argument is a HOST pointer; input arrays are copied before
+ *     the call returns and are never retained;
+ *   - output arrays are caller-owned with explicit lengths (FEMPIC_EINVAL if a
+ *     length is too short); out-parameters are written only on FEMPIC_OK;
+ *   - handles are opaque, owned by the caller, released by the matching
+ *     *_destroy; destroying NULL is a no-op;
+ *   - device-side failures (crossing cap, solver failure, HIP errors) are sticky
+ *     for a run and are reported by the next call that synchronises it.
+ * Units are SI.  Fields are E in V/m and B in T; the W1 coefficients e_i have
+ * units V and the W2 coefficients b_l units Wb.
+ */
+#ifndef FEMPIC_H
+#define FEMPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define FEMPIC_OK 0
+#define FEMPIC_EINVAL (-1)   /* bad argument */
+#define FEMPIC_ENOMEM (-2)   /* host or device allocation failed / over budget */
+#define FEMPIC_EMESH (-3)    /* degenerate or non-manifold mesh */
+#define FEMPIC_EOUTSIDE (-4) /* a particle lies outside the mesh */
+#define FEMPIC_ECROSS (-5)   /* more than 64 tet crossings in one step */
+#define FEMPIC_ESOLVE (-6)   /* linear solver did not reach its tolerance */
+#define FEMPIC_EDEVICE (-7)  /* HIP runtime error */
+#define FEMPIC_EAGAIN (-8)   /* poll: result not ready */
+#define FEMPIC_EBUSY (-9)    /* server: no capacity / run busy */
+
+#define FEMPIC_FP64 0  /* every step of the path in FP64 */
+#define FEMPIC_MIXED 1 /* FP32 gather/push and FP32 inner solve; FP64 positions,
+                          tracking, deposit, residuals and refinement */
+
+#define FEMPIC_REFLECT 0 /* particles reflect specularly at PEC walls */
+
+typedef struct fempic_mesh_s *fempic_mesh;
+typedef struct fempic_run_s *fempic_run;
+typedef struct fempic_server_s *fempic_server;
+
+/* Text of the last failure on this thread ("" if none). */
+const char *fempic_last_error(void);
+
+/* ------------------------------------------------------------------ mesh
+ * Tetrahedral complex {nodes, edges, faces, tets} (Sec. III-A).  Every boundary
+ * face is a PEC wall: n x E = 0 (Sec. II, Dirichlet condition).  `order` is the
+ * basis order k of the Appendix (1 = classic Whitney, 2 = second order).
+ * Field DoFs (Sec. III-A, Appendix): E in the order-k edge (W1) space,
+ * B in the order-k face (W2) space; charge is measured with the order-k nodal
+ * (W0) functions.
+ *
+ * fempic_mesh_create: xyz is [n_vert][3] doubles; tet4 is [n_tet][4] vertex ids
+ *   (any order; they are sorted internally).  EMESH if a tet has zero volume, a
+ *   face is shared by more than two tets, or an id is out of range.
+ * fempic_mesh_create_cube: the N^3 Kuhn-split cube [0,L]^3, 6 N^3 tets
+ *   (tet 6h+p of hex h = i + N(j + N l) follows axis permutation p in
+ *   lexicographic order).  1 <= N <= 1024.
+ *
+ * DoF numbering used by every exported vector (natural order):
+ *   edges / faces are sorted vertex tuples numbered lexicographically;
+ *   W1 k=1: edge id.  k=2: 2*edge + {0: (3 l_lo - 1) W, 1: (3 l_hi - 1) W},
+ *           2*E + 2*face + {0: 3 l_c W_ab, 1: 3 l_b W_ac};
+ *   W2 k=1: face id.  k=2: 3*face + x -> (4 l_x - 1) W_abc (x = a,b,c),
+ *           3*F + 3*tet + f -> 4 l_d W_f (local faces f = 0,1,2);
+ *   W0 k=1: vertex id.  k=2: vertex id, then n_vert + edge (2 l_a l_b).
+ */
+int32_t fempic_mesh_create(const double *xyz, int64_t n_vert, const int64_t *tet4, int64_t n_tet,
+                           int32_t order, fempic_mesh *out);
+int32_t fempic_mesh_create_cube(int32_t N, double L, int32_t order, fempic_mesh *out);
+int32_t fempic_mesh_destroy(fempic_mesh mesh);
+
+typedef struct {
+    int64_t n_vert, n_edge, n_face, n_tet;
+    int64_t n1, n1_int; /* W1 DoFs: all / off the PEC walls (the unknowns)  */
+    int64_t n2;         /* W2 DoFs                                           */
+    int64_t n0, n0_int; /* W0 DoFs: all / interior (Gauss-law check rows)    */
+    int32_t order, n1_loc, n2_loc, n0_loc;
+    /* Explicit (leapfrog) time-step limit bound 2/sqrt(max_T lmax(M1_T^-1 S_T)),
+       S_T the element curl-curl matrix; the implicit scheme has no such limit. */
+    double dt_cfl;
+} fempic_mesh_info_t;
+int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out);
+
+/* ------------------------------------------------------------------- run
+ * A run owns the device state of one simulation on the current HIP device:
+ * e, b, accumulated current moments, particles, operators, workspace.
+ * The field update is Newmark-beta with gamma = 1/2, beta = 1/4 (Sec. III-B);
+ * other values are rejected with EINVAL.  `hip_stream` may be NULL (the run
+ * creates its own default-priority stream).  pcg_rtol is the relative residual
+ * of the field solve (FP64); pcg_maxit caps its iterations (ESOLVE beyond).
+ * spill_slots sizes the per-particle buffer for path segments that leave the
+ * particle's tet (0 = default 4); a step that needs more fails with ECROSS.
+ */
+typedef struct {
+    int32_t precision;   /* FEMPIC_FP64 or FEMPIC_MIXED */
+    double dt;           /* time step [s] */
+    double gamma, beta;  /* must be 0.5, 0.25 */
+    double pcg_rtol;     /* e.g. 1e-14 */
+    int32_t pcg_maxit;   /* e.g. 5000 */
+    int32_t particle_bc; /* FEMPIC_REFLECT */
+    int32_t spill_slots; /* 0 = default */
+} fempic_params;
+
+int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out);
+int32_t fempic_run_destroy(fempic_run run);
+
+/* Load n particles of one species (charge q [C], mass m [kg], macro weight w):
+ * pos, vel are [n][3].  Locates every particle (EOUTSIDE if one is outside),
+ * and starts the 4th-order Adams-Bashforth history from the current fields:
+ * a^{-j} = a^0, v^{-j} = v^0 - j dt a^0 (j = 1..3).  Records the nodal charge
+ * rho~^0 as the reference of the Gauss-law check.  Replaces earlier particles. */
+int32_t fempic_particles_load(fempic_run run, const double *pos, const double *vel, int64_t n, double q, double m,
+                              double w);
+
+/* Advance n_steps PIC steps (Sec. III, PIC cycle; Sec. III-B), asynchronously
+ * on the run's stream.  Per step: sort particles by tet; gather E, B at r^n;
+ * AB4 push along the quartic path; track across tets (PEC walls reflect);
+ * deposit g^{n+1} - g^n with the exact path integral of the W1 basis; solve
+ * A (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - (g^{n+1} - g^n),
+ * A = *eps + dt^2/4 K^T *nu K, by Jacobi-PCG; b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}). */
+int32_t fempic_step(fempic_run run, int32_t n_steps);
+
+/* Wait for the run's queued work; reports sticky device failures. */
+int32_t fempic_sync(fempic_run run);
+
+/* Gauss's law check (Sec. II, Gauss laws; Sec. IV-D): on the interior nodal DoFs,
+ *   out[0] = R_G = |G^T *eps e + (rho~^n - rho~^0)| / |rho~^n - rho~^0|,
+ *   out[1] = R_C = |G^T g - (rho~^n - rho~^0)| / ...  (deposit only),
+ *   out[2] = R_S = |G^T (*eps e + g)| / ...          (solve only),
+ * with rho~_j = q w sum_p W0_j(r_p), g the accumulated current moments and G
+ * the gradient matrix (grad W0_j = sum_i G_ij W1_i).  Synchronises. */
+int32_t fempic_gauss_residual(fempic_run run, double out[3]);
+
+/* Copy fields out / in (natural numbering; e has n1 entries, b has n2).
+ * fields_set zeroes e on the PEC walls. */
+int32_t fempic_fields_get(fempic_run run, double *e, int64_t ne, double *b, int64_t nb);
+int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const double *b, int64_t nb);
+
+/* Current moments deposited by the last step, g^{n+1} - g^n (natural numbering,
+ * n1 entries; zero on the walls). */
+int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n);
+
+/* Particle state in load order: pos, vel [n][3]; tet [n] (may be NULL). */
+int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *tet, int64_t n);
+
+/* Full AB4 history in load order: vh, ah are [n][3][3] = v^{n-1..n-3}, a^{n-1..n-3}. */
+int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
+
+/* Per-run statistics of the last fempic_step call. */
+typedef struct {
+    int64_t steps;            /* steps taken by this run */
+    int64_t n_particles;
+    double particle_ms;       /* last call: device time of sort + particle + deposit reduction, ms */
+    double particle_kernel_ms;/* last call: device time of the particle kernel alone, ms */
+    double field_ms;          /* last call: device time of the field update, ms */
+    int32_t pcg_iters;        /* last step's PCG iterations (inner iterations in mixed mode) */
+    double pcg_relres;        /* last step's final FP64 relative residual */
+    int64_t crossings;        /* last step: face crossings (all particles) */
+    int64_t reflections;      /* last step: wall reflections */
+    int64_t spills;           /* last step: segments outside the particle's tet */
+} fempic_stats_t;
+int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
+
+/* Device bytes a run of this size needs (mesh operators + particles + workspace). */
+int32_t fempic_footprint(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes);
+
+/* ----------------------------------------------------------- serving
+ * Continuous batching of independent runs on one GPU.  A server owns a worker
+ * thread.  Jobs are admitted in arrival order when their device footprint fits
+ * the HBM budget and a slot is free.  Steps of resident runs interleave on
+ * separate streams, and a finished run frees its memory for the next job.
+ * fempic_submit copies the job's inputs and returns a ticket at once
+ * (ENOMEM if the job could never fit the budget).  fempic_poll returns EAGAIN
+ * until the job is done, then fills *out; result arrays stay owned by the server
+ * until fempic_result_release.
+ */
+typedef struct {
+    size_t hbm_budget; /* bytes of device memory the server may use */
+    int32_t max_slots; /* runs resident at once */
+} fempic_server_params;
+
+typedef struct {
+    int32_t N;          /* Kuhn cube N^3 */
+    double L;
+    int32_t order;
+    fempic_params params;
+    const double *pos, *vel; /* [n][3] */
+    int64_t n;
+    double q, m, w;
+    int32_t n_steps;
+} fempic_job;
+
+typedef struct {
+    int32_t status;       /* job status (FEMPIC_OK or the failure) */
+    int64_t n1, n2, n;    /* lengths of e, b and particles */
+    const double *e, *b;  /* final fields (natural numbering) */
+    const double *pos, *vel;
+    double gauss[3];      /* R_G, R_C, R_S at the end */
+    double queue_ms;      /* submit -> admission */
+    double run_ms;        /* admission -> done */
+    const double *step_done_ms; /* [n_steps] completion time of each step, ms since admission */
+    int32_t n_steps;
+} fempic_job_result;
+
+int32_t fempic_server_create(const fempic_server_params *params, fempic_server *out);
+int32_t fempic_server_destroy(fempic_server server);
+int32_t fempic_submit(fempic_server server, const fempic_job *job, int64_t *ticket);
+int32_t fempic_poll(fempic_server server, int64_t ticket, fempic_job_result *out);
+int32_t fempic_result_release(fempic_server server, int64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEMPIC_H */

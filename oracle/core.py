@@ -107,16 +107,18 @@ def cfl_dt(m, ops):
 class OracleRun:
     """Whole PIC loop in FP64: C particle loop + scipy sparse direct field solve."""
 
-    def __init__(self, m, dt, ops=None):
+    def __init__(self, m, dt, ops=None, particles_only=False):
+        """particles_only: skip the field operators (particle steps with given fields)."""
         self.m = m
         self.k = m.order
         self.dt = dt
-        self.ops = ops if ops is not None else assemble(m)
-        o = self.ops
-        i1 = o.int1
-        self.Ki = o.K[:, i1].tocsr()
-        self.A = (o.star_eps[i1][:, i1] + (dt * dt / 4.0) * (self.Ki.T @ o.star_nu @ self.Ki)).tocsc()
         self.lu = None
+        if not particles_only:
+            self.ops = ops if ops is not None else assemble(m)
+            o = self.ops
+            i1 = o.int1
+            self.Ki = o.K[:, i1].tocsr()
+            self.A = (o.star_eps[i1][:, i1] + (dt * dt / 4.0) * (self.Ki.T @ o.star_nu @ self.Ki)).tocsc()
         self.tables = basis.c_tables(self.k)
         self.gl = basis.gauss_legendre01(2 * self.k + 2)
         self.cm = cloop.CMesh(m, self.tables, self.gl)

@@ -182,19 +182,13 @@ def locate_kuhn(m, pos):
     """Point location on a Kuhn cube: the hex from floor(r N / L) (clamped), then
     among its 6 tets the one with the largest min_m lambda_m (ties: smallest id)."""
     N, L = m.N, m.L
-    pos = np.atleast_2d(pos)
+    pos = np.atleast_2d(np.asarray(pos, dtype=np.float64))
     idx = np.clip(np.floor(pos * N / L).astype(np.int64), 0, N - 1)
     h = idx[:, 0] + N * (idx[:, 1] + N * idx[:, 2])
-    out = np.empty(len(pos), dtype=np.int64)
-    for p in range(len(pos)):
-        best, bt = -np.inf, -1
-        for t in range(6 * h[p], 6 * h[p] + 6):
-            lam = m.aff[t] + m.grad[t] @ pos[p]
-            mn = lam.min()
-            if mn > best:
-                best, bt = mn, t
-        out[p] = bt
-    return out
+    cand = 6 * h[:, None] + np.arange(6)[None, :]  # (P,6), ascending ids
+    lam = m.aff[cand] + np.einsum("pqmk,pk->pqm", m.grad[cand], pos)
+    mn = lam.min(axis=2)
+    return cand[np.arange(len(pos)), np.argmax(mn, axis=1)]  # argmax: first (smallest id) on ties
 
 
 def locate_brute(m, pos):

@@ -1,0 +1,102 @@
+// Internal declarations of the fempic library (host side).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+#include <stdexcept>
+
+#include "../../include/fempic.h"
+
+namespace fempic {
+
+constexpr double C_LIGHT = 299792458.0;
+constexpr double MU0 = 1.25663706212e-6;
+constexpr double EPS0 = 1.0 / (MU0 * C_LIGHT * C_LIGHT);
+
+struct Error : std::runtime_error {
+    int32_t code;
+    Error(int32_t c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+// Local entity tables of a tet with sorted vertices 0<1<2<3.
+extern const int LOC_EDGE[6][2];  // (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
+extern const int LOC_FACE[4][3];  // (0,1,2),(0,1,3),(0,2,3),(1,2,3); face f is opposite vertex 3-f
+
+// Reference-element description of the order-k bases (Appendix).
+// W1_i = (qc + qs * l_qv) (l_a grad l_b - l_b grad l_a)
+struct W1Fn { int a, b, qv; double qs, qc; };
+// W2_l = (qc + qs * l_qv) * 2 (l_a gb x gc + l_b gc x ga + l_c ga x gb)
+struct W2Fn { int a, b, c, qv; double qs, qc; };
+// W0_j = c1 * l_a * (l_b or (cs*l_a + cc))  -- see refelem.cpp
+struct W0Fn { int a, b; double c1, cs, cc; };
+
+struct RefElem {
+    int order;
+    int n0, n1, n2;
+    std::vector<W1Fn> w1;
+    std::vector<W2Fn> w2;
+    std::vector<W0Fn> w0;
+    std::vector<double> G;   // [n1][n0]  grad W0_j = sum_i G[i][j] W1_i
+    std::vector<double> K;   // [n2][n1]  curl W1_j = sum_l K[l][j] W2_l
+    std::vector<double> C1;  // [n1][n1][4][4] (1/6V) int phi_i^m phi_j^n
+    std::vector<double> C2;  // [n2][n2][6][6]
+    std::vector<double> glx, glw;  // Gauss-Legendre on [0,1], 2k+2 points
+};
+const RefElem &ref_elem(int order);
+
+struct HostMesh {
+    int order = 1;
+    bool is_cube = false;
+    int cube_N = 0;
+    double cube_L = 1.0;
+    int64_t nv = 0, nt = 0, ne = 0, nf = 0;
+    std::vector<double> xyz;       // [nv][3]
+    std::vector<int32_t> tets;     // [nt][4] sorted
+    std::vector<int32_t> tet_edge; // [nt][6]
+    std::vector<int32_t> tet_face; // [nt][4]
+    std::vector<int32_t> nbr;      // [nt][4] across face opposite vertex m, -1 wall
+    std::vector<double> geo;       // [nt][16]: m = 0..3: a_m, grad_m (x,y,z)
+    std::vector<double> vol;       // [nt]
+    std::vector<uint8_t> bedge, bface, bvert;
+    // DoFs: natural numbering (documented in fempic.h) and internal numbering
+    // (DoFs off the walls first, natural order kept within each group).
+    int n1l = 0, n2l = 0, n0l = 0;
+    int64_t N1 = 0, N2 = 0, N0 = 0, N1_int = 0, N0_int = 0;
+    std::vector<int64_t> nat2int1, int2nat1, nat2int0, int2nat0;
+    std::vector<int32_t> map1, map2, map0;  // [nt][n*l] internal ids
+    double dt_cfl = 0.0;
+};
+
+HostMesh *build_mesh(const double *xyz, int64_t nv, const int64_t *tet4, int64_t nt, int order, bool cube = false);
+HostMesh *build_cube(int N, double L, int order);
+double cfl_bound(const HostMesh &m);
+
+// Element matrices of one tet: M1 (n1 x n1, without eps0), M2 (n2 x n2, without 1/mu0)
+void element_mass(const HostMesh &m, int64_t t, double *M1, double *M2);
+
+struct CSR {
+    int64_t rows = 0, cols = 0;
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)idx.size(); }
+};
+
+struct Operators {
+    CSR A;      // *eps + dt^2/4 K^T *nu K   (N1_int x N1_int)
+    CSR Meps;   // *eps                      (N1_int x N1_int)
+    CSR Ct;     // K^T *nu                   (N1_int x N2)
+    CSR K;      // curl                      (N2 x N1_int)
+    CSR Gt;     // G^T                       (N0_int x N1_int)
+    std::vector<double> Adiag_inv;
+    // deposit scatter: for interior W1 DoF j, the (tet*n1l + local) slots in tet order
+    std::vector<int64_t> inc_ptr;
+    std::vector<int32_t> inc_idx;
+    // nodal scatter for rho~: interior W0 DoF j -> (tet*n0l + local)
+    std::vector<int64_t> inc0_ptr;
+    std::vector<int32_t> inc0_idx;
+};
+
+void assemble(const HostMesh &m, double dt, Operators &ops);
+
+}  // namespace fempic

@@ -1,0 +1,128 @@
+// Launch interface of the fempic HIP kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <cstdint>
+
+namespace fempic {
+
+struct GLRule {
+    double x[8], w[8];  // Gauss-Legendre nodes / weights on [0,1]
+};
+
+struct DevMesh {
+    int32_t nt;
+    const double *geo;   // [nt][16] (a_m, grad_m) m = 0..3
+    const int32_t *nbr;  // [nt][4]
+    const int32_t *map1; // [nt][n1l] internal W1 ids (wall DoFs >= N1_int hold zero)
+    const int32_t *map2; // [nt][n2l]
+    const int32_t *map0; // [nt][n0l]
+    // Kuhn cube locate
+    int32_t cube_N;
+    double cube_L;
+};
+
+// Particle state, structure of arrays.  Positions are FP64 in both modes; the
+// velocity and the AB4 history are R (double, or float in mixed mode).
+struct DevParticles {
+    double *x;     // [3][cap]
+    void *v;       // [3][cap]   R
+    void *vh;      // [9][cap]   R: v^{n-1}, v^{n-2}, v^{n-3}
+    void *ah;      // [9][cap]   R: a^{n-1}, a^{n-2}, a^{n-3}
+    int32_t *tet;  // [cap]
+    int32_t *id;   // [cap]  load order
+    int64_t cap;
+};
+
+struct StepParams {
+    double qm;      // q / m
+    double qw;      // q * w
+    double dt;
+    int32_t tpw;    // tets per workgroup in the particle kernel
+};
+
+// device error flags (bit set)
+enum : int32_t { ERR_CROSS = 1, ERR_POOL = 2, ERR_OUTSIDE = 4, ERR_NAN = 8 };
+
+struct SpillPool {
+    double *val;     // [cap][n1l]
+    int32_t *tet;    // [cap]
+    int64_t *tag;    // [cap]   (sorted particle index << 6) | segment index
+    int32_t *count;  // [1] records written (atomic)
+    int32_t *pcount; // [np] spills of each sorted particle
+    int64_t cap;
+};
+
+struct Counters {  // device int64 [4]: crossings, reflections, spills, error bits
+    unsigned long long *c;
+};
+
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, const double *x, int32_t *tet, int32_t *err, hipStream_t s);
+hipError_t launch_startup(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
+                          const float *b32, DevParticles p, int64_t n, double qm, double dt, hipStream_t s);
+
+// stable LSD radix sort of (key, val) uint32 pairs on the low `bits` bits of key;
+// in/out buffers alternate; returns the buffer index (0 or 1) that holds the result.
+struct SortBuffers {
+    uint32_t *key[2];
+    uint32_t *val[2];
+    uint32_t *hist;   // [256 * tiles]
+    uint32_t *scan_tmp;  // scratch for the scan
+    int64_t cap;
+};
+int64_t sort_hist_entries(int64_t n);
+int64_t scan_tmp_entries(int64_t n);
+hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s);
+hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s);
+hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s);
+// bucket offsets off[t] = first index with key >= t, for t in [0, nt]
+hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s);
+// exclusive scan of uint32 (in place allowed), total into *total (device)
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total, hipStream_t s);
+
+hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
+                           const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
+                           DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
+                           Counters cnt, hipStream_t s);
+hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
+                                uint32_t *val, hipStream_t s);
+hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,
+                               const double *recval, double *P, hipStream_t s);
+hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
+                          hipStream_t s);
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,
+                          const int32_t *ptet, int64_t cap, double qw, double *Pr, hipStream_t s);
+
+// linear algebra (FP64 unless noted)
+struct DevCSR {
+    int64_t rows, cols, nnz;
+    const int64_t *ptr;
+    const int32_t *idx;
+    const double *val;
+    const float *val32;  // optional FP32 copy
+    int lanes;           // lanes per row in the SpMV
+};
+hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, double beta, const double *z,
+                hipStream_t s);  // y = alpha A x + beta z (z may alias y or be null when beta == 0)
+hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s);
+hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
+
+// Jacobi-PCG pieces; scalars is a device double[16] block
+enum { SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_BB = 5 };
+hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
+                    double *partial, double *scalars, hipStream_t s);
+hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
+                    const double *dinv, double *partial, double *scalars, hipStream_t s);
+// FP32 inner PCG (mixed mode); vectors float, scalars double
+hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
+                      double *partial, double *scalars, hipStream_t s);
+hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
+                      double *partial, double *scalars, hipStream_t s);
+hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s);
+hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStream_t s);
+
+// deterministic norms: out[k] = sum_i f_k(...) for the Gauss check
+hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
+                       double *partial, double *out4, hipStream_t s);
+hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s);
+
+}  // namespace fempic

@@ -1,0 +1,1420 @@
+// HIP kernels of the fempic hot path for gfx950 (CDNA4, wave64).
+//
+//  * k_locate_cube        point location on a Kuhn cube
+//  * k_startup            first gather and AB4 history start
+//  * k_rs_hist/_scatter   stable LSD radix sort of (tet, slot) pairs (the
+//                         per-step sort of particles by tet)
+//  * k_particle           gather E,B (order-k edge/face bases) + AB4 push +
+//                         quartic-path tet tracking + exact path-integral
+//                         deposit; home-tet contributions reduced in LDS in a
+//                         fixed order, other segments appended to a spill pool
+//  * k_spill_*            deterministic reduction of the spill pool per tet
+//  * k_scatter            per-tet partials -> DoF current moments (fixed order)
+//  * SpMV / PCG / norms   field update, deterministic reductions
+//
+// No floating-point atomics anywhere: every floating-point sum is taken in a
+// fixed order, so a run is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace fempic {
+
+namespace {
+
+constexpr int BLK = 256;
+
+// integral of the cubic Lagrange basis on nodes 0,-1,-2,-3 (AB4 path), s^d coefficients
+__device__ __constant__ const double LCOEF[4][5] = {
+    {0.0, 1.0, 11.0 / 12.0, 1.0 / 3.0, 1.0 / 24.0},
+    {0.0, 0.0, -3.0 / 2.0, -5.0 / 6.0, -1.0 / 8.0},
+    {0.0, 0.0, 3.0 / 4.0, 2.0 / 3.0, 1.0 / 8.0},
+    {0.0, 0.0, -1.0 / 6.0, -1.0 / 6.0, -1.0 / 24.0},
+};
+
+template <int K>
+struct Ord;
+template <>
+struct Ord<1> {
+    static constexpr int N1 = 6, N2 = 4, N0 = 4, NG = 4, TPW_MAX = 42;
+};
+template <>
+struct Ord<2> {
+    static constexpr int N1 = 20, N2 = 15, N0 = 10, NG = 6, TPW_MAX = 12;
+};
+
+// local edges (a,b) and faces (a,b,c); face f opposite vertex 3-f
+__device__ __constant__ const int EA[6] = {0, 0, 0, 1, 1, 2};
+__device__ __constant__ const int EB[6] = {1, 2, 3, 2, 3, 3};
+// per face: vertices, pair ids of (b,c), (a,c), (a,b)
+__device__ __constant__ const int FV[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+__device__ __constant__ const int FP[4][3] = {{3, 1, 0}, {4, 2, 0}, {5, 2, 1}, {5, 4, 3}};
+
+}  // namespace
+
+namespace {
+
+// ---------------------------------------------------------------- locate
+__global__ void k_locate_cube(DevMesh m, int64_t n, const double *__restrict__ x, int32_t *__restrict__ tet,
+                              int32_t *__restrict__ err)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int N = m.cube_N;
+    const double L = m.cube_L;
+    double r[3] = {x[p], x[n + p], x[2 * n + p]};
+    const double tol = 1e-12 * L;
+    int idx[3];
+    bool ok = true;
+    for (int k = 0; k < 3; k++) {
+        if (!(r[k] >= -tol && r[k] <= L + tol)) ok = false;
+        double f = ok ? floor(r[k] * N / L) : 0.0;
+        int i = (int)f;
+        idx[k] = i < 0 ? 0 : (i > N - 1 ? N - 1 : i);
+    }
+    int64_t h = idx[0] + (int64_t)N * (idx[1] + (int64_t)N * idx[2]);
+    double best = -1e300;
+    int32_t bt = (int32_t)(6 * h);
+    for (int q = 0; q < 6; q++) {
+        int64_t t = 6 * h + q;
+        const double *g = &m.geo[16 * t];
+        double mn = 1e300;
+        for (int f = 0; f < 4; f++) {
+            double l = g[4 * f] + g[4 * f + 1] * r[0] + g[4 * f + 2] * r[1] + g[4 * f + 3] * r[2];
+            mn = fmin(mn, l);
+        }
+        if (mn > best) {
+            best = mn;
+            bt = (int32_t)t;
+        }
+    }
+    tet[p] = bt;
+    if (!ok || !(best >= -1e-10)) atomicOr(err, (int)ERR_OUTSIDE);
+}
+
+// ------------------------------------------------------------- gather
+// E = sum_m cE[m] grad l_m ; B = sum_p cB[p] (grad l_a x grad l_b)_p
+template <int K, typename R>
+__device__ inline void gather_coeffs(const R *ec, const R *bc, const R lam[4], R cE[4], R cB[6])
+{
+#pragma unroll
+    for (int m = 0; m < 4; m++) cE[m] = R(0);
+#pragma unroll
+    for (int p = 0; p < 6; p++) cB[p] = R(0);
+    if constexpr (K == 1) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            R w = ec[e];
+            cE[EB[e]] += w * lam[EA[e]];
+            cE[EA[e]] -= w * lam[EB[e]];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            R s = R(2) * bc[f];
+            cB[FP[f][0]] += s * lam[FV[f][0]];
+            cB[FP[f][1]] -= s * lam[FV[f][1]];
+            cB[FP[f][2]] += s * lam[FV[f][2]];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int a = EA[e], b = EB[e];
+            R w = ec[2 * e] * (R(3) * lam[a] - R(1)) + ec[2 * e + 1] * (R(3) * lam[b] - R(1));
+            cE[b] += w * lam[a];
+            cE[a] -= w * lam[b];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            const int a = FV[f][0], b = FV[f][1], c = FV[f][2];
+            R w1 = ec[12 + 2 * f] * (R(3) * lam[c]);  // W_ab
+            cE[b] += w1 * lam[a];
+            cE[a] -= w1 * lam[b];
+            R w2 = ec[13 + 2 * f] * (R(3) * lam[b]);  // W_ac
+            cE[c] += w2 * lam[a];
+            cE[a] -= w2 * lam[c];
+            R s = bc[3 * f] * (R(4) * lam[a] - R(1)) + bc[3 * f + 1] * (R(4) * lam[b] - R(1)) +
+                  bc[3 * f + 2] * (R(4) * lam[c] - R(1));
+            if (f < 3) s += bc[12 + f] * (R(4) * lam[3 - f]);
+            s *= R(2);
+            cB[FP[f][0]] += s * lam[a];
+            cB[FP[f][1]] -= s * lam[b];
+            cB[FP[f][2]] += s * lam[c];
+        }
+    }
+}
+
+template <typename R>
+__device__ inline void cross3(const R *a, const R *b, R *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename R>
+__device__ inline void load_vec(const void *base, int64_t cap, int comp, int64_t i, R *o, int n)
+{
+    const R *b = (const R *)base;
+    for (int k = 0; k < n; k++) o[k] = b[(int64_t)(comp + k) * cap + i];
+}
+
+template <typename R>
+__device__ inline void store_vec(void *base, int64_t cap, int comp, int64_t i, const R *v, int n)
+{
+    R *b = (R *)base;
+    for (int k = 0; k < n; k++) b[(int64_t)(comp + k) * cap + i] = v[k];
+}
+
+// ---------------------------------------------------------------- startup
+template <int K, typename R>
+__global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restrict__ b, DevParticles P, int64_t n,
+                          double qm, double dt)
+{
+    using O = Ord<K>;
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t t = P.tet[p];
+    const double *g = &m.geo[16 * t];
+    double r[3] = {P.x[p], P.x[P.cap + p], P.x[2 * P.cap + p]};
+    R lam[4], gr[4][3];
+    for (int f = 0; f < 4; f++) {
+        lam[f] = (R)(g[4 * f] + g[4 * f + 1] * r[0] + g[4 * f + 2] * r[1] + g[4 * f + 3] * r[2]);
+        for (int k = 0; k < 3; k++) gr[f][k] = (R)g[4 * f + 1 + k];
+    }
+    R ec[O::N1], bc[O::N2];
+    for (int i = 0; i < O::N1; i++) ec[i] = e[m.map1[t * O::N1 + i]];
+    for (int l = 0; l < O::N2; l++) bc[l] = b[m.map2[t * O::N2 + l]];
+    R cE[4], cB[6];
+    gather_coeffs<K, R>(ec, bc, lam, cE, cB);
+    R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+    for (int f = 0; f < 4; f++)
+        for (int k = 0; k < 3; k++) E[k] += cE[f] * gr[f][k];
+    for (int q = 0; q < 6; q++) {
+        R X[3];
+        cross3(gr[EA[q]], gr[EB[q]], X);
+        for (int k = 0; k < 3; k++) B[k] += cB[q] * X[k];
+    }
+    R v[3], vxB[3], a[3];
+    load_vec<R>(P.v, P.cap, 0, p, v, 3);
+    cross3(v, B, vxB);
+    for (int k = 0; k < 3; k++) a[k] = (R)qm * (E[k] + vxB[k]);
+    R vh[9], ah[9];
+    for (int j = 1; j <= 3; j++)
+        for (int k = 0; k < 3; k++) {
+            ah[3 * (j - 1) + k] = a[k];
+            vh[3 * (j - 1) + k] = (R)((double)v[k] - j * dt * (double)a[k]);
+        }
+    store_vec<R>(P.vh, P.cap, 0, p, vh, 9);
+    store_vec<R>(P.ah, P.cap, 0, p, ah, 9);
+}
+
+// ------------------------------------------------------------ root finding
+__device__ inline double horner4(const double *q, double u)
+{
+    return fma(fma(fma(fma(q[4], u, q[3]), u, q[2]), u, q[1]), u, q[0]);
+}
+
+__device__ inline double dhorner4(const double *q, double u)
+{
+    return fma(fma(fma(4.0 * q[4], u, 3.0 * q[3]), u, 2.0 * q[2]), u, q[1]);
+}
+
+// coefficients of p(u + a)
+__device__ inline void taylor_shift(const double *p, double a, double *o)
+{
+    double c0 = p[0], c1 = p[1], c2 = p[2], c3 = p[3], c4 = p[4];
+    c3 = fma(a, c4, c3);
+    c2 = fma(a, c3, c2);
+    c1 = fma(a, c2, c1);
+    c0 = fma(a, c1, c0);
+    c3 = fma(a, c4, c3);
+    c2 = fma(a, c3, c2);
+    c1 = fma(a, c2, c1);
+    c3 = fma(a, c4, c3);
+    c2 = fma(a, c3, c2);
+    c3 = fma(a, c4, c3);
+    o[0] = c0;
+    o[1] = c1;
+    o[2] = c2;
+    o[3] = c3;
+    o[4] = c4;
+}
+
+// Bernstein coefficients on [lo, hi] of q (power basis in u)
+__device__ inline void bernstein(const double *q, double lo, double hi, double *bc)
+{
+    double d[5];
+    taylor_shift(q, lo, d);
+    const double h = hi - lo;
+    double d1 = d[1] * h, d2 = d[2] * h * h, d3 = d[3] * h * h * h, d4 = d[4] * (h * h) * (h * h);
+    bc[0] = d[0];
+    bc[1] = d[0] + 0.25 * d1;
+    bc[2] = d[0] + 0.5 * d1 + d2 / 6.0;
+    bc[3] = d[0] + 0.75 * d1 + 0.5 * d2 + 0.25 * d3;
+    bc[4] = d[0] + d1 + d2 + d3 + d4;
+}
+
+// smallest u in [0, H] with q(u) < 0 (q in power basis of u).  Dyadic
+// subdivision driven by Bernstein sign tests, then safeguarded Newton on the
+// isolated crossing.  Visits a bounded number of intervals.
+__device__ bool first_negative(const double *q, double H, double &uout)
+{
+    constexpr int MAXD = 40;
+    int d = 0;
+    int64_t idx = 0;
+    for (int guard = 0; guard < 1024; guard++) {
+        const double lo = H * ldexp((double)idx, -d);
+        const double hi = H * ldexp((double)(idx + 1), -d);
+        double bc[5];
+        bernstein(q, lo, hi, bc);
+        int first = -1;
+#pragma unroll
+        for (int i = 4; i >= 0; i--)
+            if (bc[i] != 0.0) first = i;
+        bool advance = false;
+        if (first < 0) {
+            advance = true;
+        } else if (bc[first] < 0.0) {
+            uout = lo;
+            return true;
+        } else {
+            bool any_neg = false;
+            int changes = 0;
+            double prev = bc[first];
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                if (i <= first) continue;
+                if (bc[i] < 0.0) any_neg = true;
+                if (bc[i] != 0.0) {
+                    if ((bc[i] < 0.0) != (prev < 0.0)) changes++;
+                    prev = bc[i];
+                }
+            }
+            if (!any_neg) {
+                advance = true;
+            } else if (changes == 1 && bc[4] < 0.0) {
+                // one crossing in (lo, hi): q(lo) >= 0, q(hi) < 0
+                double a = lo, b = hi;
+                double x = 0.5 * (a + b);
+                for (int it = 0; it < 80; it++) {
+                    double fx = horner4(q, x);
+                    if (fx < 0.0) b = x; else a = x;
+                    if (!(b - a > 4e-16 * fmax(1.0, fabs(b)))) break;
+                    double dfx = dhorner4(q, x);
+                    double xn = x - fx / dfx;
+                    if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+                    x = xn;
+                }
+                uout = fmin(fmax(x, a), b);
+                return true;
+            } else if (d >= MAXD) {
+                advance = true;  // tangency narrower than H 2^-40
+            }
+        }
+        if (advance) {
+            while (idx & 1) {
+                idx >>= 1;
+                d--;
+            }
+            if (d == 0) return false;
+            idx += 1;
+        } else {
+            d++;
+            idx <<= 1;
+        }
+    }
+    return false;
+}
+
+// deposit one segment: dep_i += q w int_{sa}^{sb} Q_i(l) (l_a l_b' - l_b l_a') ds
+template <int K>
+__device__ inline void deposit_segment(const double L[4][5], double sa, double sb, double qw, const GLRule &gl,
+                                       double *dep)
+{
+    using O = Ord<K>;
+    const double h = sb - sa;
+#pragma unroll
+    for (int g = 0; g < O::NG; g++) {
+        const double s = fma(h, gl.x[g], sa);
+        const double wg = qw * h * gl.w[g];
+        double lam[4], dl[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            lam[m] = horner4(L[m], s);
+            dl[m] = dhorner4(L[m], s);
+        }
+        double w[6];
+#pragma unroll
+        for (int e = 0; e < 6; e++) w[e] = wg * (lam[EA[e]] * dl[EB[e]] - lam[EB[e]] * dl[EA[e]]);
+        if constexpr (K == 1) {
+#pragma unroll
+            for (int e = 0; e < 6; e++) dep[e] += w[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                dep[2 * e] += (3.0 * lam[EA[e]] - 1.0) * w[e];
+                dep[2 * e + 1] += (3.0 * lam[EB[e]] - 1.0) * w[e];
+            }
+            // faces: (a,b,c) -> 3 l_c W_ab, 3 l_b W_ac ; edge ids of ab, ac
+            dep[12] += 3.0 * lam[2] * w[0];
+            dep[13] += 3.0 * lam[1] * w[1];
+            dep[14] += 3.0 * lam[3] * w[0];
+            dep[15] += 3.0 * lam[1] * w[2];
+            dep[16] += 3.0 * lam[3] * w[1];
+            dep[17] += 3.0 * lam[2] * w[2];
+            dep[18] += 3.0 * lam[3] * w[3];
+            dep[19] += 3.0 * lam[2] * w[4];
+        }
+    }
+}
+
+// -------------------------------------------------------------- particle
+template <int K, typename R>
+__global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict__ e, const R *__restrict__ b,
+                                                  const uint32_t *__restrict__ perm, const int32_t *__restrict__ off,
+                                                  DevParticles in, DevParticles out, int64_t np, StepParams sp,
+                                                  GLRule gl, double *__restrict__ P, SpillPool pool,
+                                                  unsigned long long *__restrict__ cnt)
+{
+    using O = Ord<K>;
+    constexpr int N1 = O::N1, N2 = O::N2, TM = O::TPW_MAX;
+    __shared__ double s_geo[TM][16];
+    __shared__ R s_X[TM][18];
+    __shared__ R s_e[TM][N1];
+    __shared__ R s_b[TM][N2];
+    __shared__ int32_t s_off[TM + 1];
+    __shared__ double s_hc[N1][BLK + 1];
+
+    const int tid = threadIdx.x;
+    const int tpw = sp.tpw;
+    const int T0 = blockIdx.x * tpw;
+    const int T1 = min(T0 + tpw, m.nt);
+    const int ntl = T1 - T0;
+    for (int k = tid; k < ntl * 16; k += BLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
+    for (int k = tid; k <= ntl; k += BLK) s_off[k] = off[T0 + k];
+    for (int k = tid; k < ntl * N1; k += BLK) {
+        int t = k / N1, i = k % N1;
+        s_e[t][i] = e[m.map1[(int64_t)(T0 + t) * N1 + i]];
+    }
+    for (int k = tid; k < ntl * N2; k += BLK) {
+        int t = k / N2, l = k % N2;
+        s_b[t][l] = b[m.map2[(int64_t)(T0 + t) * N2 + l]];
+    }
+    __syncthreads();
+    for (int k = tid; k < ntl * 6; k += BLK) {
+        int t = k / 6, q = k % 6;
+        double ga[3], gb[3], X[3];
+        for (int c = 0; c < 3; c++) {
+            ga[c] = s_geo[t][4 * EA[q] + 1 + c];
+            gb[c] = s_geo[t][4 * EB[q] + 1 + c];
+        }
+        cross3(ga, gb, X);
+        for (int c = 0; c < 3; c++) s_X[t][3 * q + c] = (R)X[c];
+    }
+    __syncthreads();
+
+    const int pbeg = s_off[0], pend = s_off[ntl];
+    const int wt = tid / N1, wc = tid % N1;
+    const bool worker = tid < ntl * N1;
+    double acc = 0.0;
+    unsigned long long ncr = 0, nrf = 0, nsp = 0;
+    int errs = 0;
+    const R dtR = (R)sp.dt;
+    const R qmR = (R)sp.qm;
+
+    for (int base = pbeg; base < pend; base += BLK) {
+#pragma unroll
+        for (int c = 0; c < N1; c++) s_hc[c][tid] = 0.0;
+        const int i = base + tid;
+        if (i < pend) {
+            const uint32_t slot = perm[i];
+            const int th = in.tet[slot];
+            const int lt = th - T0;
+            double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
+            R v[3], vh[9], ah[9];
+            load_vec<R>(in.v, in.cap, 0, slot, v, 3);
+            load_vec<R>(in.vh, in.cap, 0, slot, vh, 9);
+            load_vec<R>(in.ah, in.cap, 0, slot, ah, 9);
+            // barycentrics and fields at r^n (home tet, LDS)
+            R lam[4];
+#pragma unroll
+            for (int f = 0; f < 4; f++)
+                lam[f] = (R)(s_geo[lt][4 * f] + s_geo[lt][4 * f + 1] * r[0] + s_geo[lt][4 * f + 2] * r[1] +
+                             s_geo[lt][4 * f + 3] * r[2]);
+            R cE[4], cB[6];
+            gather_coeffs<K, R>(s_e[lt], s_b[lt], lam, cE, cB);
+            R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+#pragma unroll
+            for (int f = 0; f < 4; f++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) E[c] += cE[f] * (R)s_geo[lt][4 * f + 1 + c];
+#pragma unroll
+            for (int q = 0; q < 6; q++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) B[c] += cB[q] * s_X[lt][3 * q + c];
+            // Lorentz acceleration, AB4 velocity
+            R vxB[3], a[3], vn[3];
+            cross3(v, B, vxB);
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                a[c] = qmR * (E[c] + vxB[c]);
+                vn[c] = v[c] + dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]);
+            }
+            // quartic path r(s) = sum_d c_d s^d (FP64 in both modes)
+            double cp[5][3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                cp[0][c] = r[c];
+                const double v0 = (double)v[c], v1 = (double)vh[c], v2 = (double)vh[3 + c], v3 = (double)vh[6 + c];
+#pragma unroll
+                for (int d = 1; d < 5; d++)
+                    cp[d][c] = sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
+            }
+            // new velocity and shifted histories
+            R nvh[9] = {v[0], v[1], v[2], vh[0], vh[1], vh[2], vh[3], vh[4], vh[5]};
+            R nah[9] = {a[0], a[1], a[2], ah[0], ah[1], ah[2], ah[3], ah[4], ah[5]};
+            // ------------------------------------------------ track + deposit
+            int t = th, entry = -1, ncross = 0, nsp_i = 0;
+            double s_lo = 0.0;
+            bool reflected = false;
+            double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+            for (;;) {
+                double g[16];
+                if (t >= T0 && t < T1) {
+#pragma unroll
+                    for (int k = 0; k < 16; k++) g[k] = s_geo[t - T0][k];
+                } else {
+                    const double4 *gp = (const double4 *)&m.geo[(int64_t)t * 16];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        double4 q = gp[k];
+                        g[4 * k] = q.x;
+                        g[4 * k + 1] = q.y;
+                        g[4 * k + 2] = q.z;
+                        g[4 * k + 3] = q.w;
+                    }
+                }
+                double L[4][5];
+#pragma unroll
+                for (int f = 0; f < 4; f++) {
+#pragma unroll
+                    for (int d = 0; d < 5; d++)
+                        L[f][d] = g[4 * f + 1] * cp[d][0] + g[4 * f + 2] * cp[d][1] + g[4 * f + 3] * cp[d][2];
+                    L[f][0] += g[4 * f];
+                }
+                double s_exit = 2.0;
+                int f_exit = -1;
+                const double H = 1.0 - s_lo;
+                if (H > 0.0) {
+#pragma unroll
+                    for (int f = 0; f < 4; f++) {
+                        double q[5];
+                        taylor_shift(L[f], s_lo, q);
+                        if (f == entry) q[0] = 0.0;
+                        double u;
+                        if (first_negative(q, H, u)) {
+                            const double s = s_lo + u;
+                            if (s < s_exit) {
+                                s_exit = s;
+                                f_exit = f;
+                            }
+                        }
+                    }
+                }
+                const double s_hi = f_exit < 0 ? 1.0 : s_exit;
+                if (s_hi > s_lo) {
+                    double dep[N1];
+#pragma unroll
+                    for (int c = 0; c < N1; c++) dep[c] = 0.0;
+                    deposit_segment<K>(L, s_lo, s_hi, sp.qw, gl, dep);
+                    if (t == th) {
+#pragma unroll
+                        for (int c = 0; c < N1; c++) s_hc[c][tid] += dep[c];
+                    } else {
+                        // append to the spill pool (wave-aggregated atomic slot)
+                        const unsigned long long mask = __ballot(1);
+                        const int lane = __lane_id();
+                        const int leader = __ffsll((long long)mask) - 1;
+                        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+                        int basei = 0;
+                        if (lane == leader) basei = atomicAdd(pool.count, __popcll(mask));
+                        basei = __shfl(basei, leader);
+                        const int64_t slot_out = (int64_t)basei + rank;
+                        if (slot_out < pool.cap && nsp_i < 64) {
+                            pool.tet[slot_out] = t;
+                            pool.tag[slot_out] = ((int64_t)i << 6) | nsp_i;
+                            double *dst = &pool.val[slot_out * N1];
+#pragma unroll
+                            for (int c = 0; c < N1; c++) dst[c] = dep[c];
+                        } else {
+                            errs |= ERR_POOL;
+                        }
+                        nsp_i++;
+                    }
+                }
+                if (f_exit < 0) break;
+                if (++ncross > 64) {
+                    errs |= ERR_CROSS;
+                    break;
+                }
+                const int nb = m.nbr[(int64_t)t * 4 + f_exit];
+                if (nb >= 0) {
+                    int en = -1;
+#pragma unroll
+                    for (int f = 0; f < 4; f++)
+                        if (m.nbr[(int64_t)nb * 4 + f] == t) en = f;
+                    entry = en;
+                    t = nb;
+                } else {
+                    // PEC wall: mirror the path about the plane l_f = 0
+                    const double gx = g[4 * f_exit + 1], gy = g[4 * f_exit + 2], gz = g[4 * f_exit + 3];
+                    const double gg = gx * gx + gy * gy + gz * gz;
+#pragma unroll
+                    for (int d = 0; d < 5; d++) {
+                        double s = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2] + (d == 0 ? g[4 * f_exit] : 0.0);
+                        s = 2.0 * s / gg;
+                        cp[d][0] -= s * gx;
+                        cp[d][1] -= s * gy;
+                        cp[d][2] -= s * gz;
+                    }
+                    const double gv[3] = {gx, gy, gz};
+                    double Rn[9];
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; a2++)
+#pragma unroll
+                        for (int b2 = 0; b2 < 3; b2++) {
+                            double s = 0;
+#pragma unroll
+                            for (int k2 = 0; k2 < 3; k2++)
+                                s += ((a2 == k2 ? 1.0 : 0.0) - 2.0 * gv[a2] * gv[k2] / gg) * Rm[3 * k2 + b2];
+                            Rn[3 * a2 + b2] = s;
+                        }
+#pragma unroll
+                    for (int k2 = 0; k2 < 9; k2++) Rm[k2] = Rn[k2];
+                    reflected = true;
+                    nrf++;
+                    entry = f_exit;
+                }
+                s_lo = s_exit;
+            }
+            ncr += ncross;
+            nsp += nsp_i;
+            pool.pcount[i] = nsp_i;
+            if (reflected) {
+                auto mir = [&](R *w3) {
+                    double x0 = w3[0], x1 = w3[1], x2 = w3[2];
+                    for (int c = 0; c < 3; c++) w3[c] = (R)(Rm[3 * c] * x0 + Rm[3 * c + 1] * x1 + Rm[3 * c + 2] * x2);
+                };
+                mir(vn);
+                mir(&nvh[0]);
+                mir(&nvh[3]);
+                mir(&nvh[6]);
+                mir(&nah[0]);
+                mir(&nah[3]);
+                mir(&nah[6]);
+            }
+            double rn[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
+                rn[c] = horner4(pc, 1.0);
+                out.x[(int64_t)c * out.cap + i] = rn[c];
+            }
+            if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
+            store_vec<R>(out.v, out.cap, 0, i, vn, 3);
+            store_vec<R>(out.vh, out.cap, 0, i, nvh, 9);
+            store_vec<R>(out.ah, out.cap, 0, i, nah, 9);
+            out.tet[i] = t;
+            out.id[i] = in.id[slot];
+        }
+        __syncthreads();
+        if (worker) {
+            const int lo = max(s_off[wt], base) - base;
+            const int hi = min(s_off[wt + 1], base + BLK) - base;
+            for (int j = lo; j < hi; j++) acc += s_hc[wc][j];
+        }
+        __syncthreads();
+    }
+    if (worker) P[(int64_t)(T0 + wt) * N1 + wc] = acc;
+    // counters: wave sums, one integer atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        ncr += __shfl_xor(ncr, o);
+        nrf += __shfl_xor(nrf, o);
+        nsp += __shfl_xor(nsp, o);
+        errs |= __shfl_xor(errs, o);
+    }
+    if (__lane_id() == 0) {
+        if (ncr) atomicAdd(&cnt[0], ncr);
+        if (nrf) atomicAdd(&cnt[1], nrf);
+        if (nsp) atomicAdd(&cnt[2], nsp);
+        if (errs) atomicOr(&cnt[3], (unsigned long long)errs);
+    }
+}
+
+// ----------------------------------------------------------- radix sort
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = BLK * RS_ITEMS;
+
+__global__ __launch_bounds__(BLK) void k_rs_hist(const uint32_t *__restrict__ key, int64_t n, int shift,
+                                                 uint32_t *__restrict__ hist, int64_t ntiles)
+{
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t idx = base + r * BLK + tid;
+        if (idx < n) atomicAdd(&h[(key[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+__global__ __launch_bounds__(BLK) void k_rs_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                                                    int shift, const uint32_t *__restrict__ offs, int64_t ntiles,
+                                                    int iota)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[BLK / 64][256];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < RS_ITEMS; r++) {
+#pragma unroll
+        for (int q = 0; q < BLK / 64; q++) wcnt[q][tid] = 0;
+        __syncthreads();
+        const int64_t idx = base + r * BLK + tid;
+        const bool valid = idx < n;
+        const uint32_t k = valid ? kin[idx] : 0u;
+        const uint32_t d = (k >> shift) & 255u;
+        unsigned long long match = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const bool on = (d >> bit) & 1u;
+            const unsigned long long bb = __ballot(valid && on);
+            match &= on ? bb : ~bb;
+        }
+        const int rank = __popcll(match & lt);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + (uint32_t)rank;
+            for (int q = 0; q < w; q++) pos += wcnt[q][d];
+            kout[pos] = k;
+            vout[pos] = iota ? (uint32_t)idx : vin[idx];
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int q = 0; q < BLK / 64; q++) add += wcnt[q][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- scan
+constexpr int SC_THREADS = 1024;
+constexpr int SC_ITEMS = 4;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_w, uint32_t &total)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        const int nw = blockDim.x / 64;
+        uint32_t t = lane < nw ? s_w[lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(t, o);
+            if (lane >= o) t += y;
+        }
+        if (lane < nw) s_w[lane] = t;
+    }
+    __syncthreads();
+    const uint32_t wprefix = w > 0 ? s_w[w - 1] : 0u;
+    total = s_w[blockDim.x / 64 - 1];
+    __syncthreads();
+    return wprefix + x - v;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tile(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                          int64_t n, uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t s_w[SC_THREADS / 64];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t v[SC_ITEMS], s = 0;
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; k++) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(s, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; k++) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0 && sums) sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t *__restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+    const uint32_t add = sums[blockIdx.x];
+    for (int k = threadIdx.x; k < SC_TILE; k += blockDim.x)
+        if (base + k < n) out[base + k] += add;
+}
+
+__global__ void k_scan_total(const uint32_t *__restrict__ in, const uint32_t *__restrict__ out, int64_t n,
+                             uint32_t *__restrict__ total)
+{
+    *total = n > 0 ? out[n - 1] + in[n - 1] : 0u;
+}
+
+// ------------------------------------------------------------- offsets
+__global__ void k_offsets(const uint32_t *__restrict__ key, int64_t n, int32_t nt, int32_t *__restrict__ off)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n == 0) {
+        for (int64_t t = i; t <= nt; t += (int64_t)gridDim.x * blockDim.x) off[t] = 0;
+        return;
+    }
+    if (i >= n) return;
+    const int64_t k = key[i];
+    const int64_t kp = i == 0 ? -1 : (int64_t)key[i - 1];
+    for (int64_t t = kp + 1; t <= k; t++) off[t] = (int32_t)i;
+    if (i == n - 1)
+        for (int64_t t = k + 1; t <= nt; t++) off[t] = (int32_t)n;
+}
+
+__global__ void k_iota(uint32_t *v, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
+}
+
+__global__ void k_copy_keys(const int32_t *__restrict__ t, uint32_t *__restrict__ k, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) k[i] = (uint32_t)t[i];
+}
+
+// ------------------------------------------------------------- spills
+__global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t *__restrict__ ptag, int64_t nrec,
+                                const uint32_t *__restrict__ pos, uint32_t *__restrict__ key, uint32_t *__restrict__ val)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    const int64_t tag = ptag[r];
+    const int64_t i = tag >> 6;
+    const int j = (int)(tag & 63);
+    const uint32_t dst = pos[i] + (uint32_t)j;
+    key[dst] = (uint32_t)ptet[r];
+    val[dst] = (uint32_t)r;
+}
+
+template <int N1>
+__global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, const uint32_t *__restrict__ rec,
+                               const double *__restrict__ recval, double *__restrict__ P)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)nt * N1) return;
+    const int64_t t = g / N1;
+    const int c = (int)(g % N1);
+    const int32_t lo = soff[t], hi = soff[t + 1];
+    if (lo == hi) return;
+    double s = P[g];
+    for (int32_t k = lo; k < hi; k++) s += recval[(int64_t)rec[k] * N1 + c];
+    P[g] = s;
+}
+
+__global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx, int64_t n,
+                          const double *__restrict__ P, double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int64_t k = ptr[j]; k < ptr[j + 1]; k++) s += P[idx[k]];
+    out[j] = s;
+}
+
+// nodal charge per tet (order-k W0 values times q w), same tiling as k_particle
+template <int K>
+__global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__restrict__ perm,
+                                                 const int32_t *__restrict__ off, const double *__restrict__ x,
+                                                 int64_t cap, double qw, int tpw, double *__restrict__ Pr,
+                                                 const int32_t *__restrict__ ptet)
+{
+    using O = Ord<K>;
+    constexpr int N0 = O::N0;
+    __shared__ double s_w[N0][BLK + 1];
+    __shared__ int32_t s_off[BLK / N0 + 2];
+    const int tid = threadIdx.x;
+    const int T0 = blockIdx.x * tpw;
+    const int T1 = min(T0 + tpw, m.nt);
+    const int ntl = T1 - T0;
+    for (int k = tid; k <= ntl; k += BLK) s_off[k] = off[T0 + k];
+    __syncthreads();
+    const int pbeg = s_off[0], pend = s_off[ntl];
+    const int wt = tid / N0, wc = tid % N0;
+    const bool worker = tid < ntl * N0;
+    double acc = 0.0;
+    for (int base = pbeg; base < pend; base += BLK) {
+        const int i = base + tid;
+        if (i < pend) {
+            const uint32_t slot = perm[i];
+            const int64_t t = ptet[slot];
+            const double *g = &m.geo[16 * t];
+            const double r0 = x[slot], r1 = x[cap + slot], r2 = x[2 * cap + slot];
+            double l[4];
+            for (int f = 0; f < 4; f++) l[f] = g[4 * f] + g[4 * f + 1] * r0 + g[4 * f + 2] * r1 + g[4 * f + 3] * r2;
+            if constexpr (K == 1) {
+                for (int f = 0; f < 4; f++) s_w[f][tid] = qw * l[f];
+            } else {
+                for (int f = 0; f < 4; f++) s_w[f][tid] = qw * (l[f] * (2.0 * l[f] - 1.0));
+                for (int q = 0; q < 6; q++) s_w[4 + q][tid] = qw * (2.0 * l[EA[q]] * l[EB[q]]);
+            }
+        }
+        __syncthreads();
+        if (worker) {
+            const int lo = max(s_off[wt], base) - base;
+            const int hi = min(s_off[wt + 1], base + BLK) - base;
+            for (int j = lo; j < hi; j++) acc += s_w[wc][j];
+        }
+        __syncthreads();
+    }
+    if (worker) Pr[(int64_t)(T0 + wt) * N0 + wc] = acc;
+}
+
+// --------------------------------------------------------- linear algebra
+template <int LANES, typename T>
+__global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__restrict__ ptr,
+                                              const int32_t *__restrict__ idx, const T *__restrict__ val,
+                                              const T *__restrict__ x, T *__restrict__ y, double alpha, double beta,
+                                              const T *__restrict__ z, const T *__restrict__ dotv,
+                                              double *__restrict__ partial)
+{
+    __shared__ double s_red[BLK / LANES];
+    const int tid = threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.x * (BLK / LANES) + tid / LANES;
+    const int lane = tid % LANES;
+    double sum = 0.0;
+    if (row < rows) {
+        const int64_t e = ptr[row + 1];
+        for (int64_t k = ptr[row] + lane; k < e; k += LANES) sum += (double)val[k] * (double)x[idx[k]];
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LANES);
+    double d = 0.0;
+    if (row < rows && lane == 0) {
+        double yv = alpha * sum + (beta != 0.0 ? beta * (double)z[row] : 0.0);
+        y[row] = (T)yv;
+        if (dotv) d = (double)dotv[row] * (double)(T)yv;
+    }
+    if (partial) {
+        if (lane == 0) s_red[tid / LANES] = d;
+        __syncthreads();
+        for (int o = (BLK / LANES) / 2; o > 0; o >>= 1) {
+            if (tid < o) s_red[tid] += s_red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) partial[blockIdx.x] = s_red[0];
+    }
+}
+
+// fixed-order sum of n partials (one block of 1024 threads), k values interleaved
+__global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ partial, int64_t n, int k,
+                                                 double *__restrict__ out)
+{
+    __shared__ double s[4][1024];
+    const int tid = threadIdx.x;
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t i = tid; i < n; i += 1024)
+        for (int q = 0; q < k; q++) acc[q] += partial[i * k + q];
+    for (int q = 0; q < k; q++) s[q][tid] = acc[q];
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (tid < o)
+            for (int q = 0; q < k; q++) s[q][tid] += s[q][tid + o];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int q = 0; q < k; q++) out[q] = s[q][0];
+}
+
+__global__ void k_alpha(double *sc)
+{
+    sc[SC_ALPHA] = sc[SC_PQ] != 0.0 ? sc[SC_RZ] / sc[SC_PQ] : 0.0;
+}
+
+// x += a p ; r -= a q ; z = dinv r ; partial (r.z, r.r)
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
+                                                   const T *__restrict__ p, const T *__restrict__ q,
+                                                   const T *__restrict__ dinv, const double *__restrict__ sc,
+                                                   double *__restrict__ partial)
+{
+    __shared__ double s0[BLK], s1[BLK];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
+    const double a = sc[SC_ALPHA];
+    double rz = 0, rr = 0;
+    if (i < n) {
+        x[i] = (T)((double)x[i] + a * (double)p[i]);
+        T ri = (T)((double)r[i] - a * (double)q[i]);
+        r[i] = ri;
+        T zi = dinv[i] * ri;
+        z[i] = zi;
+        rz = (double)ri * (double)zi;
+        rr = (double)ri * (double)ri;
+    }
+    s0[tid] = rz;
+    s1[tid] = rr;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            s0[tid] += s0[tid + o];
+            s1[tid] += s1[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[2 * blockIdx.x] = s0[0];
+        partial[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// after k_finish into sc[8..9] = (rz_new, rr)
+__global__ void k_beta(double *sc)
+{
+    const double rzn = sc[8];
+    sc[SC_BETA] = sc[SC_RZ] != 0.0 ? rzn / sc[SC_RZ] : 0.0;
+    sc[SC_RZ] = rzn;
+    sc[SC_RR] = sc[9];
+}
+
+template <typename T>
+__global__ void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z, const double *__restrict__ sc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)((double)z[i] + sc[SC_BETA] * (double)p[i]);
+}
+
+// r = b, x = 0, z = dinv r, p = z ; partial (r.z, r.r)
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const T *__restrict__ b, T *__restrict__ x,
+                                                  T *__restrict__ r, T *__restrict__ z, T *__restrict__ p,
+                                                  const T *__restrict__ dinv, double *__restrict__ partial)
+{
+    __shared__ double s0[BLK], s1[BLK];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
+    double rz = 0, rr = 0;
+    if (i < n) {
+        T ri = b[i];
+        x[i] = T(0);
+        r[i] = ri;
+        T zi = dinv[i] * ri;
+        z[i] = zi;
+        p[i] = zi;
+        rz = (double)ri * (double)zi;
+        rr = (double)ri * (double)ri;
+    }
+    s0[tid] = rz;
+    s1[tid] = rr;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            s0[tid] += s0[tid + o];
+            s1[tid] += s1[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        partial[2 * blockIdx.x] = s0[0];
+        partial[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+__global__ void k_init_sc(double *sc)
+{
+    sc[SC_RZ] = sc[8];
+    sc[SC_RR] = sc[9];
+    sc[SC_BB] = sc[9];
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                        double *__restrict__ o)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
+}
+
+__global__ void k_cast_d2f(int64_t n, const double *__restrict__ in, float *__restrict__ out, double scale)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)(in[i] * scale);
+}
+
+__global__ void k_add_f2d(int64_t n, const float *__restrict__ in, double scale, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += scale * (double)in[i];
+}
+
+// Gauss check partial sums: |GtDe + d|^2, |Gtg - d|^2, |GtDe + Gtg|^2, |d|^2 with d = rho - rho0
+__global__ __launch_bounds__(BLK) void k_gauss_partial(int64_t n, const double *__restrict__ a,
+                                                       const double *__restrict__ g, const double *__restrict__ rho,
+                                                       const double *__restrict__ rho0, double *__restrict__ partial)
+{
+    __shared__ double s[4][BLK];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
+    double v[4] = {0, 0, 0, 0};
+    if (i < n) {
+        double d = rho[i] - rho0[i];
+        double x1 = a[i] + d, x2 = g[i] - d, x3 = a[i] + g[i];
+        v[0] = x1 * x1;
+        v[1] = x2 * x2;
+        v[2] = x3 * x3;
+        v[3] = d * d;
+    }
+    for (int q = 0; q < 4; q++) s[q][tid] = v[q];
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if (tid < o)
+            for (int q = 0; q < 4; q++) s[q][tid] += s[q][tid + o];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int q = 0; q < 4; q++) partial[4 * blockIdx.x + q] = s[q][0];
+}
+
+__global__ __launch_bounds__(BLK) void k_dot_partial(int64_t n, const double *__restrict__ a,
+                                                     const double *__restrict__ b, double *__restrict__ partial)
+{
+    __shared__ double s[BLK];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
+    s[tid] = i < n ? a[i] * b[i] : 0.0;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if (tid < o) s[tid] += s[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) partial[blockIdx.x] = s[0];
+}
+
+inline unsigned nblk(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// =================================================================== launchers
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, const double *x, int32_t *tet, int32_t *err, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, x, tet, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_startup(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
+                          const float *b32, DevParticles p, int64_t n, double qm, double dt, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (order == 1) {
+        if (mixed) hipLaunchKernelGGL((k_startup<1, float>), dim3(nblk(n)), dim3(BLK), 0, s, m, e32, b32, p, n, qm, dt);
+        else hipLaunchKernelGGL((k_startup<1, double>), dim3(nblk(n)), dim3(BLK), 0, s, m, e, b, p, n, qm, dt);
+    } else {
+        if (mixed) hipLaunchKernelGGL((k_startup<2, float>), dim3(nblk(n)), dim3(BLK), 0, s, m, e32, b32, p, n, qm, dt);
+        else hipLaunchKernelGGL((k_startup<2, double>), dim3(nblk(n)), dim3(BLK), 0, s, m, e, b, p, n, qm, dt);
+    }
+    return hipGetLastError();
+}
+
+int64_t sort_hist_entries(int64_t n) { return 256 * std::max<int64_t>(1, (n + RS_TILE - 1) / RS_TILE); }
+
+int64_t scan_tmp_entries(int64_t n)
+{
+    // level sums + their scan
+    int64_t t = 0, m = n;
+    while (m > SC_TILE) {
+        m = (m + SC_TILE - 1) / SC_TILE;
+        t += 2 * m + 2;
+    }
+    return t + 4;
+}
+
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total,
+                              hipStream_t s)
+{
+    if (n == 0) {
+        if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total);
+        return hipGetLastError();
+    }
+    const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+    if (nb == 1) {
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SC_THREADS), 0, s, in, out, n, (uint32_t *)nullptr);
+    } else {
+        uint32_t *sums = tmp;
+        uint32_t *sums_scan = tmp + nb;
+        hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, out, n, sums);
+        hipError_t err = exclusive_scan_u32(sums, sums_scan, nb, tmp + 2 * nb, nullptr, s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(BLK), 0, s, out, n, sums_scan);
+    }
+    if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total);
+    return hipGetLastError();
+}
+
+hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s)
+{
+    int cur = 0;
+    if (n == 0) {
+        *result_buf = 0;
+        return hipSuccess;
+    }
+    const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+    int passes = std::max(1, (bits + 7) / 8);
+    for (int pass = 0; pass < passes; pass++) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(BLK), 0, s, sb.key[cur], n, shift, sb.hist, ntiles);
+        hipError_t err = exclusive_scan_u32(sb.hist, sb.hist, 256 * ntiles, sb.scan_tmp, nullptr, s);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(BLK), 0, s, sb.key[cur], sb.val[cur],
+                           sb.key[1 - cur], sb.val[1 - cur], n, shift, sb.hist, ntiles,
+                           (pass == 0 && vals_are_iota) ? 1 : 0);
+        cur = 1 - cur;
+    }
+    *result_buf = cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(BLK), 0, s, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_keys, dim3(nblk(n)), dim3(BLK), 0, s, tet, key, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *off, hipStream_t s)
+{
+    const int64_t w = n > 0 ? n : (int64_t)nt + 1;
+    hipLaunchKernelGGL(k_offsets, dim3(nblk(w)), dim3(BLK), 0, s, key, n, nt, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
+                           const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
+                           DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
+                           Counters cnt, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((m.nt + sp.tpw - 1) / sp.tpw);
+    if (order == 1) {
+        if (mixed)
+            hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
+                               sp, gl, P, pool, cnt.c);
+        else
+            hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
+                               sp, gl, P, pool, cnt.c);
+    } else {
+        if (mixed)
+            hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
+                               sp, gl, P, pool, cnt.c);
+        else
+            hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
+                               sp, gl, P, pool, cnt.c);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
+                                uint32_t *val, hipStream_t s)
+{
+    (void)np;
+    if (nrec == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spill_compact, dim3(nblk(nrec)), dim3(BLK), 0, s, pool.tet, pool.tag, nrec, pos, key, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *rec, const double *recval,
+                               double *P, hipStream_t s)
+{
+    const int64_t n = (int64_t)nt * n1l;
+    if (n1l == 6) hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
+    else hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
+                          hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(n)), dim3(BLK), 0, s, ptr, idx, n, P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,
+                          const int32_t *ptet, int64_t cap, double qw, double *Pr, hipStream_t s)
+{
+    const int tpw = order == 1 ? 64 : 25;  // BLK / n0
+    const unsigned grid = (unsigned)((m.nt + tpw - 1) / tpw);
+    if (order == 1)
+        hipLaunchKernelGGL(k_rho_tet<1>, dim3(grid), dim3(BLK), 0, s, m, perm, off, x, cap, qw, tpw, Pr, ptet);
+    else
+        hipLaunchKernelGGL(k_rho_tet<2>, dim3(grid), dim3(BLK), 0, s, m, perm, off, x, cap, qw, tpw, Pr, ptet);
+    return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t spmv_t(const DevCSR &A, const T *val, const T *x, T *y, double alpha, double beta, const T *z,
+                  const T *dotv, double *partial, hipStream_t s)
+{
+    if (A.rows == 0) return hipSuccess;
+    switch (A.lanes) {
+    case 4:
+        hipLaunchKernelGGL((k_spmv<4, T>), dim3(nblk(A.rows, BLK / 4)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y,
+                           alpha, beta, z, dotv, partial);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_spmv<8, T>), dim3(nblk(A.rows, BLK / 8)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y,
+                           alpha, beta, z, dotv, partial);
+        break;
+    case 16:
+        hipLaunchKernelGGL((k_spmv<16, T>), dim3(nblk(A.rows, BLK / 16)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x,
+                           y, alpha, beta, z, dotv, partial);
+        break;
+    default:
+        hipLaunchKernelGGL((k_spmv<32, T>), dim3(nblk(A.rows, BLK / 32)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x,
+                           y, alpha, beta, z, dotv, partial);
+        break;
+    }
+    return hipGetLastError();
+}
+
+inline int64_t spmv_blocks(const DevCSR &A) { return (A.rows + (BLK / A.lanes) - 1) / (BLK / A.lanes); }
+}  // namespace
+
+hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, double beta, const double *z, hipStream_t s)
+{
+    return spmv_t<double>(A, A.val, x, y, alpha, beta, z, nullptr, nullptr, s);
+}
+
+hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s)
+{
+    return spmv_t<float>(A, A.val32, x, y, 1.0, 0.0, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(BLK), 0, s, n, a, x, b, y, out);
+    return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t pcg_init_t(int64_t n, const T *b, T *x, T *r, T *z, T *p, const T *dinv, double *partial, double *sc,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pcg_init<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)nblk(n), 2, sc + 8);
+    hipLaunchKernelGGL(k_init_sc, dim3(1), dim3(1), 0, s, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_iter_t(const DevCSR &A, const T *val, int64_t n, T *x, T *r, T *z, T *p, T *q, const T *dinv,
+                      double *partial, double *sc, hipStream_t s)
+{
+    hipError_t err = spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, spmv_blocks(A), 1, sc + SC_PQ);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, s, sc);
+    hipLaunchKernelGGL(k_update_xr<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)nblk(n), 2, sc + 8);
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, s, sc);
+    hipLaunchKernelGGL(k_update_p<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, p, z, sc);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
+                    double *partial, double *sc, hipStream_t s)
+{
+    return pcg_init_t<double>(n, b, x, r, z, p, dinv, partial, sc, s);
+}
+
+hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
+                    const double *dinv, double *partial, double *sc, hipStream_t s)
+{
+    return pcg_iter_t<double>(A, A.val, n, x, r, z, p, q, dinv, partial, sc, s);
+}
+
+hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
+                      double *partial, double *sc, hipStream_t s)
+{
+    return pcg_init_t<float>(n, b, x, r, z, p, dinv, partial, sc, s);
+}
+
+hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
+                      double *partial, double *sc, hipStream_t s)
+{
+    return pcg_iter_t<float>(A, A.val32, n, x, r, z, p, q, dinv, partial, sc, s);
+}
+
+hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_d2f, dim3(nblk(n)), dim3(BLK), 0, s, n, in, out, scale);
+    return hipGetLastError();
+}
+
+hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f2d, dim3(nblk(n)), dim3(BLK), 0, s, n, in, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
+                       double *partial, double *out4, hipStream_t s)
+{
+    const int64_t nb = std::max<int64_t>(1, nblk(n));
+    hipLaunchKernelGGL(k_gauss_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, GtDe, Gtg, rho, rho0, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 4, out4);
+    return hipGetLastError();
+}
+
+hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s)
+{
+    const int64_t nb = std::max<int64_t>(1, nblk(n));
+    hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, a, b, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 1, out);
+    return hipGetLastError();
+}
+
+}  // namespace fempic

@@ -1,0 +1,988 @@
+// Run driver and C ABI of the fempic library: device state in HBM, per-step
+// sequencing of the particle phase (sort, particle kernel, deterministic
+// deposit reduction) and of the implicit field update (Jacobi-PCG in FP64,
+// or FP32 PCG inside FP64 iterative refinement), the Gauss-law check, and
+// host <-> device copies in the natural DoF numbering.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fempic_impl.h"
+#include "kernels.h"
+#include "run.h"
+
+namespace fempic {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &s) { g_last_error = s; }
+
+#define HIPCHECK(x)                                                                                     \
+    do {                                                                                                \
+        hipError_t err__ = (x);                                                                         \
+        if (err__ != hipSuccess)                                                                        \
+            throw Error(FEMPIC_EDEVICE, std::string(#x) + ": " + hipGetErrorString(err__));             \
+    } while (0)
+
+// ------------------------------------------------------------ device memory
+DevBuf::~DevBuf() { release(); }
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+void DevBuf::alloc(size_t n)
+{
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw Error(FEMPIC_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+}
+
+template <typename T>
+static void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s)
+{
+    b.alloc(v.size() * sizeof(T));
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+static int lanes_for(const CSR &A)
+{
+    double avg = A.rows ? (double)A.nnz() / A.rows : 1;
+    if (avg <= 8) return 4;
+    if (avg <= 20) return 8;
+    if (avg <= 48) return 16;
+    return 32;
+}
+
+void Run::upload_csr(DevCSRBuf &d, const CSR &A, bool want32)
+{
+    upload(d.ptr, A.ptr, stream);
+    upload(d.idx, A.idx, stream);
+    upload(d.val, A.val, stream);
+    if (want32) {
+        std::vector<float> v32(A.val.begin(), A.val.end());
+        upload(d.val32, v32, stream);
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+    d.desc.rows = A.rows;
+    d.desc.cols = A.cols;
+    d.desc.nnz = A.nnz();
+    d.desc.ptr = (const int64_t *)d.ptr.p;
+    d.desc.idx = (const int32_t *)d.idx.p;
+    d.desc.val = (const double *)d.val.p;
+    d.desc.val32 = want32 ? (const float *)d.val32.p : nullptr;
+    d.desc.lanes = lanes_for(A);
+}
+
+Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh), prm(p)
+{
+    if (s) {
+        stream = s;
+        own_stream = false;
+    } else {
+        HIPCHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        own_stream = true;
+    }
+    mixed = p.precision == FEMPIC_MIXED;
+    order = m.order;
+    n1l = m.n1l;
+    n2l = m.n2l;
+    n0l = m.n0l;
+    const RefElem &R = ref_elem(order);
+    for (int g = 0; g < (int)R.glx.size(); g++) {
+        gl.x[g] = R.glx[g];
+        gl.w[g] = R.glw[g];
+    }
+    // mesh tables
+    upload(d_geo, m.geo, stream);
+    upload(d_nbr, m.nbr, stream);
+    upload(d_map1, m.map1, stream);
+    upload(d_map2, m.map2, stream);
+    upload(d_map0, m.map0, stream);
+    dm.nt = (int32_t)m.nt;
+    dm.geo = (const double *)d_geo.p;
+    dm.nbr = (const int32_t *)d_nbr.p;
+    dm.map1 = (const int32_t *)d_map1.p;
+    dm.map2 = (const int32_t *)d_map2.p;
+    dm.map0 = (const int32_t *)d_map0.p;
+    dm.cube_N = m.is_cube ? m.cube_N : 0;
+    dm.cube_L = m.cube_L;
+    // operators
+    Operators ops;
+    assemble(m, p.dt, ops);
+    upload_csr(A, ops.A, mixed);
+    upload_csr(Meps, ops.Meps, false);
+    upload_csr(Ct, ops.Ct, false);
+    upload_csr(K, ops.K, false);
+    upload_csr(Gt, ops.Gt, false);
+    upload(d_dinv, ops.Adiag_inv, stream);
+    if (mixed) {
+        std::vector<float> d32(ops.Adiag_inv.begin(), ops.Adiag_inv.end());
+        upload(d_dinv32, d32, stream);
+    }
+    upload(d_inc_ptr, ops.inc_ptr, stream);
+    upload(d_inc_idx, ops.inc_idx, stream);
+    upload(d_inc0_ptr, ops.inc0_ptr, stream);
+    upload(d_inc0_idx, ops.inc0_idx, stream);
+    nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Ct.nnz() + ops.K.nnz() + ops.Gt.nnz();
+    // fields and solver vectors
+    const int64_t N1 = m.N1, N1i = m.N1_int, N2 = m.N2, N0i = m.N0_int;
+    d_e.alloc(N1 * 8);
+    d_b.alloc(N2 * 8);
+    d_g.alloc(std::max<int64_t>(N1i, 1) * 8);
+    d_dg.alloc(std::max<int64_t>(N1i, 1) * 8);
+    zero(d_e);
+    zero(d_b);
+    zero(d_g);
+    zero(d_dg);
+    if (mixed) {
+        d_e32.alloc(N1 * 4);
+        d_b32.alloc(N2 * 4);
+        zero(d_e32);
+        zero(d_b32);
+    }
+    for (auto *v : {&v_x, &v_r, &v_z, &v_p, &v_q, &v_rhs, &v_tmp}) v->alloc(std::max<int64_t>(N1i, 1) * 8);
+    if (mixed)
+        for (auto *v : {&f_x, &f_r, &f_z, &f_p, &f_q}) v->alloc(std::max<int64_t>(N1i, 1) * 4);
+    v_u.alloc(std::max<int64_t>(N2, 1) * 8);
+    const int64_t maxrows = std::max<int64_t>({N1i, N2, N0i, 1});
+    d_partial.alloc((size_t)(maxrows / 4 + 1024) * 4 * 8);
+    d_sc.alloc(64 * 8);
+    zero(d_sc);
+    d_rho.alloc(std::max<int64_t>(N0i, 1) * 8);
+    d_rho0.alloc(std::max<int64_t>(N0i, 1) * 8);
+    d_GtDe.alloc(std::max<int64_t>(N0i, 1) * 8);
+    d_Gtg.alloc(std::max<int64_t>(N0i, 1) * 8);
+    d_y1.alloc(std::max<int64_t>(N1i, 1) * 8);
+    zero(d_rho0);
+    d_P.alloc((size_t)m.nt * n1l * 8);
+    d_Pr.alloc((size_t)m.nt * n0l * 8);
+    d_off.alloc((size_t)(m.nt + 1) * 4);
+    d_soff.alloc((size_t)(m.nt + 1) * 4);
+    d_cnt.alloc(8 * 8);
+    d_small.alloc(64);
+    HIPCHECK(hipHostMalloc(&h_pin, 256, hipHostMallocDefault));
+    for (auto *ev : {&ev_a, &ev_b, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
+    HIPCHECK(hipStreamSynchronize(stream));
+}
+
+Run::~Run()
+{
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto ev : {ev_a, ev_b, ev_c, ev_d, ev_e})
+        if (ev) (void)hipEventDestroy(ev);
+    if (h_pin) (void)hipHostFree(h_pin);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void Run::zero(DevBuf &b)
+{
+    if (b.bytes) HIPCHECK(hipMemsetAsync(b.p, 0, b.bytes, stream));
+}
+
+void Run::sync()
+{
+    HIPCHECK(hipStreamSynchronize(stream));
+    if (sticky) throw Error(sticky, sticky_msg);
+}
+
+size_t Run::particle_bytes(int64_t n) const
+{
+    const size_t rs = mixed ? 4 : 8;
+    return (size_t)n * (3 * 8 + 21 * rs + 8);
+}
+
+void Run::alloc_particles(int64_t n)
+{
+    np = n;
+    const int64_t cap = std::max<int64_t>(n, 1);
+    const size_t rs = mixed ? 4 : 8;
+    for (int k = 0; k < 2; k++) {
+        PBufs &B = pb[k];
+        B.x.alloc(cap * 3 * 8);
+        B.v.alloc(cap * 3 * rs);
+        B.vh.alloc(cap * 9 * rs);
+        B.ah.alloc(cap * 9 * rs);
+        B.tet.alloc(cap * 4);
+        B.id.alloc(cap * 4);
+        B.d.x = (double *)B.x.p;
+        B.d.v = B.v.p;
+        B.d.vh = B.vh.p;
+        B.d.ah = B.ah.p;
+        B.d.tet = (int32_t *)B.tet.p;
+        B.d.id = (int32_t *)B.id.p;
+        B.d.cap = cap;
+    }
+    cur = 0;
+    // particle sort
+    alloc_sort(psort, cap, hp_sort);
+    // spill pool
+    pool_cap = std::max<int64_t>(cap + cap / 2, 1 << 16);
+    alloc_pool(pool_cap);
+    d_pcount.alloc(cap * 4);
+    d_ppos.alloc(cap * 4);
+}
+
+void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
+{
+    hold.resize(6);
+    for (int k = 0; k < 2; k++) {
+        hold[k].alloc(cap * 4);
+        hold[2 + k].alloc(cap * 4);
+        sb.key[k] = (uint32_t *)hold[k].p;
+        sb.val[k] = (uint32_t *)hold[2 + k].p;
+    }
+    const int64_t hn = sort_hist_entries(cap);
+    hold[4].alloc(hn * 4);
+    hold[5].alloc(std::max<int64_t>(scan_tmp_entries(hn), scan_tmp_entries(cap)) * 4 + 64);
+    sb.hist = (uint32_t *)hold[4].p;
+    sb.scan_tmp = (uint32_t *)hold[5].p;
+    sb.cap = cap;
+}
+
+void Run::alloc_pool(int64_t cap)
+{
+    pool_cap = cap;
+    d_pool_val.alloc((size_t)cap * n1l * 8);
+    d_pool_tet.alloc((size_t)cap * 4);
+    d_pool_tag.alloc((size_t)cap * 8);
+    alloc_sort(ssort, cap, hp_ssort);
+}
+
+DevParticles Run::P(int k) const { return pb[k].d; }
+
+SpillPool Run::pool() const
+{
+    SpillPool sp;
+    sp.val = (double *)d_pool_val.p;
+    sp.tet = (int32_t *)d_pool_tet.p;
+    sp.tag = (int64_t *)d_pool_tag.p;
+    sp.count = (int32_t *)d_small.p;
+    sp.pcount = (int32_t *)d_pcount.p;
+    sp.cap = pool_cap;
+    return sp;
+}
+
+int Run::key_bits() const
+{
+    int bits = 1;
+    while (((int64_t)1 << bits) < m.nt) bits++;
+    return bits;
+}
+
+// sort the current particles by tet: returns perm (sorted -> slot) and fills d_off
+const uint32_t *Run::sort_current()
+{
+    HIPCHECK(launch_copy_keys(pb[cur].d.tet, psort.key[0], np, stream));
+    int res = 0;
+    HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream));
+    HIPCHECK(launch_offsets(psort.key[res], np, (int32_t)m.nt, (int32_t *)d_off.p, stream));
+    return psort.val[res];
+}
+
+void Run::load(const double *pos, const double *vel, int64_t n, double q_, double mass_, double w_)
+{
+    if (n < 0 || (n > 0 && (!pos || !vel))) throw Error(FEMPIC_EINVAL, "bad particle arrays");
+    if (!(mass_ > 0) || !std::isfinite(q_) || !std::isfinite(w_)) throw Error(FEMPIC_EINVAL, "bad species");
+    if (n >= ((int64_t)1 << 31) / 2) throw Error(FEMPIC_EINVAL, "too many particles");
+    q = q_;
+    mass = mass_;
+    w = w_;
+    alloc_particles(n);
+    PBufs &B = pb[0];
+    std::vector<double> xs(3 * std::max<int64_t>(n, 1));
+    for (int64_t i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) xs[c * n + i] = pos[3 * i + c];
+    if (n) HIPCHECK(hipMemcpyAsync(B.x.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
+    if (mixed) {
+        std::vector<float> vs(3 * std::max<int64_t>(n, 1));
+        for (int64_t i = 0; i < n; i++)
+            for (int c = 0; c < 3; c++) vs[c * n + i] = (float)vel[3 * i + c];
+        if (n) HIPCHECK(hipMemcpyAsync(B.v.p, vs.data(), 3 * n * 4, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    } else {
+        for (int64_t i = 0; i < n; i++)
+            for (int c = 0; c < 3; c++) xs[c * n + i] = vel[3 * i + c];
+        if (n) HIPCHECK(hipMemcpyAsync(B.v.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+    std::vector<int32_t> ids(std::max<int64_t>(n, 1));
+    std::iota(ids.begin(), ids.end(), 0);
+    if (n) HIPCHECK(hipMemcpyAsync(B.id.p, ids.data(), n * 4, hipMemcpyHostToDevice, stream));
+    // locate
+    std::vector<int32_t> tets;
+    if (m.is_cube) {
+        zero(d_small);
+        HIPCHECK(launch_locate_cube(dm, n, (const double *)B.x.p, (int32_t *)B.tet.p, (int32_t *)d_small.p, stream));
+        int32_t err = 0;
+        HIPCHECK(hipMemcpyAsync(&err, d_small.p, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        if (err & ERR_OUTSIDE) throw Error(FEMPIC_EOUTSIDE, "a particle lies outside the mesh");
+    } else {
+        tets.resize(std::max<int64_t>(n, 1));
+        locate_host(pos, n, tets.data());
+        if (n) HIPCHECK(hipMemcpyAsync(B.tet.p, tets.data(), n * 4, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+    // AB4 start-up from the current fields
+    HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p, (const float *)d_e32.p,
+                            (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
+    // Gauss reference charge
+    compute_rho((double *)d_rho0.p);
+    zero(d_g);
+    HIPCHECK(hipStreamSynchronize(stream));
+    sticky = 0;
+    loaded = true;
+}
+
+// uniform-bin point location for meshes that are not Kuhn cubes (host side, at load)
+void Run::locate_host(const double *pos, int64_t n, int32_t *out)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < m.nv; v++)
+        for (int c = 0; c < 3; c++) {
+            lo[c] = std::min(lo[c], m.xyz[3 * v + c]);
+            hi[c] = std::max(hi[c], m.xyz[3 * v + c]);
+        }
+    const int nb = std::max(1, (int)std::cbrt((double)m.nt / 4.0));
+    double h[3];
+    for (int c = 0; c < 3; c++) h[c] = std::max(hi[c] - lo[c], 1e-300) / nb;
+    std::vector<std::vector<int32_t>> bins((size_t)nb * nb * nb);
+    auto bidx = [&](double x, int c) { return std::min(nb - 1, std::max(0, (int)std::floor((x - lo[c]) / h[c]))); };
+    for (int64_t t = 0; t < m.nt; t++) {
+        double bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
+        for (int k = 0; k < 4; k++)
+            for (int c = 0; c < 3; c++) {
+                bl[c] = std::min(bl[c], m.xyz[3 * m.tets[4 * t + k] + c]);
+                bh[c] = std::max(bh[c], m.xyz[3 * m.tets[4 * t + k] + c]);
+            }
+        int i0[3], i1[3];
+        for (int c = 0; c < 3; c++) {
+            i0[c] = bidx(bl[c], c);
+            i1[c] = bidx(bh[c], c);
+        }
+        for (int a = i0[0]; a <= i1[0]; a++)
+            for (int b = i0[1]; b <= i1[1]; b++)
+                for (int c = i0[2]; c <= i1[2]; c++) bins[a + (size_t)nb * (b + (size_t)nb * c)].push_back((int32_t)t);
+    }
+    for (int64_t p = 0; p < n; p++) {
+        const double *r = &pos[3 * p];
+        for (int c = 0; c < 3; c++)
+            if (!(r[c] >= lo[c] - 1e-12 && r[c] <= hi[c] + 1e-12))
+                throw Error(FEMPIC_EOUTSIDE, "a particle lies outside the mesh");
+        const auto &cand = bins[bidx(r[0], 0) + (size_t)nb * (bidx(r[1], 1) + (size_t)nb * bidx(r[2], 2))];
+        double best = -1e300;
+        int32_t bt = -1;
+        for (int32_t t : cand) {
+            const double *g = &m.geo[16 * (size_t)t];
+            double mn = 1e300;
+            for (int f = 0; f < 4; f++) mn = std::min(mn, g[4 * f] + g[4 * f + 1] * r[0] + g[4 * f + 2] * r[1] + g[4 * f + 3] * r[2]);
+            if (mn > best || (mn == best && t < bt)) {
+                best = mn;
+                bt = t;
+            }
+        }
+        if (bt < 0 || !(best >= -1e-10)) throw Error(FEMPIC_EOUTSIDE, "a particle lies outside the mesh");
+        out[p] = bt;
+    }
+}
+
+void Run::compute_rho(double *dst)
+{
+    const uint32_t *perm = sort_current();
+    HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d.x, pb[cur].d.tet, pb[cur].d.cap,
+                            q * w, (double *)d_Pr.p, stream));
+    HIPCHECK(launch_scatter((const int64_t *)d_inc0_ptr.p, (const int32_t *)d_inc0_idx.p, m.N0_int,
+                            (const double *)d_Pr.p, dst, stream));
+}
+
+int Run::tpw() const
+{
+    const int tmax = order == 1 ? 42 : 12;
+    const double ppt = m.nt ? (double)np / m.nt : 1.0;
+    int t = (int)std::lround(256.0 / std::max(ppt, 1e-9));
+    return std::max(1, std::min(tmax, t));
+}
+
+void Run::particle_phase()
+{
+    HIPCHECK(hipEventRecord(ev_a, stream));
+    const uint32_t *perm = sort_current();
+    StepParams sp{q / mass, q * w, prm.dt, tpw()};
+    bool done = false;
+    for (int attempt = 0; attempt < 4 && !done; attempt++) {
+        zero(d_small);
+        zero(d_cnt);
+        HIPCHECK(hipEventRecord(ev_b, stream));
+        HIPCHECK(launch_particle(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p,
+                                 (const float *)d_e32.p, (const float *)d_b32.p, perm, (const int32_t *)d_off.p,
+                                 pb[cur].d, pb[1 - cur].d, np, sp, gl, (double *)d_P.p, pool(), Counters{(unsigned long long *)d_cnt.p},
+                                 stream));
+        HIPCHECK(hipEventRecord(ev_c, stream));
+        HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        const unsigned long long *c = (const unsigned long long *)h_pin;
+        const int32_t nrec = *(const int32_t *)((char *)h_pin + 32);
+        last_cross = (int64_t)c[0];
+        last_refl = (int64_t)c[1];
+        last_spill = (int64_t)c[2];
+        const unsigned long long errs = c[3];
+        if (errs & ERR_POOL) {
+            // grow the pool and redo the step (the input state is untouched)
+            alloc_pool(std::max<int64_t>(2 * pool_cap, (int64_t)nrec + nrec / 4 + 1024));
+            continue;
+        }
+        if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
+        if (errs & ERR_NAN) throw Error(FEMPIC_EDEVICE, "non-finite particle position");
+        nrec_last = nrec;
+        done = true;
+    }
+    if (!done) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
+    // deterministic reduction of the spill pool
+    const int64_t nrec = nrec_last;
+    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_pcount.p, (uint32_t *)d_ppos.p, np, psort.scan_tmp,
+                                (uint32_t *)d_small.p + 2, stream));
+    if (nrec > 0) {
+        HIPCHECK(launch_spill_compact(pool(), nrec, np, (const uint32_t *)d_ppos.p, ssort.key[0], ssort.val[0], stream));
+        int res = 0;
+        HIPCHECK(radix_sort(ssort, nrec, key_bits(), false, &res, stream));
+        HIPCHECK(launch_offsets(ssort.key[res], nrec, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
+        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, ssort.val[res],
+                                     (const double *)d_pool_val.p, (double *)d_P.p, stream));
+    }
+    HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int, (const double *)d_P.p,
+                            (double *)d_dg.p, stream));
+    HIPCHECK(hipEventRecord(ev_d, stream));
+    cur = 1 - cur;
+}
+
+void Run::field_phase()
+{
+    const int64_t N1i = m.N1_int, N2 = m.N2;
+    const double dt = prm.dt;
+    double *e = (double *)d_e.p, *b = (double *)d_b.p, *dg = (double *)d_dg.p;
+    // g += dg
+    HIPCHECK(axpby(N1i, 1.0, dg, 1.0, (const double *)d_g.p, (double *)d_g.p, stream));
+    // u = b - dt/2 K e ; rhs = dt Ct u - dg
+    HIPCHECK(spmv(K.desc, e, (double *)v_u.p, -0.5 * dt, 1.0, b, stream));
+    HIPCHECK(spmv(Ct.desc, (const double *)v_u.p, (double *)v_rhs.p, dt, -1.0, dg, stream));
+    // solve A d = rhs
+    if (mixed) solve_mixed();
+    else solve_fp64();
+    // b -= dt/2 K (2 e + d) ; e += d
+    HIPCHECK(axpby(N1i, 2.0, e, 1.0, (const double *)v_x.p, (double *)v_tmp.p, stream));
+    HIPCHECK(spmv(K.desc, (const double *)v_tmp.p, b, -0.5 * dt, 1.0, b, stream));
+    HIPCHECK(axpby(N1i, 1.0, e, 1.0, (const double *)v_x.p, e, stream));
+    (void)N2;
+    if (mixed) {
+        HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
+        HIPCHECK(cast_d2f(m.N2, b, (float *)d_b32.p, 1.0, stream));
+    }
+    HIPCHECK(hipEventRecord(ev_e, stream));
+}
+
+double Run::read_sc(int k)
+{
+    HIPCHECK(hipMemcpyAsync(h_pin, (double *)d_sc.p + k, 8, hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    return *(double *)h_pin;
+}
+
+void Run::solve_fp64()
+{
+    const int64_t n = m.N1_int;
+    double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
+    HIPCHECK(pcg_init(n, (const double *)v_rhs.p, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                      (const double *)d_dinv.p, part, sc, stream));
+    const double bb = read_sc(SC_BB);
+    last_iters = 0;
+    last_relres = 0;
+    if (bb == 0.0) return;
+    const double tol2 = prm.pcg_rtol * prm.pcg_rtol * bb;
+    const int check = 8;
+    double rr = bb, best = bb;
+    int stall = 0;
+    for (int it = 0; it < prm.pcg_maxit;) {
+        for (int k = 0; k < check && it < prm.pcg_maxit; k++, it++)
+            HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                              (double *)v_q.p, (const double *)d_dinv.p, part, sc, stream));
+        last_iters = it;
+        rr = read_sc(SC_RR);
+        if (!(rr == rr)) throw Error(FEMPIC_ESOLVE, "field solve produced NaN");
+        if (rr <= tol2) break;
+        if (rr < 0.25 * best) {
+            best = rr;
+            stall = 0;
+        } else if (++stall > 40 && rr <= 1e-24 * bb) {
+            break;  // at the attainable accuracy
+        }
+    }
+    last_relres = std::sqrt(rr / bb);
+    if (!(rr <= tol2) && !(rr <= 1e-24 * bb))
+        throw Error(FEMPIC_ESOLVE, "PCG did not reach the tolerance: relres " + std::to_string(last_relres));
+}
+
+// FP32 PCG inside FP64 iterative refinement: x = 0, r = rhs; repeat:
+// solve A32 d = r/|r| to 1e-5 in FP32, x += |r| d, r = rhs - A x in FP64.
+void Run::solve_mixed()
+{
+    const int64_t n = m.N1_int;
+    double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
+    double *x = (double *)v_x.p, *r = (double *)v_r.p;
+    const double *rhs = (const double *)v_rhs.p;
+    HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, x, stream));
+    HIPCHECK(axpby(n, 1.0, rhs, 0.0, rhs, r, stream));
+    HIPCHECK(dot_det(n, rhs, rhs, part, sc + 12, stream));
+    const double bb = read_sc(12);
+    last_iters = 0;
+    last_relres = 0;
+    if (bb == 0.0) return;
+    double rr = bb;
+    for (int outer = 0; outer < 12; outer++) {
+        if (rr <= prm.pcg_rtol * prm.pcg_rtol * bb) break;
+        const double scale = std::sqrt(rr);
+        HIPCHECK(cast_d2f(n, r, (float *)f_q.p, 1.0 / scale, stream));
+        HIPCHECK(pcg32_init(n, (const float *)f_q.p, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
+                            (const float *)d_dinv32.p, part, sc, stream));
+        const double bb32 = read_sc(SC_BB);
+        const double tol32 = 1e-5 * 1e-5 * bb32;
+        int it = 0;
+        double r32 = bb32;
+        while (it < prm.pcg_maxit) {
+            for (int k = 0; k < 8; k++, it++)
+                HIPCHECK(pcg32_iter(A.desc, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
+                                    (float *)f_q.p, (const float *)d_dinv32.p, part, sc, stream));
+            r32 = read_sc(SC_RR);
+            if (!(r32 == r32)) throw Error(FEMPIC_ESOLVE, "FP32 inner solve produced NaN");
+            if (r32 <= tol32) break;
+        }
+        last_iters += it;
+        HIPCHECK(add_f2d(n, (const float *)f_x.p, scale, x, stream));
+        // r = rhs - A x (FP64)
+        HIPCHECK(spmv(A.desc, x, r, -1.0, 1.0, rhs, stream));
+        HIPCHECK(dot_det(n, r, r, part, sc + 12, stream));
+        rr = read_sc(12);
+    }
+    last_relres = std::sqrt(rr / bb);
+    if (!(rr <= prm.pcg_rtol * prm.pcg_rtol * bb) && !(last_relres < 1e-12))
+        throw Error(FEMPIC_ESOLVE, "refined solve did not reach the tolerance: relres " + std::to_string(last_relres));
+}
+
+void Run::step(int n_steps)
+{
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    if (sticky) throw Error(sticky, sticky_msg);
+    double pms = 0, kms = 0, fms = 0;
+    try {
+        for (int s = 0; s < n_steps; s++) {
+            particle_phase();
+            field_phase();
+            HIPCHECK(hipEventSynchronize(ev_e));
+            float t1 = 0, t2 = 0, t3 = 0;
+            HIPCHECK(hipEventElapsedTime(&t1, ev_a, ev_d));
+            HIPCHECK(hipEventElapsedTime(&t2, ev_b, ev_c));
+            HIPCHECK(hipEventElapsedTime(&t3, ev_d, ev_e));
+            pms += t1;
+            kms += t2;
+            fms += t3;
+            steps_done++;
+        }
+    } catch (Error &e) {
+        sticky = e.code;
+        sticky_msg = e.what();
+        throw;
+    }
+    last_particle_ms = pms;
+    last_kernel_ms = kms;
+    last_field_ms = fms;
+}
+
+void Run::gauss(double out[3])
+{
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    compute_rho((double *)d_rho.p);
+    const int64_t N1i = m.N1_int, N0i = m.N0_int;
+    HIPCHECK(spmv(Meps.desc, (const double *)d_e.p, (double *)d_y1.p, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(spmv(Gt.desc, (const double *)d_y1.p, (double *)d_GtDe.p, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(spmv(Gt.desc, (const double *)d_g.p, (double *)d_Gtg.p, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(gauss_norms(N0i, (const double *)d_GtDe.p, (const double *)d_Gtg.p, (const double *)d_rho.p,
+                         (const double *)d_rho0.p, (double *)d_partial.p, (double *)d_sc.p + 16, stream));
+    HIPCHECK(hipMemcpyAsync(h_pin, (double *)d_sc.p + 16, 32, hipMemcpyDeviceToHost, stream));
+    sync();
+    (void)N1i;
+    const double *v = (const double *)h_pin;
+    double nrm = std::sqrt(v[3]);
+    if (nrm == 0) nrm = 1.0;
+    out[0] = std::sqrt(v[0]) / nrm;
+    out[1] = std::sqrt(v[1]) / nrm;
+    out[2] = std::sqrt(v[2]) / nrm;
+}
+
+void Run::fields_get(double *e, int64_t ne, double *b, int64_t nb)
+{
+    sync();
+    if (e) {
+        if (ne < m.N1) throw Error(FEMPIC_EINVAL, "e buffer too short");
+        std::vector<double> ei(m.N1);
+        HIPCHECK(hipMemcpy(ei.data(), d_e.p, m.N1 * 8, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < m.N1; k++) e[m.int2nat1[k]] = ei[k];
+    }
+    if (b) {
+        if (nb < m.N2) throw Error(FEMPIC_EINVAL, "b buffer too short");
+        HIPCHECK(hipMemcpy(b, d_b.p, m.N2 * 8, hipMemcpyDeviceToHost));
+    }
+}
+
+void Run::fields_set(const double *e, int64_t ne, const double *b, int64_t nb)
+{
+    sync();
+    if (e) {
+        if (ne < m.N1) throw Error(FEMPIC_EINVAL, "e buffer too short");
+        std::vector<double> ei(m.N1, 0.0);
+        for (int64_t i = 0; i < m.N1; i++) {
+            int64_t k = m.nat2int1[i];
+            if (k < m.N1_int) ei[k] = e[i];
+        }
+        HIPCHECK(hipMemcpy(d_e.p, ei.data(), m.N1 * 8, hipMemcpyHostToDevice));
+    }
+    if (b) {
+        if (nb < m.N2) throw Error(FEMPIC_EINVAL, "b buffer too short");
+        HIPCHECK(hipMemcpy(d_b.p, b, m.N2 * 8, hipMemcpyHostToDevice));
+    }
+    if (mixed) {
+        HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
+        HIPCHECK(cast_d2f(m.N2, (const double *)d_b.p, (float *)d_b32.p, 1.0, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+}
+
+void Run::deposit_get(double *dg, int64_t n)
+{
+    sync();
+    if (n < m.N1) throw Error(FEMPIC_EINVAL, "buffer too short");
+    std::vector<double> d(std::max<int64_t>(m.N1_int, 1));
+    HIPCHECK(hipMemcpy(d.data(), d_dg.p, m.N1_int * 8, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m.N1; i++) dg[i] = 0.0;
+    for (int64_t k = 0; k < m.N1_int; k++) dg[m.int2nat1[k]] = d[k];
+}
+
+void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
+{
+    sync();
+    if (n < np) throw Error(FEMPIC_EINVAL, "buffer too short");
+    const PBufs &B = pb[cur];
+    std::vector<double> x(3 * std::max<int64_t>(np, 1));
+    std::vector<int32_t> id(std::max<int64_t>(np, 1)), tt(std::max<int64_t>(np, 1));
+    const int64_t cap = B.d.cap;
+    for (int c = 0; c < 3; c++)
+        if (np) HIPCHECK(hipMemcpy(&x[c * np], (double *)B.x.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+    if (np) HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
+    if (np) HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
+    std::vector<double> v(3 * std::max<int64_t>(np, 1));
+    if (mixed) {
+        std::vector<float> vf(3 * std::max<int64_t>(np, 1));
+        for (int c = 0; c < 3; c++)
+            if (np) HIPCHECK(hipMemcpy(&vf[c * np], (float *)B.v.p + c * cap, np * 4, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < vf.size(); k++) v[k] = vf[k];
+    } else {
+        for (int c = 0; c < 3; c++)
+            if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < np; i++) {
+        const int64_t o = id[i];
+        for (int c = 0; c < 3; c++) {
+            if (pos) pos[3 * o + c] = x[c * np + i];
+            if (vel) vel[3 * o + c] = v[c * np + i];
+        }
+        if (tet) tet[o] = tt[i];
+    }
+}
+
+void Run::history_get(double *vh, double *ah, int64_t n)
+{
+    sync();
+    if (n < np) throw Error(FEMPIC_EINVAL, "buffer too short");
+    const PBufs &B = pb[cur];
+    const int64_t cap = B.d.cap;
+    std::vector<int32_t> id(std::max<int64_t>(np, 1));
+    if (np) HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
+    auto fetch = [&](const DevBuf &src, double *dst) {
+        std::vector<double> h(9 * std::max<int64_t>(np, 1));
+        if (mixed) {
+            std::vector<float> f(9 * std::max<int64_t>(np, 1));
+            for (int c = 0; c < 9; c++)
+                if (np) HIPCHECK(hipMemcpy(&f[c * np], (float *)src.p + c * cap, np * 4, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < f.size(); k++) h[k] = f[k];
+        } else {
+            for (int c = 0; c < 9; c++)
+                if (np) HIPCHECK(hipMemcpy(&h[c * np], (double *)src.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+        }
+        for (int64_t i = 0; i < np; i++)
+            for (int c = 0; c < 9; c++) dst[9 * id[i] + c] = h[c * np + i];
+    };
+    if (vh) fetch(B.vh, vh);
+    if (ah) fetch(B.ah, ah);
+}
+
+size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
+{
+    const size_t rs = mixed ? 4 : 8;
+    const double nnzA = (double)m.N1_int * (m.order == 1 ? 16.0 : 44.0);
+    const double nnzC = (double)m.N1_int * (m.order == 1 ? 10.0 : 30.0);
+    size_t ops = (size_t)((2 * nnzA + nnzC) * 12 + (mixed ? nnzA * 4 : 0) + (double)m.N2 * 8 * 12 +
+                          (double)m.N0_int * 40 * 12);
+    size_t vecs = (size_t)(m.N1 * 8 * 14 + m.N2 * 8 * 4 + m.nt * (16 * 8 + 4 * 4 + (m.n1l + m.n2l + m.n0l) * 4));
+    size_t parts = (size_t)n * 2 * (3 * 8 + 21 * rs + 8);
+    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 12 + 24);
+    size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
+    return ops + vecs + parts + sorts + tets + (64 << 20);
+}
+
+}  // namespace fempic
+
+// =================================================================== C ABI
+using namespace fempic;
+
+struct fempic_mesh_s {
+    std::unique_ptr<HostMesh> m;
+};
+struct fempic_run_s {
+    std::unique_ptr<Run> r;
+};
+
+#define API_BEGIN try {
+#define API_END                                     \
+    }                                               \
+    catch (const Error &e) {                        \
+        set_error(e.what());                        \
+        return e.code;                              \
+    }                                               \
+    catch (const std::bad_alloc &) {                \
+        set_error("host allocation failed");        \
+        return FEMPIC_ENOMEM;                       \
+    }                                               \
+    catch (const std::exception &e) {              \
+        set_error(e.what());                        \
+        return FEMPIC_EINVAL;                       \
+    }                                               \
+    catch (...) {                                   \
+        set_error("unknown failure");               \
+        return FEMPIC_EINVAL;                       \
+    }                                               \
+    set_error("");                                  \
+    return FEMPIC_OK;
+
+extern "C" {
+
+const char *fempic_last_error(void) { return g_last_error.c_str(); }
+
+int32_t fempic_mesh_create(const double *xyz, int64_t n_vert, const int64_t *tet4, int64_t n_tet, int32_t order,
+                           fempic_mesh *out)
+{
+    API_BEGIN
+    if (!out) throw Error(FEMPIC_EINVAL, "null out");
+    auto *h = new fempic_mesh_s();
+    try {
+        h->m.reset(build_mesh(xyz, n_vert, tet4, n_tet, order));
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    *out = h;
+    API_END
+}
+
+int32_t fempic_mesh_create_cube(int32_t N, double L, int32_t order, fempic_mesh *out)
+{
+    API_BEGIN
+    if (!out) throw Error(FEMPIC_EINVAL, "null out");
+    auto *h = new fempic_mesh_s();
+    try {
+        h->m.reset(build_cube(N, L, order));
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    *out = h;
+    API_END
+}
+
+int32_t fempic_mesh_destroy(fempic_mesh mesh)
+{
+    delete mesh;
+    return FEMPIC_OK;
+}
+
+int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out)
+{
+    API_BEGIN
+    if (!mesh || !out) throw Error(FEMPIC_EINVAL, "null argument");
+    const HostMesh &m = *mesh->m;
+    fempic_mesh_info_t i{};
+    i.n_vert = m.nv;
+    i.n_edge = m.ne;
+    i.n_face = m.nf;
+    i.n_tet = m.nt;
+    i.n1 = m.N1;
+    i.n1_int = m.N1_int;
+    i.n2 = m.N2;
+    i.n0 = m.N0;
+    i.n0_int = m.N0_int;
+    i.order = m.order;
+    i.n1_loc = m.n1l;
+    i.n2_loc = m.n2l;
+    i.n0_loc = m.n0l;
+    i.dt_cfl = m.dt_cfl;
+    *out = i;
+    API_END
+}
+
+int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out)
+{
+    API_BEGIN
+    if (!mesh || !params || !out) throw Error(FEMPIC_EINVAL, "null argument");
+    const fempic_params &p = *params;
+    if (p.precision != FEMPIC_FP64 && p.precision != FEMPIC_MIXED) throw Error(FEMPIC_EINVAL, "bad precision");
+    if (!(p.dt > 0) || !std::isfinite(p.dt)) throw Error(FEMPIC_EINVAL, "dt must be positive");
+    if (p.gamma != 0.5 || p.beta != 0.25) throw Error(FEMPIC_EINVAL, "only gamma = 1/2, beta = 1/4 is supported");
+    if (!(p.pcg_rtol > 0) || p.pcg_maxit < 1) throw Error(FEMPIC_EINVAL, "bad solver settings");
+    if (p.particle_bc != FEMPIC_REFLECT) throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
+    auto *h = new fempic_run_s();
+    try {
+        h->r.reset(new Run(*mesh->m, p, (hipStream_t)hip_stream));
+    } catch (...) {
+        delete h;
+        throw;
+    }
+    *out = h;
+    API_END
+}
+
+int32_t fempic_run_destroy(fempic_run run)
+{
+    delete run;
+    return FEMPIC_OK;
+}
+
+int32_t fempic_particles_load(fempic_run run, const double *pos, const double *vel, int64_t n, double q, double m,
+                              double w)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->load(pos, vel, n, q, m, w);
+    API_END
+}
+
+int32_t fempic_step(fempic_run run, int32_t n_steps)
+{
+    API_BEGIN
+    if (!run || n_steps < 0) throw Error(FEMPIC_EINVAL, "bad argument");
+    run->r->step(n_steps);
+    API_END
+}
+
+int32_t fempic_sync(fempic_run run)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->sync();
+    API_END
+}
+
+int32_t fempic_gauss_residual(fempic_run run, double out[3])
+{
+    API_BEGIN
+    if (!run || !out) throw Error(FEMPIC_EINVAL, "null argument");
+    double v[3];
+    run->r->gauss(v);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    API_END
+}
+
+int32_t fempic_fields_get(fempic_run run, double *e, int64_t ne, double *b, int64_t nb)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->fields_get(e, ne, b, nb);
+    API_END
+}
+
+int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const double *b, int64_t nb)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->fields_set(e, ne, b, nb);
+    API_END
+}
+
+int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n)
+{
+    API_BEGIN
+    if (!run || !dg) throw Error(FEMPIC_EINVAL, "null argument");
+    run->r->deposit_get(dg, n);
+    API_END
+}
+
+int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *tet, int64_t n)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->particles_get(pos, vel, tet, n);
+    API_END
+}
+
+int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->history_get(vh, ah, n);
+    API_END
+}
+
+int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
+{
+    API_BEGIN
+    if (!run || !out) throw Error(FEMPIC_EINVAL, "null argument");
+    const Run &r = *run->r;
+    fempic_stats_t s{};
+    s.steps = r.steps_done;
+    s.n_particles = r.np;
+    s.particle_ms = r.last_particle_ms;
+    s.particle_kernel_ms = r.last_kernel_ms;
+    s.field_ms = r.last_field_ms;
+    s.pcg_iters = r.last_iters;
+    s.pcg_relres = r.last_relres;
+    s.crossings = r.last_cross;
+    s.reflections = r.last_refl;
+    s.spills = r.last_spill;
+    *out = s;
+    API_END
+}
+
+int32_t fempic_footprint(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes)
+{
+    API_BEGIN
+    if (!mesh || !bytes || n_particles < 0) throw Error(FEMPIC_EINVAL, "bad argument");
+    *bytes = Run::footprint_estimate(*mesh->m, n_particles, precision == FEMPIC_MIXED);
+    API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Run: device state of one simulation and its step sequencing.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "fempic_impl.h"
+#include "kernels.h"
+
+namespace fempic {
+
+void set_error(const std::string &s);
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void alloc(size_t n);
+    void release();
+};
+
+struct DevCSRBuf {
+    DevBuf ptr, idx, val, val32;
+    DevCSR desc{};
+};
+
+struct PBufs {
+    DevBuf x, v, vh, ah, tet, id;
+    DevParticles d{};
+};
+
+class Run {
+  public:
+    Run(const HostMesh &m, const fempic_params &p, hipStream_t s);
+    ~Run();
+    void load(const double *pos, const double *vel, int64_t n, double q, double m, double w);
+    void step(int n_steps);
+    void sync();
+    void gauss(double out[3]);
+    void fields_get(double *e, int64_t ne, double *b, int64_t nb);
+    void fields_set(const double *e, int64_t ne, const double *b, int64_t nb);
+    void deposit_get(double *dg, int64_t n);
+    void particles_get(double *pos, double *vel, int64_t *tet, int64_t n);
+    void history_get(double *vh, double *ah, int64_t n);
+    static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
+
+    const HostMesh &m;
+    fempic_params prm;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool mixed = false;
+    int order = 1, n1l = 0, n2l = 0, n0l = 0;
+    GLRule gl{};
+    DevMesh dm{};
+    // statistics
+    int64_t np = 0, steps_done = 0, last_cross = 0, last_refl = 0, last_spill = 0;
+    double last_particle_ms = 0, last_kernel_ms = 0, last_field_ms = 0, last_relres = 0;
+    int32_t last_iters = 0;
+    int64_t nnz_total = 0;
+
+  private:
+    void upload_csr(DevCSRBuf &d, const CSR &A, bool want32);
+    void zero(DevBuf &b);
+    size_t particle_bytes(int64_t n) const;
+    void alloc_particles(int64_t n);
+    void alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold);
+    void alloc_pool(int64_t cap);
+    DevParticles P(int k) const;
+    SpillPool pool() const;
+    int key_bits() const;
+    int tpw() const;
+    const uint32_t *sort_current();
+    void locate_host(const double *pos, int64_t n, int32_t *out);
+    void compute_rho(double *dst);
+    void particle_phase();
+    void field_phase();
+    void solve_fp64();
+    void solve_mixed();
+    double read_sc(int k);
+
+    DevBuf d_geo, d_nbr, d_map1, d_map2, d_map0;
+    DevCSRBuf A, Meps, Ct, K, Gt;
+    DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
+    DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
+    DevBuf v_x, v_r, v_z, v_p, v_q, v_rhs, v_tmp, v_u;
+    DevBuf f_x, f_r, f_z, f_p, f_q;
+    DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
+    DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_small;
+    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos;
+    std::vector<DevBuf> hp_sort, hp_ssort;
+    PBufs pb[2];
+    int cur = 0;
+    SortBuffers psort{}, ssort{};
+    int64_t pool_cap = 0, nrec_last = 0;
+    double q = 0, mass = 1, w = 0;
+    bool loaded = false;
+    int32_t sticky = 0;
+    std::string sticky_msg;
+    void *h_pin = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr, ev_e = nullptr;
+};
+
+}  // namespace fempic

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: FP64 mode, 1e-12 relative (norm-wise, on fields, deposits and
+particle states); mixed mode, 1e-5 relative on fields after 100 steps; Gauss
+residual R_G <= 1e-12 in both modes.
+"""
+import numpy as np
+import pytest
+
+import paper_2111_12411_amd as F
+from paper_2111_12411_amd import workloads as W
+from oracle import core, mesh as omesh
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = -W.Q_E, W.M_E
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def cfl(N, k):
+    """Oracle element bound at N, from the N=4 mesh (Kuhn meshes are similar: dt_cfl ~ 1/N)."""
+    m = omesh.cube_mesh(4, k)
+    return core.cfl_dt(m, core.assemble(m)) * 4.0 / N
+
+
+def pair(N, k, dt, pos, vel, w, precision=F.FP64, particles_only=False):
+    m = omesh.cube_mesh(N, k)
+    orc = core.OracleRun(m, dt, particles_only=particles_only)
+    orc.load(pos, vel, QE, ME, w)
+    run = F.Run(F.Mesh.cube(N, k), dt, precision, pcg_rtol=1e-14)
+    run.load(pos, vel, QE, ME, w)
+    return m, orc, run
+
+
+def test_c1_order1_fp64_100_steps():
+    """Plain FP64, order-1 Whitney, 4^3 cube, 1000 thermal electrons, dt = 5 dt_cfl, 100 steps."""
+    dt = 5 * cfl(4, 1)
+    pos, vel = W.config_particles(1)
+    w = W.plasma_weight(len(pos), dt)
+    m, orc, run = pair(4, 1, dt, pos, vel, w)
+    # start-up state
+    vh_g, ah_g = run.history()
+    assert rel(vh_g, orc.vh) < 1e-14
+    for n in range(100):
+        orc.step()
+        run.step()
+        if n < 5 or n % 10 == 9:
+            assert rel(run.deposit(), orc.last_dg * m.int1) < 1e-12, n
+            RG, RC, RS = run.gauss()
+            assert RG < 1e-12 and RC < 1e-12, (n, RG, RC, RS)
+    e, b = run.fields()
+    pos_g, vel_g, tet_g = run.particles()
+    assert rel(e, orc.e) < 1e-12
+    assert rel(b, orc.b) < 1e-12
+    assert rel(pos_g, orc.pos) < 1e-13
+    assert rel(vel_g, orc.vel) < 1e-12
+    assert np.mean(tet_g == orc.tet) > 0.999
+    st = run.stats()
+    assert st["steps"] == 100 and st["crossings"] > 0
+
+
+def test_order2_fp64_beam_parity():
+    """Order 2, FP64, 6^3 cube, 20k-electron beam at 0.1c, dt = 10 dt_cfl, 20 steps (walls reflect)."""
+    dt = 10 * cfl(6, 2)
+    pos, vel = W.particles("beam", 20000, 2007, vth=0.005, drift=0.1)
+    w = W.plasma_weight(len(pos), dt)
+    m, orc, run = pair(6, 2, dt, pos, vel, w)
+    for n in range(20):
+        orc.step()
+        run.step()
+        assert rel(run.deposit(), orc.last_dg * m.int1) < 1e-12, n
+    e, b = run.fields()
+    assert rel(e, orc.e) < 1e-12 and rel(b, orc.b) < 1e-12
+    pos_g, vel_g, _ = run.particles()
+    assert rel(pos_g, orc.pos) < 1e-13 and rel(vel_g, orc.vel) < 1e-12
+    RG, RC, RS = run.gauss()
+    assert RG < 1e-12, (RG, RC, RS)
+    assert run.stats()["reflections"] >= 0 and orc.counters[1] > 0
+
+
+def test_ragged_and_empty_inputs():
+    """Particle counts that leave ragged tiles, a single particle, and no particles."""
+    for n, N, k in [(1, 3, 1), (257, 3, 2), (0, 2, 1)]:
+        dt = 5 * cfl(N, k)
+        pos, vel = W.particles("thermal", n, 31 + n, vth=0.05)
+        rng = np.random.default_rng(n)
+        mm = omesh.cube_mesh(N, k)
+        e0, b0 = rng.normal(size=mm.n1) * 1e3 * mm.int1, rng.normal(size=mm.n2) * 1e-5
+        m, orc, run = pair(N, k, dt, pos, vel, 1.0)
+        orc.e, orc.b = e0.copy(), b0.copy()
+        run.set_fields(e0, b0)
+        for _ in range(3):
+            orc.step()
+            run.step()
+        e, b = run.fields()
+        assert rel(e, orc.e) < 1e-12 and rel(b, orc.b) < 1e-12
+        if n:
+            pos_g, vel_g, _ = run.particles()
+            assert rel(pos_g, orc.pos) < 1e-13
+
+
+def test_random_fields_one_step_exact():
+    """Nonzero E and B everywhere: one step, per-particle state and deposit (k = 1, 2)."""
+    for k in (1, 2):
+        N = 5
+        dt = 10 * cfl(N, k)
+        pos, vel = W.particles("beam", 5000, 77, vth=0.02, drift=0.15)
+        m = omesh.cube_mesh(N, k)
+        e0, b0 = W.random_fields(m.n1, m.n2, 5 + k, e_scale=2e4, b_scale=2e-4)
+        e0 = e0 * m.int1
+        m, orc, run = pair(N, k, dt, pos, vel, 1e3)
+        orc.e, orc.b = e0.copy(), b0.copy()
+        run.set_fields(e0, b0)
+        dg_o = orc.particle_step()
+        run.step()
+        assert rel(run.deposit(), dg_o * m.int1) < 1e-12
+        pos_g, vel_g, tet_g = run.particles()
+        assert rel(pos_g, orc.pos) < 1e-14
+        assert rel(vel_g, orc.vel) < 1e-13
+        vh_g, ah_g = run.history()
+        assert rel(vh_g, orc.vh) < 1e-13 and rel(ah_g, orc.ah) < 1e-13
+
+
+def test_bitwise_determinism():
+    dt = 10 * cfl(5, 2)
+    pos, vel = W.particles("beam", 30000, 99, vth=0.01, drift=0.15)
+    out = []
+    for rep in range(2):
+        run = F.Run(F.Mesh.cube(5, 2), dt, F.FP64, pcg_rtol=1e-14)
+        run.load(pos, vel, QE, ME, W.plasma_weight(len(pos), dt))
+        run.step(5)
+        e, b = run.fields()
+        p, v, t = run.particles()
+        out.append((e, b, p, v, t, run.deposit()))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_mixed_precision_fields_within_1e5():
+    """Mixed precision (FP32 gather/push + FP32 PCG with FP64 refinement) vs the FP64 oracle."""
+    dt = 10 * cfl(4, 2)
+    pos, vel = W.particles("thermal", 20000, 3007, vth=0.02)
+    w = W.plasma_weight(len(pos), dt)
+    m, orc, run = pair(4, 2, dt, pos, vel, w, precision=F.MIXED)
+    for n in range(100):
+        orc.step()
+        run.step()
+    e, b = run.fields()
+    assert rel(e, orc.e) < 1e-5 and rel(b, orc.b) < 1e-5, (rel(e, orc.e), rel(b, orc.b))
+    RG, RC, RS = run.gauss()
+    assert RG < 1e-12, (RG, RC, RS)
+
+
+@pytest.mark.parametrize("precision,tol_x,tol_v", [(F.FP64, 1e-13, 1e-12), (F.MIXED, 1e-9, 2e-5)])
+def test_full_size_sampled(precision, tol_x, tol_v):
+    """The benchmark's launch configuration (40^3 cube, order 2, 16M electrons):
+    one step with random fields; a sample of particles against the oracle one by
+    one, and charge continuity of the whole deposit (R_C) at full size."""
+    N, k, n = 40, 2, 16_000_000
+    dt = 10 * cfl(N, k)
+    pos, vel = W.config_particles(3)
+    assert len(pos) == n
+    m = omesh.cube_mesh(N, k)
+    e0, b0 = W.random_fields(m.n1, m.n2, 303, e_scale=1e3, b_scale=1e-5)
+    e0 = e0 * m.int1
+    run = F.Run(F.Mesh.cube(N, k), dt, precision, pcg_rtol=1e-14)
+    run.load(pos, vel, QE, ME, W.plasma_weight(n, dt))
+    run.set_fields(e0, b0)
+    run.step()
+    pos_g, vel_g, tet_g = run.particles()
+    RG, RC, RS = run.gauss()
+    assert RC < 1e-12, RC
+    assert RG < 1e-12, RG
+    idx = np.random.default_rng(5).choice(n, 3000, replace=False)
+    orc = core.OracleRun(m, dt, particles_only=True)
+    orc.load(pos[idx], vel[idx], QE, ME, 1.0)
+    orc.e, orc.b = e0.copy(), b0.copy()
+    orc.particle_step()
+    assert rel(pos_g[idx], orc.pos) < tol_x
+    assert rel(vel_g[idx], orc.vel) < tol_v
+    assert np.mean(tet_g[idx] == orc.tet) > 0.999
+
+
+def test_failure_modes():
+    m = F.Mesh.cube(3, 1)
+    run = F.Run(m, 1e-10, F.FP64)
+    with pytest.raises(F.FempicError) as ei:
+        run.load(np.array([[2.0, 2.0, 2.0]]), np.zeros((1, 3)), QE, ME, 1.0)
+    assert ei.value.code == -4  # EOUTSIDE
+    pos, vel = W.particles("thermal", 500, 5, vth=0.05)
+    run2 = F.Run(m, 5 * cfl(3, 1), F.FP64, pcg_rtol=1e-30, pcg_maxit=1)
+    run2.load(pos, vel, QE, ME, 1e6)
+    with pytest.raises(F.FempicError) as ei:
+        run2.step()
+    assert ei.value.code == -6  # ESOLVE
+    with pytest.raises(F.FempicError):  # sticky
+        run2.step()
