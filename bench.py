@@ -32,7 +32,7 @@ def algorithmic_bytes(order, precision, n_particles, n_tet):
     particle state read + write, plus per-tet field coefficients, DoF maps and
     geometry read once and the per-tet current partials written once."""
     rs = 4 if precision == F.MIXED else 8
-    state = 3 * 8 + 21 * rs + 4  # r (FP64), v, 3 v-history, 3 a-history, tet
+    state = 6 * 8 + 18 * rs + 4  # r, v (FP64), 3 v-history, 3 a-history (rs), tet
     n1, n2 = (6, 4) if order == 1 else (20, 15)
     per_tet = 16 * 8 + (n1 + n2) * (rs + 4) + n1 * 8
     return 2 * state * n_particles + per_tet * n_tet, state, per_tet

@@ -166,7 +166,8 @@ typedef struct {
     int64_t steps;            /* steps taken by this run */
     int64_t n_particles;
     double particle_ms;       /* last call: device time of sort + particle + deposit reduction, ms */
-    double particle_kernel_ms;/* last call: device time of the particle kernel alone, ms */
+    double particle_kernel_ms;/* last call: device time of the particle kernel (gather, push, first segment), ms */
+    double continue_kernel_ms;/* last call: device time of the kernel that tracks paths leaving their tet, ms */
     double field_ms;          /* last call: device time of the field update, ms */
     int32_t pcg_iters;        /* last step's PCG iterations (inner iterations in mixed mode) */
     double pcg_relres;        /* last step's final FP64 relative residual */

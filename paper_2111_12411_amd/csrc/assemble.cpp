@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
+#include <thread>
 
 #include "fempic_impl.h"
 
@@ -102,86 +104,117 @@ double jacobi_max_eig(std::vector<double> a, int n)
     return mx;
 }
 
-// Generic CSR from element contributions.  rmap/cmap give the global row /
-// column of a local index (or -1 to skip); mask (optional) drops structural
-// zeros; `assign` stores the value (all tets must agree) instead of adding.
-struct ElemSpec {
-    int64_t rows, cols;
-    int nr, nc;
-    std::function<int64_t(int64_t, int)> rmap, cmap;
-    const double *mask = nullptr;
-    bool assign = false;
+// Run f(lo, hi) over [0, n) split into contiguous chunks on the host's threads.
+template <typename F>
+void parallel_for(int64_t n, F f)
+{
+    int nth = (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+    nth = (int)std::max<int64_t>(1, std::min<int64_t>(nth, n));
+    std::vector<std::thread> th;
+    for (int k = 0; k < nth; k++) {
+        int64_t lo = n * k / nth, hi = n * (k + 1) / nth;
+        th.emplace_back([=, &f] { f(lo, hi); });
+    }
+    for (auto &t : th) t.join();
+}
+
+// row -> (tet, local row) incidence, tets ascending
+struct RowInc {
+    std::vector<int64_t> ptr, idx;  // idx = t * nr + i
 };
 
-void csr_pattern(const HostMesh &m, const ElemSpec &s, CSR &A)
+template <typename RMap>
+RowInc row_incidence(const HostMesh &m, int64_t rows, int nr, RMap rmap)
 {
-    A.rows = s.rows;
-    A.cols = s.cols;
-    // row -> (tet, local row) incidence, tet ascending
-    std::vector<int64_t> cnt(s.rows + 1, 0);
+    RowInc ri;
+    ri.ptr.assign(rows + 1, 0);
     for (int64_t t = 0; t < m.nt; t++)
-        for (int i = 0; i < s.nr; i++) {
-            int64_t r = s.rmap(t, i);
-            if (r >= 0) cnt[r + 1]++;
+        for (int i = 0; i < nr; i++) {
+            int64_t r = rmap(t, i);
+            if (r >= 0) ri.ptr[r + 1]++;
         }
-    for (int64_t r = 0; r < s.rows; r++) cnt[r + 1] += cnt[r];
-    std::vector<int64_t> inc(cnt[s.rows]);
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t r = 0; r < rows; r++) ri.ptr[r + 1] += ri.ptr[r];
+    ri.idx.assign(ri.ptr[rows], 0);
+    std::vector<int64_t> fill(ri.ptr.begin(), ri.ptr.end() - 1);
     for (int64_t t = 0; t < m.nt; t++)
-        for (int i = 0; i < s.nr; i++) {
-            int64_t r = s.rmap(t, i);
-            if (r >= 0) inc[fill[r]++] = t * s.nr + i;
+        for (int i = 0; i < nr; i++) {
+            int64_t r = rmap(t, i);
+            if (r >= 0) ri.idx[fill[r]++] = t * nr + i;
         }
-    A.ptr.assign(s.rows + 1, 0);
-    std::vector<int32_t> cols;
-    std::vector<int32_t> all;
-    all.reserve((size_t)s.rows * 16);
-    for (int64_t r = 0; r < s.rows; r++) {
-        cols.clear();
-        for (int64_t k = cnt[r]; k < cnt[r + 1]; k++) {
-            int64_t t = inc[k] / s.nr;
-            int i = (int)(inc[k] % s.nr);
-            for (int j = 0; j < s.nc; j++) {
-                if (s.mask && s.mask[i * s.nc + j] == 0.0) continue;
-                int64_t c = s.cmap(t, j);
-                if (c >= 0) cols.push_back((int32_t)c);
-            }
-        }
-        std::sort(cols.begin(), cols.end());
-        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-        all.insert(all.end(), cols.begin(), cols.end());
-        A.ptr[r + 1] = (int64_t)all.size();
-    }
-    A.idx.swap(all);
-    A.val.assign(A.idx.size(), 0.0);
+    return ri;
 }
 
-inline int64_t find_pos(const CSR &A, int64_t r, int32_t c)
+// CSR from element contributions, row-parallel.  Each row gathers the entries
+// of its incident tets in ascending tet order (deterministic sums).  cmap gives
+// the global column of a local column (or -1); mask (optional) drops structural
+// zeros; `assign` stores the value (every tet must agree) instead of adding.
+template <typename CMap, typename Val>
+void build_csr(const RowInc &ri, int64_t rows, int64_t cols, int nr, int nc, CMap cmap, const double *mask, Val val,
+               bool assign, CSR &A)
 {
-    const int32_t *b = A.idx.data() + A.ptr[r], *e = A.idx.data() + A.ptr[r + 1];
-    const int32_t *p = std::lower_bound(b, e, c);
-    return p - A.idx.data();
-}
-
-void csr_add(const ElemSpec &s, CSR &A, int64_t t, const double *el, std::vector<uint8_t> *set)
-{
-    for (int i = 0; i < s.nr; i++) {
-        int64_t r = s.rmap(t, i);
-        if (r < 0) continue;
-        for (int j = 0; j < s.nc; j++) {
-            if (s.mask && s.mask[i * s.nc + j] == 0.0) continue;
-            int64_t c = s.cmap(t, j);
-            if (c < 0) continue;
-            int64_t p = find_pos(A, r, (int32_t)c);
-            if (s.assign) {
-                if ((*set)[p] && A.val[p] != el[i * s.nc + j])
-                    throw Error(FEMPIC_EMESH, "local exterior derivative disagrees between tets");
-                A.val[p] = el[i * s.nc + j];
-                (*set)[p] = 1;
-            } else {
-                A.val[p] += el[i * s.nc + j];
+    A.rows = rows;
+    A.cols = cols;
+    const int nth = 64;
+    std::vector<std::vector<int32_t>> cidx(nth);
+    std::vector<std::vector<double>> cval(nth);
+    std::vector<int64_t> rowlen(rows, 0);
+    std::vector<int> bad(nth, 0);
+    parallel_for(nth, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; c++) {
+            const int64_t r0 = rows * c / nth, r1 = rows * (c + 1) / nth;
+            std::vector<int32_t> colv;
+            std::vector<double> vals;
+            std::vector<uint8_t> set;
+            for (int64_t r = r0; r < r1; r++) {
+                colv.clear();
+                for (int64_t k = ri.ptr[r]; k < ri.ptr[r + 1]; k++) {
+                    const int64_t t = ri.idx[k] / nr;
+                    const int i = (int)(ri.idx[k] % nr);
+                    for (int j = 0; j < nc; j++) {
+                        if (mask && mask[i * nc + j] == 0.0) continue;
+                        const int64_t cc = cmap(t, j);
+                        if (cc >= 0) colv.push_back((int32_t)cc);
+                    }
+                }
+                std::sort(colv.begin(), colv.end());
+                colv.erase(std::unique(colv.begin(), colv.end()), colv.end());
+                vals.assign(colv.size(), 0.0);
+                set.assign(colv.size(), 0);
+                for (int64_t k = ri.ptr[r]; k < ri.ptr[r + 1]; k++) {
+                    const int64_t t = ri.idx[k] / nr;
+                    const int i = (int)(ri.idx[k] % nr);
+                    for (int j = 0; j < nc; j++) {
+                        if (mask && mask[i * nc + j] == 0.0) continue;
+                        const int64_t cc = cmap(t, j);
+                        if (cc < 0) continue;
+                        const size_t p = std::lower_bound(colv.begin(), colv.end(), (int32_t)cc) - colv.begin();
+                        const double v = val(t, i, j);
+                        if (assign) {
+                            if (set[p] && vals[p] != v) bad[c] = 1;
+                            vals[p] = v;
+                            set[p] = 1;
+                        } else {
+                            vals[p] += v;
+                        }
+                    }
+                }
+                rowlen[r] = (int64_t)colv.size();
+                cidx[c].insert(cidx[c].end(), colv.begin(), colv.end());
+                cval[c].insert(cval[c].end(), vals.begin(), vals.end());
             }
         }
+    });
+    for (int c = 0; c < nth; c++)
+        if (bad[c]) throw Error(FEMPIC_EMESH, "local exterior derivative disagrees between tets");
+    A.ptr.assign(rows + 1, 0);
+    for (int64_t r = 0; r < rows; r++) A.ptr[r + 1] = A.ptr[r] + rowlen[r];
+    A.idx.resize(A.ptr[rows]);
+    A.val.resize(A.ptr[rows]);
+    int64_t off = 0;
+    for (int c = 0; c < nth; c++) {
+        std::copy(cidx[c].begin(), cidx[c].end(), A.idx.begin() + off);
+        std::copy(cval[c].begin(), cval[c].end(), A.val.begin() + off);
+        off += (int64_t)cidx[c].size();
     }
 }
 
@@ -254,7 +287,7 @@ void assemble(const HostMesh &m, double dt, Operators &ops)
 {
     const RefElem &R = ref_elem(m.order);
     const int n1 = R.n1, n2 = R.n2, n0 = R.n0;
-    const int64_t N1i = m.N1_int, N0i = m.N0_int;
+    const int64_t N1i = m.N1_int, N0i = m.N0_int, nt = m.nt;
     auto w1int = [&](int64_t t, int i) -> int64_t {
         int32_t d = m.map1[t * n1 + i];
         return d < N1i ? d : -1;
@@ -264,47 +297,50 @@ void assemble(const HostMesh &m, double dt, Operators &ops)
         int32_t d = m.map0[t * n0 + j];
         return d < N0i ? d : -1;
     };
-
-    ElemSpec sA{N1i, N1i, n1, n1, w1int, w1int};
-    ElemSpec sC{N1i, m.N2, n1, n2, w1int, w2};
-    ElemSpec sK{m.N2, N1i, n2, n1, w2, w1int, R.K.data(), true};
+    // element matrices of every tet: eps0 M1, curl-curl S / mu0, K^T M2 / mu0
+    // (uninitialised storage: every entry is written by the parallel loop below)
+    std::unique_ptr<double[]> Mel(new double[(size_t)nt * n1 * n1]), Sel(new double[(size_t)nt * n1 * n1]),
+        Cel(new double[(size_t)nt * n1 * n2]);
+    parallel_for(nt, [&](int64_t t0, int64_t t1) {
+        std::vector<double> M1(n1 * n1), M2(n2 * n2), S(n1 * n1), KtM2(n1 * n2);
+        for (int64_t t = t0; t < t1; t++) {
+            element_mass(m, t, M1.data(), M2.data());
+            curl_products(R, M2.data(), S.data(), KtM2.data());
+            double *me = &Mel[(size_t)t * n1 * n1], *se = &Sel[(size_t)t * n1 * n1], *ce = &Cel[(size_t)t * n1 * n2];
+            for (int i = 0; i < n1 * n1; i++) {
+                me[i] = EPS0 * M1[i];
+                se[i] = S[i] / MU0;
+            }
+            for (int i = 0; i < n1 * n2; i++) ce[i] = KtM2[i] / MU0;
+        }
+    });
+    const double c_stiff = dt * dt / 4.0;
+    RowInc r1 = row_incidence(m, N1i, n1, w1int);
+    build_csr(r1, N1i, N1i, n1, n1, w1int, nullptr,
+              [&](int64_t t, int i, int j) {
+                  const size_t k = ((size_t)t * n1 + i) * n1 + j;
+                  return Mel[k] + c_stiff * Sel[k];
+              },
+              false, ops.A);
+    build_csr(r1, N1i, N1i, n1, n1, w1int, nullptr,
+              [&](int64_t t, int i, int j) { return Mel[((size_t)t * n1 + i) * n1 + j]; }, false, ops.Meps);
+    build_csr(r1, N1i, m.N2, n1, n2, w2, nullptr,
+              [&](int64_t t, int i, int l) { return Cel[((size_t)t * n1 + i) * n2 + l]; }, false, ops.Ct);
+    RowInc r2 = row_incidence(m, m.N2, n2, w2);
+    build_csr(r2, m.N2, N1i, n2, n1, w1int, R.K.data(), [&](int64_t, int l, int i) { return R.K[l * n1 + i]; },
+              true, ops.K);
     std::vector<double> Gt(n0 * n1);
     for (int j = 0; j < n0; j++)
         for (int i = 0; i < n1; i++) Gt[j * n1 + i] = R.G[i * n0 + j];
-    ElemSpec sG{N0i, N1i, n0, n1, w0int, w1int, Gt.data(), true};
-
-    csr_pattern(m, sA, ops.A);
-    ops.Meps.rows = ops.A.rows;
-    ops.Meps.cols = ops.A.cols;
-    ops.Meps.ptr = ops.A.ptr;
-    ops.Meps.idx = ops.A.idx;
-    ops.Meps.val.assign(ops.A.idx.size(), 0.0);
-    csr_pattern(m, sC, ops.Ct);
-    csr_pattern(m, sK, ops.K);
-    csr_pattern(m, sG, ops.Gt);
-
-    std::vector<double> M1(n1 * n1), M2(n2 * n2), S(n1 * n1), KtM2(n1 * n2), Ael(n1 * n1), Mel(n1 * n1),
-        Cel(n1 * n2);
-    std::vector<uint8_t> setK(ops.K.idx.size(), 0), setG(ops.Gt.idx.size(), 0);
-    const double c_stiff = dt * dt / 4.0 / MU0;
-    for (int64_t t = 0; t < m.nt; t++) {
-        element_mass(m, t, M1.data(), M2.data());
-        curl_products(R, M2.data(), S.data(), KtM2.data());
-        for (int i = 0; i < n1 * n1; i++) {
-            Mel[i] = EPS0 * M1[i];
-            Ael[i] = Mel[i] + c_stiff * S[i];
-        }
-        for (int i = 0; i < n1 * n2; i++) Cel[i] = KtM2[i] / MU0;
-        csr_add(sA, ops.A, t, Ael.data(), nullptr);
-        csr_add(sA, ops.Meps, t, Mel.data(), nullptr);
-        csr_add(sC, ops.Ct, t, Cel.data(), nullptr);
-        csr_add(sK, ops.K, t, R.K.data(), &setK);
-        csr_add(sG, ops.Gt, t, Gt.data(), &setG);
-    }
+    RowInc r0 = row_incidence(m, N0i, n0, w0int);
+    build_csr(r0, N0i, N1i, n0, n1, w1int, Gt.data(), [&](int64_t, int j, int i) { return Gt[j * n1 + i]; }, true,
+              ops.Gt);
     ops.Adiag_inv.assign(N1i, 0.0);
     for (int64_t r = 0; r < N1i; r++) {
-        int64_t p = find_pos(ops.A, r, (int32_t)r);
-        double d = ops.A.val[p];
+        const int32_t *b = ops.A.idx.data() + ops.A.ptr[r], *e = ops.A.idx.data() + ops.A.ptr[r + 1];
+        const int32_t *p = std::lower_bound(b, e, (int32_t)r);
+        if (p == e || *p != r) throw Error(FEMPIC_EMESH, "field matrix row without a diagonal");
+        const double d = ops.A.val[p - ops.A.idx.data()];
         if (!(d > 0)) throw Error(FEMPIC_EMESH, "field matrix has a non-positive diagonal");
         ops.Adiag_inv[r] = 1.0 / d;
     }

@@ -21,11 +21,11 @@ struct DevMesh {
     double cube_L;
 };
 
-// Particle state, structure of arrays.  Positions are FP64 in both modes; the
-// velocity and the AB4 history are R (double, or float in mixed mode).
+// Particle state, structure of arrays.  Position and velocity are FP64 in both
+// modes; the AB4 histories are R (double, or float in mixed mode).
 struct DevParticles {
     double *x;     // [3][cap]
-    void *v;       // [3][cap]   R
+    void *v;       // [3][cap]   double
     void *vh;      // [9][cap]   R: v^{n-1}, v^{n-2}, v^{n-3}
     void *ah;      // [9][cap]   R: a^{n-1}, a^{n-2}, a^{n-3}
     int32_t *tet;  // [cap]
@@ -50,6 +50,21 @@ struct SpillPool {
     int32_t *count;  // [1] records written (atomic)
     int32_t *pcount; // [np] spills of each sorted particle
     int64_t cap;
+};
+
+// particles whose path leaves the home tet during the step
+struct ContRec {
+    double cp[15];   // path coefficients r(s) = sum_d cp[3d + c] s^d (after wall reflections so far)
+    double s_lo;     // path parameter where the particle entered tet t
+    int32_t i;       // sorted particle index
+    int32_t t;       // current tet
+    int32_t entry;   // entry face of t (its barycentric coordinate is zero at s_lo)
+    int32_t ncross;  // face crossings so far
+};
+
+struct ContQueue {
+    ContRec *rec;    // capacity: number of particles
+    int32_t *count;  // [1] records written (atomic)
 };
 
 struct Counters {  // device int64 [4]: crossings, reflections, spills, error bits
@@ -82,7 +97,9 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
 hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
                            const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
                            DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
-                           Counters cnt, hipStream_t s);
+                           ContQueue cq, Counters cnt, hipStream_t s);
+hipError_t launch_continue(int order, bool mixed, const DevMesh &m, DevParticles out, int64_t np, StepParams sp,
+                           const GLRule &gl, SpillPool pool, ContQueue cq, Counters cnt, hipStream_t s);
 hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
                                 uint32_t *val, hipStream_t s);
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,

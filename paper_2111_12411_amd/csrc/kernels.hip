@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -196,15 +197,16 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
         cross3(gr[EA[q]], gr[EB[q]], X);
         for (int k = 0; k < 3; k++) B[k] += cB[q] * X[k];
     }
-    R v[3], vxB[3], a[3];
-    load_vec<R>(P.v, P.cap, 0, p, v, 3);
+    double vd[3];
+    load_vec<double>(P.v, P.cap, 0, p, vd, 3);
+    R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]}, vxB[3], a[3];
     cross3(v, B, vxB);
     for (int k = 0; k < 3; k++) a[k] = (R)qm * (E[k] + vxB[k]);
     R vh[9], ah[9];
     for (int j = 1; j <= 3; j++)
         for (int k = 0; k < 3; k++) {
             ah[3 * (j - 1) + k] = a[k];
-            vh[3 * (j - 1) + k] = (R)((double)v[k] - j * dt * (double)a[k]);
+            vh[3 * (j - 1) + k] = (R)(vd[k] - j * dt * (double)a[k]);
         }
     store_vec<R>(P.vh, P.cap, 0, p, vh, 9);
     store_vec<R>(P.ah, P.cap, 0, p, ah, 9);
@@ -295,19 +297,29 @@ __device__ bool first_negative(const double *q, double H, double &uout)
             if (!any_neg) {
                 advance = true;
             } else if (changes == 1 && bc[4] < 0.0) {
-                // one crossing in (lo, hi): q(lo) >= 0, q(hi) < 0
-                double a = lo, b = hi;
-                double x = 0.5 * (a + b);
-                for (int it = 0; it < 80; it++) {
-                    double fx = horner4(q, x);
-                    if (fx < 0.0) b = x; else a = x;
-                    if (!(b - a > 4e-16 * fmax(1.0, fabs(b)))) break;
-                    double dfx = dhorner4(q, x);
-                    double xn = x - fx / dfx;
+                // one crossing in (lo, hi): q(lo) >= 0 > q(hi).  Regula-falsi start,
+                // then Newton steps kept inside the shrinking bracket (bisection
+                // when a step leaves it); stop when the step is below 2 ulp.
+                double a = lo, b = hi, fa = bc[0], fb = bc[4];
+                double x = a + (b - a) * (fa / (fa - fb));
+                if (!(x > a && x < b)) x = 0.5 * (a + b);
+                for (int it = 0; it < 60; it++) {
+                    const double fx = horner4(q, x);
+                    if (fx == 0.0) break;
+                    if (fx < 0.0) {
+                        b = x;
+                        fb = fx;
+                    } else {
+                        a = x;
+                        fa = fx;
+                    }
+                    double xn = x - fx / dhorner4(q, x);
                     if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+                    const double step = fabs(xn - x);
                     x = xn;
+                    if (step <= 4e-16 * fabs(x) || !(b - a > 4e-16 * fabs(b))) break;
                 }
-                uout = fmin(fmax(x, a), b);
+                uout = fmin(fmax(x, lo), hi);
                 return true;
             } else if (d >= MAXD) {
                 advance = true;  // tangency narrower than H 2^-40
@@ -371,11 +383,136 @@ __device__ inline void deposit_segment(const double L[4][5], double sa, double s
 }
 
 // -------------------------------------------------------------- particle
+// exit of tet G from s_lo along the path cp: first s where a barycentric
+// coordinate turns negative (the entry face's coordinate is zero at s_lo)
+__device__ inline int find_exit(const double *G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
+{
+    s_exit = 2.0;
+    int f_exit = -1;
+    const double H = 1.0 - s_lo;
+    if (!(H > 0.0)) return -1;
+#pragma unroll 1
+    for (int f = 0; f < 4; f++) {
+        const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+        double q[5];
+#pragma unroll
+        for (int d = 0; d < 5; d++) q[d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
+        q[0] += a0;
+        taylor_shift(q, s_lo, q);
+        if (f == entry) q[0] = 0.0;
+        double u;
+        if (first_negative(q, H, u)) {
+            const double sx = s_lo + u;
+            if (sx < s_exit) {
+                s_exit = sx;
+                f_exit = f;
+            }
+        }
+    }
+    return f_exit;
+}
+
+// current moments of the segment [sa, sb] of path cp inside tet G
+template <int K>
+__device__ inline void segment_moments(const double *G, const double (&cp)[5][3], double sa, double sb, double qw,
+                                       const GLRule &gl, double *dep)
+{
+    double L[4][5];
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+#pragma unroll
+        for (int d = 0; d < 5; d++) L[f][d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
+        L[f][0] += a0;
+    }
+#pragma unroll
+    for (int c = 0; c < Ord<K>::N1; c++) dep[c] = 0.0;
+    deposit_segment<K>(L, sa, sb, qw, gl, dep);
+}
+
+// leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
+// rest of the path about the face plane together with the stored velocity and
+// AB4 histories of particle i (written before tracking)
+template <typename R>
+__device__ inline void cross_face(const DevMesh &m, const double *G, int f, int &t, int &entry, double (&cp)[5][3],
+                                  const DevParticles &out, int64_t i, unsigned long long &nrf)
+{
+    const int nb = m.nbr[(int64_t)t * 4 + f];
+    if (nb >= 0) {
+        int en = -1;
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (m.nbr[(int64_t)nb * 4 + q] == t) en = q;
+        entry = en;
+        t = nb;
+        return;
+    }
+    const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+    const double inv = 2.0 / (gx * gx + gy * gy + gz * gz);
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+        const double sd = (gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2] + (d == 0 ? a0 : 0.0)) * inv;
+        cp[d][0] -= sd * gx;
+        cp[d][1] -= sd * gy;
+        cp[d][2] -= sd * gz;
+    }
+    {
+        double *vp = (double *)out.v;
+        const double sd = (gx * vp[i] + gy * vp[out.cap + i] + gz * vp[2 * out.cap + i]) * inv;
+        vp[i] -= sd * gx;
+        vp[out.cap + i] -= sd * gy;
+        vp[2 * out.cap + i] -= sd * gz;
+    }
+#pragma unroll 1
+    for (int h = 0; h < 6; h++) {
+        R *hp = (R *)(h < 3 ? out.vh : out.ah) + (int64_t)(3 * (h % 3)) * out.cap;
+        const double x0 = hp[i], x1 = hp[out.cap + i], x2 = hp[2 * out.cap + i];
+        const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
+        hp[i] = (R)(x0 - sd * gx);
+        hp[out.cap + i] = (R)(x1 - sd * gy);
+        hp[2 * out.cap + i] = (R)(x2 - sd * gz);
+    }
+    nrf++;
+    entry = f;
+}
+
+// wave-aggregated slot in a shared append buffer
+__device__ inline int64_t append_slot(int32_t *count)
+{
+    const unsigned long long mask = __ballot(1);
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    int basei = 0;
+    if (lane == leader) basei = atomicAdd(count, __popcll(mask));
+    basei = __shfl(basei, leader);
+    return (int64_t)basei + rank;
+}
+
+__device__ inline void write_spill(const SpillPool &pool, int N1, int t, int64_t i, int &nsp_i, const double *dep,
+                                   int &errs)
+{
+    const int64_t slot_out = append_slot(pool.count);
+    if (slot_out < pool.cap && nsp_i < 64) {
+        pool.tet[slot_out] = t;
+        pool.tag[slot_out] = (i << 6) | nsp_i;
+        double *dst = &pool.val[slot_out * N1];
+        for (int c = 0; c < N1; c++) dst[c] = dep[c];
+    } else {
+        errs |= ERR_POOL;
+    }
+    nsp_i++;
+}
+
+// Kernel 1: per particle (sorted by tet), gather + AB4 push + the first path
+// segment, which lies in the home tet; its current moments are summed per tet
+// in LDS in a fixed order.  A particle whose path leaves the home tet is queued
+// for k_continue.
 template <int K, typename R>
 __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict__ e, const R *__restrict__ b,
                                                   const uint32_t *__restrict__ perm, const int32_t *__restrict__ off,
                                                   DevParticles in, DevParticles out, int64_t np, StepParams sp,
-                                                  GLRule gl, double *__restrict__ P, SpillPool pool,
+                                                  GLRule gl, double *__restrict__ P, SpillPool pool, ContQueue cq,
                                                   unsigned long long *__restrict__ cnt)
 {
     using O = Ord<K>;
@@ -419,7 +556,7 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
     const int wt = tid / N1, wc = tid % N1;
     const bool worker = tid < ntl * N1;
     double acc = 0.0;
-    unsigned long long ncr = 0, nrf = 0, nsp = 0;
+    unsigned long long ncr = 0, nrf = 0;
     int errs = 0;
     const R dtR = (R)sp.dt;
     const R qmR = (R)sp.qm;
@@ -433,10 +570,12 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
             const int th = in.tet[slot];
             const int lt = th - T0;
             double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
-            R v[3], vh[9], ah[9];
-            load_vec<R>(in.v, in.cap, 0, slot, v, 3);
+            double vd[3];
+            R vh[9], ah[9];
+            load_vec<double>(in.v, in.cap, 0, slot, vd, 3);
             load_vec<R>(in.vh, in.cap, 0, slot, vh, 9);
             load_vec<R>(in.ah, in.cap, 0, slot, ah, 9);
+            const R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
             // barycentrics and fields at r^n (home tet, LDS)
             R lam[4];
 #pragma unroll
@@ -454,180 +593,69 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
             for (int q = 0; q < 6; q++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) B[c] += cB[q] * s_X[lt][3 * q + c];
-            // Lorentz acceleration, AB4 velocity
-            R vxB[3], a[3], vn[3];
+            // Lorentz acceleration (precision R); AB4 velocity increment in R added to the FP64 velocity
+            R vxB[3], a[3];
+            double vn[3];
             cross3(v, B, vxB);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 a[c] = qmR * (E[c] + vxB[c]);
-                vn[c] = v[c] + dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]);
+                vn[c] = vd[c] + (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
             }
             // quartic path r(s) = sum_d c_d s^d (FP64 in both modes)
             double cp[5][3];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 cp[0][c] = r[c];
-                const double v0 = (double)v[c], v1 = (double)vh[c], v2 = (double)vh[3 + c], v3 = (double)vh[6 + c];
+                const double v0 = vd[c], v1 = (double)vh[c], v2 = (double)vh[3 + c], v3 = (double)vh[6 + c];
 #pragma unroll
                 for (int d = 1; d < 5; d++)
                     cp[d][c] = sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
             }
-            // new velocity and shifted histories
-            R nvh[9] = {v[0], v[1], v[2], vh[0], vh[1], vh[2], vh[3], vh[4], vh[5]};
-            R nah[9] = {a[0], a[1], a[2], ah[0], ah[1], ah[2], ah[3], ah[4], ah[5]};
-            // ------------------------------------------------ track + deposit
-            int t = th, entry = -1, ncross = 0, nsp_i = 0;
-            double s_lo = 0.0;
-            bool reflected = false;
-            double Rm[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-            for (;;) {
-                double g[16];
-                if (t >= T0 && t < T1) {
-#pragma unroll
-                    for (int k = 0; k < 16; k++) g[k] = s_geo[t - T0][k];
-                } else {
-                    const double4 *gp = (const double4 *)&m.geo[(int64_t)t * 16];
-#pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        double4 q = gp[k];
-                        g[4 * k] = q.x;
-                        g[4 * k + 1] = q.y;
-                        g[4 * k + 2] = q.z;
-                        g[4 * k + 3] = q.w;
-                    }
-                }
-                double L[4][5];
-#pragma unroll
-                for (int f = 0; f < 4; f++) {
-#pragma unroll
-                    for (int d = 0; d < 5; d++)
-                        L[f][d] = g[4 * f + 1] * cp[d][0] + g[4 * f + 2] * cp[d][1] + g[4 * f + 3] * cp[d][2];
-                    L[f][0] += g[4 * f];
-                }
-                double s_exit = 2.0;
-                int f_exit = -1;
-                const double H = 1.0 - s_lo;
-                if (H > 0.0) {
-#pragma unroll
-                    for (int f = 0; f < 4; f++) {
-                        double q[5];
-                        taylor_shift(L[f], s_lo, q);
-                        if (f == entry) q[0] = 0.0;
-                        double u;
-                        if (first_negative(q, H, u)) {
-                            const double s = s_lo + u;
-                            if (s < s_exit) {
-                                s_exit = s;
-                                f_exit = f;
-                            }
-                        }
-                    }
-                }
-                const double s_hi = f_exit < 0 ? 1.0 : s_exit;
-                if (s_hi > s_lo) {
-                    double dep[N1];
-#pragma unroll
-                    for (int c = 0; c < N1; c++) dep[c] = 0.0;
-                    deposit_segment<K>(L, s_lo, s_hi, sp.qw, gl, dep);
-                    if (t == th) {
-#pragma unroll
-                        for (int c = 0; c < N1; c++) s_hc[c][tid] += dep[c];
-                    } else {
-                        // append to the spill pool (wave-aggregated atomic slot)
-                        const unsigned long long mask = __ballot(1);
-                        const int lane = __lane_id();
-                        const int leader = __ffsll((long long)mask) - 1;
-                        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-                        int basei = 0;
-                        if (lane == leader) basei = atomicAdd(pool.count, __popcll(mask));
-                        basei = __shfl(basei, leader);
-                        const int64_t slot_out = (int64_t)basei + rank;
-                        if (slot_out < pool.cap && nsp_i < 64) {
-                            pool.tet[slot_out] = t;
-                            pool.tag[slot_out] = ((int64_t)i << 6) | nsp_i;
-                            double *dst = &pool.val[slot_out * N1];
-#pragma unroll
-                            for (int c = 0; c < N1; c++) dst[c] = dep[c];
-                        } else {
-                            errs |= ERR_POOL;
-                        }
-                        nsp_i++;
-                    }
-                }
-                if (f_exit < 0) break;
-                if (++ncross > 64) {
-                    errs |= ERR_CROSS;
-                    break;
-                }
-                const int nb = m.nbr[(int64_t)t * 4 + f_exit];
-                if (nb >= 0) {
-                    int en = -1;
-#pragma unroll
-                    for (int f = 0; f < 4; f++)
-                        if (m.nbr[(int64_t)nb * 4 + f] == t) en = f;
-                    entry = en;
-                    t = nb;
-                } else {
-                    // PEC wall: mirror the path about the plane l_f = 0
-                    const double gx = g[4 * f_exit + 1], gy = g[4 * f_exit + 2], gz = g[4 * f_exit + 3];
-                    const double gg = gx * gx + gy * gy + gz * gz;
-#pragma unroll
-                    for (int d = 0; d < 5; d++) {
-                        double s = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2] + (d == 0 ? g[4 * f_exit] : 0.0);
-                        s = 2.0 * s / gg;
-                        cp[d][0] -= s * gx;
-                        cp[d][1] -= s * gy;
-                        cp[d][2] -= s * gz;
-                    }
-                    const double gv[3] = {gx, gy, gz};
-                    double Rn[9];
-#pragma unroll
-                    for (int a2 = 0; a2 < 3; a2++)
-#pragma unroll
-                        for (int b2 = 0; b2 < 3; b2++) {
-                            double s = 0;
-#pragma unroll
-                            for (int k2 = 0; k2 < 3; k2++)
-                                s += ((a2 == k2 ? 1.0 : 0.0) - 2.0 * gv[a2] * gv[k2] / gg) * Rm[3 * k2 + b2];
-                            Rn[3 * a2 + b2] = s;
-                        }
-#pragma unroll
-                    for (int k2 = 0; k2 < 9; k2++) Rm[k2] = Rn[k2];
-                    reflected = true;
-                    nrf++;
-                    entry = f_exit;
-                }
-                s_lo = s_exit;
+            // new velocity and shifted histories, written now (wall reflections patch them)
+            {
+                const R nvh[9] = {v[0], v[1], v[2], vh[0], vh[1], vh[2], vh[3], vh[4], vh[5]};
+                const R nah[9] = {a[0], a[1], a[2], ah[0], ah[1], ah[2], ah[3], ah[4], ah[5]};
+                store_vec<double>(out.v, out.cap, 0, i, vn, 3);
+                store_vec<R>(out.vh, out.cap, 0, i, nvh, 9);
+                store_vec<R>(out.ah, out.cap, 0, i, nah, 9);
+                out.id[i] = in.id[slot];
             }
-            ncr += ncross;
-            nsp += nsp_i;
-            pool.pcount[i] = nsp_i;
-            if (reflected) {
-                auto mir = [&](R *w3) {
-                    double x0 = w3[0], x1 = w3[1], x2 = w3[2];
-                    for (int c = 0; c < 3; c++) w3[c] = (R)(Rm[3 * c] * x0 + Rm[3 * c + 1] * x1 + Rm[3 * c + 2] * x2);
-                };
-                mir(vn);
-                mir(&nvh[0]);
-                mir(&nvh[3]);
-                mir(&nvh[6]);
-                mir(&nah[0]);
-                mir(&nah[3]);
-                mir(&nah[6]);
-            }
-            double rn[3];
+            // first segment: in the home tet from s = 0
+            const double *G = &s_geo[lt][0];
+            double s_exit;
+            const int f_exit = find_exit(G, cp, 0.0, -1, s_exit);
+            const double s_hi = f_exit < 0 ? 1.0 : s_exit;
+            if (s_hi > 0.0) {
+                double dep[N1];
+                segment_moments<K>(G, cp, 0.0, s_hi, sp.qw, gl, dep);
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
-                rn[c] = horner4(pc, 1.0);
-                out.x[(int64_t)c * out.cap + i] = rn[c];
+                for (int c = 0; c < N1; c++) s_hc[c][tid] = dep[c];
             }
-            if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
-            store_vec<R>(out.v, out.cap, 0, i, vn, 3);
-            store_vec<R>(out.vh, out.cap, 0, i, nvh, 9);
-            store_vec<R>(out.ah, out.cap, 0, i, nah, 9);
-            out.tet[i] = t;
-            out.id[i] = in.id[slot];
+            pool.pcount[i] = 0;
+            if (f_exit < 0) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
+                    out.x[(int64_t)c * out.cap + i] = horner4(pc, 1.0);
+                }
+                out.tet[i] = th;
+            } else {
+                ncr++;
+                int t = th, entry = -1;
+                cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
+                const int64_t qi = append_slot(cq.count);
+                ContRec &rec = cq.rec[qi];  // capacity = particles: never overflows
+#pragma unroll
+                for (int d = 0; d < 5; d++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) rec.cp[3 * d + c] = cp[d][c];
+                rec.s_lo = s_exit;
+                rec.i = i;
+                rec.t = t;
+                rec.entry = entry;
+                rec.ncross = 1;
+            }
         }
         __syncthreads();
         if (worker) {
@@ -638,7 +666,70 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
         __syncthreads();
     }
     if (worker) P[(int64_t)(T0 + wt) * N1 + wc] = acc;
-    // counters: wave sums, one integer atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        ncr += __shfl_xor(ncr, o);
+        nrf += __shfl_xor(nrf, o);
+        errs |= __shfl_xor(errs, o);
+    }
+    if (__lane_id() == 0) {
+        if (ncr) atomicAdd(&cnt[0], ncr);
+        if (nrf) atomicAdd(&cnt[1], nrf);
+        if (errs) atomicOr(&cnt[3], (unsigned long long)errs);
+    }
+}
+
+// Kernel 2: the rest of the paths of queued particles, segment by segment;
+// every segment's current moments go to the spill pool tagged with
+// (sorted particle, segment), so their reduction order is canonical.
+template <int K, typename R>
+__global__ __launch_bounds__(BLK) void k_continue(DevMesh m, DevParticles out, StepParams sp, GLRule gl,
+                                                  SpillPool pool, ContQueue cq, unsigned long long *__restrict__ cnt)
+{
+    constexpr int N1 = Ord<K>::N1;
+    const int32_t nq = *cq.count;
+    unsigned long long ncr = 0, nrf = 0, nsp = 0;
+    int errs = 0;
+    for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < nq; r += (int64_t)gridDim.x * BLK) {
+        const ContRec &rec = cq.rec[r];
+        double cp[5][3];
+#pragma unroll
+        for (int d = 0; d < 5; d++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) cp[d][c] = rec.cp[3 * d + c];
+        double s_lo = rec.s_lo;
+        const int64_t i = rec.i;
+        int t = rec.t, entry = rec.entry, ncross = rec.ncross, nsp_i = 0;
+        for (;;) {
+            const double *G = &m.geo[(int64_t)t * 16];
+            double s_exit;
+            const int f_exit = find_exit(G, cp, s_lo, entry, s_exit);
+            const double s_hi = f_exit < 0 ? 1.0 : s_exit;
+            if (s_hi > s_lo) {
+                double dep[N1];
+                segment_moments<K>(G, cp, s_lo, s_hi, sp.qw, gl, dep);
+                write_spill(pool, N1, t, i, nsp_i, dep, errs);
+            }
+            if (f_exit < 0) break;
+            if (++ncross > 64) {
+                errs |= ERR_CROSS;
+                break;
+            }
+            ncr++;
+            cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
+            s_lo = s_exit;
+        }
+        nsp += nsp_i;
+        pool.pcount[i] = nsp_i;
+        double rn[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
+            rn[c] = horner4(pc, 1.0);
+            out.x[(int64_t)c * out.cap + i] = rn[c];
+        }
+        if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
+        out.tet[i] = t;
+    }
     for (int o = 32; o > 0; o >>= 1) {
         ncr += __shfl_xor(ncr, o);
         nrf += __shfl_xor(nrf, o);
@@ -1229,23 +1320,37 @@ hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *o
 hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
                            const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
                            DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
-                           Counters cnt, hipStream_t s)
+                           ContQueue cq, Counters cnt, hipStream_t s)
 {
     const unsigned grid = (unsigned)((m.nt + sp.tpw - 1) / sp.tpw);
     if (order == 1) {
         if (mixed)
             hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
-                               sp, gl, P, pool, cnt.c);
+                               sp, gl, P, pool, cq, cnt.c);
         else
             hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
-                               sp, gl, P, pool, cnt.c);
+                               sp, gl, P, pool, cq, cnt.c);
     } else {
         if (mixed)
             hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
-                               sp, gl, P, pool, cnt.c);
+                               sp, gl, P, pool, cq, cnt.c);
         else
             hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
-                               sp, gl, P, pool, cnt.c);
+                               sp, gl, P, pool, cq, cnt.c);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_continue(int order, bool mixed, const DevMesh &m, DevParticles out, int64_t np, StepParams sp,
+                           const GLRule &gl, SpillPool pool, ContQueue cq, Counters cnt, hipStream_t s)
+{
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (np + BLK - 1) / BLK));
+    if (order == 1) {
+        if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
+        else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
+    } else {
+        if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
+        else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
     }
     return hipGetLastError();
 }

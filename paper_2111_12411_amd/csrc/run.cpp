@@ -177,14 +177,14 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_cnt.alloc(8 * 8);
     d_small.alloc(64);
     HIPCHECK(hipHostMalloc(&h_pin, 256, hipHostMallocDefault));
-    for (auto *ev : {&ev_a, &ev_b, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
+    for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
     HIPCHECK(hipStreamSynchronize(stream));
 }
 
 Run::~Run()
 {
     if (stream) (void)hipStreamSynchronize(stream);
-    for (auto ev : {ev_a, ev_b, ev_c, ev_d, ev_e})
+    for (auto ev : {ev_a, ev_b, ev_c1, ev_c, ev_d, ev_e})
         if (ev) (void)hipEventDestroy(ev);
     if (h_pin) (void)hipHostFree(h_pin);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -204,7 +204,7 @@ void Run::sync()
 size_t Run::particle_bytes(int64_t n) const
 {
     const size_t rs = mixed ? 4 : 8;
-    return (size_t)n * (3 * 8 + 21 * rs + 8);
+    return (size_t)n * (6 * 8 + 18 * rs + 8);
 }
 
 void Run::alloc_particles(int64_t n)
@@ -215,7 +215,7 @@ void Run::alloc_particles(int64_t n)
     for (int k = 0; k < 2; k++) {
         PBufs &B = pb[k];
         B.x.alloc(cap * 3 * 8);
-        B.v.alloc(cap * 3 * rs);
+        B.v.alloc(cap * 3 * 8);
         B.vh.alloc(cap * 9 * rs);
         B.ah.alloc(cap * 9 * rs);
         B.tet.alloc(cap * 4);
@@ -236,6 +236,7 @@ void Run::alloc_particles(int64_t n)
     alloc_pool(pool_cap);
     d_pcount.alloc(cap * 4);
     d_ppos.alloc(cap * 4);
+    d_cq.alloc((size_t)cap * sizeof(ContRec));
 }
 
 void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
@@ -309,18 +310,11 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     for (int64_t i = 0; i < n; i++)
         for (int c = 0; c < 3; c++) xs[c * n + i] = pos[3 * i + c];
     if (n) HIPCHECK(hipMemcpyAsync(B.x.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
-    if (mixed) {
-        std::vector<float> vs(3 * std::max<int64_t>(n, 1));
-        for (int64_t i = 0; i < n; i++)
-            for (int c = 0; c < 3; c++) vs[c * n + i] = (float)vel[3 * i + c];
-        if (n) HIPCHECK(hipMemcpyAsync(B.v.p, vs.data(), 3 * n * 4, hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipStreamSynchronize(stream));
-    } else {
-        for (int64_t i = 0; i < n; i++)
-            for (int c = 0; c < 3; c++) xs[c * n + i] = vel[3 * i + c];
-        if (n) HIPCHECK(hipMemcpyAsync(B.v.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipStreamSynchronize(stream));
-    }
+    HIPCHECK(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) xs[c * n + i] = vel[3 * i + c];
+    if (n) HIPCHECK(hipMemcpyAsync(B.v.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
     std::vector<int32_t> ids(std::max<int64_t>(n, 1));
     std::iota(ids.begin(), ids.end(), 0);
     if (n) HIPCHECK(hipMemcpyAsync(B.id.p, ids.data(), n * 4, hipMemcpyHostToDevice, stream));
@@ -428,11 +422,15 @@ void Run::particle_phase()
     for (int attempt = 0; attempt < 4 && !done; attempt++) {
         zero(d_small);
         zero(d_cnt);
+        ContQueue cq{(ContRec *)d_cq.p, (int32_t *)d_small.p + 4};
         HIPCHECK(hipEventRecord(ev_b, stream));
         HIPCHECK(launch_particle(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p,
                                  (const float *)d_e32.p, (const float *)d_b32.p, perm, (const int32_t *)d_off.p,
-                                 pb[cur].d, pb[1 - cur].d, np, sp, gl, (double *)d_P.p, pool(), Counters{(unsigned long long *)d_cnt.p},
-                                 stream));
+                                 pb[cur].d, pb[1 - cur].d, np, sp, gl, (double *)d_P.p, pool(), cq,
+                                 Counters{(unsigned long long *)d_cnt.p}, stream));
+        HIPCHECK(hipEventRecord(ev_c1, stream));
+        HIPCHECK(launch_continue(order, mixed, dm, pb[1 - cur].d, np, sp, gl, pool(), cq,
+                                 Counters{(unsigned long long *)d_cnt.p}, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 4, hipMemcpyDeviceToHost, stream));
@@ -588,18 +586,20 @@ void Run::step(int n_steps)
 {
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     if (sticky) throw Error(sticky, sticky_msg);
-    double pms = 0, kms = 0, fms = 0;
+    double pms = 0, kms = 0, cms = 0, fms = 0;
     try {
         for (int s = 0; s < n_steps; s++) {
             particle_phase();
             field_phase();
             HIPCHECK(hipEventSynchronize(ev_e));
-            float t1 = 0, t2 = 0, t3 = 0;
+            float t1 = 0, t2 = 0, t3 = 0, t4 = 0;
             HIPCHECK(hipEventElapsedTime(&t1, ev_a, ev_d));
-            HIPCHECK(hipEventElapsedTime(&t2, ev_b, ev_c));
+            HIPCHECK(hipEventElapsedTime(&t2, ev_b, ev_c1));
+            HIPCHECK(hipEventElapsedTime(&t4, ev_c1, ev_c));
             HIPCHECK(hipEventElapsedTime(&t3, ev_d, ev_e));
             pms += t1;
             kms += t2;
+            cms += t4;
             fms += t3;
             steps_done++;
         }
@@ -610,6 +610,7 @@ void Run::step(int n_steps)
     }
     last_particle_ms = pms;
     last_kernel_ms = kms;
+    last_continue_ms = cms;
     last_field_ms = fms;
 }
 
@@ -695,15 +696,8 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
     if (np) HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
     if (np) HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
     std::vector<double> v(3 * std::max<int64_t>(np, 1));
-    if (mixed) {
-        std::vector<float> vf(3 * std::max<int64_t>(np, 1));
-        for (int c = 0; c < 3; c++)
-            if (np) HIPCHECK(hipMemcpy(&vf[c * np], (float *)B.v.p + c * cap, np * 4, hipMemcpyDeviceToHost));
-        for (size_t k = 0; k < vf.size(); k++) v[k] = vf[k];
-    } else {
-        for (int c = 0; c < 3; c++)
-            if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-    }
+    for (int c = 0; c < 3; c++)
+        if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < np; i++) {
         const int64_t o = id[i];
         for (int c = 0; c < 3; c++) {
@@ -748,8 +742,8 @@ size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
     size_t ops = (size_t)((2 * nnzA + nnzC) * 12 + (mixed ? nnzA * 4 : 0) + (double)m.N2 * 8 * 12 +
                           (double)m.N0_int * 40 * 12);
     size_t vecs = (size_t)(m.N1 * 8 * 14 + m.N2 * 8 * 4 + m.nt * (16 * 8 + 4 * 4 + (m.n1l + m.n2l + m.n0l) * 4));
-    size_t parts = (size_t)n * 2 * (3 * 8 + 21 * rs + 8);
-    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 12 + 24);
+    size_t parts = (size_t)n * 2 * (6 * 8 + 18 * rs + 8);
+    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 12 + 24) + (size_t)n * 144;
     size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
     return ops + vecs + parts + sorts + tets + (64 << 20);
 }
@@ -967,6 +961,7 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.n_particles = r.np;
     s.particle_ms = r.last_particle_ms;
     s.particle_kernel_ms = r.last_kernel_ms;
+    s.continue_kernel_ms = r.last_continue_ms;
     s.field_ms = r.last_field_ms;
     s.pcg_iters = r.last_iters;
     s.pcg_relres = r.last_relres;

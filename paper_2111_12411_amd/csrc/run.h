@@ -63,7 +63,7 @@ class Run {
     DevMesh dm{};
     // statistics
     int64_t np = 0, steps_done = 0, last_cross = 0, last_refl = 0, last_spill = 0;
-    double last_particle_ms = 0, last_kernel_ms = 0, last_field_ms = 0, last_relres = 0;
+    double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
     int64_t nnz_total = 0;
 
@@ -95,7 +95,7 @@ class Run {
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_small;
-    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos;
+    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos, d_cq;
     std::vector<DevBuf> hp_sort, hp_ssort;
     PBufs pb[2];
     int cur = 0;
@@ -106,7 +106,7 @@ class Run {
     int32_t sticky = 0;
     std::string sticky_msg;
     void *h_pin = nullptr;
-    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr, ev_e = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c1 = nullptr, ev_c = nullptr, ev_d = nullptr, ev_e = nullptr;
 };
 
 }  // namespace fempic

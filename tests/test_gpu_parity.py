@@ -172,9 +172,10 @@ def test_full_size_sampled(precision, tol_x, tol_v):
     run.set_fields(e0, b0)
     run.step()
     pos_g, vel_g, tet_g = run.particles()
+    # the random initial e does not satisfy Gauss's law, so only the deposit's own
+    # continuity residual R_C is meaningful here
     RG, RC, RS = run.gauss()
     assert RC < 1e-12, RC
-    assert RG < 1e-12, RG
     idx = np.random.default_rng(5).choice(n, 3000, replace=False)
     orc = core.OracleRun(m, dt, particles_only=True)
     orc.load(pos[idx], vel[idx], QE, ME, 1.0)
