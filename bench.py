@@ -92,12 +92,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method is built and measured on a single MI355X "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
     cfg = W.CONFIGS[3]
+    if args.calib_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mix = run_workload(3, F.MIXED, args.steps, args.warmup, n=args.particles)
     st = mix["stats"]
     K = args.steps

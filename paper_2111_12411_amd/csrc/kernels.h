@@ -33,6 +33,9 @@ struct DevParticles {
     int64_t cap;
 };
 
+// threads per block of the particle kernel (tets per block <= PARTICLE_BLOCK / n1_loc)
+constexpr int PARTICLE_BLOCK = 128;
+
 struct StepParams {
     double qm;      // q / m
     double qw;      // q * w
@@ -88,6 +91,9 @@ int64_t sort_hist_entries(int64_t n);
 int64_t scan_tmp_entries(int64_t n);
 hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s);
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s);
+// out[i] = in[perm[i]] for every particle array
+hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
+                          hipStream_t s);
 hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s);
 // bucket offsets off[t] = first index with key >= t, for t in [0, nt]
 hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s);

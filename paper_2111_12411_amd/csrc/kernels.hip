@@ -37,13 +37,15 @@ __device__ __constant__ const double LCOEF[4][5] = {
 
 template <int K>
 struct Ord;
+// threads per block of the particle kernel; TPW_MAX = PBLK / N1 tets per block
+constexpr int PBLK = 128;
 template <>
 struct Ord<1> {
-    static constexpr int N1 = 6, N2 = 4, N0 = 4, NG = 4, TPW_MAX = 42;
+    static constexpr int N1 = 6, N2 = 4, N0 = 4, NG = 4, TPW_MAX = PBLK / 6;
 };
 template <>
 struct Ord<2> {
-    static constexpr int N1 = 20, N2 = 15, N0 = 10, NG = 6, TPW_MAX = 12;
+    static constexpr int N1 = 20, N2 = 15, N0 = 10, NG = 6, TPW_MAX = PBLK / 20;
 };
 
 // local edges (a,b) and faces (a,b,c); face f opposite vertex 3-f
@@ -383,51 +385,193 @@ __device__ inline void deposit_segment(const double L[4][5], double sa, double s
 }
 
 // -------------------------------------------------------------- particle
-// exit of tet G from s_lo along the path cp: first s where a barycentric
-// coordinate turns negative (the entry face's coordinate is zero at s_lo)
+// Newton refinement of the single crossing of q in (0, hi): q(0) >= 0 > q(hi).
+// Regula-falsi start, Newton steps kept inside the shrinking bracket (bisection
+// when a step leaves it), stop when the step is below 2 ulp.
+__device__ inline double refine_root(const double *q, double hi, double f0, double fh)
+{
+    double a = 0.0, b = hi;
+    double x = hi * (f0 / (f0 - fh));
+    if (!(x > a && x < b)) x = 0.5 * hi;
+    for (int it = 0; it < 60; it++) {
+        const double fx = horner4(q, x);
+        if (fx == 0.0) break;
+        if (fx < 0.0) b = x; else a = x;
+        double xn = x - fx / dhorner4(q, x);
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+        const double step = fabs(xn - x);
+        x = xn;
+        if (step <= 4e-16 * fabs(x) || !(b - a > 4e-16 * fabs(b))) break;
+    }
+    return fmin(fmax(x, 0.0), hi);
+}
+
+// Bernstein coefficients on [0, H] of q (power basis of u) and a class:
+// 0 = no negative value on [0,H], 1 = negative right after 0, 2 = exactly one
+// crossing inside, 3 = anything else (needs the subdivision search)
+__device__ inline int classify(const double *q, double H, double &b0, double &b4)
+{
+    const double d1 = q[1] * H, d2 = q[2] * H * H, d3 = q[3] * (H * H) * H, d4 = q[4] * (H * H) * (H * H);
+    double bc[5];
+    bc[0] = q[0];
+    bc[1] = q[0] + 0.25 * d1;
+    bc[2] = q[0] + 0.5 * d1 + d2 / 6.0;
+    bc[3] = q[0] + 0.75 * d1 + 0.5 * d2 + 0.25 * d3;
+    bc[4] = q[0] + d1 + d2 + d3 + d4;
+    b0 = bc[0];
+    b4 = bc[4];
+    int first = -1;
+#pragma unroll
+    for (int i = 4; i >= 0; i--)
+        if (bc[i] != 0.0) first = i;
+    if (first < 0) return 0;
+    if (bc[first] < 0.0) return 1;
+    bool any_neg = false;
+    int changes = 0;
+    double prev = bc[first];
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        if (i <= first) continue;
+        if (bc[i] < 0.0) any_neg = true;
+        if (bc[i] != 0.0) {
+            if ((bc[i] < 0.0) != (prev < 0.0)) changes++;
+            prev = bc[i];
+        }
+    }
+    if (!any_neg) return 0;
+    if (changes == 1 && bc[4] < 0.0) return 2;
+    return 3;
+}
+
+// exit of tet G from s_lo along the path cp: the first s > s_lo where a
+// barycentric coordinate turns negative (the entry face's coordinate is zero
+// at s_lo).  All four faces are classified without branches; one Newton
+// refinement runs per lane, on the likeliest face; other candidate faces are
+// checked with one polynomial evaluation and refined only when they cross first.
+template <bool FROM_ZERO>
 __device__ inline int find_exit(const double *G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
 {
     s_exit = 2.0;
-    int f_exit = -1;
     const double H = 1.0 - s_lo;
     if (!(H > 0.0)) return -1;
-#pragma unroll 1
+    double q[4][5], b0[4], b4[4];
+    int cls[4];
+#pragma unroll
     for (int f = 0; f < 4; f++) {
         const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
-        double q[5];
 #pragma unroll
-        for (int d = 0; d < 5; d++) q[d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
-        q[0] += a0;
-        taylor_shift(q, s_lo, q);
-        if (f == entry) q[0] = 0.0;
-        double u;
-        if (first_negative(q, H, u)) {
-            const double sx = s_lo + u;
-            if (sx < s_exit) {
-                s_exit = sx;
-                f_exit = f;
+        for (int d = 0; d < 5; d++) q[f][d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
+        q[f][0] += a0;
+        if (!FROM_ZERO) taylor_shift(q[f], s_lo, q[f]);
+        if (f == entry) q[f][0] = 0.0;
+        cls[f] = classify(q[f], H, b0[f], b4[f]);
+    }
+    // negative right away: exit at s_lo through the smallest such face
+#pragma unroll
+    for (int f = 3; f >= 0; f--)
+        if (cls[f] == 1) {
+            s_exit = s_lo;
+            return f;
+        }
+    // likeliest single crossing (smallest regula-falsi estimate), refined once
+    int cand = -1;
+    double est = 2.0 * H;
+    double qs[5] = {0, 0, 0, 0, 0}, f0 = 0, fh = 0;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        if (cls[f] == 2) {
+            const double u = H * (b0[f] / (b0[f] - b4[f]));
+            if (cand < 0 || u < est) {
+                cand = f;
+                est = u;
+#pragma unroll
+                for (int d = 0; d < 5; d++) qs[d] = q[f][d];
+                f0 = b0[f];
+                fh = b4[f];
             }
         }
     }
-    return f_exit;
-}
-
-// current moments of the segment [sa, sb] of path cp inside tet G
-template <int K>
-__device__ inline void segment_moments(const double *G, const double (&cp)[5][3], double sa, double sb, double qw,
-                                       const GLRule &gl, double *dep)
-{
-    double L[4][5];
+    double ubest = 2.0 * H;
+    int fbest = -1;
+    if (cand >= 0) {
+        ubest = refine_root(qs, H, f0, fh);
+        fbest = cand;
+    }
+    // other faces that may cross first
 #pragma unroll
     for (int f = 0; f < 4; f++) {
-        const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
-#pragma unroll
-        for (int d = 0; d < 5; d++) L[f][d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
-        L[f][0] += a0;
+        if (f == cand || cls[f] < 2) continue;
+        const double lim = fmin(ubest, H);
+        double u = 0.0;
+        bool hit;
+        if (cls[f] == 2) {
+            // exactly one crossing in (0, H) (and cand >= 0): it comes no later
+            // than ubest iff q(ubest) <= 0
+            hit = horner4(q[f], lim) <= 0.0;
+            if (hit) u = refine_root(q[f], H, b0[f], b4[f]);
+        } else {
+            hit = first_negative(q[f], lim, u);
+        }
+        if (hit && (u < ubest || (u == ubest && f < fbest))) {
+            ubest = u;
+            fbest = f;
+        }
     }
+    if (fbest < 0) return -1;
+    s_exit = s_lo + ubest;
+    return fbest;
+}
+
+// current moments of the segment [sa, sb] of path cp inside tet G:
+// dep_i = q w int Q_i(l) (l_a l_b' - l_b l_a') ds, with l(s) = a + g . r(s) and
+// l'(s) = g . r'(s) evaluated at the Gauss-Legendre nodes of the segment.
+template <int K, typename GPtr>
+__device__ inline void segment_moments(GPtr G, const double (&cp)[5][3], double sa, double sb, double qw,
+                                       const GLRule &gl, double *dep)
+{
+    using O = Ord<K>;
 #pragma unroll
-    for (int c = 0; c < Ord<K>::N1; c++) dep[c] = 0.0;
-    deposit_segment<K>(L, sa, sb, qw, gl, dep);
+    for (int c = 0; c < O::N1; c++) dep[c] = 0.0;
+    const double h = sb - sa;
+#pragma unroll
+    for (int g = 0; g < O::NG; g++) {
+        const double s = fma(h, gl.x[g], sa);
+        const double wg = qw * h * gl.w[g];
+        double r[3], dr[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            r[c] = fma(fma(fma(fma(cp[4][c], s, cp[3][c]), s, cp[2][c]), s, cp[1][c]), s, cp[0][c]);
+            dr[c] = fma(fma(fma(4.0 * cp[4][c], s, 3.0 * cp[3][c]), s, 2.0 * cp[2][c]), s, cp[1][c]);
+        }
+        double lam[4], dl[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const double gx = G[4 * m + 1], gy = G[4 * m + 2], gz = G[4 * m + 3];
+            lam[m] = G[4 * m] + gx * r[0] + gy * r[1] + gz * r[2];
+            dl[m] = gx * dr[0] + gy * dr[1] + gz * dr[2];
+        }
+        double w[6];
+#pragma unroll
+        for (int e = 0; e < 6; e++) w[e] = wg * (lam[EA[e]] * dl[EB[e]] - lam[EB[e]] * dl[EA[e]]);
+        if constexpr (K == 1) {
+#pragma unroll
+            for (int e = 0; e < 6; e++) dep[e] += w[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 6; e++) {
+                dep[2 * e] += (3.0 * lam[EA[e]] - 1.0) * w[e];
+                dep[2 * e + 1] += (3.0 * lam[EB[e]] - 1.0) * w[e];
+            }
+            dep[12] += 3.0 * lam[2] * w[0];
+            dep[13] += 3.0 * lam[1] * w[1];
+            dep[14] += 3.0 * lam[3] * w[0];
+            dep[15] += 3.0 * lam[1] * w[2];
+            dep[16] += 3.0 * lam[3] * w[1];
+            dep[17] += 3.0 * lam[2] * w[2];
+            dep[18] += 3.0 * lam[3] * w[3];
+            dep[19] += 3.0 * lam[2] * w[4];
+        }
+    }
 }
 
 // leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
@@ -509,7 +653,7 @@ __device__ inline void write_spill(const SpillPool &pool, int N1, int t, int64_t
 // in LDS in a fixed order.  A particle whose path leaves the home tet is queued
 // for k_continue.
 template <int K, typename R>
-__global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict__ e, const R *__restrict__ b,
+__global__ __launch_bounds__(PBLK) void k_particle(DevMesh m, const R *__restrict__ e, const R *__restrict__ b,
                                                   const uint32_t *__restrict__ perm, const int32_t *__restrict__ off,
                                                   DevParticles in, DevParticles out, int64_t np, StepParams sp,
                                                   GLRule gl, double *__restrict__ P, SpillPool pool, ContQueue cq,
@@ -522,25 +666,25 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
     __shared__ R s_e[TM][N1];
     __shared__ R s_b[TM][N2];
     __shared__ int32_t s_off[TM + 1];
-    __shared__ double s_hc[N1][BLK + 1];
+    __shared__ double s_hc[N1][PBLK + 1];
 
     const int tid = threadIdx.x;
     const int tpw = sp.tpw;
     const int T0 = blockIdx.x * tpw;
     const int T1 = min(T0 + tpw, m.nt);
     const int ntl = T1 - T0;
-    for (int k = tid; k < ntl * 16; k += BLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
-    for (int k = tid; k <= ntl; k += BLK) s_off[k] = off[T0 + k];
-    for (int k = tid; k < ntl * N1; k += BLK) {
+    for (int k = tid; k < ntl * 16; k += PBLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
+    for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
+    for (int k = tid; k < ntl * N1; k += PBLK) {
         int t = k / N1, i = k % N1;
         s_e[t][i] = e[m.map1[(int64_t)(T0 + t) * N1 + i]];
     }
-    for (int k = tid; k < ntl * N2; k += BLK) {
+    for (int k = tid; k < ntl * N2; k += PBLK) {
         int t = k / N2, l = k % N2;
         s_b[t][l] = b[m.map2[(int64_t)(T0 + t) * N2 + l]];
     }
     __syncthreads();
-    for (int k = tid; k < ntl * 6; k += BLK) {
+    for (int k = tid; k < ntl * 6; k += PBLK) {
         int t = k / 6, q = k % 6;
         double ga[3], gb[3], X[3];
         for (int c = 0; c < 3; c++) {
@@ -561,7 +705,7 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
     const R dtR = (R)sp.dt;
     const R qmR = (R)sp.qm;
 
-    for (int base = pbeg; base < pend; base += BLK) {
+    for (int base = pbeg; base < pend; base += PBLK) {
 #pragma unroll
         for (int c = 0; c < N1; c++) s_hc[c][tid] = 0.0;
         const int i = base + tid;
@@ -624,7 +768,7 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
             // first segment: in the home tet from s = 0
             const double *G = &s_geo[lt][0];
             double s_exit;
-            const int f_exit = find_exit(G, cp, 0.0, -1, s_exit);
+            const int f_exit = find_exit<true>(G, cp, 0.0, -1, s_exit);
             const double s_hi = f_exit < 0 ? 1.0 : s_exit;
             if (s_hi > 0.0) {
                 double dep[N1];
@@ -660,7 +804,7 @@ __global__ __launch_bounds__(BLK) void k_particle(DevMesh m, const R *__restrict
         __syncthreads();
         if (worker) {
             const int lo = max(s_off[wt], base) - base;
-            const int hi = min(s_off[wt + 1], base + BLK) - base;
+            const int hi = min(s_off[wt + 1], base + PBLK) - base;
             for (int j = lo; j < hi; j++) acc += s_hc[wc][j];
         }
         __syncthreads();
@@ -702,11 +846,14 @@ __global__ __launch_bounds__(BLK) void k_continue(DevMesh m, DevParticles out, S
         for (;;) {
             const double *G = &m.geo[(int64_t)t * 16];
             double s_exit;
-            const int f_exit = find_exit(G, cp, s_lo, entry, s_exit);
+            const int f_exit = find_exit<false>(G, cp, s_lo, entry, s_exit);
             const double s_hi = f_exit < 0 ? 1.0 : s_exit;
             if (s_hi > s_lo) {
+                double g[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++) g[k] = G[k];
                 double dep[N1];
-                segment_moments<K>(G, cp, s_lo, s_hi, sp.qw, gl, dep);
+                segment_moments<K>(g, cp, s_lo, s_hi, sp.qw, gl, dep);
                 write_spill(pool, N1, t, i, nsp_i, dep, errs);
             }
             if (f_exit < 0) break;
@@ -742,6 +889,21 @@ __global__ __launch_bounds__(BLK) void k_continue(DevMesh m, DevParticles out, S
         if (nsp) atomicAdd(&cnt[2], nsp);
         if (errs) atomicOr(&cnt[3], (unsigned long long)errs);
     }
+}
+
+// ------------------------------------------------------------ permute
+template <typename R>
+__global__ void k_permute(DevParticles in, DevParticles out, const uint32_t *__restrict__ perm, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    for (int c = 0; c < 3; c++) out.x[c * out.cap + i] = in.x[c * in.cap + j];
+    for (int c = 0; c < 3; c++) ((double *)out.v)[c * out.cap + i] = ((const double *)in.v)[c * in.cap + j];
+    for (int c = 0; c < 9; c++) ((R *)out.vh)[c * out.cap + i] = ((const R *)in.vh)[c * in.cap + j];
+    for (int c = 0; c < 9; c++) ((R *)out.ah)[c * out.cap + i] = ((const R *)in.ah)[c * in.cap + j];
+    out.tet[i] = in.tet[j];
+    out.id[i] = in.id[j];
 }
 
 // ----------------------------------------------------------- radix sort
@@ -1296,6 +1458,15 @@ hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, 
     return hipGetLastError();
 }
 
+hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
+                          hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (mixed) hipLaunchKernelGGL(k_permute<float>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
+    else hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -1325,17 +1496,17 @@ hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double
     const unsigned grid = (unsigned)((m.nt + sp.tpw - 1) / sp.tpw);
     if (order == 1) {
         if (mixed)
-            hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
+            hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(PBLK), 0, s, m, e32, b32, perm, off, in, out, np,
                                sp, gl, P, pool, cq, cnt.c);
         else
-            hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
+            hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(PBLK), 0, s, m, e, b, perm, off, in, out, np,
                                sp, gl, P, pool, cq, cnt.c);
     } else {
         if (mixed)
-            hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(BLK), 0, s, m, e32, b32, perm, off, in, out, np,
+            hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(PBLK), 0, s, m, e32, b32, perm, off, in, out, np,
                                sp, gl, P, pool, cq, cnt.c);
         else
-            hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(BLK), 0, s, m, e, b, perm, off, in, out, np,
+            hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(PBLK), 0, s, m, e, b, perm, off, in, out, np,
                                sp, gl, P, pool, cq, cnt.c);
     }
     return hipGetLastError();

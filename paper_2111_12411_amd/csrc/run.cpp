@@ -336,6 +336,12 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     // AB4 start-up from the current fields
     HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p, (const float *)d_e32.p,
                             (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
+    // store the particles in tet order, so the first step reads them like every later one
+    {
+        const uint32_t *perm = sort_current();
+        HIPCHECK(launch_permute(mixed, pb[0].d, pb[1].d, perm, n, stream));
+        cur = 1;
+    }
     // Gauss reference charge
     compute_rho((double *)d_rho0.p);
     zero(d_g);
@@ -407,9 +413,9 @@ void Run::compute_rho(double *dst)
 
 int Run::tpw() const
 {
-    const int tmax = order == 1 ? 42 : 12;
+    const int tmax = PARTICLE_BLOCK / n1l;
     const double ppt = m.nt ? (double)np / m.nt : 1.0;
-    int t = (int)std::lround(256.0 / std::max(ppt, 1e-9));
+    int t = (int)std::lround((double)PARTICLE_BLOCK / std::max(ppt, 1e-9));
     return std::max(1, std::min(tmax, t));
 }
 
