@@ -100,12 +100,24 @@ hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int
 // exclusive scan of uint32 (in place allowed), total into *total (device)
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total, hipStream_t s);
 
-hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
-                           const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
-                           DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
-                           ContQueue cq, Counters cnt, hipStream_t s);
-hipError_t launch_continue(int order, bool mixed, const DevMesh &m, DevParticles out, int64_t np, StepParams sp,
-                           const GLRule &gl, SpillPool pool, ContQueue cq, Counters cnt, hipStream_t s);
+// Arguments of the particle kernels, kept in device memory (passed by pointer,
+// so the kernels do not hold them all in scalar registers).
+struct ParticleArgs {
+    DevMesh m;
+    const void *e, *b;        // field coefficients: double (FP64) or float (mixed)
+    const uint32_t *perm;     // sorted position -> slot of the input state
+    const int32_t *off;       // [nt+1] first sorted position of each tet
+    DevParticles in, out;
+    int64_t np;
+    StepParams sp;
+    GLRule gl;
+    double *P;                // [nt][n1l] per-tet current moments of home segments
+    SpillPool pool;
+    ContQueue cq;
+    unsigned long long *cnt;  // Counters
+};
+hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t np, hipStream_t s);
 hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
                                 uint32_t *val, hipStream_t s);
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,
@@ -130,16 +142,17 @@ hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s);
 hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 
 // Jacobi-PCG pieces; scalars is a device double[16] block
-enum { SC_RZ = 0, SC_PQ = 1, SC_ALPHA = 2, SC_BETA = 3, SC_RR = 4, SC_BB = 5 };
+// SC_RZ and SC_RZ + 10 hold r.z for even / odd iterations (parity argument `par`)
+enum { SC_RZ = 0, SC_PQ = 1, SC_RR = 4, SC_BB = 5 };
 hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
                     double *partial, double *scalars, hipStream_t s);
 hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
-                    const double *dinv, double *partial, double *scalars, hipStream_t s);
+                    const double *dinv, double *partial, double *scalars, int par, hipStream_t s);
 // FP32 inner PCG (mixed mode); vectors float, scalars double
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
                       double *partial, double *scalars, hipStream_t s);
 hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
-                      double *partial, double *scalars, hipStream_t s);
+                      double *partial, double *scalars, int par, hipStream_t s);
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s);
 hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStream_t s);
 

@@ -411,12 +411,13 @@ __device__ inline double refine_root(const double *q, double hi, double f0, doub
 // crossing inside, 3 = anything else (needs the subdivision search)
 __device__ inline int classify(const double *q, double H, double &b0, double &b4)
 {
-    const double d1 = q[1] * H, d2 = q[2] * H * H, d3 = q[3] * (H * H) * H, d4 = q[4] * (H * H) * (H * H);
+    const double H2 = H * H;
+    const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
     double bc[5];
     bc[0] = q[0];
-    bc[1] = q[0] + 0.25 * d1;
-    bc[2] = q[0] + 0.5 * d1 + d2 / 6.0;
-    bc[3] = q[0] + 0.75 * d1 + 0.5 * d2 + 0.25 * d3;
+    bc[1] = fma(0.25, d1, q[0]);
+    bc[2] = fma(1.0 / 6.0, d2, fma(0.5, d1, q[0]));
+    bc[3] = fma(0.25, d3, fma(0.5, d2, fma(0.75, d1, q[0])));
     bc[4] = q[0] + d1 + d2 + d3 + d4;
     b0 = bc[0];
     b4 = bc[4];
@@ -524,7 +525,8 @@ __device__ inline int find_exit(const double *G, const double (&cp)[5][3], doubl
 
 // current moments of the segment [sa, sb] of path cp inside tet G:
 // dep_i = q w int Q_i(l) (l_a l_b' - l_b l_a') ds, with l(s) = a + g . r(s) and
-// l'(s) = g . r'(s) evaluated at the Gauss-Legendre nodes of the segment.
+// l'(s) = g . r'(s) (l_0 = 1 - l_1 - l_2 - l_3 and l_0' = -(l_1' + l_2' + l_3'))
+// evaluated at the Gauss-Legendre nodes of the segment.
 template <int K, typename GPtr>
 __device__ inline void segment_moments(GPtr G, const double (&cp)[5][3], double sa, double sb, double qw,
                                        const GLRule &gl, double *dep)
@@ -533,43 +535,53 @@ __device__ inline void segment_moments(GPtr G, const double (&cp)[5][3], double 
 #pragma unroll
     for (int c = 0; c < O::N1; c++) dep[c] = 0.0;
     const double h = sb - sa;
+    const double qwh = qw * h;
 #pragma unroll
     for (int g = 0; g < O::NG; g++) {
         const double s = fma(h, gl.x[g], sa);
-        const double wg = qw * h * gl.w[g];
+        const double wg = qwh * gl.w[g];
         double r[3], dr[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) {
             r[c] = fma(fma(fma(fma(cp[4][c], s, cp[3][c]), s, cp[2][c]), s, cp[1][c]), s, cp[0][c]);
-            dr[c] = fma(fma(fma(4.0 * cp[4][c], s, 3.0 * cp[3][c]), s, 2.0 * cp[2][c]), s, cp[1][c]);
+            dr[c] = wg * fma(fma(fma(4.0 * cp[4][c], s, 3.0 * cp[3][c]), s, 2.0 * cp[2][c]), s, cp[1][c]);
         }
-        double lam[4], dl[4];
+        double lam[4], dl[4];  // dl carries the quadrature weight
 #pragma unroll
-        for (int m = 0; m < 4; m++) {
+        for (int m = 1; m < 4; m++) {
             const double gx = G[4 * m + 1], gy = G[4 * m + 2], gz = G[4 * m + 3];
-            lam[m] = G[4 * m] + gx * r[0] + gy * r[1] + gz * r[2];
-            dl[m] = gx * dr[0] + gy * dr[1] + gz * dr[2];
+            lam[m] = fma(gz, r[2], fma(gy, r[1], fma(gx, r[0], G[4 * m])));
+            dl[m] = fma(gz, dr[2], fma(gy, dr[1], gx * dr[0]));
         }
+        lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
+        dl[0] = -(dl[1] + dl[2] + dl[3]);
         double w[6];
 #pragma unroll
-        for (int e = 0; e < 6; e++) w[e] = wg * (lam[EA[e]] * dl[EB[e]] - lam[EB[e]] * dl[EA[e]]);
+        for (int e = 0; e < 6; e++) w[e] = fma(lam[EA[e]], dl[EB[e]], -lam[EB[e]] * dl[EA[e]]);
         if constexpr (K == 1) {
 #pragma unroll
             for (int e = 0; e < 6; e++) dep[e] += w[e];
         } else {
+            double t3[4], u3[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                u3[m] = 3.0 * lam[m];
+                t3[m] = u3[m] - 1.0;
+            }
 #pragma unroll
             for (int e = 0; e < 6; e++) {
-                dep[2 * e] += (3.0 * lam[EA[e]] - 1.0) * w[e];
-                dep[2 * e + 1] += (3.0 * lam[EB[e]] - 1.0) * w[e];
+                dep[2 * e] = fma(t3[EA[e]], w[e], dep[2 * e]);
+                dep[2 * e + 1] = fma(t3[EB[e]], w[e], dep[2 * e + 1]);
             }
-            dep[12] += 3.0 * lam[2] * w[0];
-            dep[13] += 3.0 * lam[1] * w[1];
-            dep[14] += 3.0 * lam[3] * w[0];
-            dep[15] += 3.0 * lam[1] * w[2];
-            dep[16] += 3.0 * lam[3] * w[1];
-            dep[17] += 3.0 * lam[2] * w[2];
-            dep[18] += 3.0 * lam[3] * w[3];
-            dep[19] += 3.0 * lam[2] * w[4];
+            // faces (a,b,c): 3 l_c W_ab and 3 l_b W_ac
+            dep[12] = fma(u3[2], w[0], dep[12]);
+            dep[13] = fma(u3[1], w[1], dep[13]);
+            dep[14] = fma(u3[3], w[0], dep[14]);
+            dep[15] = fma(u3[1], w[2], dep[15]);
+            dep[16] = fma(u3[3], w[1], dep[16]);
+            dep[17] = fma(u3[2], w[2], dep[17]);
+            dep[18] = fma(u3[3], w[3], dep[18]);
+            dep[19] = fma(u3[2], w[4], dep[19]);
         }
     }
 }
@@ -653,12 +665,21 @@ __device__ inline void write_spill(const SpillPool &pool, int N1, int t, int64_t
 // in LDS in a fixed order.  A particle whose path leaves the home tet is queued
 // for k_continue.
 template <int K, typename R>
-__global__ __launch_bounds__(PBLK) void k_particle(DevMesh m, const R *__restrict__ e, const R *__restrict__ b,
-                                                  const uint32_t *__restrict__ perm, const int32_t *__restrict__ off,
-                                                  DevParticles in, DevParticles out, int64_t np, StepParams sp,
-                                                  GLRule gl, double *__restrict__ P, SpillPool pool, ContQueue cq,
-                                                  unsigned long long *__restrict__ cnt)
+__global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restrict__ A)
 {
+    const DevMesh &m = A->m;
+    const R *__restrict__ e = (const R *)A->e;
+    const R *__restrict__ b = (const R *)A->b;
+    const uint32_t *__restrict__ perm = A->perm;
+    const int32_t *__restrict__ off = A->off;
+    const DevParticles &in = A->in;
+    const DevParticles &out = A->out;
+    const StepParams &sp = A->sp;
+    const GLRule &gl = A->gl;
+    double *__restrict__ P = A->P;
+    const SpillPool &pool = A->pool;
+    const ContQueue &cq = A->cq;
+    unsigned long long *__restrict__ cnt = A->cnt;
     using O = Ord<K>;
     constexpr int N1 = O::N1, N2 = O::N2, TM = O::TPW_MAX;
     __shared__ double s_geo[TM][16];
@@ -826,9 +847,15 @@ __global__ __launch_bounds__(PBLK) void k_particle(DevMesh m, const R *__restric
 // every segment's current moments go to the spill pool tagged with
 // (sorted particle, segment), so their reduction order is canonical.
 template <int K, typename R>
-__global__ __launch_bounds__(BLK) void k_continue(DevMesh m, DevParticles out, StepParams sp, GLRule gl,
-                                                  SpillPool pool, ContQueue cq, unsigned long long *__restrict__ cnt)
+__global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict__ A)
 {
+    const DevMesh &m = A->m;
+    const DevParticles &out = A->out;
+    const StepParams &sp = A->sp;
+    const GLRule &gl = A->gl;
+    const SpillPool &pool = A->pool;
+    const ContQueue &cq = A->cq;
+    unsigned long long *__restrict__ cnt = A->cnt;
     constexpr int N1 = Ord<K>::N1;
     const int32_t nq = *cq.count;
     unsigned long long ncr = 0, nrf = 0, nsp = 0;
@@ -1156,6 +1183,10 @@ __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__re
 }
 
 // --------------------------------------------------------- linear algebra
+// Reductions are deterministic: every block sums a fixed set of rows in a fixed
+// order, and k_finish sums the (at most RED_BLOCKS) block partials in order.
+constexpr int RED_BLOCKS = 2048;
+
 template <int LANES, typename T>
 __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__restrict__ ptr,
                                               const int32_t *__restrict__ idx, const T *__restrict__ val,
@@ -1164,26 +1195,29 @@ __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__res
                                               double *__restrict__ partial)
 {
     __shared__ double s_red[BLK / LANES];
+    constexpr int RPB = BLK / LANES;
     const int tid = threadIdx.x;
-    const int64_t row = (int64_t)blockIdx.x * (BLK / LANES) + tid / LANES;
     const int lane = tid % LANES;
-    double sum = 0.0;
-    if (row < rows) {
-        const int64_t e = ptr[row + 1];
-        for (int64_t k = ptr[row] + lane; k < e; k += LANES) sum += (double)val[k] * (double)x[idx[k]];
-    }
-#pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LANES);
     double d = 0.0;
-    if (row < rows && lane == 0) {
-        double yv = alpha * sum + (beta != 0.0 ? beta * (double)z[row] : 0.0);
-        y[row] = (T)yv;
-        if (dotv) d = (double)dotv[row] * (double)(T)yv;
+    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < rows; row0 += (int64_t)gridDim.x * RPB) {
+        const int64_t row = row0 + tid / LANES;
+        double sum = 0.0;
+        if (row < rows) {
+            const int64_t e = ptr[row + 1];
+            for (int64_t k = ptr[row] + lane; k < e; k += LANES) sum += (double)val[k] * (double)x[idx[k]];
+        }
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LANES);
+        if (row < rows && lane == 0) {
+            const double yv = alpha * sum + (beta != 0.0 ? beta * (double)z[row] : 0.0);
+            y[row] = (T)yv;
+            if (dotv) d += (double)dotv[row] * (double)(T)yv;
+        }
     }
     if (partial) {
         if (lane == 0) s_red[tid / LANES] = d;
         __syncthreads();
-        for (int o = (BLK / LANES) / 2; o > 0; o >>= 1) {
+        for (int o = RPB / 2; o > 0; o >>= 1) {
             if (tid < o) s_red[tid] += s_red[tid + o];
             __syncthreads();
         }
@@ -1211,31 +1245,28 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
         for (int q = 0; q < k; q++) out[q] = s[q][0];
 }
 
-__global__ void k_alpha(double *sc)
-{
-    sc[SC_ALPHA] = sc[SC_PQ] != 0.0 ? sc[SC_RZ] / sc[SC_PQ] : 0.0;
-}
-
-// x += a p ; r -= a q ; z = dinv r ; partial (r.z, r.r)
+// PCG scalars (device double block): RZ[2] ping-pong by iteration parity,
+// PQ, and after k_finish: sc[8] = r.z (new), sc[9] = r.r
+// x += a p ; r -= a q ; z = dinv r ; partial (r.z, r.r), with a = rz / pq
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
                                                    const T *__restrict__ p, const T *__restrict__ q,
-                                                   const T *__restrict__ dinv, const double *__restrict__ sc,
+                                                   const T *__restrict__ dinv, const double *__restrict__ sc, int par,
                                                    double *__restrict__ partial)
 {
     __shared__ double s0[BLK], s1[BLK];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
-    const double a = sc[SC_ALPHA];
+    const double pq = sc[SC_PQ];
+    const double a = pq != 0.0 ? sc[SC_RZ + 10 * par] / pq : 0.0;
     double rz = 0, rr = 0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
         x[i] = (T)((double)x[i] + a * (double)p[i]);
         T ri = (T)((double)r[i] - a * (double)q[i]);
         r[i] = ri;
         T zi = dinv[i] * ri;
         z[i] = zi;
-        rz = (double)ri * (double)zi;
-        rr = (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
     }
     s0[tid] = rz;
     s1[tid] = rr;
@@ -1253,20 +1284,19 @@ __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x,
     }
 }
 
-// after k_finish into sc[8..9] = (rz_new, rr)
-__global__ void k_beta(double *sc)
-{
-    const double rzn = sc[8];
-    sc[SC_BETA] = sc[SC_RZ] != 0.0 ? rzn / sc[SC_RZ] : 0.0;
-    sc[SC_RZ] = rzn;
-    sc[SC_RR] = sc[9];
-}
-
+// p = z + b p with b = rz_new / rz_old; keeps r.z for the next iteration in
+// the other parity slot (no other thread reads that slot in this launch)
 template <typename T>
-__global__ void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z, const double *__restrict__ sc)
+__global__ void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z, double *__restrict__ sc, int par)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = (T)((double)z[i] + sc[SC_BETA] * (double)p[i]);
+    const double rzo = sc[SC_RZ + 10 * par];
+    const double bt = rzo != 0.0 ? sc[8] / rzo : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[SC_RZ + 10 * (1 - par)] = sc[8];
+        sc[SC_RR] = sc[9];
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (T)((double)z[i] + bt * (double)p[i]);
 }
 
 // r = b, x = 0, z = dinv r, p = z ; partial (r.z, r.r)
@@ -1277,17 +1307,16 @@ __global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const T *__restrict
 {
     __shared__ double s0[BLK], s1[BLK];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
     double rz = 0, rr = 0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
         T ri = b[i];
         x[i] = T(0);
         r[i] = ri;
         T zi = dinv[i] * ri;
         z[i] = zi;
         p[i] = zi;
-        rz = (double)ri * (double)zi;
-        rr = (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
     }
     s0[tid] = rz;
     s1[tid] = rr;
@@ -1338,15 +1367,14 @@ __global__ __launch_bounds__(BLK) void k_gauss_partial(int64_t n, const double *
 {
     __shared__ double s[4][BLK];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
     double v[4] = {0, 0, 0, 0};
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
         double d = rho[i] - rho0[i];
         double x1 = a[i] + d, x2 = g[i] - d, x3 = a[i] + g[i];
-        v[0] = x1 * x1;
-        v[1] = x2 * x2;
-        v[2] = x3 * x3;
-        v[3] = d * d;
+        v[0] += x1 * x1;
+        v[1] += x2 * x2;
+        v[2] += x3 * x3;
+        v[3] += d * d;
     }
     for (int q = 0; q < 4; q++) s[q][tid] = v[q];
     __syncthreads();
@@ -1364,8 +1392,9 @@ __global__ __launch_bounds__(BLK) void k_dot_partial(int64_t n, const double *__
 {
     __shared__ double s[BLK];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * BLK + tid;
-    s[tid] = i < n ? a[i] * b[i] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) acc += a[i] * b[i];
+    s[tid] = acc;
     __syncthreads();
     for (int o = BLK / 2; o > 0; o >>= 1) {
         if (tid < o) s[tid] += s[tid + o];
@@ -1488,40 +1517,28 @@ hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *o
     return hipGetLastError();
 }
 
-hipError_t launch_particle(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
-                           const float *b32, const uint32_t *perm, const int32_t *off, DevParticles in,
-                           DevParticles out, int64_t np, StepParams sp, const GLRule &gl, double *P, SpillPool pool,
-                           ContQueue cq, Counters cnt, hipStream_t s)
+hipError_t launch_particle(int order, bool mixed, const ParticleArgs *A, int32_t nt, int32_t tpw, hipStream_t s)
 {
-    const unsigned grid = (unsigned)((m.nt + sp.tpw - 1) / sp.tpw);
+    const unsigned grid = (unsigned)((nt + tpw - 1) / tpw);
     if (order == 1) {
-        if (mixed)
-            hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(PBLK), 0, s, m, e32, b32, perm, off, in, out, np,
-                               sp, gl, P, pool, cq, cnt.c);
-        else
-            hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(PBLK), 0, s, m, e, b, perm, off, in, out, np,
-                               sp, gl, P, pool, cq, cnt.c);
+        if (mixed) hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(PBLK), 0, s, A);
+        else hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(PBLK), 0, s, A);
     } else {
-        if (mixed)
-            hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(PBLK), 0, s, m, e32, b32, perm, off, in, out, np,
-                               sp, gl, P, pool, cq, cnt.c);
-        else
-            hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(PBLK), 0, s, m, e, b, perm, off, in, out, np,
-                               sp, gl, P, pool, cq, cnt.c);
+        if (mixed) hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(PBLK), 0, s, A);
+        else hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(PBLK), 0, s, A);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_continue(int order, bool mixed, const DevMesh &m, DevParticles out, int64_t np, StepParams sp,
-                           const GLRule &gl, SpillPool pool, ContQueue cq, Counters cnt, hipStream_t s)
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t np, hipStream_t s)
 {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (np + BLK - 1) / BLK));
     if (order == 1) {
-        if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
-        else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
+        if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, A);
+        else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, A);
     } else {
-        if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
-        else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, m, out, sp, gl, pool, cq, cnt.c);
+        if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, A);
+        else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, A);
     }
     return hipGetLastError();
 }
@@ -1565,43 +1582,46 @@ hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, con
 }
 
 namespace {
+inline unsigned red_grid(int64_t n, int per_block) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + per_block - 1) / per_block)); }
+
 template <typename T>
 hipError_t spmv_t(const DevCSR &A, const T *val, const T *x, T *y, double alpha, double beta, const T *z,
-                  const T *dotv, double *partial, hipStream_t s)
+                  const T *dotv, double *partial, unsigned &grid, hipStream_t s)
 {
+    grid = red_grid(A.rows, BLK / A.lanes);
     if (A.rows == 0) return hipSuccess;
     switch (A.lanes) {
     case 4:
-        hipLaunchKernelGGL((k_spmv<4, T>), dim3(nblk(A.rows, BLK / 4)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y,
-                           alpha, beta, z, dotv, partial);
+        hipLaunchKernelGGL((k_spmv<4, T>), dim3(grid), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y, alpha, beta, z,
+                           dotv, partial);
         break;
     case 8:
-        hipLaunchKernelGGL((k_spmv<8, T>), dim3(nblk(A.rows, BLK / 8)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y,
-                           alpha, beta, z, dotv, partial);
+        hipLaunchKernelGGL((k_spmv<8, T>), dim3(grid), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y, alpha, beta, z,
+                           dotv, partial);
         break;
     case 16:
-        hipLaunchKernelGGL((k_spmv<16, T>), dim3(nblk(A.rows, BLK / 16)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x,
-                           y, alpha, beta, z, dotv, partial);
+        hipLaunchKernelGGL((k_spmv<16, T>), dim3(grid), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y, alpha, beta,
+                           z, dotv, partial);
         break;
     default:
-        hipLaunchKernelGGL((k_spmv<32, T>), dim3(nblk(A.rows, BLK / 32)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x,
-                           y, alpha, beta, z, dotv, partial);
+        hipLaunchKernelGGL((k_spmv<32, T>), dim3(grid), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, val, x, y, alpha, beta,
+                           z, dotv, partial);
         break;
     }
     return hipGetLastError();
 }
-
-inline int64_t spmv_blocks(const DevCSR &A) { return (A.rows + (BLK / A.lanes) - 1) / (BLK / A.lanes); }
 }  // namespace
 
 hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, double beta, const double *z, hipStream_t s)
 {
-    return spmv_t<double>(A, A.val, x, y, alpha, beta, z, nullptr, nullptr, s);
+    unsigned g;
+    return spmv_t<double>(A, A.val, x, y, alpha, beta, z, nullptr, nullptr, g, s);
 }
 
 hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s)
 {
-    return spmv_t<float>(A, A.val32, x, y, 1.0, 0.0, nullptr, nullptr, nullptr, s);
+    unsigned g;
+    return spmv_t<float>(A, A.val32, x, y, 1.0, 0.0, nullptr, nullptr, nullptr, g, s);
 }
 
 hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s)
@@ -1616,24 +1636,25 @@ template <typename T>
 hipError_t pcg_init_t(int64_t n, const T *b, T *x, T *r, T *z, T *p, const T *dinv, double *partial, double *sc,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pcg_init<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)nblk(n), 2, sc + 8);
+    const unsigned g = red_grid(n, BLK);
+    hipLaunchKernelGGL(k_pcg_init<T>, dim3(g), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g, 2, sc + 8);
     hipLaunchKernelGGL(k_init_sc, dim3(1), dim3(1), 0, s, sc);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pcg_iter_t(const DevCSR &A, const T *val, int64_t n, T *x, T *r, T *z, T *p, T *q, const T *dinv,
-                      double *partial, double *sc, hipStream_t s)
+                      double *partial, double *sc, int par, hipStream_t s)
 {
-    hipError_t err = spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, s);
+    unsigned g1;
+    hipError_t err = spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, g1, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, spmv_blocks(A), 1, sc + SC_PQ);
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1), 0, s, sc);
-    hipLaunchKernelGGL(k_update_xr<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, partial);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)nblk(n), 2, sc + 8);
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(1), 0, s, sc);
-    hipLaunchKernelGGL(k_update_p<T>, dim3(nblk(n)), dim3(BLK), 0, s, n, p, z, sc);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g1, 1, sc + SC_PQ);
+    const unsigned g2 = red_grid(n, BLK);
+    hipLaunchKernelGGL(k_update_xr<T>, dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g2, 2, sc + 8);
+    hipLaunchKernelGGL(k_update_p<T>, dim3(g2), dim3(BLK), 0, s, n, p, z, sc, par);
     return hipGetLastError();
 }
 }  // namespace
@@ -1645,9 +1666,9 @@ hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z,
 }
 
 hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
-                    const double *dinv, double *partial, double *sc, hipStream_t s)
+                    const double *dinv, double *partial, double *sc, int par, hipStream_t s)
 {
-    return pcg_iter_t<double>(A, A.val, n, x, r, z, p, q, dinv, partial, sc, s);
+    return pcg_iter_t<double>(A, A.val, n, x, r, z, p, q, dinv, partial, sc, par, s);
 }
 
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
@@ -1657,9 +1678,9 @@ hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, f
 }
 
 hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
-                      double *partial, double *sc, hipStream_t s)
+                      double *partial, double *sc, int par, hipStream_t s)
 {
-    return pcg_iter_t<float>(A, A.val32, n, x, r, z, p, q, dinv, partial, sc, s);
+    return pcg_iter_t<float>(A, A.val32, n, x, r, z, p, q, dinv, partial, sc, par, s);
 }
 
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s)
@@ -1679,7 +1700,7 @@ hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStr
 hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
                        double *partial, double *out4, hipStream_t s)
 {
-    const int64_t nb = std::max<int64_t>(1, nblk(n));
+    const int64_t nb = red_grid(n, BLK);
     hipLaunchKernelGGL(k_gauss_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, GtDe, Gtg, rho, rho0, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 4, out4);
     return hipGetLastError();
@@ -1687,7 +1708,7 @@ hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const d
 
 hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s)
 {
-    const int64_t nb = std::max<int64_t>(1, nblk(n));
+    const int64_t nb = red_grid(n, BLK);
     hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, a, b, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 1, out);
     return hipGetLastError();

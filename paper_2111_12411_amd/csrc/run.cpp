@@ -176,7 +176,8 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_soff.alloc((size_t)(m.nt + 1) * 4);
     d_cnt.alloc(8 * 8);
     d_small.alloc(64);
-    HIPCHECK(hipHostMalloc(&h_pin, 256, hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
+    d_args.alloc(sizeof(ParticleArgs));
     for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
     HIPCHECK(hipStreamSynchronize(stream));
 }
@@ -428,15 +429,26 @@ void Run::particle_phase()
     for (int attempt = 0; attempt < 4 && !done; attempt++) {
         zero(d_small);
         zero(d_cnt);
-        ContQueue cq{(ContRec *)d_cq.p, (int32_t *)d_small.p + 4};
+        ParticleArgs *ha = (ParticleArgs *)((char *)h_pin + 128);
+        ha->m = dm;
+        ha->e = mixed ? (const void *)d_e32.p : (const void *)d_e.p;
+        ha->b = mixed ? (const void *)d_b32.p : (const void *)d_b.p;
+        ha->perm = perm;
+        ha->off = (const int32_t *)d_off.p;
+        ha->in = pb[cur].d;
+        ha->out = pb[1 - cur].d;
+        ha->np = np;
+        ha->sp = sp;
+        ha->gl = gl;
+        ha->P = (double *)d_P.p;
+        ha->pool = pool();
+        ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_small.p + 4};
+        ha->cnt = (unsigned long long *)d_cnt.p;
+        HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipEventRecord(ev_b, stream));
-        HIPCHECK(launch_particle(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p,
-                                 (const float *)d_e32.p, (const float *)d_b32.p, perm, (const int32_t *)d_off.p,
-                                 pb[cur].d, pb[1 - cur].d, np, sp, gl, (double *)d_P.p, pool(), cq,
-                                 Counters{(unsigned long long *)d_cnt.p}, stream));
+        HIPCHECK(launch_particle(order, mixed, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw, stream));
         HIPCHECK(hipEventRecord(ev_c1, stream));
-        HIPCHECK(launch_continue(order, mixed, dm, pb[1 - cur].d, np, sp, gl, pool(), cq,
-                                 Counters{(unsigned long long *)d_cnt.p}, stream));
+        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, np, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 4, hipMemcpyDeviceToHost, stream));
@@ -525,7 +537,7 @@ void Run::solve_fp64()
     for (int it = 0; it < prm.pcg_maxit;) {
         for (int k = 0; k < check && it < prm.pcg_maxit; k++, it++)
             HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
-                              (double *)v_q.p, (const double *)d_dinv.p, part, sc, stream));
+                              (double *)v_q.p, (const double *)d_dinv.p, part, sc, it & 1, stream));
         last_iters = it;
         rr = read_sc(SC_RR);
         if (!(rr == rr)) throw Error(FEMPIC_ESOLVE, "field solve produced NaN");
@@ -571,7 +583,7 @@ void Run::solve_mixed()
         while (it < prm.pcg_maxit) {
             for (int k = 0; k < 8; k++, it++)
                 HIPCHECK(pcg32_iter(A.desc, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
-                                    (float *)f_q.p, (const float *)d_dinv32.p, part, sc, stream));
+                                    (float *)f_q.p, (const float *)d_dinv32.p, part, sc, it & 1, stream));
             r32 = read_sc(SC_RR);
             if (!(r32 == r32)) throw Error(FEMPIC_ESOLVE, "FP32 inner solve produced NaN");
             if (r32 <= tol32) break;
