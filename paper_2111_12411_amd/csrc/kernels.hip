@@ -260,6 +260,35 @@ __device__ inline void bernstein(const double *q, double lo, double hi, double *
     bc[4] = d[0] + d1 + d2 + d3 + d4;
 }
 
+// Newton refinement of the single crossing of q in (lo, hi): q(lo) >= 0 > q(hi)
+// (values flo, fhi).  Regula-falsi start, Newton steps kept inside the
+// shrinking bracket (bisection when a step leaves it).  Stops once the Newton
+// correction is below tol (absolute, in u): at convergence the corrected point
+// can round onto a bracket end, which must not be taken for a step that left
+// the bracket.  The bracket bound ends the loop in any case (about 60 halvings
+// reach tol from a bracket of length H).
+__device__ inline double refine_root(const double *q, double lo, double hi, double flo, double fhi, double tol)
+{
+    double a = lo, b = hi;
+    double x = lo + (hi - lo) * (flo / (flo - fhi));
+    if (!(x > a && x < b)) x = 0.5 * (a + b);
+    for (int it = 0; it < 64; it++) {
+        const double fx = horner4(q, x);
+        if (fx == 0.0) break;
+        if (fx < 0.0) b = x; else a = x;
+        const double dx = fx / dhorner4(q, x);
+        if (fabs(dx) <= tol) {
+            x -= dx;
+            break;
+        }
+        double xn = x - dx;
+        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+        x = xn;
+        if (b - a <= tol) break;
+    }
+    return fmin(fmax(x, lo), hi);
+}
+
 // smallest u in [0, H] with q(u) < 0 (q in power basis of u).  Dyadic
 // subdivision driven by Bernstein sign tests, then safeguarded Newton on the
 // isolated crossing.  Visits a bounded number of intervals.
@@ -299,29 +328,8 @@ __device__ bool first_negative(const double *q, double H, double &uout)
             if (!any_neg) {
                 advance = true;
             } else if (changes == 1 && bc[4] < 0.0) {
-                // one crossing in (lo, hi): q(lo) >= 0 > q(hi).  Regula-falsi start,
-                // then Newton steps kept inside the shrinking bracket (bisection
-                // when a step leaves it); stop when the step is below 2 ulp.
-                double a = lo, b = hi, fa = bc[0], fb = bc[4];
-                double x = a + (b - a) * (fa / (fa - fb));
-                if (!(x > a && x < b)) x = 0.5 * (a + b);
-                for (int it = 0; it < 60; it++) {
-                    const double fx = horner4(q, x);
-                    if (fx == 0.0) break;
-                    if (fx < 0.0) {
-                        b = x;
-                        fb = fx;
-                    } else {
-                        a = x;
-                        fa = fx;
-                    }
-                    double xn = x - fx / dhorner4(q, x);
-                    if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
-                    const double step = fabs(xn - x);
-                    x = xn;
-                    if (step <= 4e-16 * fabs(x) || !(b - a > 4e-16 * fabs(b))) break;
-                }
-                uout = fmin(fmax(x, lo), hi);
+                // one crossing in (lo, hi): q(lo) >= 0 > q(hi)
+                uout = refine_root(q, lo, hi, bc[0], bc[4], 4e-16 * H);
                 return true;
             } else if (d >= MAXD) {
                 advance = true;  // tangency narrower than H 2^-40
@@ -385,135 +393,56 @@ __device__ inline void deposit_segment(const double L[4][5], double sa, double s
 }
 
 // -------------------------------------------------------------- particle
-// Newton refinement of the single crossing of q in (0, hi): q(0) >= 0 > q(hi).
-// Regula-falsi start, Newton steps kept inside the shrinking bracket (bisection
-// when a step leaves it), stop when the step is below 2 ulp.
-__device__ inline double refine_root(const double *q, double hi, double f0, double fh)
+// barycentric coordinate of face f (opposite vertex f) along the path, as a
+// polynomial in u = s - s_lo
+template <bool FROM_ZERO>
+__device__ inline void face_poly(const double *G, int f, const double (&cp)[5][3], double s_lo, double *q)
 {
-    double a = 0.0, b = hi;
-    double x = hi * (f0 / (f0 - fh));
-    if (!(x > a && x < b)) x = 0.5 * hi;
-    for (int it = 0; it < 60; it++) {
-        const double fx = horner4(q, x);
-        if (fx == 0.0) break;
-        if (fx < 0.0) b = x; else a = x;
-        double xn = x - fx / dhorner4(q, x);
-        if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
-        const double step = fabs(xn - x);
-        x = xn;
-        if (step <= 4e-16 * fabs(x) || !(b - a > 4e-16 * fabs(b))) break;
-    }
-    return fmin(fmax(x, 0.0), hi);
-}
-
-// Bernstein coefficients on [0, H] of q (power basis of u) and a class:
-// 0 = no negative value on [0,H], 1 = negative right after 0, 2 = exactly one
-// crossing inside, 3 = anything else (needs the subdivision search)
-__device__ inline int classify(const double *q, double H, double &b0, double &b4)
-{
-    const double H2 = H * H;
-    const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
-    double bc[5];
-    bc[0] = q[0];
-    bc[1] = fma(0.25, d1, q[0]);
-    bc[2] = fma(1.0 / 6.0, d2, fma(0.5, d1, q[0]));
-    bc[3] = fma(0.25, d3, fma(0.5, d2, fma(0.75, d1, q[0])));
-    bc[4] = q[0] + d1 + d2 + d3 + d4;
-    b0 = bc[0];
-    b4 = bc[4];
-    int first = -1;
+    const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
 #pragma unroll
-    for (int i = 4; i >= 0; i--)
-        if (bc[i] != 0.0) first = i;
-    if (first < 0) return 0;
-    if (bc[first] < 0.0) return 1;
-    bool any_neg = false;
-    int changes = 0;
-    double prev = bc[first];
-#pragma unroll
-    for (int i = 0; i < 5; i++) {
-        if (i <= first) continue;
-        if (bc[i] < 0.0) any_neg = true;
-        if (bc[i] != 0.0) {
-            if ((bc[i] < 0.0) != (prev < 0.0)) changes++;
-            prev = bc[i];
-        }
-    }
-    if (!any_neg) return 0;
-    if (changes == 1 && bc[4] < 0.0) return 2;
-    return 3;
+    for (int d = 0; d < 5; d++) q[d] = fma(gz, cp[d][2], fma(gy, cp[d][1], gx * cp[d][0]));
+    q[0] += a0;
+    if (!FROM_ZERO) taylor_shift(q, s_lo, q);
 }
 
 // exit of tet G from s_lo along the path cp: the first s > s_lo where a
 // barycentric coordinate turns negative (the entry face's coordinate is zero
-// at s_lo).  All four faces are classified without branches; one Newton
-// refinement runs per lane, on the likeliest face; other candidate faces are
-// checked with one polynomial evaluation and refined only when they cross first.
+// at s_lo).  A face whose Bernstein coefficients on [s_lo, 1] are all
+// non-negative cannot be crossed; this straight-line test settles most lanes.
+// The flagged faces of a lane (usually one) then go through the full search,
+// in increasing face order, each limited to the best crossing found so far.
 template <bool FROM_ZERO>
 __device__ inline int find_exit(const double *G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
 {
     s_exit = 2.0;
     const double H = 1.0 - s_lo;
     if (!(H > 0.0)) return -1;
-    double q[4][5], b0[4], b4[4];
-    int cls[4];
+    const double H2 = H * H;
+    unsigned negmask = 0;
 #pragma unroll
     for (int f = 0; f < 4; f++) {
-        const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
-#pragma unroll
-        for (int d = 0; d < 5; d++) q[f][d] = gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2];
-        q[f][0] += a0;
-        if (!FROM_ZERO) taylor_shift(q[f], s_lo, q[f]);
-        if (f == entry) q[f][0] = 0.0;
-        cls[f] = classify(q[f], H, b0[f], b4[f]);
+        double q[5];
+        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        if (f == entry) q[0] = 0.0;
+        const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
+        const double b1 = fma(0.25, d1, q[0]);
+        const double b2 = fma(1.0 / 6.0, d2, fma(0.5, d1, q[0]));
+        const double b3 = fma(0.25, d3, fma(0.5, d2, fma(0.75, d1, q[0])));
+        const double b4 = q[0] + d1 + d2 + d3 + d4;
+        const double mn = fmin(fmin(q[0], b1), fmin(fmin(b2, b3), b4));
+        negmask |= (mn < 0.0 ? 1u : 0u) << f;
     }
-    // negative right away: exit at s_lo through the smallest such face
-#pragma unroll
-    for (int f = 3; f >= 0; f--)
-        if (cls[f] == 1) {
-            s_exit = s_lo;
-            return f;
-        }
-    // likeliest single crossing (smallest regula-falsi estimate), refined once
-    int cand = -1;
-    double est = 2.0 * H;
-    double qs[5] = {0, 0, 0, 0, 0}, f0 = 0, fh = 0;
-#pragma unroll
-    for (int f = 0; f < 4; f++) {
-        if (cls[f] == 2) {
-            const double u = H * (b0[f] / (b0[f] - b4[f]));
-            if (cand < 0 || u < est) {
-                cand = f;
-                est = u;
-#pragma unroll
-                for (int d = 0; d < 5; d++) qs[d] = q[f][d];
-                f0 = b0[f];
-                fh = b4[f];
-            }
-        }
-    }
-    double ubest = 2.0 * H;
+    if (!negmask) return -1;
+    double ubest = H;
     int fbest = -1;
-    if (cand >= 0) {
-        ubest = refine_root(qs, H, f0, fh);
-        fbest = cand;
-    }
-    // other faces that may cross first
-#pragma unroll
-    for (int f = 0; f < 4; f++) {
-        if (f == cand || cls[f] < 2) continue;
-        const double lim = fmin(ubest, H);
-        double u = 0.0;
-        bool hit;
-        if (cls[f] == 2) {
-            // exactly one crossing in (0, H) (and cand >= 0): it comes no later
-            // than ubest iff q(ubest) <= 0
-            hit = horner4(q[f], lim) <= 0.0;
-            if (hit) u = refine_root(q[f], H, b0[f], b4[f]);
-        } else {
-            hit = first_negative(q[f], lim, u);
-        }
-        if (hit && (u < ubest || (u == ubest && f < fbest))) {
+    while (negmask) {
+        const int f = __builtin_ctz(negmask);
+        negmask &= negmask - 1u;
+        double q[5];
+        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        if (f == entry) q[0] = 0.0;
+        double u;
+        if (first_negative(q, fbest < 0 ? H : ubest, u) && (fbest < 0 || u < ubest)) {
             ubest = u;
             fbest = f;
         }
