@@ -63,11 +63,16 @@ struct ContRec {
     int32_t t;       // current tet
     int32_t entry;   // entry face of t (its barycentric coordinate is zero at s_lo)
     int32_t ncross;  // face crossings so far
+    int32_t pending; // face of t the path leaves through at s_lo, not yet crossed (-1: none)
+    int32_t pad;
 };
 
 struct ContQueue {
-    ContRec *rec;    // capacity: number of particles
-    int32_t *count;  // [1] records written (atomic)
+    ContRec *rec;    // [np] a wave of k_particle writes its records at the start of its own particle range
+    int32_t *flag;   // [np] 1 where rec holds a record
+    int32_t *pos;    // [np] exclusive prefix sum of flag
+    int32_t *idx;    // [np] rec slots of the records, in slot order
+    int32_t *count;  // [1] number of records (the total of the prefix sum)
 };
 
 struct Counters {  // device int64 [4]: crossings, reflections, spills, error bits
@@ -117,6 +122,7 @@ struct ParticleArgs {
     unsigned long long *cnt;  // Counters
 };
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
+hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s);
 hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t np, hipStream_t s);
 hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
                                 uint32_t *val, hipStream_t s);

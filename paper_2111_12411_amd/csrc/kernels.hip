@@ -350,53 +350,11 @@ __device__ bool first_negative(const double *q, double H, double &uout)
     return false;
 }
 
-// deposit one segment: dep_i += q w int_{sa}^{sb} Q_i(l) (l_a l_b' - l_b l_a') ds
-template <int K>
-__device__ inline void deposit_segment(const double L[4][5], double sa, double sb, double qw, const GLRule &gl,
-                                       double *dep)
-{
-    using O = Ord<K>;
-    const double h = sb - sa;
-#pragma unroll
-    for (int g = 0; g < O::NG; g++) {
-        const double s = fma(h, gl.x[g], sa);
-        const double wg = qw * h * gl.w[g];
-        double lam[4], dl[4];
-#pragma unroll
-        for (int m = 0; m < 4; m++) {
-            lam[m] = horner4(L[m], s);
-            dl[m] = dhorner4(L[m], s);
-        }
-        double w[6];
-#pragma unroll
-        for (int e = 0; e < 6; e++) w[e] = wg * (lam[EA[e]] * dl[EB[e]] - lam[EB[e]] * dl[EA[e]]);
-        if constexpr (K == 1) {
-#pragma unroll
-            for (int e = 0; e < 6; e++) dep[e] += w[e];
-        } else {
-#pragma unroll
-            for (int e = 0; e < 6; e++) {
-                dep[2 * e] += (3.0 * lam[EA[e]] - 1.0) * w[e];
-                dep[2 * e + 1] += (3.0 * lam[EB[e]] - 1.0) * w[e];
-            }
-            // faces: (a,b,c) -> 3 l_c W_ab, 3 l_b W_ac ; edge ids of ab, ac
-            dep[12] += 3.0 * lam[2] * w[0];
-            dep[13] += 3.0 * lam[1] * w[1];
-            dep[14] += 3.0 * lam[3] * w[0];
-            dep[15] += 3.0 * lam[1] * w[2];
-            dep[16] += 3.0 * lam[3] * w[1];
-            dep[17] += 3.0 * lam[2] * w[2];
-            dep[18] += 3.0 * lam[3] * w[3];
-            dep[19] += 3.0 * lam[2] * w[4];
-        }
-    }
-}
-
 // -------------------------------------------------------------- particle
 // barycentric coordinate of face f (opposite vertex f) along the path, as a
 // polynomial in u = s - s_lo
-template <bool FROM_ZERO>
-__device__ inline void face_poly(const double *G, int f, const double (&cp)[5][3], double s_lo, double *q)
+template <bool FROM_ZERO, typename GPtr>
+__device__ inline void face_poly(GPtr G, int f, const double (&cp)[5][3], double s_lo, double *q)
 {
     const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
 #pragma unroll
@@ -411,8 +369,8 @@ __device__ inline void face_poly(const double *G, int f, const double (&cp)[5][3
 // non-negative cannot be crossed; this straight-line test settles most lanes.
 // The flagged faces of a lane (usually one) then go through the full search,
 // in increasing face order, each limited to the best crossing found so far.
-template <bool FROM_ZERO>
-__device__ inline int find_exit(const double *G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
+template <bool FROM_ZERO, typename GPtr>
+__device__ inline int find_exit(GPtr G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
 {
     s_exit = 2.0;
     const double H = 1.0 - s_lo;
@@ -452,75 +410,204 @@ __device__ inline int find_exit(const double *G, const double (&cp)[5][3], doubl
     return fbest;
 }
 
-// current moments of the segment [sa, sb] of path cp inside tet G:
-// dep_i = q w int Q_i(l) (l_a l_b' - l_b l_a') ds, with l(s) = a + g . r(s) and
-// l'(s) = g . r'(s) (l_0 = 1 - l_1 - l_2 - l_3 and l_0' = -(l_1' + l_2' + l_3'))
-// evaluated at the Gauss-Legendre nodes of the segment.
-template <int K, typename GPtr>
-__device__ inline void segment_moments(GPtr G, const double (&cp)[5][3], double sa, double sb, double qw,
-                                       const GLRule &gl, double *dep)
+// Exit search without data-dependent loops, for the common cases.  Each face
+// is classified by its Bernstein coefficients on [s_lo, 1]: all non-negative
+// (never crossed), or positive at s_lo and negative at 1 with exactly one sign
+// change (exactly one crossing inside).  The crossing face with the smallest
+// regula-falsi estimate is refined by a fixed number of bracketed Newton steps;
+// every other crossing face must then stay non-negative up to that root (its
+// Bernstein coefficients on [s_lo, root] are non-negative).  Returns the exit
+// face (s_exit set), -1 for no exit, or -2 when the case needs the full search
+// (any other sign pattern, a start on a face, or no convergence).
+template <bool FROM_ZERO, typename GPtr>
+__device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
+{
+    s_exit = 2.0;
+    const double H = 1.0 - s_lo;
+    if (!(H > 0.0)) return -1;
+    const double H2 = H * H;
+    int best = -1;
+    double est = 0.0;
+    bool hard = false;
+    unsigned cand = 0;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        double q[5];
+        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        if (f == entry) q[0] = 0.0;
+        const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
+        const double b0 = q[0];
+        const double b1 = fma(0.25, d1, b0);
+        const double b2 = fma(1.0 / 6.0, d2, fma(0.5, d1, b0));
+        const double b3 = fma(0.25, d3, fma(0.5, d2, fma(0.75, d1, b0)));
+        const double b4 = b0 + d1 + d2 + d3 + d4;
+        const double mn = fmin(fmin(b0, b1), fmin(fmin(b2, b3), b4));
+        if (mn < 0.0) {
+            const int ch = ((b1 < 0.0) != (b0 < 0.0)) + ((b2 < 0.0) != (b1 < 0.0)) + ((b3 < 0.0) != (b2 < 0.0)) +
+                           ((b4 < 0.0) != (b3 < 0.0));
+            if (b0 > 0.0 && b4 < 0.0 && ch == 1) {
+                const double u0 = H * (b0 / (b0 - b4));
+                cand |= 1u << f;
+                if (best < 0 || u0 < est) {
+                    best = f;
+                    est = u0;
+                }
+            } else {
+                hard = true;
+            }
+        }
+    }
+    if (hard) return -2;
+    if (best < 0) return -1;
+    double q[5];
+    face_poly<FROM_ZERO>(G, best, cp, s_lo, q);
+    double a = 0.0, b = H, x = est;
+    if (!(x > a && x < b)) x = 0.5 * H;
+    const double tol = 4e-16 * H;
+    bool conv = false;
+#pragma unroll
+    for (int it = 0; it < 6; it++) {
+        const double fx = horner4(q, x);
+        const double dx = fx / dhorner4(q, x);
+        if (!conv) {
+            if (fx < 0.0) b = x; else a = x;
+            if (fx == 0.0 || fabs(dx) <= tol) {
+                if (fx != 0.0) x -= dx;
+                conv = true;
+            } else {
+                double xn = x - dx;
+                if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+                x = xn;
+            }
+        }
+    }
+    if (!conv) return -2;
+    x = fmin(fmax(x, 0.0), H);
+    cand &= ~(1u << best);
+    const double x2 = x * x;
+#pragma unroll
+    for (int f = 0; f < 4; f++) {
+        if (cand & (1u << f)) {
+            face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+            const double d1 = q[1] * x, d2 = q[2] * x2, d3 = q[3] * x2 * x, d4 = q[4] * x2 * x2;
+            const double b1 = fma(0.25, d1, q[0]);
+            const double b2 = fma(1.0 / 6.0, d2, fma(0.5, d1, q[0]));
+            const double b3 = fma(0.25, d3, fma(0.5, d2, fma(0.75, d1, q[0])));
+            const double b4 = q[0] + d1 + d2 + d3 + d4;
+            if (fmin(fmin(b1, b2), fmin(b3, b4)) < 0.0) hard = true;
+        }
+    }
+    if (hard) return -2;
+    s_exit = s_lo + x;
+    return best;
+}
+
+// current moments of a path segment inside one tet:
+// dep_i = q w int Q_i(l) (l_a l_b' - l_b l_a') du over u in [0, h], where
+// lq[m-1] holds l_m (m = 1..3) along the path as a quartic in u (the face
+// polynomials of the exit search), l_0 = 1 - l_1 - l_2 - l_3 and
+// l_0' = -(l_1' + l_2' + l_3'); Gauss-Legendre nodes on [0, h].  Only the
+// local DoFs C0 <= i < C1 are accumulated (a caller short of registers takes
+// the DoFs in two passes).
+template <int K, int C0 = 0, int C1 = Ord<K>::N1>
+__device__ inline void segment_moments(const double (&lq)[3][5], double h, double qw, const GLRule &gl, double *dep)
 {
     using O = Ord<K>;
 #pragma unroll
-    for (int c = 0; c < O::N1; c++) dep[c] = 0.0;
-    const double h = sb - sa;
+    for (int c = C0; c < C1; c++) dep[c] = 0.0;
     const double qwh = qw * h;
 #pragma unroll
     for (int g = 0; g < O::NG; g++) {
-        const double s = fma(h, gl.x[g], sa);
+        const double u = h * gl.x[g];
         const double wg = qwh * gl.w[g];
-        double r[3], dr[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            r[c] = fma(fma(fma(fma(cp[4][c], s, cp[3][c]), s, cp[2][c]), s, cp[1][c]), s, cp[0][c]);
-            dr[c] = wg * fma(fma(fma(4.0 * cp[4][c], s, 3.0 * cp[3][c]), s, 2.0 * cp[2][c]), s, cp[1][c]);
-        }
         double lam[4], dl[4];  // dl carries the quadrature weight
 #pragma unroll
         for (int m = 1; m < 4; m++) {
-            const double gx = G[4 * m + 1], gy = G[4 * m + 2], gz = G[4 * m + 3];
-            lam[m] = fma(gz, r[2], fma(gy, r[1], fma(gx, r[0], G[4 * m])));
-            dl[m] = fma(gz, dr[2], fma(gy, dr[1], gx * dr[0]));
+            lam[m] = horner4(lq[m - 1], u);
+            dl[m] = wg * dhorner4(lq[m - 1], u);
         }
         lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
         dl[0] = -(dl[1] + dl[2] + dl[3]);
         double w[6];
 #pragma unroll
         for (int e = 0; e < 6; e++) w[e] = fma(lam[EA[e]], dl[EB[e]], -lam[EB[e]] * dl[EA[e]]);
+        auto acc = [&](int c, double f, double x) {
+            if (c >= C0 && c < C1) dep[c] = fma(f, x, dep[c]);
+        };
         if constexpr (K == 1) {
 #pragma unroll
-            for (int e = 0; e < 6; e++) dep[e] += w[e];
+            for (int e = 0; e < 6; e++) acc(e, 1.0, w[e]);
         } else {
-            double t3[4], u3[4];
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-                u3[m] = 3.0 * lam[m];
-                t3[m] = u3[m] - 1.0;
-            }
 #pragma unroll
             for (int e = 0; e < 6; e++) {
-                dep[2 * e] = fma(t3[EA[e]], w[e], dep[2 * e]);
-                dep[2 * e + 1] = fma(t3[EB[e]], w[e], dep[2 * e + 1]);
+                acc(2 * e, 3.0 * lam[EA[e]] - 1.0, w[e]);
+                acc(2 * e + 1, 3.0 * lam[EB[e]] - 1.0, w[e]);
             }
             // faces (a,b,c): 3 l_c W_ab and 3 l_b W_ac
-            dep[12] = fma(u3[2], w[0], dep[12]);
-            dep[13] = fma(u3[1], w[1], dep[13]);
-            dep[14] = fma(u3[3], w[0], dep[14]);
-            dep[15] = fma(u3[1], w[2], dep[15]);
-            dep[16] = fma(u3[3], w[1], dep[16]);
-            dep[17] = fma(u3[2], w[2], dep[17]);
-            dep[18] = fma(u3[3], w[3], dep[18]);
-            dep[19] = fma(u3[2], w[4], dep[19]);
+            acc(12, 3.0 * lam[2], w[0]);
+            acc(13, 3.0 * lam[1], w[1]);
+            acc(14, 3.0 * lam[3], w[0]);
+            acc(15, 3.0 * lam[1], w[2]);
+            acc(16, 3.0 * lam[3], w[1]);
+            acc(17, 3.0 * lam[2], w[2]);
+            acc(18, 3.0 * lam[3], w[3]);
+            acc(19, 3.0 * lam[2], w[4]);
         }
     }
+}
+
+// global-memory views of the pointers a kernel reads from its argument block:
+// accesses through them compile to global (not flat) memory instructions, so
+// waits on LDS reads do not also wait for outstanding global stores
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p)
+{
+    return (gptr<T>)p;
+}
+
+struct GMesh {
+    gptr<const double> geo;
+    gptr<const int32_t> nbr, map1, map2;
+    int32_t nt;
+};
+__device__ inline GMesh gview(const DevMesh &m)
+{
+    return GMesh{glb(m.geo), glb(m.nbr), glb(m.map1), glb(m.map2), m.nt};
+}
+
+template <typename R>
+struct GParticles {
+    gptr<double> x, v;
+    gptr<R> vh, ah;
+    gptr<int32_t> tet, id;
+    int64_t cap;
+};
+template <typename R>
+__device__ inline GParticles<R> gview(const DevParticles &p)
+{
+    return GParticles<R>{glb(p.x), glb((double *)p.v), glb((R *)p.vh), glb((R *)p.ah), glb(p.tet), glb(p.id), p.cap};
+}
+
+struct GPool {
+    gptr<double> val;
+    gptr<int32_t> tet;
+    gptr<int64_t> tag;
+    gptr<int32_t> count, pcount;
+    int64_t cap;
+};
+__device__ inline GPool gview(const SpillPool &p)
+{
+    return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.count), glb(p.pcount), p.cap};
 }
 
 // leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
 // rest of the path about the face plane together with the stored velocity and
 // AB4 histories of particle i (written before tracking)
-template <typename R>
-__device__ inline void cross_face(const DevMesh &m, const double *G, int f, int &t, int &entry, double (&cp)[5][3],
-                                  const DevParticles &out, int64_t i, unsigned long long &nrf)
+template <typename R, typename GPtr>
+__device__ inline void cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&cp)[5][3],
+                                  const GParticles<R> &out, int64_t i, unsigned long long &nrf)
 {
     const int nb = m.nbr[(int64_t)t * 4 + f];
     if (nb >= 0) {
@@ -542,15 +629,15 @@ __device__ inline void cross_face(const DevMesh &m, const double *G, int f, int 
         cp[d][2] -= sd * gz;
     }
     {
-        double *vp = (double *)out.v;
-        const double sd = (gx * vp[i] + gy * vp[out.cap + i] + gz * vp[2 * out.cap + i]) * inv;
-        vp[i] -= sd * gx;
-        vp[out.cap + i] -= sd * gy;
-        vp[2 * out.cap + i] -= sd * gz;
+        const double x0 = out.v[i], x1 = out.v[out.cap + i], x2 = out.v[2 * out.cap + i];
+        const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
+        out.v[i] = x0 - sd * gx;
+        out.v[out.cap + i] = x1 - sd * gy;
+        out.v[2 * out.cap + i] = x2 - sd * gz;
     }
 #pragma unroll 1
     for (int h = 0; h < 6; h++) {
-        R *hp = (R *)(h < 3 ? out.vh : out.ah) + (int64_t)(3 * (h % 3)) * out.cap;
+        gptr<R> hp = (h < 3 ? out.vh : out.ah) + (int64_t)(3 * (h % 3)) * out.cap;
         const double x0 = hp[i], x1 = hp[out.cap + i], x2 = hp[2 * out.cap + i];
         const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
         hp[i] = (R)(x0 - sd * gx);
@@ -562,31 +649,52 @@ __device__ inline void cross_face(const DevMesh &m, const double *G, int f, int 
 }
 
 // wave-aggregated slot in a shared append buffer
-__device__ inline int64_t append_slot(int32_t *count)
+__device__ inline int64_t append_slot(gptr<int32_t> count)
 {
     const unsigned long long mask = __ballot(1);
     const int lane = __lane_id();
     const int leader = __ffsll((long long)mask) - 1;
     const int rank = __popcll(mask & ((1ull << lane) - 1ull));
     int basei = 0;
-    if (lane == leader) basei = atomicAdd(count, __popcll(mask));
+    if (lane == leader)
+        basei = __hip_atomic_fetch_add(count, (int)__popcll(mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     basei = __shfl(basei, leader);
     return (int64_t)basei + rank;
 }
 
-__device__ inline void write_spill(const SpillPool &pool, int N1, int t, int64_t i, int &nsp_i, const double *dep,
-                                   int &errs)
+// claims a spill record for segment nsp_i of particle i in tet t; returns the
+// slot, or -1 (and flags ERR_POOL) when the pool is full
+__device__ inline int64_t spill_slot(const GPool &pool, int t, int64_t i, int &nsp_i, int &errs)
 {
-    const int64_t slot_out = append_slot(pool.count);
-    if (slot_out < pool.cap && nsp_i < 64) {
-        pool.tet[slot_out] = t;
-        pool.tag[slot_out] = (i << 6) | nsp_i;
-        double *dst = &pool.val[slot_out * N1];
-        for (int c = 0; c < N1; c++) dst[c] = dep[c];
+    int64_t slot = append_slot(pool.count);
+    if (slot < pool.cap && nsp_i < 64) {
+        pool.tet[slot] = t;
+        pool.tag[slot] = (i << 6) | nsp_i;
     } else {
         errs |= ERR_POOL;
+        slot = -1;
     }
     nsp_i++;
+    return slot;
+}
+
+// counters of a wave, summed into the step counters (one atomic per wave)
+__device__ inline void flush_counters(gptr<unsigned long long> cnt, unsigned long long ncr, unsigned long long nrf,
+                                      unsigned long long nsp, int errs)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        ncr += __shfl_xor(ncr, o);
+        nrf += __shfl_xor(nrf, o);
+        nsp += __shfl_xor(nsp, o);
+        errs |= __shfl_xor(errs, o);
+    }
+    if (__lane_id() == 0) {
+        if (ncr) __hip_atomic_fetch_add(cnt, ncr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nrf) __hip_atomic_fetch_add(cnt + 1, nrf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (nsp) __hip_atomic_fetch_add(cnt + 2, nsp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (errs)
+            __hip_atomic_fetch_or(cnt + 3, (unsigned long long)errs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Kernel 1: per particle (sorted by tet), gather + AB4 push + the first path
@@ -596,19 +704,19 @@ __device__ inline void write_spill(const SpillPool &pool, int N1, int t, int64_t
 template <int K, typename R>
 __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restrict__ A)
 {
-    const DevMesh &m = A->m;
-    const R *__restrict__ e = (const R *)A->e;
-    const R *__restrict__ b = (const R *)A->b;
-    const uint32_t *__restrict__ perm = A->perm;
-    const int32_t *__restrict__ off = A->off;
-    const DevParticles &in = A->in;
-    const DevParticles &out = A->out;
+    const GMesh m = gview(A->m);
+    const gptr<const R> e = glb((const R *)A->e);
+    const gptr<const R> b = glb((const R *)A->b);
+    const gptr<const uint32_t> perm = glb(A->perm);
+    const gptr<const int32_t> off = glb(A->off);
+    const GParticles<R> in = gview<R>(A->in);
+    const GParticles<R> out = gview<R>(A->out);
     const StepParams &sp = A->sp;
     const GLRule &gl = A->gl;
-    double *__restrict__ P = A->P;
-    const SpillPool &pool = A->pool;
-    const ContQueue &cq = A->cq;
-    unsigned long long *__restrict__ cnt = A->cnt;
+    const gptr<double> P = glb(A->P);
+    const gptr<int32_t> pcount = glb(A->pool.pcount);
+    const gptr<ContRec> qrec = glb(A->cq.rec);
+    const gptr<int32_t> qflag = glb(A->cq.flag);
     using O = Ord<K>;
     constexpr int N1 = O::N1, N2 = O::N2, TM = O::TPW_MAX;
     __shared__ double s_geo[TM][16];
@@ -650,8 +758,6 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     const int wt = tid / N1, wc = tid % N1;
     const bool worker = tid < ntl * N1;
     double acc = 0.0;
-    unsigned long long ncr = 0, nrf = 0;
-    int errs = 0;
     const R dtR = (R)sp.dt;
     const R qmR = (R)sp.qm;
 
@@ -663,12 +769,16 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
             const uint32_t slot = perm[i];
             const int th = in.tet[slot];
             const int lt = th - T0;
-            double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
+            const double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
             double vd[3];
             R vh[9], ah[9];
-            load_vec<double>(in.v, in.cap, 0, slot, vd, 3);
-            load_vec<R>(in.vh, in.cap, 0, slot, vh, 9);
-            load_vec<R>(in.ah, in.cap, 0, slot, ah, 9);
+#pragma unroll
+            for (int c = 0; c < 3; c++) vd[c] = in.v[c * in.cap + slot];
+#pragma unroll
+            for (int c = 0; c < 9; c++) {
+                vh[c] = in.vh[c * in.cap + slot];
+                ah[c] = in.ah[c * in.cap + slot];
+            }
             const R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
             // barycentrics and fields at r^n (home tet, LDS)
             R lam[4];
@@ -707,48 +817,62 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
                     cp[d][c] = sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
             }
             // new velocity and shifted histories, written now (wall reflections patch them)
-            {
-                const R nvh[9] = {v[0], v[1], v[2], vh[0], vh[1], vh[2], vh[3], vh[4], vh[5]};
-                const R nah[9] = {a[0], a[1], a[2], ah[0], ah[1], ah[2], ah[3], ah[4], ah[5]};
-                store_vec<double>(out.v, out.cap, 0, i, vn, 3);
-                store_vec<R>(out.vh, out.cap, 0, i, nvh, 9);
-                store_vec<R>(out.ah, out.cap, 0, i, nah, 9);
-                out.id[i] = in.id[slot];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                out.v[c * out.cap + i] = vn[c];
+                out.vh[c * out.cap + i] = v[c];
+                out.vh[(3 + c) * out.cap + i] = vh[c];
+                out.vh[(6 + c) * out.cap + i] = vh[3 + c];
+                out.ah[c * out.cap + i] = a[c];
+                out.ah[(3 + c) * out.cap + i] = ah[c];
+                out.ah[(6 + c) * out.cap + i] = ah[3 + c];
             }
-            // first segment: in the home tet from s = 0
+            out.id[i] = in.id[slot];
+            // first segment: in the home tet from s = 0.  A path whose exit
+            // needs the full search is handed whole to k_continue; a path that
+            // leaves is handed over at its exit point (the crossing itself is
+            // done there).
             const double *G = &s_geo[lt][0];
             double s_exit;
-            const int f_exit = find_exit<true>(G, cp, 0.0, -1, s_exit);
-            const double s_hi = f_exit < 0 ? 1.0 : s_exit;
-            if (s_hi > 0.0) {
-                double dep[N1];
-                segment_moments<K>(G, cp, 0.0, s_hi, sp.qw, gl, dep);
+            const int f_exit = fast_exit<true>(G, cp, 0.0, -1, s_exit);
+            pcount[i] = 0;
+            // queued paths of the wave go to the start of the wave's own particle
+            // range (its active lanes are a prefix of the wave), in lane order
+            const unsigned long long qmask = __ballot(f_exit != -1);
+            const int lane = tid & 63;
+            qflag[i] = lane < __popcll(qmask) ? 1 : 0;
+            if (f_exit != -1) {
+                const int64_t qi = (int64_t)(i - lane) + __popcll(qmask & ((1ull << lane) - 1ull));
+                gptr<ContRec> rec = qrec + qi;
 #pragma unroll
-                for (int c = 0; c < N1; c++) s_hc[c][tid] = dep[c];
-            }
-            pool.pcount[i] = 0;
-            if (f_exit < 0) {
+                for (int d = 0; d < 5; d++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+                rec->s_lo = f_exit >= 0 ? s_exit : 0.0;
+                rec->i = i;
+                rec->t = th;
+                rec->entry = -1;
+                rec->ncross = 0;
+                rec->pending = f_exit >= 0 ? f_exit : -1;
+            } else {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
                     out.x[(int64_t)c * out.cap + i] = horner4(pc, 1.0);
                 }
                 out.tet[i] = th;
-            } else {
-                ncr++;
-                int t = th, entry = -1;
-                cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
-                const int64_t qi = append_slot(cq.count);
-                ContRec &rec = cq.rec[qi];  // capacity = particles: never overflows
+            }
+            if (f_exit != -2) {
+                const double s_hi = f_exit < 0 ? 1.0 : s_exit;
+                double lq[3][5];  // l_1..l_3 along the path in the home tet
 #pragma unroll
-                for (int d = 0; d < 5; d++)
+                for (int mm = 1; mm < 4; mm++) face_poly<true>(G, mm, cp, 0.0, lq[mm - 1]);
+                if (s_hi > 0.0) {
+                    double dep[N1];
+                    segment_moments<K>(lq, s_hi, sp.qw, gl, dep);
 #pragma unroll
-                    for (int c = 0; c < 3; c++) rec.cp[3 * d + c] = cp[d][c];
-                rec.s_lo = s_exit;
-                rec.i = i;
-                rec.t = t;
-                rec.entry = entry;
-                rec.ncross = 1;
+                    for (int c = 0; c < N1; c++) s_hc[c][tid] = dep[c];
+                }
             }
         }
         __syncthreads();
@@ -760,16 +884,6 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
         __syncthreads();
     }
     if (worker) P[(int64_t)(T0 + wt) * N1 + wc] = acc;
-    for (int o = 32; o > 0; o >>= 1) {
-        ncr += __shfl_xor(ncr, o);
-        nrf += __shfl_xor(nrf, o);
-        errs |= __shfl_xor(errs, o);
-    }
-    if (__lane_id() == 0) {
-        if (ncr) atomicAdd(&cnt[0], ncr);
-        if (nrf) atomicAdd(&cnt[1], nrf);
-        if (errs) atomicOr(&cnt[3], (unsigned long long)errs);
-    }
 }
 
 // Kernel 2: the rest of the paths of queued particles, segment by segment;
@@ -778,73 +892,110 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
 template <int K, typename R>
 __global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict__ A)
 {
-    const DevMesh &m = A->m;
-    const DevParticles &out = A->out;
+    const GMesh m = gview(A->m);
+    const GParticles<R> out = gview<R>(A->out);
     const StepParams &sp = A->sp;
     const GLRule &gl = A->gl;
-    const SpillPool &pool = A->pool;
-    const ContQueue &cq = A->cq;
-    unsigned long long *__restrict__ cnt = A->cnt;
+    const GPool pool = gview(A->pool);
+    const gptr<ContRec> qrec = glb(A->cq.rec);
+    const gptr<const int32_t> qidx = glb((const int32_t *)A->cq.idx);
+    const gptr<unsigned long long> cnt = glb(A->cnt);
     constexpr int N1 = Ord<K>::N1;
-    const int32_t nq = *cq.count;
+    const int32_t nq = *glb(A->cq.count);
     unsigned long long ncr = 0, nrf = 0, nsp = 0;
     int errs = 0;
     for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < nq; r += (int64_t)gridDim.x * BLK) {
-        const ContRec &rec = cq.rec[r];
-        double cp[5][3];
+        const gptr<ContRec> rec = qrec + qidx[r];
+        double s_lo = rec->s_lo;
+        const int64_t i = rec->i;
+        int t = rec->t, entry = rec->entry, ncross = rec->ncross, nsp_i = 0;
+        const int pending = rec->pending;
+        if (pending >= 0) {
+            // the exit found in the home tet: cross it now
+            double cp[5][3];
 #pragma unroll
-        for (int d = 0; d < 5; d++)
+            for (int d = 0; d < 5; d++)
 #pragma unroll
-            for (int c = 0; c < 3; c++) cp[d][c] = rec.cp[3 * d + c];
-        double s_lo = rec.s_lo;
-        const int64_t i = rec.i;
-        int t = rec.t, entry = rec.entry, ncross = rec.ncross, nsp_i = 0;
-        for (;;) {
-            const double *G = &m.geo[(int64_t)t * 16];
-            double s_exit;
-            const int f_exit = find_exit<false>(G, cp, s_lo, entry, s_exit);
-            const double s_hi = f_exit < 0 ? 1.0 : s_exit;
-            if (s_hi > s_lo) {
-                double g[16];
-#pragma unroll
-                for (int k = 0; k < 16; k++) g[k] = G[k];
-                double dep[N1];
-                segment_moments<K>(g, cp, s_lo, s_hi, sp.qw, gl, dep);
-                write_spill(pool, N1, t, i, nsp_i, dep, errs);
-            }
-            if (f_exit < 0) break;
-            if (++ncross > 64) {
-                errs |= ERR_CROSS;
-                break;
-            }
+                for (int c = 0; c < 3; c++) cp[d][c] = rec->cp[3 * d + c];
+            ncross++;
             ncr++;
-            cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
+            const unsigned long long nrf0 = nrf;
+            cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, cp, out, i, nrf);
+            if (nrf != nrf0) {
+#pragma unroll
+                for (int d = 0; d < 5; d++)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+            }
+        }
+        for (;;) {
+            // the path stays in the record between segments and is re-read here,
+            // so that it is not held in registers through the deposit
+            double cp[5][3];
+#pragma unroll
+            for (int d = 0; d < 5; d++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) cp[d][c] = rec->cp[3 * d + c];
+            const gptr<const double> G = m.geo + (int64_t)t * 16;
+            double s_exit;
+            int f_exit = fast_exit<false>(G, cp, s_lo, entry, s_exit);
+            if (f_exit == -2) f_exit = find_exit<false>(G, cp, s_lo, entry, s_exit);
+            const double s_hi = f_exit < 0 ? 1.0 : s_exit;
+            double lq[3][5];  // l_1..l_3 of this tet along the path from s_lo
+#pragma unroll
+            for (int mm = 1; mm < 4; mm++) face_poly<false>(G, mm, cp, s_lo, lq[mm - 1]);
+            const int t_seg = t;
+            bool more = false;
+            if (f_exit >= 0 && ncross < 64) {
+                ncross++;
+                ncr++;
+                const unsigned long long nrf0 = nrf;
+                cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
+                if (nrf != nrf0) {  // a wall reflection changed the path
+#pragma unroll
+                    for (int d = 0; d < 5; d++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+                }
+                more = true;
+            } else {
+                if (f_exit >= 0) errs |= ERR_CROSS;
+                double rn[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
+                    rn[c] = horner4(pc, 1.0);
+                    out.x[(int64_t)c * out.cap + i] = rn[c];
+                }
+                if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
+                out.tet[i] = t;
+            }
+            asm volatile("" ::: "memory");
+            if (s_hi > s_lo) {
+                const int64_t slot = spill_slot(pool, t_seg, i, nsp_i, errs);
+                if (slot >= 0) {
+                    double dep[N1];
+                    segment_moments<K>(lq, s_hi - s_lo, sp.qw, gl, dep);
+                    const gptr<double> dst = pool.val + slot * N1;
+#pragma unroll
+                    for (int c = 0; c < N1; c++) dst[c] = dep[c];
+                }
+            }
+            if (!more) break;
             s_lo = s_exit;
         }
         nsp += nsp_i;
         pool.pcount[i] = nsp_i;
-        double rn[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
-            rn[c] = horner4(pc, 1.0);
-            out.x[(int64_t)c * out.cap + i] = rn[c];
-        }
-        if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
-        out.tet[i] = t;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        ncr += __shfl_xor(ncr, o);
-        nrf += __shfl_xor(nrf, o);
-        nsp += __shfl_xor(nsp, o);
-        errs |= __shfl_xor(errs, o);
-    }
-    if (__lane_id() == 0) {
-        if (ncr) atomicAdd(&cnt[0], ncr);
-        if (nrf) atomicAdd(&cnt[1], nrf);
-        if (nsp) atomicAdd(&cnt[2], nsp);
-        if (errs) atomicOr(&cnt[3], (unsigned long long)errs);
-    }
+    flush_counters(cnt, ncr, nrf, nsp, errs);
+}
+
+// compacted list of the queued record slots: idx[pos[i]] = i where flag[i]
+__global__ void k_queue_index(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
+                              int32_t *__restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (i < n && flag[i]) idx[pos[i]] = (int32_t)i;
 }
 
 // ------------------------------------------------------------ permute
@@ -1456,6 +1607,12 @@ hipError_t launch_particle(int order, bool mixed, const ParticleArgs *A, int32_t
         if (mixed) hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(PBLK), 0, s, A);
         else hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(PBLK), 0, s, A);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s)
+{
+    if (np > 0) hipLaunchKernelGGL(k_queue_index, dim3(nblk(np)), dim3(BLK), 0, s, cq.flag, cq.pos, np, cq.idx);
     return hipGetLastError();
 }
 

@@ -238,6 +238,9 @@ void Run::alloc_particles(int64_t n)
     d_pcount.alloc(cap * 4);
     d_ppos.alloc(cap * 4);
     d_cq.alloc((size_t)cap * sizeof(ContRec));
+    d_qflag.alloc(cap * 4);
+    d_qpos.alloc(cap * 4);
+    d_qidx.alloc(cap * 4);
 }
 
 void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
@@ -442,12 +445,17 @@ void Run::particle_phase()
         ha->gl = gl;
         ha->P = (double *)d_P.p;
         ha->pool = pool();
-        ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_small.p + 4};
+        ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_qflag.p, (int32_t *)d_qpos.p, (int32_t *)d_qidx.p,
+                           (int32_t *)d_small.p + 6};
         ha->cnt = (unsigned long long *)d_cnt.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipEventRecord(ev_b, stream));
         HIPCHECK(launch_particle(order, mixed, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw, stream));
         HIPCHECK(hipEventRecord(ev_c1, stream));
+        // compact the queue written by k_particle, then continue the queued paths
+        HIPCHECK(exclusive_scan_u32((const uint32_t *)d_qflag.p, (uint32_t *)d_qpos.p, np, psort.scan_tmp,
+                                    (uint32_t *)d_small.p + 6, stream));
+        HIPCHECK(launch_queue_index(ha->cq, np, stream));
         HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, np, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));

@@ -95,7 +95,7 @@ class Run {
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_small, d_args;
-    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos, d_cq;
+    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos, d_cq, d_qflag, d_qpos, d_qidx;
     std::vector<DevBuf> hp_sort, hp_ssort;
     PBufs pb[2];
     int cur = 0;
