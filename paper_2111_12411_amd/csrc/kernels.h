@@ -120,10 +120,14 @@ struct ParticleArgs {
     SpillPool pool;
     ContQueue cq;
     unsigned long long *cnt;  // Counters
+    unsigned long long *cntb; // [CONT_BLOCKS][4] per-block counters of the continuation kernel
 };
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
 hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s);
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t np, hipStream_t s);
+// blocks of the continuation kernel (one counter slot each in cntb)
+constexpr int CONT_BLOCKS = 4096;
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t np, unsigned long long *cntb,
+                           unsigned long long *cnt, hipStream_t s);
 hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
                                 uint32_t *val, hipStream_t s);
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,

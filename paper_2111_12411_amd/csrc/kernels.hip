@@ -662,11 +662,14 @@ __device__ inline int64_t append_slot(gptr<int32_t> count)
     return (int64_t)basei + rank;
 }
 
-// claims a spill record for segment nsp_i of particle i in tet t; returns the
-// slot, or -1 (and flags ERR_POOL) when the pool is full
-__device__ inline int64_t spill_slot(const GPool &pool, int t, int64_t i, int &nsp_i, int &errs)
+// claims the spill record for segment nsp_i of queued record r (particle i,
+// tet t): segments 0 and 1 take the fixed slots 2r and 2r+1, later ones are
+// appended after the fixed region of 2 nq slots.  Returns the slot, or -1 (and
+// flags ERR_POOL) when the pool is full.
+__device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, int t, int64_t i, int &nsp_i,
+                                     int &errs)
 {
-    int64_t slot = append_slot(pool.count);
+    int64_t slot = nsp_i < 2 ? 2 * r + nsp_i : 2 * nq + append_slot(pool.count);
     if (slot < pool.cap && nsp_i < 64) {
         pool.tet[slot] = t;
         pool.tag[slot] = (i << 6) | nsp_i;
@@ -678,22 +681,30 @@ __device__ inline int64_t spill_slot(const GPool &pool, int t, int64_t i, int &n
     return slot;
 }
 
-// counters of a wave, summed into the step counters (one atomic per wave)
-__device__ inline void flush_counters(gptr<unsigned long long> cnt, unsigned long long ncr, unsigned long long nrf,
+// counters of a block (crossings, reflections, spills, error flags), summed in
+// a fixed order and written to the block's own slot of cntb
+__device__ inline void block_counters(gptr<unsigned long long> cntb, unsigned long long ncr, unsigned long long nrf,
                                       unsigned long long nsp, int errs)
 {
+    __shared__ unsigned long long s_c[BLK / 64][4];
     for (int o = 32; o > 0; o >>= 1) {
         ncr += __shfl_xor(ncr, o);
         nrf += __shfl_xor(nrf, o);
         nsp += __shfl_xor(nsp, o);
         errs |= __shfl_xor(errs, o);
     }
+    const int w = threadIdx.x / 64;
     if (__lane_id() == 0) {
-        if (ncr) __hip_atomic_fetch_add(cnt, ncr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (nrf) __hip_atomic_fetch_add(cnt + 1, nrf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (nsp) __hip_atomic_fetch_add(cnt + 2, nsp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (errs)
-            __hip_atomic_fetch_or(cnt + 3, (unsigned long long)errs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_c[w][0] = ncr;
+        s_c[w][1] = nrf;
+        s_c[w][2] = nsp;
+        s_c[w][3] = (unsigned long long)errs;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        unsigned long long v = 0;
+        for (int k = 0; k < BLK / 64; k++) v = threadIdx.x == 3 ? (v | s_c[k][3]) : v + s_c[k][threadIdx.x];
+        cntb[(int64_t)blockIdx.x * 4 + threadIdx.x] = v;
     }
 }
 
@@ -890,7 +901,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
 // every segment's current moments go to the spill pool tagged with
 // (sorted particle, segment), so their reduction order is canonical.
 template <int K, typename R>
-__global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict__ A)
+__global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restrict__ A)
 {
     const GMesh m = gview(A->m);
     const GParticles<R> out = gview<R>(A->out);
@@ -899,7 +910,7 @@ __global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict
     const GPool pool = gview(A->pool);
     const gptr<ContRec> qrec = glb(A->cq.rec);
     const gptr<const int32_t> qidx = glb((const int32_t *)A->cq.idx);
-    const gptr<unsigned long long> cnt = glb(A->cnt);
+    const gptr<unsigned long long> cntb = glb(A->cntb);
     constexpr int N1 = Ord<K>::N1;
     const int32_t nq = *glb(A->cq.count);
     unsigned long long ncr = 0, nrf = 0, nsp = 0;
@@ -972,7 +983,7 @@ __global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict
             }
             asm volatile("" ::: "memory");
             if (s_hi > s_lo) {
-                const int64_t slot = spill_slot(pool, t_seg, i, nsp_i, errs);
+                const int64_t slot = spill_slot(pool, r, nq, t_seg, i, nsp_i, errs);
                 if (slot >= 0) {
                     double dep[N1];
                     segment_moments<K>(lq, s_hi - s_lo, sp.qw, gl, dep);
@@ -984,10 +995,41 @@ __global__ __launch_bounds__(BLK) void k_continue(const ParticleArgs *__restrict
             if (!more) break;
             s_lo = s_exit;
         }
+        // fixed slots left unused are marked empty
+        for (int j = nsp_i; j < 2; j++)
+            if (2 * r + j < pool.cap) pool.tag[2 * r + j] = -1;
         nsp += nsp_i;
         pool.pcount[i] = nsp_i;
     }
-    flush_counters(cnt, ncr, nrf, nsp, errs);
+    block_counters(cntb, ncr, nrf, nsp, errs);
+}
+
+// step counters: sum (or, for the error flags) of the per-block counters
+// (integer sums: exact in any order)
+__global__ __launch_bounds__(BLK) void k_counters(const unsigned long long *__restrict__ cntb, int nb,
+                                                  unsigned long long *__restrict__ cnt)
+{
+    __shared__ unsigned long long s_v[4][BLK];
+    unsigned long long v[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nb; b += BLK) {
+        v[0] += cntb[b * 4];
+        v[1] += cntb[b * 4 + 1];
+        v[2] += cntb[b * 4 + 2];
+        v[3] |= cntb[b * 4 + 3];
+    }
+    for (int k = 0; k < 4; k++) s_v[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = BLK / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int k = 0; k < 3; k++) s_v[k][threadIdx.x] += s_v[k][threadIdx.x + h];
+            s_v[3][threadIdx.x] |= s_v[3][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        cnt[k] = k == 3 ? (cnt[k] | s_v[3][0]) : cnt[k] + s_v[k][0];
+    }
 }
 
 // compacted list of the queued record slots: idx[pos[i]] = i where flag[i]
@@ -1182,6 +1224,7 @@ __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t 
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrec) return;
     const int64_t tag = ptag[r];
+    if (tag < 0) return;  // unused fixed slot
     const int64_t i = tag >> 6;
     const int j = (int)(tag & 63);
     const uint32_t dst = pos[i] + (uint32_t)j;
@@ -1616,9 +1659,10 @@ hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t np, hipStream_t s)
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t np, unsigned long long *cntb,
+                           unsigned long long *cnt, hipStream_t s)
 {
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (np + BLK - 1) / BLK));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(CONT_BLOCKS, (np + BLK - 1) / BLK));
     if (order == 1) {
         if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, A);
         else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, A);
@@ -1626,6 +1670,7 @@ hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t
         if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, A);
         else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, A);
     }
+    hipLaunchKernelGGL(k_counters, dim3(1), dim3(BLK), 0, s, cntb, (int)grid, cnt);
     return hipGetLastError();
 }
 

@@ -175,6 +175,7 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_off.alloc((size_t)(m.nt + 1) * 4);
     d_soff.alloc((size_t)(m.nt + 1) * 4);
     d_cnt.alloc(8 * 8);
+    d_cntb.alloc((size_t)CONT_BLOCKS * 4 * 8);
     d_small.alloc(64);
     HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
     d_args.alloc(sizeof(ParticleArgs));
@@ -448,6 +449,7 @@ void Run::particle_phase()
         ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_qflag.p, (int32_t *)d_qpos.p, (int32_t *)d_qidx.p,
                            (int32_t *)d_small.p + 6};
         ha->cnt = (unsigned long long *)d_cnt.p;
+        ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipEventRecord(ev_b, stream));
         HIPCHECK(launch_particle(order, mixed, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw, stream));
@@ -456,25 +458,29 @@ void Run::particle_phase()
         HIPCHECK(exclusive_scan_u32((const uint32_t *)d_qflag.p, (uint32_t *)d_qpos.p, np, psort.scan_tmp,
                                     (uint32_t *)d_small.p + 6, stream));
         HIPCHECK(launch_queue_index(ha->cq, np, stream));
-        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, np, stream));
+        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, np, (unsigned long long *)d_cntb.p,
+                                 (unsigned long long *)d_cnt.p, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
-        HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         const unsigned long long *c = (const unsigned long long *)h_pin;
-        const int32_t nrec = *(const int32_t *)((char *)h_pin + 32);
+        const int32_t *sm = (const int32_t *)((char *)h_pin + 32);
+        // spill slots in use: the fixed pair of every queued record, then the appended ones
+        const int64_t nslots = 2 * (int64_t)sm[6] + sm[0];
         last_cross = (int64_t)c[0];
         last_refl = (int64_t)c[1];
         last_spill = (int64_t)c[2];
         const unsigned long long errs = c[3];
         if (errs & ERR_POOL) {
             // grow the pool and redo the step (the input state is untouched)
-            alloc_pool(std::max<int64_t>(2 * pool_cap, (int64_t)nrec + nrec / 4 + 1024));
+            alloc_pool(std::max<int64_t>(2 * pool_cap, nslots + nslots / 4 + 1024));
             continue;
         }
         if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
         if (errs & ERR_NAN) throw Error(FEMPIC_EDEVICE, "non-finite particle position");
-        nrec_last = nrec;
+        nslot_last = nslots;
+        nrec_last = last_spill;
         done = true;
     }
     if (!done) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
@@ -483,7 +489,8 @@ void Run::particle_phase()
     HIPCHECK(exclusive_scan_u32((const uint32_t *)d_pcount.p, (uint32_t *)d_ppos.p, np, psort.scan_tmp,
                                 (uint32_t *)d_small.p + 2, stream));
     if (nrec > 0) {
-        HIPCHECK(launch_spill_compact(pool(), nrec, np, (const uint32_t *)d_ppos.p, ssort.key[0], ssort.val[0], stream));
+        HIPCHECK(launch_spill_compact(pool(), nslot_last, np, (const uint32_t *)d_ppos.p, ssort.key[0], ssort.val[0],
+                                      stream));
         int res = 0;
         HIPCHECK(radix_sort(ssort, nrec, key_bits(), false, &res, stream));
         HIPCHECK(launch_offsets(ssort.key[res], nrec, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
