@@ -11,8 +11,10 @@ precision; the plain FP64 path on the same workload is timed beside it.
 Prints ONE JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,6 +38,25 @@ def algorithmic_bytes(order, precision, n_particles, n_tet):
     n1, n2 = (6, 4) if order == 1 else (20, 15)
     per_tet = 16 * 8 + (n1 + n2) * (rs + 4) + n1 * 8
     return 2 * state * n_particles + per_tet * n_tet, state, per_tet
+
+
+def profiled_traffic():
+    """HBM bytes per launch of k_particle<2, float> on the default workload, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None
+    when the kernel sources changed since those counters were taken."""
+    try:
+        txt = open(os.path.join(ROOT, "profiles", "k_particle_c3_mixed_hbm_counters.md")).read()
+    except OSError:
+        return None
+    m1 = re.search(r"traffic_bytes_per_launch: (\S+)", txt)
+    m2 = re.search(r"kernel_source_sha256: (\S+)", txt)
+    if not (m1 and m2):
+        return None
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2111_12411_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return float(m1.group(1)) if h.hexdigest() == m2.group(1) else None
 
 
 def run_workload(cfg_id, precision, steps, warmup, n=None):
@@ -116,6 +137,7 @@ def main():
     alg, state_b, tet_b = algorithmic_bytes(cfg["order"], F.MIXED, mix["n"], mix["info"]["n_tet"])
     kernel_s = kms / K / 1e3
     achieved = alg / kernel_s / 1e9
+    traffic = profiled_traffic() if args.particles is None else None
     out = {
         "metric": "particle-steps/sec (gather+push+deposit) at p=1/2, FP64 vs mixed; Gauss residual",
         "value": value,
@@ -140,7 +162,8 @@ def main():
         "crossings_per_particle_step": st["crossings"] / mix["n"],
         "spills_per_particle_step": st["spills"] / mix["n"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "kernel": "k_particle<2,float>", "kernel_ms": kms / K,
                      "alg_bytes_per_launch": alg, "state_bytes": state_b, "per_tet_bytes": tet_b},
     }

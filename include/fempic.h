@@ -103,8 +103,10 @@ int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out);
  * other values are rejected with EINVAL.  `hip_stream` may be NULL (the run
  * creates its own default-priority stream).  pcg_rtol is the relative residual
  * of the field solve (FP64); pcg_maxit caps its iterations (ESOLVE beyond).
- * spill_slots sizes the per-particle buffer for path segments that leave the
- * particle's tet (0 = default 4); a step that needs more fails with ECROSS.
+ * spill_slots is reserved and ignored: the buffer of path segments outside the
+ * particle's home tet grows on demand (a step that overflows it is redone after
+ * the buffer doubles; ENOMEM if that keeps failing).  A path that crosses more
+ * than 64 faces in one step fails the step with ECROSS.
  */
 typedef struct {
     int32_t precision;   /* FEMPIC_FP64 or FEMPIC_MIXED */
@@ -113,7 +115,7 @@ typedef struct {
     double pcg_rtol;     /* e.g. 1e-14 */
     int32_t pcg_maxit;   /* e.g. 5000 */
     int32_t particle_bc; /* FEMPIC_REFLECT */
-    int32_t spill_slots; /* 0 = default */
+    int32_t spill_slots; /* reserved, ignored */
 } fempic_params;
 
 int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out);
