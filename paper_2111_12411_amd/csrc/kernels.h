@@ -33,8 +33,12 @@ struct DevParticles {
     int64_t cap;
 };
 
-// threads per block of the particle kernel (tets per block <= PARTICLE_BLOCK / n1_loc)
-constexpr int PARTICLE_BLOCK = 128;
+// particle kernel: threads per block, most tets per block (order 1, 2), and the
+// number of particles a block aims at (tets per block = that / particles per tet)
+constexpr int PARTICLE_BLOCK = 256;
+constexpr int PARTICLE_TPW_MAX_1 = 64;
+constexpr int PARTICLE_TPW_MAX_2 = 16;
+constexpr int PARTICLE_TARGET = 512;
 
 struct StepParams {
     double qm;      // q / m

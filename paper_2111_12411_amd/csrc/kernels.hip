@@ -37,15 +37,16 @@ __device__ __constant__ const double LCOEF[4][5] = {
 
 template <int K>
 struct Ord;
-// threads per block of the particle kernel; TPW_MAX = PBLK / N1 tets per block
-constexpr int PBLK = 128;
+// threads per block of the particle kernel; a block owns up to TPW_MAX
+// consecutive tets and walks their particles in chunks of PBLK
+constexpr int PBLK = PARTICLE_BLOCK;
 template <>
 struct Ord<1> {
-    static constexpr int N1 = 6, N2 = 4, N0 = 4, NG = 4, TPW_MAX = PBLK / 6;
+    static constexpr int N1 = 6, N2 = 4, N0 = 4, NG = 4, TPW_MAX = PARTICLE_TPW_MAX_1;
 };
 template <>
 struct Ord<2> {
-    static constexpr int N1 = 20, N2 = 15, N0 = 10, NG = 6, TPW_MAX = PBLK / 20;
+    static constexpr int N1 = 20, N2 = 15, N0 = 10, NG = 6, TPW_MAX = PARTICLE_TPW_MAX_2;
 };
 
 // local edges (a,b) and faces (a,b,c); face f opposite vertex 3-f
@@ -766,9 +767,11 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     __syncthreads();
 
     const int pbeg = s_off[0], pend = s_off[ntl];
-    const int wt = tid / N1, wc = tid % N1;
-    const bool worker = tid < ntl * N1;
-    double acc = 0.0;
+    // (tet, component) pairs of the block's sums: pair tid + q PBLK for q < NP
+    constexpr int NP = (TM * N1 + PBLK - 1) / PBLK;
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; q++) acc[q] = 0.0;
     const R dtR = (R)sp.dt;
     const R qmR = (R)sp.qm;
 
@@ -887,14 +890,35 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
             }
         }
         __syncthreads();
-        if (worker) {
-            const int lo = max(s_off[wt], base) - base;
-            const int hi = min(s_off[wt + 1], base + PBLK) - base;
-            for (int j = lo; j < hi; j++) acc += s_hc[wc][j];
+#pragma unroll
+        for (int q = 0; q < NP; q++) {
+            const int pr = tid + q * PBLK;
+            if (pr < ntl * N1) {
+                // fixed order: four interleaved partial sums, then (0+1)+(2+3)
+                const int wt = pr / N1, wc = pr % N1;
+                const int lo = max(s_off[wt], base) - base;
+                const int hi = min(s_off[wt + 1], base + PBLK) - base;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int j = lo;
+                for (; j + 3 < hi; j += 4) {
+                    a0 += s_hc[wc][j];
+                    a1 += s_hc[wc][j + 1];
+                    a2 += s_hc[wc][j + 2];
+                    a3 += s_hc[wc][j + 3];
+                }
+                if (j < hi) a0 += s_hc[wc][j];
+                if (j + 1 < hi) a1 += s_hc[wc][j + 1];
+                if (j + 2 < hi) a2 += s_hc[wc][j + 2];
+                acc[q] += (a0 + a1) + (a2 + a3);
+            }
         }
         __syncthreads();
     }
-    if (worker) P[(int64_t)(T0 + wt) * N1 + wc] = acc;
+#pragma unroll
+    for (int q = 0; q < NP; q++) {
+        const int pr = tid + q * PBLK;
+        if (pr < ntl * N1) P[(int64_t)T0 * N1 + pr] = acc[q];
+    }
 }
 
 // Kernel 2: the rest of the paths of queued particles, segment by segment;

@@ -418,9 +418,9 @@ void Run::compute_rho(double *dst)
 
 int Run::tpw() const
 {
-    const int tmax = PARTICLE_BLOCK / n1l;
+    const int tmax = order == 1 ? PARTICLE_TPW_MAX_1 : PARTICLE_TPW_MAX_2;
     const double ppt = m.nt ? (double)np / m.nt : 1.0;
-    int t = (int)std::lround((double)PARTICLE_BLOCK / std::max(ppt, 1e-9));
+    int t = (int)std::lround((double)PARTICLE_TARGET / std::max(ppt, 1e-9));
     return std::max(1, std::min(tmax, t));
 }
 
