@@ -53,9 +53,9 @@ enum : int32_t { ERR_CROSS = 1, ERR_POOL = 2, ERR_OUTSIDE = 4, ERR_NAN = 8 };
 struct SpillPool {
     double *val;     // [cap][n1l]
     int32_t *tet;    // [cap]
-    int64_t *tag;    // [cap]   (sorted particle index << 6) | segment index
-    int32_t *count;  // [1] records written (atomic)
-    int32_t *pcount; // [np] spills of each sorted particle
+    int64_t *tag;    // [cap]   (queued record << 6) | segment index; -1: unused slot
+    int32_t *count;  // [1] records appended past the fixed slots (atomic)
+    int32_t *rcount; // [np] spill records of each queued record
     int64_t cap;
 };
 

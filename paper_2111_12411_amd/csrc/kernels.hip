@@ -595,12 +595,12 @@ struct GPool {
     gptr<double> val;
     gptr<int32_t> tet;
     gptr<int64_t> tag;
-    gptr<int32_t> count, pcount;
+    gptr<int32_t> count, rcount;
     int64_t cap;
 };
 __device__ inline GPool gview(const SpillPool &p)
 {
-    return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.count), glb(p.pcount), p.cap};
+    return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.count), glb(p.rcount), p.cap};
 }
 
 // leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
@@ -663,17 +663,15 @@ __device__ inline int64_t append_slot(gptr<int32_t> count)
     return (int64_t)basei + rank;
 }
 
-// claims the spill record for segment nsp_i of queued record r (particle i,
-// tet t): segments 0 and 1 take the fixed slots 2r and 2r+1, later ones are
+// claims the spill record for segment nsp_i of queued record r (tet t): segments 0 and 1 take the fixed slots 2r and 2r+1, later ones are
 // appended after the fixed region of 2 nq slots.  Returns the slot, or -1 (and
 // flags ERR_POOL) when the pool is full.
-__device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, int t, int64_t i, int &nsp_i,
-                                     int &errs)
+__device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, int t, int &nsp_i, int &errs)
 {
     int64_t slot = nsp_i < 2 ? 2 * r + nsp_i : 2 * nq + append_slot(pool.count);
     if (slot < pool.cap && nsp_i < 64) {
         pool.tet[slot] = t;
-        pool.tag[slot] = (i << 6) | nsp_i;
+        pool.tag[slot] = (r << 6) | nsp_i;
     } else {
         errs |= ERR_POOL;
         slot = -1;
@@ -726,7 +724,6 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     const StepParams &sp = A->sp;
     const GLRule &gl = A->gl;
     const gptr<double> P = glb(A->P);
-    const gptr<int32_t> pcount = glb(A->pool.pcount);
     const gptr<ContRec> qrec = glb(A->cq.rec);
     const gptr<int32_t> qflag = glb(A->cq.flag);
     using O = Ord<K>;
@@ -849,7 +846,6 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
             const double *G = &s_geo[lt][0];
             double s_exit;
             const int f_exit = fast_exit<true>(G, cp, 0.0, -1, s_exit);
-            pcount[i] = 0;
             // queued paths of the wave go to the start of the wave's own particle
             // range (its active lanes are a prefix of the wave), in lane order
             const unsigned long long qmask = __ballot(f_exit != -1);
@@ -1007,7 +1003,7 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
             }
             asm volatile("" ::: "memory");
             if (s_hi > s_lo) {
-                const int64_t slot = spill_slot(pool, r, nq, t_seg, i, nsp_i, errs);
+                const int64_t slot = spill_slot(pool, r, nq, t_seg, nsp_i, errs);
                 if (slot >= 0) {
                     double dep[N1];
                     segment_moments<K>(lq, s_hi - s_lo, sp.qw, gl, dep);
@@ -1023,7 +1019,7 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
         for (int j = nsp_i; j < 2; j++)
             if (2 * r + j < pool.cap) pool.tag[2 * r + j] = -1;
         nsp += nsp_i;
-        pool.pcount[i] = nsp_i;
+        pool.rcount[r] = nsp_i;
     }
     block_counters(cntb, ncr, nrf, nsp, errs);
 }
@@ -1249,9 +1245,9 @@ __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t 
     if (r >= nrec) return;
     const int64_t tag = ptag[r];
     if (tag < 0) return;  // unused fixed slot
-    const int64_t i = tag >> 6;
+    const int64_t q = tag >> 6;
     const int j = (int)(tag & 63);
-    const uint32_t dst = pos[i] + (uint32_t)j;
+    const uint32_t dst = pos[q] + (uint32_t)j;
     key[dst] = (uint32_t)ptet[r];
     val[dst] = (uint32_t)r;
 }
@@ -1266,9 +1262,20 @@ __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, con
     const int c = (int)(g % N1);
     const int32_t lo = soff[t], hi = soff[t + 1];
     if (lo == hi) return;
-    double s = P[g];
-    for (int32_t k = lo; k < hi; k++) s += recval[(int64_t)rec[k] * N1 + c];
-    P[g] = s;
+    // fixed order: four interleaved partial sums, then (0+1)+(2+3), added to the home sum
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t k = lo;
+    for (; k + 3 < hi; k += 4) {
+        const uint32_t r0 = rec[k], r1 = rec[k + 1], r2 = rec[k + 2], r3 = rec[k + 3];
+        a0 += recval[(int64_t)r0 * N1 + c];
+        a1 += recval[(int64_t)r1 * N1 + c];
+        a2 += recval[(int64_t)r2 * N1 + c];
+        a3 += recval[(int64_t)r3 * N1 + c];
+    }
+    if (k < hi) a0 += recval[(int64_t)rec[k] * N1 + c];
+    if (k + 1 < hi) a1 += recval[(int64_t)rec[k + 1] * N1 + c];
+    if (k + 2 < hi) a2 += recval[(int64_t)rec[k + 2] * N1 + c];
+    P[g] += (a0 + a1) + (a2 + a3);
 }
 
 __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx, int64_t n,

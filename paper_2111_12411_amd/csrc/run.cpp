@@ -236,8 +236,8 @@ void Run::alloc_particles(int64_t n)
     // spill pool
     pool_cap = std::max<int64_t>(cap + cap / 2, 1 << 16);
     alloc_pool(pool_cap);
-    d_pcount.alloc(cap * 4);
-    d_ppos.alloc(cap * 4);
+    d_rcount.alloc(cap * 4);
+    d_rpos.alloc(cap * 4);
     d_cq.alloc((size_t)cap * sizeof(ContRec));
     d_qflag.alloc(cap * 4);
     d_qpos.alloc(cap * 4);
@@ -279,7 +279,7 @@ SpillPool Run::pool() const
     sp.tet = (int32_t *)d_pool_tet.p;
     sp.tag = (int64_t *)d_pool_tag.p;
     sp.count = (int32_t *)d_small.p;
-    sp.pcount = (int32_t *)d_pcount.p;
+    sp.rcount = (int32_t *)d_rcount.p;
     sp.cap = pool_cap;
     return sp;
 }
@@ -480,16 +480,18 @@ void Run::particle_phase()
         if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
         if (errs & ERR_NAN) throw Error(FEMPIC_EDEVICE, "non-finite particle position");
         nslot_last = nslots;
+        nq_last = sm[6];
         nrec_last = last_spill;
         done = true;
     }
     if (!done) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
     // deterministic reduction of the spill pool
     const int64_t nrec = nrec_last;
-    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_pcount.p, (uint32_t *)d_ppos.p, np, psort.scan_tmp,
+    // canonical order of the spill records: queued record, then segment
+    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_last, psort.scan_tmp,
                                 (uint32_t *)d_small.p + 2, stream));
     if (nrec > 0) {
-        HIPCHECK(launch_spill_compact(pool(), nslot_last, np, (const uint32_t *)d_ppos.p, ssort.key[0], ssort.val[0],
+        HIPCHECK(launch_spill_compact(pool(), nslot_last, np, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
                                       stream));
         int res = 0;
         HIPCHECK(radix_sort(ssort, nrec, key_bits(), false, &res, stream));

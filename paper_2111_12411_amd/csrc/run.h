@@ -95,12 +95,12 @@ class Run {
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_cntb, d_small, d_args;
-    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pcount, d_ppos, d_cq, d_qflag, d_qpos, d_qidx;
+    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_rcount, d_rpos, d_cq, d_qflag, d_qpos, d_qidx;
     std::vector<DevBuf> hp_sort, hp_ssort;
     PBufs pb[2];
     int cur = 0;
     SortBuffers psort{}, ssort{};
-    int64_t pool_cap = 0, nrec_last = 0, nslot_last = 0;
+    int64_t pool_cap = 0, nrec_last = 0, nslot_last = 0, nq_last = 0;
     double q = 0, mass = 1, w = 0;
     bool loaded = false;
     int32_t sticky = 0;
