@@ -12,7 +12,7 @@ struct GLRule {
 struct DevMesh {
     int32_t nt;
     const double *geo;   // [nt][16] (a_m, grad_m) m = 0..3
-    const int32_t *nbr;  // [nt][4]
+    const int32_t *nbr;  // [nt][4] 4 nb + (face of nb shared with t) across the face opposite vertex m; -1 wall
     const int32_t *map1; // [nt][n1l] internal W1 ids (wall DoFs >= N1_int hold zero)
     const int32_t *map2; // [nt][n2l]
     const int32_t *map0; // [nt][n0l]
@@ -98,7 +98,9 @@ struct SortBuffers {
 };
 int64_t sort_hist_entries(int64_t n);
 int64_t scan_tmp_entries(int64_t n);
-hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s);
+// key_in (optional): keys of the first pass, read in place of sb.key[0]
+hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s,
+                      const uint32_t *key_in = nullptr);
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s);
 // out[i] = in[perm[i]] for every particle array
 hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
@@ -129,8 +131,9 @@ struct ParticleArgs {
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
 hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s);
 // blocks of the continuation kernel (one counter slot each in cntb)
-constexpr int CONT_BLOCKS = 4096;
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t np, unsigned long long *cntb,
+constexpr int CONT_BLOCKS = 65536;
+// nq_hint: expected queue length (sizes the grid; any length is processed)
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t nq_hint, unsigned long long *cntb,
                            unsigned long long *cnt, hipStream_t s);
 hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
                                 uint32_t *val, hipStream_t s);

@@ -610,14 +610,10 @@ template <typename R, typename GPtr>
 __device__ inline void cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&cp)[5][3],
                                   const GParticles<R> &out, int64_t i, unsigned long long &nrf)
 {
-    const int nb = m.nbr[(int64_t)t * 4 + f];
-    if (nb >= 0) {
-        int en = -1;
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (m.nbr[(int64_t)nb * 4 + q] == t) en = q;
-        entry = en;
-        t = nb;
+    const int nx = m.nbr[(int64_t)t * 4 + f];
+    if (nx >= 0) {
+        entry = nx & 3;
+        t = nx >> 2;
         return;
     }
     const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
@@ -1618,7 +1614,8 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
     return hipGetLastError();
 }
 
-hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s)
+hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s,
+                      const uint32_t *key_in)
 {
     int cur = 0;
     if (n == 0) {
@@ -1629,10 +1626,11 @@ hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, 
     int passes = std::max(1, (bits + 7) / 8);
     for (int pass = 0; pass < passes; pass++) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(BLK), 0, s, sb.key[cur], n, shift, sb.hist, ntiles);
+        const uint32_t *kin = (pass == 0 && key_in) ? key_in : sb.key[cur];
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(BLK), 0, s, kin, n, shift, sb.hist, ntiles);
         hipError_t err = exclusive_scan_u32(sb.hist, sb.hist, 256 * ntiles, sb.scan_tmp, nullptr, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(BLK), 0, s, sb.key[cur], sb.val[cur],
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(BLK), 0, s, kin, sb.val[cur],
                            sb.key[1 - cur], sb.val[1 - cur], n, shift, sb.hist, ntiles,
                            (pass == 0 && vals_are_iota) ? 1 : 0);
         cur = 1 - cur;
@@ -1690,10 +1688,12 @@ hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t np, unsigned long long *cntb,
+hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t nq_hint, unsigned long long *cntb,
                            unsigned long long *cnt, hipStream_t s)
 {
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(CONT_BLOCKS, (np + BLK - 1) / BLK));
+    // about one queued path per thread (a grid-stride loop covers a longer queue)
+    const int64_t want = (nq_hint + nq_hint / 8 + BLK - 1) / BLK + 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(CONT_BLOCKS, want));
     if (order == 1) {
         if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, A);
         else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, A);

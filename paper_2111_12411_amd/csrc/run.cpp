@@ -110,7 +110,22 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     }
     // mesh tables
     upload(d_geo, m.geo, stream);
-    upload(d_nbr, m.nbr, stream);
+    {
+        // device neighbour table: 4 nb + (face of nb shared with t), -1 at a wall
+        std::vector<int32_t> nbx(m.nbr.size(), -1);
+        for (int64_t t = 0; t < m.nt; t++)
+            for (int f = 0; f < 4; f++) {
+                const int32_t nb = m.nbr[4 * t + f];
+                if (nb < 0) continue;
+                int en = -1;
+                for (int q = 0; q < 4; q++)
+                    if (m.nbr[4 * (int64_t)nb + q] == (int32_t)t) en = q;
+                if (en < 0) throw Error(FEMPIC_EMESH, "inconsistent neighbour table");
+                nbx[4 * t + f] = 4 * nb + en;
+            }
+        upload(d_nbr, nbx, stream);
+        HIPCHECK(hipStreamSynchronize(stream));  // nbx is freed at the end of this block
+    }
     upload(d_map1, m.map1, stream);
     upload(d_map2, m.map2, stream);
     upload(d_map0, m.map0, stream);
@@ -294,9 +309,8 @@ int Run::key_bits() const
 // sort the current particles by tet: returns perm (sorted -> slot) and fills d_off
 const uint32_t *Run::sort_current()
 {
-    HIPCHECK(launch_copy_keys(pb[cur].d.tet, psort.key[0], np, stream));
     int res = 0;
-    HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream));
+    HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream, (const uint32_t *)pb[cur].d.tet));
     HIPCHECK(launch_offsets(psort.key[res], np, (int32_t)m.nt, (int32_t *)d_off.p, stream));
     return psort.val[res];
 }
@@ -458,7 +472,8 @@ void Run::particle_phase()
         HIPCHECK(exclusive_scan_u32((const uint32_t *)d_qflag.p, (uint32_t *)d_qpos.p, np, psort.scan_tmp,
                                     (uint32_t *)d_small.p + 6, stream));
         HIPCHECK(launch_queue_index(ha->cq, np, stream));
-        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, np, (unsigned long long *)d_cntb.p,
+        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, nq_last > 0 ? nq_last : np / 8,
+                                 (unsigned long long *)d_cntb.p,
                                  (unsigned long long *)d_cnt.p, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));

@@ -1,0 +1,76 @@
+"""GPU: the submit/poll server runs independent jobs concurrently, and each
+job's result is bitwise the result of the same job run alone (the step is
+deterministic and jobs share no state)."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2111_12411_amd as F
+from paper_2111_12411_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = -W.Q_E, W.M_E
+
+
+def _jobs():
+    """(N, order, kind, n, seed, steps, precision): small mixed set of shapes."""
+    return [
+        (4, 1, "thermal", 800, 11, 12, F.FP64),
+        (6, 2, "beam", 3000, 12, 8, F.FP64),
+        (5, 2, "thermal", 2000, 13, 10, F.MIXED),
+        (4, 2, "beam", 1500, 14, 6, F.MIXED),
+    ]
+
+
+def _alone(N, order, pos, vel, w, dt, steps, precision):
+    run = F.Run(F.Mesh.cube(N, order), dt, precision, pcg_rtol=1e-13)
+    run.load(pos, vel, QE, ME, w)
+    run.step(steps)
+    e, b = run.fields()
+    p, v, _ = run.particles()
+    rg = run.gauss()
+    run.close()
+    return e, b, p, v, rg
+
+
+def test_server_matches_standalone_runs():
+    specs = []
+    for N, order, kind, n, seed, steps, prec in _jobs():
+        dt = 5.0 * F.Mesh.cube(N, order).info()["dt_cfl"]
+        pos, vel = W.particles(kind, n, seed, vth=0.01, drift=0.1)
+        w = W.plasma_weight(n, dt)
+        specs.append((N, order, pos, vel, w, dt, steps, prec))
+    srv = F.Server(hbm_budget=8 << 30, max_slots=2)
+    tickets = [srv.submit(N, order, pos, vel, QE, ME, w, steps, dt, precision=prec)
+               for (N, order, pos, vel, w, dt, steps, prec) in specs]
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets):
+        assert time.time() - t0 < 120, "server did not finish the jobs"
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.01)
+    srv.close()
+    for t, (N, order, pos, vel, w, dt, steps, prec) in zip(tickets, specs):
+        r = results[t]
+        assert r["status"] == 0
+        e, b, p, v, rg = _alone(N, order, pos, vel, w, dt, steps, prec)
+        assert np.array_equal(r["e"], e) and np.array_equal(r["b"], b)
+        assert np.array_equal(r["pos"], p) and np.array_equal(r["vel"], v)
+        assert len(r["step_done_ms"]) == steps and np.all(np.diff(r["step_done_ms"]) >= 0)
+        if prec == F.FP64:
+            assert r["gauss"][0] < 1e-12
+
+
+def test_server_rejects_job_beyond_budget():
+    srv = F.Server(hbm_budget=1 << 20, max_slots=1)  # 1 MiB: no run fits
+    pos, vel = W.particles("thermal", 1000, 3)
+    with pytest.raises(F.FempicError) as ex:
+        srv.submit(8, 2, pos, vel, QE, ME, 1.0, 2, 1e-12)
+    assert "ENOMEM" in str(ex.value)
+    srv.close()
