@@ -81,7 +81,13 @@ def run_workload(cfg_id, precision, steps, warmup, n=None):
     wall = time.perf_counter() - t0
     st = run.stats()
     rg = run.gauss()
-    return dict(run=run, info=info, dt=dt, n=npart, wall=wall, stats=st, gauss=rg, setup_s=t_setup)
+    e, b = run.fields()
+    return dict(run=run, info=info, dt=dt, n=npart, wall=wall, stats=st, gauss=rg, setup_s=t_setup, e=e, b=b)
+
+
+def rel(a, b):
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
 
 
 def cpu_baseline(cfg, n_sample, steps):
@@ -169,9 +175,12 @@ def main():
     }
     mix["run"].close()
     if not args.no_fp64:
-        f64 = run_workload(3, F.FP64, max(K // 2, 1), 2, n=args.particles)
+        # the plain FP64 path on the same inputs and the same number of steps
+        f64 = run_workload(3, F.FP64, K, args.warmup, n=args.particles)
         s2 = f64["stats"]
-        k2 = max(K // 2, 1)
+        k2 = K
+        out["mixed_vs_fp64"] = {"steps": K + args.warmup, "e_rel": rel(mix["e"], f64["e"]),
+                                "b_rel": rel(mix["b"], f64["b"])}
         alg2, _, _ = algorithmic_bytes(cfg["order"], F.FP64, f64["n"], f64["info"]["n_tet"])
         out["fp64"] = {"value": f64["n"] * k2 / (s2["particle_ms"] / 1e3), "unit": "particle-steps/s",
                        "particle_ms_per_step": s2["particle_ms"] / k2, "ms_per_step": f64["wall"] * 1e3 / k2,

@@ -428,7 +428,7 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
     if (!(H > 0.0)) return -1;
     const double H2 = H * H;
     int best = -1;
-    double est = 0.0;
+    double bnum = 0.0, bden = 1.0;  // regula-falsi estimate of the best face: H bnum / bden
     bool hard = false;
     unsigned cand = 0;
 #pragma unroll
@@ -447,11 +447,12 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
             const int ch = ((b1 < 0.0) != (b0 < 0.0)) + ((b2 < 0.0) != (b1 < 0.0)) + ((b3 < 0.0) != (b2 < 0.0)) +
                            ((b4 < 0.0) != (b3 < 0.0));
             if (b0 > 0.0 && b4 < 0.0 && ch == 1) {
-                const double u0 = H * (b0 / (b0 - b4));
+                // estimates compared without dividing: b0/(b0-b4) < bnum/bden
                 cand |= 1u << f;
-                if (best < 0 || u0 < est) {
+                if (best < 0 || b0 * bden < bnum * (b0 - b4)) {
                     best = f;
-                    est = u0;
+                    bnum = b0;
+                    bden = b0 - b4;
                 }
             } else {
                 hard = true;
@@ -462,12 +463,13 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
     if (best < 0) return -1;
     double q[5];
     face_poly<FROM_ZERO>(G, best, cp, s_lo, q);
-    double a = 0.0, b = H, x = est;
+    double a = 0.0, b = H, x = H * (bnum / bden);
     if (!(x > a && x < b)) x = 0.5 * H;
     const double tol = 4e-16 * H;
     bool conv = false;
 #pragma unroll
     for (int it = 0; it < 6; it++) {
+        if (__all(conv)) break;
         const double fx = horner4(q, x);
         const double dx = fx / dhorner4(q, x);
         if (!conv) {
