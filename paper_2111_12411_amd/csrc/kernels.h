@@ -152,6 +152,13 @@ struct DevCSR {
     const double *val;
     const float *val32;  // optional FP32 copy
     int lanes;           // lanes per row in the SpMV
+    // optional 2x2 block copy (rows 2R, 2R+1 x columns 2C, 2C+1), used by the
+    // SpMV when present: bval[4k..4k+3] = block k row-major
+    int64_t brows;
+    const int64_t *bptr;
+    const int32_t *bidx;
+    const double *bval;
+    const float *bval32;
 };
 hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, double beta, const double *z,
                 hipStream_t s);  // y = alpha A x + beta z (z may alias y or be null when beta == 0)

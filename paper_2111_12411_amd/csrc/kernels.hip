@@ -1377,6 +1377,58 @@ __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__res
     }
 }
 
+// y = alpha A x + beta z with A in 2x2 blocks: LANES lanes per block row, a
+// block's four values and the two x entries it needs are loaded as vectors;
+// optional fused partial dot(dotv, y) per workgroup (fixed order)
+template <int LANES, typename T>
+__global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__restrict__ bptr,
+                                               const int32_t *__restrict__ bidx, const T *__restrict__ bval,
+                                               const T *__restrict__ x, T *__restrict__ y, double alpha, double beta,
+                                               const T *__restrict__ z, const T *__restrict__ dotv,
+                                               double *__restrict__ partial)
+{
+    __shared__ double s_red[BLK / LANES];
+    constexpr int RPB = BLK / LANES;
+    const int tid = threadIdx.x;
+    const int lane = tid % LANES;
+    double d = 0.0;
+    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < brows; row0 += (int64_t)gridDim.x * RPB) {
+        const int64_t br = row0 + tid / LANES;
+        double s0 = 0.0, s1 = 0.0;
+        if (br < brows) {
+            const int64_t e = bptr[br + 1];
+            for (int64_t k = bptr[br] + lane; k < e; k += LANES) {
+                const int64_t c = 2 * (int64_t)bidx[k];
+                const T *v = bval + 4 * k;
+                const double x0 = (double)x[c], x1 = (double)x[c + 1];
+                s0 = fma((double)v[0], x0, fma((double)v[1], x1, s0));
+                s1 = fma((double)v[2], x0, fma((double)v[3], x1, s1));
+            }
+        }
+#pragma unroll
+        for (int o = LANES / 2; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, LANES);
+            s1 += __shfl_xor(s1, o, LANES);
+        }
+        if (br < brows && lane == 0) {
+            const double y0 = alpha * s0 + (beta != 0.0 ? beta * (double)z[2 * br] : 0.0);
+            const double y1 = alpha * s1 + (beta != 0.0 ? beta * (double)z[2 * br + 1] : 0.0);
+            y[2 * br] = (T)y0;
+            y[2 * br + 1] = (T)y1;
+            if (dotv) d += (double)dotv[2 * br] * (double)(T)y0 + (double)dotv[2 * br + 1] * (double)(T)y1;
+        }
+    }
+    if (partial) {
+        if (lane == 0) s_red[tid / LANES] = d;
+        __syncthreads();
+        for (int o = RPB / 2; o > 0; o >>= 1) {
+            if (tid < o) s_red[tid] += s_red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) partial[blockIdx.x] = s_red[0];
+    }
+}
+
 // fixed-order sum of n partials (one block of 1024 threads), k values interleaved
 __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ partial, int64_t n, int k,
                                                  double *__restrict__ out)
@@ -1752,6 +1804,16 @@ template <typename T>
 hipError_t spmv_t(const DevCSR &A, const T *val, const T *x, T *y, double alpha, double beta, const T *z,
                   const T *dotv, double *partial, unsigned &grid, hipStream_t s)
 {
+    const T *bv = nullptr;
+    if constexpr (sizeof(T) == 8) bv = (const T *)A.bval;
+    else bv = (const T *)A.bval32;
+    if (A.bptr && bv) {
+        constexpr int BL = 8;
+        grid = red_grid(A.brows, BLK / BL);
+        hipLaunchKernelGGL((k_bspmv<BL, T>), dim3(grid), dim3(BLK), 0, s, A.brows, A.bptr, A.bidx, bv, x, y, alpha,
+                           beta, z, dotv, partial);
+        return hipGetLastError();
+    }
     grid = red_grid(A.rows, BLK / A.lanes);
     if (A.rows == 0) return hipSuccess;
     switch (A.lanes) {

@@ -29,7 +29,7 @@ struct DevBuf {
 };
 
 struct DevCSRBuf {
-    DevBuf ptr, idx, val, val32;
+    DevBuf ptr, idx, val, val32, bptr, bidx, bval, bval32;
     DevCSR desc{};
 };
 
