@@ -69,7 +69,7 @@ def run_workload(cfg_id, precision, steps, warmup, n=None):
     npart = len(pos)
     w = W.plasma_weight(npart, dt)
     t0 = time.perf_counter()
-    run = F.Run(mesh, dt, precision, pcg_rtol=1e-13)
+    run = F.Run(mesh, dt, precision, pcg_rtol=1e-14)
     run.load(pos, vel, -W.Q_E, W.M_E, w)
     t_setup = time.perf_counter() - t0
     del pos, vel
@@ -110,6 +110,59 @@ def cpu_baseline(cfg, n_sample, steps):
                        "single-threaded plain C, %.1f s" % (n_sample, steps, dtm))
 
 
+def serving(n_jobs=24, slots=2, mean_gap_ms=15.0, seed=4007):
+    """Continuous batching: n_jobs independent mixed-precision runs with Poisson
+    arrivals go through fempic_submit / fempic_poll; each run's mesh, order,
+    particle count and kind are drawn at random (a smaller instance of the
+    serving workload). Reports per-step latency (intervals between consecutive
+    step completions of a run, over all runs), queue delay and aggregate
+    particle-steps/s = sum n steps / makespan."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dt8 = {k: F.Mesh.cube(8, k).info()["dt_cfl"] for k in (1, 2)}  # Kuhn cubes: dt_cfl ~ 1/N
+    jobs = []
+    for j in range(n_jobs):
+        N = int(rng.integers(8, 21))
+        k = int(rng.integers(1, 3))
+        n = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+        kind = "beam" if rng.random() < 0.5 else "thermal"
+        steps = int(rng.integers(20, 61))
+        dt = 10.0 * dt8[k] * 8.0 / N
+        pos, vel = W.particles(kind, n, seed + j, vth=0.01, drift=0.1)
+        jobs.append((N, k, pos, vel, W.plasma_weight(n, dt), steps, dt, n))
+    gaps = rng.exponential(mean_gap_ms / 1e3, n_jobs)
+    srv = F.Server(hbm_budget=64 << 30, max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for j, (N, k, pos, vel, w, steps, dt, n) in enumerate(jobs):
+        time.sleep(gaps[j])
+        tickets.append(srv.submit(N, k, pos, vel, -W.Q_E, W.M_E, w, steps, dt, precision=F.MIXED))
+    res = {}
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                r = srv.poll(t)
+                if r is not None:
+                    res[t] = r
+        time.sleep(0.002)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat, queue = [], []
+    for t in tickets:
+        r = res[t]
+        assert r["status"] == 0
+        lat.extend(np.diff(r["step_done_ms"]).tolist())
+        queue.append(r["queue_ms"])
+    work = sum(n * steps for (_, _, _, _, _, steps, _, n) in jobs)
+    return {"metric": "serving: per-step latency p50/p99 and aggregate particle-steps/s", "value": work / makespan,
+            "unit": "particle-steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+            "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
+            "queue_p50_ms": float(np.percentile(queue, 50)), "queue_max_ms": float(np.max(queue)),
+            "makespan_s": makespan,
+            "config": {"workload": "%d runs, Poisson arrivals (mean gap %.0f ms), %d slots; N in [8,20], order 1|2, "
+                                   "1e4-1e6 particles (log-uniform), beam|thermal, 20-60 steps, dt = 10 x explicit "
+                                   "bound, mixed precision" % (n_jobs, mean_gap_ms, slots)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,11 +174,16 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration for profiles)")
+    ap.add_argument("--serving", action="store_true",
+                    help="measure the submit/poll server on a stream of independent runs instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method is built and measured on a single MI355X "
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        print(json.dumps(serving()))
+        return
     cfg = W.CONFIGS[3]
     if args.calib_copy:
         import torch

@@ -165,16 +165,19 @@ hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, doubl
 hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s);
 hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y, double *out, hipStream_t s);
 
-// Jacobi-PCG pieces; scalars is a device double[16] block
+// PCG pieces; scalars is a device double[16] block
 // SC_RZ and SC_RZ + 10 hold r.z for even / odd iterations (parity argument `par`)
+// The preconditioner is Jacobi (dinv[i] = 1/A_ii) or, when A carries its 2x2
+// block copy, 2x2 block Jacobi (dinv[4j..4j+3]: inverse diagonal block of rows
+// 2j, 2j+1); `block` of the init call must say which (A.bptr != nullptr).
 enum { SC_RZ = 0, SC_PQ = 1, SC_RR = 4, SC_BB = 5 };
 hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
-                    double *partial, double *scalars, hipStream_t s);
+                    double *partial, double *scalars, bool block, hipStream_t s);
 hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
                     const double *dinv, double *partial, double *scalars, int par, hipStream_t s);
 // FP32 inner PCG (mixed mode); vectors float, scalars double
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
-                      double *partial, double *scalars, hipStream_t s);
+                      double *partial, double *scalars, bool block, hipStream_t s);
 hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
                       double *partial, double *scalars, int par, hipStream_t s);
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s);

@@ -1452,7 +1452,10 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
 // PCG scalars (device double block): RZ[2] ping-pong by iteration parity,
 // PQ, and after k_finish: sc[8] = r.z (new), sc[9] = r.r
 // x += a p ; r -= a q ; z = dinv r ; partial (r.z, r.r), with a = rz / pq
-template <typename T>
+// the preconditioner: Jacobi (dinv[i] = 1 / A_ii), or with BLOCK 2x2 block
+// Jacobi (dinv[4j..4j+3] = inverse of the diagonal block of rows 2j, 2j+1,
+// row-major); with BLOCK a thread handles one pair of rows
+template <typename T, bool BLOCK>
 __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
                                                    const T *__restrict__ p, const T *__restrict__ q,
                                                    const T *__restrict__ dinv, const double *__restrict__ sc, int par,
@@ -1463,14 +1466,32 @@ __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x,
     const double pq = sc[SC_PQ];
     const double a = pq != 0.0 ? sc[SC_RZ + 10 * par] / pq : 0.0;
     double rz = 0, rr = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
-        x[i] = (T)((double)x[i] + a * (double)p[i]);
-        T ri = (T)((double)r[i] - a * (double)q[i]);
-        r[i] = ri;
-        T zi = dinv[i] * ri;
-        z[i] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
+    if constexpr (BLOCK) {
+        for (int64_t j = (int64_t)blockIdx.x * BLK + tid; 2 * j < n; j += (int64_t)gridDim.x * BLK) {
+            const int64_t i = 2 * j;
+            x[i] = (T)((double)x[i] + a * (double)p[i]);
+            x[i + 1] = (T)((double)x[i + 1] + a * (double)p[i + 1]);
+            const T r0 = (T)((double)r[i] - a * (double)q[i]);
+            const T r1 = (T)((double)r[i + 1] - a * (double)q[i + 1]);
+            r[i] = r0;
+            r[i + 1] = r1;
+            const T z0 = dinv[4 * j] * r0 + dinv[4 * j + 1] * r1;
+            const T z1 = dinv[4 * j + 2] * r0 + dinv[4 * j + 3] * r1;
+            z[i] = z0;
+            z[i + 1] = z1;
+            rz += (double)r0 * (double)z0 + (double)r1 * (double)z1;
+            rr += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
+            x[i] = (T)((double)x[i] + a * (double)p[i]);
+            T ri = (T)((double)r[i] - a * (double)q[i]);
+            r[i] = ri;
+            T zi = dinv[i] * ri;
+            z[i] = zi;
+            rz += (double)ri * (double)zi;
+            rr += (double)ri * (double)ri;
+        }
     }
     s0[tid] = rz;
     s1[tid] = rr;
@@ -1504,7 +1525,7 @@ __global__ void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z
 }
 
 // r = b, x = 0, z = dinv r, p = z ; partial (r.z, r.r)
-template <typename T>
+template <typename T, bool BLOCK>
 __global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const T *__restrict__ b, T *__restrict__ x,
                                                   T *__restrict__ r, T *__restrict__ z, T *__restrict__ p,
                                                   const T *__restrict__ dinv, double *__restrict__ partial)
@@ -1512,15 +1533,34 @@ __global__ __launch_bounds__(BLK) void k_pcg_init(int64_t n, const T *__restrict
     __shared__ double s0[BLK], s1[BLK];
     const int tid = threadIdx.x;
     double rz = 0, rr = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
-        T ri = b[i];
-        x[i] = T(0);
-        r[i] = ri;
-        T zi = dinv[i] * ri;
-        z[i] = zi;
-        p[i] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
+    if constexpr (BLOCK) {
+        for (int64_t j = (int64_t)blockIdx.x * BLK + tid; 2 * j < n; j += (int64_t)gridDim.x * BLK) {
+            const int64_t i = 2 * j;
+            const T r0 = b[i], r1 = b[i + 1];
+            x[i] = T(0);
+            x[i + 1] = T(0);
+            r[i] = r0;
+            r[i + 1] = r1;
+            const T z0 = dinv[4 * j] * r0 + dinv[4 * j + 1] * r1;
+            const T z1 = dinv[4 * j + 2] * r0 + dinv[4 * j + 3] * r1;
+            z[i] = z0;
+            z[i + 1] = z1;
+            p[i] = z0;
+            p[i + 1] = z1;
+            rz += (double)r0 * (double)z0 + (double)r1 * (double)z1;
+            rr += (double)r0 * (double)r0 + (double)r1 * (double)r1;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
+            T ri = b[i];
+            x[i] = T(0);
+            r[i] = ri;
+            T zi = dinv[i] * ri;
+            z[i] = zi;
+            p[i] = zi;
+            rz += (double)ri * (double)zi;
+            rr += (double)ri * (double)ri;
+        }
     }
     s0[tid] = rz;
     s1[tid] = rr;
@@ -1860,10 +1900,11 @@ hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y
 namespace {
 template <typename T>
 hipError_t pcg_init_t(int64_t n, const T *b, T *x, T *r, T *z, T *p, const T *dinv, double *partial, double *sc,
-                      hipStream_t s)
+                      bool block, hipStream_t s)
 {
-    const unsigned g = red_grid(n, BLK);
-    hipLaunchKernelGGL(k_pcg_init<T>, dim3(g), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
+    const unsigned g = red_grid(block ? (n + 1) / 2 : n, BLK);
+    if (block) hipLaunchKernelGGL((k_pcg_init<T, true>), dim3(g), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
+    else hipLaunchKernelGGL((k_pcg_init<T, false>), dim3(g), dim3(BLK), 0, s, n, b, x, r, z, p, dinv, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g, 2, sc + 8);
     hipLaunchKernelGGL(k_init_sc, dim3(1), dim3(1), 0, s, sc);
     return hipGetLastError();
@@ -1877,8 +1918,12 @@ hipError_t pcg_iter_t(const DevCSR &A, const T *val, int64_t n, T *x, T *r, T *z
     hipError_t err = spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, g1, s);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g1, 1, sc + SC_PQ);
-    const unsigned g2 = red_grid(n, BLK);
-    hipLaunchKernelGGL(k_update_xr<T>, dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
+    const bool block = A.bptr != nullptr;
+    const unsigned g2 = red_grid(block ? (n + 1) / 2 : n, BLK);
+    if (block)
+        hipLaunchKernelGGL((k_update_xr<T, true>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
+    else
+        hipLaunchKernelGGL((k_update_xr<T, false>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g2, 2, sc + 8);
     hipLaunchKernelGGL(k_update_p<T>, dim3(g2), dim3(BLK), 0, s, n, p, z, sc, par);
     return hipGetLastError();
@@ -1886,9 +1931,9 @@ hipError_t pcg_iter_t(const DevCSR &A, const T *val, int64_t n, T *x, T *r, T *z
 }  // namespace
 
 hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
-                    double *partial, double *sc, hipStream_t s)
+                    double *partial, double *sc, bool block, hipStream_t s)
 {
-    return pcg_init_t<double>(n, b, x, r, z, p, dinv, partial, sc, s);
+    return pcg_init_t<double>(n, b, x, r, z, p, dinv, partial, sc, block, s);
 }
 
 hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
@@ -1898,9 +1943,9 @@ hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z,
 }
 
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
-                      double *partial, double *sc, hipStream_t s)
+                      double *partial, double *sc, bool block, hipStream_t s)
 {
-    return pcg_init_t<float>(n, b, x, r, z, p, dinv, partial, sc, s);
+    return pcg_init_t<float>(n, b, x, r, z, p, dinv, partial, sc, block, s);
 }
 
 hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,

@@ -192,10 +192,29 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     upload_csr(Ct, ops.Ct, false);
     upload_csr(K, ops.K, false);
     upload_csr(Gt, ops.Gt, false);
-    upload(d_dinv, ops.Adiag_inv, stream);
-    if (mixed) {
-        std::vector<float> d32(ops.Adiag_inv.begin(), ops.Adiag_inv.end());
-        upload(d_dinv32, d32, stream);
+    {
+        // preconditioner: inverse 2x2 diagonal blocks when A is 2x2-blocked, else 1/A_ii
+        std::vector<double> dinv = ops.Adiag_inv;
+        if (A.desc.bptr) {
+            const CSR &Ah = ops.A;
+            dinv.assign(2 * (size_t)Ah.rows, 0.0);
+            for (int64_t j = 0; 2 * j < Ah.rows; j++) {
+                double blk[2][2] = {{0, 0}, {0, 0}};
+                for (int h = 0; h < 2; h++)
+                    for (int64_t k = Ah.ptr[2 * j + h]; k < Ah.ptr[2 * j + h + 1]; k++)
+                        if (Ah.idx[k] == 2 * j || Ah.idx[k] == 2 * j + 1) blk[h][Ah.idx[k] - 2 * j] = Ah.val[k];
+                const double det = blk[0][0] * blk[1][1] - blk[0][1] * blk[1][0];
+                if (!(det > 0.0)) throw Error(FEMPIC_EMESH, "system matrix has a singular diagonal block");
+                dinv[4 * j] = blk[1][1] / det;
+                dinv[4 * j + 1] = -blk[0][1] / det;
+                dinv[4 * j + 2] = -blk[1][0] / det;
+                dinv[4 * j + 3] = blk[0][0] / det;
+            }
+        }
+        upload(d_dinv, dinv, stream);
+        std::vector<float> d32(dinv.begin(), dinv.end());
+        if (mixed) upload(d_dinv32, d32, stream);
+        HIPCHECK(hipStreamSynchronize(stream));  // dinv and d32 are freed at the end of this block
     }
     upload(d_inc_ptr, ops.inc_ptr, stream);
     upload(d_inc_idx, ops.inc_idx, stream);
@@ -604,7 +623,7 @@ void Run::solve_fp64()
     const int64_t n = m.N1_int;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     HIPCHECK(pcg_init(n, (const double *)v_rhs.p, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
-                      (const double *)d_dinv.p, part, sc, stream));
+                      (const double *)d_dinv.p, part, sc, A.desc.bptr != nullptr, stream));
     const double bb = read_sc(SC_BB);
     last_iters = 0;
     last_relres = 0;
@@ -641,12 +660,12 @@ void Run::solve_mixed()
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     double *x = (double *)v_x.p, *r = (double *)v_r.p;
     const double *rhs = (const double *)v_rhs.p;
-    HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, x, stream));
-    HIPCHECK(axpby(n, 1.0, rhs, 0.0, rhs, r, stream));
     HIPCHECK(dot_det(n, rhs, rhs, part, sc + 12, stream));
     const double bb = read_sc(12);
     last_iters = 0;
     last_relres = 0;
+    HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, x, stream));
+    HIPCHECK(axpby(n, 1.0, rhs, 0.0, rhs, r, stream));
     if (bb == 0.0) return;
     double rr = bb;
     for (int outer = 0; outer < 12; outer++) {
@@ -654,7 +673,7 @@ void Run::solve_mixed()
         const double scale = std::sqrt(rr);
         HIPCHECK(cast_d2f(n, r, (float *)f_q.p, 1.0 / scale, stream));
         HIPCHECK(pcg32_init(n, (const float *)f_q.p, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
-                            (const float *)d_dinv32.p, part, sc, stream));
+                            (const float *)d_dinv32.p, part, sc, A.desc.bptr != nullptr, stream));
         const double bb32 = read_sc(SC_BB);
         // the inner solve reduces its residual by 1e-5 (about what FP32 holds),
         // or by less on the last cycle: just what the target still needs, with
