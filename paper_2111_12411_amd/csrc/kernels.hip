@@ -597,12 +597,12 @@ struct GPool {
     gptr<double> val;
     gptr<int32_t> tet;
     gptr<int64_t> tag;
-    gptr<int32_t> count, rcount;
+    gptr<int32_t> pid, count, rcount;
     int64_t cap;
 };
 __device__ inline GPool gview(const SpillPool &p)
 {
-    return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.count), glb(p.rcount), p.cap};
+    return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.pid), glb(p.count), glb(p.rcount), p.cap};
 }
 
 // leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
@@ -662,14 +662,17 @@ __device__ inline int64_t append_slot(gptr<int32_t> count)
 }
 
 // claims the spill record for segment nsp_i of queued record r (tet t): segments 0 and 1 take the fixed slots 2r and 2r+1, later ones are
-// appended after the fixed region of 2 nq slots.  Returns the slot, or -1 (and
-// flags ERR_POOL) when the pool is full.
-__device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, int t, int &nsp_i, int &errs)
+// appended after the fixed region of 2 nq slots.  The record of the path's
+// last segment (last) also carries the particle's sorted index i.  Returns the
+// slot, or -1 (and flags ERR_POOL) when the pool is full.
+__device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, int t, bool last, int64_t i,
+                                     int &nsp_i, int &errs)
 {
     int64_t slot = nsp_i < 2 ? 2 * r + nsp_i : 2 * nq + append_slot(pool.count);
     if (slot < pool.cap && nsp_i < 64) {
         pool.tet[slot] = t;
-        pool.tag[slot] = (r << 6) | nsp_i;
+        pool.tag[slot] = (r << 7) | ((int64_t)last << 6) | nsp_i;
+        if (last) pool.pid[slot] = (int32_t)i;
     } else {
         errs |= ERR_POOL;
         slot = -1;
@@ -724,6 +727,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     const gptr<double> P = glb(A->P);
     const gptr<ContRec> qrec = glb(A->cq.rec);
     const gptr<int32_t> qflag = glb(A->cq.flag);
+    const gptr<uint8_t> qmoved = glb(A->cq.moved);
     using O = Ord<K>;
     constexpr int N1 = O::N1, N2 = O::N2, TM = O::TPW_MAX;
     __shared__ double s_geo[TM][16];
@@ -738,6 +742,10 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     const int T0 = blockIdx.x * tpw;
     const int T1 = min(T0 + tpw, m.nt);
     const int ntl = T1 - T0;
+    // sort slot of this thread's particle in the block's first chunk, requested
+    // ahead of the staging below (each chunk requests the next chunk's slot)
+    const int pbeg = off[T0], pend = off[T1];
+    uint32_t nslot = pbeg + tid < pend ? perm[pbeg + tid] : 0u;
     for (int k = tid; k < ntl * 16; k += PBLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
     for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
     for (int k = tid; k < ntl * N1; k += PBLK) {
@@ -761,7 +769,6 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     }
     __syncthreads();
 
-    const int pbeg = s_off[0], pend = s_off[ntl];
     // (tet, component) pairs of the block's sums: pair tid + q PBLK for q < NP
     constexpr int NP = (TM * N1 + PBLK - 1) / PBLK;
     double acc[NP];
@@ -774,8 +781,9 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
 #pragma unroll
         for (int c = 0; c < N1; c++) s_hc[c][tid] = 0.0;
         const int i = base + tid;
+        const uint32_t slot = min(nslot, (uint32_t)(in.cap - 1));  // perm holds slots < cap
+        if (i + PBLK < pend) nslot = perm[i + PBLK];
         if (i < pend) {
-            const uint32_t slot = perm[i];
             const int th = in.tet[slot];
             const int lt = th - T0;
             const double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
@@ -849,6 +857,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
             const unsigned long long qmask = __ballot(f_exit != -1);
             const int lane = tid & 63;
             qflag[i] = lane < __popcll(qmask) ? 1 : 0;
+            qmoved[i] = f_exit != -1 ? 1 : 0;
             if (f_exit != -1) {
                 const int64_t qi = (int64_t)(i - lane) + __popcll(qmask & ((1ull << lane) - 1ull));
                 gptr<ContRec> rec = qrec + qi;
@@ -1000,11 +1009,13 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
                 out.tet[i] = t;
             }
             asm volatile("" ::: "memory");
-            if (s_hi > s_lo) {
-                const int64_t slot = spill_slot(pool, r, nq, t_seg, nsp_i, errs);
+            // every path's last segment has a record, also of zero length: it
+            // names the tet the particle ends in
+            if (s_hi > s_lo || !more) {
+                const int64_t slot = spill_slot(pool, r, nq, t_seg, !more, i, nsp_i, errs);
                 if (slot >= 0) {
                     double dep[N1];
-                    segment_moments<K>(lq, s_hi - s_lo, sp.qw, gl, dep);
+                    segment_moments<K>(lq, fmax(s_hi - s_lo, 0.0), sp.qw, gl, dep);
                     const gptr<double> dst = pool.val + slot * N1;
 #pragma unroll
                     for (int c = 0; c < N1; c++) dst[c] = dep[c];
@@ -1243,11 +1254,11 @@ __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t 
     if (r >= nrec) return;
     const int64_t tag = ptag[r];
     if (tag < 0) return;  // unused fixed slot
-    const int64_t q = tag >> 6;
+    const int64_t q = tag >> 7;
     const int j = (int)(tag & 63);
     const uint32_t dst = pos[q] + (uint32_t)j;
     key[dst] = (uint32_t)ptet[r];
-    val[dst] = (uint32_t)r;
+    val[dst] = (uint32_t)r | ((tag >> 6) & 1 ? SREC_LAST : 0u);
 }
 
 template <int N1>
@@ -1264,16 +1275,82 @@ __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, con
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int32_t k = lo;
     for (; k + 3 < hi; k += 4) {
-        const uint32_t r0 = rec[k], r1 = rec[k + 1], r2 = rec[k + 2], r3 = rec[k + 3];
+        const uint32_t r0 = rec[k] & ~SREC_LAST, r1 = rec[k + 1] & ~SREC_LAST, r2 = rec[k + 2] & ~SREC_LAST,
+                       r3 = rec[k + 3] & ~SREC_LAST;
         a0 += recval[(int64_t)r0 * N1 + c];
         a1 += recval[(int64_t)r1 * N1 + c];
         a2 += recval[(int64_t)r2 * N1 + c];
         a3 += recval[(int64_t)r3 * N1 + c];
     }
-    if (k < hi) a0 += recval[(int64_t)rec[k] * N1 + c];
-    if (k + 1 < hi) a1 += recval[(int64_t)rec[k + 1] * N1 + c];
-    if (k + 2 < hi) a2 += recval[(int64_t)rec[k + 2] * N1 + c];
+    if (k < hi) a0 += recval[(int64_t)(rec[k] & ~SREC_LAST) * N1 + c];
+    if (k + 1 < hi) a1 += recval[(int64_t)(rec[k + 1] & ~SREC_LAST) * N1 + c];
+    if (k + 2 < hi) a2 += recval[(int64_t)(rec[k + 2] & ~SREC_LAST) * N1 + c];
     P[g] += (a0 + a1) + (a2 + a3);
+}
+
+// Next step's particle order, one wave per tet (see launch_bucket_count).  The
+// stayers of old bucket [off[t], off[t+1]) are those with moved == 0; the
+// arrivals are the last-segment records among t's sorted spill records.
+__global__ __launch_bounds__(BLK) void k_bucket_count(int32_t nt, const int32_t *__restrict__ off,
+                                                      const uint8_t *__restrict__ moved,
+                                                      const int32_t *__restrict__ soff,
+                                                      const uint32_t *__restrict__ srec, int64_t nrec,
+                                                      uint32_t *__restrict__ cnt)
+{
+    const int64_t t = ((int64_t)blockIdx.x * BLK + threadIdx.x) / 64;  // the same for the whole wave
+    const int lane = threadIdx.x & 63;
+    if (t >= nt) return;
+    const int32_t a = off[t], b = off[t + 1];
+    int32_t n = 0;
+    for (int32_t base = a; base < b; base += 64) {
+        const int32_t j = base + lane;
+        n += __popcll(__ballot(j < b && moved[j] == 0));
+    }
+    if (nrec > 0) {
+        const int32_t lo = soff[t], hi = soff[t + 1];
+        for (int32_t base = lo; base < hi; base += 64) {
+            const int32_t k = base + lane;
+            n += __popcll(__ballot(k < hi && (srec[k] & SREC_LAST) != 0));
+        }
+    }
+    if (lane == 0) cnt[t] = (uint32_t)n;
+}
+
+__global__ __launch_bounds__(BLK) void k_place(int32_t nt, const int32_t *__restrict__ off,
+                                               const uint8_t *__restrict__ moved, const int32_t *__restrict__ soff,
+                                               const uint32_t *__restrict__ srec, int64_t nrec,
+                                               const int32_t *__restrict__ pid, const int32_t *__restrict__ noff,
+                                               int64_t np, uint32_t *__restrict__ perm,
+                                               unsigned long long *__restrict__ err)
+{
+    const int64_t t = ((int64_t)blockIdx.x * BLK + threadIdx.x) / 64;
+    const int lane = threadIdx.x & 63;
+    if (t >= nt) return;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int32_t a = off[t], b = off[t + 1], end = noff[t + 1];
+    const int32_t lim = (int32_t)min((int64_t)end, np);  // writes stay inside perm in any case
+    int32_t p = noff[t];
+    for (int32_t base = a; base < b; base += 64) {
+        const int32_t j = base + lane;
+        const bool st = j < b && moved[j] == 0;
+        const unsigned long long mk = __ballot(st);
+        const int32_t dst = p + __popcll(mk & below);
+        if (st && dst < lim) perm[dst] = (uint32_t)j;
+        p += __popcll(mk);
+    }
+    if (nrec > 0) {
+        const int32_t lo = soff[t], hi = soff[t + 1];
+        for (int32_t base = lo; base < hi; base += 64) {
+            const int32_t k = base + lane;
+            const uint32_t v = k < hi ? srec[k] : 0u;
+            const bool last = (v & SREC_LAST) != 0;
+            const unsigned long long mk = __ballot(last);
+            const int32_t dst = p + __popcll(mk & below);
+            if (last && dst < lim) perm[dst] = (uint32_t)pid[v & ~SREC_LAST];
+            p += __popcll(mk);
+        }
+    }
+    if (lane == 0 && (p != end || end > np)) *err = 1;  // cannot happen while the counts above hold
 }
 
 __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx, int64_t n,
@@ -1814,6 +1891,23 @@ hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const u
     const int64_t n = (int64_t)nt * n1l;
     if (n1l == 6) hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
     else hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_count(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
+                               const uint32_t *srec, int64_t nrec, uint32_t *cnt, hipStream_t s)
+{
+    if (nt > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk((int64_t)nt * 64)), dim3(BLK), 0, s, nt, off, moved,
+                                   soff, srec, nrec, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
+                        const uint32_t *srec, int64_t nrec, const int32_t *pid, const int32_t *noff, int64_t np,
+                        uint32_t *perm, unsigned long long *err, hipStream_t s)
+{
+    if (nt > 0) hipLaunchKernelGGL(k_place, dim3(nblk((int64_t)nt * 64)), dim3(BLK), 0, s, nt, off, moved, soff,
+                                   srec, nrec, pid, noff, np, perm, err);
     return hipGetLastError();
 }
 

@@ -254,6 +254,10 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_P.alloc((size_t)m.nt * n1l * 8);
     d_Pr.alloc((size_t)m.nt * n0l * 8);
     d_off.alloc((size_t)(m.nt + 1) * 4);
+    d_noff.alloc((size_t)(m.nt + 1) * 4);
+    d_tcnt.alloc((size_t)std::max<int64_t>(m.nt, 1) * 4);
+    d_perr.alloc(8);
+    zero(d_perr);
     d_soff.alloc((size_t)(m.nt + 1) * 4);
     d_cnt.alloc(8 * 8);
     d_cntb.alloc((size_t)CONT_BLOCKS * 4 * 8);
@@ -312,6 +316,7 @@ void Run::alloc_particles(int64_t n)
         B.d.cap = cap;
     }
     cur = 0;
+    perm_valid = false;
     // particle sort
     alloc_sort(psort, cap, hp_sort);
     // spill pool
@@ -321,6 +326,7 @@ void Run::alloc_particles(int64_t n)
     d_rpos.alloc(cap * 4);
     d_cq.alloc((size_t)cap * sizeof(ContRec));
     d_qflag.alloc(cap * 4);
+    d_moved.alloc(cap);
     d_qpos.alloc(cap * 4);
     d_qidx.alloc(cap * 4);
 }
@@ -336,7 +342,8 @@ void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
     }
     const int64_t hn = sort_hist_entries(cap);
     hold[4].alloc(hn * 4);
-    hold[5].alloc(std::max<int64_t>(scan_tmp_entries(hn), scan_tmp_entries(cap)) * 4 + 64);
+    // the scans: histograms, particle flags, and per-tet bucket sizes
+    hold[5].alloc(std::max({scan_tmp_entries(hn), scan_tmp_entries(cap), scan_tmp_entries(m.nt)}) * 4 + 64);
     sb.hist = (uint32_t *)hold[4].p;
     sb.scan_tmp = (uint32_t *)hold[5].p;
     sb.cap = cap;
@@ -344,8 +351,10 @@ void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
 
 void Run::alloc_pool(int64_t cap)
 {
+    if (cap >= (int64_t)SREC_LAST) throw Error(FEMPIC_ENOMEM, "spill pool beyond 2^31 records");
     pool_cap = cap;
     d_pool_val.alloc((size_t)cap * n1l * 8);
+    d_pool_pid.alloc((size_t)cap * 4);
     d_pool_tet.alloc((size_t)cap * 4);
     d_pool_tag.alloc((size_t)cap * 8);
     alloc_sort(ssort, cap, hp_ssort);
@@ -359,6 +368,7 @@ SpillPool Run::pool() const
     sp.val = (double *)d_pool_val.p;
     sp.tet = (int32_t *)d_pool_tet.p;
     sp.tag = (int64_t *)d_pool_tag.p;
+    sp.pid = (int32_t *)d_pool_pid.p;
     sp.count = (int32_t *)d_small.p;
     sp.rcount = (int32_t *)d_rcount.p;
     sp.cap = pool_cap;
@@ -375,10 +385,32 @@ int Run::key_bits() const
 // sort the current particles by tet: returns perm (sorted -> slot) and fills d_off
 const uint32_t *Run::sort_current()
 {
+    if (perm_valid) return cur_perm;
     int res = 0;
     HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream, (const uint32_t *)pb[cur].d.tet));
     HIPCHECK(launch_offsets(psort.key[res], np, (int32_t)m.nt, (int32_t *)d_off.p, stream));
-    return psort.val[res];
+    cur_perm = psort.val[res];
+    perm_valid = true;
+    return cur_perm;
+}
+
+// the particle order of the state the particle phase has just written: per
+// tet, its particles that were not queued, then the queued ones whose path
+// ended in it (srec: the tet-sorted spill records, nrec of them)
+void Run::next_order(int64_t nrec, const uint32_t *srec)
+{
+    HIPCHECK(launch_bucket_count((int32_t)m.nt, (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
+                                 (const int32_t *)d_soff.p, srec, nrec, (uint32_t *)d_tcnt.p, stream));
+    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_tcnt.p, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp,
+                                (uint32_t *)d_noff.p + m.nt, stream));
+    uint32_t *next = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
+    HIPCHECK(launch_place((int32_t)m.nt, (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
+                          (const int32_t *)d_soff.p, srec, nrec, (const int32_t *)d_pool_pid.p,
+                          (const int32_t *)d_noff.p, np, next, (unsigned long long *)d_perr.p, stream));
+    std::swap(d_off.p, d_noff.p);
+    std::swap(d_off.bytes, d_noff.bytes);
+    cur_perm = next;
+    perm_valid = true;
 }
 
 void Run::load(const double *pos, const double *vel, int64_t n, double q_, double mass_, double w_)
@@ -426,6 +458,7 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
         const uint32_t *perm = sort_current();
         HIPCHECK(launch_permute(mixed, pb[0].d, pb[1].d, perm, n, stream));
         cur = 1;
+        perm_valid = false;
     }
     // Gauss reference charge
     compute_rho((double *)d_rho0.p);
@@ -527,7 +560,7 @@ void Run::particle_phase()
         ha->P = (double *)d_P.p;
         ha->pool = pool();
         ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_qflag.p, (int32_t *)d_qpos.p, (int32_t *)d_qidx.p,
-                           (int32_t *)d_small.p + 6};
+                           (int32_t *)d_small.p + 6, (uint8_t *)d_moved.p};
         ha->cnt = (unsigned long long *)d_cnt.p;
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
@@ -544,7 +577,10 @@ void Run::particle_phase()
         HIPCHECK(hipEventRecord(ev_c, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 32, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync((char *)h_pin + 64, d_perr.p, 8, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
+        if (*(const unsigned long long *)((char *)h_pin + 64))
+            throw Error(FEMPIC_EDEVICE, "inconsistent particle order after the previous step");
         const unsigned long long *c = (const unsigned long long *)h_pin;
         const int32_t *sm = (const int32_t *)((char *)h_pin + 32);
         // spill slots in use: the fixed pair of every queued record, then the appended ones
@@ -571,17 +607,20 @@ void Run::particle_phase()
     // canonical order of the spill records: queued record, then segment
     HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_last, psort.scan_tmp,
                                 (uint32_t *)d_small.p + 2, stream));
+    const uint32_t *srec = nullptr;
     if (nrec > 0) {
         HIPCHECK(launch_spill_compact(pool(), nslot_last, np, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
                                       stream));
         int res = 0;
         HIPCHECK(radix_sort(ssort, nrec, key_bits(), false, &res, stream));
         HIPCHECK(launch_offsets(ssort.key[res], nrec, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
-        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, ssort.val[res],
+        srec = ssort.val[res];
+        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec,
                                      (const double *)d_pool_val.p, (double *)d_P.p, stream));
     }
     HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int, (const double *)d_P.p,
                             (double *)d_dg.p, stream));
+    next_order(nrec, srec);
     HIPCHECK(hipEventRecord(ev_d, stream));
     cur = 1 - cur;
 }
@@ -865,7 +904,8 @@ size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
     size_t vecs = (size_t)(m.N1 * 8 * 14 + m.N2 * 8 * 4 + m.nt * (16 * 8 + 4 * 4 + (m.n1l + m.n2l + m.n0l) * 4));
     size_t parts = (size_t)n * 2 * (6 * 8 + 18 * rs + 8);
     // sort buffers, spill pool (1.5 n slots), continuation queue (record + flag, position, index, counts)
-    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 12 + 24) + (size_t)n * (sizeof(ContRec) + 20);
+    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 16 + 24) + (size_t)n * (sizeof(ContRec) + 21) +
+                   (size_t)m.nt * 12;
     size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
     return ops + vecs + parts + sorts + tets + (64 << 20);
 }
