@@ -79,6 +79,7 @@ struct ContQueue {
     int32_t *idx;    // [np] rec slots of the records, in slot order
     int32_t *count;  // [1] number of records (the total of the prefix sum)
     uint8_t *moved;  // [np] 1 where sorted particle i is queued (its path leaves the home tet)
+    int32_t *nstay;  // [nt] particles of each tet that are not queued
 };
 
 struct Counters {  // device int64 [4]: crossings, reflections, spills, error bits
@@ -141,20 +142,20 @@ hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np,
                                 uint32_t *val, hipStream_t s);
 // sorted spill values: pool slot, with SREC_LAST set on the record of a path's last segment
 constexpr uint32_t SREC_LAST = 0x80000000u;
+// adds the spill records to P; when cnt is set, also cnt[t] = nstay[t] + (last-segment records in t)
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,
-                               const double *recval, double *P, hipStream_t s);
-// Particle order of the next step without a sort.  Tet t's new bucket holds the
-// particles of its old bucket that were not queued (old order), then the
+                               const double *recval, double *P, const int32_t *nstay, uint32_t *cnt, hipStream_t s);
+// Particle order of the next step without a sort.  Tet t's new bucket, from
+// noff[t] (exclusive scan of cnt), holds the particles of its old bucket
+// [off[t], off[t+1]) that were not queued (moved == 0, old order), then the
 // queued particles whose path ends in t, in the order of their last-segment
-// records among t's sorted spill records (queue order).  bucket_count writes
-// per-tet stayer counts and bucket sizes; place writes perm from the new bucket
-// offsets noff (exclusive scan of the sizes) and sets *err if a bucket does not
+// records among t's sorted spill records (queue order).  tpw: tets per block
+// (at most the particle kernel's largest).  *err is set if a bucket does not
 // come out at its size.  nrec = 0: no spill records (soff, srec unread).
-hipError_t launch_bucket_count(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
-                               const uint32_t *srec, int64_t nrec, uint32_t *cnt, hipStream_t s);
-hipError_t launch_place(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
-                        const uint32_t *srec, int64_t nrec, const int32_t *pid, const int32_t *noff, int64_t np,
-                        uint32_t *perm, unsigned long long *err, hipStream_t s);
+hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
+                        const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
+                        const int32_t *pid, const int32_t *noff, uint32_t *perm, unsigned long long *err,
+                        hipStream_t s);
 hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
                           hipStream_t s);
 hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,

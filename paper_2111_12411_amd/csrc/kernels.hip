@@ -708,12 +708,22 @@ __device__ inline void block_counters(gptr<unsigned long long> cntb, unsigned lo
     }
 }
 
+// lanes [lo, hi) of a wave as a bit mask (bounds clamped to [0, 64])
+__device__ inline unsigned long long lane_range(int lo, int hi)
+{
+    lo = max(lo, 0);
+    hi = min(hi, 64);
+    if (lo >= hi) return 0ull;
+    const unsigned long long up = hi == 64 ? ~0ull : (1ull << hi) - 1ull;
+    return up & ~((1ull << lo) - 1ull);
+}
+
 // Kernel 1: per particle (sorted by tet), gather + AB4 push + the first path
 // segment, which lies in the home tet; its current moments are summed per tet
 // in LDS in a fixed order.  A particle whose path leaves the home tet is queued
 // for k_continue.
 template <int K, typename R>
-__global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restrict__ A)
+__global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__restrict__ A)
 {
     const GMesh m = gview(A->m);
     const gptr<const R> e = glb((const R *)A->e);
@@ -735,6 +745,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     __shared__ R s_e[TM][N1];
     __shared__ R s_b[TM][N2];
     __shared__ int32_t s_off[TM + 1];
+    __shared__ int32_t s_nstay[TM];  // particles of each tet that are not queued
     __shared__ double s_hc[N1][PBLK + 1];
 
     const int tid = threadIdx.x;
@@ -748,6 +759,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
     uint32_t nslot = pbeg + tid < pend ? perm[pbeg + tid] : 0u;
     for (int k = tid; k < ntl * 16; k += PBLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
     for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
+    for (int k = tid; k < TM; k += PBLK) s_nstay[k] = 0;
     for (int k = tid; k < ntl * N1; k += PBLK) {
         int t = k / N1, i = k % N1;
         s_e[t][i] = e[m.map1[(int64_t)(T0 + t) * N1 + i]];
@@ -858,6 +870,13 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
             const int lane = tid & 63;
             qflag[i] = lane < __popcll(qmask) ? 1 : 0;
             qmoved[i] = f_exit != -1 ? 1 : 0;
+            {
+                // the first lane of each tet in the wave counts the tet's staying lanes
+                const unsigned long long st = __ballot(f_exit == -1);
+                const int wb = i - lane;
+                const int lo = max(s_off[lt] - wb, 0);
+                if (lane == lo) atomicAdd(&s_nstay[lt], __popcll(st & lane_range(lo, s_off[lt + 1] - wb)));
+            }
             if (f_exit != -1) {
                 const int64_t qi = (int64_t)(i - lane) + __popcll(qmask & ((1ull << lane) - 1ull));
                 gptr<ContRec> rec = qrec + qi;
@@ -922,6 +941,7 @@ __global__ __launch_bounds__(PBLK) void k_particle(const ParticleArgs *__restric
         const int pr = tid + q * PBLK;
         if (pr < ntl * N1) P[(int64_t)T0 * N1 + pr] = acc[q];
     }
+    if (tid < ntl) glb(A->cq.nstay)[T0 + tid] = s_nstay[tid];
 }
 
 // Kernel 2: the rest of the paths of queued particles, segment by segment;
@@ -1263,13 +1283,20 @@ __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t 
 
 template <int N1>
 __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, const uint32_t *__restrict__ rec,
-                               const double *__restrict__ recval, double *__restrict__ P)
+                               const double *__restrict__ recval, double *__restrict__ P,
+                               const int32_t *__restrict__ nstay, uint32_t *__restrict__ cnt)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= (int64_t)nt * N1) return;
     const int64_t t = g / N1;
     const int c = (int)(g % N1);
     const int32_t lo = soff[t], hi = soff[t + 1];
+    if (cnt && c == 0) {
+        // size of tet t's bucket in the next particle order
+        int32_t n = nstay[t];
+        for (int32_t k = lo; k < hi; k++) n += (rec[k] & SREC_LAST) ? 1 : 0;
+        cnt[t] = (uint32_t)n;
+    }
     if (lo == hi) return;
     // fixed order: four interleaved partial sums, then (0+1)+(2+3), added to the home sum
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -1288,69 +1315,80 @@ __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, con
     P[g] += (a0 + a1) + (a2 + a3);
 }
 
-// Next step's particle order, one wave per tet (see launch_bucket_count).  The
-// stayers of old bucket [off[t], off[t+1]) are those with moved == 0; the
-// arrivals are the last-segment records among t's sorted spill records.
-__global__ __launch_bounds__(BLK) void k_bucket_count(int32_t nt, const int32_t *__restrict__ off,
-                                                      const uint8_t *__restrict__ moved,
-                                                      const int32_t *__restrict__ soff,
-                                                      const uint32_t *__restrict__ srec, int64_t nrec,
-                                                      uint32_t *__restrict__ cnt)
+// Next step's particle order (see launch_place).  The particles that stayed:
+// one block per tet range of the particle kernel's partition, walking its
+// particles in chunks; each goes to its tet's new bucket at its rank among
+// the tet's staying particles (earlier chunks, earlier waves, lower lanes).
+constexpr int PLACE_TPW_MAX = PARTICLE_TPW_MAX_1 > PARTICLE_TPW_MAX_2 ? PARTICLE_TPW_MAX_1 : PARTICLE_TPW_MAX_2;
+__global__ __launch_bounds__(BLK) void k_place_stayers(int32_t nt, int32_t tpw, const int32_t *__restrict__ off,
+                                                       const int32_t *__restrict__ noff,
+                                                       const uint8_t *__restrict__ moved, int64_t np,
+                                                       uint32_t *__restrict__ perm)
 {
-    const int64_t t = ((int64_t)blockIdx.x * BLK + threadIdx.x) / 64;  // the same for the whole wave
-    const int lane = threadIdx.x & 63;
-    if (t >= nt) return;
-    const int32_t a = off[t], b = off[t + 1];
-    int32_t n = 0;
-    for (int32_t base = a; base < b; base += 64) {
-        const int32_t j = base + lane;
-        n += __popcll(__ballot(j < b && moved[j] == 0));
+    __shared__ int32_t s_off[PLACE_TPW_MAX + 1], s_noff[PLACE_TPW_MAX], s_carry[PLACE_TPW_MAX];
+    __shared__ unsigned long long s_stay[2][BLK / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int T0 = blockIdx.x * tpw, ntl = min(T0 + tpw, nt) - T0;
+    for (int k = tid; k <= ntl; k += BLK) s_off[k] = off[T0 + k];
+    for (int k = tid; k < ntl; k += BLK) {
+        s_noff[k] = noff[T0 + k];
+        s_carry[k] = 0;
     }
-    if (nrec > 0) {
-        const int32_t lo = soff[t], hi = soff[t + 1];
-        for (int32_t base = lo; base < hi; base += 64) {
-            const int32_t k = base + lane;
-            n += __popcll(__ballot(k < hi && (srec[k] & SREC_LAST) != 0));
+    __syncthreads();
+    const int pbeg = s_off[0], pend = s_off[ntl];
+    int par = 0;
+    for (int base = pbeg; base < pend; base += BLK) {
+        const int j = base + tid;
+        const bool st = j < pend && moved[j] == 0;
+        const unsigned long long mk = __ballot(st);
+        if (lane == 0) s_stay[par][wv] = mk;
+        __syncthreads();
+        if (st) {
+            // j's tet: the last one whose range starts at or before j
+            int lo = 0, hi = ntl;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_off[mid] <= j) lo = mid;
+                else hi = mid;
+            }
+            const int tb = s_off[lo] - base, te = s_off[lo + 1] - base;
+            int rk = s_carry[lo];
+            for (int w2 = 0; w2 < wv; w2++) rk += __popcll(s_stay[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
+            rk += __popcll(mk & lane_range(tb - 64 * wv, lane));
+            const int64_t dst = (int64_t)s_noff[lo] + rk;
+            if (dst < np) perm[dst] = (uint32_t)j;
         }
+        __syncthreads();
+        if (tid < ntl) {
+            const int tb = s_off[tid] - base, te = s_off[tid + 1] - base;
+            int c = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < BLK / 64; w2++) c += __popcll(s_stay[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
+            s_carry[tid] += c;
+        }
+        par ^= 1;
     }
-    if (lane == 0) cnt[t] = (uint32_t)n;
 }
 
-__global__ __launch_bounds__(BLK) void k_place(int32_t nt, const int32_t *__restrict__ off,
-                                               const uint8_t *__restrict__ moved, const int32_t *__restrict__ soff,
-                                               const uint32_t *__restrict__ srec, int64_t nrec,
-                                               const int32_t *__restrict__ pid, const int32_t *__restrict__ noff,
-                                               int64_t np, uint32_t *__restrict__ perm,
-                                               unsigned long long *__restrict__ err)
+// the arrivals: one thread per tet walking its sorted spill records
+__global__ void k_place_arrivals(int32_t nt, const int32_t *__restrict__ nstay, const int32_t *__restrict__ soff,
+                                 const uint32_t *__restrict__ srec, int64_t nrec, const int32_t *__restrict__ pid,
+                                 const int32_t *__restrict__ noff, int64_t np, uint32_t *__restrict__ perm,
+                                 unsigned long long *__restrict__ err)
 {
-    const int64_t t = ((int64_t)blockIdx.x * BLK + threadIdx.x) / 64;
-    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const int32_t a = off[t], b = off[t + 1], end = noff[t + 1];
-    const int32_t lim = (int32_t)min((int64_t)end, np);  // writes stay inside perm in any case
-    int32_t p = noff[t];
-    for (int32_t base = a; base < b; base += 64) {
-        const int32_t j = base + lane;
-        const bool st = j < b && moved[j] == 0;
-        const unsigned long long mk = __ballot(st);
-        const int32_t dst = p + __popcll(mk & below);
-        if (st && dst < lim) perm[dst] = (uint32_t)j;
-        p += __popcll(mk);
-    }
-    if (nrec > 0) {
-        const int32_t lo = soff[t], hi = soff[t + 1];
-        for (int32_t base = lo; base < hi; base += 64) {
-            const int32_t k = base + lane;
-            const uint32_t v = k < hi ? srec[k] : 0u;
-            const bool last = (v & SREC_LAST) != 0;
-            const unsigned long long mk = __ballot(last);
-            const int32_t dst = p + __popcll(mk & below);
-            if (last && dst < lim) perm[dst] = (uint32_t)pid[v & ~SREC_LAST];
-            p += __popcll(mk);
+    const int32_t end = noff[t + 1];
+    int32_t p = noff[t] + nstay[t];
+    if (nrec > 0)
+        for (int32_t k = soff[t], hi = soff[t + 1]; k < hi; k++) {
+            const uint32_t v = srec[k];
+            if (v & SREC_LAST) {
+                if (p < end && p < np) perm[p] = (uint32_t)pid[v & ~SREC_LAST];
+                p++;
+            }
         }
-    }
-    if (lane == 0 && (p != end || end > np)) *err = 1;  // cannot happen while the counts above hold
+    if (p != end || end > np) *err = 1;  // cannot happen while the counts hold
 }
 
 __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx, int64_t n,
@@ -1886,28 +1924,28 @@ hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np,
 }
 
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *rec, const double *recval,
-                               double *P, hipStream_t s)
+                               double *P, const int32_t *nstay, uint32_t *cnt, hipStream_t s)
 {
     const int64_t n = (int64_t)nt * n1l;
-    if (n1l == 6) hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
-    else hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P);
+    if (n1l == 6)
+        hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P, nstay, cnt);
+    else
+        hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P, nstay, cnt);
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_count(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
-                               const uint32_t *srec, int64_t nrec, uint32_t *cnt, hipStream_t s)
+hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
+                        const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
+                        const int32_t *pid, const int32_t *noff, uint32_t *perm, unsigned long long *err,
+                        hipStream_t s)
 {
-    if (nt > 0) hipLaunchKernelGGL(k_bucket_count, dim3(nblk((int64_t)nt * 64)), dim3(BLK), 0, s, nt, off, moved,
-                                   soff, srec, nrec, cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_place(int32_t nt, const int32_t *off, const uint8_t *moved, const int32_t *soff,
-                        const uint32_t *srec, int64_t nrec, const int32_t *pid, const int32_t *noff, int64_t np,
-                        uint32_t *perm, unsigned long long *err, hipStream_t s)
-{
-    if (nt > 0) hipLaunchKernelGGL(k_place, dim3(nblk((int64_t)nt * 64)), dim3(BLK), 0, s, nt, off, moved, soff,
-                                   srec, nrec, pid, noff, np, perm, err);
+    if (tpw < 1 || tpw > PLACE_TPW_MAX) return hipErrorInvalidValue;
+    if (nt > 0) {
+        hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)((nt + tpw - 1) / tpw)), dim3(BLK), 0, s, nt, tpw, off,
+                           noff, moved, np, perm);
+        hipLaunchKernelGGL(k_place_arrivals, dim3(nblk(nt)), dim3(BLK), 0, s, nt, nstay, soff, srec, nrec, pid, noff,
+                           np, perm, err);
+    }
     return hipGetLastError();
 }
 

@@ -256,6 +256,7 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_off.alloc((size_t)(m.nt + 1) * 4);
     d_noff.alloc((size_t)(m.nt + 1) * 4);
     d_tcnt.alloc((size_t)std::max<int64_t>(m.nt, 1) * 4);
+    d_nstay.alloc((size_t)std::max<int64_t>(m.nt, 1) * 4);
     d_perr.alloc(8);
     zero(d_perr);
     d_soff.alloc((size_t)(m.nt + 1) * 4);
@@ -399,14 +400,14 @@ const uint32_t *Run::sort_current()
 // ended in it (srec: the tet-sorted spill records, nrec of them)
 void Run::next_order(int64_t nrec, const uint32_t *srec)
 {
-    HIPCHECK(launch_bucket_count((int32_t)m.nt, (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
-                                 (const int32_t *)d_soff.p, srec, nrec, (uint32_t *)d_tcnt.p, stream));
-    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_tcnt.p, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp,
-                                (uint32_t *)d_noff.p + m.nt, stream));
+    // bucket sizes: from the spill reduction, or with no spill records the stayers alone
+    const uint32_t *cnt = nrec > 0 ? (const uint32_t *)d_tcnt.p : (const uint32_t *)d_nstay.p;
+    HIPCHECK(exclusive_scan_u32(cnt, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp, (uint32_t *)d_noff.p + m.nt, stream));
     uint32_t *next = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
-    HIPCHECK(launch_place((int32_t)m.nt, (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
-                          (const int32_t *)d_soff.p, srec, nrec, (const int32_t *)d_pool_pid.p,
-                          (const int32_t *)d_noff.p, np, next, (unsigned long long *)d_perr.p, stream));
+    HIPCHECK(launch_place(np, (int32_t)m.nt, tpw(), (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
+                          (const int32_t *)d_nstay.p, (const int32_t *)d_soff.p, srec, nrec,
+                          (const int32_t *)d_pool_pid.p, (const int32_t *)d_noff.p, next,
+                          (unsigned long long *)d_perr.p, stream));
     std::swap(d_off.p, d_noff.p);
     std::swap(d_off.bytes, d_noff.bytes);
     cur_perm = next;
@@ -560,7 +561,7 @@ void Run::particle_phase()
         ha->P = (double *)d_P.p;
         ha->pool = pool();
         ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_qflag.p, (int32_t *)d_qpos.p, (int32_t *)d_qidx.p,
-                           (int32_t *)d_small.p + 6, (uint8_t *)d_moved.p};
+                           (int32_t *)d_small.p + 6, (uint8_t *)d_moved.p, (int32_t *)d_nstay.p};
         ha->cnt = (unsigned long long *)d_cnt.p;
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
@@ -616,7 +617,8 @@ void Run::particle_phase()
         HIPCHECK(launch_offsets(ssort.key[res], nrec, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
         srec = ssort.val[res];
         HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec,
-                                     (const double *)d_pool_val.p, (double *)d_P.p, stream));
+                                     (const double *)d_pool_val.p, (double *)d_P.p, (const int32_t *)d_nstay.p,
+                                     (uint32_t *)d_tcnt.p, stream));
     }
     HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int, (const double *)d_P.p,
                             (double *)d_dg.p, stream));
@@ -904,8 +906,8 @@ size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
     size_t vecs = (size_t)(m.N1 * 8 * 14 + m.N2 * 8 * 4 + m.nt * (16 * 8 + 4 * 4 + (m.n1l + m.n2l + m.n0l) * 4));
     size_t parts = (size_t)n * 2 * (6 * 8 + 18 * rs + 8);
     // sort buffers, spill pool (1.5 n slots), continuation queue (record + flag, position, index, counts)
-    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 16 + 24) + (size_t)n * (sizeof(ContRec) + 21) +
-                   (size_t)m.nt * 12;
+    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 16 + 24) + (size_t)n * (sizeof(ContRec) + 25) +
+                   (size_t)m.nt * 16;
     size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
     return ops + vecs + parts + sorts + tets + (64 << 20);
 }

@@ -99,7 +99,7 @@ class Run {
     DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pool_pid, d_rcount, d_rpos, d_cq, d_qflag, d_qpos, d_qidx;
     // particle order: cur_perm (sorted position -> slot) and d_off describe the
     // current state while perm_valid; the particle phase builds the next ones
-    DevBuf d_moved, d_noff, d_tcnt, d_perr;
+    DevBuf d_moved, d_nstay, d_noff, d_tcnt, d_perr;
     const uint32_t *cur_perm = nullptr;
     bool perm_valid = false;
     std::vector<DevBuf> hp_sort, hp_ssort;

@@ -51,7 +51,7 @@ size_t cube_footprint(int N, int order, int64_t n, bool mixed)
     double ops = (2 * nnzA + nnzC) * 12 + (mixed ? nnzA * 4 : 0) + N2 * 8 * 12 + N0 * 40 * 12;
     double vecs = N1 * 8 * 14 + N2 * 8 * 4 + T * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
     double parts = (double)n * 2 * (6 * 8 + 18 * rs + 8);
-    double sorts = (double)n * 24 + n * 1.5 * (n1l * 8 + 40) + (double)n * (sizeof(ContRec) + 21) + T * 12;
+    double sorts = (double)n * 24 + n * 1.5 * (n1l * 8 + 40) + (double)n * (sizeof(ContRec) + 25) + T * 16;
     double tets = T * (n1l + n0l) * 8;
     return (size_t)(ops + vecs + parts + sorts + tets) + (64u << 20);
 }
