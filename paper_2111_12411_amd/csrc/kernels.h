@@ -74,8 +74,7 @@ struct ContRec {
 
 struct ContQueue {
     ContRec *rec;    // [np] a wave of k_particle writes its records at the start of its own particle range
-    int32_t *flag;   // [np] 1 where rec holds a record
-    int32_t *pos;    // [np] exclusive prefix sum of flag
+    uint8_t *flag;   // [np + 16] 1 where rec holds a record
     int32_t *idx;    // [np] rec slots of the records, in slot order
     int32_t *count;  // [1] number of records (the total of the prefix sum)
     uint8_t *moved;  // [np] 1 where sorted particle i is queued (its path leaves the home tet)
@@ -101,18 +100,22 @@ struct SortBuffers {
 };
 int64_t sort_hist_entries(int64_t n);
 int64_t scan_tmp_entries(int64_t n);
-// key_in (optional): keys of the first pass, read in place of sb.key[0]
+// key_in (optional): keys of the first pass, read in place of sb.key[0].
+// dn (optional): device count of the pairs, at most n; the launches are sized
+// for n (the same holds for the dn arguments below)
 hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s,
-                      const uint32_t *key_in = nullptr);
+                      const uint32_t *key_in = nullptr, const int32_t *dn = nullptr);
 hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s);
 // out[i] = in[perm[i]] for every particle array
 hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
                           hipStream_t s);
 hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s);
 // bucket offsets off[t] = first index with key >= t, for t in [0, nt]
-hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s);
+hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s,
+                          const int32_t *dn = nullptr);
 // exclusive scan of uint32 (in place allowed), total into *total (device)
-hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total, hipStream_t s);
+hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total, hipStream_t s,
+                              const int32_t *dn = nullptr);
 
 // Arguments of the particle kernels, kept in device memory (passed by pointer,
 // so the kernels do not hold them all in scalar registers).
@@ -132,19 +135,27 @@ struct ParticleArgs {
     unsigned long long *cntb; // [CONT_BLOCKS][4] per-block counters of the continuation kernel
 };
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
-hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s);
+// fills cq.idx and *cq.count from cq.flag; tmp: device scratch of at least
+// 2 (np / 4096 + 1) + scan_tmp_entries(np / 4096 + 1) entries
+hipError_t launch_queue_index(const ContQueue &cq, int64_t np, uint32_t *tmp, hipStream_t s);
 // blocks of the continuation kernel (one counter slot each in cntb)
 constexpr int CONT_BLOCKS = 65536;
 // nq_hint: expected queue length (sizes the grid; any length is processed)
 hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t nq_hint, unsigned long long *cntb,
                            unsigned long long *cnt, hipStream_t s);
-hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
-                                uint32_t *val, hipStream_t s);
+// spill records in canonical order (queued record, then segment): key = tet,
+// val = slot (| SREC_LAST); nslots: launch size, nq: device count of queued
+// records (the slots in use are 2 nq plus the pool's appended count); kcap:
+// capacity of key and val
+hipError_t launch_spill_compact(const SpillPool &pool, int64_t nslots, const int32_t *nq, const uint32_t *pos,
+                                uint32_t *key, uint32_t *val, int64_t kcap, hipStream_t s);
 // sorted spill values: pool slot, with SREC_LAST set on the record of a path's last segment
 constexpr uint32_t SREC_LAST = 0x80000000u;
-// adds the spill records to P; when cnt is set, also cnt[t] = nstay[t] + (last-segment records in t)
+// adds the spill records (values recval[cap][n1l]) to P; when cnt is set, also
+// cnt[t] = nstay[t] + (last-segment records in t)
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *sorted_rec,
-                               const double *recval, double *P, const int32_t *nstay, uint32_t *cnt, hipStream_t s);
+                               const double *recval, int64_t cap, double *P, const int32_t *nstay, uint32_t *cnt,
+                               hipStream_t s);
 // Particle order of the next step without a sort.  Tet t's new bucket, from
 // noff[t] (exclusive scan of cnt), holds the particles of its old bucket
 // [off[t], off[t+1]) that were not queued (moved == 0, old order), then the
@@ -154,8 +165,8 @@ hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const u
 // come out at its size.  nrec = 0: no spill records (soff, srec unread).
 hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
                         const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
-                        const int32_t *pid, const int32_t *noff, uint32_t *perm, unsigned long long *err,
-                        hipStream_t s);
+                        const int32_t *pid, int64_t cap, const int32_t *noff, uint32_t *perm,
+                        unsigned long long *err, hipStream_t s);
 hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
                           hipStream_t s);
 hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,

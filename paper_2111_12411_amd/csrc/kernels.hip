@@ -736,7 +736,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
     const GLRule &gl = A->gl;
     const gptr<double> P = glb(A->P);
     const gptr<ContRec> qrec = glb(A->cq.rec);
-    const gptr<int32_t> qflag = glb(A->cq.flag);
+    const gptr<uint8_t> qflag = glb(A->cq.flag);
     const gptr<uint8_t> qmoved = glb(A->cq.moved);
     using O = Ord<K>;
     constexpr int N1 = O::N1, N2 = O::N2, TM = O::TPW_MAX;
@@ -1082,11 +1082,54 @@ __global__ __launch_bounds__(BLK) void k_counters(const unsigned long long *__re
 }
 
 // compacted list of the queued record slots: idx[pos[i]] = i where flag[i]
-__global__ void k_queue_index(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
-                              int32_t *__restrict__ idx)
+// Queue compaction: the slots whose byte flag is set, in increasing order, in
+// two passes over tiles of QTILE flags (16 per thread): per-tile counts, then,
+// after a scan of the counts, each tile writes its slots from its offset.
+constexpr int QT_ITEMS = 16;
+constexpr int QTILE = BLK * QT_ITEMS;
+
+// the 16 flags from base as bits (flags are 0 or 1; those at n and beyond read as 0)
+__device__ inline uint32_t flag_bits16(const uint8_t *__restrict__ flag, int64_t base, int64_t n)
 {
-    const int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-    if (i < n && flag[i]) idx[pos[i]] = (int32_t)i;
+    uint32_t b = 0;
+    if (base + QT_ITEMS <= n) {
+        const uint4 u = *(const uint4 *)(flag + base);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) b |= ((w[q] >> (8 * k)) & 1u) << (4 * q + k);
+    } else {
+        for (int k = 0; k < QT_ITEMS; k++)
+            if (base + k < n && flag[base + k]) b |= 1u << k;
+    }
+    return b;
+}
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_w, uint32_t &total);
+
+__global__ __launch_bounds__(BLK) void k_flag_count(const uint8_t *__restrict__ flag, int64_t n,
+                                                    uint32_t *__restrict__ tsum)
+{
+    __shared__ uint32_t s_w[BLK / 64];
+    const int64_t base = (int64_t)blockIdx.x * QTILE + (int64_t)threadIdx.x * QT_ITEMS;
+    uint32_t tot;
+    block_exclusive_scan((uint32_t)__popc(flag_bits16(flag, base, n)), s_w, tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BLK) void k_flag_compact(const uint8_t *__restrict__ flag, int64_t n,
+                                                      const uint32_t *__restrict__ tpos, int32_t *__restrict__ idx)
+{
+    __shared__ uint32_t s_w[BLK / 64];
+    const int64_t base = (int64_t)blockIdx.x * QTILE + (int64_t)threadIdx.x * QT_ITEMS;
+    uint32_t b = flag_bits16(flag, base, n), tot;
+    uint32_t pos = tpos[blockIdx.x] + block_exclusive_scan((uint32_t)__popc(b), s_w, tot);
+    while (b) {
+        const int k = __builtin_ctz(b);
+        b &= b - 1u;
+        idx[pos++] = (int32_t)(base + k);
+    }
 }
 
 // ------------------------------------------------------------ permute
@@ -1105,14 +1148,23 @@ __global__ void k_permute(DevParticles in, DevParticles out, const uint32_t *__r
 }
 
 // ----------------------------------------------------------- radix sort
+// element count of a launch sized on the host for n: the count at dn when
+// given (a device value the host has not read), else n
+__device__ inline int64_t dev_count(int64_t n, const int32_t *dn)
+{
+    return dn ? min(n, (int64_t)max(*dn, 0)) : n;
+}
+
 constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = BLK * RS_ITEMS;
 
 __global__ __launch_bounds__(BLK) void k_rs_hist(const uint32_t *__restrict__ key, int64_t n, int shift,
-                                                 uint32_t *__restrict__ hist, int64_t ntiles)
+                                                 uint32_t *__restrict__ hist, int64_t ntiles,
+                                                 const int32_t *__restrict__ dn)
 {
     __shared__ uint32_t h[256];
     const int tid = threadIdx.x;
+    n = dev_count(n, dn);
     h[tid] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -1128,9 +1180,10 @@ __global__ __launch_bounds__(BLK) void k_rs_hist(const uint32_t *__restrict__ ke
 __global__ __launch_bounds__(BLK) void k_rs_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
                                                     int shift, const uint32_t *__restrict__ offs, int64_t ntiles,
-                                                    int iota)
+                                                    int iota, const int32_t *__restrict__ dn)
 {
     __shared__ uint32_t run[256];
+    n = dev_count(n, dn);
     __shared__ uint32_t wcnt[BLK / 64][256];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -1204,9 +1257,11 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_w, uint3
 }
 
 __global__ __launch_bounds__(SC_THREADS) void k_scan_tile(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                                          int64_t n, uint32_t *__restrict__ sums)
+                                                          int64_t n, uint32_t *__restrict__ sums,
+                                                          const int32_t *__restrict__ dn)
 {
     __shared__ uint32_t s_w[SC_THREADS / 64];
+    n = dev_count(n, dn);
     const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
     uint32_t v[SC_ITEMS], s = 0;
 #pragma unroll
@@ -1224,8 +1279,10 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_tile(const uint32_t *__rest
     if (threadIdx.x == 0 && sums) sums[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t *__restrict__ sums)
+__global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t *__restrict__ sums,
+                           const int32_t *__restrict__ dn)
 {
+    n = dev_count(n, dn);
     const int64_t base = (int64_t)blockIdx.x * SC_TILE;
     const uint32_t add = sums[blockIdx.x];
     for (int k = threadIdx.x; k < SC_TILE; k += blockDim.x)
@@ -1233,22 +1290,26 @@ __global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t
 }
 
 __global__ void k_scan_total(const uint32_t *__restrict__ in, const uint32_t *__restrict__ out, int64_t n,
-                             uint32_t *__restrict__ total)
+                             uint32_t *__restrict__ total, const int32_t *__restrict__ dn)
 {
+    n = dev_count(n, dn);
     *total = n > 0 ? out[n - 1] + in[n - 1] : 0u;
 }
 
 // ------------------------------------------------------------- offsets
-__global__ void k_offsets(const uint32_t *__restrict__ key, int64_t n, int32_t nt, int32_t *__restrict__ off)
+__global__ void k_offsets(const uint32_t *__restrict__ key, int64_t n, int32_t nt, int32_t *__restrict__ off,
+                          const int32_t *__restrict__ dn)
 {
+    n = dev_count(n, dn);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n == 0) {
         for (int64_t t = i; t <= nt; t += (int64_t)gridDim.x * blockDim.x) off[t] = 0;
         return;
     }
     if (i >= n) return;
-    const int64_t k = key[i];
-    const int64_t kp = i == 0 ? -1 : (int64_t)key[i - 1];
+    // keys are tets; the clamp keeps the writes inside off whatever the keys hold
+    const int64_t k = min((int64_t)key[i], (int64_t)nt);
+    const int64_t kp = i == 0 ? -1 : min((int64_t)key[i - 1], (int64_t)nt);
     for (int64_t t = kp + 1; t <= k; t++) off[t] = (int32_t)i;
     if (i == n - 1)
         for (int64_t t = k + 1; t <= nt; t++) off[t] = (int32_t)n;
@@ -1268,22 +1329,26 @@ __global__ void k_copy_keys(const int32_t *__restrict__ t, uint32_t *__restrict_
 
 // ------------------------------------------------------------- spills
 __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t *__restrict__ ptag, int64_t nrec,
-                                const uint32_t *__restrict__ pos, uint32_t *__restrict__ key, uint32_t *__restrict__ val)
+                                const uint32_t *__restrict__ pos, uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                                const int32_t *__restrict__ nq, const int32_t *__restrict__ nappend, int64_t kcap)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // slots in use: the fixed pair of each queued record, then the appended ones
+    if (nq) nrec = min(nrec, 2 * (int64_t)max(*nq, 0) + max(*nappend, 0));
     if (r >= nrec) return;
     const int64_t tag = ptag[r];
     if (tag < 0) return;  // unused fixed slot
     const int64_t q = tag >> 7;
     const int j = (int)(tag & 63);
     const uint32_t dst = pos[q] + (uint32_t)j;
+    if (dst >= kcap) return;  // only when the pool overflowed (the step is redone)
     key[dst] = (uint32_t)ptet[r];
     val[dst] = (uint32_t)r | ((tag >> 6) & 1 ? SREC_LAST : 0u);
 }
 
 template <int N1>
 __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, const uint32_t *__restrict__ rec,
-                               const double *__restrict__ recval, double *__restrict__ P,
+                               const double *__restrict__ recval, int64_t cap, double *__restrict__ P,
                                const int32_t *__restrict__ nstay, uint32_t *__restrict__ cnt)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1291,27 +1356,32 @@ __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, con
     const int64_t t = g / N1;
     const int c = (int)(g % N1);
     const int32_t lo = soff[t], hi = soff[t + 1];
-    if (cnt && c == 0) {
-        // size of tet t's bucket in the next particle order
-        int32_t n = nstay[t];
-        for (int32_t k = lo; k < hi; k++) n += (rec[k] & SREC_LAST) ? 1 : 0;
-        cnt[t] = (uint32_t)n;
-    }
-    if (lo == hi) return;
-    // fixed order: four interleaved partial sums, then (0+1)+(2+3), added to the home sum
+    // fixed order: four interleaved partial sums, then (0+1)+(2+3), added to the
+    // home sum; the last-segment records are counted on the way
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int32_t narr = 0;
+    // (slots are below cap in a valid step; the clamp keeps any other inside the pool)
+    auto slot = [&](uint32_t v) { return min((int64_t)(v & ~SREC_LAST), cap - 1); };
     int32_t k = lo;
     for (; k + 3 < hi; k += 4) {
-        const uint32_t r0 = rec[k] & ~SREC_LAST, r1 = rec[k + 1] & ~SREC_LAST, r2 = rec[k + 2] & ~SREC_LAST,
-                       r3 = rec[k + 3] & ~SREC_LAST;
-        a0 += recval[(int64_t)r0 * N1 + c];
-        a1 += recval[(int64_t)r1 * N1 + c];
-        a2 += recval[(int64_t)r2 * N1 + c];
-        a3 += recval[(int64_t)r3 * N1 + c];
+        const uint32_t v0 = rec[k], v1 = rec[k + 1], v2 = rec[k + 2], v3 = rec[k + 3];
+        narr += (int32_t)((v0 >> 31) + (v1 >> 31) + (v2 >> 31) + (v3 >> 31));
+        a0 += recval[slot(v0) * N1 + c];
+        a1 += recval[slot(v1) * N1 + c];
+        a2 += recval[slot(v2) * N1 + c];
+        a3 += recval[slot(v3) * N1 + c];
     }
-    if (k < hi) a0 += recval[(int64_t)(rec[k] & ~SREC_LAST) * N1 + c];
-    if (k + 1 < hi) a1 += recval[(int64_t)(rec[k + 1] & ~SREC_LAST) * N1 + c];
-    if (k + 2 < hi) a2 += recval[(int64_t)(rec[k + 2] & ~SREC_LAST) * N1 + c];
+    for (int q = 0; q < 3 && k + q < hi; q++) {
+        const uint32_t v = rec[k + q];
+        narr += (int32_t)(v >> 31);
+        const double x = recval[slot(v) * N1 + c];
+        if (q == 0) a0 += x;
+        else if (q == 1) a1 += x;
+        else a2 += x;
+    }
+    // size of tet t's bucket in the next particle order
+    if (cnt && c == 0) cnt[t] = (uint32_t)(nstay[t] + narr);
+    if (lo == hi) return;
     P[g] += (a0 + a1) + (a2 + a3);
 }
 
@@ -1373,8 +1443,8 @@ __global__ __launch_bounds__(BLK) void k_place_stayers(int32_t nt, int32_t tpw, 
 // the arrivals: one thread per tet walking its sorted spill records
 __global__ void k_place_arrivals(int32_t nt, const int32_t *__restrict__ nstay, const int32_t *__restrict__ soff,
                                  const uint32_t *__restrict__ srec, int64_t nrec, const int32_t *__restrict__ pid,
-                                 const int32_t *__restrict__ noff, int64_t np, uint32_t *__restrict__ perm,
-                                 unsigned long long *__restrict__ err)
+                                 int64_t cap, const int32_t *__restrict__ noff, int64_t np,
+                                 uint32_t *__restrict__ perm, unsigned long long *__restrict__ err)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
@@ -1384,7 +1454,7 @@ __global__ void k_place_arrivals(int32_t nt, const int32_t *__restrict__ nstay, 
         for (int32_t k = soff[t], hi = soff[t + 1]; k < hi; k++) {
             const uint32_t v = srec[k];
             if (v & SREC_LAST) {
-                if (p < end && p < np) perm[p] = (uint32_t)pid[v & ~SREC_LAST];
+                if (p < end && p < np) perm[p] = (uint32_t)pid[min((int64_t)(v & ~SREC_LAST), cap - 1)];
                 p++;
             }
         }
@@ -1802,29 +1872,30 @@ int64_t scan_tmp_entries(int64_t n)
 }
 
 hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, uint32_t *total,
-                              hipStream_t s)
+                              hipStream_t s, const int32_t *dn)
 {
+    const int32_t *nodn = nullptr;
     if (n == 0) {
-        if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total);
+        if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total, nodn);
         return hipGetLastError();
     }
     const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SC_THREADS), 0, s, in, out, n, (uint32_t *)nullptr);
+        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SC_THREADS), 0, s, in, out, n, (uint32_t *)nullptr, dn);
     } else {
         uint32_t *sums = tmp;
         uint32_t *sums_scan = tmp + nb;
-        hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, out, n, sums);
+        hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, out, n, sums, dn);
         hipError_t err = exclusive_scan_u32(sums, sums_scan, nb, tmp + 2 * nb, nullptr, s);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(BLK), 0, s, out, n, sums_scan);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(BLK), 0, s, out, n, sums_scan, dn);
     }
-    if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total);
+    if (total) hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(1), 0, s, in, out, n, total, dn);
     return hipGetLastError();
 }
 
 hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s,
-                      const uint32_t *key_in)
+                      const uint32_t *key_in, const int32_t *dn)
 {
     int cur = 0;
     if (n == 0) {
@@ -1836,12 +1907,12 @@ hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, 
     for (int pass = 0; pass < passes; pass++) {
         const int shift = 8 * pass;
         const uint32_t *kin = (pass == 0 && key_in) ? key_in : sb.key[cur];
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(BLK), 0, s, kin, n, shift, sb.hist, ntiles);
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(BLK), 0, s, kin, n, shift, sb.hist, ntiles, dn);
         hipError_t err = exclusive_scan_u32(sb.hist, sb.hist, 256 * ntiles, sb.scan_tmp, nullptr, s);
         if (err != hipSuccess) return err;
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(BLK), 0, s, kin, sb.val[cur],
                            sb.key[1 - cur], sb.val[1 - cur], n, shift, sb.hist, ntiles,
-                           (pass == 0 && vals_are_iota) ? 1 : 0);
+                           (pass == 0 && vals_are_iota) ? 1 : 0, dn);
         cur = 1 - cur;
     }
     *result_buf = cur;
@@ -1871,10 +1942,11 @@ hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *off, hipStream_t s)
+hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *off, hipStream_t s, const int32_t *dn)
 {
-    const int64_t w = n > 0 ? n : (int64_t)nt + 1;
-    hipLaunchKernelGGL(k_offsets, dim3(nblk(w)), dim3(BLK), 0, s, key, n, nt, off);
+    // with a device count, n may come out as 0: then nt + 1 threads clear off
+    const int64_t w = dn ? std::max<int64_t>(n, (int64_t)nt + 1) : (n > 0 ? n : (int64_t)nt + 1);
+    hipLaunchKernelGGL(k_offsets, dim3(nblk(w)), dim3(BLK), 0, s, key, n, nt, off, dn);
     return hipGetLastError();
 }
 
@@ -1891,9 +1963,15 @@ hipError_t launch_particle(int order, bool mixed, const ParticleArgs *A, int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_queue_index(const ContQueue &cq, int64_t np, hipStream_t s)
+hipError_t launch_queue_index(const ContQueue &cq, int64_t np, uint32_t *tmp, hipStream_t s)
 {
-    if (np > 0) hipLaunchKernelGGL(k_queue_index, dim3(nblk(np)), dim3(BLK), 0, s, cq.flag, cq.pos, np, cq.idx);
+    if (np == 0) return exclusive_scan_u32(tmp, tmp, 0, tmp, (uint32_t *)cq.count, s);
+    const int64_t nt = (np + QTILE - 1) / QTILE;
+    uint32_t *tsum = tmp, *tpos = tmp + nt;
+    hipLaunchKernelGGL(k_flag_count, dim3((unsigned)nt), dim3(BLK), 0, s, cq.flag, np, tsum);
+    hipError_t err = exclusive_scan_u32(tsum, tpos, nt, tmp + 2 * nt, (uint32_t *)cq.count, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_flag_compact, dim3((unsigned)nt), dim3(BLK), 0, s, cq.flag, np, tpos, cq.idx);
     return hipGetLastError();
 }
 
@@ -1914,37 +1992,41 @@ hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, int64_t np, const uint32_t *pos, uint32_t *key,
-                                uint32_t *val, hipStream_t s)
+hipError_t launch_spill_compact(const SpillPool &pool, int64_t nrec, const int32_t *nq, const uint32_t *pos,
+                                uint32_t *key, uint32_t *val, int64_t kcap, hipStream_t s)
 {
-    (void)np;
     if (nrec == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spill_compact, dim3(nblk(nrec)), dim3(BLK), 0, s, pool.tet, pool.tag, nrec, pos, key, val);
+    hipLaunchKernelGGL(k_spill_compact, dim3(nblk(nrec)), dim3(BLK), 0, s, pool.tet, pool.tag, nrec, pos, key, val, nq,
+                       (const int32_t *)pool.count, kcap);
     return hipGetLastError();
 }
 
 hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const uint32_t *rec, const double *recval,
-                               double *P, const int32_t *nstay, uint32_t *cnt, hipStream_t s)
+                               int64_t cap, double *P, const int32_t *nstay, uint32_t *cnt, hipStream_t s)
 {
     const int64_t n = (int64_t)nt * n1l;
+    if (n == 0 || cap < 1) return hipSuccess;
     if (n1l == 6)
-        hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P, nstay, cnt);
+        hipLaunchKernelGGL(k_spill_reduce<6>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, cap, P, nstay,
+                           cnt);
     else
-        hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, P, nstay, cnt);
+        hipLaunchKernelGGL(k_spill_reduce<20>, dim3(nblk(n)), dim3(BLK), 0, s, nt, soff, rec, recval, cap, P, nstay,
+                           cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
                         const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
-                        const int32_t *pid, const int32_t *noff, uint32_t *perm, unsigned long long *err,
-                        hipStream_t s)
+                        const int32_t *pid, int64_t cap, const int32_t *noff, uint32_t *perm,
+                        unsigned long long *err, hipStream_t s)
 {
     if (tpw < 1 || tpw > PLACE_TPW_MAX) return hipErrorInvalidValue;
+    if (cap < 1) nrec = 0;
     if (nt > 0) {
         hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)((nt + tpw - 1) / tpw)), dim3(BLK), 0, s, nt, tpw, off,
                            noff, moved, np, perm);
-        hipLaunchKernelGGL(k_place_arrivals, dim3(nblk(nt)), dim3(BLK), 0, s, nt, nstay, soff, srec, nrec, pid, noff,
-                           np, perm, err);
+        hipLaunchKernelGGL(k_place_arrivals, dim3(nblk(nt)), dim3(BLK), 0, s, nt, nstay, soff, srec, nrec, pid, cap,
+                           noff, np, perm, err);
     }
     return hipGetLastError();
 }

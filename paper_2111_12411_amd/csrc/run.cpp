@@ -318,6 +318,7 @@ void Run::alloc_particles(int64_t n)
     }
     cur = 0;
     perm_valid = false;
+    counts_known = false;
     // particle sort
     alloc_sort(psort, cap, hp_sort);
     // spill pool
@@ -326,9 +327,9 @@ void Run::alloc_particles(int64_t n)
     d_rcount.alloc(cap * 4);
     d_rpos.alloc(cap * 4);
     d_cq.alloc((size_t)cap * sizeof(ContRec));
-    d_qflag.alloc(cap * 4);
+    d_qflag.alloc(cap + 16);  // byte flags, read 16 at a time
     d_moved.alloc(cap);
-    d_qpos.alloc(cap * 4);
+    d_qtmp.alloc((2 * (cap / 4096 + 1) + scan_tmp_entries(cap / 4096 + 1)) * 4 + 64);
     d_qidx.alloc(cap * 4);
 }
 
@@ -397,20 +398,24 @@ const uint32_t *Run::sort_current()
 
 // the particle order of the state the particle phase has just written: per
 // tet, its particles that were not queued, then the queued ones whose path
-// ended in it (srec: the tet-sorted spill records, nrec of them)
+// ended in it (srec: the tet-sorted spill records, at most nrec of them).
+// Built into the buffers not in use; commit_order() makes it current.
 void Run::next_order(int64_t nrec, const uint32_t *srec)
 {
-    // bucket sizes: from the spill reduction, or with no spill records the stayers alone
-    const uint32_t *cnt = nrec > 0 ? (const uint32_t *)d_tcnt.p : (const uint32_t *)d_nstay.p;
-    HIPCHECK(exclusive_scan_u32(cnt, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp, (uint32_t *)d_noff.p + m.nt, stream));
-    uint32_t *next = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
+    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_tcnt.p, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp,
+                                (uint32_t *)d_noff.p + m.nt, stream));
+    next_perm = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
     HIPCHECK(launch_place(np, (int32_t)m.nt, tpw(), (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
                           (const int32_t *)d_nstay.p, (const int32_t *)d_soff.p, srec, nrec,
-                          (const int32_t *)d_pool_pid.p, (const int32_t *)d_noff.p, next,
+                          (const int32_t *)d_pool_pid.p, pool_cap, (const int32_t *)d_noff.p, next_perm,
                           (unsigned long long *)d_perr.p, stream));
+}
+
+void Run::commit_order()
+{
     std::swap(d_off.p, d_noff.p);
     std::swap(d_off.bytes, d_noff.bytes);
-    cur_perm = next;
+    cur_perm = next_perm;
     perm_valid = true;
 }
 
@@ -543,10 +548,21 @@ void Run::particle_phase()
     HIPCHECK(hipEventRecord(ev_a, stream));
     const uint32_t *perm = sort_current();
     StepParams sp{q / mass, q * w, prm.dt, tpw()};
-    bool done = false;
-    for (int attempt = 0; attempt < 4 && !done; attempt++) {
+    // The queue and spill stages run on counts that stay on the device: their
+    // launches are sized by bounds from the previous step's counts (the largest
+    // possible before the first), and the host reads the counts once, at the end
+    // of the phase.  A step whose counts exceed the bounds, or that overflows
+    // the spill pool, is redone: its input state is untouched until the commit.
+    auto grow = [](int64_t x) { return x + x / 4 + 4096; };
+    int64_t nq_ub = counts_known ? std::min<int64_t>(np, grow(nq_last)) : np;
+    int64_t nslot_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nslot_last)) : pool_cap;
+    int64_t nrec_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nrec_last)) : pool_cap;
+    const int32_t *d_nq = (const int32_t *)d_small.p + 6, *d_nrec = (const int32_t *)d_small.p + 2;
+    for (int attempt = 0;; attempt++) {
+        if (attempt == 6) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
         zero(d_small);
         zero(d_cnt);
+        zero(d_perr);
         ParticleArgs *ha = (ParticleArgs *)((char *)h_pin + 128);
         ha->m = dm;
         ha->e = mixed ? (const void *)d_e32.p : (const void *)d_e.p;
@@ -560,8 +576,8 @@ void Run::particle_phase()
         ha->gl = gl;
         ha->P = (double *)d_P.p;
         ha->pool = pool();
-        ha->cq = ContQueue{(ContRec *)d_cq.p, (int32_t *)d_qflag.p, (int32_t *)d_qpos.p, (int32_t *)d_qidx.p,
-                           (int32_t *)d_small.p + 6, (uint8_t *)d_moved.p, (int32_t *)d_nstay.p};
+        ha->cq = ContQueue{(ContRec *)d_cq.p, (uint8_t *)d_qflag.p, (int32_t *)d_qidx.p, (int32_t *)d_small.p + 6,
+                           (uint8_t *)d_moved.p, (int32_t *)d_nstay.p};
         ha->cnt = (unsigned long long *)d_cnt.p;
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
@@ -569,61 +585,66 @@ void Run::particle_phase()
         HIPCHECK(launch_particle(order, mixed, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw, stream));
         HIPCHECK(hipEventRecord(ev_c1, stream));
         // compact the queue written by k_particle, then continue the queued paths
-        HIPCHECK(exclusive_scan_u32((const uint32_t *)d_qflag.p, (uint32_t *)d_qpos.p, np, psort.scan_tmp,
-                                    (uint32_t *)d_small.p + 6, stream));
-        HIPCHECK(launch_queue_index(ha->cq, np, stream));
-        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, nq_last > 0 ? nq_last : np / 8,
-                                 (unsigned long long *)d_cntb.p,
-                                 (unsigned long long *)d_cnt.p, stream));
+        HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
+        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, counts_known ? nq_last : np / 8,
+                                 (unsigned long long *)d_cntb.p, (unsigned long long *)d_cnt.p, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
+        // deterministic reduction of the spill pool: records in canonical order
+        // (queued record, then segment), sorted by tet, summed per tet
+        HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_ub, psort.scan_tmp,
+                                    (uint32_t *)d_small.p + 2, stream, d_nq));
+        HIPCHECK(launch_spill_compact(pool(), nslot_ub, d_nq, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
+                                      ssort.cap, stream));
+        int res = 0;
+        HIPCHECK(radix_sort(ssort, nrec_ub, key_bits(), false, &res, stream, nullptr, d_nrec));
+        HIPCHECK(launch_offsets(ssort.key[res], nrec_ub, (int32_t)m.nt, (int32_t *)d_soff.p, stream, d_nrec));
+        const uint32_t *srec = ssort.val[res];
+        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec, (const double *)d_pool_val.p,
+                                     pool_cap, (double *)d_P.p, (const int32_t *)d_nstay.p, (uint32_t *)d_tcnt.p,
+                                     stream));
+        HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int,
+                                (const double *)d_P.p, (double *)d_dg.p, stream));
+        next_order(nrec_ub, srec);
+        HIPCHECK(hipEventRecord(ev_d, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 32, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync((char *)h_pin + 64, d_perr.p, 8, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
-        if (*(const unsigned long long *)((char *)h_pin + 64))
-            throw Error(FEMPIC_EDEVICE, "inconsistent particle order after the previous step");
         const unsigned long long *c = (const unsigned long long *)h_pin;
         const int32_t *sm = (const int32_t *)((char *)h_pin + 32);
+        const int64_t nq = sm[6];
         // spill slots in use: the fixed pair of every queued record, then the appended ones
-        const int64_t nslots = 2 * (int64_t)sm[6] + sm[0];
-        last_cross = (int64_t)c[0];
-        last_refl = (int64_t)c[1];
-        last_spill = (int64_t)c[2];
+        const int64_t nslots = 2 * nq + sm[0];
+        const int64_t nrec = (uint32_t)sm[2];
         const unsigned long long errs = c[3];
         if (errs & ERR_POOL) {
-            // grow the pool and redo the step (the input state is untouched)
+            // grow the pool and redo the step
             alloc_pool(std::max<int64_t>(2 * pool_cap, nslots + nslots / 4 + 1024));
+            nq_ub = std::max<int64_t>(nq_ub, nq);
+            nslot_ub = std::min<int64_t>(pool_cap, nslots);
+            nrec_ub = std::min<int64_t>(pool_cap, nrec);
             continue;
         }
         if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
         if (errs & ERR_NAN) throw Error(FEMPIC_EDEVICE, "non-finite particle position");
+        if (nq > nq_ub || nslots > nslot_ub || nrec > nrec_ub) {
+            nq_ub = nq;
+            nslot_ub = nslots;
+            nrec_ub = nrec;
+            continue;
+        }
+        if (*(const unsigned long long *)((char *)h_pin + 64))
+            throw Error(FEMPIC_EDEVICE, "inconsistent particle order");
+        last_cross = (int64_t)c[0];
+        last_refl = (int64_t)c[1];
+        last_spill = (int64_t)c[2];
         nslot_last = nslots;
-        nq_last = sm[6];
-        nrec_last = last_spill;
-        done = true;
+        nq_last = nq;
+        nrec_last = nrec;
+        counts_known = true;
+        break;
     }
-    if (!done) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
-    // deterministic reduction of the spill pool
-    const int64_t nrec = nrec_last;
-    // canonical order of the spill records: queued record, then segment
-    HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_last, psort.scan_tmp,
-                                (uint32_t *)d_small.p + 2, stream));
-    const uint32_t *srec = nullptr;
-    if (nrec > 0) {
-        HIPCHECK(launch_spill_compact(pool(), nslot_last, np, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
-                                      stream));
-        int res = 0;
-        HIPCHECK(radix_sort(ssort, nrec, key_bits(), false, &res, stream));
-        HIPCHECK(launch_offsets(ssort.key[res], nrec, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
-        srec = ssort.val[res];
-        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec,
-                                     (const double *)d_pool_val.p, (double *)d_P.p, (const int32_t *)d_nstay.p,
-                                     (uint32_t *)d_tcnt.p, stream));
-    }
-    HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int, (const double *)d_P.p,
-                            (double *)d_dg.p, stream));
-    next_order(nrec, srec);
-    HIPCHECK(hipEventRecord(ev_d, stream));
+    commit_order();
     cur = 1 - cur;
 }
 

@@ -83,6 +83,7 @@ class Run {
     void compute_rho(double *dst);
     void particle_phase();
     void next_order(int64_t nrec, const uint32_t *srec);
+    void commit_order();
     void field_phase();
     void solve_fp64();
     void solve_mixed();
@@ -96,12 +97,14 @@ class Run {
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_cntb, d_small, d_args;
-    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pool_pid, d_rcount, d_rpos, d_cq, d_qflag, d_qpos, d_qidx;
+    DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pool_pid, d_rcount, d_rpos, d_cq, d_qflag, d_qtmp, d_qidx;
     // particle order: cur_perm (sorted position -> slot) and d_off describe the
     // current state while perm_valid; the particle phase builds the next ones
     DevBuf d_moved, d_nstay, d_noff, d_tcnt, d_perr;
     const uint32_t *cur_perm = nullptr;
+    uint32_t *next_perm = nullptr;
     bool perm_valid = false;
+    bool counts_known = false;  // nq_last, nslot_last, nrec_last hold the last step's counts
     std::vector<DevBuf> hp_sort, hp_ssort;
     PBufs pb[2];
     int cur = 0;
