@@ -85,7 +85,9 @@ struct Counters {  // device int64 [4]: crossings, reflections, spills, error bi
     unsigned long long *c;
 };
 
-hipError_t launch_locate_cube(const DevMesh &m, int64_t n, const double *x, int32_t *tet, int32_t *err, hipStream_t s);
+// x: [3][cap] positions of n particles
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
+                              hipStream_t s);
 hipError_t launch_startup(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
                           const float *b32, DevParticles p, int64_t n, double qm, double dt, hipStream_t s);
 

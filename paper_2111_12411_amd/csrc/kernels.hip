@@ -61,14 +61,14 @@ __device__ __constant__ const int FP[4][3] = {{3, 1, 0}, {4, 2, 0}, {5, 2, 1}, {
 namespace {
 
 // ---------------------------------------------------------------- locate
-__global__ void k_locate_cube(DevMesh m, int64_t n, const double *__restrict__ x, int32_t *__restrict__ tet,
-                              int32_t *__restrict__ err)
+__global__ void k_locate_cube(DevMesh m, int64_t n, int64_t cap, const double *__restrict__ x,
+                              int32_t *__restrict__ tet, int32_t *__restrict__ err)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int N = m.cube_N;
     const double L = m.cube_L;
-    double r[3] = {x[p], x[n + p], x[2 * n + p]};
+    double r[3] = {x[p], x[cap + p], x[2 * cap + p]};
     const double tol = 1e-12 * L;
     int idx[3];
     bool ok = true;
@@ -1837,10 +1837,11 @@ inline unsigned nblk(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b
 }  // namespace
 
 // =================================================================== launchers
-hipError_t launch_locate_cube(const DevMesh &m, int64_t n, const double *x, int32_t *tet, int32_t *err, hipStream_t s)
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
+                              hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, x, tet, err);
+    hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, cap, x, tet, err);
     return hipGetLastError();
 }
 

@@ -445,7 +445,8 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     std::vector<int32_t> tets;
     if (m.is_cube) {
         zero(d_small);
-        HIPCHECK(launch_locate_cube(dm, n, (const double *)B.x.p, (int32_t *)B.tet.p, (int32_t *)d_small.p, stream));
+        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.x.p, (int32_t *)B.tet.p, (int32_t *)d_small.p,
+                                    stream));
         int32_t err = 0;
         HIPCHECK(hipMemcpyAsync(&err, d_small.p, 4, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
