@@ -26,7 +26,7 @@ struct DevMesh {
 struct DevParticles {
     double *x;     // [3][cap]
     void *v;       // [3][cap]   double
-    void *vh;      // [9][cap]   R: v^{n-1}, v^{n-2}, v^{n-3}
+    void *vh;      // [9][cap]   R: v^{n-1} - v^n, v^{n-2} - v^n, v^{n-3} - v^n
     void *ah;      // [9][cap]   R: a^{n-1}, a^{n-2}, a^{n-3}
     int32_t *tet;  // [cap]
     int32_t *id;   // [cap]  load order

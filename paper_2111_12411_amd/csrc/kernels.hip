@@ -206,10 +206,11 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
     cross3(v, B, vxB);
     for (int k = 0; k < 3; k++) a[k] = (R)qm * (E[k] + vxB[k]);
     R vh[9], ah[9];
+    // velocity history as differences from the current velocity: v^{n-j} - v^n
     for (int j = 1; j <= 3; j++)
         for (int k = 0; k < 3; k++) {
             ah[3 * (j - 1) + k] = a[k];
-            vh[3 * (j - 1) + k] = (R)(vd[k] - j * dt * (double)a[k]);
+            vh[3 * (j - 1) + k] = (R)(-j * dt * (double)a[k]);
         }
     store_vec<R>(P.vh, P.cap, 0, p, vh, 9);
     store_vec<R>(P.ah, P.cap, 0, p, ah, 9);
@@ -828,19 +829,23 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 for (int c = 0; c < 3; c++) B[c] += cB[q] * s_X[lt][3 * q + c];
             // Lorentz acceleration (precision R); AB4 velocity increment in R added to the FP64 velocity
             R vxB[3], a[3];
-            double vn[3];
+            double dv[3], vn[3];
             cross3(v, B, vxB);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 a[c] = qmR * (E[c] + vxB[c]);
-                vn[c] = vd[c] + (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
+                dv[c] = (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
+                vn[c] = vd[c] + dv[c];
             }
-            // quartic path r(s) = sum_d c_d s^d (FP64 in both modes)
+            // quartic path r(s) = sum_d c_d s^d (FP64 in both modes); the history
+            // holds v^{n-j} - v^n, so in R it is rounded relative to the change
+            // of velocity, not to the velocity
             double cp[5][3];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 cp[0][c] = r[c];
-                const double v0 = vd[c], v1 = (double)vh[c], v2 = (double)vh[3 + c], v3 = (double)vh[6 + c];
+                const double v0 = vd[c], v1 = vd[c] + (double)vh[c], v2 = vd[c] + (double)vh[3 + c],
+                             v3 = vd[c] + (double)vh[6 + c];
 #pragma unroll
                 for (int d = 1; d < 5; d++)
                     cp[d][c] = sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
@@ -849,9 +854,9 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 out.v[c * out.cap + i] = vn[c];
-                out.vh[c * out.cap + i] = v[c];
-                out.vh[(3 + c) * out.cap + i] = vh[c];
-                out.vh[(6 + c) * out.cap + i] = vh[3 + c];
+                out.vh[c * out.cap + i] = (R)(-dv[c]);
+                out.vh[(3 + c) * out.cap + i] = (R)((double)vh[c] - dv[c]);
+                out.vh[(6 + c) * out.cap + i] = (R)((double)vh[3 + c] - dv[c]);
                 out.ah[c * out.cap + i] = a[c];
                 out.ah[(3 + c) * out.cap + i] = ah[c];
                 out.ah[(6 + c) * out.cap + i] = ah[3 + c];

@@ -914,7 +914,16 @@ void Run::history_get(double *vh, double *ah, int64_t n)
         for (int64_t i = 0; i < np; i++)
             for (int c = 0; c < 9; c++) dst[9 * id[i] + c] = h[c * np + i];
     };
-    if (vh) fetch(B.vh, vh);
+    if (vh) {
+        // the device keeps v^{n-j} - v^n; the caller gets v^{n-j}
+        fetch(B.vh, vh);
+        std::vector<double> v(3 * std::max<int64_t>(np, 1));
+        for (int c = 0; c < 3; c++)
+            if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < np; i++)
+            for (int j = 0; j < 3; j++)
+                for (int c = 0; c < 3; c++) vh[9 * id[i] + 3 * j + c] += v[c * np + i];
+    }
     if (ah) fetch(B.ah, ah);
 }
 
