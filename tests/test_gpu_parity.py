@@ -200,3 +200,43 @@ def test_failure_modes():
     assert ei.value.code == -6  # ESOLVE
     with pytest.raises(F.FempicError):  # sticky
         run2.step()
+
+
+def test_step_redone_when_counts_exceed_bounds():
+    """The queue and spill stages run on counts that stay on the device, with launches sized by
+    bounds from the previous step; a step whose counts exceed them is redone with the exact counts.
+    Particles at rest for two steps (empty queue, so the bounds are at their minimum), then a strong
+    field set before the second makes most of them cross faces in the third: that step must be
+    redone, and it must match the oracle started from the GPU's state and fields."""
+    N, k = 4, 2
+    m = omesh.cube_mesh(N, k)
+    dt = 5 * cfl(N, k)
+    n = 12000
+    pos, _ = W.particles("thermal", n, 4242)
+    vel = np.zeros_like(pos)
+    w = W.plasma_weight(n, dt)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.FP64)
+    run.load(pos, vel, QE, ME, w)
+    run.step(1)
+    assert run.stats()["crossings"] == 0
+    e0, b0 = W.random_fields(m.n1, m.n2, 77, e_scale=2e5, b_scale=1e-5)
+    run.set_fields(e0 * m.int1, b0)
+    run.step(1)
+    assert run.stats()["crossings"] == 0
+    p0, v0, t0 = run.particles()
+    vh0, ah0 = run.history()
+    e1, b1 = run.fields()
+    run.step(1)
+    p1, v1, t1 = run.particles()
+    # far more queued paths than the bound taken from the previous (empty) step
+    assert run.stats()["crossings"] > 3 * 4096
+    orc = core.OracleRun(m, dt, particles_only=True)
+    orc.load(p0, v0, QE, ME, w, tet=t0)
+    orc.vh = np.ascontiguousarray(vh0, dtype=np.float64)
+    orc.ah = np.ascontiguousarray(ah0, dtype=np.float64)
+    orc.e, orc.b = e1.copy(), b1.copy()
+    orc.particle_step()
+    assert rel(p1, orc.pos) < 1e-13
+    assert rel(v1, orc.vel) < 1e-12
+    assert np.mean(t1 == orc.tet) > 0.999
+    run.close()
