@@ -166,9 +166,8 @@ hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const u
 // (at most the particle kernel's largest).  *err is set if a bucket does not
 // come out at its size.  nrec = 0: no spill records (soff, srec unread).
 hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
-                        const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
-                        const int32_t *pid, int64_t cap, const int32_t *noff, uint32_t *perm,
-                        unsigned long long *err, hipStream_t s);
+                        const int32_t *soff, const uint32_t *srec, int64_t nrec, const int32_t *pid, int64_t cap,
+                        const int32_t *noff, uint32_t *perm, unsigned long long *err, hipStream_t s);
 hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
                           hipStream_t s);
 hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,

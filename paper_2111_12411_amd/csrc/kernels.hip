@@ -1390,80 +1390,74 @@ __global__ void k_spill_reduce(int32_t nt, const int32_t *__restrict__ soff, con
     P[g] += (a0 + a1) + (a2 + a3);
 }
 
-// Next step's particle order (see launch_place).  The particles that stayed:
-// one block per tet range of the particle kernel's partition, walking its
-// particles in chunks; each goes to its tet's new bucket at its rank among
-// the tet's staying particles (earlier chunks, earlier waves, lower lanes).
+// Next step's particle order (see launch_place), one block per tet range of
+// the particle kernel's partition.  Two passes place items in order within
+// each tet: first the tets' particles that stayed (items: old positions, tet
+// ranges off), then their arrivals (items: sorted spill records, tet ranges
+// soff, the last-segment ones).  An item goes to its tet's next place: its
+// rank among the tet's placed items, from earlier chunks (a per-tet carry in
+// LDS), earlier waves and lower lanes of its chunk (wave ballots).
 constexpr int PLACE_TPW_MAX = PARTICLE_TPW_MAX_1 > PARTICLE_TPW_MAX_2 ? PARTICLE_TPW_MAX_1 : PARTICLE_TPW_MAX_2;
-__global__ __launch_bounds__(BLK) void k_place_stayers(int32_t nt, int32_t tpw, const int32_t *__restrict__ off,
-                                                       const int32_t *__restrict__ noff,
-                                                       const uint8_t *__restrict__ moved, int64_t np,
-                                                       uint32_t *__restrict__ perm)
+__global__ __launch_bounds__(BLK) void k_place(int32_t nt, int32_t tpw, const int32_t *__restrict__ off,
+                                               const int32_t *__restrict__ noff, const uint8_t *__restrict__ moved,
+                                               const int32_t *__restrict__ soff, const uint32_t *__restrict__ srec,
+                                               int64_t nrec, const int32_t *__restrict__ pid, int64_t pool_cap,
+                                               int64_t np, uint32_t *__restrict__ perm,
+                                               unsigned long long *__restrict__ err)
 {
-    __shared__ int32_t s_off[PLACE_TPW_MAX + 1], s_noff[PLACE_TPW_MAX], s_carry[PLACE_TPW_MAX];
-    __shared__ unsigned long long s_stay[2][BLK / 64];
+    __shared__ int32_t s_off[PLACE_TPW_MAX + 1], s_soff[PLACE_TPW_MAX + 1], s_noff[PLACE_TPW_MAX + 1];
+    __shared__ int32_t s_carry[PLACE_TPW_MAX];
+    __shared__ unsigned long long s_mask[2][BLK / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int T0 = blockIdx.x * tpw, ntl = min(T0 + tpw, nt) - T0;
-    for (int k = tid; k <= ntl; k += BLK) s_off[k] = off[T0 + k];
-    for (int k = tid; k < ntl; k += BLK) {
+    for (int k = tid; k <= ntl; k += BLK) {
+        s_off[k] = off[T0 + k];
         s_noff[k] = noff[T0 + k];
-        s_carry[k] = 0;
+        s_soff[k] = nrec > 0 ? soff[T0 + k] : 0;
     }
+    for (int k = tid; k < ntl; k += BLK) s_carry[k] = 0;
     __syncthreads();
-    const int pbeg = s_off[0], pend = s_off[ntl];
     int par = 0;
-    for (int base = pbeg; base < pend; base += BLK) {
-        const int j = base + tid;
-        const bool st = j < pend && moved[j] == 0;
-        const unsigned long long mk = __ballot(st);
-        if (lane == 0) s_stay[par][wv] = mk;
-        __syncthreads();
-        if (st) {
-            // j's tet: the last one whose range starts at or before j
-            int lo = 0, hi = ntl;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_off[mid] <= j) lo = mid;
-                else hi = mid;
+    auto pass = [&](const int32_t *R, auto sel, auto value) {
+        for (int base = R[0]; base < R[ntl]; base += BLK) {
+            const int j = base + tid;
+            const bool on = j < R[ntl] && sel(j);
+            const unsigned long long mk = __ballot(on);
+            if (lane == 0) s_mask[par][wv] = mk;
+            __syncthreads();
+            if (on) {
+                // j's tet: the last one whose range starts at or before j
+                int lo = 0, hi = ntl;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (R[mid] <= j) lo = mid;
+                    else hi = mid;
+                }
+                const int tb = R[lo] - base, te = R[lo + 1] - base;
+                int rk = s_carry[lo];
+                for (int w2 = 0; w2 < wv; w2++) rk += __popcll(s_mask[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
+                rk += __popcll(mk & lane_range(tb - 64 * wv, lane));
+                const int64_t dst = (int64_t)s_noff[lo] + rk;
+                if (dst < s_noff[lo + 1] && dst < np) perm[dst] = value(j);
             }
-            const int tb = s_off[lo] - base, te = s_off[lo + 1] - base;
-            int rk = s_carry[lo];
-            for (int w2 = 0; w2 < wv; w2++) rk += __popcll(s_stay[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
-            rk += __popcll(mk & lane_range(tb - 64 * wv, lane));
-            const int64_t dst = (int64_t)s_noff[lo] + rk;
-            if (dst < np) perm[dst] = (uint32_t)j;
-        }
-        __syncthreads();
-        if (tid < ntl) {
-            const int tb = s_off[tid] - base, te = s_off[tid + 1] - base;
-            int c = 0;
+            __syncthreads();
+            if (tid < ntl) {
+                const int tb = R[tid] - base, te = R[tid + 1] - base;
+                int c = 0;
 #pragma unroll
-            for (int w2 = 0; w2 < BLK / 64; w2++) c += __popcll(s_stay[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
-            s_carry[tid] += c;
-        }
-        par ^= 1;
-    }
-}
-
-// the arrivals: one thread per tet walking its sorted spill records
-__global__ void k_place_arrivals(int32_t nt, const int32_t *__restrict__ nstay, const int32_t *__restrict__ soff,
-                                 const uint32_t *__restrict__ srec, int64_t nrec, const int32_t *__restrict__ pid,
-                                 int64_t cap, const int32_t *__restrict__ noff, int64_t np,
-                                 uint32_t *__restrict__ perm, unsigned long long *__restrict__ err)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    const int32_t end = noff[t + 1];
-    int32_t p = noff[t] + nstay[t];
-    if (nrec > 0)
-        for (int32_t k = soff[t], hi = soff[t + 1]; k < hi; k++) {
-            const uint32_t v = srec[k];
-            if (v & SREC_LAST) {
-                if (p < end && p < np) perm[p] = (uint32_t)pid[min((int64_t)(v & ~SREC_LAST), cap - 1)];
-                p++;
+                for (int w2 = 0; w2 < BLK / 64; w2++) c += __popcll(s_mask[par][w2] & lane_range(tb - 64 * w2, te - 64 * w2));
+                s_carry[tid] += c;
             }
+            par ^= 1;
         }
-    if (p != end || end > np) *err = 1;  // cannot happen while the counts hold
+    };
+    pass(s_off, [&](int j) { return moved[j] == 0; }, [&](int j) { return (uint32_t)j; });
+    if (nrec > 0)
+        pass(s_soff, [&](int k) { return (srec[k] & SREC_LAST) != 0; },
+             [&](int k) { return (uint32_t)pid[min((int64_t)(srec[k] & ~SREC_LAST), pool_cap - 1)]; });
+    // every tet's bucket is full (the carries were last updated by these threads)
+    if (tid < ntl && s_carry[tid] != s_noff[tid + 1] - s_noff[tid]) *err = 1;
+    if (blockIdx.x == 0 && tid == 0 && noff[nt] > np) *err = 1;
 }
 
 __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx, int64_t n,
@@ -2022,18 +2016,14 @@ hipError_t launch_spill_reduce(int n1l, int32_t nt, const int32_t *soff, const u
 }
 
 hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off, const uint8_t *moved,
-                        const int32_t *nstay, const int32_t *soff, const uint32_t *srec, int64_t nrec,
-                        const int32_t *pid, int64_t cap, const int32_t *noff, uint32_t *perm,
-                        unsigned long long *err, hipStream_t s)
+                        const int32_t *soff, const uint32_t *srec, int64_t nrec, const int32_t *pid, int64_t cap,
+                        const int32_t *noff, uint32_t *perm, unsigned long long *err, hipStream_t s)
 {
     if (tpw < 1 || tpw > PLACE_TPW_MAX) return hipErrorInvalidValue;
     if (cap < 1) nrec = 0;
-    if (nt > 0) {
-        hipLaunchKernelGGL(k_place_stayers, dim3((unsigned)((nt + tpw - 1) / tpw)), dim3(BLK), 0, s, nt, tpw, off,
-                           noff, moved, np, perm);
-        hipLaunchKernelGGL(k_place_arrivals, dim3(nblk(nt)), dim3(BLK), 0, s, nt, nstay, soff, srec, nrec, pid, cap,
-                           noff, np, perm, err);
-    }
+    if (nt > 0)
+        hipLaunchKernelGGL(k_place, dim3((unsigned)((nt + tpw - 1) / tpw)), dim3(BLK), 0, s, nt, tpw, off, noff,
+                           moved, soff, srec, nrec, pid, cap, np, perm, err);
     return hipGetLastError();
 }
 

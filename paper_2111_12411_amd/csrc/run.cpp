@@ -406,7 +406,7 @@ void Run::next_order(int64_t nrec, const uint32_t *srec)
                                 (uint32_t *)d_noff.p + m.nt, stream));
     next_perm = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
     HIPCHECK(launch_place(np, (int32_t)m.nt, tpw(), (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
-                          (const int32_t *)d_nstay.p, (const int32_t *)d_soff.p, srec, nrec,
+                          (const int32_t *)d_soff.p, srec, nrec,
                           (const int32_t *)d_pool_pid.p, pool_cap, (const int32_t *)d_noff.p, next_perm,
                           (unsigned long long *)d_perr.p, stream));
 }
