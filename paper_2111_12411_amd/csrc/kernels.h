@@ -107,11 +107,9 @@ int64_t scan_tmp_entries(int64_t n);
 // for n (the same holds for the dn arguments below)
 hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, int *result_buf, hipStream_t s,
                       const uint32_t *key_in = nullptr, const int32_t *dn = nullptr);
-hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s);
 // out[i] = in[perm[i]] for every particle array
 hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
                           hipStream_t s);
-hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s);
 // bucket offsets off[t] = first index with key >= t, for t in [0, nt]
 hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s,
                           const int32_t *dn = nullptr);

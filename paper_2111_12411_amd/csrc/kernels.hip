@@ -1320,18 +1320,6 @@ __global__ void k_offsets(const uint32_t *__restrict__ key, int64_t n, int32_t n
         for (int64_t t = k + 1; t <= nt; t++) off[t] = (int32_t)n;
 }
 
-__global__ void k_iota(uint32_t *v, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v[i] = (uint32_t)i;
-}
-
-__global__ void k_copy_keys(const int32_t *__restrict__ t, uint32_t *__restrict__ k, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) k[i] = (uint32_t)t[i];
-}
-
 // ------------------------------------------------------------- spills
 __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t *__restrict__ ptag, int64_t nrec,
                                 const uint32_t *__restrict__ pos, uint32_t *__restrict__ key, uint32_t *__restrict__ val,
@@ -1925,20 +1913,6 @@ hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const u
     if (n == 0) return hipSuccess;
     if (mixed) hipLaunchKernelGGL(k_permute<float>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
     else hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_iota(uint32_t *v, int64_t n, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(BLK), 0, s, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_keys(const int32_t *tet, uint32_t *key, int64_t n, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_keys, dim3(nblk(n)), dim3(BLK), 0, s, tet, key, n);
     return hipGetLastError();
 }
 
