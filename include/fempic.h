@@ -129,12 +129,18 @@ int32_t fempic_run_destroy(fempic_run run);
 int32_t fempic_particles_load(fempic_run run, const double *pos, const double *vel, int64_t n, double q, double m,
                               double w);
 
-/* Advance n_steps PIC steps (Sec. III, PIC cycle; Sec. III-B), asynchronously
- * on the run's stream.  Per step: sort particles by tet; gather E, B at r^n;
- * AB4 push along the quartic path; track across tets (PEC walls reflect);
- * deposit g^{n+1} - g^n with the exact path integral of the W1 basis; solve
- * A (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - (g^{n+1} - g^n),
- * A = *eps + dt^2/4 K^T *nu K, by Jacobi-PCG; b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}). */
+/* Advance n_steps PIC steps (Sec. III, PIC cycle; Sec. III-B) on the run's
+ * stream.  Per step: particles in tet order (a sort after load; each step then
+ * orders them for the next from its own exit queue and spill records); gather
+ * E, B at r^n; AB4 push along the quartic path; track across tets (PEC walls
+ * reflect); deposit g^{n+1} - g^n with the exact path integral of the W1 basis;
+ * solve A (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - (g^{n+1} - g^n),
+ * A = *eps + dt^2/4 K^T *nu K, by PCG (Jacobi, or 2x2 block Jacobi at order 2;
+ * FP32 PCG inside FP64 refinement in mixed precision);
+ * b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}).  The call waits on the device once per
+ * particle phase (queue and spill counts, error flags) and every 8 PCG
+ * iterations; the last step's final field updates may still be queued when it
+ * returns (fempic_sync waits for them). */
 int32_t fempic_step(fempic_run run, int32_t n_steps);
 
 /* Wait for the run's queued work; reports sticky device failures. */
@@ -167,7 +173,7 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
 typedef struct {
     int64_t steps;            /* steps taken by this run */
     int64_t n_particles;
-    double particle_ms;       /* last call: device time of sort + particle + deposit reduction, ms */
+    double particle_ms;       /* last call: device time of ordering + particle + deposit reduction, ms */
     double particle_kernel_ms;/* last call: device time of the particle kernel (gather, push, first segment), ms */
     double continue_kernel_ms;/* last call: device time of the kernel that tracks paths leaving their tet, ms */
     double field_ms;          /* last call: device time of the field update, ms */
