@@ -229,7 +229,10 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "kernel": "k_particle<2,float>", "kernel_ms": kms / K,
-                     "alg_bytes_per_launch": alg, "state_bytes": state_b, "per_tet_bytes": tet_b},
+                     "alg_bytes_per_launch": alg, "state_bytes": state_b, "per_tet_bytes": tet_b,
+                     # the whole particle phase (a1-a6, all its kernels and host waits) against the
+                     # same algorithmic bytes per step
+                     "phase_frac": alg / (pms / K / 1e3) / 1e9 / HBM_PEAK_GBS},
     }
     mix["run"].close()
     if not args.no_fp64:
