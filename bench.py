@@ -59,9 +59,9 @@ def profiled_traffic():
     return float(m1.group(1)) if h.hexdigest() == m2.group(1) else None
 
 
-def run_workload(cfg_id, precision, steps, warmup, n=None):
+def run_workload(cfg_id, precision, steps, warmup, n=None, order=None):
     cfg = W.CONFIGS[cfg_id]
-    N, k = cfg["N"], cfg["order"]
+    N, k = cfg["N"], (cfg["order"] if order is None else order)
     mesh = F.Mesh.cube(N, k)
     info = mesh.info()
     dt = cfg["cfl"] * info["dt_cfl"]
@@ -170,7 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--particles", type=int, default=None, help="override the particle count (testing)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="only the mixed order-2 run (no FP64 or order-1 comparison runs)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration for profiles)")
@@ -248,6 +249,18 @@ def main():
                        "R_G": f64["gauss"][0],
                        "roofline_frac": alg2 / (s2["particle_kernel_ms"] / k2 / 1e3) / 1e9 / HBM_PEAK_GBS}
         f64["run"].close()
+    if not args.no_fp64:
+        # the same workload with order-1 bases, mixed and FP64
+        out["order1"] = {}
+        for name, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
+            r1 = run_workload(3, prec, K, args.warmup, n=args.particles, order=1)
+            s1 = r1["stats"]
+            alg1, _, _ = algorithmic_bytes(1, prec, r1["n"], r1["info"]["n_tet"])
+            out["order1"][name] = {"value": r1["n"] * K / (s1["particle_ms"] / 1e3), "unit": "particle-steps/s",
+                                   "particle_ms_per_step": s1["particle_ms"] / K,
+                                   "ms_per_step": r1["wall"] * 1e3 / K, "R_G": r1["gauss"][0],
+                                   "roofline_frac": alg1 / (s1["particle_kernel_ms"] / K / 1e3) / 1e9 / HBM_PEAK_GBS}
+            r1["run"].close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, 2)
     print(json.dumps(out))
