@@ -259,6 +259,7 @@ def main():
             out["order1"][name] = {"value": r1["n"] * K / (s1["particle_ms"] / 1e3), "unit": "particle-steps/s",
                                    "particle_ms_per_step": s1["particle_ms"] / K,
                                    "ms_per_step": r1["wall"] * 1e3 / K, "R_G": r1["gauss"][0],
+                                   "crossings_per_particle_step": s1["crossings"] / r1["n"],
                                    "roofline_frac": alg1 / (s1["particle_kernel_ms"] / K / 1e3) / 1e9 / HBM_PEAK_GBS}
             r1["run"].close()
     if not args.no_cpu:
