@@ -133,6 +133,7 @@ struct ParticleArgs {
     ContQueue cq;
     unsigned long long *cnt;  // Counters
     unsigned long long *cntb; // [CONT_BLOCKS][4] per-block counters of the continuation kernel
+    unsigned long long *perr; // [1] particle-order error flag (launch_place)
 };
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
 // fills cq.idx and *cq.count from cq.flag; tmp: device scratch of at least

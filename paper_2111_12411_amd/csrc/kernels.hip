@@ -761,6 +761,12 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
     for (int k = tid; k < ntl * 16; k += PBLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
     for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
     for (int k = tid; k < TM; k += PBLK) s_nstay[k] = 0;
+    // the step's counters, which later kernels of the step accumulate into
+    if (blockIdx.x == 0 && tid < 4) glb(A->cnt)[tid] = 0ull;
+    if (blockIdx.x == 0 && tid == 0) {
+        *glb(A->pool.count) = 0;
+        *glb(A->perr) = 0ull;
+    }
     for (int k = tid; k < ntl * N1; k += PBLK) {
         int t = k / N1, i = k % N1;
         s_e[t][i] = e[m.map1[(int64_t)(T0 + t) * N1 + i]];

@@ -257,12 +257,13 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_noff.alloc((size_t)(m.nt + 1) * 4);
     d_tcnt.alloc((size_t)std::max<int64_t>(m.nt, 1) * 4);
     d_nstay.alloc((size_t)std::max<int64_t>(m.nt, 1) * 4);
-    d_perr.alloc(8);
-    zero(d_perr);
     d_soff.alloc((size_t)(m.nt + 1) * 4);
-    d_cnt.alloc(8 * 8);
+    d_ctl.alloc(128);
+    zero(d_ctl);
+    p_cnt = (unsigned long long *)d_ctl.p;
+    p_small = (int32_t *)((char *)d_ctl.p + 32);
+    p_perr = (unsigned long long *)((char *)d_ctl.p + 64);
     d_cntb.alloc((size_t)CONT_BLOCKS * 4 * 8);
-    d_small.alloc(64);
     HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
     d_args.alloc(sizeof(ParticleArgs));
     for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
@@ -371,7 +372,7 @@ SpillPool Run::pool() const
     sp.tet = (int32_t *)d_pool_tet.p;
     sp.tag = (int64_t *)d_pool_tag.p;
     sp.pid = (int32_t *)d_pool_pid.p;
-    sp.count = (int32_t *)d_small.p;
+    sp.count = p_small;
     sp.rcount = (int32_t *)d_rcount.p;
     sp.cap = pool_cap;
     return sp;
@@ -408,7 +409,7 @@ void Run::next_order(int64_t nrec, const uint32_t *srec)
     HIPCHECK(launch_place(np, (int32_t)m.nt, tpw(), (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
                           (const int32_t *)d_soff.p, srec, nrec,
                           (const int32_t *)d_pool_pid.p, pool_cap, (const int32_t *)d_noff.p, next_perm,
-                          (unsigned long long *)d_perr.p, stream));
+                          p_perr, stream));
 }
 
 void Run::commit_order()
@@ -444,11 +445,11 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     // locate
     std::vector<int32_t> tets;
     if (m.is_cube) {
-        zero(d_small);
-        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.x.p, (int32_t *)B.tet.p, (int32_t *)d_small.p,
+        HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
+        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.x.p, (int32_t *)B.tet.p, p_small,
                                     stream));
         int32_t err = 0;
-        HIPCHECK(hipMemcpyAsync(&err, d_small.p, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(&err, p_small, 4, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         if (err & ERR_OUTSIDE) throw Error(FEMPIC_EOUTSIDE, "a particle lies outside the mesh");
     } else {
@@ -558,12 +559,10 @@ void Run::particle_phase()
     int64_t nq_ub = counts_known ? std::min<int64_t>(np, grow(nq_last)) : np;
     int64_t nslot_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nslot_last)) : pool_cap;
     int64_t nrec_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nrec_last)) : pool_cap;
-    const int32_t *d_nq = (const int32_t *)d_small.p + 6, *d_nrec = (const int32_t *)d_small.p + 2;
+    const int32_t *d_nq = p_small + 6, *d_nrec = p_small + 2;
     for (int attempt = 0;; attempt++) {
         if (attempt == 6) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
-        zero(d_small);
-        zero(d_cnt);
-        zero(d_perr);
+        // (k_particle clears the counters, the spill pool's append count and the order error flag)
         ParticleArgs *ha = (ParticleArgs *)((char *)h_pin + 128);
         ha->m = dm;
         ha->e = mixed ? (const void *)d_e32.p : (const void *)d_e.p;
@@ -577,9 +576,10 @@ void Run::particle_phase()
         ha->gl = gl;
         ha->P = (double *)d_P.p;
         ha->pool = pool();
-        ha->cq = ContQueue{(ContRec *)d_cq.p, (uint8_t *)d_qflag.p, (int32_t *)d_qidx.p, (int32_t *)d_small.p + 6,
+        ha->cq = ContQueue{(ContRec *)d_cq.p, (uint8_t *)d_qflag.p, (int32_t *)d_qidx.p, p_small + 6,
                            (uint8_t *)d_moved.p, (int32_t *)d_nstay.p};
-        ha->cnt = (unsigned long long *)d_cnt.p;
+        ha->cnt = p_cnt;
+        ha->perr = p_perr;
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipEventRecord(ev_b, stream));
@@ -588,12 +588,12 @@ void Run::particle_phase()
         // compact the queue written by k_particle, then continue the queued paths
         HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
         HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, counts_known ? nq_last : np / 8,
-                                 (unsigned long long *)d_cntb.p, (unsigned long long *)d_cnt.p, stream));
+                                 (unsigned long long *)d_cntb.p, p_cnt, stream));
         HIPCHECK(hipEventRecord(ev_c, stream));
         // deterministic reduction of the spill pool: records in canonical order
         // (queued record, then segment), sorted by tet, summed per tet
         HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_ub, psort.scan_tmp,
-                                    (uint32_t *)d_small.p + 2, stream, d_nq));
+                                    (uint32_t *)(p_small + 2), stream, d_nq));
         HIPCHECK(launch_spill_compact(pool(), nslot_ub, d_nq, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
                                       ssort.cap, stream));
         int res = 0;
@@ -607,9 +607,7 @@ void Run::particle_phase()
                                 (const double *)d_P.p, (double *)d_dg.p, stream));
         next_order(nrec_ub, srec);
         HIPCHECK(hipEventRecord(ev_d, stream));
-        HIPCHECK(hipMemcpyAsync(h_pin, d_cnt.p, 32, hipMemcpyDeviceToHost, stream));
-        HIPCHECK(hipMemcpyAsync((char *)h_pin + 32, d_small.p, 32, hipMemcpyDeviceToHost, stream));
-        HIPCHECK(hipMemcpyAsync((char *)h_pin + 64, d_perr.p, 8, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(h_pin, d_ctl.p, 72, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         const unsigned long long *c = (const unsigned long long *)h_pin;
         const int32_t *sm = (const int32_t *)((char *)h_pin + 32);

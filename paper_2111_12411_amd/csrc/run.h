@@ -96,11 +96,16 @@ class Run {
     DevBuf v_x, v_r, v_z, v_p, v_q, v_rhs, v_tmp, v_u;
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
-    DevBuf d_P, d_Pr, d_off, d_soff, d_cnt, d_cntb, d_small, d_args;
+    DevBuf d_P, d_Pr, d_off, d_soff, d_ctl, d_cntb, d_args;
+    // d_ctl holds the step's control words, read back in one copy:
+    // [0, 32) counters (int64 x 4), [32, 64) small (int32 x 8: 0 appended spill
+    // slots, 2 spill records, 6 queued paths), [64, 72) particle-order error
+    unsigned long long *p_cnt = nullptr, *p_perr = nullptr;
+    int32_t *p_small = nullptr;
     DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pool_pid, d_rcount, d_rpos, d_cq, d_qflag, d_qtmp, d_qidx;
     // particle order: cur_perm (sorted position -> slot) and d_off describe the
     // current state while perm_valid; the particle phase builds the next ones
-    DevBuf d_moved, d_nstay, d_noff, d_tcnt, d_perr;
+    DevBuf d_moved, d_nstay, d_noff, d_tcnt;
     const uint32_t *cur_perm = nullptr;
     uint32_t *next_perm = nullptr;
     bool perm_valid = false;
