@@ -110,7 +110,7 @@ def cpu_baseline(cfg, n_sample, steps):
                        "single-threaded plain C, %.1f s" % (n_sample, steps, dtm))
 
 
-def serving(n_jobs=24, slots=2, mean_gap_ms=15.0, seed=4007):
+def serving(n_jobs=24, slots=4, mean_gap_ms=15.0, seed=4007):
     """Continuous batching: n_jobs independent mixed-precision runs with Poisson
     arrivals go through fempic_submit / fempic_poll; each run's mesh, order,
     particle count and kind are drawn at random (a smaller instance of the
@@ -175,6 +175,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration for profiles)")
+    ap.add_argument("--slots", type=int, default=4, help="resident runs in --serving mode")
     ap.add_argument("--serving", action="store_true",
                     help="measure the submit/poll server on a stream of independent runs instead")
     args = ap.parse_args()
@@ -183,7 +184,7 @@ def main():
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
     if args.serving:
-        print(json.dumps(serving()))
+        print(json.dumps(serving(slots=args.slots)))
         return
     cfg = W.CONFIGS[3]
     if args.calib_copy:
