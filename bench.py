@@ -180,8 +180,8 @@ def main():
                     help="measure the submit/poll server on a stream of independent runs instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the method is built and measured on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the library runs one simulation per MI355X "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.serving:
         print(json.dumps(serving(slots=args.slots)))
