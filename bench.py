@@ -67,7 +67,7 @@ def run_workload(cfg_id, precision, steps, warmup, n=None, order=None):
     dt = cfg["cfl"] * info["dt_cfl"]
     pos, vel = W.config_particles(cfg_id, n=n)
     npart = len(pos)
-    w = W.plasma_weight(npart, dt)
+    w = W.config_weight(cfg_id, npart, dt)
     t0 = time.perf_counter()
     run = F.Run(mesh, dt, precision, pcg_rtol=1e-14)
     run.load(pos, vel, -W.Q_E, W.M_E, w)
@@ -100,7 +100,7 @@ def cpu_baseline(cfg, n_sample, steps):
     dt = cfg["cfl"] * core.cfl_dt(m4, core.assemble(m4)) * 4.0 / N
     pos, vel = W.config_particles(3, n=n_sample)
     orc = core.OracleRun(m, dt, particles_only=True)
-    orc.load(pos, vel, -W.Q_E, W.M_E, W.plasma_weight(n_sample, dt))
+    orc.load(pos, vel, -W.Q_E, W.M_E, W.config_weight(3, n_sample, dt))
     t0 = time.perf_counter()
     for _ in range(steps):
         orc.particle_step()
@@ -220,9 +220,9 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "40^3 Kuhn cube (384000 tets), order 2, %d electrons, 1%% sinusoidal density "
-                               "perturbation in x, v_th 0.02c, dt = 10 x explicit bound, PEC walls, mixed precision"
-                               % mix["n"], "order": 2, "n_tet": mix["info"]["n_tet"], "particles": mix["n"],
-                   "dt": mix["dt"]},
+                               "perturbation in x, v_th 0.02c, omega_p dt = 0.02, dt = 10 x explicit bound, PEC walls, "
+                               "mixed precision" % mix["n"], "order": 2, "n_tet": mix["info"]["n_tet"],
+                   "particles": mix["n"], "dt": mix["dt"], "omega_p_dt": W.CONFIGS[3]["omega_dt"]},
         "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2]},
         "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"]},
         "crossings_per_particle_step": st["crossings"] / mix["n"],

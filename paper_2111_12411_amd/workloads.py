@@ -19,7 +19,10 @@ M_E = 9.1093837015e-31
 CONFIGS = {
     1: dict(N=4, order=1, n=1000, kind="thermal", vth=0.01, steps=100, cfl=5.0, precision="fp64"),
     2: dict(N=20, order=2, n=1_000_000, kind="beam", vth=0.005, drift=0.1, steps=200, cfl=10.0, precision="fp64"),
-    3: dict(N=40, order=2, n=16_000_000, kind="oscillation", vth=0.02, steps=500, cfl=10.0, precision="mixed"),
+    # omega_dt: plasma frequency times dt at the mean density (the macro-particle
+    # weight); 0.02 puts the Debye length at about 1.2 cells on this mesh
+    3: dict(N=40, order=2, n=16_000_000, kind="oscillation", vth=0.02, steps=500, cfl=10.0, precision="mixed",
+            omega_dt=0.02),
     5: dict(N=56, order=2, n=64_000_000, kind="two_stream", vth=0.01, drift=0.2, steps=1000, cfl=10.0,
             precision="mixed"),
 }
@@ -81,6 +84,11 @@ def plasma_weight(n, dt, L=1.0, omega_dt=0.1):
     density satisfies omega_p dt = omega_dt (omega_p^2 = n_e e^2 / (eps0 m_e))."""
     vol = L ** 3
     return (omega_dt / dt) ** 2 * EPS0 * M_E * vol / (n * Q_E ** 2)
+
+
+def config_weight(cfg_id, n, dt, L=1.0):
+    """Macro-particle weight of a configuration: plasma_weight at its omega_dt (0.1 unless set)."""
+    return plasma_weight(n, dt, L, CONFIGS[cfg_id].get("omega_dt", 0.1))
 
 
 def config_particles(cfg_id, n=None, seed=None, L=1.0):

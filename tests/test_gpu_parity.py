@@ -168,7 +168,7 @@ def test_full_size_sampled(precision, tol_x, tol_v):
     e0, b0 = W.random_fields(m.n1, m.n2, 303, e_scale=1e3, b_scale=1e-5)
     e0 = e0 * m.int1
     run = F.Run(F.Mesh.cube(N, k), dt, precision, pcg_rtol=1e-14)
-    run.load(pos, vel, QE, ME, W.plasma_weight(n, dt))
+    run.load(pos, vel, QE, ME, W.config_weight(3, n, dt))
     run.set_fields(e0, b0)
     run.step()
     pos_g, vel_g, tet_g = run.particles()
