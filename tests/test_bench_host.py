@@ -1,0 +1,72 @@
+"""CPU checks of bench.py's host logic: the byte model behind the roofline figures, the guard
+that ties the profiled traffic to the kernel sources, the workloads' plasma weights, and the
+one-GPU rule (no GPU needed)."""
+import hashlib
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+import paper_2111_12411_amd as F
+from paper_2111_12411_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_algorithmic_bytes_per_particle_and_tet():
+    # state: r, v in FP64 (48 B), three v and three a histories (18 values), tet (4 B)
+    alg, state, tet = bench.algorithmic_bytes(2, F.MIXED, 1, 0)
+    assert state == 48 + 18 * 4 + 4 == 124 and alg == 2 * 124
+    alg, state, tet = bench.algorithmic_bytes(2, F.FP64, 1, 0)
+    assert state == 48 + 18 * 8 + 4 == 196 and alg == 2 * 196
+    # per tet: geometry (16 doubles), 20 W1 + 15 W2 coefficients with their int32 maps, 20 FP64 partials
+    _, _, tet = bench.algorithmic_bytes(2, F.MIXED, 0, 1)
+    assert tet == 128 + 35 * (4 + 4) + 20 * 8 == 568
+    _, _, tet = bench.algorithmic_bytes(1, F.FP64, 0, 1)
+    assert tet == 128 + 10 * (8 + 4) + 6 * 8
+    # the benchmark launch: 16M particles, 384 000 tets
+    alg, _, _ = bench.algorithmic_bytes(2, F.MIXED, 16_000_000, 384_000)
+    assert alg == 4_186_112_000
+
+
+def _profile_copy(tmp_path, digest):
+    root = tmp_path / "repo"
+    (root / "profiles").mkdir(parents=True)
+    (root / "paper_2111_12411_amd" / "csrc").mkdir(parents=True)
+    for f in ("kernels.hip", "kernels.h"):
+        shutil.copy(os.path.join(ROOT, "paper_2111_12411_amd", "csrc", f), root / "paper_2111_12411_amd" / "csrc" / f)
+    (root / "profiles" / "k_particle_c3_mixed_hbm_counters.md").write_text(
+        "```\ntraffic_bytes_per_launch: 7.5e+09\nkernel_source_sha256: %s\n```\n" % digest)
+    return root
+
+
+def test_profiled_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2111_12411_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    monkeypatch.setattr(bench, "ROOT", str(_profile_copy(tmp_path / "a", h.hexdigest())))
+    assert bench.profiled_traffic() == 7.5e9
+    monkeypatch.setattr(bench, "ROOT", str(_profile_copy(tmp_path / "b", "0" * 64)))
+    assert bench.profiled_traffic() is None
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path / "missing"))
+    assert bench.profiled_traffic() is None
+
+
+@pytest.mark.parametrize("cfg_id,omega_dt", [(1, 0.1), (2, 0.1), (3, 0.02), (5, 0.1)])
+def test_config_weight_gives_the_plasma_frequency(cfg_id, omega_dt):
+    n, dt = 1000, 2.5e-10
+    w = W.config_weight(cfg_id, n, dt)
+    # omega_p^2 = n_e e^2 / (eps0 m_e), with n_e = n w / L^3 electrons per m^3 on the unit cube
+    omega_p = np.sqrt(n * w * W.Q_E ** 2 / (W.EPS0 * W.M_E))
+    assert abs(omega_p * dt - omega_dt) < 1e-12 * omega_dt
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
