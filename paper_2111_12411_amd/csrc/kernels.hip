@@ -1517,6 +1517,13 @@ __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__re
 // order, and k_finish sums the (at most RED_BLOCKS) block partials in order.
 constexpr int RED_BLOCKS = 2048;
 
+// blocks (2x2 SpMV) or entries (CSR SpMV) per lane whose loads are issued together
+constexpr int BSPMV_U = 2;
+
+// y = alpha A x + beta z (CSR), LANES lanes per row; optional fused partial
+// dot(dotv, y) per workgroup (fixed order).  Loads are grouped as in k_bspmv:
+// each lane takes its entries k = start + lane, start + lane + LANES, ... in
+// that order, BSPMV_U of them requested together.
 template <int LANES, typename T>
 __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__restrict__ ptr,
                                               const int32_t *__restrict__ idx, const T *__restrict__ val,
@@ -1526,22 +1533,55 @@ __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__res
 {
     __shared__ double s_red[BLK / LANES];
     constexpr int RPB = BLK / LANES;
+    constexpr int U = BSPMV_U;
     const int tid = threadIdx.x;
     const int lane = tid % LANES;
+    const int64_t stride = (int64_t)gridDim.x * RPB;
     double d = 0.0;
-    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < rows; row0 += (int64_t)gridDim.x * RPB) {
-        const int64_t row = row0 + tid / LANES;
+    int64_t row = (int64_t)blockIdx.x * RPB + tid / LANES;
+    int64_t kb = 0, ke = 0;
+    if (row < rows) {
+        kb = ptr[row];
+        ke = ptr[row + 1];
+    }
+    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < rows; row0 += stride, row += stride) {
+        const int64_t e = ke;
+        int64_t k0 = kb + lane;
+        if (row + stride < rows) {
+            kb = ptr[row + stride];
+            ke = ptr[row + stride + 1];
+        }
+        const bool wr = row < rows && lane == 0;
+        T z0 = 0, w0 = 0;
+        if (wr && beta != 0.0) z0 = z[row];
+        if (wr && dotv) w0 = dotv[row];
         double sum = 0.0;
         if (row < rows) {
-            const int64_t e = ptr[row + 1];
-            for (int64_t k = ptr[row] + lane; k < e; k += LANES) sum += (double)val[k] * (double)x[idx[k]];
+            for (; k0 < e; k0 += U * LANES) {
+                // lanes past the row's end load its last entry again and do not add it
+                int32_t c[U];
+                T v[U], xv[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) c[u] = idx[min(k0 + u * LANES, e - 1)];
+#pragma unroll
+                for (int u = 0; u < U; u++) v[u] = val[min(k0 + u * LANES, e - 1)];
+#pragma unroll
+                for (int u = 0; u < U; u++) xv[u] = x[c[u]];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const double t = fma((double)v[u], (double)xv[u], sum);
+                    sum = k0 + u * LANES < e ? t : sum;
+                }
+            }
         }
 #pragma unroll
         for (int o = LANES / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LANES);
-        if (row < rows && lane == 0) {
-            const double yv = alpha * sum + (beta != 0.0 ? beta * (double)z[row] : 0.0);
+        if (wr) {
+            // keeps the conversions of z0 and w0 (and the wait for them) here
+            asm volatile("" : "+v"(z0), "+v"(w0));
+            const double yv = alpha * sum + (beta != 0.0 ? beta * (double)z0 : 0.0);
             y[row] = (T)yv;
-            if (dotv) d += (double)dotv[row] * (double)(T)yv;
+            if (dotv) d += (double)w0 * (double)(T)yv;
         }
     }
     if (partial) {
@@ -1557,7 +1597,12 @@ __global__ __launch_bounds__(BLK) void k_spmv(int64_t rows, const int64_t *__res
 
 // y = alpha A x + beta z with A in 2x2 blocks: LANES lanes per block row, a
 // block's four values and the two x entries it needs are loaded as vectors;
-// optional fused partial dot(dotv, y) per workgroup (fixed order)
+// optional fused partial dot(dotv, y) per workgroup (fixed order).  Rows go to
+// the blocks in a grid stride, so at any time the GPU works on one compact
+// window of rows and the x entries it references stay in every XCD's L2.
+// Each lane takes its blocks k = start + lane, start + lane + LANES, ... in
+// that order; BSPMV_U of them are requested together (indices, then values,
+// then x entries), and the next row's bounds are read one row ahead.
 template <int LANES, typename T>
 __global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__restrict__ bptr,
                                                const int32_t *__restrict__ bidx, const T *__restrict__ bval,
@@ -1567,20 +1612,64 @@ __global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__r
 {
     __shared__ double s_red[BLK / LANES];
     constexpr int RPB = BLK / LANES;
+    constexpr int U = BSPMV_U;
     const int tid = threadIdx.x;
     const int lane = tid % LANES;
+    const int64_t stride = (int64_t)gridDim.x * RPB;
     double d = 0.0;
-    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < brows; row0 += (int64_t)gridDim.x * RPB) {
-        const int64_t br = row0 + tid / LANES;
+    int64_t br = (int64_t)blockIdx.x * RPB + tid / LANES;
+    int64_t kb = 0, ke = 0;
+    if (br < brows) {
+        kb = bptr[br];
+        ke = bptr[br + 1];
+    }
+    for (int64_t row0 = (int64_t)blockIdx.x * RPB; row0 < brows; row0 += stride, br += stride) {
+        const int64_t e = ke;
+        int64_t k0 = kb + lane;
+        if (br + stride < brows) {
+            kb = bptr[br + stride];
+            ke = bptr[br + stride + 1];
+        }
+        // the row's z and dotv entries, requested before its products
+        const bool wr = br < brows && lane == 0;
+        T z0 = 0, z1 = 0, w0 = 0, w1 = 0;
+        if (wr && beta != 0.0) {
+            z0 = z[2 * br];
+            z1 = z[2 * br + 1];
+        }
+        if (wr && dotv) {
+            w0 = dotv[2 * br];
+            w1 = dotv[2 * br + 1];
+        }
         double s0 = 0.0, s1 = 0.0;
         if (br < brows) {
-            const int64_t e = bptr[br + 1];
-            for (int64_t k = bptr[br] + lane; k < e; k += LANES) {
-                const int64_t c = 2 * (int64_t)bidx[k];
-                const T *v = bval + 4 * k;
-                const double x0 = (double)x[c], x1 = (double)x[c + 1];
-                s0 = fma((double)v[0], x0, fma((double)v[1], x1, s0));
-                s1 = fma((double)v[2], x0, fma((double)v[3], x1, s1));
+            for (; k0 < e; k0 += U * LANES) {
+                // lanes past the row's end load its last block again (in
+                // bounds, same lines) and do not add it
+                int64_t c[U];
+                T v[U][4], xv[U][2];
+#pragma unroll
+                for (int u = 0; u < U; u++) c[u] = 2 * (int64_t)bidx[min(k0 + u * LANES, e - 1)];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const int64_t k = min(k0 + u * LANES, e - 1);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) v[u][j] = bval[4 * k + j];
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    xv[u][0] = x[c[u]];
+                    xv[u][1] = x[c[u] + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const bool in = k0 + u * LANES < e;
+                    const double x0 = (double)xv[u][0], x1 = (double)xv[u][1];
+                    const double t0 = fma((double)v[u][0], x0, fma((double)v[u][1], x1, s0));
+                    const double t1 = fma((double)v[u][2], x0, fma((double)v[u][3], x1, s1));
+                    s0 = in ? t0 : s0;
+                    s1 = in ? t1 : s1;
+                }
             }
         }
 #pragma unroll
@@ -1588,12 +1677,15 @@ __global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__r
             s0 += __shfl_xor(s0, o, LANES);
             s1 += __shfl_xor(s1, o, LANES);
         }
-        if (br < brows && lane == 0) {
-            const double y0 = alpha * s0 + (beta != 0.0 ? beta * (double)z[2 * br] : 0.0);
-            const double y1 = alpha * s1 + (beta != 0.0 ? beta * (double)z[2 * br + 1] : 0.0);
+        if (wr) {
+            // an empty statement that takes the four values here, so that their
+            // conversions (and the wait for their loads) are not moved up
+            asm volatile("" : "+v"(z0), "+v"(z1), "+v"(w0), "+v"(w1));
+            const double y0 = alpha * s0 + (beta != 0.0 ? beta * (double)z0 : 0.0);
+            const double y1 = alpha * s1 + (beta != 0.0 ? beta * (double)z1 : 0.0);
             y[2 * br] = (T)y0;
             y[2 * br + 1] = (T)y1;
-            if (dotv) d += (double)dotv[2 * br] * (double)(T)y0 + (double)dotv[2 * br + 1] * (double)(T)y1;
+            if (dotv) d += (double)w0 * (double)(T)y0 + (double)w1 * (double)(T)y1;
         }
     }
     if (partial) {
