@@ -116,6 +116,10 @@ typedef struct {
     int32_t pcg_maxit;   /* e.g. 5000 */
     int32_t particle_bc; /* FEMPIC_REFLECT */
     int32_t spill_slots; /* reserved, ignored */
+    int32_t gauss_every; /* 0: off; k > 0: fempic_step evaluates the Gauss-law
+                            residuals (fempic_gauss_residual) after every step
+                            whose count is a multiple of k, into
+                            fempic_stats_t.gauss (one device wait each) */
 } fempic_params;
 
 int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out);
@@ -169,6 +173,40 @@ int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *
 /* Full AB4 history in load order: vh, ah are [n][3][3] = v^{n-1..n-3}, a^{n-1..n-3}. */
 int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
 
+/* ------------------------------------------------------------- checkpoint
+ * fempic_run_save writes the run's state to the file at `path` (created or
+ * replaced): the particles, with their AB4 velocity and acceleration histories
+ * in the run's storage precision and in the order the next step takes them;
+ * e, b, the accumulated current moments and the reference charge of the
+ * Gauss-law check; the species and the step counter.  Synchronises; the run
+ * itself is unchanged.
+ * fempic_run_load reads such a file into a run created on the same mesh (same
+ * sizes and order) with the same precision and dt, replacing its particles and
+ * fields and clearing a sticky failure.  The steps a run takes after the load
+ * equal, bit for bit, those the saved run takes after the save.
+ * EINVAL: null path; a file that cannot be opened, read or written; a file of
+ * another mesh, precision or dt; a damaged file (checksum, particle ids, tets
+ * outside the mesh, non-finite positions or velocities).  The format is this
+ * library's own, in native byte order. */
+int32_t fempic_run_save(fempic_run run, const char *path);
+int32_t fempic_run_load(fempic_run run, const char *path);
+
+/* -------------------------------------------------------------- allocator
+ * Routes the device buffers that runs and servers make from now on through
+ * the caller's allocator (a framework's caching allocator, say):
+ * alloc(bytes, ctx) returns memory of the current HIP device, at least `bytes`
+ * long and 256-byte aligned, or NULL (the call that needed it fails with
+ * ENOMEM); release(ptr, ctx) takes it back.  The library synchronises the
+ * device before each release, so no queued work uses the memory when the
+ * caller gets it back.  A buffer keeps the allocator that made it, so the two
+ * functions and ctx must stay valid while any of their buffers exists.  They
+ * may be called on any thread the library runs on (a server steps its runs on
+ * threads of its own).  Both NULL restores hipMalloc/hipFree; one NULL is
+ * EINVAL.  Process-wide; pinned host staging memory is not affected. */
+typedef void *(*fempic_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fempic_free_fn)(void *ptr, void *ctx);
+int32_t fempic_set_allocator(fempic_alloc_fn alloc, fempic_free_fn release, void *ctx);
+
 /* Per-run statistics of the last fempic_step call. */
 typedef struct {
     int64_t steps;            /* steps taken by this run */
@@ -182,6 +220,8 @@ typedef struct {
     int64_t crossings;        /* last step: face crossings (all particles) */
     int64_t reflections;      /* last step: wall reflections */
     int64_t spills;           /* last step: segments outside the particle's tet */
+    double gauss[3];          /* R_G, R_C, R_S at step gauss_step (params.gauss_every) */
+    int64_t gauss_step;       /* step count of that evaluation; 0: none yet */
 } fempic_stats_t;
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
 

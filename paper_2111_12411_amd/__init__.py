@@ -33,14 +33,14 @@ class MeshInfo(C.Structure):
 class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dt", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32), ("particle_bc", C.c_int32),
-                ("spill_slots", C.c_int32)]
+                ("spill_slots", C.c_int32), ("gauss_every", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("n_particles", C.c_int64), ("particle_ms", C.c_double),
                 ("particle_kernel_ms", C.c_double), ("continue_kernel_ms", C.c_double), ("field_ms", C.c_double), ("pcg_iters", C.c_int32),
                 ("pcg_relres", C.c_double), ("crossings", C.c_int64), ("reflections", C.c_int64),
-                ("spills", C.c_int64)]
+                ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -78,6 +78,9 @@ SYMBOLS = {
     "fempic_deposit_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_particles_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_history_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "fempic_run_save": (C.c_int32, [C.c_void_p, C.c_char_p]),
+    "fempic_run_load": (C.c_int32, [C.c_void_p, C.c_char_p]),
+    "fempic_set_allocator": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fempic_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_footprint": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
     "fempic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -150,18 +153,61 @@ class Mesh:
             self.h = None
 
 
-def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000):
-    return Params(precision, dt, 0.5, 0.25, pcg_rtol, pcg_maxit, 0, 0)
+def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, gauss_every=0):
+    return Params(precision, dt, 0.5, 0.25, pcg_rtol, pcg_maxit, 0, 0, gauss_every)
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# every callback pair ever installed: buffers made through a pair keep using it
+_allocators = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Make the library's device buffers through alloc(nbytes) -> address and
+    free(address) from now on (fempic_set_allocator); no arguments restores
+    hipMalloc/hipFree."""
+    if alloc is None and free is None:
+        _check(lib().fempic_set_allocator(None, None, None))
+        return
+    if alloc is None or free is None:
+        raise ValueError("set_allocator needs both functions, or neither")
+    a = ALLOC_FN(lambda n, ctx: alloc(n) or None)
+    f = FREE_FN(lambda ptr, ctx: free(ptr))
+    _allocators.append((a, f))
+    _check(lib().fempic_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+
+
+def hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    with open("/proc/self/maps") as f:
+        return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+
+
+def use_torch_allocator(device=None):
+    """Route the library's device buffers through torch's caching allocator.
+
+    torch ships its own HIP runtime.  The library shares it only when torch is
+    imported before the library is first loaded; otherwise the process holds two
+    runtimes and torch's memory must not reach the library's kernels, so this
+    raises."""
+    import torch
+    lib()
+    if len(hip_runtimes()) != 1:
+        raise RuntimeError("two HIP runtimes are loaded (%s): import torch before the library's first use"
+                           % ", ".join(hip_runtimes()))
+    dev = torch.cuda.current_device() if device is None else device
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev), torch.cuda.caching_allocator_delete)
 
 
 class Run:
     """One simulation on the current HIP device."""
 
-    def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None):
+    def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None, gauss_every=0):
         self.mesh = mesh
         self.info = mesh.info()
         self.h = C.c_void_p()
-        p = params(dt, precision, pcg_rtol, pcg_maxit)
+        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every)
         _check(lib().fempic_run_create(mesh.h, C.byref(p), stream, C.byref(self.h)))
         self.n = 0
 
@@ -211,10 +257,21 @@ class Run:
         _check(lib().fempic_history_get(self.h, _p(vh), _p(ah), self.n))
         return vh, ah
 
+    def save(self, path):
+        """Write the run's state to a checkpoint file (fempic_run_save)."""
+        _check(lib().fempic_run_save(self.h, os.fsencode(path)))
+
+    def restore(self, path):
+        """Replace the run's state with a checkpoint of a run on the same mesh (fempic_run_load)."""
+        _check(lib().fempic_run_load(self.h, os.fsencode(path)))
+        self.n = self.stats()["n_particles"]
+
     def stats(self):
         s = Stats()
         _check(lib().fempic_stats(self.h, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in Stats._fields_}
+        out = {k: getattr(s, k) for k, _ in Stats._fields_}
+        out["gauss"] = list(out["gauss"])
+        return out
 
     def close(self):
         if getattr(self, "h", None) and _lib is not None:

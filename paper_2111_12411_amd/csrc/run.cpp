@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -33,22 +34,71 @@ void set_error(const std::string &s) { g_last_error = s; }
     } while (0)
 
 // ------------------------------------------------------------ device memory
+// device allocator of new buffers: hipMalloc/hipFree, or the caller's pair
+namespace {
+std::mutex alloc_mu;
+fempic_alloc_fn alloc_fn = nullptr;
+fempic_free_fn free_fn = nullptr;
+void *alloc_ctx = nullptr;
+}  // namespace
+
+void set_device_allocator(fempic_alloc_fn a, fempic_free_fn f, void *ctx)
+{
+    if ((a == nullptr) != (f == nullptr)) throw Error(FEMPIC_EINVAL, "allocator needs both functions, or neither");
+    std::lock_guard<std::mutex> g(alloc_mu);
+    alloc_fn = a;
+    free_fn = f;
+    alloc_ctx = a ? ctx : nullptr;
+}
+
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    if (p) {
+        if (fr) {
+            // the caller's allocator may hand the memory out at once, so wait
+            // for every queued use first (as hipFree does)
+            (void)hipDeviceSynchronize();
+            fr(p, fr_ctx);
+        } else {
+            (void)hipFree(p);
+        }
+    }
     p = nullptr;
     bytes = 0;
+    fr = nullptr;
+    fr_ctx = nullptr;
 }
 void DevBuf::alloc(size_t n)
 {
     release();
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) {
-        p = nullptr;
-        (void)hipGetLastError();
-        throw Error(FEMPIC_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    fempic_alloc_fn a;
+    fempic_free_fn f;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> g(alloc_mu);
+        a = alloc_fn;
+        f = free_fn;
+        ctx = alloc_ctx;
+    }
+    if (a) {
+        p = a(n, ctx);
+        if (!p) throw Error(FEMPIC_ENOMEM, "the installed allocator failed to provide " + std::to_string(n) + " bytes");
+        if ((uintptr_t)p % 256) {
+            f(p, ctx);
+            p = nullptr;
+            throw Error(FEMPIC_EINVAL, "the installed allocator returned memory that is not 256-byte aligned");
+        }
+        fr = f;
+        fr_ctx = ctx;
+    } else {
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(FEMPIC_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+        }
     }
     bytes = n;
 }
@@ -784,6 +834,10 @@ void Run::step(int n_steps)
             cms += t4;
             fms += t3;
             steps_done++;
+            if (prm.gauss_every > 0 && steps_done % prm.gauss_every == 0) {
+                gauss(gauss_last);
+                gauss_step = steps_done;
+            }
         }
     } catch (Error &e) {
         sticky = e.code;
@@ -890,6 +944,205 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
     }
 }
 
+// ------------------------------------------------------------ checkpoint
+// A checkpoint holds the state the next step reads, raw as it lies on the
+// device: the particles in the order the next step takes them (tet order),
+// with their velocity and AB4 histories in the run's storage precision; e, b,
+// the accumulated current moments g and the reference charge rho~^0; the
+// species, the step counter and the sizes that identify mesh and precision.
+// A run restored from it on the same mesh with the same parameters takes the
+// next steps bit for bit as the saved run does.
+namespace {
+constexpr char CKPT_MAGIC[8] = {'F', 'E', 'M', 'P', 'I', 'C', 'C', 'K'};
+constexpr uint32_t CKPT_VERSION = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t precision, order, hist_bytes;
+    int64_t nt, n1, n1_int, n2, n0_int, np, steps;
+    double dt, q, mass, w;
+};
+
+// 64-bit FNV-1a over the payload, eight bytes at a time
+struct Hash64 {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *p, size_t n)
+    {
+        const unsigned char *c = (const unsigned char *)p;
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t wd;
+            std::memcpy(&wd, c + i, 8);
+            h = (h ^ wd) * 1099511628211ull;
+        }
+        for (; i < n; i++) h = (h ^ c[i]) * 1099511628211ull;
+    }
+};
+
+struct CkptFile {
+    std::FILE *f = nullptr;
+    std::string path;
+    Hash64 hash;
+    CkptFile(const char *p, const char *mode) : path(p)
+    {
+        f = std::fopen(p, mode);
+        if (!f) throw Error(FEMPIC_EINVAL, "cannot open checkpoint " + path);
+    }
+    ~CkptFile()
+    {
+        if (f) std::fclose(f);
+    }
+    void write(const void *p, size_t n, bool hashed = true)
+    {
+        if (n && std::fwrite(p, 1, n, f) != n) throw Error(FEMPIC_EINVAL, "cannot write checkpoint " + path);
+        if (hashed) hash.add(p, n);
+    }
+    void read(void *p, size_t n, bool hashed = true)
+    {
+        if (n && std::fread(p, 1, n, f) != n) throw Error(FEMPIC_EINVAL, "checkpoint " + path + " is truncated");
+        if (hashed) hash.add(p, n);
+    }
+    void close_write()
+    {
+        const int r = std::fclose(f);
+        f = nullptr;
+        if (r != 0) throw Error(FEMPIC_EINVAL, "cannot write checkpoint " + path);
+    }
+};
+}  // namespace
+
+void Run::save(const char *path)
+{
+    if (!path) throw Error(FEMPIC_EINVAL, "null path");
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    sync();
+    // the particles in the next step's order, into the buffer set the next step writes
+    const uint32_t *perm = sort_current();
+    HIPCHECK(launch_permute(mixed, pb[cur].d, pb[1 - cur].d, perm, np, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    CkptHeader h{};
+    std::memcpy(h.magic, CKPT_MAGIC, 8);
+    h.version = CKPT_VERSION;
+    h.precision = mixed ? FEMPIC_MIXED : FEMPIC_FP64;
+    h.order = order;
+    h.hist_bytes = mixed ? 4 : 8;
+    h.nt = m.nt;
+    h.n1 = m.N1;
+    h.n1_int = m.N1_int;
+    h.n2 = m.N2;
+    h.n0_int = m.N0_int;
+    h.np = np;
+    h.steps = steps_done;
+    h.dt = prm.dt;
+    h.q = q;
+    h.mass = mass;
+    h.w = w;
+    CkptFile F(path, "wb");
+    F.write(&h, sizeof h);
+    std::vector<char> stage;
+    auto put = [&](const void *d, size_t bytes) {
+        stage.resize(std::max<size_t>(bytes, 1));
+        if (bytes) HIPCHECK(hipMemcpy(stage.data(), d, bytes, hipMemcpyDeviceToHost));
+        F.write(stage.data(), bytes);
+    };
+    const PBufs &S = pb[1 - cur];
+    const int64_t cap = S.d.cap;
+    const size_t rs = mixed ? 4 : 8;
+    for (int c = 0; c < 3; c++) put((const double *)S.x.p + c * cap, np * 8);
+    for (int c = 0; c < 3; c++) put((const double *)S.v.p + c * cap, np * 8);
+    for (int c = 0; c < 9; c++) put((const char *)S.vh.p + c * cap * rs, np * rs);
+    for (int c = 0; c < 9; c++) put((const char *)S.ah.p + c * cap * rs, np * rs);
+    put(S.tet.p, np * 4);
+    put(S.id.p, np * 4);
+    put(d_e.p, m.N1 * 8);
+    put(d_b.p, m.N2 * 8);
+    put(d_g.p, m.N1_int * 8);
+    put(d_rho0.p, m.N0_int * 8);
+    const uint64_t sum = F.hash.h;
+    F.write(&sum, 8, false);
+    F.close_write();
+}
+
+void Run::restore(const char *path)
+{
+    if (!path) throw Error(FEMPIC_EINVAL, "null path");
+    HIPCHECK(hipStreamSynchronize(stream));
+    CkptFile F(path, "rb");
+    CkptHeader h{};
+    F.read(&h, sizeof h);
+    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != CKPT_VERSION)
+        throw Error(FEMPIC_EINVAL, "not a checkpoint of this library: " + F.path);
+    if (h.precision != (mixed ? FEMPIC_MIXED : FEMPIC_FP64) || h.hist_bytes != (mixed ? 4 : 8))
+        throw Error(FEMPIC_EINVAL, "checkpoint precision differs from the run's");
+    if (h.order != order || h.nt != m.nt || h.n1 != m.N1 || h.n1_int != m.N1_int || h.n2 != m.N2 ||
+        h.n0_int != m.N0_int)
+        throw Error(FEMPIC_EINVAL, "checkpoint is of another mesh or order");
+    if (h.dt != prm.dt) throw Error(FEMPIC_EINVAL, "checkpoint time step differs from the run's");
+    if (h.np < 0 || h.np >= ((int64_t)1 << 31) / 2 || h.steps < 0)
+        throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
+    if (!(h.mass > 0) || !std::isfinite(h.q) || !std::isfinite(h.w))
+        throw Error(FEMPIC_EINVAL, "checkpoint species is corrupt");
+    const int64_t n = h.np;
+    const size_t rs = mixed ? 4 : 8;
+    // read and check everything on the host before any of it reaches the device
+    std::vector<double> x(3 * n), v(3 * n);
+    std::vector<char> vh(9 * n * rs), ah(9 * n * rs);
+    std::vector<int32_t> tet(n), id(n);
+    std::vector<double> e(m.N1), b(m.N2), g(m.N1_int), rho0(m.N0_int);
+    F.read(x.data(), x.size() * 8);
+    F.read(v.data(), v.size() * 8);
+    F.read(vh.data(), vh.size());
+    F.read(ah.data(), ah.size());
+    F.read(tet.data(), n * 4);
+    F.read(id.data(), n * 4);
+    F.read(e.data(), e.size() * 8);
+    F.read(b.data(), b.size() * 8);
+    F.read(g.data(), g.size() * 8);
+    F.read(rho0.data(), rho0.size() * 8);
+    const uint64_t want = F.hash.h;
+    uint64_t sum = 0;
+    F.read(&sum, 8, false);
+    if (sum != want) throw Error(FEMPIC_EINVAL, "checkpoint checksum mismatch: " + F.path);
+    for (double a : x)
+        if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite position");
+    for (double a : v)
+        if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite velocity");
+    std::vector<char> seen(std::max<int64_t>(n, 1), 0);
+    for (int64_t i = 0; i < n; i++) {
+        if (tet[i] < 0 || tet[i] >= m.nt) throw Error(FEMPIC_EINVAL, "checkpoint holds a tet outside the mesh");
+        if (id[i] < 0 || id[i] >= n || seen[id[i]]) throw Error(FEMPIC_EINVAL, "checkpoint particle ids are corrupt");
+        seen[id[i]] = 1;
+    }
+    q = h.q;
+    mass = h.mass;
+    w = h.w;
+    alloc_particles(n);
+    PBufs &B = pb[0];
+    const int64_t cap = B.d.cap;
+    auto get = [&](void *d, const void *src, size_t bytes) {
+        if (bytes) HIPCHECK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
+    };
+    for (int c = 0; c < 3; c++) get((double *)B.x.p + c * cap, &x[c * n], n * 8);
+    for (int c = 0; c < 3; c++) get((double *)B.v.p + c * cap, &v[c * n], n * 8);
+    for (int c = 0; c < 9; c++) get((char *)B.vh.p + c * cap * rs, &vh[c * n * rs], n * rs);
+    for (int c = 0; c < 9; c++) get((char *)B.ah.p + c * cap * rs, &ah[c * n * rs], n * rs);
+    get(B.tet.p, tet.data(), n * 4);
+    get(B.id.p, id.data(), n * 4);
+    get(d_e.p, e.data(), e.size() * 8);
+    get(d_b.p, b.data(), b.size() * 8);
+    get(d_g.p, g.data(), g.size() * 8);
+    get(d_rho0.p, rho0.data(), rho0.size() * 8);
+    if (mixed) {
+        HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
+        HIPCHECK(cast_d2f(m.N2, (const double *)d_b.p, (float *)d_b32.p, 1.0, stream));
+    }
+    HIPCHECK(hipStreamSynchronize(stream));
+    steps_done = h.steps;
+    sticky = 0;
+    loaded = true;
+}
+
 void Run::history_get(double *vh, double *ah, int64_t n)
 {
     sync();
@@ -939,6 +1192,16 @@ size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
                    (size_t)m.nt * 16;
     size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
     return ops + vecs + parts + sorts + tets + (64 << 20);
+}
+
+void check_params(const fempic_params &p)
+{
+    if (p.precision != FEMPIC_FP64 && p.precision != FEMPIC_MIXED) throw Error(FEMPIC_EINVAL, "bad precision");
+    if (!(p.dt > 0) || !std::isfinite(p.dt)) throw Error(FEMPIC_EINVAL, "dt must be positive");
+    if (p.gamma != 0.5 || p.beta != 0.25) throw Error(FEMPIC_EINVAL, "only gamma = 1/2, beta = 1/4 is supported");
+    if (!(p.pcg_rtol > 0) || p.pcg_maxit < 1) throw Error(FEMPIC_EINVAL, "bad solver settings");
+    if (p.particle_bc != FEMPIC_REFLECT) throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
+    if (p.gauss_every < 0) throw Error(FEMPIC_EINVAL, "gauss_every must be >= 0");
 }
 
 }  // namespace fempic
@@ -1045,11 +1308,7 @@ int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *h
     API_BEGIN
     if (!mesh || !params || !out) throw Error(FEMPIC_EINVAL, "null argument");
     const fempic_params &p = *params;
-    if (p.precision != FEMPIC_FP64 && p.precision != FEMPIC_MIXED) throw Error(FEMPIC_EINVAL, "bad precision");
-    if (!(p.dt > 0) || !std::isfinite(p.dt)) throw Error(FEMPIC_EINVAL, "dt must be positive");
-    if (p.gamma != 0.5 || p.beta != 0.25) throw Error(FEMPIC_EINVAL, "only gamma = 1/2, beta = 1/4 is supported");
-    if (!(p.pcg_rtol > 0) || p.pcg_maxit < 1) throw Error(FEMPIC_EINVAL, "bad solver settings");
-    if (p.particle_bc != FEMPIC_REFLECT) throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
+    check_params(p);
     auto *h = new fempic_run_s();
     try {
         h->r.reset(new Run(*mesh->m, p, (hipStream_t)hip_stream));
@@ -1144,6 +1403,29 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n)
     API_END
 }
 
+int32_t fempic_run_save(fempic_run run, const char *path)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->save(path);
+    API_END
+}
+
+int32_t fempic_run_load(fempic_run run, const char *path)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->restore(path);
+    API_END
+}
+
+int32_t fempic_set_allocator(fempic_alloc_fn alloc, fempic_free_fn release, void *ctx)
+{
+    API_BEGIN
+    set_device_allocator(alloc, release, ctx);
+    API_END
+}
+
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
 {
     API_BEGIN
@@ -1161,6 +1443,8 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.crossings = r.last_cross;
     s.reflections = r.last_refl;
     s.spills = r.last_spill;
+    for (int k = 0; k < 3; k++) s.gauss[k] = r.gauss_last[k];
+    s.gauss_step = r.gauss_step;
     *out = s;
     API_END
 }

@@ -11,15 +11,24 @@
 namespace fempic {
 
 void set_error(const std::string &s);
+// allocator of device buffers made from now on (both null: hipMalloc/hipFree)
+void set_device_allocator(fempic_alloc_fn a, fempic_free_fn f, void *ctx);
+// EINVAL for parameters outside what the library supports
+void check_params(const fempic_params &p);
 
+// device buffer; freed with the allocator that made it
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    fempic_free_fn fr = nullptr;  // null: hipFree
+    void *fr_ctx = nullptr;
     DevBuf() = default;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes)
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), fr(o.fr), fr_ctx(o.fr_ctx)
     {
         o.p = nullptr;
         o.bytes = 0;
+        o.fr = nullptr;
+        o.fr_ctx = nullptr;
     }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -51,6 +60,8 @@ class Run {
     void deposit_get(double *dg, int64_t n);
     void particles_get(double *pos, double *vel, int64_t *tet, int64_t n);
     void history_get(double *vh, double *ah, int64_t n);
+    void save(const char *path);
+    void restore(const char *path);
     static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
 
     const HostMesh &m;
@@ -66,6 +77,8 @@ class Run {
     double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
     int64_t nnz_total = 0;
+    double gauss_last[3] = {0, 0, 0};  // the last evaluation that params.gauss_every asked for
+    int64_t gauss_step = 0;
 
   private:
     void upload_csr(DevCSRBuf &d, const CSR &A, bool want32);

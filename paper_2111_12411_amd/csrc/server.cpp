@@ -179,6 +179,7 @@ int32_t fempic_submit(fempic_server s, const fempic_job *job, int64_t *ticket)
     if (job->N < 1 || (job->order != 1 && job->order != 2) || job->n < 0 || job->n_steps < 0 ||
         (job->n > 0 && (!job->pos || !job->vel)))
         throw Error(FEMPIC_EINVAL, "bad job");
+    check_params(job->params);
     auto j = std::make_shared<Job>();
     j->spec = *job;
     j->pos.assign(job->pos, job->pos + 3 * job->n);

@@ -78,3 +78,35 @@ def test_run_rejects_bad_params_without_gpu():
     assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
     p = F.params(-1.0)
     assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+
+
+def test_run_rejects_negative_gauss_cadence_without_gpu():
+    m = F.Mesh.cube(2, 1)
+    h = F.C.c_void_p()
+    p = F.params(1e-11, gauss_every=-1)
+    assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+    assert "gauss_every" in F.lib().fempic_last_error().decode()
+
+
+def test_set_allocator_arguments_without_gpu():
+    """One of the two functions alone is EINVAL; both NULL (hipMalloc/hipFree) is OK."""
+    keep = F.ALLOC_FN(lambda n, ctx: None)
+    assert F.lib().fempic_set_allocator(F.C.cast(keep, F.C.c_void_p), None, None) == -1
+    assert F.lib().fempic_set_allocator(None, None, None) == 0
+    with pytest.raises(ValueError):
+        F.set_allocator(lambda n: 0, None)
+    F.set_allocator()
+
+
+def test_torch_allocator_refuses_a_second_hip_runtime_without_gpu():
+    """Loaded before torch, the library has a HIP runtime of its own, and torch's memory must not
+    reach it: use_torch_allocator raises (in a child process, so the import order is known)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, sys.argv[1]); import paper_2111_12411_amd as F; F.lib(); "
+            "import torch\n"
+            "try:\n    F.use_torch_allocator(0)\nexcept RuntimeError as e:\n    print('refused:', e)\n")
+    r = subprocess.run([sys.executable, "-c", code, root], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "refused: two HIP runtimes" in r.stdout, r.stdout
