@@ -40,6 +40,24 @@ def algorithmic_bytes(order, precision, n_particles, n_tet):
     return 2 * state * n_particles + per_tet * n_tet, state, per_tet
 
 
+def pcg_bytes_per_iter(order, precision, rows, nnz):
+    """Bytes one inner PCG iteration must move: q = A p with the fused dot(p, q); x, r and the
+    preconditioned residual z updated with dot(r, z); p = z + beta p.  Order 2 stores A in 2x2
+    blocks with one int32 column per block and a 2x2 block-Jacobi preconditioner, order 1 in CSR
+    with Jacobi.  Inner vectors and values are FP32 in mixed precision, FP64 otherwise."""
+    vs = 4 if precision == F.MIXED else 8
+    if order == 2:
+        blocks, brows = nnz // 4, rows // 2
+        spmv = blocks * (4 * vs + 4) + brows * (8 + 3 * 2 * vs)  # values, column; row pointer, x, y, dot pairs
+        precond = brows * 4 * vs
+    else:
+        spmv = nnz * (vs + 4) + rows * (8 + 3 * vs)
+        precond = rows * vs
+    update_xr = rows * 7 * vs + precond  # read x, p, r, q; write x, r, z
+    update_p = rows * 3 * vs  # read z, p; write p
+    return spmv + update_xr + update_p
+
+
 def profiled_traffic():
     """HBM bytes per launch of k_particle<2, float> on the default workload, from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (copy-calibrated), or None
@@ -234,6 +252,11 @@ def main():
     kernel_s = kms / K / 1e3
     achieved = alg / kernel_s / 1e9
     traffic = profiled_traffic() if args.particles is None else None
+    it = max(st["pcg_iters"], 1)
+    pcg_b = pcg_bytes_per_iter(cfg["order"], F.MIXED, st["a_rows"], st["a_nnz"])
+    # the field phase per step divided by its inner iterations: it also holds the right-hand
+    # side, the Faraday update and the FP64 refinement residuals, so the rate is a lower bound
+    pcg_ms = st["field_ms"] / K / it
     out = {
         "metric": "particle-steps/sec (gather+push+deposit) at p=1/2, FP64 vs mixed; Gauss residual",
         "value": value,
@@ -254,7 +277,9 @@ def main():
                                "mixed precision" % mix["n"], "order": 2, "n_tet": mix["info"]["n_tet"],
                    "particles": mix["n"], "dt": mix["dt"], "omega_p_dt": W.CONFIGS[3]["omega_dt"]},
         "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2]},
-        "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"]},
+        "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"], "a_rows": st["a_rows"],
+                "a_nnz": st["a_nnz"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
+                "gb_s": pcg_b / (pcg_ms / 1e3) / 1e9},
         "crossings_per_particle_step": st["crossings"] / mix["n"],
         "spills_per_particle_step": st["spills"] / mix["n"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -222,6 +222,7 @@ typedef struct {
     int64_t spills;           /* last step: segments outside the particle's tet */
     double gauss[3];          /* R_G, R_C, R_S at step gauss_step (params.gauss_every) */
     int64_t gauss_step;       /* step count of that evaluation; 0: none yet */
+    int64_t a_rows, a_nnz;    /* system matrix A of the field solve: rows (interior W1 DoFs), nonzeros */
 } fempic_stats_t;
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
 

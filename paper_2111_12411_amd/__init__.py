@@ -40,7 +40,8 @@ class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("n_particles", C.c_int64), ("particle_ms", C.c_double),
                 ("particle_kernel_ms", C.c_double), ("continue_kernel_ms", C.c_double), ("field_ms", C.c_double), ("pcg_iters", C.c_int32),
                 ("pcg_relres", C.c_double), ("crossings", C.c_int64), ("reflections", C.c_int64),
-                ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64)]
+                ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64),
+                ("a_rows", C.c_int64), ("a_nnz", C.c_int64)]
 
 
 class ServerParams(C.Structure):

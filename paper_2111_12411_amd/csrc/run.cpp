@@ -4,6 +4,7 @@
 // or FP32 PCG inside FP64 iterative refinement), the Gauss-law check, and
 // host <-> device copies in the natural DoF numbering.
 #include <hip/hip_runtime_api.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -32,6 +33,15 @@ void set_error(const std::string &s) { g_last_error = s; }
         if (err__ != hipSuccess)                                                                        \
             throw Error(FEMPIC_EDEVICE, std::string(#x) + ": " + hipGetErrorString(err__));             \
     } while (0)
+
+// a named range on the roctx timeline (rocprofv3 --marker-trace) for the
+// lifetime of a scope; host side, so it spans issue and the waits inside
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 // ------------------------------------------------------------ device memory
 // device allocator of new buffers: hipMalloc/hipFree, or the caller's pair
@@ -271,6 +281,7 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     upload(d_inc0_ptr, ops.inc0_ptr, stream);
     upload(d_inc0_idx, ops.inc0_idx, stream);
     nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Ct.nnz() + ops.K.nnz() + ops.Gt.nnz();
+    a_nnz = ops.A.nnz();
     // fields and solver vectors
     const int64_t N1 = m.N1, N1i = m.N1_int, N2 = m.N2, N0i = m.N0_int;
     d_e.alloc(N1 * 8);
@@ -472,6 +483,7 @@ void Run::commit_order()
 
 void Run::load(const double *pos, const double *vel, int64_t n, double q_, double mass_, double w_)
 {
+    Range rg("fempic load");
     if (n < 0 || (n > 0 && (!pos || !vel))) throw Error(FEMPIC_EINVAL, "bad particle arrays");
     if (!(mass_ > 0) || !std::isfinite(q_) || !std::isfinite(w_)) throw Error(FEMPIC_EINVAL, "bad species");
     if (n >= ((int64_t)1 << 31) / 2) throw Error(FEMPIC_EINVAL, "too many particles");
@@ -597,6 +609,7 @@ int Run::tpw() const
 
 void Run::particle_phase()
 {
+    Range rg("fempic particle phase (a1-a6)");
     HIPCHECK(hipEventRecord(ev_a, stream));
     const uint32_t *perm = sort_current();
     StepParams sp{q / mass, q * w, prm.dt, tpw()};
@@ -699,6 +712,7 @@ void Run::particle_phase()
 
 void Run::field_phase()
 {
+    Range rg("fempic field update (a7)");
     const int64_t N1i = m.N1_int, N2 = m.N2;
     const double dt = prm.dt;
     double *e = (double *)d_e.p, *b = (double *)d_b.p, *dg = (double *)d_dg.p;
@@ -731,6 +745,7 @@ double Run::read_sc(int k)
 
 void Run::solve_fp64()
 {
+    Range rg("fempic pcg");
     const int64_t n = m.N1_int;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     HIPCHECK(pcg_init(n, (const double *)v_rhs.p, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
@@ -767,6 +782,7 @@ void Run::solve_fp64()
 // solve A32 d = r/|r| to 1e-5 in FP32, x += |r| d, r = rhs - A x in FP64.
 void Run::solve_mixed()
 {
+    Range rg("fempic pcg (FP32 inner, FP64 refinement)");
     const int64_t n = m.N1_int;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     double *x = (double *)v_x.p, *r = (double *)v_r.p;
@@ -821,6 +837,7 @@ void Run::step(int n_steps)
     double pms = 0, kms = 0, cms = 0, fms = 0;
     try {
         for (int s = 0; s < n_steps; s++) {
+            Range rg("fempic step");
             particle_phase();
             field_phase();
             HIPCHECK(hipEventSynchronize(ev_e));
@@ -852,6 +869,7 @@ void Run::step(int n_steps)
 
 void Run::gauss(double out[3])
 {
+    Range rg("fempic gauss residual (a8)");
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     compute_rho((double *)d_rho.p);
     const int64_t N1i = m.N1_int, N0i = m.N0_int;
@@ -1014,6 +1032,7 @@ struct CkptFile {
 
 void Run::save(const char *path)
 {
+    Range rg("fempic checkpoint save");
     if (!path) throw Error(FEMPIC_EINVAL, "null path");
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     sync();
@@ -1066,6 +1085,7 @@ void Run::save(const char *path)
 
 void Run::restore(const char *path)
 {
+    Range rg("fempic checkpoint load");
     if (!path) throw Error(FEMPIC_EINVAL, "null path");
     HIPCHECK(hipStreamSynchronize(stream));
     CkptFile F(path, "rb");
@@ -1445,6 +1465,8 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.spills = r.last_spill;
     for (int k = 0; k < 3; k++) s.gauss[k] = r.gauss_last[k];
     s.gauss_step = r.gauss_step;
+    s.a_rows = r.m.N1_int;
+    s.a_nnz = r.a_nnz;
     *out = s;
     API_END
 }

@@ -76,7 +76,7 @@ class Run {
     int64_t np = 0, steps_done = 0, last_cross = 0, last_refl = 0, last_spill = 0;
     double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
-    int64_t nnz_total = 0;
+    int64_t nnz_total = 0, a_nnz = 0;
     double gauss_last[3] = {0, 0, 0};  // the last evaluation that params.gauss_every asked for
     int64_t gauss_step = 0;
 

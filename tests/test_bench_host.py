@@ -44,6 +44,17 @@ def _profile_copy(tmp_path, digest):
     return root
 
 
+def test_pcg_bytes_per_iteration():
+    # order 2, mixed: one 2x2 block row with one block: 16 B values + 4 B column; row pointer 8 B and
+    # x, y, dot pairs 3 x 8 B; block-Jacobi 16 B; x, p, r, q read and x, r, z written (7 x 8 B);
+    # z, p read and p written (3 x 8 B)
+    assert bench.pcg_bytes_per_iter(2, F.MIXED, 2, 4) == 20 + 32 + 16 + 56 + 24
+    # order 1, FP64, one row with one entry: 8 + 4, 8 + 3 x 8, Jacobi 8, 7 x 8, 3 x 8
+    assert bench.pcg_bytes_per_iter(1, F.FP64, 1, 1) == 12 + 32 + 8 + 56 + 24
+    # the benchmark system: 2 384 240 rows, 25 457 008 blocks -> 0.662 GB per iteration
+    assert abs(bench.pcg_bytes_per_iter(2, F.MIXED, 2_384_240, 4 * 25_457_008) / 1e9 - 0.6617) < 1e-3
+
+
 def test_profiled_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     h = hashlib.sha256()
     for f in ("kernels.hip", "kernels.h"):
