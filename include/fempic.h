@@ -191,6 +191,16 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
 int32_t fempic_run_save(fempic_run run, const char *path);
 int32_t fempic_run_load(fempic_run run, const char *path);
 
+/* Step log: after every step of fempic_step, append one JSON object on a line
+ * of its own to the file at `path` and flush it: {"step", "n_particles",
+ * "particle_ms", "particle_kernel_ms", "continue_kernel_ms", "field_ms",
+ * "pcg_iters", "pcg_relres", "crossings", "reflections", "spills"} of that step
+ * (fields as in fempic_stats_t, for the one step), plus "gauss": [R_G, R_C, R_S]
+ * on the steps params.gauss_every evaluates them.  Non-finite values are
+ * written as null.  NULL or "" stops logging.  EINVAL if the file cannot be
+ * opened; a failed write fails the step with EINVAL. */
+int32_t fempic_run_set_log(fempic_run run, const char *path);
+
 /* -------------------------------------------------------------- allocator
  * Routes the device buffers that runs and servers make from now on through
  * the caller's allocator (a framework's caching allocator, say):

@@ -81,6 +81,7 @@ SYMBOLS = {
     "fempic_history_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_run_save": (C.c_int32, [C.c_void_p, C.c_char_p]),
     "fempic_run_load": (C.c_int32, [C.c_void_p, C.c_char_p]),
+    "fempic_run_set_log": (C.c_int32, [C.c_void_p, C.c_char_p]),
     "fempic_set_allocator": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fempic_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_footprint": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
@@ -266,6 +267,10 @@ class Run:
         """Replace the run's state with a checkpoint of a run on the same mesh (fempic_run_load)."""
         _check(lib().fempic_run_load(self.h, os.fsencode(path)))
         self.n = self.stats()["n_particles"]
+
+    def set_log(self, path):
+        """Append one JSON line per step to `path` (fempic_run_set_log); None stops."""
+        _check(lib().fempic_run_set_log(self.h, os.fsencode(path) if path else None))
 
     def stats(self):
         s = Stats()

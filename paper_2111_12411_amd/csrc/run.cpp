@@ -333,6 +333,7 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
 
 Run::~Run()
 {
+    if (log) std::fclose(log);
     if (stream) (void)hipStreamSynchronize(stream);
     for (auto ev : {ev_a, ev_b, ev_c1, ev_c, ev_d, ev_e})
         if (ev) (void)hipEventDestroy(ev);
@@ -855,6 +856,7 @@ void Run::step(int n_steps)
                 gauss(gauss_last);
                 gauss_step = steps_done;
             }
+            if (log) log_step(t1, t2, t4, t3, gauss_step == steps_done);
         }
     } catch (Error &e) {
         sticky = e.code;
@@ -865,6 +867,37 @@ void Run::step(int n_steps)
     last_kernel_ms = kms;
     last_continue_ms = cms;
     last_field_ms = fms;
+}
+
+// the step log: one JSON object per line, appended and flushed after each step
+void Run::set_log(const char *path)
+{
+    if (log) std::fclose(log);
+    log = nullptr;
+    if (path && *path) {
+        log = std::fopen(path, "a");
+        if (!log) throw Error(FEMPIC_EINVAL, std::string("cannot open step log ") + path);
+    }
+}
+
+void Run::log_step(float particle_ms, float kernel_ms, float continue_ms, float field_ms, bool with_gauss)
+{
+    auto num = [](double v) {
+        char b[32];
+        if (std::isfinite(v)) std::snprintf(b, sizeof b, "%.17g", v);
+        else std::snprintf(b, sizeof b, "null");
+        return std::string(b);
+    };
+    std::string s = "{\"step\": " + std::to_string(steps_done) + ", \"n_particles\": " + std::to_string(np) +
+                    ", \"particle_ms\": " + num(particle_ms) + ", \"particle_kernel_ms\": " + num(kernel_ms) +
+                    ", \"continue_kernel_ms\": " + num(continue_ms) + ", \"field_ms\": " + num(field_ms) +
+                    ", \"pcg_iters\": " + std::to_string(last_iters) + ", \"pcg_relres\": " + num(last_relres) +
+                    ", \"crossings\": " + std::to_string(last_cross) + ", \"reflections\": " +
+                    std::to_string(last_refl) + ", \"spills\": " + std::to_string(last_spill);
+    if (with_gauss)
+        s += ", \"gauss\": [" + num(gauss_last[0]) + ", " + num(gauss_last[1]) + ", " + num(gauss_last[2]) + "]";
+    s += "}\n";
+    if (std::fputs(s.c_str(), log) < 0 || std::fflush(log) != 0) throw Error(FEMPIC_EINVAL, "cannot write the step log");
 }
 
 void Run::gauss(double out[3])
@@ -1436,6 +1469,14 @@ int32_t fempic_run_load(fempic_run run, const char *path)
     API_BEGIN
     if (!run) throw Error(FEMPIC_EINVAL, "null run");
     run->r->restore(path);
+    API_END
+}
+
+int32_t fempic_run_set_log(fempic_run run, const char *path)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->set_log(path);
     API_END
 }
 

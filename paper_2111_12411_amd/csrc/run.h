@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,7 @@ class Run {
     void history_get(double *vh, double *ah, int64_t n);
     void save(const char *path);
     void restore(const char *path);
+    void set_log(const char *path);
     static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
 
     const HostMesh &m;
@@ -133,6 +135,8 @@ class Run {
     int32_t sticky = 0;
     std::string sticky_msg;
     void *h_pin = nullptr;
+    std::FILE *log = nullptr;  // per-step JSON lines (set_log)
+    void log_step(float particle_ms, float kernel_ms, float continue_ms, float field_ms, bool with_gauss);
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c1 = nullptr, ev_c = nullptr, ev_d = nullptr, ev_e = nullptr;
 };
 

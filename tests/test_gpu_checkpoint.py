@@ -1,4 +1,4 @@
-"""Checkpoint/resume, the caller's allocator and the Gauss-residual cadence, through the C ABI.
+"""Checkpoint/resume, the caller's allocator, the Gauss-residual cadence and the step log, through the C ABI.
 
 A run saved after some steps and restored into a fresh run on the same mesh
 must take the following steps bit for bit as the saved run does, and saving
@@ -174,4 +174,30 @@ def test_gauss_cadence():
     st = run.stats()
     assert st["gauss_step"] == 6 and np.array_equal(np.array(st["gauss"]), g6)
     assert g6[0] < 1e-12
+    run.close()
+
+
+def test_step_log(tmp_path):
+    """One JSON line per step: steps 1..5, the Gauss residuals on the steps gauss_every = 2 evaluates
+    (equal to the statistics), the last step's counts equal to the statistics, and the per-step
+    particle-phase times summing to the call's."""
+    import json
+    mesh, dt, pos, vel, w = beam_setup(n=5000)
+    path = tmp_path / "steps.jsonl"
+    run = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14, gauss_every=2)
+    run.load(pos, vel, QE, ME, w)
+    run.set_log(str(path))
+    run.step(5)
+    st = run.stats()
+    run.set_log(None)
+    run.step(1)
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert [x["step"] for x in lines] == [1, 2, 3, 4, 5]
+    assert ["gauss" in x for x in lines] == [False, True, False, True, False]
+    assert lines[3]["gauss"] == st["gauss"] and st["gauss_step"] == 4
+    last = lines[-1]
+    for k in ("crossings", "reflections", "spills", "pcg_iters", "pcg_relres", "n_particles"):
+        assert last[k] == st[k], k
+    assert abs(sum(x["particle_ms"] for x in lines) - st["particle_ms"]) < 1e-3 * st["particle_ms"] + 1e-6
+    assert all(x["field_ms"] > 0 and x["crossings"] > 0 for x in lines)
     run.close()
