@@ -98,9 +98,12 @@ def run_workload(cfg_id, precision, steps, warmup, n=None, order=None):
     run.sync()
     wall = time.perf_counter() - t0
     st = run.stats()
+    t0 = time.perf_counter()
     rg = run.gauss()
+    gauss_ms = (time.perf_counter() - t0) * 1e3
     e, b = run.fields()
-    return dict(run=run, info=info, dt=dt, n=npart, wall=wall, stats=st, gauss=rg, setup_s=t_setup, e=e, b=b)
+    return dict(run=run, info=info, dt=dt, n=npart, wall=wall, stats=st, gauss=rg, gauss_ms=gauss_ms, setup_s=t_setup,
+                e=e, b=b)
 
 
 def rel(a, b):
@@ -195,7 +198,7 @@ def largest(steps, warmup):
            "data": "synthetic",
            "config": {"workload": "56^3 Kuhn cube (1053696 tets), order 2, %d electrons in two streams at +-0.2c, "
                                   "v_th 0.01c, dt = 10 x explicit bound, PEC walls, mixed precision" % r["n"]},
-           "gauss_residual": {"R_G": r["gauss"][0], "R_C": r["gauss"][1], "R_S": r["gauss"][2]},
+           "gauss_residual": {"R_G": r["gauss"][0], "R_C": r["gauss"][1], "R_S": r["gauss"][2], "ms": r["gauss_ms"]},
            "crossings_per_particle_step": st["crossings"] / r["n"],
            "roofline": {"bound": "hbm", "kernel": "k_particle<2,float>", "kernel_ms": kms / steps,
                         "frac": alg / (kms / steps / 1e3) / 1e9 / HBM_PEAK_GBS,
@@ -276,7 +279,8 @@ def main():
                                "perturbation in x, v_th 0.02c, omega_p dt = 0.02, dt = 10 x explicit bound, PEC walls, "
                                "mixed precision" % mix["n"], "order": 2, "n_tet": mix["info"]["n_tet"],
                    "particles": mix["n"], "dt": mix["dt"], "omega_p_dt": W.CONFIGS[3]["omega_dt"]},
-        "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2]},
+        "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2],
+                           "ms": mix["gauss_ms"]},
         "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"], "a_rows": st["a_rows"],
                 "a_nnz": st["a_nnz"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
                 "gb_s": pcg_b / (pcg_ms / 1e3) / 1e9},

@@ -535,6 +535,8 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     compute_rho((double *)d_rho0.p);
     zero(d_g);
     HIPCHECK(hipStreamSynchronize(stream));
+    gauss_step = 0;
+    for (double &g : gauss_last) g = 0.0;
     sticky = 0;
     loaded = true;
 }
@@ -1192,6 +1194,8 @@ void Run::restore(const char *path)
     }
     HIPCHECK(hipStreamSynchronize(stream));
     steps_done = h.steps;
+    gauss_step = 0;
+    for (double &g : gauss_last) g = 0.0;
     sticky = 0;
     loaded = true;
 }
