@@ -140,12 +140,14 @@ def test_bitwise_determinism():
         assert np.array_equal(a, b)
 
 
-def test_mixed_precision_fields_within_1e5():
-    """Mixed precision (FP32 gather/push + FP32 PCG with FP64 refinement) vs the FP64 oracle."""
-    dt = 10 * cfl(4, 2)
+@pytest.mark.parametrize("k", [1, 2])
+def test_mixed_precision_fields_within_1e5(k):
+    """Mixed precision (FP32 gather/push + FP32 PCG with FP64 refinement) vs the FP64 oracle:
+    4^3 cube, order k, 20k thermal electrons at 0.02c, dt = 10 dt_cfl, 100 steps."""
+    dt = 10 * cfl(4, k)
     pos, vel = W.particles("thermal", 20000, 3007, vth=0.02)
     w = W.plasma_weight(len(pos), dt)
-    m, orc, run = pair(4, 2, dt, pos, vel, w, precision=F.MIXED)
+    m, orc, run = pair(4, k, dt, pos, vel, w, precision=F.MIXED)
     for n in range(100):
         orc.step()
         run.step()
