@@ -63,12 +63,14 @@ def test_c1_order1_fp64_100_steps():
     assert st["steps"] == 100 and st["crossings"] > 0
 
 
-def test_order2_fp64_beam_parity():
-    """Order 2, FP64, 6^3 cube, 20k-electron beam at 0.1c, dt = 10 dt_cfl, 20 steps (walls reflect)."""
-    dt = 10 * cfl(6, 2)
+@pytest.mark.parametrize("k", [1, 2])
+def test_fp64_beam_parity(k):
+    """FP64, order k, 6^3 cube, 20k-electron beam at 0.1c, dt = 10 dt_cfl, 20 steps (walls reflect):
+    every step's deposit, then fields, particles and the Gauss residual."""
+    dt = 10 * cfl(6, k)
     pos, vel = W.particles("beam", 20000, 2007, vth=0.005, drift=0.1)
     w = W.plasma_weight(len(pos), dt)
-    m, orc, run = pair(6, 2, dt, pos, vel, w)
+    m, orc, run = pair(6, k, dt, pos, vel, w)
     for n in range(20):
         orc.step()
         run.step()
