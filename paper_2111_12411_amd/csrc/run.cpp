@@ -1140,6 +1140,16 @@ void Run::restore(const char *path)
         throw Error(FEMPIC_EINVAL, "checkpoint species is corrupt");
     const int64_t n = h.np;
     const size_t rs = mixed ? 4 : 8;
+    {
+        // the size the header implies, before anything is allocated for it
+        const long here = std::ftell(F.f);
+        const uint64_t want = (uint64_t)sizeof(CkptHeader) + (uint64_t)n * (6 * 8 + 18 * rs + 8) +
+                              (uint64_t)(m.N1 + m.N2 + m.N1_int + m.N0_int) * 8 + 8;
+        if (here < 0 || std::fseek(F.f, 0, SEEK_END) != 0) throw Error(FEMPIC_EINVAL, "cannot read checkpoint " + F.path);
+        const long size = std::ftell(F.f);
+        if (size < 0 || (uint64_t)size != want || std::fseek(F.f, here, SEEK_SET) != 0)
+            throw Error(FEMPIC_EINVAL, "checkpoint " + F.path + " is truncated or has the wrong size");
+    }
     // read and check everything on the host before any of it reaches the device
     std::vector<double> x(3 * n), v(3 * n);
     std::vector<char> vh(9 * n * rs), ah(9 * n * rs);

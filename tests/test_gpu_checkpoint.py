@@ -95,6 +95,12 @@ def test_checkpoint_rejects_mismatch_and_damage(tmp_path):
     bad = str(tmp_path / "bad.ckpt")
     open(bad, "wb").write(bytes(flipped))
     assert "checksum" in rejected(b, bad, "checksum")
+    # a particle count far beyond the file (header field at byte 64) is caught before any allocation
+    import struct
+    big = bytearray(blob)
+    big[64:72] = struct.pack("<q", (1 << 30) - 1)
+    open(bad, "wb").write(bytes(big))
+    assert "wrong size" in rejected(b, bad, "particle count")
     b.step(1)
     assert b.stats()["steps"] == 1 and b.stats()["n_particles"] == 100
     with pytest.raises(F.FempicError):
