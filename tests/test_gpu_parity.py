@@ -10,6 +10,7 @@ import pytest
 import paper_2111_12411_amd as F
 from paper_2111_12411_amd import workloads as W
 from oracle import core, mesh as omesh
+from flux_check import relative_net_flux
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +78,8 @@ def test_fp64_beam_parity(k):
         assert rel(run.deposit(), orc.last_dg * m.int1) < 1e-12, n
     e, b = run.fields()
     assert rel(e, orc.e) < 1e-12 and rel(b, orc.b) < 1e-12
+    # magnetic Gauss law: no net flux out of any tet
+    assert relative_net_flux(m, b) < 1e-13
     pos_g, vel_g, _ = run.particles()
     assert rel(pos_g, orc.pos) < 1e-13 and rel(vel_g, orc.vel) < 1e-12
     RG, RC, RS = run.gauss()
@@ -155,6 +158,7 @@ def test_mixed_precision_fields_within_1e5(k):
         run.step()
     e, b = run.fields()
     assert rel(e, orc.e) < 1e-5 and rel(b, orc.b) < 1e-5, (rel(e, orc.e), rel(b, orc.b))
+    assert relative_net_flux(m, b) < 1e-13
     RG, RC, RS = run.gauss()
     assert RG < 1e-12, (RG, RC, RS)
 

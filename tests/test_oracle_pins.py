@@ -611,6 +611,23 @@ def test_p9_energy_conserved_without_current():
         assert run.energy() == pytest.approx(U0, rel=1e-12)
 
 
+@pytest.mark.parametrize("k", [1, 2])
+def test_p9_magnetic_flux_stays_zero(k):
+    """P9 (magnetic Gauss law): b changes only by curls (K e), so every tet's net outward flux
+    stays at rounding level through steps with moving charge.  A curl of a random e passes the same
+    check and a random b fails it by far, so the check itself can fail."""
+    from flux_check import relative_net_flux
+    run = small_run(3, k, dt_factor=10.0)
+    pos, vel = W.particles("beam", 2000, 31, vth=0.01, drift=0.15)
+    run.load(pos, vel, -W.Q_E, W.M_E, W.plasma_weight(len(pos), run.dt))
+    run.step(8)
+    assert np.linalg.norm(run.b) > 0
+    assert relative_net_flux(run.m, run.b) < 1e-13
+    rng = np.random.default_rng(2)
+    assert relative_net_flux(run.m, run.ops.K @ (rng.normal(size=run.m.n1) * run.m.int1)) < 1e-13
+    assert relative_net_flux(run.m, rng.normal(size=run.m.n2)) > 1e-2
+
+
 def test_p9_gauss_invariant_and_whole_step():
     """P9 + P10: G^T(*eps e + g) stays at zero and R_G <= 1e-12 every step (c1 shape)."""
     run = small_run(4, 1)
