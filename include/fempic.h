@@ -129,7 +129,8 @@ int32_t fempic_run_destroy(fempic_run run);
  * pos, vel are [n][3].  Locates every particle (EOUTSIDE if one is outside),
  * and starts the 4th-order Adams-Bashforth history from the current fields:
  * a^{-j} = a^0, v^{-j} = v^0 - j dt a^0 (j = 1..3).  Records the nodal charge
- * rho~^0 as the reference of the Gauss-law check.  Replaces earlier particles. */
+ * rho~^0 as the reference of the Gauss-law check.  Replaces earlier particles.
+ * EINVAL for a non-finite position or velocity (nothing reaches the device). */
 int32_t fempic_particles_load(fempic_run run, const double *pos, const double *vel, int64_t n, double q, double m,
                               double w);
 

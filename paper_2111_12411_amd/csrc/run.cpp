@@ -488,6 +488,9 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     if (n < 0 || (n > 0 && (!pos || !vel))) throw Error(FEMPIC_EINVAL, "bad particle arrays");
     if (!(mass_ > 0) || !std::isfinite(q_) || !std::isfinite(w_)) throw Error(FEMPIC_EINVAL, "bad species");
     if (n >= ((int64_t)1 << 31) / 2) throw Error(FEMPIC_EINVAL, "too many particles");
+    for (int64_t k = 0; k < 3 * n; k++)
+        if (!std::isfinite(pos[k]) || !std::isfinite(vel[k]))
+            throw Error(FEMPIC_EINVAL, "particle " + std::to_string(k / 3) + " has a non-finite position or velocity");
     q = q_;
     mass = mass_;
     w = w_;

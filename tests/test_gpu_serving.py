@@ -74,3 +74,39 @@ def test_server_rejects_job_beyond_budget():
         srv.submit(8, 2, pos, vel, QE, ME, 1.0, 2, 1e-12)
     assert "ENOMEM" in str(ex.value)
     srv.close()
+
+
+def test_server_isolates_a_failing_job():
+    """A job with a NaN velocity fails with EINVAL at load; the jobs around it, one resident at a
+    time, finish bitwise equal to the same jobs run alone."""
+    specs = []
+    for N, order, kind, n, seed, steps, prec in _jobs()[:2]:
+        dt = 5.0 * F.Mesh.cube(N, order).info()["dt_cfl"]
+        pos, vel = W.particles(kind, n, seed, vth=0.01, drift=0.1)
+        specs.append((N, order, pos, vel, W.plasma_weight(n, dt), dt, steps, prec))
+    bad = list(specs[0])
+    bad_vel = bad[3].copy()
+    bad_vel[7, 1] = np.nan
+    bad[3] = bad_vel
+    order = [specs[0], tuple(bad), specs[1]]
+    srv = F.Server(hbm_budget=8 << 30, max_slots=1)
+    tickets = [srv.submit(N, o, pos, vel, QE, ME, w, steps, dt, precision=prec)
+               for (N, o, pos, vel, w, dt, steps, prec) in order]
+    results = {}
+    t0 = time.time()
+    while len(results) < len(tickets):
+        assert time.time() - t0 < 120, "server did not finish the jobs"
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.01)
+    srv.close()
+    assert results[tickets[1]]["status"] == -1
+    for t, (N, o, pos, vel, w, dt, steps, prec) in ((tickets[0], specs[0]), (tickets[2], specs[1])):
+        r = results[t]
+        assert r["status"] == 0
+        e, b, p, v, _ = _alone(N, o, pos, vel, w, dt, steps, prec)
+        assert np.array_equal(r["e"], e) and np.array_equal(r["b"], b)
+        assert np.array_equal(r["pos"], p) and np.array_equal(r["vel"], v)
