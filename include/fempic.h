@@ -160,7 +160,7 @@ int32_t fempic_sync(fempic_run run);
 int32_t fempic_gauss_residual(fempic_run run, double out[3]);
 
 /* Copy fields out / in (natural numbering; e has n1 entries, b has n2).
- * fields_set zeroes e on the PEC walls. */
+ * fields_set zeroes e on the PEC walls; EINVAL for a non-finite coefficient. */
 int32_t fempic_fields_get(fempic_run run, double *e, int64_t ne, double *b, int64_t nb);
 int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const double *b, int64_t nb);
 
@@ -187,8 +187,8 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
  * equal, bit for bit, those the saved run takes after the save.
  * EINVAL: null path; a file that cannot be opened, read or written; a file of
  * another mesh, precision or dt; a damaged file (checksum, particle ids, tets
- * outside the mesh, non-finite positions or velocities).  The format is this
- * library's own, in native byte order. */
+ * outside the mesh, non-finite positions, velocities, histories or fields).  The
+ * format is this library's own, in native byte order. */
 int32_t fempic_run_save(fempic_run run, const char *path);
 int32_t fempic_run_load(fempic_run run, const char *path);
 

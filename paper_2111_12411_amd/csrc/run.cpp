@@ -945,6 +945,12 @@ void Run::fields_get(double *e, int64_t ne, double *b, int64_t nb)
 void Run::fields_set(const double *e, int64_t ne, const double *b, int64_t nb)
 {
     sync();
+    if (e && ne >= m.N1)
+        for (int64_t i = 0; i < m.N1; i++)
+            if (!std::isfinite(e[i])) throw Error(FEMPIC_EINVAL, "non-finite e coefficient");
+    if (b && nb >= m.N2)
+        for (int64_t i = 0; i < m.N2; i++)
+            if (!std::isfinite(b[i])) throw Error(FEMPIC_EINVAL, "non-finite b coefficient");
     if (e) {
         if (ne < m.N1) throw Error(FEMPIC_EINVAL, "e buffer too short");
         std::vector<double> ei(m.N1, 0.0);
@@ -1176,6 +1182,21 @@ void Run::restore(const char *path)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite position");
     for (double a : v)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite velocity");
+    for (const std::vector<double> *f : {&e, &b})
+        for (double a : *f)
+            if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite field coefficient");
+    for (const std::vector<char> *hv : {&vh, &ah})
+        for (size_t k = 0; k < hv->size(); k += rs) {
+            double a;
+            if (mixed) {
+                float f;
+                std::memcpy(&f, hv->data() + k, 4);
+                a = f;
+            } else {
+                std::memcpy(&a, hv->data() + k, 8);
+            }
+            if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite history value");
+        }
     std::vector<char> seen(std::max<int64_t>(n, 1), 0);
     for (int64_t i = 0; i < n; i++) {
         if (tet[i] < 0 || tet[i] >= m.nt) throw Error(FEMPIC_EINVAL, "checkpoint holds a tet outside the mesh");

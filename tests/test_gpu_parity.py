@@ -205,6 +205,11 @@ def test_failure_modes():
     with pytest.raises(F.FempicError) as ei:
         run.load(np.full((2, 3), 0.5), bad_v, QE, ME, 1.0)
     assert ei.value.code == -1 and "non-finite" in str(ei.value)  # EINVAL
+    e_bad, b_ok = np.zeros(m.info()["n1"]), np.zeros(m.info()["n2"])
+    e_bad[3] = np.inf
+    with pytest.raises(F.FempicError) as ei:
+        run.set_fields(e_bad, b_ok)
+    assert ei.value.code == -1 and "non-finite" in str(ei.value)
     pos, vel = W.particles("thermal", 500, 5, vth=0.05)
     run2 = F.Run(m, 5 * cfl(3, 1), F.FP64, pcg_rtol=1e-30, pcg_maxit=1)
     run2.load(pos, vel, QE, ME, 1e6)
