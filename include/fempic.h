@@ -114,7 +114,8 @@ typedef struct {
     double gamma, beta;  /* must be 0.5, 0.25 */
     double pcg_rtol;     /* e.g. 1e-14 */
     int32_t pcg_maxit;   /* e.g. 5000 */
-    int32_t particle_bc; /* FEMPIC_REFLECT */
+    int32_t particle_bc; /* FEMPIC_REFLECT, the only wall condition for particles
+                            (other values: EINVAL) */
     int32_t spill_slots; /* reserved, ignored */
     int32_t gauss_every; /* 0: off; k > 0: fempic_step evaluates the Gauss-law
                             residuals (fempic_gauss_residual) after every step
