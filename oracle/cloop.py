@@ -38,11 +38,16 @@ _lib = None
 
 
 def lib():
+    """The compiled loop; FEMPIC_ORACLE_LIB names another build of the same source
+    (the sanitizer test loads one built with UBSan)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = C.CDLL(LIB)
+        path = os.environ.get("FEMPIC_ORACLE_LIB")
+        if not path:
+            if not os.path.exists(LIB):
+                build()
+            path = LIB
+        L = C.CDLL(path)
         vp, i64, f64 = C.c_void_p, C.c_int64, C.c_double
         L.oracle_step.restype = C.c_int
         L.oracle_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, vp]
