@@ -110,3 +110,28 @@ def test_torch_allocator_refuses_a_second_hip_runtime_without_gpu():
     r = subprocess.run([sys.executable, "-c", code, root], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     assert "refused: two HIP runtimes" in r.stdout, r.stdout
+
+
+def test_null_handles_are_einval_without_gpu():
+    """Every run entry point refuses a null handle with EINVAL and a message (no GPU is touched)."""
+    L = F.lib()
+    buf = (F.C.c_double * 8)()
+    calls = [
+        lambda: L.fempic_step(None, 1),
+        lambda: L.fempic_sync(None),
+        lambda: L.fempic_gauss_residual(None, buf),
+        lambda: L.fempic_fields_get(None, buf, 1, buf, 1),
+        lambda: L.fempic_fields_set(None, buf, 1, buf, 1),
+        lambda: L.fempic_deposit_get(None, buf, 1),
+        lambda: L.fempic_particles_get(None, buf, buf, None, 1),
+        lambda: L.fempic_history_get(None, buf, buf, 1),
+        lambda: L.fempic_run_save(None, b"x"),
+        lambda: L.fempic_run_load(None, b"x"),
+        lambda: L.fempic_run_set_log(None, b"x"),
+        lambda: L.fempic_stats(None, buf),
+        lambda: L.fempic_particles_load(None, buf, buf, 1, 1.0, 1.0, 1.0),
+    ]
+    for call in calls:
+        assert call() == -1
+        assert L.fempic_last_error().decode() != ""
+    assert L.fempic_run_destroy(None) == 0  # destroying NULL is a no-op
