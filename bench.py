@@ -77,7 +77,7 @@ def profiled_traffic():
     return float(m1.group(1)) if h.hexdigest() == m2.group(1) else None
 
 
-def run_workload(cfg_id, precision, steps, warmup, n=None, order=None):
+def run_workload(cfg_id, precision, steps, warmup, n=None, order=None, gauss_every=0, log=None):
     cfg = W.CONFIGS[cfg_id]
     N, k = cfg["N"], (cfg["order"] if order is None else order)
     mesh = F.Mesh.cube(N, k)
@@ -87,7 +87,9 @@ def run_workload(cfg_id, precision, steps, warmup, n=None, order=None):
     npart = len(pos)
     w = W.config_weight(cfg_id, npart, dt)
     t0 = time.perf_counter()
-    run = F.Run(mesh, dt, precision, pcg_rtol=1e-14)
+    run = F.Run(mesh, dt, precision, pcg_rtol=1e-14, gauss_every=gauss_every)
+    if log:
+        run.set_log(log)
     run.load(pos, vel, -W.Q_E, W.M_E, w)
     t_setup = time.perf_counter() - t0
     del pos, vel
@@ -184,10 +186,11 @@ def serving(n_jobs=24, slots=4, mean_gap_ms=15.0, seed=4007):
                                    "bound, mixed precision" % (n_jobs, mean_gap_ms, slots)}}
 
 
-def largest(steps, warmup):
+def largest(steps, warmup, gauss_every=0, log=None):
     """The largest single-GPU run: 56^3 Kuhn cube (1 053 696 tets), order 2, 64M electrons in two
-    counter-streaming beams at +-0.2c (thermal 0.01c), dt = 10 x explicit bound, mixed precision."""
-    r = run_workload(5, F.MIXED, steps, warmup)
+    counter-streaming beams at +-0.2c (thermal 0.01c), dt = 10 x explicit bound, mixed precision.
+    gauss_every > 0 evaluates R_G, R_C, R_S every that many steps into the step log `log`."""
+    r = run_workload(5, F.MIXED, steps, warmup, gauss_every=gauss_every, log=log)
     st = r["stats"]
     alg, _, _ = algorithmic_bytes(2, F.MIXED, r["n"], r["info"]["n_tet"])
     pms, kms = st["particle_ms"], st["particle_kernel_ms"]
@@ -224,6 +227,9 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="resident runs in --serving mode")
     ap.add_argument("--largest", action="store_true",
                     help="the largest single run instead: 56^3 cube, order 2, 64M electrons in two streams, mixed")
+    ap.add_argument("--gauss-every", type=int, default=0,
+                    help="with --largest: Gauss-law residuals every that many steps, into the --log step log")
+    ap.add_argument("--log", default=None, help="with --largest: append one JSON line per step to this file")
     ap.add_argument("--serving", action="store_true",
                     help="measure the submit/poll server on a stream of independent runs instead")
     args = ap.parse_args()
@@ -235,7 +241,7 @@ def main():
         print(json.dumps(serving(slots=args.slots)))
         return
     if args.largest:
-        print(json.dumps(largest(args.steps, args.warmup)))
+        print(json.dumps(largest(args.steps, args.warmup, args.gauss_every, args.log)))
         return
     cfg = W.CONFIGS[3]
     if args.calib_copy:

@@ -48,6 +48,8 @@ extern "C" {
                           tracking, deposit, residuals and refinement */
 
 #define FEMPIC_REFLECT 0 /* particles reflect specularly at PEC walls */
+#define FEMPIC_ABSORB 1  /* a particle that reaches a wall deposits its current up to
+                            the wall and leaves the run there */
 
 typedef struct fempic_mesh_s *fempic_mesh;
 typedef struct fempic_run_s *fempic_run;
@@ -69,7 +71,10 @@ const char *fempic_last_error(void);
  *   face is shared by more than two tets, or an id is out of range.
  * fempic_mesh_create_cube: the N^3 Kuhn-split cube [0,L]^3, 6 N^3 tets
  *   (tet 6h+p of hex h = i + N(j + N l) follows axis permutation p in
- *   lexicographic order).  1 <= N <= 1024.
+ *   lexicographic order).  1 <= N <= 126 (fewer than 2^21 vertices); EINVAL
+ *   otherwise, before anything of that size is allocated.
+ * fempic_mesh_destroy may be called while runs made on the mesh still exist:
+ *   each run keeps what it needs of the mesh until it is destroyed.
  *
  * DoF numbering used by every exported vector (natural order):
  *   edges / faces are sorted vertex tuples numbered lexicographically;
@@ -99,8 +104,14 @@ int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out);
 /* ------------------------------------------------------------------- run
  * A run owns the device state of one simulation on the current HIP device:
  * e, b, accumulated current moments, particles, operators, workspace.
- * The field update is Newmark-beta with gamma = 1/2, beta = 1/4 (Sec. III-B);
- * other values are rejected with EINVAL.  `hip_stream` may be NULL (the run
+ * The field update is Newmark-beta (Sec. III-B, eq. (maxnmb)) with parameters
+ * gamma, beta: 1/2, 1/4 (the paper's choice: the trapezoidal rule, two-level
+ * form) or any other unconditionally stable pair, 2 beta >= gamma >= 1/2, such
+ * as backward difference (1.5, 1) or Galerkin (1.5, 0.8) of Sec. IV-D, in the
+ * three-level form, which starts from a field history at rest (the fields
+ * before the first step equal those at load or fields_set); EINVAL otherwise.
+ * Both keep Gauss's law: the current enters with the time stencil of the
+ * mass term.  `hip_stream` may be NULL (the run
  * creates its own default-priority stream).  pcg_rtol is the relative residual
  * of the field solve (FP64); pcg_maxit caps its iterations (ESOLVE beyond).
  * spill_slots is reserved and ignored: the buffer of path segments outside the
@@ -111,11 +122,12 @@ int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out);
 typedef struct {
     int32_t precision;   /* FEMPIC_FP64 or FEMPIC_MIXED */
     double dt;           /* time step [s] */
-    double gamma, beta;  /* must be 0.5, 0.25 */
+    double gamma, beta;  /* Newmark-beta: 0.5, 0.25, or 2 beta >= gamma >= 0.5 */
     double pcg_rtol;     /* e.g. 1e-14 */
     int32_t pcg_maxit;   /* e.g. 5000 */
-    int32_t particle_bc; /* FEMPIC_REFLECT, the only wall condition for particles
-                            (other values: EINVAL) */
+    int32_t particle_bc; /* FEMPIC_REFLECT or FEMPIC_ABSORB (other values: EINVAL).
+                            Both conserve charge on the interior nodes: the
+                            interior W0 functions vanish on the walls */
     int32_t spill_slots; /* reserved, ignored */
     int32_t gauss_every; /* 0: off; k > 0: fempic_step evaluates the Gauss-law
                             residuals (fempic_gauss_residual) after every step
@@ -143,7 +155,9 @@ int32_t fempic_particles_load(fempic_run run, const double *pos, const double *v
  * solve A (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - (g^{n+1} - g^n),
  * A = *eps + dt^2/4 K^T *nu K, by PCG (Jacobi, or 2x2 block Jacobi at order 2;
  * FP32 PCG inside FP64 refinement in mixed precision);
- * b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}).  The call waits on the device once per
+ * b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}) (gamma, beta = 1/2, 1/4; other pairs take
+ * the three-level form with A = *eps + (beta/gamma)^2 dt^2 K^T *nu K and the
+ * previous step's fields and current).  The call waits on the device once per
  * particle phase (queue and spill counts, error flags) and every 8 PCG
  * iterations; the last step's final field updates may still be queued when it
  * returns (fempic_sync waits for them). */
@@ -169,10 +183,20 @@ int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const dou
  * n1 entries; zero on the walls). */
 int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n);
 
-/* Particle state in load order: pos, vel [n][3]; tet [n] (may be NULL). */
+/* Nodal charge measured with the order-k W0 functions (Sec. III-A: charge on
+ * the primal nodes; Sec. IV-D, the Gauss check): rho[j] = q w sum_p W0_j(r_p)
+ * at the current positions, and rho0 the reference taken at load (natural W0
+ * numbering, n >= n0 entries each; 0 on W0 DoFs on the walls, which the check
+ * leaves out).  Either pointer may be NULL.  Synchronises; EINVAL before a load. */
+int32_t fempic_rho_get(fempic_run run, double *rho, double *rho0, int64_t n);
+
+/* Particle state in load order: pos, vel [n][3]; tet [n] (any may be NULL);
+ * n >= the number loaded.  A particle absorbed at a wall has tet -1 and NaN
+ * position and velocity. */
 int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *tet, int64_t n);
 
-/* Full AB4 history in load order: vh, ah are [n][3][3] = v^{n-1..n-3}, a^{n-1..n-3}. */
+/* Full AB4 history in load order: vh, ah are [n][3][3] = v^{n-1..n-3}, a^{n-1..n-3}
+ * (NaN for absorbed particles). */
 int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
 
 /* ------------------------------------------------------------- checkpoint
@@ -180,10 +204,11 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
  * replaced): the particles, with their AB4 velocity and acceleration histories
  * in the run's storage precision and in the order the next step takes them;
  * e, b, the accumulated current moments and the reference charge of the
- * Gauss-law check; the species and the step counter.  Synchronises; the run
+ * Gauss-law check; the three-level scheme's previous fields and current; the
+ * species and the step counter.  Synchronises; the run
  * itself is unchanged.
  * fempic_run_load reads such a file into a run created on the same mesh (same
- * sizes and order) with the same precision and dt, replacing its particles and
+ * sizes and order) with the same precision, dt, gamma and beta, replacing its particles and
  * fields and clearing a sticky failure.  The steps a run takes after the load
  * equal, bit for bit, those the saved run takes after the save.
  * EINVAL: null path; a file that cannot be opened, read or written; a file of
@@ -196,7 +221,7 @@ int32_t fempic_run_load(fempic_run run, const char *path);
 /* Step log: after every step of fempic_step, append one JSON object on a line
  * of its own to the file at `path` and flush it: {"step", "n_particles",
  * "particle_ms", "particle_kernel_ms", "continue_kernel_ms", "field_ms",
- * "pcg_iters", "pcg_relres", "crossings", "reflections", "spills"} of that step
+ * "pcg_iters", "pcg_relres", "crossings", "reflections", "absorbed", "spills"} of that step
  * (fields as in fempic_stats_t, for the one step), plus "gauss": [R_G, R_C, R_S]
  * on the steps params.gauss_every evaluates them.  Non-finite values are
  * written as null.  NULL or "" stops logging.  EINVAL if the file cannot be
@@ -222,7 +247,10 @@ int32_t fempic_set_allocator(fempic_alloc_fn alloc, fempic_free_fn release, void
 /* Per-run statistics of the last fempic_step call. */
 typedef struct {
     int64_t steps;            /* steps taken by this run */
-    int64_t n_particles;
+    int64_t n_particles;      /* particles in the run now */
+    int64_t n_loaded;         /* particles loaded (n_particles + those absorbed since) */
+    int64_t absorbed;         /* last step: particles absorbed at a wall */
+    int64_t absorbed_total;   /* since load */
     double particle_ms;       /* last call: device time of ordering + particle + deposit reduction, ms */
     double particle_kernel_ms;/* last call: device time of the particle kernel (gather, push, first segment), ms */
     double continue_kernel_ms;/* last call: device time of the kernel that tracks paths leaving their tet, ms */
@@ -235,16 +263,31 @@ typedef struct {
     double gauss[3];          /* R_G, R_C, R_S at step gauss_step (params.gauss_every) */
     int64_t gauss_step;       /* step count of that evaluation; 0: none yet */
     int64_t a_rows, a_nnz;    /* system matrix A of the field solve: rows (interior W1 DoFs), nonzeros */
+    int64_t device_bytes;     /* device memory the run holds now */
+    int64_t device_peak_bytes;/* and the most it has held */
 } fempic_stats_t;
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
 
-/* Device bytes a run of this size needs (mesh operators + particles + workspace). */
-int32_t fempic_footprint(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes);
+/* Device bytes a run needs: operators, fields, solver vectors, particle state
+ * (two buffers), sort, exit queue and the initial buffer of segments outside
+ * their home tet (1.5 n records).  A run whose crossings need a larger buffer
+ * grows it during a step.  Operator sizes are bounded per row by what Kuhn
+ * cubes reach (order 1: 17 nonzeros per row of A, order 2: 46); a mesh of much
+ * higher vertex valence can need more.
+ * fempic_footprint: for a mesh of n_tet tets whose entity counts are those of a
+ *   Kuhn cube with 6 N^3 = n_tet (exact for such cubes).  EINVAL for order not
+ *   1|2, n_tet < 1, n_particles < 0 or an unknown precision.
+ * fempic_footprint_mesh: the same from the counts of a built mesh. */
+int32_t fempic_footprint(int32_t order, int64_t n_tet, int64_t n_particles, int32_t precision, size_t *bytes);
+int32_t fempic_footprint_mesh(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes);
 
 /* ----------------------------------------------------------- serving
  * Continuous batching of independent runs on one GPU.  A server owns a worker
- * thread.  Jobs are admitted in arrival order when their device footprint fits
- * the HBM budget and a slot is free.  Steps of resident runs interleave on
+ * thread.  Jobs are admitted in arrival order when their device footprint
+ * (fempic_footprint of the cube) fits the HBM budget and a slot is free; a run
+ * may not hold more device memory than it was admitted with (a step that would
+ * need more, to grow its buffer of segments outside their home tet, fails the
+ * job with ENOMEM).  Steps of resident runs interleave on
  * separate streams, and a finished run frees its memory for the next job.
  * fempic_submit copies the job's inputs and returns a ticket at once
  * (ENOMEM if the job could never fit the budget).  fempic_poll returns EAGAIN

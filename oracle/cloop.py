@@ -18,7 +18,7 @@ def build(force=True):
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", "-o", tmp, SRC, "-lm"])
+                               "-ffp-contract=off", "-fopenmp", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -50,7 +50,10 @@ def lib():
         L = C.CDLL(path)
         vp, i64, f64 = C.c_void_p, C.c_int64, C.c_double
         L.oracle_step.restype = C.c_int
-        L.oracle_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, vp]
+        L.oracle_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, vp, C.c_int]
+        L.oracle_step_chunked.restype = C.c_int
+        L.oracle_step_chunked.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, i64, vp,
+                                          C.c_int, vp, C.c_int]
         L.oracle_startup.restype = None
         L.oracle_startup.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64]
         L.oracle_gather.restype = None

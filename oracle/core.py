@@ -105,14 +105,27 @@ def cfl_dt(m, ops):
 
 
 class OracleRun:
-    """Whole PIC loop in FP64: C particle loop + scipy sparse direct field solve."""
+    """Whole PIC loop in FP64: C particle loop + scipy sparse direct field solve.
 
-    def __init__(self, m, dt, ops=None, particles_only=False):
-        """particles_only: skip the field operators (particle steps with given fields)."""
+    gamma, beta: parameters of the Newmark-beta scheme (Sec. III-B).  At 1/2, 1/4
+    the step is the two-level trapezoidal form above (unless three_level is set);
+    otherwise, or with three_level, it is the three-level weighted-residual form
+    of the scheme for M dX/dt + S X = F (field_step_newmark)."""
+
+    def __init__(self, m, dt, ops=None, particles_only=False, gamma=0.5, beta=0.25, three_level=False,
+                 absorb=False):
+        """particles_only: skip the field operators (particle steps with given fields).
+        absorb: a particle that reaches a wall deposits its current up to the wall and leaves the
+        run (tet -1); otherwise walls reflect."""
         self.m = m
+        self.absorb = 1 if absorb else 0
         self.k = m.order
         self.dt = dt
         self.lu = None
+        self.gamma, self.beta = gamma, beta
+        self.three_level = three_level or (gamma, beta) != (0.5, 0.25)
+        self.lu3 = None
+        self.prev = None  # (b^{n-1}, e^{n-1}, g^{n-1}) of the three-level scheme
         if not particles_only:
             self.ops = ops if ops is not None else assemble(m)
             o = self.ops
@@ -125,7 +138,7 @@ class OracleRun:
         self.e = np.zeros(m.n1)
         self.b = np.zeros(m.n2)
         self.g = np.zeros(m.n1)  # accumulated current moments
-        self.counters = np.zeros(2, dtype=np.int64)
+        self.counters = np.zeros(3, dtype=np.int64)  # crossings, reflections, absorbed
         self.step_count = 0
 
     # ------------------------------------------------------------ particles
@@ -143,11 +156,23 @@ class OracleRun:
                          q, mass, self.dt)
         self.rho0 = self.rho()
 
-    def particle_step(self, idx=None):
-        """Gather + push + track + deposit for all particles (or idx); returns dg (n1)."""
+    def particle_step(self, idx=None, threads=1):
+        """Gather + push + track + deposit for all particles (or idx); returns dg (n1).
+        threads > 1: the particles in that many contiguous chunks on as many threads, each
+        chunk's deposit summed apart and the chunks added in order."""
         dg = np.zeros(self.m.n1)
         L = cloop.lib()
         n = len(self.pos)
+        if threads > 1 and idx is None:
+            work = np.empty(threads * self.m.n1)
+            st = L.oracle_step_chunked(self.cm.ref, cloop.ptr(self.e), cloop.ptr(self.b), n, cloop.ptr(self.pos),
+                                       cloop.ptr(self.vel), cloop.ptr(self.vh), cloop.ptr(self.ah),
+                                       cloop.ptr(self.tet), self.q, self.mass, self.w, self.dt, cloop.ptr(dg),
+                                       self.m.n1, cloop.ptr(self.counters), threads, cloop.ptr(work),
+                                       self.absorb)
+            if st != 0:
+                raise RuntimeError("oracle particle step failed with status %d" % st)
+            return dg
         if idx is None:
             ip, ni = None, 0
         else:
@@ -155,7 +180,7 @@ class OracleRun:
             ip, ni = cloop.ptr(idx), len(idx)
         st = L.oracle_step(self.cm.ref, cloop.ptr(self.e), cloop.ptr(self.b), n, ip, ni, cloop.ptr(self.pos),
                            cloop.ptr(self.vel), cloop.ptr(self.vh), cloop.ptr(self.ah), cloop.ptr(self.tet),
-                           self.q, self.mass, self.w, self.dt, cloop.ptr(dg), cloop.ptr(self.counters))
+                           self.q, self.mass, self.w, self.dt, cloop.ptr(dg), cloop.ptr(self.counters), self.absorb)
         if st != 0:
             raise RuntimeError("oracle particle step failed with status %d" % st)
         return dg
@@ -174,12 +199,51 @@ class OracleRun:
         self.e[i1] = enew
         self.last_solve_residual = np.linalg.norm(self.A @ d - rhs) / max(np.linalg.norm(rhs), 1e-300)
 
+    def field_step_newmark(self, g_old):
+        """Three-level Newmark-beta step (Sec. III-B, eq. (maxnmb)), read as the weighted-residual
+        scheme for M dX/dt + S X = F with X = (b, e):
+          M [gamma X^{n+1} + (1 - 2 gamma) X^n + (gamma - 1) X^{n-1}] / dt
+            + S [beta X^{n+1} + (1/2 - 2 beta + gamma) X^n + (1/2 + beta - gamma) X^{n-1}] = F~,
+        with M = diag(*nu, *eps) and S = [[0, *nu K], [-K^T *nu, 0]] (PEC walls: no impedance
+        block), and the current term -dG/dt taken with the same time stencil as M:
+          F~ = (0, -[gamma g^{n+1} + (1 - 2 gamma) g^n + (gamma - 1) g^{n-1}] / dt).
+        The coupled system for (b^{n+1}, e^{n+1}) is solved directly.  Before the first step the
+        history is at rest: X^{-1} = X^0 and g^{-1} = g^0.  self.g holds g^{n+1}; g_old is g^n."""
+        o, dt, i1 = self.ops, self.dt, self.ops.int1
+        gm, bt = self.gamma, self.beta
+        c1, c0 = 0.5 - 2.0 * bt + gm, 0.5 + bt - gm  # weights of X^n and X^{n-1} in the S term
+        Ki, nu = self.Ki, o.star_nu
+        Me = o.star_eps[i1][:, i1]
+        e_n, b_n = self.e[i1], self.b
+        if self.prev is None:
+            self.prev = (b_n.copy(), e_n.copy(), g_old.copy())
+        b_m, e_m, g_m = self.prev
+        if self.lu3 is None:
+            top = sps.hstack([(gm / dt) * nu, bt * (nu @ Ki)])
+            bot = sps.hstack([-bt * (Ki.T @ nu), (gm / dt) * Me])
+            self.lu3 = spla.splu(sps.vstack([top, bot]).tocsc())
+        rb = -((1 - 2 * gm) / dt) * (nu @ b_n) - c1 * (nu @ (Ki @ e_n)) \
+             - ((gm - 1) / dt) * (nu @ b_m) - c0 * (nu @ (Ki @ e_m))
+        gt = (gm * self.g + (1 - 2 * gm) * g_old + (gm - 1) * g_m)[i1]
+        re = -((1 - 2 * gm) / dt) * (Me @ e_n) + c1 * (Ki.T @ (nu @ b_n)) \
+             - ((gm - 1) / dt) * (Me @ e_m) + c0 * (Ki.T @ (nu @ b_m)) - gt / dt
+        x = self.lu3.solve(np.concatenate([rb, re]))
+        self.prev = (b_n.copy(), e_n.copy(), g_old.copy())
+        n2 = self.m.n2
+        self.b = x[:n2].copy()
+        self.e = np.zeros(self.m.n1)
+        self.e[i1] = x[n2:]
+
     def step(self, n=1):
         for _ in range(n):
             dg = self.particle_step()
             self.last_dg = dg
+            g_old = self.g.copy()
             self.g += dg
-            self.field_step(dg)
+            if self.three_level:
+                self.field_step_newmark(g_old)
+            else:
+                self.field_step(dg)
             self.step_count += 1
 
     # ----------------------------------------------------------- diagnostics

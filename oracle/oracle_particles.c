@@ -21,7 +21,9 @@
  *      integrand has degree 4k+3, so 2k+2 points) - the exact path integral
  *      that keeps charge conserved (Sec. III-B, eq. for G and g_i);
  *   5. a boundary (PEC) face reflects the remaining path, and the velocity and
- *      the whole AB4 history are mirrored at the end of the step.
+ *      the whole AB4 history are mirrored at the end of the step; or, with the
+ *      absorbing rule, the path ends there: its current is deposited up to the
+ *      wall and the particle leaves the run (tet = -1, position at the wall).
  */
 #include <math.h>
 #include <string.h>
@@ -29,6 +31,7 @@
 
 #define ORACLE_MAX_CROSS 64
 #define ORACLE_ECROSS (-5)
+#define ORACLE_ABSORBED (-100) /* track_and_deposit: the path ended at a wall */
 
 typedef struct {
     int64_t n_tet;
@@ -208,6 +211,9 @@ typedef struct {
     double *dg;     /* global W1 accumulator (natural numbering) */
     int64_t ncross;
     int64_t nrefl;
+    int absorb;     /* 1: a wall absorbs the particle instead of reflecting it */
+    int64_t nabs;   /* particles absorbed */
+    double s_wall;  /* path parameter where the last absorbed path met the wall */
     int64_t *trace_t; /* optional: tet of every segment */
     double *trace_s;  /* optional: end parameter of every segment */
     int ntrace;
@@ -289,6 +295,11 @@ static int64_t track_and_deposit(const OMesh *m, int64_t t0, double c[5][3], Dep
         if (++ncross > ORACLE_MAX_CROSS) return ORACLE_ECROSS;
         ctx->ncross++;
         int64_t nb = m->nbr[4 * t + f_exit];
+        if (nb < 0 && ctx->absorb) {
+            ctx->nabs++;
+            ctx->s_wall = s_exit;
+            return ORACLE_ABSORBED;
+        }
         if (nb >= 0) {
             int e = -1;
             for (int f = 0; f < 4; f++)
@@ -310,63 +321,125 @@ static int64_t track_and_deposit(const OMesh *m, int64_t t0, double c[5][3], Dep
 }
 
 /*
+ * One time step of particle p: gather, AB4, path, track + deposit into ctx->dg,
+ * then the new state.  Returns 0 or a negative status.
+ */
+static int step_one(const OMesh *m, const double *e, const double *bv, int64_t p, double *pos, double *vel,
+                    double *vh, double *ah, int64_t *tet, double q, double mass, double dt, DepCtx *ctx)
+{
+    if (tet[p] < 0) return 0; /* absorbed at a wall in an earlier step */
+    double *r = &pos[3 * p], *v = &vel[3 * p], *VH = &vh[9 * p], *AH = &ah[9 * p];
+    double E[3], B[3], vxB[3], a[3];
+    gather(m, tet[p], r, e, bv, E, B);
+    cross3(v, B, vxB);
+    for (int k = 0; k < 3; k++) a[k] = q / mass * (E[k] + vxB[k]);
+    /* path from v^n, v^{n-1}, v^{n-2}, v^{n-3} */
+    const double *vj[4] = {v, &VH[0], &VH[3], &VH[6]};
+    double c[5][3];
+    for (int k = 0; k < 3; k++) {
+        c[0][k] = r[k];
+        for (int d = 1; d < 5; d++) {
+            double s = 0.0;
+            for (int j = 0; j < 4; j++) s += LC[j][d] * vj[j][k];
+            c[d][k] = dt * s;
+        }
+    }
+    double vnew[3];
+    for (int k = 0; k < 3; k++)
+        vnew[k] = v[k] + dt / 24.0 * (55.0 * a[k] - 59.0 * AH[k] + 37.0 * AH[3 + k] - 9.0 * AH[6 + k]);
+    int nrefl;
+    int64_t refl_t[ORACLE_MAX_CROSS + 1];
+    int refl_f[ORACLE_MAX_CROSS + 1];
+    int64_t tn = track_and_deposit(m, tet[p], c, ctx, &nrefl, refl_t, refl_f);
+    if (tn == ORACLE_ABSORBED) {
+        /* gone: its last position is the point where it met the wall */
+        path_eval(c, ctx->s_wall, r, NULL);
+        tet[p] = -1;
+        return 0;
+    }
+    if (tn < 0) return (int)tn;
+    double rn[3];
+    path_eval(c, 1.0, rn, NULL);
+    /* shift histories: v^{n}, v^{n-1}, v^{n-2};  a^{n}, a^{n-1}, a^{n-2} */
+    memmove(&VH[3], &VH[0], 6 * sizeof(double));
+    memcpy(&VH[0], v, 3 * sizeof(double));
+    memmove(&AH[3], &AH[0], 6 * sizeof(double));
+    memcpy(&AH[0], a, 3 * sizeof(double));
+    memcpy(v, vnew, 3 * sizeof(double));
+    for (int i = 0; i < nrefl; i++) {
+        reflect(m, refl_t[i], refl_f[i], v, 0);
+        for (int j = 0; j < 3; j++) {
+            reflect(m, refl_t[i], refl_f[i], &VH[3 * j], 0);
+            reflect(m, refl_t[i], refl_f[i], &AH[3 * j], 0);
+        }
+    }
+    memcpy(r, rn, 3 * sizeof(double));
+    tet[p] = tn;
+    return 0;
+}
+
+/*
  * One time step for particles idx[0..n_idx) (or all n_p if idx == NULL).
  * State per particle: pos[3], vel[3], vh[3][3] = v^{n-1..n-3}, ah[3][3] = a^{n-1..n-3}, tet.
  * dg (length n1 global) accumulates q w int W1 . dr.  Returns 0 or a negative status.
  */
 int oracle_step(const OMesh *m, const double *e, const double *bv, int64_t n_p, const int64_t *idx, int64_t n_idx,
                 double *pos, double *vel, double *vh, double *ah, int64_t *tet, double q, double mass, double w,
-                double dt, double *dg, int64_t *counters)
+                double dt, double *dg, int64_t *counters, int absorb)
 {
-    DepCtx ctx = {q * w, dg, 0, 0, NULL, NULL, 0};
+    DepCtx ctx = {q * w, dg, 0, 0, absorb, 0, 0.0, NULL, NULL, 0};
     int64_t n = idx ? n_idx : n_p;
     for (int64_t ii = 0; ii < n; ii++) {
-        int64_t p = idx ? idx[ii] : ii;
-        double *r = &pos[3 * p], *v = &vel[3 * p], *VH = &vh[9 * p], *AH = &ah[9 * p];
-        double E[3], B[3], vxB[3], a[3];
-        gather(m, tet[p], r, e, bv, E, B);
-        cross3(v, B, vxB);
-        for (int k = 0; k < 3; k++) a[k] = q / mass * (E[k] + vxB[k]);
-        /* path from v^n, v^{n-1}, v^{n-2}, v^{n-3} */
-        const double *vj[4] = {v, &VH[0], &VH[3], &VH[6]};
-        double c[5][3];
-        for (int k = 0; k < 3; k++) {
-            c[0][k] = r[k];
-            for (int d = 1; d < 5; d++) {
-                double s = 0.0;
-                for (int j = 0; j < 4; j++) s += LC[j][d] * vj[j][k];
-                c[d][k] = dt * s;
-            }
-        }
-        double vnew[3];
-        for (int k = 0; k < 3; k++)
-            vnew[k] = v[k] + dt / 24.0 * (55.0 * a[k] - 59.0 * AH[k] + 37.0 * AH[3 + k] - 9.0 * AH[6 + k]);
-        int nrefl;
-        int64_t refl_t[ORACLE_MAX_CROSS + 1];
-        int refl_f[ORACLE_MAX_CROSS + 1];
-        int64_t tn = track_and_deposit(m, tet[p], c, &ctx, &nrefl, refl_t, refl_f);
-        if (tn < 0) return (int)tn;
-        double rn[3];
-        path_eval(c, 1.0, rn, NULL);
-        /* shift histories: v^{n}, v^{n-1}, v^{n-2};  a^{n}, a^{n-1}, a^{n-2} */
-        memmove(&VH[3], &VH[0], 6 * sizeof(double));
-        memcpy(&VH[0], v, 3 * sizeof(double));
-        memmove(&AH[3], &AH[0], 6 * sizeof(double));
-        memcpy(&AH[0], a, 3 * sizeof(double));
-        memcpy(v, vnew, 3 * sizeof(double));
-        for (int i = 0; i < nrefl; i++) {
-            reflect(m, refl_t[i], refl_f[i], v, 0);
-            for (int j = 0; j < 3; j++) {
-                reflect(m, refl_t[i], refl_f[i], &VH[3 * j], 0);
-                reflect(m, refl_t[i], refl_f[i], &AH[3 * j], 0);
-            }
-        }
-        memcpy(r, rn, 3 * sizeof(double));
-        tet[p] = tn;
+        int st = step_one(m, e, bv, idx ? idx[ii] : ii, pos, vel, vh, ah, tet, q, mass, dt, &ctx);
+        if (st) return st;
     }
     if (counters) {
         counters[0] += ctx.ncross;
         counters[1] += ctx.nrefl;
+        counters[2] += ctx.nabs;
+    }
+    return 0;
+}
+
+/*
+ * The same step for all n_p particles on n_threads threads (OpenMP; one
+ * thread without it): the particles are split into n_threads contiguous
+ * chunks, chunk c deposits into its own buffer of n_dg entries, and the
+ * buffers are added to dg in chunk order, so the result depends only on
+ * n_threads.  work holds n_threads * n_dg doubles.  Returns the first failing
+ * chunk's status, or 0.
+ */
+int oracle_step_chunked(const OMesh *m, const double *e, const double *bv, int64_t n_p, double *pos, double *vel,
+                        double *vh, double *ah, int64_t *tet, double q, double mass, double w, double dt, double *dg,
+                        int64_t n_dg, int64_t *counters, int n_threads, double *work, int absorb)
+{
+    int status[256];
+    int64_t ncr[256], nrf[256], nab[256];
+    if (n_threads < 1 || n_threads > 256) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(n_threads) schedule(static, 1)
+#endif
+    for (int c = 0; c < n_threads; c++) {
+        double *buf = &work[(int64_t)c * n_dg];
+        memset(buf, 0, (size_t)n_dg * sizeof(double));
+        DepCtx ctx = {q * w, buf, 0, 0, absorb, 0, 0.0, NULL, NULL, 0};
+        int64_t lo = n_p * c / n_threads, hi = n_p * (c + 1) / n_threads;
+        status[c] = 0;
+        for (int64_t p = lo; p < hi && !status[c]; p++)
+            status[c] = step_one(m, e, bv, p, pos, vel, vh, ah, tet, q, mass, dt, &ctx);
+        ncr[c] = ctx.ncross;
+        nrf[c] = ctx.nrefl;
+        nab[c] = ctx.nabs;
+    }
+    for (int c = 0; c < n_threads; c++) {
+        if (status[c]) return status[c];
+        const double *buf = &work[(int64_t)c * n_dg];
+        for (int64_t i = 0; i < n_dg; i++) dg[i] += buf[i];
+        if (counters) {
+            counters[0] += ncr[c];
+            counters[1] += nrf[c];
+            counters[2] += nab[c];
+        }
     }
     return 0;
 }
@@ -400,6 +473,7 @@ void oracle_rho(const OMesh *m, int64_t n, const double *pos, const int64_t *tet
 {
     for (int64_t p = 0; p < n; p++) {
         double lam[4];
+        if (tet[p] < 0) continue; /* absorbed */
         bary(m, tet[p], &pos[3 * p], lam);
         for (int j = 0; j < m->n0; j++) rho[m->map0[(int64_t)m->n0 * tet[p] + j]] += qw * w0_eval(m, j, lam);
     }
@@ -411,7 +485,7 @@ int64_t oracle_path_deposit(const OMesh *m, int64_t t0, double *cflat, double qw
 {
     double c[5][3];
     memcpy(c, cflat, sizeof c);
-    DepCtx ctx = {qw, dg, 0, 0, trace_t, trace_s, 0};
+    DepCtx ctx = {qw, dg, 0, 0, 0, 0, 0.0, trace_t, trace_s, 0};
     int nrefl;
     int64_t refl_t[ORACLE_MAX_CROSS + 1];
     int refl_f[ORACLE_MAX_CROSS + 1];

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfempic.so")
 
 FP64, MIXED = 0, 1
+REFLECT, ABSORB = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "EOUTSIDE", -5: "ECROSS", -6: "ESOLVE",
           -7: "EDEVICE", -8: "EAGAIN", -9: "EBUSY"}
 
@@ -37,11 +38,13 @@ class Params(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("steps", C.c_int64), ("n_particles", C.c_int64), ("particle_ms", C.c_double),
+    _fields_ = [("steps", C.c_int64), ("n_particles", C.c_int64), ("n_loaded", C.c_int64), ("absorbed", C.c_int64),
+                ("absorbed_total", C.c_int64), ("particle_ms", C.c_double),
                 ("particle_kernel_ms", C.c_double), ("continue_kernel_ms", C.c_double), ("field_ms", C.c_double), ("pcg_iters", C.c_int32),
                 ("pcg_relres", C.c_double), ("crossings", C.c_int64), ("reflections", C.c_int64),
                 ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64),
-                ("a_rows", C.c_int64), ("a_nnz", C.c_int64)]
+                ("a_rows", C.c_int64), ("a_nnz", C.c_int64), ("device_bytes", C.c_int64),
+                ("device_peak_bytes", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -77,6 +80,7 @@ SYMBOLS = {
     "fempic_fields_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_fields_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_deposit_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "fempic_rho_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_particles_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_history_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_run_save": (C.c_int32, [C.c_void_p, C.c_char_p]),
@@ -84,7 +88,8 @@ SYMBOLS = {
     "fempic_run_set_log": (C.c_int32, [C.c_void_p, C.c_char_p]),
     "fempic_set_allocator": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fempic_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
-    "fempic_footprint": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "fempic_footprint": (C.c_int32, [C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_void_p]),
+    "fempic_footprint_mesh": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
     "fempic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_server_destroy": (C.c_int32, [C.c_void_p]),
     "fempic_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -145,8 +150,9 @@ class Mesh:
         return {k: getattr(i, k) for k, _ in MeshInfo._fields_}
 
     def footprint(self, n_particles, precision=FP64):
+        """Device bytes of a run on this mesh (fempic_footprint_mesh)."""
         b = C.c_size_t()
-        _check(lib().fempic_footprint(self.h, n_particles, precision, C.byref(b)))
+        _check(lib().fempic_footprint_mesh(self.h, n_particles, precision, C.byref(b)))
         return b.value
 
     def __del__(self):
@@ -155,8 +161,16 @@ class Mesh:
             self.h = None
 
 
-def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, gauss_every=0):
-    return Params(precision, dt, 0.5, 0.25, pcg_rtol, pcg_maxit, 0, 0, gauss_every)
+def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, gauss_every=0, gamma=0.5, beta=0.25,
+           particle_bc=0):
+    return Params(precision, dt, gamma, beta, pcg_rtol, pcg_maxit, particle_bc, 0, gauss_every)
+
+
+def footprint(order, n_tet, n_particles, precision=FP64):
+    """Device bytes of a run on a Kuhn-cube-like mesh of n_tet tets (fempic_footprint)."""
+    b = C.c_size_t()
+    _check(lib().fempic_footprint(order, n_tet, n_particles, precision, C.byref(b)))
+    return b.value
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -205,11 +219,12 @@ def use_torch_allocator(device=None):
 class Run:
     """One simulation on the current HIP device."""
 
-    def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None, gauss_every=0):
+    def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None, gauss_every=0,
+                 gamma=0.5, beta=0.25, particle_bc=0):
         self.mesh = mesh
         self.info = mesh.info()
         self.h = C.c_void_p()
-        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every)
+        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every, gamma, beta, particle_bc)
         _check(lib().fempic_run_create(mesh.h, C.byref(p), stream, C.byref(self.h)))
         self.n = 0
 
@@ -246,6 +261,13 @@ class Run:
         _check(lib().fempic_deposit_get(self.h, _p(d), len(d)))
         return d
 
+    def rho(self):
+        """Nodal charge now and at load (fempic_rho_get), natural W0 numbering."""
+        r = np.zeros(self.info["n0"])
+        r0 = np.zeros(self.info["n0"])
+        _check(lib().fempic_rho_get(self.h, _p(r), _p(r0), len(r)))
+        return r, r0
+
     def particles(self):
         pos = np.zeros((self.n, 3))
         vel = np.zeros((self.n, 3))
@@ -266,7 +288,7 @@ class Run:
     def restore(self, path):
         """Replace the run's state with a checkpoint of a run on the same mesh (fempic_run_load)."""
         _check(lib().fempic_run_load(self.h, os.fsencode(path)))
-        self.n = self.stats()["n_particles"]
+        self.n = self.stats()["n_loaded"]
 
     def set_log(self, path):
         """Append one JSON line per step to `path` (fempic_run_set_log); None stops."""

@@ -2,7 +2,8 @@
 // Sec. III-B) in CSR over the internal DoF numbering:
 //   *eps  = eps0 <W1_i, W1_j>,  *nu = (1/mu0) <W2_i, W2_j>,
 //   K     = local curl matrix by assignment (curl W1_j = sum_l K_lj W2_l),
-//   A     = *eps + dt^2/4 K^T *nu K  (assembled element by element),
+//   A     = *eps + c dt^2 K^T *nu K  (assembled element by element; c = (beta/gamma)^2
+//           of the Newmark-beta scheme, 1/4 for gamma = 1/2, beta = 1/4),
 //   K^T *nu, G^T (gradient matrix by assignment).
 // Only W1 DoFs off the PEC walls are unknowns; W0 rows of the Gauss check are
 // the interior nodal DoFs.  Also the explicit time-step bound and the
@@ -283,7 +284,7 @@ double cfl_bound(const HostMesh &m)
     return 2.0 / std::sqrt(lmax);
 }
 
-void assemble(const HostMesh &m, double dt, Operators &ops)
+void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
 {
     const RefElem &R = ref_elem(m.order);
     const int n1 = R.n1, n2 = R.n2, n0 = R.n0;
@@ -314,7 +315,7 @@ void assemble(const HostMesh &m, double dt, Operators &ops)
             for (int i = 0; i < n1 * n2; i++) ce[i] = KtM2[i] / MU0;
         }
     });
-    const double c_stiff = dt * dt / 4.0;
+    const double c_stiff = c_dt2 * dt * dt;
     RowInc r1 = row_incidence(m, N1i, n1, w1int);
     build_csr(r1, N1i, N1i, n1, n1, w1int, nullptr,
               [&](int64_t t, int i, int j) {

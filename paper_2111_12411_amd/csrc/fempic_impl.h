@@ -68,6 +68,8 @@ struct HostMesh {
 };
 
 HostMesh *build_mesh(const double *xyz, int64_t nv, const int64_t *tet4, int64_t nt, int order, bool cube = false);
+// largest Kuhn cube: (N+1)^3 vertices below the 2^21 vertex cap of build_mesh
+constexpr int CUBE_N_MAX = 126;
 HostMesh *build_cube(int N, double L, int order);
 double cfl_bound(const HostMesh &m);
 
@@ -83,7 +85,7 @@ struct CSR {
 };
 
 struct Operators {
-    CSR A;      // *eps + dt^2/4 K^T *nu K   (N1_int x N1_int)
+    CSR A;      // *eps + c dt^2 K^T *nu K   (N1_int x N1_int)
     CSR Meps;   // *eps                      (N1_int x N1_int)
     CSR Ct;     // K^T *nu                   (N1_int x N2)
     CSR K;      // curl                      (N2 x N1_int)
@@ -97,6 +99,19 @@ struct Operators {
     std::vector<int32_t> inc0_idx;
 };
 
-void assemble(const HostMesh &m, double dt, Operators &ops);
+// A = *eps + c_dt2 dt^2 K^T *nu K (c_dt2 = (beta / gamma)^2 of the Newmark-beta scheme)
+void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2 = 0.25);
+
+// Device bytes a run allocates for a mesh of these sizes and n particles
+// (operators with their nonzeros bounded per row for meshes of Kuhn-cube
+// valence, fields, solver vectors, particle state, sort, queue and the initial
+// spill pool).
+struct FootprintSizes {
+    int order;
+    int64_t nt, n1, n1_int, n2, n0_int;
+};
+size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed);
+// sizes of the N^3 Kuhn cube with nt = 6 N^3 tets, N taken real (totals stand in for interior counts)
+FootprintSizes kuhn_sizes(int order, double nt);
 
 }  // namespace fempic

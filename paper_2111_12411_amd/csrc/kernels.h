@@ -45,7 +45,15 @@ struct StepParams {
     double qw;      // q * w
     double dt;
     int32_t tpw;    // tets per workgroup in the particle kernel
+    int32_t absorb; // 1: a particle that reaches a wall is removed there (else it reflects)
 };
+
+// step counters (device int64 each): crossings, reflections, spilled segments,
+// error bits (or-ed), absorbed particles; the rest are zero
+constexpr int NCNT = 8;
+enum { CNT_CROSS = 0, CNT_REFL = 1, CNT_SPILL = 2, CNT_ERR = 3, CNT_ABSORB = 4 };
+// pool.pid of an absorbed particle's last record: never placed in the next order
+constexpr int32_t PID_ABSORBED = -1;
 
 // device error flags (bit set)
 enum : int32_t { ERR_CROSS = 1, ERR_POOL = 2, ERR_OUTSIDE = 4, ERR_NAN = 8 };
@@ -53,7 +61,7 @@ enum : int32_t { ERR_CROSS = 1, ERR_POOL = 2, ERR_OUTSIDE = 4, ERR_NAN = 8 };
 struct SpillPool {
     double *val;     // [cap][n1l]
     int32_t *tet;    // [cap]
-    int64_t *tag;    // [cap]   (queued record << 7) | (last segment of the path << 6) | segment index; -1: unused slot
+    int64_t *tag;    // [cap]   (queued record << 8) | (last segment of the path << 7) | segment index; -1: unused slot
     int32_t *pid;    // [cap]   sorted particle index, set on the record of a path's last segment
     int32_t *count;  // [1] records appended past the fixed slots (atomic)
     int32_t *rcount; // [np] spill records of each queued record
@@ -81,9 +89,6 @@ struct ContQueue {
     int32_t *nstay;  // [nt] particles of each tet that are not queued
 };
 
-struct Counters {  // device int64 [4]: crossings, reflections, spills, error bits
-    unsigned long long *c;
-};
 
 // x: [3][cap] positions of n particles
 hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
@@ -131,8 +136,8 @@ struct ParticleArgs {
     double *P;                // [nt][n1l] per-tet current moments of home segments
     SpillPool pool;
     ContQueue cq;
-    unsigned long long *cnt;  // Counters
-    unsigned long long *cntb; // [CONT_BLOCKS][4] per-block counters of the continuation kernel
+    unsigned long long *cnt;  // [NCNT] step counters
+    unsigned long long *cntb; // [CONT_BLOCKS][NCNT] per-block counters of the continuation kernel
     unsigned long long *perr; // [1] particle-order error flag (launch_place)
 };
 hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
@@ -215,5 +220,6 @@ hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStr
 hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
                        double *partial, double *out4, hipStream_t s);
 hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s);
+
 
 }  // namespace fempic

@@ -608,17 +608,19 @@ __device__ inline GPool gview(const SpillPool &p)
 
 // leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
 // rest of the path about the face plane together with the stored velocity and
-// AB4 histories of particle i (written before tracking)
+// AB4 histories of particle i (written before tracking).  With absorb, a wall
+// ends the path instead: nothing is mirrored and true is returned.
 template <typename R, typename GPtr>
-__device__ inline void cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&cp)[5][3],
-                                  const GParticles<R> &out, int64_t i, unsigned long long &nrf)
+__device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&cp)[5][3],
+                                  const GParticles<R> &out, int64_t i, unsigned long long &nrf, bool absorb)
 {
     const int nx = m.nbr[(int64_t)t * 4 + f];
     if (nx >= 0) {
         entry = nx & 3;
         t = nx >> 2;
-        return;
+        return false;
     }
+    if (absorb) return true;
     const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
     const double inv = 2.0 / (gx * gx + gy * gy + gz * gz);
 #pragma unroll
@@ -646,6 +648,7 @@ __device__ inline void cross_face(const GMesh &m, GPtr G, int f, int &t, int &en
     }
     nrf++;
     entry = f;
+    return false;
 }
 
 // wave-aggregated slot in a shared append buffer
@@ -662,6 +665,12 @@ __device__ inline int64_t append_slot(gptr<int32_t> count)
     return (int64_t)basei + rank;
 }
 
+// A path crosses at most MAX_CROSS faces in one step, so it has at most
+// MAX_CROSS + 1 segments; every segment of a path handed whole to k_continue
+// is a spill record.  Spill tags: (queued record << 8) | (last << 7) | segment.
+constexpr int MAX_CROSS = 64;
+constexpr int MAX_SEG = MAX_CROSS + 1;
+
 // claims the spill record for segment nsp_i of queued record r (tet t): segments 0 and 1 take the fixed slots 2r and 2r+1, later ones are
 // appended after the fixed region of 2 nq slots.  The record of the path's
 // last segment (last) also carries the particle's sorted index i.  Returns the
@@ -670,9 +679,9 @@ __device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, i
                                      int &nsp_i, int &errs)
 {
     int64_t slot = nsp_i < 2 ? 2 * r + nsp_i : 2 * nq + append_slot(pool.count);
-    if (slot < pool.cap && nsp_i < 64) {
+    if (slot < pool.cap && nsp_i < MAX_SEG) {
         pool.tet[slot] = t;
-        pool.tag[slot] = (r << 7) | ((int64_t)last << 6) | nsp_i;
+        pool.tag[slot] = (r << 8) | ((int64_t)last << 7) | nsp_i;
         if (last) pool.pid[slot] = (int32_t)i;
     } else {
         errs |= ERR_POOL;
@@ -682,30 +691,34 @@ __device__ inline int64_t spill_slot(const GPool &pool, int64_t r, int64_t nq, i
     return slot;
 }
 
-// counters of a block (crossings, reflections, spills, error flags), summed in
-// a fixed order and written to the block's own slot of cntb
+// counters of a block (crossings, reflections, spills, error flags, absorbed),
+// summed in a fixed order and written to the block's own slot of cntb
 __device__ inline void block_counters(gptr<unsigned long long> cntb, unsigned long long ncr, unsigned long long nrf,
-                                      unsigned long long nsp, int errs)
+                                      unsigned long long nsp, int errs, unsigned long long nab)
 {
-    __shared__ unsigned long long s_c[BLK / 64][4];
+    __shared__ unsigned long long s_c[BLK / 64][NCNT];
     for (int o = 32; o > 0; o >>= 1) {
         ncr += __shfl_xor(ncr, o);
         nrf += __shfl_xor(nrf, o);
         nsp += __shfl_xor(nsp, o);
         errs |= __shfl_xor(errs, o);
+        nab += __shfl_xor(nab, o);
     }
     const int w = threadIdx.x / 64;
     if (__lane_id() == 0) {
-        s_c[w][0] = ncr;
-        s_c[w][1] = nrf;
-        s_c[w][2] = nsp;
-        s_c[w][3] = (unsigned long long)errs;
+        s_c[w][CNT_CROSS] = ncr;
+        s_c[w][CNT_REFL] = nrf;
+        s_c[w][CNT_SPILL] = nsp;
+        s_c[w][CNT_ERR] = (unsigned long long)errs;
+        s_c[w][CNT_ABSORB] = nab;
+        for (int k = CNT_ABSORB + 1; k < NCNT; k++) s_c[w][k] = 0ull;
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < NCNT) {
         unsigned long long v = 0;
-        for (int k = 0; k < BLK / 64; k++) v = threadIdx.x == 3 ? (v | s_c[k][3]) : v + s_c[k][threadIdx.x];
-        cntb[(int64_t)blockIdx.x * 4 + threadIdx.x] = v;
+        for (int k = 0; k < BLK / 64; k++)
+            v = threadIdx.x == CNT_ERR ? (v | s_c[k][CNT_ERR]) : v + s_c[k][threadIdx.x];
+        cntb[(int64_t)blockIdx.x * NCNT + threadIdx.x] = v;
     }
 }
 
@@ -762,7 +775,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
     for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
     for (int k = tid; k < TM; k += PBLK) s_nstay[k] = 0;
     // the step's counters, which later kernels of the step accumulate into
-    if (blockIdx.x == 0 && tid < 4) glb(A->cnt)[tid] = 0ull;
+    if (blockIdx.x == 0 && tid < NCNT) glb(A->cnt)[tid] = 0ull;
     if (blockIdx.x == 0 && tid == 0) {
         *glb(A->pool.count) = 0;
         *glb(A->perr) = 0ull;
@@ -971,7 +984,8 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
     const gptr<unsigned long long> cntb = glb(A->cntb);
     constexpr int N1 = Ord<K>::N1;
     const int32_t nq = *glb(A->cq.count);
-    unsigned long long ncr = 0, nrf = 0, nsp = 0;
+    const bool absorb = sp.absorb != 0;
+    unsigned long long ncr = 0, nrf = 0, nsp = 0, nab = 0;
     int errs = 0;
     for (int64_t r = (int64_t)blockIdx.x * BLK + threadIdx.x; r < nq; r += (int64_t)gridDim.x * BLK) {
         const gptr<ContRec> rec = qrec + qidx[r];
@@ -979,6 +993,7 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
         const int64_t i = rec->i;
         int t = rec->t, entry = rec->entry, ncross = rec->ncross, nsp_i = 0;
         const int pending = rec->pending;
+        bool gone = false;  // absorbed at a wall
         if (pending >= 0) {
             // the exit found in the home tet: cross it now
             double cp[5][3];
@@ -989,15 +1004,16 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
             ncross++;
             ncr++;
             const unsigned long long nrf0 = nrf;
-            cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, cp, out, i, nrf);
+            gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, cp, out, i, nrf, absorb);
             if (nrf != nrf0) {
 #pragma unroll
                 for (int d = 0; d < 5; d++)
 #pragma unroll
                     for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
             }
+            if (gone) nab++;
         }
-        for (;;) {
+        while (!gone) {
             // the path stays in the record between segments and is re-read here,
             // so that it is not held in registers through the deposit
             double cp[5][3];
@@ -1015,18 +1031,19 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
             for (int mm = 1; mm < 4; mm++) face_poly<false>(G, mm, cp, s_lo, lq[mm - 1]);
             const int t_seg = t;
             bool more = false;
-            if (f_exit >= 0 && ncross < 64) {
+            if (f_exit >= 0 && ncross < MAX_CROSS) {
                 ncross++;
                 ncr++;
                 const unsigned long long nrf0 = nrf;
-                cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf);
+                gone = cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf, absorb);
                 if (nrf != nrf0) {  // a wall reflection changed the path
 #pragma unroll
                     for (int d = 0; d < 5; d++)
 #pragma unroll
                         for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
                 }
-                more = true;
+                more = !gone;
+                if (gone) nab++;
             } else {
                 if (f_exit >= 0) errs |= ERR_CROSS;
                 double rn[3];
@@ -1041,9 +1058,11 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
             }
             asm volatile("" ::: "memory");
             // every path's last segment has a record, also of zero length: it
-            // names the tet the particle ends in
-            if (s_hi > s_lo || !more) {
-                const int64_t slot = spill_slot(pool, r, nq, t_seg, !more, i, nsp_i, errs);
+            // names the tet the particle ends in (an absorbed particle's segment
+            // up to the wall is not a last one: the particle is not placed again)
+            const bool last = !more && !gone;
+            if (s_hi > s_lo || last) {
+                const int64_t slot = spill_slot(pool, r, nq, t_seg, last, i, nsp_i, errs);
                 if (slot >= 0) {
                     double dep[N1];
                     segment_moments<K>(lq, fmax(s_hi - s_lo, 0.0), sp.qw, gl, dep);
@@ -1061,7 +1080,7 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
         nsp += nsp_i;
         pool.rcount[r] = nsp_i;
     }
-    block_counters(cntb, ncr, nrf, nsp, errs);
+    block_counters(cntb, ncr, nrf, nsp, errs, nab);
 }
 
 // step counters: sum (or, for the error flags) of the per-block counters
@@ -1069,26 +1088,23 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
 __global__ __launch_bounds__(BLK) void k_counters(const unsigned long long *__restrict__ cntb, int nb,
                                                   unsigned long long *__restrict__ cnt)
 {
-    __shared__ unsigned long long s_v[4][BLK];
-    unsigned long long v[4] = {0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += BLK) {
-        v[0] += cntb[b * 4];
-        v[1] += cntb[b * 4 + 1];
-        v[2] += cntb[b * 4 + 2];
-        v[3] |= cntb[b * 4 + 3];
-    }
-    for (int k = 0; k < 4; k++) s_v[k][threadIdx.x] = v[k];
+    __shared__ unsigned long long s_v[NCNT][BLK];
+    unsigned long long v[NCNT] = {};
+    for (int b = threadIdx.x; b < nb; b += BLK)
+        for (int k = 0; k < NCNT; k++)
+            v[k] = k == CNT_ERR ? (v[k] | cntb[b * NCNT + k]) : v[k] + cntb[b * NCNT + k];
+    for (int k = 0; k < NCNT; k++) s_v[k][threadIdx.x] = v[k];
     __syncthreads();
     for (int h = BLK / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            for (int k = 0; k < 3; k++) s_v[k][threadIdx.x] += s_v[k][threadIdx.x + h];
-            s_v[3][threadIdx.x] |= s_v[3][threadIdx.x + h];
-        }
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < NCNT; k++)
+                s_v[k][threadIdx.x] = k == CNT_ERR ? (s_v[k][threadIdx.x] | s_v[k][threadIdx.x + h])
+                                                   : s_v[k][threadIdx.x] + s_v[k][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < NCNT) {
         const int k = threadIdx.x;
-        cnt[k] = k == 3 ? (cnt[k] | s_v[3][0]) : cnt[k] + s_v[k][0];
+        cnt[k] = k == CNT_ERR ? (cnt[k] | s_v[k][0]) : cnt[k] + s_v[k][0];
     }
 }
 
@@ -1337,12 +1353,12 @@ __global__ void k_spill_compact(const int32_t *__restrict__ ptet, const int64_t 
     if (r >= nrec) return;
     const int64_t tag = ptag[r];
     if (tag < 0) return;  // unused fixed slot
-    const int64_t q = tag >> 7;
-    const int j = (int)(tag & 63);
+    const int64_t q = tag >> 8;
+    const int j = (int)(tag & 127);
     const uint32_t dst = pos[q] + (uint32_t)j;
     if (dst >= kcap) return;  // only when the pool overflowed (the step is redone)
     key[dst] = (uint32_t)ptet[r];
-    val[dst] = (uint32_t)r | ((tag >> 6) & 1 ? SREC_LAST : 0u);
+    val[dst] = (uint32_t)r | ((tag >> 7) & 1 ? SREC_LAST : 0u);
 }
 
 template <int N1>

@@ -236,7 +236,10 @@ HostMesh *build_mesh(const double *xyz, int64_t nv, const int64_t *tet4, int64_t
 
 HostMesh *build_cube(int N, double L, int order)
 {
-    if (N < 1 || N > 1024 || !(L > 0)) throw Error(FEMPIC_EINVAL, "cube needs 1 <= N <= 1024 and L > 0");
+    // (N+1)^3 vertices must stay below the 2^21 cap of build_mesh; checked
+    // here, before anything of the size of the cube is allocated
+    if (N < 1 || N > CUBE_N_MAX || !(L > 0))
+        throw Error(FEMPIC_EINVAL, "cube needs 1 <= N <= " + std::to_string(CUBE_N_MAX) + " and L > 0");
     const int64_t n1 = N + 1;
     std::vector<double> xyz(3 * n1 * n1 * n1);
     for (int64_t l = 0; l <= N; l++)

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <numeric>
@@ -61,9 +62,17 @@ void set_device_allocator(fempic_alloc_fn a, fempic_free_fn f, void *ctx)
     alloc_ctx = a ? ctx : nullptr;
 }
 
+namespace {
+thread_local DevAccount *cur_account = nullptr;
+}
+AccountScope::AccountScope(DevAccount *a) : prev(cur_account) { cur_account = a; }
+AccountScope::~AccountScope() { cur_account = prev; }
+
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release()
 {
+    if (p && acct) acct->bytes -= bytes;
+    acct = nullptr;
     if (p) {
         if (fr) {
             // the caller's allocator may hand the memory out at once, so wait
@@ -83,6 +92,10 @@ void DevBuf::alloc(size_t n)
 {
     release();
     if (n == 0) n = 16;
+    DevAccount *a_ = cur_account;
+    if (a_ && a_->limit && a_->bytes + n > a_->limit)
+        throw Error(FEMPIC_ENOMEM, "a buffer of " + std::to_string(n) + " bytes would take the run past its device "
+                                   "byte limit of " + std::to_string(a_->limit));
     fempic_alloc_fn a;
     fempic_free_fn f;
     void *ctx;
@@ -111,6 +124,11 @@ void DevBuf::alloc(size_t n)
         }
     }
     bytes = n;
+    if (a_) {
+        acct = a_;
+        a_->bytes += n;
+        a_->peak = std::max(a_->peak, a_->bytes);
+    }
 }
 
 template <typename T>
@@ -196,8 +214,11 @@ void Run::upload_csr(DevCSRBuf &d, const CSR &A, bool want32)
     d.desc.bval32 = want32 ? (const float *)d.bval32.p : nullptr;
 }
 
-Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh), prm(p)
+Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream_t s, size_t byte_limit)
+    : mesh_hold(std::move(mesh)), m(*mesh_hold), prm(p)
 {
+    acct.limit = byte_limit;
+    AccountScope charge(&acct);
     if (s) {
         stream = s;
         own_stream = false;
@@ -246,7 +267,8 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     dm.cube_L = m.cube_L;
     // operators
     Operators ops;
-    assemble(m, p.dt, ops);
+    three_level = !(p.gamma == 0.5 && p.beta == 0.25);
+    assemble(m, p.dt, ops, (p.beta / p.gamma) * (p.beta / p.gamma));
     upload_csr(A, ops.A, mixed);
     upload_csr(Meps, ops.Meps, false);
     upload_csr(Ct, ops.Ct, false);
@@ -302,6 +324,15 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     if (mixed)
         for (auto *v : {&f_x, &f_r, &f_z, &f_p, &f_q}) v->alloc(std::max<int64_t>(N1i, 1) * 4);
     v_u.alloc(std::max<int64_t>(N2, 1) * 8);
+    if (three_level) {
+        d_eprev.alloc(std::max<int64_t>(N1i, 1) * 8);
+        d_bprev.alloc(std::max<int64_t>(N2, 1) * 8);
+        d_dgprev.alloc(std::max<int64_t>(N1i, 1) * 8);
+        v_b2.alloc(std::max<int64_t>(N2, 1) * 8);
+        zero(d_eprev);
+        zero(d_bprev);
+        zero(d_dgprev);
+    }
     const int64_t maxrows = std::max<int64_t>({N1i, N2, N0i, 1});
     d_partial.alloc((size_t)(maxrows / 4 + 1024) * 4 * 8);
     d_sc.alloc(64 * 8);
@@ -322,9 +353,9 @@ Run::Run(const HostMesh &mesh, const fempic_params &p, hipStream_t s) : m(mesh),
     d_ctl.alloc(128);
     zero(d_ctl);
     p_cnt = (unsigned long long *)d_ctl.p;
-    p_small = (int32_t *)((char *)d_ctl.p + 32);
-    p_perr = (unsigned long long *)((char *)d_ctl.p + 64);
-    d_cntb.alloc((size_t)CONT_BLOCKS * 4 * 8);
+    p_small = (int32_t *)((char *)d_ctl.p + CTL_SMALL);
+    p_perr = (unsigned long long *)((char *)d_ctl.p + CTL_PERR);
+    d_cntb.alloc((size_t)CONT_BLOCKS * NCNT * 8);
     HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
     d_args.alloc(sizeof(ParticleArgs));
     for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
@@ -361,6 +392,7 @@ size_t Run::particle_bytes(int64_t n) const
 void Run::alloc_particles(int64_t n)
 {
     np = n;
+    np_loaded = n;
     const int64_t cap = std::max<int64_t>(n, 1);
     const size_t rs = mixed ? 4 : 8;
     for (int k = 0; k < 2; k++) {
@@ -485,6 +517,7 @@ void Run::commit_order()
 void Run::load(const double *pos, const double *vel, int64_t n, double q_, double mass_, double w_)
 {
     Range rg("fempic load");
+    AccountScope charge(&acct);
     if (n < 0 || (n > 0 && (!pos || !vel))) throw Error(FEMPIC_EINVAL, "bad particle arrays");
     if (!(mass_ > 0) || !std::isfinite(q_) || !std::isfinite(w_)) throw Error(FEMPIC_EINVAL, "bad species");
     if (n >= ((int64_t)1 << 31) / 2) throw Error(FEMPIC_EINVAL, "too many particles");
@@ -538,6 +571,9 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     compute_rho((double *)d_rho0.p);
     zero(d_g);
     HIPCHECK(hipStreamSynchronize(stream));
+    have_prev = false;  // the three-level scheme starts from a history at rest
+    absorbed_total = 0;
+    last_absorb = 0;
     gauss_step = 0;
     for (double &g : gauss_last) g = 0.0;
     sticky = 0;
@@ -596,13 +632,15 @@ void Run::locate_host(const double *pos, int64_t n, int32_t *out)
     }
 }
 
-void Run::compute_rho(double *dst)
+// nodal charge into dst (interior W0 DoFs), through per-tet partials in Pr (default: the run's)
+void Run::compute_rho(double *dst, double *Pr)
 {
+    if (!Pr) Pr = (double *)d_Pr.p;
     const uint32_t *perm = sort_current();
     HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d.x, pb[cur].d.tet, pb[cur].d.cap,
-                            q * w, (double *)d_Pr.p, stream));
+                            q * w, Pr, stream));
     HIPCHECK(launch_scatter((const int64_t *)d_inc0_ptr.p, (const int32_t *)d_inc0_idx.p, m.N0_int,
-                            (const double *)d_Pr.p, dst, stream));
+                            (const double *)Pr, dst, stream));
 }
 
 int Run::tpw() const
@@ -616,9 +654,10 @@ int Run::tpw() const
 void Run::particle_phase()
 {
     Range rg("fempic particle phase (a1-a6)");
+    AccountScope charge(&acct);  // the spill pool may grow
     HIPCHECK(hipEventRecord(ev_a, stream));
     const uint32_t *perm = sort_current();
-    StepParams sp{q / mass, q * w, prm.dt, tpw()};
+    StepParams sp{q / mass, q * w, prm.dt, tpw(), prm.particle_bc == FEMPIC_ABSORB ? 1 : 0};
     // The queue and spill stages run on counts that stay on the device: their
     // launches are sized by bounds from the previous step's counts (the largest
     // possible before the first), and the host reads the counts once, at the end
@@ -676,15 +715,17 @@ void Run::particle_phase()
                                 (const double *)d_P.p, (double *)d_dg.p, stream));
         next_order(nrec_ub, srec);
         HIPCHECK(hipEventRecord(ev_d, stream));
-        HIPCHECK(hipMemcpyAsync(h_pin, d_ctl.p, 72, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(h_pin, d_ctl.p, CTL_BYTES, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         const unsigned long long *c = (const unsigned long long *)h_pin;
-        const int32_t *sm = (const int32_t *)((char *)h_pin + 32);
+        const int32_t *sm = (const int32_t *)((char *)h_pin + CTL_SMALL);
         const int64_t nq = sm[6];
         // spill slots in use: the fixed pair of every queued record, then the appended ones
         const int64_t nslots = 2 * nq + sm[0];
         const int64_t nrec = (uint32_t)sm[2];
-        const unsigned long long errs = c[3];
+        const unsigned long long errs = c[CNT_ERR];
+        // a path over the crossing cap fails the step whatever else happened
+        if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
         if (errs & ERR_POOL) {
             // grow the pool and redo the step
             alloc_pool(std::max<int64_t>(2 * pool_cap, nslots + nslots / 4 + 1024));
@@ -693,7 +734,6 @@ void Run::particle_phase()
             nrec_ub = std::min<int64_t>(pool_cap, nrec);
             continue;
         }
-        if (errs & ERR_CROSS) throw Error(FEMPIC_ECROSS, "a particle crossed more than 64 faces in one step");
         if (errs & ERR_NAN) throw Error(FEMPIC_EDEVICE, "non-finite particle position");
         if (nq > nq_ub || nslots > nslot_ub || nrec > nrec_ub) {
             nq_ub = nq;
@@ -701,11 +741,12 @@ void Run::particle_phase()
             nrec_ub = nrec;
             continue;
         }
-        if (*(const unsigned long long *)((char *)h_pin + 64))
+        if (*(const unsigned long long *)((char *)h_pin + CTL_PERR))
             throw Error(FEMPIC_EDEVICE, "inconsistent particle order");
-        last_cross = (int64_t)c[0];
-        last_refl = (int64_t)c[1];
-        last_spill = (int64_t)c[2];
+        last_cross = (int64_t)c[CNT_CROSS];
+        last_refl = (int64_t)c[CNT_REFL];
+        last_spill = (int64_t)c[CNT_SPILL];
+        last_absorb = (int64_t)c[CNT_ABSORB];
         nslot_last = nslots;
         nq_last = nq;
         nrec_last = nrec;
@@ -714,10 +755,74 @@ void Run::particle_phase()
     }
     commit_order();
     cur = 1 - cur;
+    // particles absorbed at a wall are not in the new order
+    np -= last_absorb;
+    absorbed_total += last_absorb;
+}
+
+// Three-level Newmark-beta (Sec. III-B, eq. (maxnmb)) for gamma, beta other than
+// 1/2, 1/4: M [gamma X^{n+1} + (1-2gamma) X^n + (gamma-1) X^{n-1}] / dt
+// + S [beta X^{n+1} + an X^n + am X^{n-1}] = -(0, the same time stencil of g),
+// an = 1/2 - 2beta + gamma, am = 1/2 + beta - gamma, X = (b, e), M = diag(*nu, *eps),
+// S = [[0, *nu K], [-K^T *nu, 0]].  b^{n+1} is eliminated through the Faraday row:
+//   A d = -((1-gamma)/gamma) [*eps (e^n - e^{n-1}) + (g^n - g^{n-1})] - (g^{n+1} - g^n)
+//         + (dt/gamma) K^T *nu u,
+//   u = B0 b^n + B1 b^{n-1} - (dt beta/gamma) K ((an + beta) e^n + am e^{n-1}),
+//   A = *eps + (beta/gamma)^2 dt^2 K^T *nu K,  e^{n+1} = e^n + d,
+//   b^{n+1} = -((1-2gamma) b^n + (gamma-1) b^{n-1}) / gamma
+//             - (dt/gamma) K (beta e^{n+1} + an e^n + am e^{n-1}),
+// with B0 = an - beta (1-2gamma)/gamma, B1 = am - beta (gamma-1)/gamma.  Before the
+// first step the history is at rest (X^{-1} = X^n, no earlier current).
+void Run::field_phase_three_level()
+{
+    Range rg("fempic field update, three-level Newmark-beta (a7)");
+    const int64_t N1i = m.N1_int, N2 = m.N2;
+    const double dt = prm.dt, gm = prm.gamma, bt = prm.beta;
+    const double an = 0.5 - 2.0 * bt + gm, am = 0.5 + bt - gm;
+    const double B0 = an - bt * (1.0 - 2.0 * gm) / gm, B1 = am - bt * (gm - 1.0) / gm;
+    double *e = (double *)d_e.p, *b = (double *)d_b.p, *dg = (double *)d_dg.p, *g = (double *)d_g.p;
+    double *ep = (double *)d_eprev.p, *bp = (double *)d_bprev.p, *dgp = (double *)d_dgprev.p;
+    double *w = (double *)v_tmp.p, *u = (double *)v_u.p, *rhs = (double *)v_rhs.p, *y = (double *)d_y1.p;
+    double *b2 = (double *)v_b2.p, *d = (double *)v_x.p;
+    if (!have_prev) {
+        HIPCHECK(axpby(N1i, 1.0, e, 0.0, e, ep, stream));
+        HIPCHECK(axpby(N2, 1.0, b, 0.0, b, bp, stream));
+        HIPCHECK(axpby(N1i, 0.0, dg, 0.0, dg, dgp, stream));
+        have_prev = true;
+    }
+    HIPCHECK(axpby(N1i, 1.0, dg, 1.0, g, g, stream));
+    // u = B0 b + B1 b^{n-1} - (dt beta / gamma) K ((an + beta) e + am e^{n-1})
+    HIPCHECK(axpby(N1i, an + bt, e, am, ep, w, stream));
+    HIPCHECK(axpby(N2, B0, b, B1, bp, u, stream));
+    HIPCHECK(spmv(K.desc, w, u, -dt * bt / gm, 1.0, u, stream));
+    // rhs = (dt/gamma) K^T *nu u - dg - ((1-gamma)/gamma) (*eps (e - e^{n-1}) + dg^{n-1})
+    HIPCHECK(spmv(Ct.desc, u, rhs, dt / gm, -1.0, dg, stream));
+    HIPCHECK(axpby(N1i, 1.0, e, -1.0, ep, w, stream));
+    HIPCHECK(spmv(Meps.desc, w, y, 1.0, 1.0, dgp, stream));
+    HIPCHECK(axpby(N1i, 1.0, rhs, -(1.0 - gm) / gm, y, rhs, stream));
+    if (mixed) solve_mixed();
+    else solve_fp64();
+    // b^{n+1} = -((1-2gamma) b + (gamma-1) b^{n-1}) / gamma - (dt/gamma) K ((beta + an) e + beta d + am e^{n-1})
+    HIPCHECK(axpby(N1i, bt + an, e, bt, d, w, stream));
+    HIPCHECK(axpby(N1i, 1.0, w, am, ep, w, stream));
+    HIPCHECK(axpby(N2, -(1.0 - 2.0 * gm) / gm, b, -(gm - 1.0) / gm, bp, b2, stream));
+    HIPCHECK(spmv(K.desc, w, b2, -dt / gm, 1.0, b2, stream));
+    // shift the history, then the new fields
+    HIPCHECK(axpby(N2, 1.0, b, 0.0, b, bp, stream));
+    HIPCHECK(axpby(N2, 1.0, b2, 0.0, b2, b, stream));
+    HIPCHECK(axpby(N1i, 1.0, e, 0.0, e, ep, stream));
+    HIPCHECK(axpby(N1i, 1.0, e, 1.0, d, e, stream));
+    HIPCHECK(axpby(N1i, 1.0, dg, 0.0, dg, dgp, stream));
+    if (mixed) {
+        HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
+        HIPCHECK(cast_d2f(m.N2, b, (float *)d_b32.p, 1.0, stream));
+    }
+    HIPCHECK(hipEventRecord(ev_e, stream));
 }
 
 void Run::field_phase()
 {
+    if (three_level) return field_phase_three_level();
     Range rg("fempic field update (a7)");
     const int64_t N1i = m.N1_int, N2 = m.N2;
     const double dt = prm.dt;
@@ -898,7 +1003,8 @@ void Run::log_step(float particle_ms, float kernel_ms, float continue_ms, float 
                     ", \"continue_kernel_ms\": " + num(continue_ms) + ", \"field_ms\": " + num(field_ms) +
                     ", \"pcg_iters\": " + std::to_string(last_iters) + ", \"pcg_relres\": " + num(last_relres) +
                     ", \"crossings\": " + std::to_string(last_cross) + ", \"reflections\": " +
-                    std::to_string(last_refl) + ", \"spills\": " + std::to_string(last_spill);
+                    std::to_string(last_refl) + ", \"absorbed\": " + std::to_string(last_absorb) +
+                    ", \"spills\": " + std::to_string(last_spill);
     if (with_gauss)
         s += ", \"gauss\": [" + num(gauss_last[0]) + ", " + num(gauss_last[1]) + ", " + num(gauss_last[2]) + "]";
     s += "}\n";
@@ -909,16 +1015,22 @@ void Run::gauss(double out[3])
 {
     Range rg("fempic gauss residual (a8)");
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
-    compute_rho((double *)d_rho.p);
-    const int64_t N1i = m.N1_int, N0i = m.N0_int;
-    HIPCHECK(spmv(Meps.desc, (const double *)d_e.p, (double *)d_y1.p, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(spmv(Gt.desc, (const double *)d_y1.p, (double *)d_GtDe.p, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(spmv(Gt.desc, (const double *)d_g.p, (double *)d_Gtg.p, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(gauss_norms(N0i, (const double *)d_GtDe.p, (const double *)d_Gtg.p, (const double *)d_rho.p,
-                         (const double *)d_rho0.p, (double *)d_partial.p, (double *)d_sc.p + 16, stream));
-    HIPCHECK(hipMemcpyAsync(h_pin, (double *)d_sc.p + 16, 32, hipMemcpyDeviceToHost, stream));
+    gauss_with((double *)d_Pr.p, (double *)d_rho.p, (double *)d_GtDe.p, (double *)d_Gtg.p, (double *)d_y1.p,
+               (double *)d_partial.p, (double *)d_sc.p + 16, out);
+}
+
+void Run::gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *partial, double *out4,
+                     double out[3])
+{
+    compute_rho(rho, Pr);
+    const int64_t N0i = m.N0_int;
+    HIPCHECK(spmv(Meps.desc, (const double *)d_e.p, y1, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(spmv(Gt.desc, (const double *)y1, GtDe, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(spmv(Gt.desc, (const double *)d_g.p, Gtg, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(gauss_norms(N0i, (const double *)GtDe, (const double *)Gtg, (const double *)rho,
+                         (const double *)d_rho0.p, partial, out4, stream));
+    HIPCHECK(hipMemcpyAsync(h_pin, out4, 32, hipMemcpyDeviceToHost, stream));
     sync();
-    (void)N1i;
     const double *v = (const double *)h_pin;
     double nrm = std::sqrt(v[3]);
     if (nrm == 0) nrm = 1.0;
@@ -945,6 +1057,7 @@ void Run::fields_get(double *e, int64_t ne, double *b, int64_t nb)
 void Run::fields_set(const double *e, int64_t ne, const double *b, int64_t nb)
 {
     sync();
+    have_prev = false;  // new fields: the three-level scheme's history starts at rest
     if (e && ne >= m.N1)
         for (int64_t i = 0; i < m.N1; i++)
             if (!std::isfinite(e[i])) throw Error(FEMPIC_EINVAL, "non-finite e coefficient");
@@ -981,21 +1094,61 @@ void Run::deposit_get(double *dg, int64_t n)
     for (int64_t k = 0; k < m.N1_int; k++) dg[m.int2nat1[k]] = d[k];
 }
 
+void Run::rho_get(double *rho, double *rho0, int64_t n)
+{
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    sync();
+    if (n < m.N0) throw Error(FEMPIC_EINVAL, "buffer too short");
+    std::vector<double> d(std::max<int64_t>(m.N0_int, 1));
+    auto out = [&](const void *src, double *dst) {
+        if (!dst) return;
+        if (m.N0_int) HIPCHECK(hipMemcpy(d.data(), src, m.N0_int * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < m.N0; i++) dst[i] = 0.0;
+        for (int64_t k = 0; k < m.N0_int; k++) dst[m.int2nat0[k]] = d[k];
+    };
+    if (rho) {
+        compute_rho((double *)d_rho.p);
+        HIPCHECK(hipStreamSynchronize(stream));
+        out(d_rho.p, rho);
+    }
+    out(d_rho0.p, rho0);
+}
+
+// the current particles, gathered in the order the next step takes them into
+// the buffer set that step writes (it overwrites them), and returned as that
+// buffer set: rows [0, np) hold every particle still in the run
+const PBufs &Run::gather_current()
+{
+    const uint32_t *perm = sort_current();
+    HIPCHECK(launch_permute(mixed, pb[cur].d, pb[1 - cur].d, perm, np, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    return pb[1 - cur];
+}
+
 void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
 {
     sync();
-    if (n < np) throw Error(FEMPIC_EINVAL, "buffer too short");
-    const PBufs &B = pb[cur];
-    std::vector<double> x(3 * std::max<int64_t>(np, 1));
-    std::vector<int32_t> id(std::max<int64_t>(np, 1)), tt(std::max<int64_t>(np, 1));
+    if (n < np_loaded) throw Error(FEMPIC_EINVAL, "buffer too short");
+    // particles absorbed at a wall: tet -1, position and velocity NaN
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    for (int64_t o = 0; o < np_loaded; o++) {
+        for (int c = 0; c < 3; c++) {
+            if (pos) pos[3 * o + c] = nan;
+            if (vel) vel[3 * o + c] = nan;
+        }
+        if (tet) tet[o] = -1;
+    }
+    if (!loaded || np == 0) return;
+    const PBufs &B = gather_current();
+    std::vector<double> x(3 * np), v(3 * np);
+    std::vector<int32_t> id(np), tt(np);
     const int64_t cap = B.d.cap;
-    for (int c = 0; c < 3; c++)
-        if (np) HIPCHECK(hipMemcpy(&x[c * np], (double *)B.x.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-    if (np) HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
-    if (np) HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
-    std::vector<double> v(3 * std::max<int64_t>(np, 1));
-    for (int c = 0; c < 3; c++)
-        if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+    for (int c = 0; c < 3; c++) {
+        HIPCHECK(hipMemcpy(&x[c * np], (double *)B.x.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+    }
+    HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < np; i++) {
         const int64_t o = id[i];
         for (int c = 0; c < 3; c++) {
@@ -1016,7 +1169,7 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
 // next steps bit for bit as the saved run does.
 namespace {
 constexpr char CKPT_MAGIC[8] = {'F', 'E', 'M', 'P', 'I', 'C', 'C', 'K'};
-constexpr uint32_t CKPT_VERSION = 1;
+constexpr uint32_t CKPT_VERSION = 2;
 
 struct CkptHeader {
     char magic[8];
@@ -1024,6 +1177,10 @@ struct CkptHeader {
     int32_t precision, order, hist_bytes;
     int64_t nt, n1, n1_int, n2, n0_int, np, steps;
     double dt, q, mass, w;
+    double gamma, beta;  // Newmark-beta parameters
+    int32_t have_prev;   // three-level scheme: the field history below holds a step
+    int32_t particle_bc;
+    int64_t np_loaded;   // particles at load (ids are below it; absorbed ones are gone)
 };
 
 // 64-bit FNV-1a over the payload, eight bytes at a time
@@ -1081,9 +1238,7 @@ void Run::save(const char *path)
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     sync();
     // the particles in the next step's order, into the buffer set the next step writes
-    const uint32_t *perm = sort_current();
-    HIPCHECK(launch_permute(mixed, pb[cur].d, pb[1 - cur].d, perm, np, stream));
-    HIPCHECK(hipStreamSynchronize(stream));
+    const PBufs &S = gather_current();
     CkptHeader h{};
     std::memcpy(h.magic, CKPT_MAGIC, 8);
     h.version = CKPT_VERSION;
@@ -1101,6 +1256,11 @@ void Run::save(const char *path)
     h.q = q;
     h.mass = mass;
     h.w = w;
+    h.gamma = prm.gamma;
+    h.beta = prm.beta;
+    h.have_prev = three_level && have_prev ? 1 : 0;
+    h.particle_bc = prm.particle_bc;
+    h.np_loaded = np_loaded;
     CkptFile F(path, "wb");
     F.write(&h, sizeof h);
     std::vector<char> stage;
@@ -1109,7 +1269,6 @@ void Run::save(const char *path)
         if (bytes) HIPCHECK(hipMemcpy(stage.data(), d, bytes, hipMemcpyDeviceToHost));
         F.write(stage.data(), bytes);
     };
-    const PBufs &S = pb[1 - cur];
     const int64_t cap = S.d.cap;
     const size_t rs = mixed ? 4 : 8;
     for (int c = 0; c < 3; c++) put((const double *)S.x.p + c * cap, np * 8);
@@ -1122,6 +1281,11 @@ void Run::save(const char *path)
     put(d_b.p, m.N2 * 8);
     put(d_g.p, m.N1_int * 8);
     put(d_rho0.p, m.N0_int * 8);
+    if (h.have_prev) {
+        put(d_eprev.p, m.N1_int * 8);
+        put(d_bprev.p, m.N2 * 8);
+        put(d_dgprev.p, m.N1_int * 8);
+    }
     const uint64_t sum = F.hash.h;
     F.write(&sum, 8, false);
     F.close_write();
@@ -1130,6 +1294,7 @@ void Run::save(const char *path)
 void Run::restore(const char *path)
 {
     Range rg("fempic checkpoint load");
+    AccountScope charge(&acct);
     if (!path) throw Error(FEMPIC_EINVAL, "null path");
     HIPCHECK(hipStreamSynchronize(stream));
     CkptFile F(path, "rb");
@@ -1143,8 +1308,13 @@ void Run::restore(const char *path)
         h.n0_int != m.N0_int)
         throw Error(FEMPIC_EINVAL, "checkpoint is of another mesh or order");
     if (h.dt != prm.dt) throw Error(FEMPIC_EINVAL, "checkpoint time step differs from the run's");
-    if (h.np < 0 || h.np >= ((int64_t)1 << 31) / 2 || h.steps < 0)
+    if (h.gamma != prm.gamma || h.beta != prm.beta)
+        throw Error(FEMPIC_EINVAL, "checkpoint Newmark-beta parameters differ from the run's");
+    if (h.have_prev != 0 && (h.have_prev != 1 || !three_level)) throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
+    if (h.np < 0 || h.np >= ((int64_t)1 << 31) / 2 || h.steps < 0 || h.np_loaded < h.np ||
+        h.np_loaded >= ((int64_t)1 << 31) / 2)
         throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
+    if (h.particle_bc != prm.particle_bc) throw Error(FEMPIC_EINVAL, "checkpoint particle wall condition differs");
     if (!(h.mass > 0) || !std::isfinite(h.q) || !std::isfinite(h.w))
         throw Error(FEMPIC_EINVAL, "checkpoint species is corrupt");
     const int64_t n = h.np;
@@ -1153,7 +1323,8 @@ void Run::restore(const char *path)
         // the size the header implies, before anything is allocated for it
         const long here = std::ftell(F.f);
         const uint64_t want = (uint64_t)sizeof(CkptHeader) + (uint64_t)n * (6 * 8 + 18 * rs + 8) +
-                              (uint64_t)(m.N1 + m.N2 + m.N1_int + m.N0_int) * 8 + 8;
+                              (uint64_t)(m.N1 + m.N2 + m.N1_int + m.N0_int) * 8 +
+                              (h.have_prev ? (uint64_t)(2 * m.N1_int + m.N2) * 8 : 0) + 8;
         if (here < 0 || std::fseek(F.f, 0, SEEK_END) != 0) throw Error(FEMPIC_EINVAL, "cannot read checkpoint " + F.path);
         const long size = std::ftell(F.f);
         if (size < 0 || (uint64_t)size != want || std::fseek(F.f, here, SEEK_SET) != 0)
@@ -1174,6 +1345,15 @@ void Run::restore(const char *path)
     F.read(b.data(), b.size() * 8);
     F.read(g.data(), g.size() * 8);
     F.read(rho0.data(), rho0.size() * 8);
+    std::vector<double> ep, bp, dgp;
+    if (h.have_prev) {
+        ep.resize(m.N1_int);
+        bp.resize(m.N2);
+        dgp.resize(m.N1_int);
+        F.read(ep.data(), ep.size() * 8);
+        F.read(bp.data(), bp.size() * 8);
+        F.read(dgp.data(), dgp.size() * 8);
+    }
     const uint64_t want = F.hash.h;
     uint64_t sum = 0;
     F.read(&sum, 8, false);
@@ -1182,7 +1362,7 @@ void Run::restore(const char *path)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite position");
     for (double a : v)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite velocity");
-    for (const std::vector<double> *f : {&e, &b})
+    for (const std::vector<double> *f : {&e, &b, &ep, &bp})
         for (double a : *f)
             if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite field coefficient");
     for (const std::vector<char> *hv : {&vh, &ah})
@@ -1197,10 +1377,11 @@ void Run::restore(const char *path)
             }
             if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite history value");
         }
-    std::vector<char> seen(std::max<int64_t>(n, 1), 0);
+    std::vector<char> seen(std::max<int64_t>(h.np_loaded, 1), 0);
     for (int64_t i = 0; i < n; i++) {
         if (tet[i] < 0 || tet[i] >= m.nt) throw Error(FEMPIC_EINVAL, "checkpoint holds a tet outside the mesh");
-        if (id[i] < 0 || id[i] >= n || seen[id[i]]) throw Error(FEMPIC_EINVAL, "checkpoint particle ids are corrupt");
+        if (id[i] < 0 || id[i] >= h.np_loaded || seen[id[i]])
+            throw Error(FEMPIC_EINVAL, "checkpoint particle ids are corrupt");
         seen[id[i]] = 1;
     }
     q = h.q;
@@ -1222,6 +1403,15 @@ void Run::restore(const char *path)
     get(d_b.p, b.data(), b.size() * 8);
     get(d_g.p, g.data(), g.size() * 8);
     get(d_rho0.p, rho0.data(), rho0.size() * 8);
+    if (h.have_prev) {
+        get(d_eprev.p, ep.data(), ep.size() * 8);
+        get(d_bprev.p, bp.data(), bp.size() * 8);
+        get(d_dgprev.p, dgp.data(), dgp.size() * 8);
+    }
+    have_prev = h.have_prev != 0;
+    np_loaded = h.np_loaded;
+    absorbed_total = h.np_loaded - h.np;
+    last_absorb = 0;
     if (mixed) {
         HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
         HIPCHECK(cast_d2f(m.N2, (const double *)d_b.p, (float *)d_b32.p, 1.0, stream));
@@ -1237,21 +1427,27 @@ void Run::restore(const char *path)
 void Run::history_get(double *vh, double *ah, int64_t n)
 {
     sync();
-    if (n < np) throw Error(FEMPIC_EINVAL, "buffer too short");
-    const PBufs &B = pb[cur];
+    if (n < np_loaded) throw Error(FEMPIC_EINVAL, "buffer too short");
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    for (int64_t k = 0; k < 9 * np_loaded; k++) {
+        if (vh) vh[k] = nan;
+        if (ah) ah[k] = nan;
+    }
+    if (!loaded || np == 0) return;
+    const PBufs &B = gather_current();
     const int64_t cap = B.d.cap;
-    std::vector<int32_t> id(std::max<int64_t>(np, 1));
-    if (np) HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
+    std::vector<int32_t> id(np);
+    HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
     auto fetch = [&](const DevBuf &src, double *dst) {
-        std::vector<double> h(9 * std::max<int64_t>(np, 1));
+        std::vector<double> h(9 * np);
         if (mixed) {
-            std::vector<float> f(9 * std::max<int64_t>(np, 1));
+            std::vector<float> f(9 * np);
             for (int c = 0; c < 9; c++)
-                if (np) HIPCHECK(hipMemcpy(&f[c * np], (float *)src.p + c * cap, np * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(&f[c * np], (float *)src.p + c * cap, np * 4, hipMemcpyDeviceToHost));
             for (size_t k = 0; k < f.size(); k++) h[k] = f[k];
         } else {
             for (int c = 0; c < 9; c++)
-                if (np) HIPCHECK(hipMemcpy(&h[c * np], (double *)src.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(&h[c * np], (double *)src.p + c * cap, np * 8, hipMemcpyDeviceToHost));
         }
         for (int64_t i = 0; i < np; i++)
             for (int c = 0; c < 9; c++) dst[9 * id[i] + c] = h[c * np + i];
@@ -1259,9 +1455,9 @@ void Run::history_get(double *vh, double *ah, int64_t n)
     if (vh) {
         // the device keeps v^{n-j} - v^n; the caller gets v^{n-j}
         fetch(B.vh, vh);
-        std::vector<double> v(3 * std::max<int64_t>(np, 1));
+        std::vector<double> v(3 * np);
         for (int c = 0; c < 3; c++)
-            if (np) HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+            HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < np; i++)
             for (int j = 0; j < 3; j++)
                 for (int c = 0; c < 3; c++) vh[9 * id[i] + 3 * j + c] += v[c * np + i];
@@ -1269,29 +1465,74 @@ void Run::history_get(double *vh, double *ah, int64_t n)
     if (ah) fetch(B.ah, ah);
 }
 
+// Mirrors what the constructor, load and the first particle phase allocate.
+// The operators' nonzeros are bounded per row by what Kuhn cubes reach as N
+// grows (order 1: A 16, K 3, G^T 14; order 2: about 44, 12 and 24), with a margin.
+size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
+{
+    const bool k2 = z.order == 2;
+    const double n1l = k2 ? 20 : 6, n2l = k2 ? 15 : 4, n0l = k2 ? 10 : 4;
+    const double nt = (double)z.nt, N1 = (double)z.n1, N1i = (double)z.n1_int, N2 = (double)z.n2,
+                 N0i = (double)z.n0_int;
+    const double nnzA = N1i * (k2 ? 46.0 : 17.0), nnzK = N2 * (k2 ? 13.0 : 3.0), nnzG = N0i * (k2 ? 25.0 : 15.0);
+    const double rs = mixed ? 4 : 8;
+    auto csr = [](double rows, double nnz) { return (rows + 1) * 8 + nnz * 12 + 256; };
+    // A and *eps, with 2x2 block copies at order 2; K, K^T *nu, G^T
+    double ops = 2 * csr(N1i, nnzA) + (mixed ? nnzA * 4 : 0) + 2 * csr(N2, nnzK) + csr(N0i, nnzG);
+    ops = ops - csr(N2, nnzK) + csr(N1i, nnzK);  // K^T *nu has N1_int rows
+    if (k2) ops += 2 * ((N1i / 2 + 1) * 8 + nnzA * 9 + 256) + (mixed ? nnzA * 4 : 0);
+    const double precond = (k2 ? 2 : 1) * N1i * (8 + (mixed ? 4 : 0));
+    const double inc = (N1i + 1) * 8 + nt * n1l * 4 + (N0i + 1) * 8 + nt * n0l * 4;
+    const double mesh = nt * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
+    double vecs = (N1 + N2) * 8 + 2 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
+                  (mixed ? 5 * N1i * 4 : 0) + N2 * 8 + 4 * N0i * 8;
+    vecs += (std::max({N1i, N2, N0i, 1.0}) / 4 + 1024) * 32 + 512;
+    const double tets = nt * (n1l + n0l) * 8 + 5 * (nt + 1) * 4 + (double)CONT_BLOCKS * 32 + 4096;
+    const double cap = (double)std::max<int64_t>(n, 1);
+    const double parts = 2 * cap * (6 * 8 + 18 * rs + 8);
+    auto sorts = [&](double c) {
+        const double hn = (double)sort_hist_entries((int64_t)c);
+        const double tmp = (double)std::max({scan_tmp_entries((int64_t)hn), scan_tmp_entries((int64_t)c),
+                                             scan_tmp_entries(z.nt)});
+        return 4 * c * 4 + hn * 4 + tmp * 4 + 64;
+    };
+    const double pool_cap = std::max(cap + std::floor(cap / 2), 65536.0);
+    const double pool = pool_cap * (n1l * 8 + 16) + sorts(pool_cap);
+    const double queue = cap * (4 + 4 + sizeof(ContRec) + 1 + 4) + cap + 16 +
+                         (2 * (cap / 4096 + 1) + (double)scan_tmp_entries((int64_t)(cap / 4096 + 1))) * 4 + 64;
+    // every buffer is at least 16 bytes; a generous allowance for the few dozen small ones
+    const double small = 64 * 1024;
+    return (size_t)(ops + precond + inc + mesh + vecs + tets + parts + sorts(cap) + pool + queue + small);
+}
+
+FootprintSizes kuhn_sizes(int order, double nt)
+{
+    const double N = std::cbrt(std::max(nt, 1.0) / 6.0);
+    const double V = std::pow(N + 1.0, 3), T = 6.0 * N * N * N;
+    const double E = 3.0 * N * (N + 1.0) * (N + 1.0) + 3.0 * N * N * (N + 1.0) + N * N * N;
+    const double F = 12.0 * N * N * N + 6.0 * N * N;
+    const double N1 = order == 1 ? E : 2 * E + 2 * F, N2 = order == 1 ? F : 3 * F + 3 * T;
+    const double N0 = order == 1 ? V : V + E;
+    auto up = [](double x) { return (int64_t)std::ceil(x); };
+    return FootprintSizes{order, up(T), up(N1), up(N1), up(N2), up(N0)};
+}
+
 size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
 {
-    const size_t rs = mixed ? 4 : 8;
-    const double nnzA = (double)m.N1_int * (m.order == 1 ? 16.0 : 44.0);
-    const double nnzC = (double)m.N1_int * (m.order == 1 ? 10.0 : 30.0);
-    size_t ops = (size_t)((2 * nnzA + nnzC) * 12 + (mixed ? nnzA * 4 : 0) + (double)m.N2 * 8 * 12 +
-                          (double)m.N0_int * 40 * 12);
-    size_t vecs = (size_t)(m.N1 * 8 * 14 + m.N2 * 8 * 4 + m.nt * (16 * 8 + 4 * 4 + (m.n1l + m.n2l + m.n0l) * 4));
-    size_t parts = (size_t)n * 2 * (6 * 8 + 18 * rs + 8);
-    // sort buffers, spill pool (1.5 n slots), continuation queue (record + flag, position, index, counts)
-    size_t sorts = (size_t)n * 4 * 6 + (size_t)(n * 1.5) * (m.n1l * 8 + 16 + 24) + (size_t)n * (sizeof(ContRec) + 25) +
-                   (size_t)m.nt * 16;
-    size_t tets = (size_t)m.nt * (m.n1l + m.n0l) * 8;
-    return ops + vecs + parts + sorts + tets + (64 << 20);
+    return footprint_bytes(FootprintSizes{m.order, m.nt, m.N1, m.N1_int, m.N2, m.N0_int}, n, mixed);
 }
 
 void check_params(const fempic_params &p)
 {
     if (p.precision != FEMPIC_FP64 && p.precision != FEMPIC_MIXED) throw Error(FEMPIC_EINVAL, "bad precision");
     if (!(p.dt > 0) || !std::isfinite(p.dt)) throw Error(FEMPIC_EINVAL, "dt must be positive");
-    if (p.gamma != 0.5 || p.beta != 0.25) throw Error(FEMPIC_EINVAL, "only gamma = 1/2, beta = 1/4 is supported");
+    // the unconditionally stable members of the Newmark-beta family: 2 beta >= gamma >= 1/2
+    if (!std::isfinite(p.gamma) || !std::isfinite(p.beta) || !(p.gamma >= 0.5) || !(2.0 * p.beta >= p.gamma) ||
+        p.gamma > 1e6)
+        throw Error(FEMPIC_EINVAL, "Newmark-beta needs 2 beta >= gamma >= 1/2");
     if (!(p.pcg_rtol > 0) || p.pcg_maxit < 1) throw Error(FEMPIC_EINVAL, "bad solver settings");
-    if (p.particle_bc != FEMPIC_REFLECT) throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
+    if (p.particle_bc != FEMPIC_REFLECT && p.particle_bc != FEMPIC_ABSORB)
+        throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
     if (p.gauss_every < 0) throw Error(FEMPIC_EINVAL, "gauss_every must be >= 0");
 }
 
@@ -1301,7 +1542,7 @@ void check_params(const fempic_params &p)
 using namespace fempic;
 
 struct fempic_mesh_s {
-    std::unique_ptr<HostMesh> m;
+    std::shared_ptr<const HostMesh> m;  // runs made on the mesh hold it too
 };
 struct fempic_run_s {
     std::unique_ptr<Run> r;
@@ -1338,14 +1579,8 @@ int32_t fempic_mesh_create(const double *xyz, int64_t n_vert, const int64_t *tet
 {
     API_BEGIN
     if (!out) throw Error(FEMPIC_EINVAL, "null out");
-    auto *h = new fempic_mesh_s();
-    try {
-        h->m.reset(build_mesh(xyz, n_vert, tet4, n_tet, order));
-    } catch (...) {
-        delete h;
-        throw;
-    }
-    *out = h;
+    std::shared_ptr<const HostMesh> m(build_mesh(xyz, n_vert, tet4, n_tet, order));
+    *out = new fempic_mesh_s{std::move(m)};
     API_END
 }
 
@@ -1353,14 +1588,8 @@ int32_t fempic_mesh_create_cube(int32_t N, double L, int32_t order, fempic_mesh 
 {
     API_BEGIN
     if (!out) throw Error(FEMPIC_EINVAL, "null out");
-    auto *h = new fempic_mesh_s();
-    try {
-        h->m.reset(build_cube(N, L, order));
-    } catch (...) {
-        delete h;
-        throw;
-    }
-    *out = h;
+    std::shared_ptr<const HostMesh> m(build_cube(N, L, order));
+    *out = new fempic_mesh_s{std::move(m)};
     API_END
 }
 
@@ -1402,7 +1631,7 @@ int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *h
     check_params(p);
     auto *h = new fempic_run_s();
     try {
-        h->r.reset(new Run(*mesh->m, p, (hipStream_t)hip_stream));
+        h->r.reset(new Run(mesh->m, p, (hipStream_t)hip_stream));
     } catch (...) {
         delete h;
         throw;
@@ -1478,6 +1707,14 @@ int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n)
     API_END
 }
 
+int32_t fempic_rho_get(fempic_run run, double *rho, double *rho0, int64_t n)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->rho_get(rho, rho0, n);
+    API_END
+}
+
 int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *tet, int64_t n)
 {
     API_BEGIN
@@ -1533,6 +1770,9 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     fempic_stats_t s{};
     s.steps = r.steps_done;
     s.n_particles = r.np;
+    s.n_loaded = r.np_loaded;
+    s.absorbed = r.last_absorb;
+    s.absorbed_total = r.absorbed_total;
     s.particle_ms = r.last_particle_ms;
     s.particle_kernel_ms = r.last_kernel_ms;
     s.continue_kernel_ms = r.last_continue_ms;
@@ -1546,15 +1786,28 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.gauss_step = r.gauss_step;
     s.a_rows = r.m.N1_int;
     s.a_nnz = r.a_nnz;
+    s.device_bytes = (int64_t)r.account().bytes;
+    s.device_peak_bytes = (int64_t)r.account().peak;
     *out = s;
     API_END
 }
 
-int32_t fempic_footprint(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes)
+int32_t fempic_footprint_mesh(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes)
 {
     API_BEGIN
-    if (!mesh || !bytes || n_particles < 0) throw Error(FEMPIC_EINVAL, "bad argument");
+    if (!mesh || !bytes || n_particles < 0 || (precision != FEMPIC_FP64 && precision != FEMPIC_MIXED))
+        throw Error(FEMPIC_EINVAL, "bad argument");
     *bytes = Run::footprint_estimate(*mesh->m, n_particles, precision == FEMPIC_MIXED);
+    API_END
+}
+
+int32_t fempic_footprint(int32_t order, int64_t n_tet, int64_t n_particles, int32_t precision, size_t *bytes)
+{
+    API_BEGIN
+    if (!bytes || (order != 1 && order != 2) || n_tet < 1 || n_particles < 0 ||
+        (precision != FEMPIC_FP64 && precision != FEMPIC_MIXED))
+        throw Error(FEMPIC_EINVAL, "bad argument");
+    *bytes = footprint_bytes(kuhn_sizes(order, (double)n_tet), n_particles, precision == FEMPIC_MIXED);
     API_END
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -17,19 +18,37 @@ void set_device_allocator(fempic_alloc_fn a, fempic_free_fn f, void *ctx);
 // EINVAL for parameters outside what the library supports
 void check_params(const fempic_params &p);
 
+// Device bytes held by one run's buffers, their peak, and an optional cap
+// (0: none).  A buffer made while an account is current (AccountScope on this
+// thread) is charged to it until it is freed; a buffer that would take the
+// account past its cap is refused with ENOMEM.
+struct DevAccount {
+    size_t bytes = 0, peak = 0, limit = 0;
+};
+// makes `a` the account of the buffers this thread allocates during the scope
+struct AccountScope {
+    explicit AccountScope(DevAccount *a);
+    ~AccountScope();
+    AccountScope(const AccountScope &) = delete;
+    AccountScope &operator=(const AccountScope &) = delete;
+    DevAccount *prev;
+};
+
 // device buffer; freed with the allocator that made it
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     fempic_free_fn fr = nullptr;  // null: hipFree
     void *fr_ctx = nullptr;
+    DevAccount *acct = nullptr;   // charged account, if any
     DevBuf() = default;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), fr(o.fr), fr_ctx(o.fr_ctx)
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), fr(o.fr), fr_ctx(o.fr_ctx), acct(o.acct)
     {
         o.p = nullptr;
         o.bytes = 0;
         o.fr = nullptr;
         o.fr_ctx = nullptr;
+        o.acct = nullptr;
     }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -50,7 +69,10 @@ struct PBufs {
 
 class Run {
   public:
-    Run(const HostMesh &m, const fempic_params &p, hipStream_t s);
+    // the run shares ownership of its mesh, so destroying the caller's mesh
+    // handle while the run lives leaves the run intact
+    // byte_limit: cap of the run's device bytes (0: none), see set_byte_limit
+    Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream_t s, size_t byte_limit = 0);
     ~Run();
     void load(const double *pos, const double *vel, int64_t n, double q, double m, double w);
     void step(int n_steps);
@@ -59,13 +81,19 @@ class Run {
     void fields_get(double *e, int64_t ne, double *b, int64_t nb);
     void fields_set(const double *e, int64_t ne, const double *b, int64_t nb);
     void deposit_get(double *dg, int64_t n);
+    void rho_get(double *rho, double *rho0, int64_t n);
     void particles_get(double *pos, double *vel, int64_t *tet, int64_t n);
     void history_get(double *vh, double *ah, int64_t n);
     void save(const char *path);
     void restore(const char *path);
     void set_log(const char *path);
     static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
+    // refuse (ENOMEM) any allocation that would take the run's device bytes past `bytes` (0: no cap)
+    void set_byte_limit(size_t bytes) { acct.limit = bytes; }
+    const DevAccount &account() const { return acct; }
 
+    DevAccount acct;  // before every buffer member: destroyed after them
+    std::shared_ptr<const HostMesh> mesh_hold;
     const HostMesh &m;
     fempic_params prm;
     hipStream_t stream = nullptr;
@@ -75,7 +103,9 @@ class Run {
     GLRule gl{};
     DevMesh dm{};
     // statistics
-    int64_t np = 0, steps_done = 0, last_cross = 0, last_refl = 0, last_spill = 0;
+    // np: particles in the run now; np_loaded: at load (absorbed ones leave np)
+    int64_t np = 0, np_loaded = 0, steps_done = 0, last_cross = 0, last_refl = 0, last_spill = 0;
+    int64_t last_absorb = 0, absorbed_total = 0;
     double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
     int64_t nnz_total = 0, a_nnz = 0;
@@ -95,11 +125,15 @@ class Run {
     int tpw() const;
     const uint32_t *sort_current();
     void locate_host(const double *pos, int64_t n, int32_t *out);
-    void compute_rho(double *dst);
+    void compute_rho(double *dst, double *Pr = nullptr);
+    const PBufs &gather_current();
+    void gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *partial, double *out4,
+                    double out[3]);
     void particle_phase();
     void next_order(int64_t nrec, const uint32_t *srec);
     void commit_order();
     void field_phase();
+    void field_phase_three_level();
     void solve_fp64();
     void solve_mixed();
     double read_sc(int k);
@@ -108,13 +142,18 @@ class Run {
     DevCSRBuf A, Meps, Ct, K, Gt;
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
+    // three-level Newmark-beta (gamma, beta other than 1/2, 1/4): e^{n-1}, b^{n-1},
+    // g^n - g^{n-1}, and whether they hold a step yet (else the history is at rest)
+    bool three_level = false, have_prev = false;
+    DevBuf d_eprev, d_bprev, d_dgprev, v_b2;
     DevBuf v_x, v_r, v_z, v_p, v_q, v_rhs, v_tmp, v_u;
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_ctl, d_cntb, d_args;
     // d_ctl holds the step's control words, read back in one copy:
-    // [0, 32) counters (int64 x 4), [32, 64) small (int32 x 8: 0 appended spill
-    // slots, 2 spill records, 6 queued paths), [64, 72) particle-order error
+    // [0, 64) counters (int64 x NCNT), [64, 96) small (int32 x 8: 0 appended spill
+    // slots, 2 spill records, 6 queued paths), [96, 104) particle-order error
+    static constexpr int CTL_SMALL = 8 * NCNT, CTL_PERR = CTL_SMALL + 32, CTL_BYTES = CTL_PERR + 8;
     unsigned long long *p_cnt = nullptr, *p_perr = nullptr;
     int32_t *p_small = nullptr;
     DevBuf d_pool_val, d_pool_tet, d_pool_tag, d_pool_pid, d_rcount, d_rpos, d_cq, d_qflag, d_qtmp, d_qidx;

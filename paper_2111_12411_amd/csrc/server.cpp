@@ -37,23 +37,10 @@ struct Job {
     double gauss[3] = {0, 0, 0};
 };
 
+// the same estimate as fempic_footprint for the N^3 Kuhn cube
 size_t cube_footprint(int N, int order, int64_t n, bool mixed)
 {
-    // Kuhn cube counts in closed form
-    const double V = std::pow(N + 1.0, 3), T = 6.0 * N * N * N;
-    const double E = 3.0 * N * (N + 1.0) * (N + 1.0) + 3.0 * N * N * (N + 1.0) + (double)N * N * N;
-    const double F = 12.0 * N * N * N + 6.0 * N * N;
-    const double N1 = order == 1 ? E : 2 * E + 2 * F, N2 = order == 1 ? F : 3 * F + 3 * T;
-    const double N0 = order == 1 ? V : V + E;
-    const int n1l = order == 1 ? 6 : 20, n2l = order == 1 ? 4 : 15, n0l = order == 1 ? 4 : 10;
-    const size_t rs = mixed ? 4 : 8;
-    const double nnzA = N1 * (order == 1 ? 16.0 : 44.0), nnzC = N1 * (order == 1 ? 10.0 : 30.0);
-    double ops = (2 * nnzA + nnzC) * 12 + (mixed ? nnzA * 4 : 0) + N2 * 8 * 12 + N0 * 40 * 12;
-    double vecs = N1 * 8 * 14 + N2 * 8 * 4 + T * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
-    double parts = (double)n * 2 * (6 * 8 + 18 * rs + 8);
-    double sorts = (double)n * 24 + n * 1.5 * (n1l * 8 + 40) + (double)n * (sizeof(ContRec) + 25) + T * 16;
-    double tets = T * (n1l + n0l) * 8;
-    return (size_t)(ops + vecs + parts + sorts + tets) + (64u << 20);
+    return footprint_bytes(kuhn_sizes(order, 6.0 * N * N * N), n, mixed);
 }
 
 }  // namespace
@@ -77,8 +64,9 @@ struct fempic_server_s {
         (void)hipSetDevice(device);
         int32_t st = FEMPIC_OK;
         try {
-            std::unique_ptr<HostMesh> mesh(build_cube(j->spec.N, j->spec.L, j->spec.order));
-            Run run(*mesh, j->spec.params, nullptr);
+            std::shared_ptr<const HostMesh> mesh(build_cube(j->spec.N, j->spec.L, j->spec.order));
+            // the run may not grow past what the job was admitted with
+            Run run(mesh, j->spec.params, nullptr, j->footprint);
             run.load(j->pos.data(), j->vel.data(), j->spec.n, j->spec.q, j->spec.m, j->spec.w);
             for (int s = 0; s < j->spec.n_steps; s++) {
                 run.step(1);
@@ -176,7 +164,7 @@ int32_t fempic_submit(fempic_server s, const fempic_job *job, int64_t *ticket)
 {
     API_TRY
     if (!s || !job || !ticket) throw Error(FEMPIC_EINVAL, "null argument");
-    if (job->N < 1 || (job->order != 1 && job->order != 2) || job->n < 0 || job->n_steps < 0 ||
+    if (job->N < 1 || job->N > CUBE_N_MAX || (job->order != 1 && job->order != 2) || job->n < 0 || job->n_steps < 0 ||
         (job->n > 0 && (!job->pos || !job->vel)))
         throw Error(FEMPIC_EINVAL, "bad job");
     check_params(job->params);

@@ -73,9 +73,11 @@ def test_generic_mesh_and_errors():
 def test_run_rejects_bad_params_without_gpu():
     m = F.Mesh.cube(2, 1)
     h = F.C.c_void_p()
-    p = F.params(1e-11)
-    p.gamma = 1.5
-    assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+    # Newmark-beta outside the unconditionally stable family 2 beta >= gamma >= 1/2
+    for gamma, beta in ((0.4, 0.25), (1.5, 0.7), (float("nan"), 0.25), (0.5, float("inf"))):
+        p = F.params(1e-11, gamma=gamma, beta=beta)
+        assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+        assert "Newmark" in F.lib().fempic_last_error().decode()
     p = F.params(-1.0)
     assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
 
@@ -124,6 +126,7 @@ def test_null_handles_are_einval_without_gpu():
         lambda: L.fempic_fields_set(None, buf, 1, buf, 1),
         lambda: L.fempic_deposit_get(None, buf, 1),
         lambda: L.fempic_particles_get(None, buf, buf, None, 1),
+        lambda: L.fempic_rho_get(None, buf, buf, 1),
         lambda: L.fempic_history_get(None, buf, buf, 1),
         lambda: L.fempic_run_save(None, b"x"),
         lambda: L.fempic_run_load(None, b"x"),
@@ -135,3 +138,33 @@ def test_null_handles_are_einval_without_gpu():
         assert call() == -1
         assert L.fempic_last_error().decode() != ""
     assert L.fempic_run_destroy(None) == 0  # destroying NULL is a no-op
+
+
+@pytest.mark.parametrize("N,k", [(2, 1), (5, 2), (12, 1), (20, 2)])
+def test_footprint_by_tet_count_equals_mesh_footprint_for_cubes(N, k):
+    """fempic_footprint(order, n_tet, n, precision) is the estimate of the N^3 cube's own counts."""
+    m = F.Mesh.cube(N, k)
+    for prec in (F.FP64, F.MIXED):
+        for n in (0, 1000, 3_000_000):
+            a = F.footprint(k, 6 * N ** 3, n, prec)
+            b = m.footprint(n, prec)
+            # the by-count form takes totals for interior counts, so it may only be larger
+            assert b <= a <= 1.3 * b + (1 << 20), (N, k, prec, n, a, b)
+    assert F.footprint(k, 6 * N ** 3, 10 ** 6, F.FP64) > F.footprint(k, 6 * N ** 3, 10 ** 6, F.MIXED)
+
+
+def test_footprint_arguments_and_cube_bound_without_gpu():
+    L = F.lib()
+    out = F.C.c_size_t()
+    assert L.fempic_footprint(3, 100, 10, F.FP64, F.C.byref(out)) == -1
+    assert L.fempic_footprint(1, 0, 10, F.FP64, F.C.byref(out)) == -1
+    assert L.fempic_footprint(1, 100, -1, F.FP64, F.C.byref(out)) == -1
+    assert L.fempic_footprint(1, 100, 10, 7, F.C.byref(out)) == -1
+    assert L.fempic_footprint(1, 100, 10, F.FP64, None) == -1
+    # (N+1)^3 must stay below 2^21 vertices: N = 126 is the largest cube, and a larger one is
+    # refused before anything of its size is allocated
+    with pytest.raises(F.FempicError) as ei:
+        F.Mesh.cube(127, 1)
+    assert ei.value.code == -1 and "126" in str(ei.value)
+    with pytest.raises(F.FempicError):
+        F.Mesh.cube(1024, 1)

@@ -13,15 +13,12 @@ import pytest
 import paper_2111_12411_amd as F
 from paper_2111_12411_amd import workloads as W
 from oracle import core, mesh as omesh
+from parity_util import close, rel
+from test_gpu_parity import tets_agree
 
 pytestmark = pytest.mark.gpu
 
 QE, ME = -W.Q_E, W.M_E
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def cfl(N, k):
@@ -63,9 +60,9 @@ def test_beam_order2_fp64_full_size_200_steps():
     p1, v1, t1, orc = sampled_last_step(run, m, dt, w, idx, 199)
     RG, RC, RS = run.gauss()
     assert RG < 1e-12 and RC < 1e-12, (RG, RC, RS)
-    assert rel(p1, orc.pos) < 1e-13
-    assert rel(v1, orc.vel) < 1e-12
-    assert np.mean(t1 == orc.tet) > 0.999
+    close(p1, orc.pos, 1e-13)
+    close(v1, orc.vel, 1e-12)
+    tets_agree(m, p1, t1, orc.tet)
     st = run.stats()
     assert st["steps"] == 200 and st["reflections"] > 0
     run.close()
@@ -88,9 +85,9 @@ def test_two_stream_order2_mixed_full_size():
     RG, RC, RS = run.gauss()
     assert RC < 1e-12 and RG < 1e-12, (RG, RC, RS)
     # FP32 gather and force: position to ~1e-9, velocity to ~1e-5 relative
-    assert rel(p1, orc.pos) < 1e-9
+    close(p1, orc.pos, 1e-9)
     assert rel(v1, orc.vel) < 2e-5
-    assert np.mean(t1 == orc.tet) > 0.999
+    tets_agree(m, p1, t1, orc.tet, tol=1e-9)
     assert run.stats()["steps"] == 3
     run.close()
 

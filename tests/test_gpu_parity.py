@@ -1,9 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances: FP64 mode, 1e-12 relative (norm-wise, on fields, deposits and
-particle states); mixed mode, 1e-5 relative on fields after 100 steps; Gauss
+Tolerances: FP64 mode, 1e-12 relative on fields, deposits, nodal charge and
+particle states, both norm-wise and element-wise (the largest difference over
+the largest entry); mixed mode, 1e-5 relative on fields after 100 steps; Gauss
 residual R_G <= 1e-12 in both modes.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -11,15 +14,13 @@ import paper_2111_12411_amd as F
 from paper_2111_12411_amd import workloads as W
 from oracle import core, mesh as omesh
 from flux_check import relative_net_flux
+from parity_util import close, elementwise, rel
 
 pytestmark = pytest.mark.gpu
 
 QE, ME = -W.Q_E, W.M_E
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+# host threads of the chunked oracle step at full size (the GPU machine gives a share of 16)
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def cfl(N, k):
@@ -46,20 +47,27 @@ def test_c1_order1_fp64_100_steps():
     # start-up state
     vh_g, ah_g = run.history()
     assert rel(vh_g, orc.vh) < 1e-14
+    r_g, r0_g = run.rho()
+    close(r0_g, orc.rho0 * m.int0, 1e-13)
     for n in range(100):
+        c0 = orc.counters.copy()
         orc.step()
         run.step()
+        st = run.stats()
+        assert st["crossings"] == orc.counters[0] - c0[0] and st["reflections"] == orc.counters[1] - c0[1], n
         if n < 5 or n % 10 == 9:
-            assert rel(run.deposit(), orc.last_dg * m.int1) < 1e-12, n
+            close(run.deposit(), orc.last_dg * m.int1, 1e-12)
             RG, RC, RS = run.gauss()
             assert RG < 1e-12 and RC < 1e-12, (n, RG, RC, RS)
     e, b = run.fields()
     pos_g, vel_g, tet_g = run.particles()
-    assert rel(e, orc.e) < 1e-12
-    assert rel(b, orc.b) < 1e-12
-    assert rel(pos_g, orc.pos) < 1e-13
-    assert rel(vel_g, orc.vel) < 1e-12
-    assert np.mean(tet_g == orc.tet) > 0.999
+    close(e, orc.e, 1e-12)
+    close(b, orc.b, 1e-12)
+    close(pos_g, orc.pos, 1e-13)
+    close(vel_g, orc.vel, 1e-12)
+    assert np.array_equal(tet_g, orc.tet)
+    r_g, _ = run.rho()
+    close(r_g, orc.rho() * m.int0, 1e-12)
     st = run.stats()
     assert st["steps"] == 100 and st["crossings"] > 0
 
@@ -72,19 +80,31 @@ def test_fp64_beam_parity(k):
     pos, vel = W.particles("beam", 20000, 2007, vth=0.005, drift=0.1)
     w = W.plasma_weight(len(pos), dt)
     m, orc, run = pair(6, k, dt, pos, vel, w)
+    refl = 0
     for n in range(20):
+        c0 = orc.counters.copy()
         orc.step()
         run.step()
-        assert rel(run.deposit(), orc.last_dg * m.int1) < 1e-12, n
+        close(run.deposit(), orc.last_dg * m.int1, 1e-12)
+        st = run.stats()
+        # the same face crossings and wall reflections, step by step
+        assert st["crossings"] == orc.counters[0] - c0[0], n
+        assert st["reflections"] == orc.counters[1] - c0[1], n
+        refl += st["reflections"]
+    assert refl > 100
     e, b = run.fields()
-    assert rel(e, orc.e) < 1e-12 and rel(b, orc.b) < 1e-12
+    close(e, orc.e, 1e-12)
+    close(b, orc.b, 1e-12)
     # magnetic Gauss law: no net flux out of any tet
     assert relative_net_flux(m, b) < 1e-13
     pos_g, vel_g, _ = run.particles()
-    assert rel(pos_g, orc.pos) < 1e-13 and rel(vel_g, orc.vel) < 1e-12
+    close(pos_g, orc.pos, 1e-13)
+    close(vel_g, orc.vel, 1e-12)
+    vh_g, ah_g = run.history()
+    close(vh_g, orc.vh, 1e-12)
+    close(ah_g, orc.ah, 1e-12)
     RG, RC, RS = run.gauss()
     assert RG < 1e-12, (RG, RC, RS)
-    assert run.stats()["reflections"] >= 0 and orc.counters[1] > 0
 
 
 def test_ragged_and_empty_inputs():
@@ -102,10 +122,12 @@ def test_ragged_and_empty_inputs():
             orc.step()
             run.step()
         e, b = run.fields()
-        assert rel(e, orc.e) < 1e-12 and rel(b, orc.b) < 1e-12
+        close(e, orc.e, 1e-12)
+        close(b, orc.b, 1e-12)
         if n:
             pos_g, vel_g, _ = run.particles()
-            assert rel(pos_g, orc.pos) < 1e-13
+            close(pos_g, orc.pos, 1e-13)
+            close(vel_g, orc.vel, 1e-12)
 
 
 def test_random_fields_one_step_exact():
@@ -122,12 +144,14 @@ def test_random_fields_one_step_exact():
         run.set_fields(e0, b0)
         dg_o = orc.particle_step()
         run.step()
-        assert rel(run.deposit(), dg_o * m.int1) < 1e-12
+        close(run.deposit(), dg_o * m.int1, 1e-12)
         pos_g, vel_g, tet_g = run.particles()
-        assert rel(pos_g, orc.pos) < 1e-14
-        assert rel(vel_g, orc.vel) < 1e-13
+        close(pos_g, orc.pos, 1e-14)
+        close(vel_g, orc.vel, 1e-13)
+        assert np.array_equal(tet_g, orc.tet)
         vh_g, ah_g = run.history()
-        assert rel(vh_g, orc.vh) < 1e-13 and rel(ah_g, orc.ah) < 1e-13
+        close(vh_g, orc.vh, 1e-13)
+        close(ah_g, orc.ah, 1e-13)
 
 
 def test_bitwise_determinism():
@@ -158,16 +182,18 @@ def test_mixed_precision_fields_within_1e5(k):
         run.step()
     e, b = run.fields()
     assert rel(e, orc.e) < 1e-5 and rel(b, orc.b) < 1e-5, (rel(e, orc.e), rel(b, orc.b))
+    # element-wise: mixed precision moves no single DoF far either
+    assert elementwise(e, orc.e) < 1e-4 and elementwise(b, orc.b) < 1e-4, (elementwise(e, orc.e),
+                                                                          elementwise(b, orc.b))
     assert relative_net_flux(m, b) < 1e-13
     RG, RC, RS = run.gauss()
     assert RG < 1e-12, (RG, RC, RS)
 
 
-@pytest.mark.parametrize("precision,tol_x,tol_v", [(F.FP64, 1e-13, 1e-12), (F.MIXED, 1e-9, 2e-5)])
-def test_full_size_sampled(precision, tol_x, tol_v):
-    """The benchmark's launch configuration (40^3 cube, order 2, 16M electrons):
-    one step with random fields; a sample of particles against the oracle one by
-    one, and charge continuity of the whole deposit (R_C) at full size."""
+def test_full_size_benchmark_step_whole_deposit():
+    """The benchmark's launch configuration (40^3 cube, order 2, 16M electrons), FP64: one step with
+    random fields, every DoF of the deposit and every particle against the oracle (its chunked step
+    on the host's threads), and charge continuity of the whole deposit (R_C) at full size."""
     N, k, n = 40, 2, 16_000_000
     dt = 10 * cfl(N, k)
     pos, vel = W.config_particles(3)
@@ -175,23 +201,125 @@ def test_full_size_sampled(precision, tol_x, tol_v):
     m = omesh.cube_mesh(N, k)
     e0, b0 = W.random_fields(m.n1, m.n2, 303, e_scale=1e3, b_scale=1e-5)
     e0 = e0 * m.int1
-    run = F.Run(F.Mesh.cube(N, k), dt, precision, pcg_rtol=1e-14)
-    run.load(pos, vel, QE, ME, W.config_weight(3, n, dt))
+    w = W.config_weight(3, n, dt)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.FP64, pcg_rtol=1e-14)
+    run.load(pos, vel, QE, ME, w)
     run.set_fields(e0, b0)
     run.step()
+    dg_g = run.deposit()
     pos_g, vel_g, tet_g = run.particles()
     # the random initial e does not satisfy Gauss's law, so only the deposit's own
     # continuity residual R_C is meaningful here
     RG, RC, RS = run.gauss()
     assert RC < 1e-12, RC
+    run.close()
+    orc = core.OracleRun(m, dt, particles_only=True)
+    orc.load(pos, vel, QE, ME, w)
+    del pos, vel
+    orc.e, orc.b = e0.copy(), b0.copy()
+    dg_o = orc.particle_step(threads=ORACLE_THREADS)
+    close(dg_g, dg_o * m.int1, 1e-12)
+    close(pos_g, orc.pos, 1e-13)
+    close(vel_g, orc.vel, 1e-12)
+    tets_agree(m, pos_g, tet_g, orc.tet)
+
+
+def test_full_size_beam_step_whole_deposit():
+    """The beam workload at full size (20^3 cube, order 2, 1M electrons at 0.1c, FP64): two steps
+    from random fields, every DoF of each step's deposit and the particle state against the oracle."""
+    N, k = 20, 2
+    dt = 10 * cfl(N, k)
+    pos, vel = W.config_particles(2)
+    m = omesh.cube_mesh(N, k)
+    e0, b0 = W.random_fields(m.n1, m.n2, 202, e_scale=1e3, b_scale=1e-5)
+    e0 = e0 * m.int1
+    w = W.config_weight(2, len(pos), dt)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.FP64, pcg_rtol=1e-14)
+    run.load(pos, vel, QE, ME, w)
+    run.set_fields(e0, b0)
+    orc = core.OracleRun(m, dt, particles_only=True)
+    orc.load(pos, vel, QE, ME, w)
+    orc.e, orc.b = e0.copy(), b0.copy()
+    for n in range(2):
+        run.set_fields(e0, b0)  # the same fields for both steps on both sides
+        c0 = orc.counters.copy()
+        run.step()
+        dg_o = orc.particle_step(threads=ORACLE_THREADS)
+        close(run.deposit(), dg_o * m.int1, 1e-12)
+        st = run.stats()
+        assert st["crossings"] == orc.counters[0] - c0[0] and st["reflections"] == orc.counters[1] - c0[1]
+    pos_g, vel_g, tet_g = run.particles()
+    close(pos_g, orc.pos, 1e-13)
+    close(vel_g, orc.vel, 1e-12)
+    tets_agree(m, pos_g, tet_g, orc.tet)
+
+
+def test_full_size_mixed_sampled():
+    """Mixed precision at the benchmark size: a sample of particles against the FP64 oracle one by
+    one (FP32 gather and force), and the whole deposit within 1e-5."""
+    N, k, n = 40, 2, 16_000_000
+    dt = 10 * cfl(N, k)
+    pos, vel = W.config_particles(3)
+    m = omesh.cube_mesh(N, k)
+    e0, b0 = W.random_fields(m.n1, m.n2, 303, e_scale=1e3, b_scale=1e-5)
+    e0 = e0 * m.int1
+    w = W.config_weight(3, n, dt)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.MIXED, pcg_rtol=1e-14)
+    run.load(pos, vel, QE, ME, w)
+    run.set_fields(e0, b0)
+    run.step()
+    pos_g, vel_g, tet_g = run.particles()
+    RG, RC, RS = run.gauss()
+    assert RC < 1e-12, RC
     idx = np.random.default_rng(5).choice(n, 3000, replace=False)
     orc = core.OracleRun(m, dt, particles_only=True)
-    orc.load(pos[idx], vel[idx], QE, ME, 1.0)
+    orc.load(pos[idx], vel[idx], QE, ME, w)
     orc.e, orc.b = e0.copy(), b0.copy()
     orc.particle_step()
-    assert rel(pos_g[idx], orc.pos) < tol_x
-    assert rel(vel_g[idx], orc.vel) < tol_v
-    assert np.mean(tet_g[idx] == orc.tet) > 0.999
+    assert rel(pos_g[idx], orc.pos) < 1e-9
+    assert rel(vel_g[idx], orc.vel) < 2e-5
+    tets_agree(m, pos_g[idx], tet_g[idx], orc.tet, tol=1e-9)
+
+
+def tets_agree(m, pos, tet_a, tet_b, tol=1e-12):
+    """Tet ids are unique except for a particle on a face shared by two tets (either is correct):
+    where the ids differ, the position must lie in both tets up to rounding."""
+    diff = np.nonzero(tet_a != tet_b)[0]
+    assert len(diff) <= max(3, len(tet_a) // 100000), len(diff)
+    for i in diff:
+        for t in (tet_a[i], tet_b[i]):
+            lam = m.aff[t] + m.grad[t] @ pos[i]
+            assert lam.min() > -tol, (i, t, lam)
+
+
+def test_gauss_residuals_and_nodal_charge_match_the_oracle():
+    """a8: the GPU's nodal charge rho~ (now and at load) equals the oracle's DoF by DoF, and its
+    R_G, R_C, R_S stay at rounding level with the oracle's.  Negative control: a random e set on
+    both sides breaks Gauss's law, and R_G and R_S then come out O(1) and equal to the oracle's,
+    while R_C (deposit only) stays at rounding level."""
+    for k in (1, 2):
+        N = 4
+        dt = 5 * cfl(N, k)
+        pos, vel = W.particles("beam", 6000, 41 + k, vth=0.01, drift=0.1)
+        w = W.plasma_weight(len(pos), dt)
+        m, orc, run = pair(N, k, dt, pos, vel, w)
+        for n in range(10):
+            orc.step()
+            run.step()
+        rho_g, rho0_g = run.rho()
+        close(rho0_g, orc.rho0 * m.int0, 1e-13)
+        close(rho_g, orc.rho() * m.int0, 1e-12)
+        g_gpu = run.gauss()
+        g_orc = orc.gauss_residuals()
+        assert max(g_gpu) < 1e-12 and max(g_orc) < 1e-12, (g_gpu, g_orc)
+        e_bad = np.random.default_rng(9).normal(size=m.n1) * m.int1 * np.abs(orc.e).max()
+        orc.e = e_bad.copy()
+        run.set_fields(e_bad, orc.b)
+        g_gpu = run.gauss()
+        g_orc = orc.gauss_residuals()
+        assert g_orc[0] > 1e-3 and g_orc[2] > 1e-3 and g_orc[1] < 1e-12, g_orc
+        assert g_gpu[0] == pytest.approx(g_orc[0], rel=1e-10) and g_gpu[2] == pytest.approx(g_orc[2], rel=1e-10)
+        assert g_gpu[1] < 1e-12, g_gpu
 
 
 def test_failure_modes():
