@@ -174,6 +174,20 @@ int32_t fempic_sync(fempic_run run);
  * the gradient matrix (grad W0_j = sum_i G_ij W1_i).  Synchronises. */
 int32_t fempic_gauss_residual(fempic_run run, double out[3]);
 
+/* fempic_gauss_residual without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same values, bit for bit, as
+ * fempic_gauss_residual.  Its intermediates (per-tet partial charges, the
+ * nodal vectors, reduction partials) live in a static device array of the
+ * library, 64 MiB on every device it runs on, held until the process ends.
+ * Nothing is allocated: no hipMalloc, no installed allocator, no library
+ * routine that allocates.  EINVAL when the run's mesh needs more scratch than
+ * that (8 n_tet n0_loc + 24 n0_int + 8 n1_int bytes and 64 KiB: up to about the
+ * 40^3 cube at order 2).  Every call on a device shares that device's array, so
+ * calls that overlap on one device (runs on different streams or threads) race
+ * and must be serialised by the caller.  Synchronises the run's stream. */
+int32_t fempic_gauss_residual_noalloc(fempic_run run, double out[3]);
+
 /* Copy fields out / in (natural numbering; e has n1 entries, b has n2).
  * fields_set zeroes e on the PEC walls; EINVAL for a non-finite coefficient. */
 int32_t fempic_fields_get(fempic_run run, double *e, int64_t ne, double *b, int64_t nb);

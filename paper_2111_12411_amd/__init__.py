@@ -77,6 +77,7 @@ SYMBOLS = {
     "fempic_step": (C.c_int32, [C.c_void_p, C.c_int32]),
     "fempic_sync": (C.c_int32, [C.c_void_p]),
     "fempic_gauss_residual": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fempic_gauss_residual_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_fields_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_fields_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_deposit_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -243,6 +244,12 @@ class Run:
     def gauss(self):
         out = np.zeros(3)
         _check(lib().fempic_gauss_residual(self.h, _p(out)))
+        return out
+
+    def gauss_noalloc(self):
+        """fempic_gauss_residual_noalloc: the same check with nothing allocated."""
+        out = np.zeros(3)
+        _check(lib().fempic_gauss_residual_noalloc(self.h, _p(out)))
         return out
 
     def fields(self):

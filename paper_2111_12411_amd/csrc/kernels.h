@@ -220,6 +220,15 @@ hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStr
 hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
                        double *partial, double *out4, hipStream_t s);
 hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s);
+// entries of the partial-sum buffer that gauss_norms and dot_det use at most
+int64_t gauss_partial_entries();
 
+// Device scratch of the entry point that allocates nothing
+// (fempic_gauss_residual_noalloc): NOALLOC_SCRATCH_BYTES on every device, held
+// until the process ends.  noalloc_scratch gives its address on the current
+// device (looked up on the first call per device, then kept).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(void **ptr);
 
 }  // namespace fempic

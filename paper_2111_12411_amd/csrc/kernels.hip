@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.h"
@@ -2281,6 +2282,36 @@ hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial,
     hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, a, b, partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 1, out);
     return hipGetLastError();
+}
+
+int64_t gauss_partial_entries() { return 4 * (int64_t)RED_BLOCKS; }
+
+// --------------------------------------------------- no-allocation scratch
+// Device memory of the entry point that allocates nothing: one array per
+// device (every device the library runs on holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and kept.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace fempic

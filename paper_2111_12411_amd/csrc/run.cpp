@@ -219,6 +219,7 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
 {
     acct.limit = byte_limit;
     AccountScope charge(&acct);
+    HIPCHECK(hipGetDevice(&device));
     if (s) {
         stream = s;
         own_stream = false;
@@ -1019,6 +1020,45 @@ void Run::gauss(double out[3])
                (double *)d_partial.p, (double *)d_sc.p + 16, out);
 }
 
+// The Gauss check with every intermediate in the library's static device
+// scratch (kernels.hip): nothing is allocated, on the device or through the
+// installed allocator.  Concurrent calls on one device share that scratch.
+void Run::gauss_noalloc(double out[3])
+{
+    Range rg("fempic gauss residual without allocation (a8)");
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    int cur_dev = 0;
+    HIPCHECK(hipGetDevice(&cur_dev));
+    if (cur_dev != device) HIPCHECK(hipSetDevice(device));
+    struct Restore {
+        int dev, run_dev;
+        ~Restore()
+        {
+            if (dev != run_dev) (void)hipSetDevice(dev);
+        }
+    } restore{cur_dev, device};
+    void *base = nullptr;
+    HIPCHECK(noalloc_scratch(&base));
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t n0 = (size_t)std::max<int64_t>(m.N0_int, 1), n1 = (size_t)std::max<int64_t>(m.N1_int, 1);
+    const size_t b_pr = al((size_t)m.nt * n0l * 8), b_v0 = al(n0 * 8), b_v1 = al(n1 * 8),
+                 b_part = al((size_t)gauss_partial_entries() * 8);
+    const size_t need = b_pr + 3 * b_v0 + b_v1 + b_part + 256;
+    if (need > NOALLOC_SCRATCH_BYTES)
+        throw Error(FEMPIC_EINVAL, "the Gauss check of this mesh needs " + std::to_string(need) +
+                                       " bytes of scratch; the library's static scratch holds " +
+                                       std::to_string(NOALLOC_SCRATCH_BYTES));
+    char *p = (char *)base;
+    double *Pr = (double *)p;
+    double *rho = (double *)(p += b_pr);
+    double *GtDe = (double *)(p += b_v0);
+    double *Gtg = (double *)(p += b_v0);
+    double *y1 = (double *)(p += b_v0);
+    double *part = (double *)(p += b_v1);
+    double *out4 = (double *)(p += b_part);
+    gauss_with(Pr, rho, GtDe, Gtg, y1, part, out4, out);
+}
+
 void Run::gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *partial, double *out4,
                      double out[3])
 {
@@ -1677,6 +1717,18 @@ int32_t fempic_gauss_residual(fempic_run run, double out[3])
     if (!run || !out) throw Error(FEMPIC_EINVAL, "null argument");
     double v[3];
     run->r->gauss(v);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    API_END
+}
+
+int32_t fempic_gauss_residual_noalloc(fempic_run run, double out[3])
+{
+    API_BEGIN
+    if (!run || !out) throw Error(FEMPIC_EINVAL, "null argument");
+    double v[3];
+    run->r->gauss_noalloc(v);
     out[0] = v[0];
     out[1] = v[1];
     out[2] = v[2];

@@ -78,6 +78,9 @@ class Run {
     void step(int n_steps);
     void sync();
     void gauss(double out[3]);
+    // the same check with its intermediates in the library's static device
+    // scratch: allocates nothing (EINVAL when the mesh needs more than it holds)
+    void gauss_noalloc(double out[3]);
     void fields_get(double *e, int64_t ne, double *b, int64_t nb);
     void fields_set(const double *e, int64_t ne, const double *b, int64_t nb);
     void deposit_get(double *dg, int64_t n);
@@ -98,6 +101,7 @@ class Run {
     fempic_params prm;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;  // the HIP device the run was made on
     bool mixed = false;
     int order = 1, n1l = 0, n2l = 0, n0l = 0;
     GLRule gl{};

@@ -122,6 +122,7 @@ def test_null_handles_are_einval_without_gpu():
         lambda: L.fempic_step(None, 1),
         lambda: L.fempic_sync(None),
         lambda: L.fempic_gauss_residual(None, buf),
+        lambda: L.fempic_gauss_residual_noalloc(None, buf),
         lambda: L.fempic_fields_get(None, buf, 1, buf, 1),
         lambda: L.fempic_fields_set(None, buf, 1, buf, 1),
         lambda: L.fempic_deposit_get(None, buf, 1),
