@@ -140,3 +140,62 @@ def test_explicit_bound_against_dense_global_eigensolve(N, k):
     S1 = ops.Kloc.T @ ops.M2_el[0] @ ops.Kloc / core.MU0
     one = sla.eigh(S1, M1, eigvals_only=True)[-1]
     assert one <= (2.0 / dt_elem) ** 2 * (1 + 1e-12)
+
+
+# ------------------------------------------------------------ absorbing walls
+@pytest.mark.parametrize("k", [1, 2])
+def test_absorbed_particle_ends_at_the_wall_point_and_carries_its_charge_away(k):
+    """Field-free particle into the wall x = 1 with the absorbing rule: it leaves the run (tet -1) at
+    the closed-form point where its straight path meets the wall, and its deposit moves exactly its
+    own charge off the interior nodes: G^T dg = -q w W0(r0) there (the interior W0 vanish on walls)."""
+    m = omesh.cube_mesh(4, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    run = core.OracleRun(m, dt, ops, absorb=True)
+    p0 = np.array([0.93, 0.47, 0.52])
+    v0 = np.array([0.12, 0.035, -0.02]) / dt
+    run.load(p0[None], v0[None], QE, ME, 1.0)
+    rho0 = run.rho().copy()
+    dg = run.particle_step()
+    assert run.tet[0] == -1 and run.counters[2] == 1 and run.counters[1] == 0
+    s = (1.0 - p0[0]) / (v0[0] * dt)
+    np.testing.assert_allclose(run.pos[0], p0 + s * v0 * dt, rtol=0, atol=1e-15)
+    i0 = ops.int0
+    np.testing.assert_allclose((ops.G.T @ dg)[i0], -rho0[i0], rtol=0, atol=1e-14 * abs(QE))
+    assert np.all(run.rho() == 0.0)  # no particle is left to measure
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_absorbing_run_keeps_gauss_law_and_leaves_other_particles_alone(k):
+    """A beam into the z walls: particles leave every step, R_G and R_C stay at rounding level; with
+    the fields held fixed, the particles that never reach a wall move exactly as under reflection."""
+    m = omesh.cube_mesh(3, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    pos, vel = W.particles("beam", 1500, 61 + k, vth=0.01, drift=0.15)
+    run = core.OracleRun(m, dt, ops, absorb=True)
+    run.load(pos, vel, QE, ME, W.plasma_weight(len(pos), dt))
+    for n in range(12):
+        run.step()
+        RG, RC, RS = run.gauss_residuals()
+        assert RG < 1e-12 and RC < 1e-12, (n, RG, RC, RS)
+    gone = run.tet < 0
+    assert gone.mean() > 0.5 and run.counters[2] == gone.sum()
+    # fixed random fields, particles only: absorbing and reflecting runs agree on the particles
+    # that stay inside
+    e0, b0 = W.random_fields(m.n1, m.n2, 8, e_scale=1e3, b_scale=1e-5)
+    runs = []
+    for absorb in (True, False):
+        r = core.OracleRun(m, dt, ops, absorb=absorb, particles_only=True)
+        r.load(pos, vel, QE, ME, 1.0)
+        r.e, r.b = e0 * m.int1, b0
+        for _ in range(5):
+            r.particle_step()
+        runs.append(r)
+    a, rf = runs
+    alive = a.tet >= 0
+    assert (~alive).sum() > 50 and rf.counters[1] > 50
+    # reflected particles may later differ; those that never met a wall are bit-identical
+    same = np.all(a.pos[alive] == rf.pos[alive], axis=1)
+    assert same.mean() > 0.95
+    assert np.array_equal(a.tet[alive][same], rf.tet[alive][same])
