@@ -40,6 +40,41 @@ def algorithmic_bytes(order, precision, n_particles, n_tet):
     return 2 * state * n_particles + per_tet * n_tet, state, per_tet
 
 
+def survey_bytes(order, precision, n_particles, n_tet, n1_int):
+    """Algorithmic bytes of one particle phase (gather, push, track, deposit) in the model of the
+    hot-path scope: particle state read and written once (r, v, the AB4 histories and the tet:
+    196 B in FP64, 112 B in mixed precision with FP32 velocity and histories), per tet the field
+    DoFs and geometry read once (516 B at order 2, 216 B at order 1) and the deposit partials
+    written and read once (320 B, 96 B), and the deposit dg written once (8 B per interior W1 DoF).
+    Sort traffic and spill records are not counted: they count against the implementation."""
+    state = 196 if precision == F.FP64 else 112
+    per_tet = (516 + 320) if order == 2 else (216 + 96)
+    return 2 * state * n_particles + per_tet * n_tet + 8 * n1_int, state, per_tet
+
+
+def copy_bandwidth(gib=2, reps=5):
+    """Measured device-to-device copy bandwidth (read + write bytes per second, GB/s) of a plain
+    torch copy of `gib` GiB, the best of `reps` timed copies."""
+    import torch
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        t = a.elapsed_time(b) / 1e3
+        best = t if best is None else min(best, t)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / best / 1e9
+
+
 def pcg_bytes_per_iter(order, precision, rows, nnz):
     """Bytes one inner PCG iteration must move: q = A p with the fused dot(p, q); x, r and the
     preconditioned residual z updated with dot(r, z); p = z + beta p.  Order 2 stores A in 2x2
@@ -77,7 +112,10 @@ def profiled_traffic():
     return float(m1.group(1)) if h.hexdigest() == m2.group(1) else None
 
 
-def run_workload(cfg_id, precision, steps, warmup, n=None, order=None, gauss_every=0, log=None):
+def run_workload(cfg_id, precision, steps, warmup, n=None, order=None, gauss_every=0, log=None, blocks=1):
+    """Load the workload, take `warmup` steps, then time `steps` steps in `blocks` consecutive
+    blocks; per block the device time of the particle phase and of its kernels (HIP events on the
+    library's stream) comes from the run's statistics."""
     cfg = W.CONFIGS[cfg_id]
     N, k = cfg["N"], (cfg["order"] if order is None else order)
     mesh = F.Mesh.cube(N, k)
@@ -95,17 +133,23 @@ def run_workload(cfg_id, precision, steps, warmup, n=None, order=None, gauss_eve
     del pos, vel
     run.step(warmup)
     run.sync()
+    sizes = [steps // blocks + (1 if b < steps % blocks else 0) for b in range(blocks)]
+    per_block = []
     t0 = time.perf_counter()
-    run.step(steps)
+    for kb in sizes:
+        run.step(kb)
+        per_block.append((kb, run.stats()))
     run.sync()
     wall = time.perf_counter() - t0
-    st = run.stats()
+    st = dict(per_block[-1][1])
+    for key in ("particle_ms", "particle_kernel_ms", "continue_kernel_ms", "field_ms"):
+        st[key] = sum(b[key] for _, b in per_block)
     t0 = time.perf_counter()
     rg = run.gauss()
     gauss_ms = (time.perf_counter() - t0) * 1e3
     e, b = run.fields()
     return dict(run=run, info=info, dt=dt, n=npart, wall=wall, stats=st, gauss=rg, gauss_ms=gauss_ms, setup_s=t_setup,
-                e=e, b=b)
+                e=e, b=b, blocks=per_block)
 
 
 def rel(a, b):
@@ -113,77 +157,128 @@ def rel(a, b):
     return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
 
 
+def oracle_threads():
+    """Host threads of the oracle's all-cores leg: the CPUs this process may run on, at most 16
+    (the host share of one GPU on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def cpu_baseline(cfg, n_sample, steps):
-    """The FP64 oracle (plain C loop, one thread) on a bounded sample."""
+    """The FP64 oracle on a bounded sample of the workload: its plain C particle loop on all host
+    threads (contiguous particle chunks, one deposit buffer per chunk, merged in chunk order) and,
+    beside it, on one thread."""
     from oracle import core, mesh as omesh
     N, k = cfg["N"], cfg["order"]
     m = omesh.cube_mesh(N, k)
     # explicit-limit bound of the oracle at N=4, scaled by 4/N (similar meshes)
     m4 = omesh.cube_mesh(4, k)
     dt = cfg["cfl"] * core.cfl_dt(m4, core.assemble(m4)) * 4.0 / N
-    pos, vel = W.config_particles(3, n=n_sample)
-    orc = core.OracleRun(m, dt, particles_only=True)
-    orc.load(pos, vel, -W.Q_E, W.M_E, W.config_weight(3, n_sample, dt))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        orc.particle_step()
-    dtm = time.perf_counter() - t0
-    return dict(value=n_sample * steps / dtm, unit="particle-steps/s", cores=1, kind="oracle",
-                sample="%d particles x %d steps of the same workload (40^3 cube, order 2, zero fields), "
-                       "single-threaded plain C, %.1f s" % (n_sample, steps, dtm))
+    threads = oracle_threads()
+    legs = {}
+    for name, nt_, n in (("all_cores", threads, n_sample * max(1, threads // 4)), ("one_thread", 1, n_sample)):
+        pos, vel = W.config_particles(3, n=n)
+        orc = core.OracleRun(m, dt, particles_only=True)
+        orc.load(pos, vel, -W.Q_E, W.M_E, W.config_weight(3, n, dt))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            orc.particle_step(threads=nt_)
+        dtm = time.perf_counter() - t0
+        legs[name] = (n * steps / dtm, n, dtm, nt_)
+        del orc, pos, vel
+    v, n, dtm, nt_ = legs["all_cores"]
+    v1, n1, dtm1, _ = legs["one_thread"]
+    return dict(value=v, unit="particle-steps/s", cores=nt_, kind="oracle",
+                sample="%d particles x %d steps of the same workload (40^3 cube, order 2, zero fields), the "
+                       "oracle's plain C loop on %d threads, %.1f s; one thread: %d particles x %d steps, %.1f s"
+                       % (n, steps, nt_, dtm, n1, steps, dtm1),
+                one_thread=dict(value=v1, unit="particle-steps/s", cores=1))
 
 
-def serving(n_jobs=24, slots=4, mean_gap_ms=15.0, seed=4007):
-    """Continuous batching: n_jobs independent mixed-precision runs with Poisson
-    arrivals go through fempic_submit / fempic_poll; each run's mesh, order,
-    particle count and kind are drawn at random (a smaller instance of the
-    serving workload). Reports per-step latency (intervals between consecutive
-    step completions of a run, over all runs), queue delay and aggregate
+def serving(n_jobs=64, slots=4, seed=4007, budget_gib=64):
+    """The serving stream: n_jobs independent mixed-precision runs arrive with Poisson gaps and go
+    through fempic_submit / fempic_poll.  Per run (numpy PCG64, seed 4007): N^3 cube with N uniform
+    in [8, 30], order 1 or 2, 1e4-4e6 particles (log-uniform), beam (c2 shape) or thermal (v_th
+    0.01c) at random, 50-300 steps, dt = 10 x the explicit bound.  The mean gap is half the mean
+    time a run takes alone, measured first: four of the runs alone for 10 steps each, scaled by
+    their step counts to the mean run.  Reports per-step latency (intervals between consecutive
+    step completions of a run, over all runs: p50, p99), queue delay and aggregate
     particle-steps/s = sum n steps / makespan."""
     rng = np.random.Generator(np.random.PCG64(seed))
     dt8 = {k: F.Mesh.cube(8, k).info()["dt_cfl"] for k in (1, 2)}  # Kuhn cubes: dt_cfl ~ 1/N
-    jobs = []
+    specs = []
     for j in range(n_jobs):
-        N = int(rng.integers(8, 21))
+        N = int(rng.integers(8, 31))
         k = int(rng.integers(1, 3))
-        n = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+        n = int(np.exp(rng.uniform(np.log(1e4), np.log(4e6))))
         kind = "beam" if rng.random() < 0.5 else "thermal"
-        steps = int(rng.integers(20, 61))
-        dt = 10.0 * dt8[k] * 8.0 / N
+        steps = int(rng.integers(50, 301))
+        specs.append((N, k, n, kind, steps, 10.0 * dt8[k] * 8.0 / N))
+    # mean isolated run time: four runs alone, 10 steps each, scaled to their step counts
+    per_step = []
+    for (N, k, n, kind, steps, dt) in specs[:4]:
+        pos, vel = W.particles(kind, n, seed + 1000, vth=0.01, drift=0.1)
+        run = F.Run(F.Mesh.cube(N, k), dt, F.MIXED, pcg_rtol=1e-13)
+        run.load(pos, vel, -W.Q_E, W.M_E, W.plasma_weight(n, dt))
+        run.step(2)
+        run.sync()
+        t0 = time.perf_counter()
+        run.step(10)
+        run.sync()
+        per_step.append((time.perf_counter() - t0) / 10)
+        run.close()
+    mean_steps = float(np.mean([sp[4] for sp in specs]))
+    iso_s = float(np.mean(per_step)) * mean_steps
+    gaps = rng.exponential(0.5 * iso_s, n_jobs)
+    jobs = []
+    for j, (N, k, n, kind, steps, dt) in enumerate(specs):
         pos, vel = W.particles(kind, n, seed + j, vth=0.01, drift=0.1)
         jobs.append((N, k, pos, vel, W.plasma_weight(n, dt), steps, dt, n))
-    gaps = rng.exponential(mean_gap_ms / 1e3, n_jobs)
-    srv = F.Server(hbm_budget=64 << 30, max_slots=slots)
+    srv = F.Server(hbm_budget=budget_gib << 30, max_slots=slots)
     t0 = time.perf_counter()
     tickets = []
-    for j, (N, k, pos, vel, w, steps, dt, n) in enumerate(jobs):
-        time.sleep(gaps[j])
-        tickets.append(srv.submit(N, k, pos, vel, -W.Q_E, W.M_E, w, steps, dt, precision=F.MIXED))
     res = {}
-    while len(res) < len(tickets):
+
+    def drain():
         for t in tickets:
             if t not in res:
                 r = srv.poll(t)
                 if r is not None:
                     res[t] = r
+
+    for j, (N, k, pos, vel, w, steps, dt, n) in enumerate(jobs):
+        t_next = time.perf_counter() + gaps[j]
+        while time.perf_counter() < t_next:
+            drain()
+            time.sleep(0.002)
+        tickets.append(srv.submit(N, k, pos, vel, -W.Q_E, W.M_E, w, steps, dt, precision=F.MIXED))
+    while len(res) < len(tickets):
+        drain()
         time.sleep(0.002)
     makespan = time.perf_counter() - t0
     srv.close()
-    lat, queue = [], []
+    lat, queue, failed = [], [], 0
     for t in tickets:
         r = res[t]
-        assert r["status"] == 0
+        if r["status"] != 0:
+            failed += 1
+            continue
         lat.extend(np.diff(r["step_done_ms"]).tolist())
         queue.append(r["queue_ms"])
-    work = sum(n * steps for (_, _, _, _, _, steps, _, n) in jobs)
+    work = sum(n * steps for (_, _, _, _, _, steps, _, n), t in zip(jobs, tickets) if res[t]["status"] == 0)
     return {"metric": "serving: per-step latency p50/p99 and aggregate particle-steps/s", "value": work / makespan,
             "unit": "particle-steps/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
             "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
             "queue_p50_ms": float(np.percentile(queue, 50)), "queue_max_ms": float(np.max(queue)),
-            "makespan_s": makespan,
-            "config": {"workload": "%d runs, Poisson arrivals (mean gap %.0f ms), %d slots; N in [8,20], order 1|2, "
-                                   "1e4-1e6 particles (log-uniform), beam|thermal, 20-60 steps, dt = 10 x explicit "
-                                   "bound, mixed precision" % (n_jobs, mean_gap_ms, slots)}}
+            "makespan_s": makespan, "runs": n_jobs, "failed": failed, "mean_gap_s": 0.5 * iso_s,
+            "particle_steps": work,
+            "config": {"workload": "%d runs, Poisson arrivals (mean gap %.2f s = half the mean isolated run time), "
+                                   "%d slots, %d GiB budget; N in [8,30], order 1|2, 1e4-4e6 particles "
+                                   "(log-uniform), beam|thermal, 50-300 steps, dt = 10 x explicit bound, mixed "
+                                   "precision" % (n_jobs, 0.5 * iso_s, slots, budget_gib)}}
 
 
 def largest(steps, warmup, gauss_every=0, log=None):
@@ -192,7 +287,7 @@ def largest(steps, warmup, gauss_every=0, log=None):
     gauss_every > 0 evaluates R_G, R_C, R_S every that many steps into the step log `log`."""
     r = run_workload(5, F.MIXED, steps, warmup, gauss_every=gauss_every, log=log)
     st = r["stats"]
-    alg, _, _ = algorithmic_bytes(2, F.MIXED, r["n"], r["info"]["n_tet"])
+    alg, _, _ = survey_bytes(2, F.MIXED, r["n"], r["info"]["n_tet"], r["info"]["n1_int"])
     pms, kms = st["particle_ms"], st["particle_kernel_ms"]
     out = {"metric": "particle-steps/sec (gather+push+deposit), largest single run", "value": r["n"] * steps / (pms / 1e3),
            "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -222,6 +317,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true",
                     help="only the mixed order-2 run (no FP64 or order-1 comparison runs)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--no-copy", action="store_true", help="skip the device copy-bandwidth measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (counter calibration for profiles)")
     ap.add_argument("--slots", type=int, default=4, help="resident runs in --serving mode")
@@ -244,6 +340,8 @@ def main():
         print(json.dumps(largest(args.steps, args.warmup, args.gauss_every, args.log)))
         return
     cfg = W.CONFIGS[3]
+    # torch before the library's first use, so both share one HIP runtime
+    copy_gbs = copy_bandwidth() if not args.no_copy else None
     if args.calib_copy:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -251,14 +349,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    mix = run_workload(3, F.MIXED, args.steps, args.warmup, n=args.particles)
+    mix = run_workload(3, F.MIXED, args.steps, args.warmup, n=args.particles, blocks=3)
     st = mix["stats"]
     K = args.steps
+    n, nt, n1i = mix["n"], mix["info"]["n_tet"], mix["info"]["n1_int"]
+    # the particle phase's rate in each of three consecutive blocks of the timed steps; the
+    # reported value is their median
+    rates = [n * kb / (b["particle_ms"] / 1e3) for kb, b in mix["blocks"]]
+    value = float(np.median(rates))
     pms = st["particle_ms"]
     kms = st["particle_kernel_ms"]
-    value = mix["n"] * K / (pms / 1e3)
-    alg, state_b, tet_b = algorithmic_bytes(cfg["order"], F.MIXED, mix["n"], mix["info"]["n_tet"])
     kernel_s = kms / K / 1e3
+    alg, state_b, tet_b = survey_bytes(cfg["order"], F.MIXED, n, nt, n1i)
+    alg_build, state_build, tet_build = algorithmic_bytes(cfg["order"], F.MIXED, n, nt)
     achieved = alg / kernel_s / 1e9
     traffic = profiled_traffic() if args.particles is None else None
     it = max(st["pcg_iters"], 1)
@@ -283,23 +386,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": "40^3 Kuhn cube (384000 tets), order 2, %d electrons, 1%% sinusoidal density "
                                "perturbation in x, v_th 0.02c, omega_p dt = 0.02, dt = 10 x explicit bound, PEC walls, "
-                               "mixed precision" % mix["n"], "order": 2, "n_tet": mix["info"]["n_tet"],
-                   "particles": mix["n"], "dt": mix["dt"], "omega_p_dt": W.CONFIGS[3]["omega_dt"]},
+                               "mixed precision" % n, "order": 2, "n_tet": nt,
+                   "particles": n, "dt": mix["dt"], "omega_p_dt": W.CONFIGS[3]["omega_dt"]},
+        "block_rates": rates,
         "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2],
                            "ms": mix["gauss_ms"]},
         "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"], "a_rows": st["a_rows"],
                 "a_nnz": st["a_nnz"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
                 "gb_s": pcg_b / (pcg_ms / 1e3) / 1e9},
-        "crossings_per_particle_step": st["crossings"] / mix["n"],
-        "spills_per_particle_step": st["spills"] / mix["n"],
+        "crossings_per_particle_step": st["crossings"] / n,
+        "spills_per_particle_step": st["spills"] / n,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "kernel": "k_particle<2,float>", "kernel_ms": kms / K,
-                     "alg_bytes_per_launch": alg, "state_bytes": state_b, "per_tet_bytes": tet_b,
+                     "alg_bytes_per_launch": alg, "alg_bytes_per_particle_step": alg / n,
+                     "state_bytes": state_b, "per_tet_bytes": tet_b,
+                     # the same launch against the bytes this build's layout moves (FP64 velocity in
+                     # mixed precision: 124-B state; 568 B per tet)
+                     "build_model": {"alg_bytes_per_launch": alg_build, "state_bytes": state_build,
+                                     "per_tet_bytes": tet_build,
+                                     "frac": alg_build / kernel_s / 1e9 / HBM_PEAK_GBS},
+                     "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if copy_gbs else None,
                      # the whole particle phase (a1-a6, all its kernels and host waits) against the
                      # same algorithmic bytes per step
-                     "phase_frac": alg / (pms / K / 1e3) / 1e9 / HBM_PEAK_GBS},
+                     "phase_frac": alg / (pms / K / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "phase_frac_of_copy": (alg / (pms / K / 1e3) / 1e9 / copy_gbs) if copy_gbs else None},
     }
     mix["run"].close()
     if not args.no_fp64:
@@ -309,7 +421,7 @@ def main():
         k2 = K
         out["mixed_vs_fp64"] = {"steps": K + args.warmup, "e_rel": rel(mix["e"], f64["e"]),
                                 "b_rel": rel(mix["b"], f64["b"])}
-        alg2, _, _ = algorithmic_bytes(cfg["order"], F.FP64, f64["n"], f64["info"]["n_tet"])
+        alg2, _, _ = survey_bytes(cfg["order"], F.FP64, f64["n"], f64["info"]["n_tet"], f64["info"]["n1_int"])
         out["fp64"] = {"value": f64["n"] * k2 / (s2["particle_ms"] / 1e3), "unit": "particle-steps/s",
                        "particle_ms_per_step": s2["particle_ms"] / k2, "ms_per_step": f64["wall"] * 1e3 / k2,
                        "R_G": f64["gauss"][0],
@@ -321,7 +433,7 @@ def main():
         for name, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
             r1 = run_workload(3, prec, K, args.warmup, n=args.particles, order=1)
             s1 = r1["stats"]
-            alg1, _, _ = algorithmic_bytes(1, prec, r1["n"], r1["info"]["n_tet"])
+            alg1, _, _ = survey_bytes(1, prec, r1["n"], r1["info"]["n_tet"], r1["info"]["n1_int"])
             out["order1"][name] = {"value": r1["n"] * K / (s1["particle_ms"] / 1e3), "unit": "particle-steps/s",
                                    "particle_ms_per_step": s1["particle_ms"] / K,
                                    "ms_per_step": r1["wall"] * 1e3 / K, "R_G": r1["gauss"][0],

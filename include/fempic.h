@@ -113,7 +113,11 @@ int32_t fempic_mesh_info(fempic_mesh mesh, fempic_mesh_info_t *out);
  * Both keep Gauss's law: the current enters with the time stencil of the
  * mass term.  `hip_stream` may be NULL (the run
  * creates its own default-priority stream).  pcg_rtol is the relative residual
- * of the field solve (FP64); pcg_maxit caps its iterations (ESOLVE beyond).
+ * the field solve must reach (ESOLVE otherwise); the residual is evaluated in
+ * double-double, against a right-hand side formed in double-double, and the
+ * solve is refined on to a relative residual of 1e-17 when pcg_rtol is larger,
+ * so that the solve adds no drift to the Gauss residual over long runs.
+ * pcg_maxit caps the iterations of each (inner) PCG solve.
  * spill_slots is reserved and ignored: the buffer of path segments outside the
  * particle's home tet grows on demand (a step that overflows it is redone after
  * the buffer doubles; ENOMEM if that keeps failing).  A path that crosses more
@@ -166,12 +170,17 @@ int32_t fempic_step(fempic_run run, int32_t n_steps);
 /* Wait for the run's queued work; reports sticky device failures. */
 int32_t fempic_sync(fempic_run run);
 
-/* Gauss's law check (Sec. II, Gauss laws; Sec. IV-D): on the interior nodal DoFs,
+/* Gauss's law check (Sec. II, Gauss laws; Sec. IV-D): on the interior nodal DoFs
+ * (the running sums e and g are kept with compensated summation, and the
+ * products below are evaluated in double-double, so the residuals measure the
+ * scheme, not the rounding of FP64 running sums),
  *   out[0] = R_G = |G^T *eps e + (rho~^n - rho~^0)| / |rho~^n - rho~^0|,
  *   out[1] = R_C = |G^T g - (rho~^n - rho~^0)| / ...  (deposit only),
  *   out[2] = R_S = |G^T (*eps e + g)| / ...          (solve only),
  * with rho~_j = q w sum_p W0_j(r_p), g the accumulated current moments and G
- * the gradient matrix (grad W0_j = sum_i G_ij W1_i).  Synchronises. */
+ * the gradient matrix (grad W0_j = sum_i G_ij W1_i; its entries are thirds at
+ * order 2, so the check multiplies by 3 G, whose entries are integers, and
+ * divides the products by 3).  Synchronises. */
 int32_t fempic_gauss_residual(fempic_run run, double out[3]);
 
 /* fempic_gauss_residual without any allocation, for callers that cannot
@@ -179,10 +188,10 @@ int32_t fempic_gauss_residual(fempic_run run, double out[3]);
  * harnesses that forbid hipMalloc): the same values, bit for bit, as
  * fempic_gauss_residual.  Its intermediates (per-tet partial charges, the
  * nodal vectors, reduction partials) live in a static device array of the
- * library, 64 MiB on every device it runs on, held until the process ends.
+ * library, 96 MiB on every device it runs on, held until the process ends.
  * Nothing is allocated: no hipMalloc, no installed allocator, no library
  * routine that allocates.  EINVAL when the run's mesh needs more scratch than
- * that (8 n_tet n0_loc + 24 n0_int + 8 n1_int bytes and 64 KiB: up to about the
+ * that (8 n_tet n0_loc + 24 n0_int + 16 n1_int bytes and 64 KiB: up to about the
  * 40^3 cube at order 2).  Every call on a device shares that device's array, so
  * calls that overlap on one device (runs on different streams or threads) race
  * and must be serialised by the caller.  Synchronises the run's stream. */
@@ -204,9 +213,33 @@ int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n);
  * leaves out).  Either pointer may be NULL.  Synchronises; EINVAL before a load. */
 int32_t fempic_rho_get(fempic_run run, double *rho, double *rho0, int64_t n);
 
+/* Impressed magnetic flux density (Sec. III-C, eq. (conB); Tables I and II): an
+ * external B (magnets, lenses) that pushes the particles but does not enter
+ * Ampere's law.
+ * fempic_impressed_points writes the points at which the caller samples B:
+ * n1d^3 per tet (a collapsed Gauss-Legendre rule, 1 <= n1d <= 8), tet-major,
+ * xyz [n_tet * n1d^3][3]; n >= n_tet * n1d^3 points, else EINVAL.
+ * fempic_impressed_set takes B at those points (B [n_tet * n1d^3][3], tesla,
+ * same n1d), forms the moments f_l = <W2_l, B / mu0> and projects: with
+ * constrained = 0, *nu b = f; with constrained = 1, b is the *nu-orthogonal
+ * projection onto the faces whose discrete divergence vanishes (the solution of
+ * the saddle-point system of eq. (conB); computed as b = K a over the curl of
+ * every edge function, which spans those faces on a simply connected mesh, so
+ * div b is zero to rounding).  The run keeps b as its impressed field from then
+ * on (also through checkpoints): the gather uses b_self + b.  b_out (NULL, or
+ * >= n2 entries) receives b in natural face numbering.  EINVAL on bad sizes or a
+ * non-finite B; ESOLVE if a projection solve does not converge. */
+int32_t fempic_impressed_points(fempic_mesh mesh, int32_t n1d, double *xyz, int64_t n);
+int32_t fempic_impressed_set(fempic_run run, const double *B, int64_t n, int32_t n1d, int32_t constrained,
+                             double *b_out, int64_t nb);
+
 /* Particle state in load order: pos, vel [n][3]; tet [n] (any may be NULL);
  * n >= the number loaded.  A particle absorbed at a wall has tet -1 and NaN
- * position and velocity. */
+ * position and velocity.  The run holds each position as the barycentric
+ * coordinates of the particle in its tet (taken over exactly from tet to tet
+ * and from step to step, which keeps the deposit's charge continuity free of
+ * the rounding of the tets' barycentric maps); pos is computed from them,
+ * x_0 + sum_m l_m (x_m - x_0) over the tet's vertices x_m. */
 int32_t fempic_particles_get(fempic_run run, double *pos, double *vel, int64_t *tet, int64_t n);
 
 /* Full AB4 history in load order: vh, ah are [n][3][3] = v^{n-1..n-3}, a^{n-1..n-3}
@@ -215,7 +248,8 @@ int32_t fempic_history_get(fempic_run run, double *vh, double *ah, int64_t n);
 
 /* ------------------------------------------------------------- checkpoint
  * fempic_run_save writes the run's state to the file at `path` (created or
- * replaced): the particles, with their AB4 velocity and acceleration histories
+ * replaced): the particles (positions as barycentric coordinates in their
+ * tets), with their AB4 velocity and acceleration histories
  * in the run's storage precision and in the order the next step takes them;
  * e, b, the accumulated current moments and the reference charge of the
  * Gauss-law check; the three-level scheme's previous fields and current; the

@@ -91,6 +91,9 @@ SYMBOLS = {
     "fempic_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_footprint": (C.c_int32, [C.c_int32, C.c_int64, C.c_int64, C.c_int32, C.c_void_p]),
     "fempic_footprint_mesh": (C.c_int32, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]),
+    "fempic_impressed_points": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
+    "fempic_impressed_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
+                                         C.c_int64]),
     "fempic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fempic_server_destroy": (C.c_int32, [C.c_void_p]),
     "fempic_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -149,6 +152,13 @@ class Mesh:
         i = MeshInfo()
         _check(lib().fempic_mesh_info(self.h, C.byref(i)))
         return {k: getattr(i, k) for k, _ in MeshInfo._fields_}
+
+    def impressed_points(self, n1d):
+        """Points (n_tet * n1d^3, 3) at which an impressed B is sampled (fempic_impressed_points)."""
+        n = self.info()["n_tet"] * n1d ** 3
+        xyz = np.zeros((n, 3))
+        _check(lib().fempic_impressed_points(self.h, n1d, _p(xyz), n))
+        return xyz
 
     def footprint(self, n_particles, precision=FP64):
         """Device bytes of a run on this mesh (fempic_footprint_mesh)."""
@@ -274,6 +284,14 @@ class Run:
         r0 = np.zeros(self.info["n0"])
         _check(lib().fempic_rho_get(self.h, _p(r), _p(r0), len(r)))
         return r, r0
+
+    def impress(self, B, n1d, constrained=True):
+        """Project B sampled at Mesh.impressed_points(n1d) and keep it as the run's impressed
+        field (fempic_impressed_set); returns its face coefficients."""
+        B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1, 3)
+        b = np.zeros(self.info["n2"])
+        _check(lib().fempic_impressed_set(self.h, _p(B), len(B), n1d, 1 if constrained else 0, _p(b), len(b)))
+        return b
 
     def particles(self):
         pos = np.zeros((self.n, 3))

@@ -4,7 +4,9 @@
 //   K     = local curl matrix by assignment (curl W1_j = sum_l K_lj W2_l),
 //   A     = *eps + c dt^2 K^T *nu K  (assembled element by element; c = (beta/gamma)^2
 //           of the Newmark-beta scheme, 1/4 for gamma = 1/2, beta = 1/4),
-//   K^T *nu, G^T (gradient matrix by assignment).
+//   *nu and K^T apart (the field update applies K^T to *nu u in double-double,
+//   so that G^T of it vanishes as in exact arithmetic), and G^T by assignment,
+//   scaled to integer entries.
 // Only W1 DoFs off the PEC walls are unknowns; W0 rows of the Gauss check are
 // the interior nodal DoFs.  Also the explicit time-step bound and the
 // DoF -> (tet, local) incidence lists that the deterministic deposit scatter uses.
@@ -301,18 +303,18 @@ void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
     // element matrices of every tet: eps0 M1, curl-curl S / mu0, K^T M2 / mu0
     // (uninitialised storage: every entry is written by the parallel loop below)
     std::unique_ptr<double[]> Mel(new double[(size_t)nt * n1 * n1]), Sel(new double[(size_t)nt * n1 * n1]),
-        Cel(new double[(size_t)nt * n1 * n2]);
+        Nel(new double[(size_t)nt * n2 * n2]);
     parallel_for(nt, [&](int64_t t0, int64_t t1) {
         std::vector<double> M1(n1 * n1), M2(n2 * n2), S(n1 * n1), KtM2(n1 * n2);
         for (int64_t t = t0; t < t1; t++) {
             element_mass(m, t, M1.data(), M2.data());
             curl_products(R, M2.data(), S.data(), KtM2.data());
-            double *me = &Mel[(size_t)t * n1 * n1], *se = &Sel[(size_t)t * n1 * n1], *ce = &Cel[(size_t)t * n1 * n2];
+            double *me = &Mel[(size_t)t * n1 * n1], *se = &Sel[(size_t)t * n1 * n1], *ne = &Nel[(size_t)t * n2 * n2];
             for (int i = 0; i < n1 * n1; i++) {
                 me[i] = EPS0 * M1[i];
                 se[i] = S[i] / MU0;
             }
-            for (int i = 0; i < n1 * n2; i++) ce[i] = KtM2[i] / MU0;
+            for (int i = 0; i < n2 * n2; i++) ne[i] = M2[i] / MU0;
         }
     });
     const double c_stiff = c_dt2 * dt * dt;
@@ -325,14 +327,28 @@ void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
               false, ops.A);
     build_csr(r1, N1i, N1i, n1, n1, w1int, nullptr,
               [&](int64_t t, int i, int j) { return Mel[((size_t)t * n1 + i) * n1 + j]; }, false, ops.Meps);
-    build_csr(r1, N1i, m.N2, n1, n2, w2, nullptr,
-              [&](int64_t t, int i, int l) { return Cel[((size_t)t * n1 + i) * n2 + l]; }, false, ops.Ct);
     RowInc r2 = row_incidence(m, m.N2, n2, w2);
+    build_csr(r2, m.N2, m.N2, n2, n2, w2, nullptr,
+              [&](int64_t t, int l, int q) { return Nel[((size_t)t * n2 + l) * n2 + q]; }, false, ops.Mnu);
     build_csr(r2, m.N2, N1i, n2, n1, w1int, R.K.data(), [&](int64_t, int l, int i) { return R.K[l * n1 + i]; },
               true, ops.K);
+    std::vector<double> KT(n1 * n2);
+    for (int i = 0; i < n1; i++)
+        for (int l = 0; l < n2; l++) KT[i * n2 + l] = R.K[l * n1 + i];
+    build_csr(r1, N1i, m.N2, n1, n2, w2, KT.data(), [&](int64_t, int i, int l) { return KT[i * n2 + l]; }, true,
+              ops.Kt);
+    // G's entries are rationals (thirds at order 2); scaled to integers they make
+    // the Gauss check's products exact
+    ops.gscale = 0.0;
+    for (int sc = 1; sc <= 12 && ops.gscale == 0.0; sc++) {
+        bool ok = true;
+        for (double gv : R.G) ok = ok && std::fabs(gv * sc - std::nearbyint(gv * sc)) < 1e-9;
+        if (ok) ops.gscale = sc;
+    }
+    if (ops.gscale == 0.0) throw Error(FEMPIC_EMESH, "gradient matrix without a small integer scale");
     std::vector<double> Gt(n0 * n1);
     for (int j = 0; j < n0; j++)
-        for (int i = 0; i < n1; i++) Gt[j * n1 + i] = R.G[i * n0 + j];
+        for (int i = 0; i < n1; i++) Gt[j * n1 + i] = std::nearbyint(R.G[i * n0 + j] * ops.gscale);
     RowInc r0 = row_incidence(m, N0i, n0, w0int);
     build_csr(r0, N0i, N1i, n0, n1, w1int, Gt.data(), [&](int64_t, int j, int i) { return Gt[j * n1 + i]; }, true,
               ops.Gt);
@@ -347,6 +363,24 @@ void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
     }
     incidence(m, N1i, n1, m.map1, ops.inc_ptr, ops.inc_idx);
     incidence(m, N0i, n0, m.map0, ops.inc0_ptr, ops.inc0_idx);
+}
+
+void assemble_impressed(const HostMesh &m, ImpressedOps &io)
+{
+    const RefElem &R = ref_elem(m.order);
+    const int n1 = R.n1, n2 = R.n2;
+    auto w1all = [&](int64_t t, int i) -> int64_t { return m.map1[t * n1 + i]; };
+    auto w2 = [&](int64_t t, int l) -> int64_t { return m.map2[t * n2 + l]; };
+    RowInc r2 = row_incidence(m, m.N2, n2, w2);
+    build_csr(r2, m.N2, m.N1, n2, n1, w1all, R.K.data(), [&](int64_t, int l, int i) { return R.K[l * n1 + i]; },
+              true, io.K);
+    std::vector<double> KT(n1 * n2);
+    for (int i = 0; i < n1; i++)
+        for (int l = 0; l < n2; l++) KT[i * n2 + l] = R.K[l * n1 + i];
+    RowInc r1 = row_incidence(m, m.N1, n1, w1all);
+    build_csr(r1, m.N1, m.N2, n1, n2, w2, KT.data(), [&](int64_t, int i, int l) { return KT[i * n2 + l]; }, true,
+              io.Kt);
+    incidence(m, m.N2, n2, m.map2, io.inc2_ptr, io.inc2_idx);
 }
 
 }  // namespace fempic

@@ -87,9 +87,13 @@ struct CSR {
 struct Operators {
     CSR A;      // *eps + c dt^2 K^T *nu K   (N1_int x N1_int)
     CSR Meps;   // *eps                      (N1_int x N1_int)
-    CSR Ct;     // K^T *nu                   (N1_int x N2)
+    CSR Mnu;    // *nu                       (N2 x N2)
     CSR K;      // curl                      (N2 x N1_int)
-    CSR Gt;     // G^T                       (N0_int x N1_int)
+    CSR Kt;     // K^T                       (N1_int x N2)
+    CSR Gt;     // gscale G^T                (N0_int x N1_int)
+    // the smallest integer that makes every entry of G an integer (1 at order 1,
+    // 3 at order 2): products with gscale G^T are then exact in double-double
+    double gscale = 1.0;
     std::vector<double> Adiag_inv;
     // deposit scatter: for interior W1 DoF j, the (tet*n1l + local) slots in tet order
     std::vector<int64_t> inc_ptr;
@@ -101,6 +105,21 @@ struct Operators {
 
 // A = *eps + c_dt2 dt^2 K^T *nu K (c_dt2 = (beta / gamma)^2 of the Newmark-beta scheme)
 void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2 = 0.25);
+
+// Operators of the impressed-field projection (Sec. III-C): the curl over every
+// W1 DoF, walls included (N2 x N1) and its transpose, and the face DoF ->
+// (tet * n2l + local) incidence lists in tet order.
+struct ImpressedOps {
+    CSR K, Kt;
+    std::vector<int64_t> inc2_ptr;
+    std::vector<int32_t> inc2_idx;
+};
+void assemble_impressed(const HostMesh &m, ImpressedOps &io);
+
+// collapsed Gauss-Legendre rule on the reference tet with n^3 points (the
+// quadrature of the impressed field's moments): barycentric coordinates
+// lam [n^3][4] and weights w [n^3] summing to 1
+void impressed_rule(int n, std::vector<double> &lam, std::vector<double> &w);
 
 // Device bytes a run allocates for a mesh of these sizes and n particles
 // (operators with their nonzeros bounded per row for meshes of Kuhn-cube

@@ -21,10 +21,12 @@ struct DevMesh {
     double cube_L;
 };
 
-// Particle state, structure of arrays.  Position and velocity are FP64 in both
-// modes; the AB4 histories are R (double, or float in mixed mode).
+// Particle state, structure of arrays.  The position is held as the particle's
+// barycentric coordinates l_1, l_2, l_3 in its tet (l_0 = 1 - l_1 - l_2 - l_3),
+// FP64 like the velocity in both modes; the AB4 histories are R (double, or
+// float in mixed mode).
 struct DevParticles {
-    double *x;     // [3][cap]
+    double *lam;   // [3][cap]
     void *v;       // [3][cap]   double
     void *vh;      // [9][cap]   R: v^{n-1} - v^n, v^{n-2} - v^n, v^{n-3} - v^n
     void *ah;      // [9][cap]   R: a^{n-1}, a^{n-2}, a^{n-3}
@@ -70,7 +72,8 @@ struct SpillPool {
 
 // particles whose path leaves the home tet during the step
 struct ContRec {
-    double cp[15];   // path coefficients r(s) = sum_d cp[3d + c] s^d (after wall reflections so far)
+    double lam[3];   // l_1..l_3 of tet t at s_lo (l_0 = 1 - l_1 - l_2 - l_3)
+    double dp[12];   // path displacement r(s) - r(0) = sum_{d=1..4} dp[3(d-1) + c] s^d (after wall reflections so far)
     double s_lo;     // path parameter where the particle entered tet t
     int32_t i;       // sorted particle index
     int32_t t;       // current tet
@@ -93,6 +96,8 @@ struct ContQueue {
 // x: [3][cap] positions of n particles
 hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
                               hipStream_t s);
+// positions x ([3][cap], in tet[p]) replaced in place by l_1..l_3 of that tet
+hipError_t launch_to_bary(const DevMesh &m, int64_t n, int64_t cap, double *x, const int32_t *tet, hipStream_t s);
 hipError_t launch_startup(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
                           const float *b32, DevParticles p, int64_t n, double qm, double dt, hipStream_t s);
 
@@ -174,8 +179,8 @@ hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off,
                         const int32_t *noff, uint32_t *perm, unsigned long long *err, hipStream_t s);
 hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
                           hipStream_t s);
-hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,
-                          const int32_t *ptet, int64_t cap, double qw, double *Pr, hipStream_t s);
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *lam,
+                          int64_t cap, double qw, double *Pr, hipStream_t s);
 
 // linear algebra (FP64 unless noted)
 struct DevCSR {
@@ -216,18 +221,45 @@ hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, 
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s);
 hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStream_t s);
 
-// deterministic norms: out[k] = sum_i f_k(...) for the Gauss check
+// deterministic norms: out[k] = sum_i f_k(...) for the Gauss check; GtDe and Gtg
+// are products with gscale G^T (gscale makes G's entries integers), divided here
 hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
-                       double *partial, double *out4, hipStream_t s);
+                       double gscale, double *partial, double *out4, hipStream_t s);
 hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial, double *out, hipStream_t s);
 // entries of the partial-sum buffer that gauss_norms and dot_det use at most
 int64_t gauss_partial_entries();
+
+// compensated running sum: hi = fl(hi + d) (the plain FP64 sum), lo += its rounding error
+hipError_t add_comp(int64_t n, double *hi, double *lo, const double *d, hipStream_t s);
+// y = A (x_hi + x_lo) accumulated as a compensated (double-double) dot product per
+// row; the result as y_hi + y_lo (y_lo may be null: y_hi is the rounded result)
+hipError_t spmv_dd(const DevCSR &A, const double *x_hi, const double *x_lo, double *y_hi, double *y_lo,
+                   hipStream_t s);
+
+// out = a1 (P1 x1) + a2 (P2 (x2 + x2lo)) + c1 v1 + c2 v2 in double-double (out_hi +
+// out_lo; out_lo may be null); any of P1, P2 (same row count), x2lo, v1, v2 may be null
+hipError_t combo_dd(int64_t rows, const DevCSR *P1, const double *x1, double a1, const DevCSR *P2, const double *x2,
+                    const double *x2lo, double a2, const double *v1, double c1, const double *v2, double c2,
+                    double *out_hi, double *out_lo, hipStream_t s);
+// x += scale f, compensated (xlo += the rounding error of each addition)
+hipError_t add_f2d_comp(int64_t n, const float *f, double scale, double *x, double *xlo, hipStream_t s);
+
+// impressed field (Sec. III-C): per-tet moments Pf[t][n2l] of B sampled at the
+// P points of the collapsed Gauss rule (lamq [P][4], wq [P] summing to 1),
+// B [nt][P][3], times scale
+hipError_t launch_impressed_rhs(int order, const DevMesh &m, int P, const double *lamq, const double *wq,
+                                const double *B, double scale, double *Pf, hipStream_t s);
+// out = a .* b
+hipError_t mul(int64_t n, const double *a, const double *b, double *out, hipStream_t s);
+// dinv = 1 / diag(A), or 1 / diag(A diag(Dinv)^-1 A^T) when Dinv is given (1 where
+// not positive)
+hipError_t jacobi(const DevCSR &A, const double *Dinv, double *dinv, hipStream_t s);
 
 // Device scratch of the entry point that allocates nothing
 // (fempic_gauss_residual_noalloc): NOALLOC_SCRATCH_BYTES on every device, held
 // until the process ends.  noalloc_scratch gives its address on the current
 // device (looked up on the first call per device, then kept).
-constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)96 << 20;
 constexpr int NOALLOC_MAX_DEVICES = 64;
 hipError_t noalloc_scratch(void **ptr);
 

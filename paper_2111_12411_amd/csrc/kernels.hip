@@ -61,6 +61,9 @@ __device__ __constant__ const int FP[4][3] = {{3, 1, 0}, {4, 2, 0}, {5, 2, 1}, {
 
 namespace {
 
+// l_0 from the stored l_1..l_3 (always in this order of operations)
+__device__ __forceinline__ double bary0(double l1, double l2, double l3) { return 1.0 - l1 - l2 - l3; }
+
 // ---------------------------------------------------------------- locate
 __global__ void k_locate_cube(DevMesh m, int64_t n, int64_t cap, const double *__restrict__ x,
                               int32_t *__restrict__ tet, int32_t *__restrict__ err)
@@ -97,6 +100,18 @@ __global__ void k_locate_cube(DevMesh m, int64_t n, int64_t cap, const double *_
     }
     tet[p] = bt;
     if (!ok || !(best >= -1e-10)) atomicOr(err, (int)ERR_OUTSIDE);
+}
+
+// positions replaced in place by l_1..l_3 of their tets
+__global__ void k_to_bary(DevMesh m, int64_t n, int64_t cap, double *__restrict__ x, const int32_t *__restrict__ tet)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double *g = &m.geo[16 * (int64_t)tet[p]];
+    const double r0 = x[p], r1 = x[cap + p], r2 = x[2 * cap + p];
+    double l[3];
+    for (int f = 1; f < 4; f++) l[f - 1] = g[4 * f] + g[4 * f + 1] * r0 + g[4 * f + 2] * r1 + g[4 * f + 3] * r2;
+    for (int c = 0; c < 3; c++) x[c * cap + p] = l[c];
 }
 
 // ------------------------------------------------------------- gather
@@ -182,12 +197,10 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
     if (p >= n) return;
     const int64_t t = P.tet[p];
     const double *g = &m.geo[16 * t];
-    double r[3] = {P.x[p], P.x[P.cap + p], P.x[2 * P.cap + p]};
-    R lam[4], gr[4][3];
-    for (int f = 0; f < 4; f++) {
-        lam[f] = (R)(g[4 * f] + g[4 * f + 1] * r[0] + g[4 * f + 2] * r[1] + g[4 * f + 3] * r[2]);
+    const double l1 = P.lam[p], l2 = P.lam[P.cap + p], l3 = P.lam[2 * P.cap + p];
+    R lam[4] = {(R)bary0(l1, l2, l3), (R)l1, (R)l2, (R)l3}, gr[4][3];
+    for (int f = 0; f < 4; f++)
         for (int k = 0; k < 3; k++) gr[f][k] = (R)g[4 * f + 1 + k];
-    }
     R ec[O::N1], bc[O::N2];
     for (int i = 0; i < O::N1; i++) ec[i] = e[m.map1[t * O::N1 + i]];
     for (int l = 0; l < O::N2; l++) bc[l] = b[m.map2[t * O::N2 + l]];
@@ -355,25 +368,31 @@ __device__ bool first_negative(const double *q, double H, double &uout)
 
 // -------------------------------------------------------------- particle
 // barycentric coordinate of face f (opposite vertex f) along the path, as a
-// polynomial in u = s - s_lo
+// polynomial in u = s - s_lo: its value l0 at s_lo plus grad l_f . (r(s) - r(s_lo)),
+// where dp holds the displacement r(s) - r(0) as powers 1..4 of s.  The value at
+// s_lo is carried from segment to segment (and from step to step) rather than
+// recomputed from a position, so that the W0 values at the ends of consecutive
+// segments are the same numbers and the deposit telescopes exactly.
 template <bool FROM_ZERO, typename GPtr>
-__device__ inline void face_poly(GPtr G, int f, const double (&cp)[5][3], double s_lo, double *q)
+__device__ inline void face_poly(GPtr G, int f, const double (&dp)[4][3], double s_lo, double l0, double *q)
 {
-    const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+    const double gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+    q[0] = 0.0;
 #pragma unroll
-    for (int d = 0; d < 5; d++) q[d] = fma(gz, cp[d][2], fma(gy, cp[d][1], gx * cp[d][0]));
-    q[0] += a0;
+    for (int d = 1; d < 5; d++) q[d] = fma(gz, dp[d - 1][2], fma(gy, dp[d - 1][1], gx * dp[d - 1][0]));
     if (!FROM_ZERO) taylor_shift(q, s_lo, q);
+    q[0] = l0;
 }
 
-// exit of tet G from s_lo along the path cp: the first s > s_lo where a
-// barycentric coordinate turns negative (the entry face's coordinate is zero
-// at s_lo).  A face whose Bernstein coefficients on [s_lo, 1] are all
+// exit of tet G from s_lo along the path dp, whose barycentric coordinates at
+// s_lo are l0: the first s > s_lo where a coordinate turns negative (the entry
+// face's coordinate is zero at s_lo).  A face whose Bernstein coefficients on [s_lo, 1] are all
 // non-negative cannot be crossed; this straight-line test settles most lanes.
 // The flagged faces of a lane (usually one) then go through the full search,
 // in increasing face order, each limited to the best crossing found so far.
 template <bool FROM_ZERO, typename GPtr>
-__device__ inline int find_exit(GPtr G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
+__device__ inline int find_exit(GPtr G, const double (&dp)[4][3], const double (&l0)[4], double s_lo, int entry,
+                                double &s_exit)
 {
     s_exit = 2.0;
     const double H = 1.0 - s_lo;
@@ -383,7 +402,7 @@ __device__ inline int find_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
 #pragma unroll
     for (int f = 0; f < 4; f++) {
         double q[5];
-        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        face_poly<FROM_ZERO>(G, f, dp, s_lo, l0[f], q);
         if (f == entry) q[0] = 0.0;
         const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
         const double b1 = fma(0.25, d1, q[0]);
@@ -400,7 +419,7 @@ __device__ inline int find_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
         const int f = __builtin_ctz(negmask);
         negmask &= negmask - 1u;
         double q[5];
-        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        face_poly<FROM_ZERO>(G, f, dp, s_lo, l0[f], q);
         if (f == entry) q[0] = 0.0;
         double u;
         if (first_negative(q, fbest < 0 ? H : ubest, u) && (fbest < 0 || u < ubest)) {
@@ -423,7 +442,8 @@ __device__ inline int find_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
 // face (s_exit set), -1 for no exit, or -2 when the case needs the full search
 // (any other sign pattern, a start on a face, or no convergence).
 template <bool FROM_ZERO, typename GPtr>
-__device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, int entry, double &s_exit)
+__device__ inline int fast_exit(GPtr G, const double (&dp)[4][3], const double (&l0)[4], double s_lo, int entry,
+                                double &s_exit)
 {
     s_exit = 2.0;
     const double H = 1.0 - s_lo;
@@ -436,7 +456,7 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
 #pragma unroll
     for (int f = 0; f < 4; f++) {
         double q[5];
-        face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+        face_poly<FROM_ZERO>(G, f, dp, s_lo, l0[f], q);
         if (f == entry) q[0] = 0.0;
         const double d1 = q[1] * H, d2 = q[2] * H2, d3 = q[3] * H2 * H, d4 = q[4] * H2 * H2;
         const double b0 = q[0];
@@ -464,7 +484,7 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
     if (hard) return -2;
     if (best < 0) return -1;
     double q[5];
-    face_poly<FROM_ZERO>(G, best, cp, s_lo, q);
+    face_poly<FROM_ZERO>(G, best, dp, s_lo, l0[best], q);
     double a = 0.0, b = H, x = H * (bnum / bden);
     if (!(x > a && x < b)) x = 0.5 * H;
     const double tol = 4e-16 * H;
@@ -493,7 +513,7 @@ __device__ inline int fast_exit(GPtr G, const double (&cp)[5][3], double s_lo, i
 #pragma unroll
     for (int f = 0; f < 4; f++) {
         if (cand & (1u << f)) {
-            face_poly<FROM_ZERO>(G, f, cp, s_lo, q);
+            face_poly<FROM_ZERO>(G, f, dp, s_lo, l0[f], q);
             const double d1 = q[1] * x, d2 = q[2] * x2, d3 = q[3] * x2 * x, d4 = q[4] * x2 * x2;
             const double b1 = fma(0.25, d1, q[0]);
             const double b2 = fma(1.0 / 6.0, d2, fma(0.5, d1, q[0]));
@@ -584,7 +604,7 @@ __device__ inline GMesh gview(const DevMesh &m)
 
 template <typename R>
 struct GParticles {
-    gptr<double> x, v;
+    gptr<double> lam, v;
     gptr<R> vh, ah;
     gptr<int32_t> tet, id;
     int64_t cap;
@@ -592,7 +612,7 @@ struct GParticles {
 template <typename R>
 __device__ inline GParticles<R> gview(const DevParticles &p)
 {
-    return GParticles<R>{glb(p.x), glb((double *)p.v), glb((R *)p.vh), glb((R *)p.ah), glb(p.tet), glb(p.id), p.cap};
+    return GParticles<R>{glb(p.lam), glb((double *)p.v), glb((R *)p.vh), glb((R *)p.ah), glb(p.tet), glb(p.id), p.cap};
 }
 
 struct GPool {
@@ -607,29 +627,46 @@ __device__ inline GPool gview(const SpillPool &p)
     return GPool{glb(p.val), glb(p.tet), glb(p.tag), glb(p.pid), glb(p.count), glb(p.rcount), p.cap};
 }
 
-// leave tet t through face f: move to the neighbour, or at a PEC wall mirror the
-// rest of the path about the face plane together with the stored velocity and
-// AB4 histories of particle i (written before tracking).  With absorb, a wall
-// ends the path instead: nothing is mirrored and true is returned.
+// leave tet t through face f, with lam the coordinates of tet t at the crossing
+// point: move to the neighbour, whose coordinates there replace lam, or at a PEC
+// wall mirror the rest of the path about the face plane together with the
+// stored velocity and AB4 histories of particle i (written before tracking).
+// With absorb, a wall ends the path instead: nothing is mirrored and true is
+// returned.
 template <typename R, typename GPtr>
-__device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&cp)[5][3],
-                                  const GParticles<R> &out, int64_t i, unsigned long long &nrf, bool absorb)
+__device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&dp)[4][3],
+                                  double (&lam)[4], const GParticles<R> &out, int64_t i, unsigned long long &nrf,
+                                  bool absorb)
 {
     const int nx = m.nbr[(int64_t)t * 4 + f];
     if (nx >= 0) {
-        entry = nx & 3;
+        // both tets list their vertices in ascending global order, so the three
+        // shared vertices come in the same order in each: they keep their
+        // coordinates, and the neighbour's vertex across the face starts at 0
+        const int e = nx & 3;
+        const double s0 = f == 0 ? lam[1] : lam[0];
+        const double s1 = f <= 1 ? lam[2] : lam[1];
+        const double s2 = f <= 2 ? lam[3] : lam[2];
+        lam[0] = e == 0 ? 0.0 : s0;
+        lam[1] = e == 0 ? s0 : (e == 1 ? 0.0 : s1);
+        lam[2] = e <= 1 ? s1 : (e == 2 ? 0.0 : s2);
+        lam[3] = e <= 2 ? s2 : 0.0;
+        entry = e;
         t = nx >> 2;
         return false;
     }
     if (absorb) return true;
-    const double a0 = G[4 * f], gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
+    lam[f] = 0.0;
+    const double gx = G[4 * f + 1], gy = G[4 * f + 2], gz = G[4 * f + 3];
     const double inv = 2.0 / (gx * gx + gy * gy + gz * gz);
+    // the crossing point lies on the plane: mirroring the displacement from it
+    // mirrors the path
 #pragma unroll
-    for (int d = 0; d < 5; d++) {
-        const double sd = (gx * cp[d][0] + gy * cp[d][1] + gz * cp[d][2] + (d == 0 ? a0 : 0.0)) * inv;
-        cp[d][0] -= sd * gx;
-        cp[d][1] -= sd * gy;
-        cp[d][2] -= sd * gz;
+    for (int d = 0; d < 4; d++) {
+        const double sd = (gx * dp[d][0] + gy * dp[d][1] + gz * dp[d][2]) * inv;
+        dp[d][0] -= sd * gx;
+        dp[d][1] -= sd * gy;
+        dp[d][2] -= sd * gz;
     }
     {
         const double x0 = out.v[i], x1 = out.v[out.cap + i], x2 = out.v[2 * out.cap + i];
@@ -819,7 +856,8 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
         if (i < pend) {
             const int th = in.tet[slot];
             const int lt = th - T0;
-            const double r[3] = {in.x[slot], in.x[in.cap + slot], in.x[2 * in.cap + slot]};
+            const double l1 = in.lam[slot], l2 = in.lam[in.cap + slot], l3 = in.lam[2 * in.cap + slot];
+            const double ls[4] = {bary0(l1, l2, l3), l1, l2, l3};
             double vd[3];
             R vh[9], ah[9];
 #pragma unroll
@@ -830,12 +868,8 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 ah[c] = in.ah[c * in.cap + slot];
             }
             const R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
-            // barycentrics and fields at r^n (home tet, LDS)
-            R lam[4];
-#pragma unroll
-            for (int f = 0; f < 4; f++)
-                lam[f] = (R)(s_geo[lt][4 * f] + s_geo[lt][4 * f + 1] * r[0] + s_geo[lt][4 * f + 2] * r[1] +
-                             s_geo[lt][4 * f + 3] * r[2]);
+            // fields at r^n (home tet, LDS)
+            const R lam[4] = {(R)ls[0], (R)ls[1], (R)ls[2], (R)ls[3]};
             R cE[4], cB[6];
             gather_coeffs<K, R>(s_e[lt], s_b[lt], lam, cE, cB);
             R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
@@ -857,18 +891,18 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 dv[c] = (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
                 vn[c] = vd[c] + dv[c];
             }
-            // quartic path r(s) = sum_d c_d s^d (FP64 in both modes); the history
-            // holds v^{n-j} - v^n, so in R it is rounded relative to the change
-            // of velocity, not to the velocity
-            double cp[5][3];
+            // quartic path r(s) = r^n + sum_{d=1..4} dp_d s^d (FP64 in both modes);
+            // the history holds v^{n-j} - v^n, so in R it is rounded relative to
+            // the change of velocity, not to the velocity
+            double dp[4][3];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                cp[0][c] = r[c];
                 const double v0 = vd[c], v1 = vd[c] + (double)vh[c], v2 = vd[c] + (double)vh[3 + c],
                              v3 = vd[c] + (double)vh[6 + c];
 #pragma unroll
                 for (int d = 1; d < 5; d++)
-                    cp[d][c] = sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
+                    dp[d - 1][c] =
+                        sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
             }
             // new velocity and shifted histories, written now (wall reflections patch them)
 #pragma unroll
@@ -888,7 +922,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
             // done there).
             const double *G = &s_geo[lt][0];
             double s_exit;
-            const int f_exit = fast_exit<true>(G, cp, 0.0, -1, s_exit);
+            const int f_exit = fast_exit<true>(G, dp, ls, 0.0, -1, s_exit);
             // queued paths of the wave go to the start of the wave's own particle
             // range (its active lanes are a prefix of the wave), in lane order
             const unsigned long long qmask = __ballot(f_exit != -1);
@@ -902,32 +936,37 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 const int lo = max(s_off[lt] - wb, 0);
                 if (lane == lo) atomicAdd(&s_nstay[lt], __popcll(st & lane_range(lo, s_off[lt + 1] - wb)));
             }
+            const int64_t qi = (int64_t)(i - lane) + __popcll(qmask & ((1ull << lane) - 1ull));
+            const gptr<ContRec> rec = qrec + qi;
             if (f_exit != -1) {
-                const int64_t qi = (int64_t)(i - lane) + __popcll(qmask & ((1ull << lane) - 1ull));
-                gptr<ContRec> rec = qrec + qi;
 #pragma unroll
-                for (int d = 0; d < 5; d++)
+                for (int d = 0; d < 4; d++)
 #pragma unroll
-                    for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+                    for (int c = 0; c < 3; c++) rec->dp[3 * d + c] = dp[d][c];
                 rec->s_lo = f_exit >= 0 ? s_exit : 0.0;
                 rec->i = i;
                 rec->t = th;
                 rec->entry = -1;
                 rec->ncross = 0;
                 rec->pending = f_exit >= 0 ? f_exit : -1;
+            }
+            double lq[3][5];  // l_1..l_3 along the path in the home tet
+            if (f_exit != -2) {
+#pragma unroll
+                for (int mm = 1; mm < 4; mm++) face_poly<true>(G, mm, dp, 0.0, ls[mm], lq[mm - 1]);
+            }
+            if (f_exit != -1) {
+                // coordinates where k_continue takes the path up: the exit point, or
+                // the start for a path handed over whole
+#pragma unroll
+                for (int c = 0; c < 3; c++) rec->lam[c] = f_exit >= 0 ? horner4(lq[c], s_exit) : ls[c + 1];
             } else {
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
-                    out.x[(int64_t)c * out.cap + i] = horner4(pc, 1.0);
-                }
+                for (int c = 0; c < 3; c++) out.lam[(int64_t)c * out.cap + i] = horner4(lq[c], 1.0);
                 out.tet[i] = th;
             }
             if (f_exit != -2) {
                 const double s_hi = f_exit < 0 ? 1.0 : s_exit;
-                double lq[3][5];  // l_1..l_3 along the path in the home tet
-#pragma unroll
-                for (int mm = 1; mm < 4; mm++) face_poly<true>(G, mm, cp, 0.0, lq[mm - 1]);
                 if (s_hi > 0.0) {
                     double dep[N1];
                     segment_moments<K>(lq, s_hi, sp.qw, gl, dep);
@@ -973,7 +1012,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
 // every segment's current moments go to the spill pool tagged with
 // (sorted particle, segment), so their reduction order is canonical.
 template <int K, typename R>
-__global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restrict__ A)
+__global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restrict__ A)
 {
     const GMesh m = gview(A->m);
     const GParticles<R> out = gview<R>(A->out);
@@ -997,65 +1036,89 @@ __global__ __launch_bounds__(BLK, 3) void k_continue(const ParticleArgs *__restr
         bool gone = false;  // absorbed at a wall
         if (pending >= 0) {
             // the exit found in the home tet: cross it now
-            double cp[5][3];
+            double dp[4][3], lam[4];
 #pragma unroll
-            for (int d = 0; d < 5; d++)
+            for (int d = 0; d < 4; d++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) cp[d][c] = rec->cp[3 * d + c];
+                for (int c = 0; c < 3; c++) dp[d][c] = rec->dp[3 * d + c];
+            lam[1] = rec->lam[0];
+            lam[2] = rec->lam[1];
+            lam[3] = rec->lam[2];
+            lam[0] = bary0(lam[1], lam[2], lam[3]);
             ncross++;
             ncr++;
             const unsigned long long nrf0 = nrf;
-            gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, cp, out, i, nrf, absorb);
+            gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, dp, lam, out, i, nrf, absorb);
+#pragma unroll
+            for (int c = 0; c < 3; c++) rec->lam[c] = lam[c + 1];
             if (nrf != nrf0) {
 #pragma unroll
-                for (int d = 0; d < 5; d++)
+                for (int d = 0; d < 4; d++)
 #pragma unroll
-                    for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+                    for (int c = 0; c < 3; c++) rec->dp[3 * d + c] = dp[d][c];
             }
             if (gone) nab++;
         }
         while (!gone) {
             // the path stays in the record between segments and is re-read here,
             // so that it is not held in registers through the deposit
-            double cp[5][3];
+            double dp[4][3], ls[4];
 #pragma unroll
-            for (int d = 0; d < 5; d++)
+            for (int d = 0; d < 4; d++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) cp[d][c] = rec->cp[3 * d + c];
+                for (int c = 0; c < 3; c++) dp[d][c] = rec->dp[3 * d + c];
+            ls[1] = rec->lam[0];
+            ls[2] = rec->lam[1];
+            ls[3] = rec->lam[2];
+            ls[0] = bary0(ls[1], ls[2], ls[3]);
             const gptr<const double> G = m.geo + (int64_t)t * 16;
             double s_exit;
-            int f_exit = fast_exit<false>(G, cp, s_lo, entry, s_exit);
-            if (f_exit == -2) f_exit = find_exit<false>(G, cp, s_lo, entry, s_exit);
+            int f_exit = fast_exit<false>(G, dp, ls, s_lo, entry, s_exit);
+            if (f_exit == -2) f_exit = find_exit<false>(G, dp, ls, s_lo, entry, s_exit);
             const double s_hi = f_exit < 0 ? 1.0 : s_exit;
             double lq[3][5];  // l_1..l_3 of this tet along the path from s_lo
 #pragma unroll
-            for (int mm = 1; mm < 4; mm++) face_poly<false>(G, mm, cp, s_lo, lq[mm - 1]);
+            for (int mm = 1; mm < 4; mm++) face_poly<false>(G, mm, dp, s_lo, ls[mm], lq[mm - 1]);
             const int t_seg = t;
+            const bool crossing = f_exit >= 0 && ncross < MAX_CROSS;
             bool more = false;
-            if (f_exit >= 0 && ncross < MAX_CROSS) {
-                ncross++;
-                ncr++;
-                const unsigned long long nrf0 = nrf;
-                gone = cross_face<R>(m, G, f_exit, t, entry, cp, out, i, nrf, absorb);
-                if (nrf != nrf0) {  // a wall reflection changed the path
+            {
+                // coordinates at the segment's end: the exit point, handed to the
+                // next tet, or the end of the path
+                double le[4];
 #pragma unroll
-                    for (int d = 0; d < 5; d++)
+                for (int c = 0; c < 3; c++) le[c + 1] = horner4(lq[c], (crossing ? s_exit : 1.0) - s_lo);
+                le[0] = bary0(le[1], le[2], le[3]);
+                if (crossing) {
+                    ncross++;
+                    ncr++;
+                    // the path again from the record (a wall mirrors it), not held
+                    // in registers since the exit search
+                    asm volatile("" ::: "memory");
+                    double dq[4][3];
 #pragma unroll
-                        for (int c = 0; c < 3; c++) rec->cp[3 * d + c] = cp[d][c];
+                    for (int d = 0; d < 4; d++)
+#pragma unroll
+                        for (int c = 0; c < 3; c++) dq[d][c] = rec->dp[3 * d + c];
+                    const unsigned long long nrf0 = nrf;
+                    gone = cross_face<R>(m, G, f_exit, t, entry, dq, le, out, i, nrf, absorb);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) rec->lam[c] = le[c + 1];
+                    if (nrf != nrf0) {  // a wall reflection changed the path
+#pragma unroll
+                        for (int d = 0; d < 4; d++)
+#pragma unroll
+                            for (int c = 0; c < 3; c++) rec->dp[3 * d + c] = dq[d][c];
+                    }
+                    more = !gone;
+                    if (gone) nab++;
+                } else {
+                    if (f_exit >= 0) errs |= ERR_CROSS;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) out.lam[(int64_t)c * out.cap + i] = le[c + 1];
+                    if (!(le[1] == le[1] && le[2] == le[2] && le[3] == le[3])) errs |= ERR_NAN;
+                    out.tet[i] = t;
                 }
-                more = !gone;
-                if (gone) nab++;
-            } else {
-                if (f_exit >= 0) errs |= ERR_CROSS;
-                double rn[3];
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    const double pc[5] = {cp[0][c], cp[1][c], cp[2][c], cp[3][c], cp[4][c]};
-                    rn[c] = horner4(pc, 1.0);
-                    out.x[(int64_t)c * out.cap + i] = rn[c];
-                }
-                if (!(rn[0] == rn[0] && rn[1] == rn[1] && rn[2] == rn[2])) errs |= ERR_NAN;
-                out.tet[i] = t;
             }
             asm volatile("" ::: "memory");
             // every path's last segment has a record, also of zero length: it
@@ -1167,7 +1230,7 @@ __global__ void k_permute(DevParticles in, DevParticles out, const uint32_t *__r
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = perm[i];
-    for (int c = 0; c < 3; c++) out.x[c * out.cap + i] = in.x[c * in.cap + j];
+    for (int c = 0; c < 3; c++) out.lam[c * out.cap + i] = in.lam[c * in.cap + j];
     for (int c = 0; c < 3; c++) ((double *)out.v)[c * out.cap + i] = ((const double *)in.v)[c * in.cap + j];
     for (int c = 0; c < 9; c++) ((R *)out.vh)[c * out.cap + i] = ((const R *)in.vh)[c * in.cap + j];
     for (int c = 0; c < 9; c++) ((R *)out.ah)[c * out.cap + i] = ((const R *)in.ah)[c * in.cap + j];
@@ -1484,9 +1547,8 @@ __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__rest
 // nodal charge per tet (order-k W0 values times q w), same tiling as k_particle
 template <int K>
 __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__restrict__ perm,
-                                                 const int32_t *__restrict__ off, const double *__restrict__ x,
-                                                 int64_t cap, double qw, int tpw, double *__restrict__ Pr,
-                                                 const int32_t *__restrict__ ptet)
+                                                 const int32_t *__restrict__ off, const double *__restrict__ lam,
+                                                 int64_t cap, double qw, int tpw, double *__restrict__ Pr)
 {
     using O = Ord<K>;
     constexpr int N0 = O::N0;
@@ -1506,11 +1568,11 @@ __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__re
         const int i = base + tid;
         if (i < pend) {
             const uint32_t slot = perm[i];
-            const int64_t t = ptet[slot];
-            const double *g = &m.geo[16 * t];
-            const double r0 = x[slot], r1 = x[cap + slot], r2 = x[2 * cap + slot];
             double l[4];
-            for (int f = 0; f < 4; f++) l[f] = g[4 * f] + g[4 * f + 1] * r0 + g[4 * f + 2] * r1 + g[4 * f + 3] * r2;
+            l[1] = lam[slot];
+            l[2] = lam[cap + slot];
+            l[3] = lam[2 * cap + slot];
+            l[0] = bary0(l[1], l[2], l[3]);
             if constexpr (K == 1) {
                 for (int f = 0; f < 4; f++) s_w[f][tid] = qw * l[f];
             } else {
@@ -1894,14 +1956,15 @@ __global__ void k_add_f2d(int64_t n, const float *__restrict__ in, double scale,
 // Gauss check partial sums: |GtDe + d|^2, |Gtg - d|^2, |GtDe + Gtg|^2, |d|^2 with d = rho - rho0
 __global__ __launch_bounds__(BLK) void k_gauss_partial(int64_t n, const double *__restrict__ a,
                                                        const double *__restrict__ g, const double *__restrict__ rho,
-                                                       const double *__restrict__ rho0, double *__restrict__ partial)
+                                                       const double *__restrict__ rho0, double gscale,
+                                                       double *__restrict__ partial)
 {
     __shared__ double s[4][BLK];
     const int tid = threadIdx.x;
     double v[4] = {0, 0, 0, 0};
     for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
-        double d = rho[i] - rho0[i];
-        double x1 = a[i] + d, x2 = g[i] - d, x3 = a[i] + g[i];
+        const double d = rho[i] - rho0[i], ai = a[i] / gscale, gi = g[i] / gscale;
+        double x1 = ai + d, x2 = gi - d, x3 = ai + gi;
         v[0] += x1 * x1;
         v[1] += x2 * x2;
         v[2] += x3 * x3;
@@ -1944,6 +2007,13 @@ hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const do
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, cap, x, tet, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bary(const DevMesh &m, int64_t n, int64_t cap, double *x, const int32_t *tet, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_bary, dim3(nblk(n)), dim3(BLK), 0, s, m, n, cap, x, tet);
     return hipGetLastError();
 }
 
@@ -2124,15 +2194,15 @@ hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, con
     return hipGetLastError();
 }
 
-hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *x,
-                          const int32_t *ptet, int64_t cap, double qw, double *Pr, hipStream_t s)
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *lam,
+                          int64_t cap, double qw, double *Pr, hipStream_t s)
 {
     const int tpw = order == 1 ? 64 : 25;  // BLK / n0
     const unsigned grid = (unsigned)((m.nt + tpw - 1) / tpw);
     if (order == 1)
-        hipLaunchKernelGGL(k_rho_tet<1>, dim3(grid), dim3(BLK), 0, s, m, perm, off, x, cap, qw, tpw, Pr, ptet);
+        hipLaunchKernelGGL(k_rho_tet<1>, dim3(grid), dim3(BLK), 0, s, m, perm, off, lam, cap, qw, tpw, Pr);
     else
-        hipLaunchKernelGGL(k_rho_tet<2>, dim3(grid), dim3(BLK), 0, s, m, perm, off, x, cap, qw, tpw, Pr, ptet);
+        hipLaunchKernelGGL(k_rho_tet<2>, dim3(grid), dim3(BLK), 0, s, m, perm, off, lam, cap, qw, tpw, Pr);
     return hipGetLastError();
 }
 
@@ -2268,10 +2338,11 @@ hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStr
 }
 
 hipError_t gauss_norms(int64_t n, const double *GtDe, const double *Gtg, const double *rho, const double *rho0,
-                       double *partial, double *out4, hipStream_t s)
+                       double gscale, double *partial, double *out4, hipStream_t s)
 {
     const int64_t nb = red_grid(n, BLK);
-    hipLaunchKernelGGL(k_gauss_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, GtDe, Gtg, rho, rho0, partial);
+    hipLaunchKernelGGL(k_gauss_partial, dim3((unsigned)nb), dim3(BLK), 0, s, n, GtDe, Gtg, rho, rho0, gscale,
+                       partial);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, nb, 4, out4);
     return hipGetLastError();
 }
@@ -2285,6 +2356,296 @@ hipError_t dot_det(int64_t n, const double *a, const double *b, double *partial,
 }
 
 int64_t gauss_partial_entries() { return 4 * (int64_t)RED_BLOCKS; }
+
+// ------------------------------------------- compensated sums, double-double SpMV
+// Error-free transformations (Knuth's TwoSum, and TwoProd through the fused
+// multiply-add) for the Gauss check: the running sums e and g keep their plain
+// FP64 value in hi (bit for bit what hi + d gives) and the rounding error of
+// every addition in lo, and the check's products are accumulated as in the
+// compensated dot product of Ogita, Rump and Oishi (Dot2), i.e. as if in twice
+// the working precision.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e)
+{
+    // no contraction here or in the helpers below: once inlined, a product
+    // feeding these sums must not fuse into an FMA, which would drop the
+    // rounding errors the pairs carry
+#pragma clang fp contract(off)
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__global__ void k_add_comp(int64_t n, double *__restrict__ hi, double *__restrict__ lo, const double *__restrict__ d)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s, e;
+    two_sum(hi[i], d[i], s, e);
+    hi[i] = s;
+    lo[i] += e;
+}
+
+// y = A (x_hi + x_lo), one row per thread, Dot2 accumulation; y_hi + y_lo is
+// the result to about twice FP64 (y_lo may be null: y_hi is then the rounded sum)
+__global__ __launch_bounds__(BLK) void k_spmv_dd(int64_t rows, const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                 const double *__restrict__ x_hi, const double *__restrict__ x_lo,
+                                                 double *__restrict__ y_hi, double *__restrict__ y_lo)
+{
+#pragma clang fp contract(off)
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double s = 0.0, c = 0.0;
+    for (int64_t k = ptr[r]; k < ptr[r + 1]; k++) {
+        const double a = val[k];
+        const int32_t j = idx[k];
+        const double p = a * x_hi[j];
+        const double q = fma(a, x_hi[j], -p);
+        double t, e;
+        two_sum(s, p, t, e);
+        s = t;
+        c += q + e + a * x_lo[j];
+    }
+    double h, l;
+    two_sum(s, c, h, l);
+    y_hi[r] = h;
+    if (y_lo) y_lo[r] = l;
+}
+
+hipError_t add_comp(int64_t n, double *hi, double *lo, const double *d, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_comp, dim3(nblk(n)), dim3(BLK), 0, s, n, hi, lo, d);
+    return hipGetLastError();
+}
+
+hipError_t spmv_dd(const DevCSR &A, const double *x_hi, const double *x_lo, double *y_hi, double *y_lo,
+                   hipStream_t s)
+{
+    if (A.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv_dd, dim3(nblk(A.rows)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, A.val, x_hi, x_lo,
+                       y_hi, y_lo);
+    return hipGetLastError();
+}
+
+// Linear combination of sparse products and vectors in double-double:
+//   out = a1 (P1 x1) + a2 (P2 (x2 + x2lo)) + c1 v1 + c2 v2
+// (any operand may be null), as out_hi + out_lo (out_lo may be null: out_hi is
+// then the rounded result).  L lanes per row each accumulate a compensated dot
+// product (Dot2), the lanes' pairs are added with TwoSum, and the row's terms
+// are scaled with TwoProd and summed compensated.  The field update takes its
+// right-hand side and its refinement residuals from here, so that their
+// discrete divergence is that of the exact arithmetic to about twice FP64.
+struct DD {
+    double s = 0.0, c = 0.0;
+};
+__device__ __forceinline__ void dd_add(DD &a, double x)
+{
+#pragma clang fp contract(off)
+    double t, e;
+    two_sum(a.s, x, t, e);
+    a.s = t;
+    a.c += e;
+}
+__device__ __forceinline__ void dd_fma(DD &a, double u, double v)  // a += u v
+{
+#pragma clang fp contract(off)
+    const double p = u * v;
+    const double q = fma(u, v, -p);
+    dd_add(a, p);
+    a.c += q;
+}
+__device__ __forceinline__ void dd_add_scaled(DD &a, double k, const DD &b)  // a += k b
+{
+#pragma clang fp contract(off)
+    dd_fma(a, k, b.s);
+    a.c += k * b.c;
+}
+
+template <int L>
+__device__ inline DD row_dot_dd(const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                const double *__restrict__ val, const double *__restrict__ x,
+                                const double *__restrict__ xlo, int64_t r, int lane)
+{
+#pragma clang fp contract(off)
+    DD a;
+    for (int64_t k = ptr[r] + lane; k < ptr[r + 1]; k += L) {
+        const double v = val[k];
+        const int32_t j = idx[k];
+        dd_fma(a, v, x[j]);
+        if (xlo) a.c += v * xlo[j];
+    }
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) {
+        const double s2 = __shfl_xor(a.s, o, L), c2 = __shfl_xor(a.c, o, L);
+        double t, e;
+        two_sum(a.s, s2, t, e);
+        a.s = t;
+        a.c += c2 + e;
+    }
+    return a;
+}
+
+template <int L>
+__global__ __launch_bounds__(BLK) void k_combo_dd(int64_t rows, DevCSR P1, const double *__restrict__ x1, double a1,
+                                                  DevCSR P2, const double *__restrict__ x2,
+                                                  const double *__restrict__ x2lo, double a2,
+                                                  const double *__restrict__ v1, double c1,
+                                                  const double *__restrict__ v2, double c2,
+                                                  double *__restrict__ out_hi, double *__restrict__ out_lo)
+{
+#pragma clang fp contract(off)
+    const int64_t r = ((int64_t)blockIdx.x * BLK + threadIdx.x) / L;
+    const int lane = threadIdx.x % L;
+    if (r >= rows) return;  // whole groups of L lanes leave together
+    DD acc;
+    if (P1.ptr) {
+        const DD d = row_dot_dd<L>(P1.ptr, P1.idx, P1.val, x1, nullptr, r, lane);
+        dd_add_scaled(acc, a1, d);
+    }
+    if (P2.ptr) {
+        const DD d = row_dot_dd<L>(P2.ptr, P2.idx, P2.val, x2, x2lo, r, lane);
+        dd_add_scaled(acc, a2, d);
+    }
+    if (lane != 0) return;
+    if (v1) dd_fma(acc, c1, v1[r]);
+    if (v2) dd_fma(acc, c2, v2[r]);
+    double h, l;
+    two_sum(acc.s, acc.c, h, l);
+    out_hi[r] = h;
+    if (out_lo) out_lo[r] = l;
+}
+
+hipError_t combo_dd(int64_t rows, const DevCSR *P1, const double *x1, double a1, const DevCSR *P2, const double *x2,
+                    const double *x2lo, double a2, const double *v1, double c1, const double *v2, double c2,
+                    double *out_hi, double *out_lo, hipStream_t s)
+{
+    if (rows == 0) return hipSuccess;
+    DevCSR none{};
+    constexpr int L = 8;
+    const int64_t threads = rows * L;
+    hipLaunchKernelGGL(k_combo_dd<L>, dim3((unsigned)((threads + BLK - 1) / BLK)), dim3(BLK), 0, s, rows,
+                       P1 ? *P1 : none, x1, a1, P2 ? *P2 : none, x2, x2lo, a2, v1, c1, v2, c2, out_hi, out_lo);
+    return hipGetLastError();
+}
+
+// x += scale f, compensated: the rounding error of each addition goes to xlo
+__global__ void k_add_f2d_comp(int64_t n, const float *__restrict__ f, double scale, double *__restrict__ x,
+                               double *__restrict__ xlo)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s, e;
+    two_sum(x[i], scale * (double)f[i], s, e);
+    x[i] = s;
+    xlo[i] += e;
+}
+
+hipError_t add_f2d_comp(int64_t n, const float *f, double scale, double *x, double *xlo, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f2d_comp, dim3(nblk(n)), dim3(BLK), 0, s, n, f, scale, x, xlo);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ impressed field
+// Moments f_l = sum_q w_q vol_T scale B(x_q) . W2_l(x_q) of one tet per thread
+// (collapsed Gauss rule: P points with barycentrics lamq, weights wq summing to
+// 1), into Pf[t][n2l].  W2_l = phi_l(lam) W~_abc with W~_abc = 2 (l_a X_bc
+// - l_b X_ac + l_c X_ab), X_pq = grad l_p x grad l_q: the face functions the
+// gather evaluates.
+template <int K>
+__global__ void k_impressed_rhs(DevMesh m, int P, const double *__restrict__ lamq, const double *__restrict__ wq,
+                                const double *__restrict__ B, double scale, double *__restrict__ Pf)
+{
+    using O = Ord<K>;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m.nt) return;
+    const double *g = &m.geo[16 * t];
+    double X[6][3];
+    for (int q = 0; q < 6; q++) {
+        const double *ga = &g[4 * EA[q] + 1], *gb = &g[4 * EB[q] + 1];
+        X[q][0] = ga[1] * gb[2] - ga[2] * gb[1];
+        X[q][1] = ga[2] * gb[0] - ga[0] * gb[2];
+        X[q][2] = ga[0] * gb[1] - ga[1] * gb[0];
+    }
+    // grad l_1 . (grad l_2 x grad l_3) = 1 / (6 vol), up to sign
+    const double det = g[5] * X[5][0] + g[6] * X[5][1] + g[7] * X[5][2];
+    const double vs = scale / (6.0 * fabs(det));
+    double f[O::N2];
+    for (int l = 0; l < O::N2; l++) f[l] = 0.0;
+    for (int q = 0; q < P; q++) {
+        const double *lam = &lamq[4 * q];
+        const double *b = &B[3 * (t * P + q)];
+        const double w = wq[q] * vs;
+        double BX[6];
+        for (int p = 0; p < 6; p++) BX[p] = b[0] * X[p][0] + b[1] * X[p][1] + b[2] * X[p][2];
+        for (int fi = 0; fi < 4; fi++) {
+            const int a = FV[fi][0], bb = FV[fi][1], c = FV[fi][2];
+            const double tf = w * 2.0 * (lam[a] * BX[FP[fi][0]] - lam[bb] * BX[FP[fi][1]] + lam[c] * BX[FP[fi][2]]);
+            if constexpr (K == 1) {
+                f[fi] += tf;
+            } else {
+                f[3 * fi] += (4.0 * lam[a] - 1.0) * tf;
+                f[3 * fi + 1] += (4.0 * lam[bb] - 1.0) * tf;
+                f[3 * fi + 2] += (4.0 * lam[c] - 1.0) * tf;
+                if (fi < 3) f[12 + fi] += 4.0 * lam[3 - fi] * tf;
+            }
+        }
+    }
+    for (int l = 0; l < O::N2; l++) Pf[t * O::N2 + l] = f[l];
+}
+
+hipError_t launch_impressed_rhs(int order, const DevMesh &m, int P, const double *lamq, const double *wq,
+                                const double *B, double scale, double *Pf, hipStream_t s)
+{
+    if (m.nt == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((m.nt + BLK - 1) / BLK);
+    if (order == 1)
+        hipLaunchKernelGGL(k_impressed_rhs<1>, dim3(grid), dim3(BLK), 0, s, m, P, lamq, wq, B, scale, Pf);
+    else
+        hipLaunchKernelGGL(k_impressed_rhs<2>, dim3(grid), dim3(BLK), 0, s, m, P, lamq, wq, B, scale, Pf);
+    return hipGetLastError();
+}
+
+// out = a .* b
+__global__ void k_mul(int64_t n, const double *__restrict__ a, const double *__restrict__ b, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] * b[i];
+}
+
+hipError_t mul(int64_t n, const double *a, const double *b, double *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mul, dim3(nblk(n)), dim3(BLK), 0, s, n, a, b, out);
+    return hipGetLastError();
+}
+
+// Jacobi weights: 1 / (diagonal of A), or of A diag(D)^-1 A^T when Dinv is given
+// (with A = K^T and Dinv = 1 / diag(*nu): the diagonal of K^T *nu K without
+// *nu's off-diagonal part); 1 where the diagonal is not positive
+__global__ void k_jacobi(int64_t rows, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                         const double *__restrict__ val, const double *__restrict__ Dinv, double *__restrict__ dinv)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    double d = 0.0;
+    for (int64_t k = ptr[r]; k < ptr[r + 1]; k++) {
+        if (Dinv) d += val[k] * val[k] / Dinv[idx[k]];
+        else if (idx[k] == r) d = val[k];
+    }
+    dinv[r] = d > 0.0 ? 1.0 / d : 1.0;
+}
+
+hipError_t jacobi(const DevCSR &A, const double *Dinv, double *dinv, hipStream_t s)
+{
+    if (A.rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi, dim3(nblk(A.rows)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, A.val, Dinv, dinv);
+    return hipGetLastError();
+}
 
 // --------------------------------------------------- no-allocation scratch
 // Device memory of the entry point that allocates nothing: one array per

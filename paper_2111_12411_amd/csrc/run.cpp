@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -272,9 +273,11 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     assemble(m, p.dt, ops, (p.beta / p.gamma) * (p.beta / p.gamma));
     upload_csr(A, ops.A, mixed);
     upload_csr(Meps, ops.Meps, false);
-    upload_csr(Ct, ops.Ct, false);
+    upload_csr(Mnu, ops.Mnu, false);
     upload_csr(K, ops.K, false);
+    upload_csr(Kt, ops.Kt, false);
     upload_csr(Gt, ops.Gt, false);
+    gscale = ops.gscale;
     {
         // preconditioner: inverse 2x2 diagonal blocks when A is 2x2-blocked, else 1/A_ii
         std::vector<double> dinv = ops.Adiag_inv;
@@ -303,7 +306,7 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     upload(d_inc_idx, ops.inc_idx, stream);
     upload(d_inc0_ptr, ops.inc0_ptr, stream);
     upload(d_inc0_idx, ops.inc0_idx, stream);
-    nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Ct.nnz() + ops.K.nnz() + ops.Gt.nnz();
+    nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Mnu.nnz() + ops.K.nnz() + ops.Kt.nnz() + ops.Gt.nnz();
     a_nnz = ops.A.nnz();
     // fields and solver vectors
     const int64_t N1 = m.N1, N1i = m.N1_int, N2 = m.N2, N0i = m.N0_int;
@@ -311,17 +314,22 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     d_b.alloc(N2 * 8);
     d_g.alloc(std::max<int64_t>(N1i, 1) * 8);
     d_dg.alloc(std::max<int64_t>(N1i, 1) * 8);
+    for (auto *v : {&d_e_lo, &d_g_lo, &d_y1_lo}) v->alloc(std::max<int64_t>(N1i, 1) * 8);
     zero(d_e);
     zero(d_b);
     zero(d_g);
     zero(d_dg);
+    zero(d_e_lo);
+    zero(d_g_lo);
     if (mixed) {
         d_e32.alloc(N1 * 4);
         d_b32.alloc(N2 * 4);
         zero(d_e32);
         zero(d_b32);
     }
-    for (auto *v : {&v_x, &v_r, &v_z, &v_p, &v_q, &v_rhs, &v_tmp}) v->alloc(std::max<int64_t>(N1i, 1) * 8);
+    for (auto *v : {&v_x, &v_r, &v_z, &v_p, &v_q, &v_rhs, &v_tmp, &v_rhs_lo, &v_x_lo, &v_xs})
+        v->alloc(std::max<int64_t>(N1i, 1) * 8);
+    v_nu.alloc(std::max<int64_t>(N2, 1) * 8);
     if (mixed)
         for (auto *v : {&f_x, &f_r, &f_z, &f_p, &f_q}) v->alloc(std::max<int64_t>(N1i, 1) * 4);
     v_u.alloc(std::max<int64_t>(N2, 1) * 8);
@@ -329,10 +337,14 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
         d_eprev.alloc(std::max<int64_t>(N1i, 1) * 8);
         d_bprev.alloc(std::max<int64_t>(N2, 1) * 8);
         d_dgprev.alloc(std::max<int64_t>(N1i, 1) * 8);
+        d_dprev.alloc(std::max<int64_t>(N1i, 1) * 8);
+        d_dprev_lo.alloc(std::max<int64_t>(N1i, 1) * 8);
         v_b2.alloc(std::max<int64_t>(N2, 1) * 8);
         zero(d_eprev);
         zero(d_bprev);
         zero(d_dgprev);
+        zero(d_dprev);
+        zero(d_dprev_lo);
     }
     const int64_t maxrows = std::max<int64_t>({N1i, N2, N0i, 1});
     d_partial.alloc((size_t)(maxrows / 4 + 1024) * 4 * 8);
@@ -360,6 +372,9 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
     d_args.alloc(sizeof(ParticleArgs));
     for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
+    // FEMPIC_GRAPHS=0 launches the PCG batches kernel by kernel instead of replaying graphs
+    const char *g = std::getenv("FEMPIC_GRAPHS");
+    use_graphs = !(g && std::strcmp(g, "0") == 0);
     HIPCHECK(hipStreamSynchronize(stream));
 }
 
@@ -367,6 +382,8 @@ Run::~Run()
 {
     if (log) std::fclose(log);
     if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &gx : pcg_graph)
+        if (gx) (void)hipGraphExecDestroy(gx);
     for (auto ev : {ev_a, ev_b, ev_c1, ev_c, ev_d, ev_e})
         if (ev) (void)hipEventDestroy(ev);
     if (h_pin) (void)hipHostFree(h_pin);
@@ -398,13 +415,13 @@ void Run::alloc_particles(int64_t n)
     const size_t rs = mixed ? 4 : 8;
     for (int k = 0; k < 2; k++) {
         PBufs &B = pb[k];
-        B.x.alloc(cap * 3 * 8);
+        B.lam.alloc(cap * 3 * 8);
         B.v.alloc(cap * 3 * 8);
         B.vh.alloc(cap * 9 * rs);
         B.ah.alloc(cap * 9 * rs);
         B.tet.alloc(cap * 4);
         B.id.alloc(cap * 4);
-        B.d.x = (double *)B.x.p;
+        B.d.lam = (double *)B.lam.p;
         B.d.v = B.v.p;
         B.d.vh = B.vh.p;
         B.d.ah = B.ah.p;
@@ -533,7 +550,7 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     std::vector<double> xs(3 * std::max<int64_t>(n, 1));
     for (int64_t i = 0; i < n; i++)
         for (int c = 0; c < 3; c++) xs[c * n + i] = pos[3 * i + c];
-    if (n) HIPCHECK(hipMemcpyAsync(B.x.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
+    if (n) HIPCHECK(hipMemcpyAsync(B.lam.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
     HIPCHECK(hipStreamSynchronize(stream));
     for (int64_t i = 0; i < n; i++)
         for (int c = 0; c < 3; c++) xs[c * n + i] = vel[3 * i + c];
@@ -546,7 +563,7 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     std::vector<int32_t> tets;
     if (m.is_cube) {
         HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
-        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.x.p, (int32_t *)B.tet.p, p_small,
+        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.lam.p, (int32_t *)B.tet.p, p_small,
                                     stream));
         int32_t err = 0;
         HIPCHECK(hipMemcpyAsync(&err, p_small, 4, hipMemcpyDeviceToHost, stream));
@@ -558,9 +575,11 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
         if (n) HIPCHECK(hipMemcpyAsync(B.tet.p, tets.data(), n * 4, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipStreamSynchronize(stream));
     }
+    // the positions become barycentric coordinates in the located tets
+    HIPCHECK(launch_to_bary(dm, n, B.d.cap, (double *)B.lam.p, (const int32_t *)B.tet.p, stream));
     // AB4 start-up from the current fields
-    HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)d_b.p, (const float *)d_e32.p,
-                            (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
+    HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
+                            (const float *)d_e32.p, (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
     // store the particles in tet order, so the first step reads them like every later one
     {
         const uint32_t *perm = sort_current();
@@ -571,6 +590,7 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     // Gauss reference charge
     compute_rho((double *)d_rho0.p);
     zero(d_g);
+    zero(d_g_lo);
     HIPCHECK(hipStreamSynchronize(stream));
     have_prev = false;  // the three-level scheme starts from a history at rest
     absorbed_total = 0;
@@ -638,8 +658,8 @@ void Run::compute_rho(double *dst, double *Pr)
 {
     if (!Pr) Pr = (double *)d_Pr.p;
     const uint32_t *perm = sort_current();
-    HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d.x, pb[cur].d.tet, pb[cur].d.cap,
-                            q * w, Pr, stream));
+    HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d.lam, pb[cur].d.cap, q * w, Pr,
+                            stream));
     HIPCHECK(launch_scatter((const int64_t *)d_inc0_ptr.p, (const int32_t *)d_inc0_idx.p, m.N0_int,
                             (const double *)Pr, dst, stream));
 }
@@ -675,7 +695,7 @@ void Run::particle_phase()
         ParticleArgs *ha = (ParticleArgs *)((char *)h_pin + 128);
         ha->m = dm;
         ha->e = mixed ? (const void *)d_e32.p : (const void *)d_e.p;
-        ha->b = mixed ? (const void *)d_b32.p : (const void *)d_b.p;
+        ha->b = gather_b();
         ha->perm = perm;
         ha->off = (const int32_t *)d_off.p;
         ha->in = pb[cur].d;
@@ -785,22 +805,27 @@ void Run::field_phase_three_level()
     double *ep = (double *)d_eprev.p, *bp = (double *)d_bprev.p, *dgp = (double *)d_dgprev.p;
     double *w = (double *)v_tmp.p, *u = (double *)v_u.p, *rhs = (double *)v_rhs.p, *y = (double *)d_y1.p;
     double *b2 = (double *)v_b2.p, *d = (double *)v_x.p;
+    double *dp = (double *)d_dprev.p, *dp_lo = (double *)d_dprev_lo.p;
     if (!have_prev) {
         HIPCHECK(axpby(N1i, 1.0, e, 0.0, e, ep, stream));
         HIPCHECK(axpby(N2, 1.0, b, 0.0, b, bp, stream));
         HIPCHECK(axpby(N1i, 0.0, dg, 0.0, dg, dgp, stream));
+        HIPCHECK(axpby(N1i, 0.0, dg, 0.0, dg, dp, stream));
+        HIPCHECK(axpby(N1i, 0.0, dg, 0.0, dg, dp_lo, stream));
         have_prev = true;
     }
-    HIPCHECK(axpby(N1i, 1.0, dg, 1.0, g, g, stream));
+    HIPCHECK(add_comp(N1i, g, (double *)d_g_lo.p, dg, stream));
     // u = B0 b + B1 b^{n-1} - (dt beta / gamma) K ((an + beta) e + am e^{n-1})
     HIPCHECK(axpby(N1i, an + bt, e, am, ep, w, stream));
     HIPCHECK(axpby(N2, B0, b, B1, bp, u, stream));
     HIPCHECK(spmv(K.desc, w, u, -dt * bt / gm, 1.0, u, stream));
-    // rhs = (dt/gamma) K^T *nu u - dg - ((1-gamma)/gamma) (*eps (e - e^{n-1}) + dg^{n-1})
-    HIPCHECK(spmv(Ct.desc, u, rhs, dt / gm, -1.0, dg, stream));
-    HIPCHECK(axpby(N1i, 1.0, e, -1.0, ep, w, stream));
-    HIPCHECK(spmv(Meps.desc, w, y, 1.0, 1.0, dgp, stream));
-    HIPCHECK(axpby(N1i, 1.0, rhs, -(1.0 - gm) / gm, y, rhs, stream));
+    // rhs = (dt/gamma) K^T (*nu u) - ((1-gamma)/gamma) (*eps (e - e^{n-1}) + dg^{n-1}) - dg in
+    // double-double, with e - e^{n-1} the previous increment kept as hi + lo
+    HIPCHECK(spmv(Mnu.desc, u, (double *)v_nu.p, 1.0, 0.0, nullptr, stream));
+    const double cprev = -(1.0 - gm) / gm;
+    HIPCHECK(combo_dd(N1i, &Kt.desc, (const double *)v_nu.p, dt / gm, &Meps.desc, dp, dp_lo, cprev, dgp, cprev, dg,
+                      -1.0, rhs, (double *)v_rhs_lo.p, stream));
+    (void)y;
     if (mixed) solve_mixed();
     else solve_fp64();
     // b^{n+1} = -((1-2gamma) b + (gamma-1) b^{n-1}) / gamma - (dt/gamma) K ((beta + an) e + beta d + am e^{n-1})
@@ -812,12 +837,13 @@ void Run::field_phase_three_level()
     HIPCHECK(axpby(N2, 1.0, b, 0.0, b, bp, stream));
     HIPCHECK(axpby(N2, 1.0, b2, 0.0, b2, b, stream));
     HIPCHECK(axpby(N1i, 1.0, e, 0.0, e, ep, stream));
-    HIPCHECK(axpby(N1i, 1.0, e, 1.0, d, e, stream));
+    HIPCHECK(add_comp(N1i, e, (double *)d_e_lo.p, d, stream));
+    HIPCHECK(axpby(N1i, 1.0, (const double *)d_e_lo.p, 1.0, (const double *)v_x_lo.p, (double *)d_e_lo.p, stream));
     HIPCHECK(axpby(N1i, 1.0, dg, 0.0, dg, dgp, stream));
-    if (mixed) {
-        HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
-        HIPCHECK(cast_d2f(m.N2, b, (float *)d_b32.p, 1.0, stream));
-    }
+    HIPCHECK(axpby(N1i, 1.0, d, 0.0, d, dp, stream));
+    HIPCHECK(axpby(N1i, 1.0, (const double *)v_x_lo.p, 0.0, (const double *)v_x_lo.p, dp_lo, stream));
+    if (mixed) HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
+    refresh_gather_b();
     HIPCHECK(hipEventRecord(ev_e, stream));
 }
 
@@ -828,23 +854,25 @@ void Run::field_phase()
     const int64_t N1i = m.N1_int, N2 = m.N2;
     const double dt = prm.dt;
     double *e = (double *)d_e.p, *b = (double *)d_b.p, *dg = (double *)d_dg.p;
-    // g += dg
-    HIPCHECK(axpby(N1i, 1.0, dg, 1.0, (const double *)d_g.p, (double *)d_g.p, stream));
-    // u = b - dt/2 K e ; rhs = dt Ct u - dg
+    // g += dg (compensated: d_g_lo keeps the rounding errors for the Gauss check)
+    HIPCHECK(add_comp(N1i, (double *)d_g.p, (double *)d_g_lo.p, dg, stream));
+    // u = b - dt/2 K e ; rhs = dt K^T (*nu u) - dg, the last step in double-double
+    // (whatever *nu u rounds to, G^T K^T of it is zero)
     HIPCHECK(spmv(K.desc, e, (double *)v_u.p, -0.5 * dt, 1.0, b, stream));
-    HIPCHECK(spmv(Ct.desc, (const double *)v_u.p, (double *)v_rhs.p, dt, -1.0, dg, stream));
-    // solve A d = rhs
+    HIPCHECK(spmv(Mnu.desc, (const double *)v_u.p, (double *)v_nu.p, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(combo_dd(N1i, &Kt.desc, (const double *)v_nu.p, dt, nullptr, nullptr, nullptr, 0.0, dg, -1.0, nullptr,
+                      0.0, (double *)v_rhs.p, (double *)v_rhs_lo.p, stream));
+    // solve A d = rhs (d = v_x + v_x_lo)
     if (mixed) solve_mixed();
     else solve_fp64();
-    // b -= dt/2 K (2 e + d) ; e += d
+    // b -= dt/2 K (2 e + d) ; e += d (compensated)
     HIPCHECK(axpby(N1i, 2.0, e, 1.0, (const double *)v_x.p, (double *)v_tmp.p, stream));
     HIPCHECK(spmv(K.desc, (const double *)v_tmp.p, b, -0.5 * dt, 1.0, b, stream));
-    HIPCHECK(axpby(N1i, 1.0, e, 1.0, (const double *)v_x.p, e, stream));
+    HIPCHECK(add_comp(N1i, e, (double *)d_e_lo.p, (const double *)v_x.p, stream));
+    HIPCHECK(axpby(N1i, 1.0, (const double *)d_e_lo.p, 1.0, (const double *)v_x_lo.p, (double *)d_e_lo.p, stream));
     (void)N2;
-    if (mixed) {
-        HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
-        HIPCHECK(cast_d2f(m.N2, b, (float *)d_b32.p, 1.0, stream));
-    }
+    if (mixed) HIPCHECK(cast_d2f(m.N1, e, (float *)d_e32.p, 1.0, stream));
+    refresh_gather_b();
     HIPCHECK(hipEventRecord(ev_e, stream));
 }
 
@@ -855,26 +883,67 @@ double Run::read_sc(int k)
     return *(double *)h_pin;
 }
 
-void Run::solve_fp64()
+// Eight PCG iterations: FP64 on v_*, or the FP32 inner solve on f_*.  The
+// kernels and their arguments are the same for every batch (the iteration
+// parity alternates 0, 1 within it), so the batch is captured once per run as a
+// HIP graph and replayed; it holds kernels only.
+void Run::pcg_batch(bool fp32)
 {
-    Range rg("fempic pcg");
     const int64_t n = m.N1_int;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
-    HIPCHECK(pcg_init(n, (const double *)v_rhs.p, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+    auto launch = [&]() {
+        for (int k = 0; k < 8; k++) {
+            if (fp32)
+                HIPCHECK(pcg32_iter(A.desc, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
+                                    (float *)f_q.p, (const float *)d_dinv32.p, part, sc, k & 1, stream));
+            else
+                HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                                  (double *)v_q.p, (const double *)d_dinv.p, part, sc, k & 1, stream));
+        }
+    };
+    if (!use_graphs) return launch();
+    hipGraphExec_t &gx = pcg_graph[fp32 ? 1 : 0];
+    if (!gx) {
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            launch();
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHECK(hipStreamEndCapture(stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            gx = nullptr;
+            throw Error(FEMPIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHECK(hipGraphLaunch(gx, stream));
+}
+
+// PCG (FP64) on A x = b from x = 0 until |r|^2 <= tol2 (or at the attainable
+// accuracy); returns |r|^2 of the recurrence.  The iterate is v_x.
+double Run::pcg64(const double *b, double tol2, double bb)
+{
+    const int64_t n = m.N1_int;
+    double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
+    HIPCHECK(pcg_init(n, b, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
                       (const double *)d_dinv.p, part, sc, A.desc.bptr != nullptr, stream));
-    const double bb = read_sc(SC_BB);
-    last_iters = 0;
-    last_relres = 0;
-    if (bb == 0.0) return;
-    const double tol2 = prm.pcg_rtol * prm.pcg_rtol * bb;
-    const int check = 8;
-    double rr = bb, best = bb;
-    int stall = 0;
-    for (int it = 0; it < prm.pcg_maxit;) {
-        for (int k = 0; k < check && it < prm.pcg_maxit; k++, it++)
-            HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
-                              (double *)v_q.p, (const double *)d_dinv.p, part, sc, it & 1, stream));
-        last_iters = it;
+    double rr = read_sc(SC_BB), best = rr;
+    if (rr == 0.0) return 0.0;
+    int stall = 0, it = 0;
+    while (it < prm.pcg_maxit) {
+        if (it + 8 <= prm.pcg_maxit) {
+            pcg_batch(false);
+            it += 8;
+        } else {
+            for (; it < prm.pcg_maxit; it++)
+                HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                                  (double *)v_q.p, (const double *)d_dinv.p, part, sc, it & 1, stream));
+        }
         rr = read_sc(SC_RR);
         if (!(rr == rr)) throw Error(FEMPIC_ESOLVE, "field solve produced NaN");
         if (rr <= tol2) break;
@@ -885,30 +954,85 @@ void Run::solve_fp64()
             break;  // at the attainable accuracy
         }
     }
-    last_relres = std::sqrt(rr / bb);
+    last_iters += it;
     if (!(rr <= tol2) && !(rr <= 1e-24 * bb))
+        throw Error(FEMPIC_ESOLVE, "PCG did not reach the tolerance: relres " + std::to_string(std::sqrt(rr / bb)));
+    return rr;
+}
+
+// The residual of the refinement, r = (rhs + rhs_lo) - A (x + x_lo), in
+// double-double, rounded into r; returns |r|^2.
+double Run::residual_dd(const double *x, const double *x_lo, double *r)
+{
+    const int64_t n = m.N1_int;
+    HIPCHECK(combo_dd(n, nullptr, nullptr, 0.0, &A.desc, x, x_lo, -1.0, (const double *)v_rhs.p, 1.0,
+                      (const double *)v_rhs_lo.p, 1.0, r, nullptr, stream));
+    HIPCHECK(dot_det(n, r, r, (double *)d_partial.p, (double *)d_sc.p + 12, stream));
+    return read_sc(12);
+}
+
+// Both solvers leave the solution as v_x + v_x_lo.  The right-hand side is
+// v_rhs + v_rhs_lo (double-double), and the solve is refined against it with
+// residuals in double-double down to gauss_rtol (below pcg_rtol): the part of
+// the residual that reaches G^T is what each step would otherwise add to the
+// Gauss residual, and at FP64 accuracy (1e-15 relative) it adds up, step after
+// step, to more than 1e-12 over a thousand steps.
+double Run::solve_target() const { return std::min(prm.pcg_rtol, GAUSS_RTOL); }
+
+void Run::solve_fp64()
+{
+    Range rg("fempic pcg");
+    const int64_t n = m.N1_int;
+    const double *rhs = (const double *)v_rhs.p;
+    double *x = (double *)v_x.p, *xs = (double *)v_xs.p, *xlo = (double *)v_x_lo.p, *rc = (double *)v_tmp.p;
+    HIPCHECK(dot_det(n, rhs, rhs, (double *)d_partial.p, (double *)d_sc.p + 12, stream));
+    const double bb = read_sc(12);
+    last_iters = 0;
+    last_relres = 0;
+    HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, xlo, stream));
+    if (bb == 0.0) {
+        HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, x, stream));
+        return;
+    }
+    const double tgt2 = solve_target() * solve_target() * bb;
+    pcg64(rhs, prm.pcg_rtol * prm.pcg_rtol * bb, bb);
+    HIPCHECK(axpby(n, 1.0, x, 0.0, x, xs, stream));
+    double rr = residual_dd(xs, xlo, rc);
+    for (int cyc = 0; cyc < 4 && rr > tgt2; cyc++) {
+        // correction A c = r to the reduction the target still needs (margin 4)
+        const double red = std::max(1e-10, std::min(1e-1, 0.25 * std::sqrt(tgt2 / rr)));
+        pcg64(rc, red * red * rr, rr);
+        HIPCHECK(add_comp(n, xs, xlo, x, stream));
+        rr = residual_dd(xs, xlo, rc);
+    }
+    HIPCHECK(axpby(n, 1.0, xs, 0.0, xs, x, stream));
+    last_relres = std::sqrt(rr / bb);
+    if (!(last_relres <= prm.pcg_rtol))
         throw Error(FEMPIC_ESOLVE, "PCG did not reach the tolerance: relres " + std::to_string(last_relres));
 }
 
-// FP32 PCG inside FP64 iterative refinement: x = 0, r = rhs; repeat:
-// solve A32 d = r/|r| to 1e-5 in FP32, x += |r| d, r = rhs - A x in FP64.
+// FP32 PCG inside FP64 iterative refinement: x = 0, r = rhs; repeat: an inner
+// FP32 solve of A c = r / |r|, x += |r| c (compensated into x + x_lo), r = the
+// double-double residual, until |r| <= target |rhs|.
 void Run::solve_mixed()
 {
     Range rg("fempic pcg (FP32 inner, FP64 refinement)");
     const int64_t n = m.N1_int;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
-    double *x = (double *)v_x.p, *r = (double *)v_r.p;
+    double *x = (double *)v_x.p, *xlo = (double *)v_x_lo.p, *r = (double *)v_r.p;
     const double *rhs = (const double *)v_rhs.p;
     HIPCHECK(dot_det(n, rhs, rhs, part, sc + 12, stream));
     const double bb = read_sc(12);
     last_iters = 0;
     last_relres = 0;
     HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, x, stream));
+    HIPCHECK(axpby(n, 0.0, rhs, 0.0, rhs, xlo, stream));
     HIPCHECK(axpby(n, 1.0, rhs, 0.0, rhs, r, stream));
     if (bb == 0.0) return;
+    const double tgt = solve_target();
     double rr = bb;
     for (int outer = 0; outer < 12; outer++) {
-        if (rr <= prm.pcg_rtol * prm.pcg_rtol * bb) break;
+        if (rr <= tgt * tgt * bb) break;
         const double scale = std::sqrt(rr);
         HIPCHECK(cast_d2f(n, r, (float *)f_q.p, 1.0 / scale, stream));
         HIPCHECK(pcg32_init(n, (const float *)f_q.p, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
@@ -917,28 +1041,24 @@ void Run::solve_mixed()
         // the inner solve reduces its residual by 1e-5 (about what FP32 holds),
         // or by less on the last cycle: just what the target still needs, with
         // a margin of 4
-        const double need = 0.25 * prm.pcg_rtol * std::sqrt(bb / rr);
+        const double need = 0.25 * tgt * std::sqrt(bb / rr);
         const double red = std::max(1e-5, std::min(1.0, need));
         const double tol32 = red * red * bb32;
         int it = 0;
         double r32 = bb32;
         while (it < prm.pcg_maxit) {
-            for (int k = 0; k < 8; k++, it++)
-                HIPCHECK(pcg32_iter(A.desc, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
-                                    (float *)f_q.p, (const float *)d_dinv32.p, part, sc, it & 1, stream));
+            pcg_batch(true);
+            it += 8;
             r32 = read_sc(SC_RR);
             if (!(r32 == r32)) throw Error(FEMPIC_ESOLVE, "FP32 inner solve produced NaN");
             if (r32 <= tol32) break;
         }
         last_iters += it;
-        HIPCHECK(add_f2d(n, (const float *)f_x.p, scale, x, stream));
-        // r = rhs - A x (FP64)
-        HIPCHECK(spmv(A.desc, x, r, -1.0, 1.0, rhs, stream));
-        HIPCHECK(dot_det(n, r, r, part, sc + 12, stream));
-        rr = read_sc(12);
+        HIPCHECK(add_f2d_comp(n, (const float *)f_x.p, scale, x, xlo, stream));
+        rr = residual_dd(x, xlo, r);
     }
     last_relres = std::sqrt(rr / bb);
-    if (!(rr <= prm.pcg_rtol * prm.pcg_rtol * bb) && !(last_relres < 1e-12))
+    if (!(last_relres <= prm.pcg_rtol) && !(last_relres < 1e-12))
         throw Error(FEMPIC_ESOLVE, "refined solve did not reach the tolerance: relres " + std::to_string(last_relres));
 }
 
@@ -1017,7 +1137,7 @@ void Run::gauss(double out[3])
     Range rg("fempic gauss residual (a8)");
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     gauss_with((double *)d_Pr.p, (double *)d_rho.p, (double *)d_GtDe.p, (double *)d_Gtg.p, (double *)d_y1.p,
-               (double *)d_partial.p, (double *)d_sc.p + 16, out);
+               (double *)d_y1_lo.p, (double *)d_partial.p, (double *)d_sc.p + 16, out);
 }
 
 // The Gauss check with every intermediate in the library's static device
@@ -1043,7 +1163,7 @@ void Run::gauss_noalloc(double out[3])
     const size_t n0 = (size_t)std::max<int64_t>(m.N0_int, 1), n1 = (size_t)std::max<int64_t>(m.N1_int, 1);
     const size_t b_pr = al((size_t)m.nt * n0l * 8), b_v0 = al(n0 * 8), b_v1 = al(n1 * 8),
                  b_part = al((size_t)gauss_partial_entries() * 8);
-    const size_t need = b_pr + 3 * b_v0 + b_v1 + b_part + 256;
+    const size_t need = b_pr + 3 * b_v0 + 2 * b_v1 + b_part + 256;
     if (need > NOALLOC_SCRATCH_BYTES)
         throw Error(FEMPIC_EINVAL, "the Gauss check of this mesh needs " + std::to_string(need) +
                                        " bytes of scratch; the library's static scratch holds " +
@@ -1054,21 +1174,26 @@ void Run::gauss_noalloc(double out[3])
     double *GtDe = (double *)(p += b_v0);
     double *Gtg = (double *)(p += b_v0);
     double *y1 = (double *)(p += b_v0);
+    double *y1_lo = (double *)(p += b_v1);
     double *part = (double *)(p += b_v1);
     double *out4 = (double *)(p += b_part);
-    gauss_with(Pr, rho, GtDe, Gtg, y1, part, out4, out);
+    gauss_with(Pr, rho, GtDe, Gtg, y1, y1_lo, part, out4, out);
 }
 
-void Run::gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *partial, double *out4,
-                     double out[3])
+// G^T *eps e and G^T g are sums of large terms that cancel down to the nodal
+// charge change; they are evaluated from the compensated running sums (hi +
+// lo) in double-double, so the check sees the scheme's Gauss residual, not the
+// rounding of FP64 running sums and products.
+void Run::gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *y1_lo, double *partial,
+                     double *out4, double out[3])
 {
     compute_rho(rho, Pr);
     const int64_t N0i = m.N0_int;
-    HIPCHECK(spmv(Meps.desc, (const double *)d_e.p, y1, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(spmv(Gt.desc, (const double *)y1, GtDe, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(spmv(Gt.desc, (const double *)d_g.p, Gtg, 1.0, 0.0, nullptr, stream));
+    HIPCHECK(spmv_dd(Meps.desc, (const double *)d_e.p, (const double *)d_e_lo.p, y1, y1_lo, stream));
+    HIPCHECK(spmv_dd(Gt.desc, y1, y1_lo, GtDe, nullptr, stream));
+    HIPCHECK(spmv_dd(Gt.desc, (const double *)d_g.p, (const double *)d_g_lo.p, Gtg, nullptr, stream));
     HIPCHECK(gauss_norms(N0i, (const double *)GtDe, (const double *)Gtg, (const double *)rho,
-                         (const double *)d_rho0.p, partial, out4, stream));
+                         (const double *)d_rho0.p, gscale, partial, out4, stream));
     HIPCHECK(hipMemcpyAsync(h_pin, out4, 32, hipMemcpyDeviceToHost, stream));
     sync();
     const double *v = (const double *)h_pin;
@@ -1112,16 +1237,16 @@ void Run::fields_set(const double *e, int64_t ne, const double *b, int64_t nb)
             if (k < m.N1_int) ei[k] = e[i];
         }
         HIPCHECK(hipMemcpy(d_e.p, ei.data(), m.N1 * 8, hipMemcpyHostToDevice));
+        zero(d_e_lo);
+        HIPCHECK(hipStreamSynchronize(stream));
     }
     if (b) {
         if (nb < m.N2) throw Error(FEMPIC_EINVAL, "b buffer too short");
         HIPCHECK(hipMemcpy(d_b.p, b, m.N2 * 8, hipMemcpyHostToDevice));
     }
-    if (mixed) {
-        HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
-        HIPCHECK(cast_d2f(m.N2, (const double *)d_b.p, (float *)d_b32.p, 1.0, stream));
-        HIPCHECK(hipStreamSynchronize(stream));
-    }
+    if (mixed) HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
+    refresh_gather_b();
+    HIPCHECK(hipStreamSynchronize(stream));
 }
 
 void Run::deposit_get(double *dg, int64_t n)
@@ -1132,6 +1257,133 @@ void Run::deposit_get(double *dg, int64_t n)
     HIPCHECK(hipMemcpy(d.data(), d_dg.p, m.N1_int * 8, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < m.N1; i++) dg[i] = 0.0;
     for (int64_t k = 0; k < m.N1_int; k++) dg[m.int2nat1[k]] = d[k];
+}
+
+// ------------------------------------------------------- impressed field
+const void *Run::gather_b() const
+{
+    if (mixed) return d_b32.p;
+    return has_imp ? d_bg.p : d_b.p;
+}
+
+void Run::refresh_gather_b()
+{
+    const double *b = (const double *)d_b.p;
+    if (has_imp) {
+        HIPCHECK(axpby(m.N2, 1.0, b, 1.0, (const double *)d_bimp.p, (double *)d_bg.p, stream));
+        b = (const double *)d_bg.p;
+    }
+    if (mixed) HIPCHECK(cast_d2f(m.N2, b, (float *)d_b32.p, 1.0, stream));
+}
+
+double Run::cg_general(int64_t n, const std::function<void(const double *, double *)> &apply, const double *dinv,
+                       const double *b, double *x, double rtol, int maxit)
+{
+    DevBuf r, z, p, q;
+    for (DevBuf *v : {&r, &z, &p, &q}) v->alloc(std::max<int64_t>(n, 1) * 8);
+    double *part = (double *)d_partial.p, *sc = (double *)d_sc.p;
+    auto dot = [&](const double *a, const double *c) {
+        HIPCHECK(dot_det(n, a, c, part, sc + 12, stream));
+        return read_sc(12);
+    };
+    HIPCHECK(axpby(n, 0.0, b, 0.0, b, x, stream));
+    HIPCHECK(axpby(n, 1.0, b, 0.0, b, (double *)r.p, stream));
+    const double bb = dot(b, b);
+    if (bb == 0.0) return 0.0;
+    HIPCHECK(mul(n, dinv, (const double *)r.p, (double *)z.p, stream));
+    HIPCHECK(axpby(n, 1.0, (const double *)z.p, 0.0, (const double *)z.p, (double *)p.p, stream));
+    double rz = dot((const double *)r.p, (const double *)z.p), rr = bb;
+    for (int it = 0; it < maxit && rr > rtol * rtol * bb; it++) {
+        apply((const double *)p.p, (double *)q.p);
+        const double pq = dot((const double *)p.p, (const double *)q.p);
+        if (!(pq > 0.0)) break;  // the iterate has left the operator's range: at its accuracy
+        const double al = rz / pq;
+        HIPCHECK(axpby(n, 1.0, x, al, (const double *)p.p, x, stream));
+        HIPCHECK(axpby(n, 1.0, (const double *)r.p, -al, (const double *)q.p, (double *)r.p, stream));
+        HIPCHECK(mul(n, dinv, (const double *)r.p, (double *)z.p, stream));
+        const double rz2 = dot((const double *)r.p, (const double *)z.p);
+        rr = dot((const double *)r.p, (const double *)r.p);
+        HIPCHECK(axpby(n, 1.0, (const double *)z.p, rz2 / rz, (const double *)p.p, (double *)p.p, stream));
+        rz = rz2;
+    }
+    return std::sqrt(rr / bb);
+}
+
+// Projection of an impressed B onto the face space (Sec. III-C).  The moments
+// f_l = <W2_l, B / mu0> come from B at the n1d^3 collapsed Gauss points of each
+// tet.  Without the constraint, *nu b = f.  With it (eq. (conB)), b is the
+// *nu-orthogonal projection onto the faces whose discrete divergence vanishes;
+// on a simply connected box these are exactly the curls of edge fields, b = K a
+// over every W1 DoF (walls included), so a solves K^T *nu K a = K^T f (CG on a
+// semi-definite system with a consistent right-hand side) and b = K a is
+// divergence-free by construction, as the saddle-point system's b is.
+void Run::impressed_set(const double *B, int64_t n, int n1d, bool constrained, double *b_out, int64_t nb)
+{
+    sync();
+    AccountScope charge(&acct);
+    if (n1d < 1 || n1d > 8) throw Error(FEMPIC_EINVAL, "the rule takes 1 to 8 points per direction");
+    const int P = n1d * n1d * n1d;
+    if (!B || n < (int64_t)m.nt * P) throw Error(FEMPIC_EINVAL, "B must hold n_tet * n1d^3 points");
+    if (b_out && nb < m.N2) throw Error(FEMPIC_EINVAL, "b buffer too short");
+    for (int64_t k = 0; k < 3 * (int64_t)m.nt * P; k++)
+        if (!std::isfinite(B[k])) throw Error(FEMPIC_EINVAL, "non-finite impressed B");
+    const int64_t N2 = m.N2, N1 = m.N1, n2l = m.order == 2 ? 15 : 4;
+    std::vector<double> lam, wq;
+    impressed_rule(n1d, lam, wq);
+    ImpressedOps io;
+    assemble_impressed(m, io);
+    DevBuf d_lam, d_w, d_B, d_Pf, d_ip, d_ii, d_f;
+    upload(d_lam, lam, stream);
+    upload(d_w, wq, stream);
+    d_B.alloc((size_t)m.nt * P * 3 * 8);
+    HIPCHECK(hipMemcpyAsync(d_B.p, B, (size_t)m.nt * P * 3 * 8, hipMemcpyHostToDevice, stream));
+    d_Pf.alloc((size_t)m.nt * n2l * 8);
+    upload(d_ip, io.inc2_ptr, stream);
+    upload(d_ii, io.inc2_idx, stream);
+    d_f.alloc(std::max<int64_t>(N2, 1) * 8);
+    HIPCHECK(launch_impressed_rhs(m.order, dm, P, (const double *)d_lam.p, (const double *)d_w.p,
+                                  (const double *)d_B.p, 1.0 / MU0, (double *)d_Pf.p, stream));
+    HIPCHECK(launch_scatter((const int64_t *)d_ip.p, (const int32_t *)d_ii.p, N2, (const double *)d_Pf.p,
+                            (double *)d_f.p, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    d_B.release();
+    d_Pf.release();
+    if (!d_bimp.p) d_bimp.alloc(std::max<int64_t>(N2, 1) * 8);
+    double *bi = (double *)d_bimp.p;
+    DevBuf dnu;
+    dnu.alloc(std::max<int64_t>(N2, 1) * 8);
+    HIPCHECK(jacobi(Mnu.desc, nullptr, (double *)dnu.p, stream));
+    const int maxit = std::max(prm.pcg_maxit, 1000);
+    if (!constrained) {
+        auto apply = [&](const double *x, double *y) { HIPCHECK(spmv(Mnu.desc, x, y, 1.0, 0.0, nullptr, stream)); };
+        const double rel = cg_general(N2, apply, (const double *)dnu.p, (const double *)d_f.p, bi, 1e-14, maxit);
+        if (!(rel <= 1e-12)) throw Error(FEMPIC_ESOLVE, "impressed-field projection: relres " + std::to_string(rel));
+    } else {
+        DevCSRBuf Ka, Kta;
+        upload_csr(Ka, io.K, false);
+        upload_csr(Kta, io.Kt, false);
+        DevBuf rhs, a, dk, t2;
+        for (DevBuf *v : {&rhs, &a, &dk}) v->alloc(std::max<int64_t>(N1, 1) * 8);
+        t2.alloc(std::max<int64_t>(N2, 1) * 8);
+        // K^T f, then K^T *nu K a = K^T f, Jacobi from the diagonal of K^T diag(*nu) K
+        HIPCHECK(spmv(Kta.desc, (const double *)d_f.p, (double *)rhs.p, 1.0, 0.0, nullptr, stream));
+        HIPCHECK(jacobi(Kta.desc, (const double *)dnu.p, (double *)dk.p, stream));
+        auto apply = [&](const double *x, double *y) {
+            HIPCHECK(spmv(Ka.desc, x, (double *)t2.p, 1.0, 0.0, nullptr, stream));
+            HIPCHECK(spmv(Mnu.desc, (const double *)t2.p, bi, 1.0, 0.0, nullptr, stream));
+            HIPCHECK(spmv(Kta.desc, bi, y, 1.0, 0.0, nullptr, stream));
+        };
+        const double rel = cg_general(N1, apply, (const double *)dk.p, (const double *)rhs.p, (double *)a.p, 1e-12,
+                                      20 * maxit);
+        if (!(rel <= 1e-8)) throw Error(FEMPIC_ESOLVE, "constrained impressed-field projection: relres " +
+                                                           std::to_string(rel));
+        HIPCHECK(spmv(Ka.desc, (const double *)a.p, bi, 1.0, 0.0, nullptr, stream));
+    }
+    if (!d_bg.p && !mixed) d_bg.alloc(std::max<int64_t>(N2, 1) * 8);
+    has_imp = true;
+    refresh_gather_b();
+    if (b_out) HIPCHECK(hipMemcpyAsync(b_out, bi, N2 * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
 }
 
 void Run::rho_get(double *rho, double *rho0, int64_t n)
@@ -1184,15 +1436,20 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
     std::vector<int32_t> id(np), tt(np);
     const int64_t cap = B.d.cap;
     for (int c = 0; c < 3; c++) {
-        HIPCHECK(hipMemcpy(&x[c * np], (double *)B.x.p + c * cap, np * 8, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(&x[c * np], (double *)B.lam.p + c * cap, np * 8, hipMemcpyDeviceToHost));
         HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
     }
     HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
     HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < np; i++) {
         const int64_t o = id[i];
+        // position from the barycentric coordinates: x_0 + sum_m l_m (x_m - x_0)
+        const int32_t *tv = &m.tets[4 * (int64_t)tt[i]];
+        const double *x0 = &m.xyz[3 * tv[0]];
         for (int c = 0; c < 3; c++) {
-            if (pos) pos[3 * o + c] = x[c * np + i];
+            double r = x0[c];
+            for (int k = 1; k < 4; k++) r += x[(k - 1) * np + i] * (m.xyz[3 * tv[k] + c] - x0[c]);
+            if (pos) pos[3 * o + c] = r;
             if (vel) vel[3 * o + c] = v[c * np + i];
         }
         if (tet) tet[o] = tt[i];
@@ -1209,7 +1466,7 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
 // next steps bit for bit as the saved run does.
 namespace {
 constexpr char CKPT_MAGIC[8] = {'F', 'E', 'M', 'P', 'I', 'C', 'C', 'K'};
-constexpr uint32_t CKPT_VERSION = 2;
+constexpr uint32_t CKPT_VERSION = 3;
 
 struct CkptHeader {
     char magic[8];
@@ -1221,21 +1478,45 @@ struct CkptHeader {
     int32_t have_prev;   // three-level scheme: the field history below holds a step
     int32_t particle_bc;
     int64_t np_loaded;   // particles at load (ids are below it; absorbed ones are gone)
+    int32_t has_imp;     // an impressed field follows the payload's fields
+    int32_t reserved;
 };
 
-// 64-bit FNV-1a over the payload, eight bytes at a time
+// 64-bit FNV-1a over the payload taken as a stream of 8-byte words (a last
+// partial word is zero-padded), so the value does not depend on how the payload
+// is split into calls
 struct Hash64 {
     uint64_t h = 1469598103934665603ull;
+    unsigned char buf[8] = {};
+    int nbuf = 0;
+    void word(const unsigned char *c)
+    {
+        uint64_t wd;
+        std::memcpy(&wd, c, 8);
+        h = (h ^ wd) * 1099511628211ull;
+    }
     void add(const void *p, size_t n)
     {
         const unsigned char *c = (const unsigned char *)p;
         size_t i = 0;
-        for (; i + 8 <= n; i += 8) {
-            uint64_t wd;
-            std::memcpy(&wd, c + i, 8);
-            h = (h ^ wd) * 1099511628211ull;
+        while (nbuf && i < n) {
+            buf[nbuf++] = c[i++];
+            if (nbuf == 8) {
+                word(buf);
+                nbuf = 0;
+            }
         }
-        for (; i < n; i++) h = (h ^ c[i]) * 1099511628211ull;
+        for (; i + 8 <= n; i += 8) word(c + i);
+        while (i < n) buf[nbuf++] = c[i++];
+    }
+    uint64_t value() const
+    {
+        Hash64 t = *this;
+        if (t.nbuf) {
+            std::memset(t.buf + t.nbuf, 0, 8 - t.nbuf);
+            t.word(t.buf);
+        }
+        return t.h;
     }
 };
 
@@ -1301,6 +1582,7 @@ void Run::save(const char *path)
     h.have_prev = three_level && have_prev ? 1 : 0;
     h.particle_bc = prm.particle_bc;
     h.np_loaded = np_loaded;
+    h.has_imp = has_imp ? 1 : 0;
     CkptFile F(path, "wb");
     F.write(&h, sizeof h);
     std::vector<char> stage;
@@ -1311,7 +1593,7 @@ void Run::save(const char *path)
     };
     const int64_t cap = S.d.cap;
     const size_t rs = mixed ? 4 : 8;
-    for (int c = 0; c < 3; c++) put((const double *)S.x.p + c * cap, np * 8);
+    for (int c = 0; c < 3; c++) put((const double *)S.lam.p + c * cap, np * 8);
     for (int c = 0; c < 3; c++) put((const double *)S.v.p + c * cap, np * 8);
     for (int c = 0; c < 9; c++) put((const char *)S.vh.p + c * cap * rs, np * rs);
     for (int c = 0; c < 9; c++) put((const char *)S.ah.p + c * cap * rs, np * rs);
@@ -1321,12 +1603,17 @@ void Run::save(const char *path)
     put(d_b.p, m.N2 * 8);
     put(d_g.p, m.N1_int * 8);
     put(d_rho0.p, m.N0_int * 8);
+    put(d_e_lo.p, m.N1_int * 8);
+    put(d_g_lo.p, m.N1_int * 8);
     if (h.have_prev) {
         put(d_eprev.p, m.N1_int * 8);
         put(d_bprev.p, m.N2 * 8);
         put(d_dgprev.p, m.N1_int * 8);
+        put(d_dprev.p, m.N1_int * 8);
+        put(d_dprev_lo.p, m.N1_int * 8);
     }
-    const uint64_t sum = F.hash.h;
+    if (h.has_imp) put(d_bimp.p, m.N2 * 8);
+    const uint64_t sum = F.hash.value();
     F.write(&sum, 8, false);
     F.close_write();
 }
@@ -1351,6 +1638,7 @@ void Run::restore(const char *path)
     if (h.gamma != prm.gamma || h.beta != prm.beta)
         throw Error(FEMPIC_EINVAL, "checkpoint Newmark-beta parameters differ from the run's");
     if (h.have_prev != 0 && (h.have_prev != 1 || !three_level)) throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
+    if (h.has_imp != 0 && h.has_imp != 1) throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
     if (h.np < 0 || h.np >= ((int64_t)1 << 31) / 2 || h.steps < 0 || h.np_loaded < h.np ||
         h.np_loaded >= ((int64_t)1 << 31) / 2)
         throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
@@ -1363,8 +1651,9 @@ void Run::restore(const char *path)
         // the size the header implies, before anything is allocated for it
         const long here = std::ftell(F.f);
         const uint64_t want = (uint64_t)sizeof(CkptHeader) + (uint64_t)n * (6 * 8 + 18 * rs + 8) +
-                              (uint64_t)(m.N1 + m.N2 + m.N1_int + m.N0_int) * 8 +
-                              (h.have_prev ? (uint64_t)(2 * m.N1_int + m.N2) * 8 : 0) + 8;
+                              (uint64_t)(m.N1 + m.N2 + 3 * m.N1_int + m.N0_int) * 8 +
+                              (h.have_prev ? (uint64_t)(4 * m.N1_int + m.N2) * 8 : 0) +
+                              (h.has_imp ? (uint64_t)m.N2 * 8 : 0) + 8;
         if (here < 0 || std::fseek(F.f, 0, SEEK_END) != 0) throw Error(FEMPIC_EINVAL, "cannot read checkpoint " + F.path);
         const long size = std::ftell(F.f);
         if (size < 0 || (uint64_t)size != want || std::fseek(F.f, here, SEEK_SET) != 0)
@@ -1374,7 +1663,7 @@ void Run::restore(const char *path)
     std::vector<double> x(3 * n), v(3 * n);
     std::vector<char> vh(9 * n * rs), ah(9 * n * rs);
     std::vector<int32_t> tet(n), id(n);
-    std::vector<double> e(m.N1), b(m.N2), g(m.N1_int), rho0(m.N0_int);
+    std::vector<double> e(m.N1), b(m.N2), g(m.N1_int), rho0(m.N0_int), e_lo(m.N1_int), g_lo(m.N1_int);
     F.read(x.data(), x.size() * 8);
     F.read(v.data(), v.size() * 8);
     F.read(vh.data(), vh.size());
@@ -1385,16 +1674,27 @@ void Run::restore(const char *path)
     F.read(b.data(), b.size() * 8);
     F.read(g.data(), g.size() * 8);
     F.read(rho0.data(), rho0.size() * 8);
-    std::vector<double> ep, bp, dgp;
+    F.read(e_lo.data(), e_lo.size() * 8);
+    F.read(g_lo.data(), g_lo.size() * 8);
+    std::vector<double> ep, bp, dgp, dpv, dpl;
     if (h.have_prev) {
         ep.resize(m.N1_int);
         bp.resize(m.N2);
         dgp.resize(m.N1_int);
+        dpv.resize(m.N1_int);
+        dpl.resize(m.N1_int);
         F.read(ep.data(), ep.size() * 8);
         F.read(bp.data(), bp.size() * 8);
         F.read(dgp.data(), dgp.size() * 8);
+        F.read(dpv.data(), dpv.size() * 8);
+        F.read(dpl.data(), dpl.size() * 8);
     }
-    const uint64_t want = F.hash.h;
+    std::vector<double> bim;
+    if (h.has_imp) {
+        bim.resize(m.N2);
+        F.read(bim.data(), bim.size() * 8);
+    }
+    const uint64_t want = F.hash.value();
     uint64_t sum = 0;
     F.read(&sum, 8, false);
     if (sum != want) throw Error(FEMPIC_EINVAL, "checkpoint checksum mismatch: " + F.path);
@@ -1402,7 +1702,7 @@ void Run::restore(const char *path)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite position");
     for (double a : v)
         if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite velocity");
-    for (const std::vector<double> *f : {&e, &b, &ep, &bp})
+    for (const std::vector<double> *f : {&e, &b, &ep, &bp, &dpv, &dpl, &bim})
         for (double a : *f)
             if (!std::isfinite(a)) throw Error(FEMPIC_EINVAL, "checkpoint holds a non-finite field coefficient");
     for (const std::vector<char> *hv : {&vh, &ah})
@@ -1433,7 +1733,7 @@ void Run::restore(const char *path)
     auto get = [&](void *d, const void *src, size_t bytes) {
         if (bytes) HIPCHECK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
     };
-    for (int c = 0; c < 3; c++) get((double *)B.x.p + c * cap, &x[c * n], n * 8);
+    for (int c = 0; c < 3; c++) get((double *)B.lam.p + c * cap, &x[c * n], n * 8);
     for (int c = 0; c < 3; c++) get((double *)B.v.p + c * cap, &v[c * n], n * 8);
     for (int c = 0; c < 9; c++) get((char *)B.vh.p + c * cap * rs, &vh[c * n * rs], n * rs);
     for (int c = 0; c < 9; c++) get((char *)B.ah.p + c * cap * rs, &ah[c * n * rs], n * rs);
@@ -1443,19 +1743,27 @@ void Run::restore(const char *path)
     get(d_b.p, b.data(), b.size() * 8);
     get(d_g.p, g.data(), g.size() * 8);
     get(d_rho0.p, rho0.data(), rho0.size() * 8);
+    get(d_e_lo.p, e_lo.data(), e_lo.size() * 8);
+    get(d_g_lo.p, g_lo.data(), g_lo.size() * 8);
     if (h.have_prev) {
         get(d_eprev.p, ep.data(), ep.size() * 8);
         get(d_bprev.p, bp.data(), bp.size() * 8);
         get(d_dgprev.p, dgp.data(), dgp.size() * 8);
+        get(d_dprev.p, dpv.data(), dpv.size() * 8);
+        get(d_dprev_lo.p, dpl.data(), dpl.size() * 8);
     }
     have_prev = h.have_prev != 0;
+    has_imp = h.has_imp != 0;
+    if (has_imp) {
+        if (!d_bimp.p) d_bimp.alloc(std::max<int64_t>(m.N2, 1) * 8);
+        if (!mixed && !d_bg.p) d_bg.alloc(std::max<int64_t>(m.N2, 1) * 8);
+        get(d_bimp.p, bim.data(), bim.size() * 8);
+    }
     np_loaded = h.np_loaded;
     absorbed_total = h.np_loaded - h.np;
     last_absorb = 0;
-    if (mixed) {
-        HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
-        HIPCHECK(cast_d2f(m.N2, (const double *)d_b.p, (float *)d_b32.p, 1.0, stream));
-    }
+    if (mixed) HIPCHECK(cast_d2f(m.N1, (const double *)d_e.p, (float *)d_e32.p, 1.0, stream));
+    refresh_gather_b();
     HIPCHECK(hipStreamSynchronize(stream));
     steps_done = h.steps;
     gauss_step = 0;
@@ -1514,20 +1822,22 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     const double n1l = k2 ? 20 : 6, n2l = k2 ? 15 : 4, n0l = k2 ? 10 : 4;
     const double nt = (double)z.nt, N1 = (double)z.n1, N1i = (double)z.n1_int, N2 = (double)z.n2,
                  N0i = (double)z.n0_int;
-    const double nnzA = N1i * (k2 ? 46.0 : 17.0), nnzK = N2 * (k2 ? 13.0 : 3.0), nnzG = N0i * (k2 ? 25.0 : 15.0);
+    const double nnzA = N1i * (k2 ? 46.0 : 17.0), nnzK = N2 * (k2 ? 13.0 : 3.0), nnzG = N0i * (k2 ? 25.0 : 15.0),
+                 nnzNu = N2 * (k2 ? 24.0 : 7.0);
     const double rs = mixed ? 4 : 8;
     auto csr = [](double rows, double nnz) { return (rows + 1) * 8 + nnz * 12 + 256; };
-    // A and *eps, with 2x2 block copies at order 2; K, K^T *nu, G^T
-    double ops = 2 * csr(N1i, nnzA) + (mixed ? nnzA * 4 : 0) + 2 * csr(N2, nnzK) + csr(N0i, nnzG);
-    ops = ops - csr(N2, nnzK) + csr(N1i, nnzK);  // K^T *nu has N1_int rows
+    // A and *eps, with 2x2 block copies at order 2; K, K^T, *nu, G^T
+    double ops = 2 * csr(N1i, nnzA) + (mixed ? nnzA * 4 : 0) + csr(N2, nnzK) + csr(N1i, nnzK) + csr(N2, nnzNu) +
+                 csr(N0i, nnzG);
     if (k2) ops += 2 * ((N1i / 2 + 1) * 8 + nnzA * 9 + 256) + (mixed ? nnzA * 4 : 0);
     const double precond = (k2 ? 2 : 1) * N1i * (8 + (mixed ? 4 : 0));
     const double inc = (N1i + 1) * 8 + nt * n1l * 4 + (N0i + 1) * 8 + nt * n0l * 4;
     const double mesh = nt * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
-    double vecs = (N1 + N2) * 8 + 2 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
+    double vecs = (N1 + N2) * 8 + 5 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
                   (mixed ? 5 * N1i * 4 : 0) + N2 * 8 + 4 * N0i * 8;
+    vecs += 5 * N1i * 8 + N2 * 8;  // double-double halves, *nu u, the previous increment
     vecs += (std::max({N1i, N2, N0i, 1.0}) / 4 + 1024) * 32 + 512;
-    const double tets = nt * (n1l + n0l) * 8 + 5 * (nt + 1) * 4 + (double)CONT_BLOCKS * 32 + 4096;
+    const double tets = nt * (n1l + n0l) * 8 + 5 * (nt + 1) * 4 + (double)CONT_BLOCKS * NCNT * 8 + 4096;
     const double cap = (double)std::max<int64_t>(n, 1);
     const double parts = 2 * cap * (6 * 8 + 18 * rs + 8);
     auto sorts = [&](double c) {
@@ -1756,6 +2066,37 @@ int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n)
     API_BEGIN
     if (!run || !dg) throw Error(FEMPIC_EINVAL, "null argument");
     run->r->deposit_get(dg, n);
+    API_END
+}
+
+int32_t fempic_impressed_points(fempic_mesh mesh, int32_t n1d, double *xyz, int64_t n)
+{
+    API_BEGIN
+    if (!mesh) throw Error(FEMPIC_EINVAL, "null mesh");
+    if (n1d < 1 || n1d > 8) throw Error(FEMPIC_EINVAL, "the rule takes 1 to 8 points per direction");
+    const HostMesh &m = *mesh->m;
+    std::vector<double> lam, w;
+    impressed_rule(n1d, lam, w);
+    const int64_t P = (int64_t)w.size();
+    if (!xyz || n < m.nt * P) throw Error(FEMPIC_EINVAL, "xyz must hold n_tet * n1d^3 points");
+    for (int64_t t = 0; t < m.nt; t++) {
+        const int32_t *v = &m.tets[4 * t];
+        for (int64_t q = 0; q < P; q++)
+            for (int c = 0; c < 3; c++) {
+                double r = 0.0;
+                for (int k = 0; k < 4; k++) r += lam[4 * q + k] * m.xyz[3 * v[k] + c];
+                xyz[3 * (t * P + q) + c] = r;
+            }
+    }
+    API_END
+}
+
+int32_t fempic_impressed_set(fempic_run run, const double *B, int64_t n, int32_t n1d, int32_t constrained,
+                             double *b_out, int64_t nb)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->impressed_set(B, n, n1d, constrained != 0, b_out, nb);
     API_END
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdio>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -63,7 +64,7 @@ struct DevCSRBuf {
 };
 
 struct PBufs {
-    DevBuf x, v, vh, ah, tet, id;
+    DevBuf lam, v, vh, ah, tet, id;
     DevParticles d{};
 };
 
@@ -85,6 +86,10 @@ class Run {
     void fields_set(const double *e, int64_t ne, const double *b, int64_t nb);
     void deposit_get(double *dg, int64_t n);
     void rho_get(double *rho, double *rho0, int64_t n);
+    // impressed magnetic flux density: B sampled at the points of the n1d^3 rule
+    // of every tet, projected (constrained: onto the divergence-free faces) and
+    // kept as the run's impressed field; b_out (nullable) receives it
+    void impressed_set(const double *B, int64_t n, int n1d, bool constrained, double *b_out, int64_t nb);
     void particles_get(double *pos, double *vel, int64_t *tet, int64_t n);
     void history_get(double *vh, double *ah, int64_t n);
     void save(const char *path);
@@ -131,8 +136,8 @@ class Run {
     void locate_host(const double *pos, int64_t n, int32_t *out);
     void compute_rho(double *dst, double *Pr = nullptr);
     const PBufs &gather_current();
-    void gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *partial, double *out4,
-                    double out[3]);
+    void gauss_with(double *Pr, double *rho, double *GtDe, double *Gtg, double *y1, double *y1_lo, double *partial,
+                    double *out4, double out[3]);
     void particle_phase();
     void next_order(int64_t nrec, const uint32_t *srec);
     void commit_order();
@@ -140,17 +145,47 @@ class Run {
     void field_phase_three_level();
     void solve_fp64();
     void solve_mixed();
+    double pcg64(const double *b, double tol2, double bb);
+    // preconditioned CG on a symmetric positive semi-definite operator (consistent
+    // right-hand side) from x = 0 until |r| <= rtol |b|; returns the relative residual
+    double cg_general(int64_t n, const std::function<void(const double *, double *)> &apply, const double *dinv,
+                      const double *b, double *x, double rtol, int maxit);
+    // the field coefficients the particle kernels read: b (+ the impressed field),
+    // cast to FP32 in mixed precision
+    void refresh_gather_b();
+    const void *gather_b() const;
+    double residual_dd(const double *x, const double *x_lo, double *r);
+    double solve_target() const;
+    // the refined field solve's target relative residual (exact, in double-double)
+    static constexpr double GAUSS_RTOL = 1e-17;
     double read_sc(int k);
+    // 8 PCG iterations (FP64, or the FP32 inner solve) as one HIP graph replay,
+    // captured on first use; eager launches when graphs are off
+    void pcg_batch(bool fp32);
+    bool use_graphs = true;
+    hipGraphExec_t pcg_graph[2] = {nullptr, nullptr};
 
     DevBuf d_geo, d_nbr, d_map1, d_map2, d_map0;
-    DevCSRBuf A, Meps, Ct, K, Gt;
+    DevCSRBuf A, Meps, Mnu, K, Kt, Gt;
+    double gscale = 1.0;  // Gt holds gscale G^T
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
+    // rounding errors of the running sums e and g (compensated summation), and
+    // the low half of *eps e in the Gauss check
+    DevBuf d_e_lo, d_g_lo, d_y1_lo;
     // three-level Newmark-beta (gamma, beta other than 1/2, 1/4): e^{n-1}, b^{n-1},
     // g^n - g^{n-1}, and whether they hold a step yet (else the history is at rest)
     bool three_level = false, have_prev = false;
     DevBuf d_eprev, d_bprev, d_dgprev, v_b2;
     DevBuf v_x, v_r, v_z, v_p, v_q, v_rhs, v_tmp, v_u;
+    // double-double halves of the right-hand side and the solution, the FP64
+    // solver's accumulated solution, *nu u; the three-level scheme's previous
+    // increment e^n - e^{n-1} as hi + lo
+    DevBuf v_rhs_lo, v_x_lo, v_xs, v_nu, d_dprev, d_dprev_lo;
+    // impressed field (face coefficients, FP64) and, in FP64 runs that have one,
+    // b + it for the gather
+    bool has_imp = false;
+    DevBuf d_bimp, d_bg;
     DevBuf f_x, f_r, f_z, f_p, f_q;
     DevBuf d_partial, d_sc, d_rho, d_rho0, d_GtDe, d_Gtg, d_y1;
     DevBuf d_P, d_Pr, d_off, d_soff, d_ctl, d_cntb, d_args;

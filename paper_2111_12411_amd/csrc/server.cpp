@@ -51,7 +51,9 @@ struct fempic_server_s {
     std::condition_variable cv;
     std::deque<std::shared_ptr<Job>> queue;
     std::map<int64_t, std::shared_ptr<Job>> jobs;
-    std::vector<std::thread> slots;
+    // slot threads with their jobs; a finished one is joined the next time the
+    // admission thread wakes (its job is done, so it no longer needs the lock)
+    std::vector<std::pair<std::thread, std::shared_ptr<Job>>> slots;
     std::thread admit;
     int64_t next_ticket = 1;
     size_t used = 0;
@@ -97,6 +99,20 @@ struct fempic_server_s {
         cv.notify_all();
     }
 
+    // join the slot threads whose jobs are done (called with mu held)
+    void reap()
+    {
+        for (size_t k = 0; k < slots.size();) {
+            if (slots[k].second->done) {
+                slots[k].first.join();
+                slots[k] = std::move(slots.back());
+                slots.pop_back();
+            } else {
+                k++;
+            }
+        }
+    }
+
     void admit_main()
     {
         (void)hipSetDevice(device);
@@ -104,17 +120,19 @@ struct fempic_server_s {
         for (;;) {
             cv.wait(lk, [&] {
                 if (stop) return true;
+                reap();
                 if (queue.empty()) return false;
                 auto &j = queue.front();
                 return resident < prm.max_slots && used + j->footprint <= prm.hbm_budget;
             });
             if (stop) break;
+            reap();
             auto j = queue.front();
             queue.pop_front();
             used += j->footprint;
             resident++;
             j->t_admit = clk::now();
-            slots.emplace_back(&fempic_server_s::slot_main, this, j);
+            slots.emplace_back(std::thread(&fempic_server_s::slot_main, this, j), j);
         }
     }
 };
@@ -155,7 +173,7 @@ int32_t fempic_server_destroy(fempic_server s)
         s->cv.notify_all();
     }
     s->admit.join();
-    for (auto &t : s->slots) t.join();
+    for (auto &t : s->slots) t.first.join();
     delete s;
     return FEMPIC_OK;
 }

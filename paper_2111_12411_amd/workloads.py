@@ -23,8 +23,11 @@ CONFIGS = {
     # weight); 0.02 puts the Debye length at about 1.2 cells on this mesh
     3: dict(N=40, order=2, n=16_000_000, kind="oscillation", vth=0.02, steps=500, cfl=10.0, precision="mixed",
             omega_dt=0.02),
+    # 0.01 puts this run's Debye length (v_th = 0.01 c) at about 1.2 cells too; at 0.1 it is 0.12
+    # cells, and the finite-grid heating takes the crossings per particle-step from 0.5 to 8.6
+    # within 1000 steps
     5: dict(N=56, order=2, n=64_000_000, kind="two_stream", vth=0.01, drift=0.2, steps=1000, cfl=10.0,
-            precision="mixed"),
+            precision="mixed", omega_dt=0.01),
 }
 
 _EDGE = 1e-9  # keep initial positions off the walls

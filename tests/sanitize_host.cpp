@@ -48,8 +48,11 @@ int main()
             assemble(*m, 5 * m->dt_cfl, ops);
             check_csr(ops.A, m->N1_int, m->N1_int);
             check_csr(ops.Meps, m->N1_int, m->N1_int);
-            check_csr(ops.Ct, m->N1_int, m->N2);
+            check_csr(ops.Mnu, m->N2, m->N2);
             check_csr(ops.K, m->N2, m->N1_int);
+            check_csr(ops.Kt, m->N1_int, m->N2);
+            CHECK(ops.gscale == (m->order == 2 ? 3.0 : 1.0));
+            for (double v : ops.Gt.val) CHECK(v == std::nearbyint(v));
             check_csr(ops.Gt, m->N0_int, m->N1_int);
             CHECK((int64_t)ops.Adiag_inv.size() >= m->N1_int);
             CHECK((int64_t)ops.inc_ptr.size() == m->N1_int + 1);

@@ -33,6 +33,24 @@ def test_algorithmic_bytes_per_particle_and_tet():
     assert alg == 4_186_112_000
 
 
+def test_survey_byte_model():
+    """The scope's model: 2 x 112 B (mixed) or 2 x 196 B (FP64) of state per particle, 836 B per tet
+    at order 2 (312 B at order 1), 8 B per interior W1 DoF; the benchmark launch moves 3.924 GB,
+    about 245 B per particle-step."""
+    alg, state, tet = bench.survey_bytes(2, F.MIXED, 16_000_000, 384_000, 2_384_240)
+    assert state == 112 and tet == 836
+    assert alg == 16_000_000 * 224 + 384_000 * 836 + 2_384_240 * 8
+    assert round(alg / 16e6) == 245
+    alg, state, tet = bench.survey_bytes(2, F.FP64, 1, 0, 0)
+    assert state == 196 and alg == 392
+    _, _, tet = bench.survey_bytes(1, F.MIXED, 0, 1, 0)
+    assert tet == 216 + 96
+
+
+def test_oracle_thread_count_is_bounded():
+    assert 1 <= bench.oracle_threads() <= 16
+
+
 def _profile_copy(tmp_path, digest):
     root = tmp_path / "repo"
     (root / "profiles").mkdir(parents=True)
@@ -68,7 +86,7 @@ def test_profiled_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     assert bench.profiled_traffic() is None
 
 
-@pytest.mark.parametrize("cfg_id,omega_dt", [(1, 0.1), (2, 0.1), (3, 0.02), (5, 0.1)])
+@pytest.mark.parametrize("cfg_id,omega_dt", [(1, 0.1), (2, 0.1), (3, 0.02), (5, 0.01)])
 def test_config_weight_gives_the_plasma_frequency(cfg_id, omega_dt):
     n, dt = 1000, 2.5e-10
     w = W.config_weight(cfg_id, n, dt)

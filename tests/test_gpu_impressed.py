@@ -1,0 +1,101 @@
+"""GPU parity of the impressed-field projection (Sec. III-C, eq. (conB); Tables I
+and II) through the C ABI, and of the push in an impressed field.
+
+- The face coefficients of B(r) = sin(y) x + cos(x) y on the box of Tables I-II
+  (Kuhn-split, k = 1, 2) against the oracle's projection, without the
+  constraint (a mass-matrix solve) and with it (the oracle solves the
+  saddle-point system with the order-k [div] built from the volume functions;
+  the library the curl-curl system over all edges): the same coefficients, and
+  the library's constrained field is divergence-free to rounding while the
+  unconstrained one is not.
+- One step of particles in an impressed uniform B: positions and velocities
+  against the oracle stepping with that field as its b.
+- The impressed field travels in a checkpoint: a restored run steps bit for bit
+  as the saved one.
+"""
+import numpy as np
+import pytest
+
+import paper_2111_12411_amd as F
+from paper_2111_12411_amd import workloads as W
+from oracle import core, impressed as I, mesh as omesh
+from parity_util import close
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = -W.Q_E, W.M_E
+SIZE = (0.5, 0.15, 0.2)
+
+
+def sin_field(p):
+    return np.stack([np.sin(p[:, 1]), np.cos(p[:, 0]), 0 * p[:, 0]], axis=1)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_projection_matches_the_oracle(k):
+    m = I.block_mesh(3, SIZE, k)
+    ops = core.assemble(m)
+    mesh = F.Mesh.from_arrays(m.xyz, m.tets, k)
+    run = F.Run(mesh, mesh.info()["dt_cfl"], F.FP64)
+    pts = mesh.impressed_points(6)
+    B = sin_field(pts)
+    res = {}
+    for constrained in (False, True):
+        b_orc = I.project(m, ops, sin_field, constrained)
+        b = run.impress(B, 6, constrained)
+        close(b, b_orc, 1e-12 if not constrained else 1e-9)
+        res[constrained] = I.errors(m, b, sin_field)
+    (err_u, div_u), (err_c, div_c) = res[False], res[True]
+    # oracle on this machine: div 2.5e-2 / 1.6e-3 unconstrained (k = 1 / 2), below 1e-14 constrained
+    assert div_u > 1e-3 and div_c < 1e-11, (div_c, div_u)
+    assert err_c < 1.1 * err_u and err_u < 0.02, (err_c, err_u)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_one_step_in_an_impressed_uniform_field_matches_the_oracle(k):
+    N = 4
+    m = omesh.cube_mesh(N, k)
+    mesh = F.Mesh.cube(N, k)
+    dt = 10 * mesh.info()["dt_cfl"]
+    B0 = np.array([0.0, 0.02, 0.05])
+    run = F.Run(mesh, dt, F.FP64, pcg_rtol=1e-14)
+    b_imp = run.impress(np.broadcast_to(B0, (m.nt * 27, 3)).copy(), 3, constrained=True)
+    pos, vel = W.particles("thermal", 3000, 77 + k, vth=0.02)
+    w = W.plasma_weight(len(pos), dt, omega_dt=0.01)
+    run.load(pos, vel, QE, ME, w)
+    run.step()
+    orc = core.OracleRun(m, dt, particles_only=True)
+    orc.b = b_imp.copy()
+    orc.load(pos, vel, QE, ME, w)
+    orc.particle_step()
+    p, v, t = run.particles()
+    close(p, orc.pos, 1e-13)
+    close(v, orc.vel, 1e-12)
+    assert np.mean(t == orc.tet) > 0.999
+    # a uniform field lies in the face space: the projection reproduces it exactly
+    E, B = orc.gather(orc.pos, orc.tet)
+    close(B, np.broadcast_to(B0, B.shape), 1e-12)
+
+
+def test_impressed_field_travels_in_a_checkpoint(tmp_path):
+    N, k = 4, 2
+    mesh = F.Mesh.cube(N, k)
+    dt = 10 * mesh.info()["dt_cfl"]
+    n_pts = 6 * N ** 3 * 8
+    pts = mesh.impressed_points(2)
+    B = np.stack([0.01 + 0 * pts[:, 0], 0.03 * pts[:, 0], 0.02 + 0 * pts[:, 0]], axis=1)
+    pos, vel = W.particles("beam", 8000, 21, vth=0.01, drift=0.1)
+    w = W.plasma_weight(len(pos), dt)
+    a = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14)
+    a.impress(B, 2)
+    a.load(pos, vel, QE, ME, w)
+    a.step(3)
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.step(3)
+    b = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14)
+    b.restore(path)
+    b.step(3)
+    assert len(pts) == n_pts
+    for x, y in zip(a.fields() + a.particles(), b.fields() + b.particles()):
+        assert np.array_equal(x, y)

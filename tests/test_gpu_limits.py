@@ -117,3 +117,67 @@ def test_device_bytes_stay_within_the_footprint(N, k, precision, n):
     assert st["device_peak_bytes"] > 0.66 * mesh.footprint(n, precision)
     assert 0 < st["device_bytes"] <= st["device_peak_bytes"]
     run.close()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_absorbing_walls_match_the_oracle(k):
+    """FEMPIC_ABSORB: a beam into the z walls of the 5^3 cube, FP64, 15 steps.  Every step's deposit
+    DoF by DoF and the absorbed count against the oracle; then the surviving particles (the same
+    set), fields and the Gauss residual; absorbed particles read back with tet -1 and NaN state."""
+    N = 5
+    m = omesh.cube_mesh(N, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    pos, vel = W.particles("beam", 12000, 81 + k, vth=0.01, drift=0.12)
+    w = W.plasma_weight(len(pos), dt)
+    orc = core.OracleRun(m, dt, ops, absorb=True)
+    orc.load(pos, vel, QE, ME, w)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.FP64, pcg_rtol=1e-15, particle_bc=F.ABSORB)
+    run.load(pos, vel, QE, ME, w)
+    for n in range(15):
+        c0 = orc.counters.copy()
+        orc.step()
+        run.step()
+        close(run.deposit(), orc.last_dg * m.int1, 1e-12)
+        st = run.stats()
+        assert st["absorbed"] == orc.counters[2] - c0[2], n
+        assert st["reflections"] == 0 and st["n_particles"] == int((orc.tet >= 0).sum())
+    assert st["absorbed_total"] > 2000 and st["n_loaded"] == len(pos)
+    p, v, t = run.particles()
+    alive = orc.tet >= 0
+    assert np.array_equal(t < 0, ~alive)
+    assert np.all(np.isnan(p[~alive])) and np.all(np.isnan(v[~alive]))
+    close(p[alive], orc.pos[alive], 1e-13)
+    close(v[alive], orc.vel[alive], 1e-12)
+    e, b = run.fields()
+    close(e, orc.e, 1e-12)
+    close(b, orc.b, 1e-12)
+    rho, _ = run.rho()
+    close(rho, orc.rho() * m.int0, 1e-12)
+    RG, RC, RS = run.gauss()
+    assert RG < 1e-12 and RC < 1e-12, (RG, RC, RS)
+
+
+def test_absorbing_run_resumes_bitwise(tmp_path):
+    N, k = 5, 2
+    mesh = F.Mesh.cube(N, k)
+    dt = 10 * mesh.info()["dt_cfl"]
+    pos, vel = W.particles("beam", 20000, 13, vth=0.01, drift=0.1)
+    w = W.plasma_weight(len(pos), dt)
+    a = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14, particle_bc=F.ABSORB)
+    a.load(pos, vel, QE, ME, w)
+    a.step(5)
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.step(5)
+    b = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14, particle_bc=F.ABSORB)
+    b.restore(path)
+    assert b.stats()["n_loaded"] == len(pos) and b.stats()["n_particles"] < len(pos)
+    b.step(5)
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)
+    pa, va, ta = a.particles()
+    pb, vb, tb = b.particles()
+    assert np.array_equal(ta, tb)
+    ok = ta >= 0
+    assert np.array_equal(pa[ok], pb[ok]) and np.array_equal(va[ok], vb[ok])

@@ -15,12 +15,17 @@ QE, ME = -W.Q_E, W.M_E
 
 
 def _jobs():
-    """(N, order, kind, n, seed, steps, precision): small mixed set of shapes."""
+    """(N, order, kind, n, seed, steps, precision): eight jobs over both orders, both precisions,
+    beam and thermal particles and different mesh and particle sizes."""
     return [
         (4, 1, "thermal", 800, 11, 12, F.FP64),
         (6, 2, "beam", 3000, 12, 8, F.FP64),
         (5, 2, "thermal", 2000, 13, 10, F.MIXED),
         (4, 2, "beam", 1500, 14, 6, F.MIXED),
+        (7, 1, "beam", 5000, 15, 9, F.MIXED),
+        (3, 1, "thermal", 300, 16, 14, F.FP64),
+        (8, 2, "thermal", 8000, 17, 5, F.FP64),
+        (6, 1, "beam", 2500, 18, 11, F.MIXED),
     ]
 
 
@@ -42,7 +47,7 @@ def test_server_matches_standalone_runs():
         pos, vel = W.particles(kind, n, seed, vth=0.01, drift=0.1)
         w = W.plasma_weight(n, dt)
         specs.append((N, order, pos, vel, w, dt, steps, prec))
-    srv = F.Server(hbm_budget=8 << 30, max_slots=2)
+    srv = F.Server(hbm_budget=8 << 30, max_slots=3)
     tickets = [srv.submit(N, order, pos, vel, QE, ME, w, steps, dt, precision=prec)
                for (N, order, pos, vel, w, dt, steps, prec) in specs]
     results = {}
@@ -110,3 +115,28 @@ def test_server_isolates_a_failing_job():
         e, b, p, v, _ = _alone(N, o, pos, vel, w, dt, steps, prec)
         assert np.array_equal(r["e"], e) and np.array_equal(r["b"], b)
         assert np.array_equal(r["pos"], p) and np.array_equal(r["vel"], v)
+
+
+def test_graph_replay_equals_eager_launches(monkeypatch):
+    """The PCG batches replay a HIP graph captured once per run; with FEMPIC_GRAPHS=0 the same
+    kernels launch one by one.  Every step (each replays the graph many times, with the run's
+    own eager work and host reads between the replays) gives bit-identical fields, in both
+    precisions and both orders."""
+    for N, k, prec in ((5, 2, F.FP64), (5, 2, F.MIXED), (6, 1, F.MIXED)):
+        dt = 10.0 * F.Mesh.cube(N, k).info()["dt_cfl"]
+        pos, vel = W.particles("beam", 6000, 40 + N + k, vth=0.01, drift=0.1)
+        w = W.plasma_weight(len(pos), dt)
+        out = []
+        for graphs in ("1", "0"):
+            monkeypatch.setenv("FEMPIC_GRAPHS", graphs)
+            run = F.Run(F.Mesh.cube(N, k), dt, prec, pcg_rtol=1e-14)
+            run.load(pos, vel, QE, ME, w)
+            steps = []
+            for _ in range(6):
+                run.step()
+                steps.append(run.fields())
+                assert run.stats()["pcg_iters"] >= 16
+            out.append(steps)
+            run.close()
+        for (e1, b1), (e0, b0) in zip(*out):
+            assert np.array_equal(e1, e0) and np.array_equal(b1, b0)

@@ -70,7 +70,7 @@ def test_noalloc_gauss_equals_gauss_on_two_runs_the_second_smaller():
 
 
 def test_noalloc_gauss_refuses_a_mesh_beyond_the_scratch():
-    """The 48^3 cube at order 2 needs about 107 MB of scratch for the check; the library holds 64 MiB."""
+    """The 48^3 cube at order 2 needs about 140 MB of scratch for the check; the library holds 96 MiB."""
     run = _run(48, 2, 1000, 7, F.MIXED)
     out = np.zeros(3)
     code = F.lib().fempic_gauss_residual_noalloc(run.h, F._p(out))
