@@ -47,6 +47,10 @@ extern "C" {
 #define FEMPIC_MIXED 1 /* FP32 gather/push and FP32 inner solve; FP64 positions,
                           tracking, deposit, residuals and refinement */
 
+#define FEMPIC_PUSH_AB4 0   /* fourth-order Adams-Bashforth push, quartic path (Sec. III-B) */
+#define FEMPIC_PUSH_BORIS 1 /* Boris leapfrog, straight path (the push is de-linked from
+                               the current mapping, Sec. III-B); velocities are v^{n-1/2} */
+
 #define FEMPIC_REFLECT 0 /* particles reflect specularly at PEC walls */
 #define FEMPIC_ABSORB 1  /* a particle that reaches a wall deposits its current up to
                             the wall and leaves the run there */
@@ -137,6 +141,10 @@ typedef struct {
                             residuals (fempic_gauss_residual) after every step
                             whose count is a multiple of k, into
                             fempic_stats_t.gauss (one device wait each) */
+    int32_t pusher;      /* FEMPIC_PUSH_AB4 (0) or FEMPIC_PUSH_BORIS; with Boris the
+                            loaded velocity is taken as v^{-1/2}, the step moves
+                            along the straight path r^n + s dt v^{n+1/2} and deposits
+                            its exact path integral, and fempic_history_get is EINVAL */
 } fempic_params;
 
 int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out);
@@ -150,6 +158,17 @@ int32_t fempic_run_destroy(fempic_run run);
  * EINVAL for a non-finite position or velocity (nothing reaches the device). */
 int32_t fempic_particles_load(fempic_run run, const double *pos, const double *vel, int64_t n, double q, double m,
                               double w);
+
+/* Append n particles of the loaded species (pos, vel [n][3], ids after the
+ * existing ones), between steps: a beam source (Table III injects a few
+ * particles every step).  Each is located (EOUTSIDE if outside the mesh) and
+ * started like a loaded particle.  Their charge enters the run here rather than
+ * through a current, so it joins the Gauss check's reference rho~^0, as the
+ * charge present at load does; injected on a wall, where the interior W0
+ * functions vanish, it adds nothing there.  The buffers grow by half again when
+ * they are full; the next step sorts the particles again.  EINVAL before a
+ * load, for a non-finite position or velocity, or for a NULL array with n > 0. */
+int32_t fempic_particles_inject(fempic_run run, const double *pos, const double *vel, int64_t n);
 
 /* Advance n_steps PIC steps (Sec. III, PIC cycle; Sec. III-B) on the run's
  * stream.  Per step: particles in tet order (a sort after load; each step then

@@ -50,10 +50,11 @@ def lib():
         L = C.CDLL(path)
         vp, i64, f64 = C.c_void_p, C.c_int64, C.c_double
         L.oracle_step.restype = C.c_int
-        L.oracle_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, vp, C.c_int]
+        L.oracle_step.argtypes = [vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, vp, C.c_int,
+                                  C.c_int]
         L.oracle_step_chunked.restype = C.c_int
         L.oracle_step_chunked.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64, f64, vp, i64, vp,
-                                          C.c_int, vp, C.c_int]
+                                          C.c_int, vp, C.c_int, C.c_int]
         L.oracle_startup.restype = None
         L.oracle_startup.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, f64, f64, f64]
         L.oracle_gather.restype = None

@@ -113,12 +113,15 @@ class OracleRun:
     of the scheme for M dX/dt + S X = F (field_step_newmark)."""
 
     def __init__(self, m, dt, ops=None, particles_only=False, gamma=0.5, beta=0.25, three_level=False,
-                 absorb=False):
+                 absorb=False, pusher="ab4"):
         """particles_only: skip the field operators (particle steps with given fields).
         absorb: a particle that reaches a wall deposits its current up to the wall and leaves the
-        run (tet -1); otherwise walls reflect."""
+        run (tet -1); otherwise walls reflect.
+        pusher: "ab4" (the paper's fourth-order Adams-Bashforth push, quartic path) or "boris"
+        (Boris leapfrog, straight path; the stored velocity is then v^{n-1/2})."""
         self.m = m
         self.absorb = 1 if absorb else 0
+        self.pusher = {"ab4": 0, "boris": 1}[pusher]
         self.k = m.order
         self.dt = dt
         self.lu = None
@@ -156,6 +159,28 @@ class OracleRun:
                          q, mass, self.dt)
         self.rho0 = self.rho()
 
+    def inject(self, pos, vel):
+        """Append particles of the loaded species, started like loaded ones (the AB4 history from
+        the current fields).  Their charge enters here, not through a current, so it joins the
+        reference rho~^0 of the Gauss check, like the charge present at load."""
+        pos = np.array(pos, dtype=np.float64).reshape(-1, 3).copy()
+        vel = np.array(vel, dtype=np.float64).reshape(-1, 3).copy()
+        n = len(pos)
+        tet = omesh.locate_kuhn(self.m, pos).copy()
+        vh = np.zeros((n, 3, 3))
+        ah = np.zeros((n, 3, 3))
+        L = cloop.lib()
+        L.oracle_startup(self.cm.ref, cloop.ptr(self.e), cloop.ptr(self.b), n, cloop.ptr(pos), cloop.ptr(vel),
+                         cloop.ptr(vh), cloop.ptr(ah), cloop.ptr(tet), self.q, self.mass, self.dt)
+        rho_new = np.zeros(self.m.n0)
+        L.oracle_rho(self.cm.ref, n, cloop.ptr(pos), cloop.ptr(tet), self.q * self.w, cloop.ptr(rho_new))
+        self.pos = np.concatenate([self.pos, pos])
+        self.vel = np.concatenate([self.vel, vel])
+        self.vh = np.concatenate([self.vh, vh])
+        self.ah = np.concatenate([self.ah, ah])
+        self.tet = np.concatenate([self.tet, tet])
+        self.rho0 = self.rho0 + rho_new
+
     def particle_step(self, idx=None, threads=1):
         """Gather + push + track + deposit for all particles (or idx); returns dg (n1).
         threads > 1: the particles in that many contiguous chunks on as many threads, each
@@ -169,7 +194,7 @@ class OracleRun:
                                        cloop.ptr(self.vel), cloop.ptr(self.vh), cloop.ptr(self.ah),
                                        cloop.ptr(self.tet), self.q, self.mass, self.w, self.dt, cloop.ptr(dg),
                                        self.m.n1, cloop.ptr(self.counters), threads, cloop.ptr(work),
-                                       self.absorb)
+                                       self.absorb, self.pusher)
             if st != 0:
                 raise RuntimeError("oracle particle step failed with status %d" % st)
             return dg
@@ -180,7 +205,8 @@ class OracleRun:
             ip, ni = cloop.ptr(idx), len(idx)
         st = L.oracle_step(self.cm.ref, cloop.ptr(self.e), cloop.ptr(self.b), n, ip, ni, cloop.ptr(self.pos),
                            cloop.ptr(self.vel), cloop.ptr(self.vh), cloop.ptr(self.ah), cloop.ptr(self.tet),
-                           self.q, self.mass, self.w, self.dt, cloop.ptr(dg), cloop.ptr(self.counters), self.absorb)
+                           self.q, self.mass, self.w, self.dt, cloop.ptr(dg), cloop.ptr(self.counters), self.absorb,
+                           self.pusher)
         if st != 0:
             raise RuntimeError("oracle particle step failed with status %d" % st)
         return dg

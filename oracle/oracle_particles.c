@@ -24,6 +24,14 @@
  *      the whole AB4 history are mirrored at the end of the step; or, with the
  *      absorbing rule, the path ends there: its current is deposited up to the
  *      wall and the particle leaves the run (tet = -1, position at the wall).
+ *
+ * The push and the current mapping are independent (Sec. III-B: the particle
+ * integrator is de-linked from the field update); with pusher = 1 the step uses
+ * the Boris leapfrog instead: the stored velocity is v^{n-1/2}, the Boris
+ * rotation (half electric kick, rotation about B through the angle
+ * 2 atan(|q| |B| dt / 2m), half kick) gives v^{n+1/2}, and the path is the
+ * straight line r(s) = r^n + s dt v^{n+1/2}; tracking, deposit and walls are the
+ * same, and the AB4 histories are not used.
  */
 #include <math.h>
 #include <string.h>
@@ -217,6 +225,7 @@ typedef struct {
     int64_t *trace_t; /* optional: tet of every segment */
     double *trace_s;  /* optional: end parameter of every segment */
     int ntrace;
+    int pusher;     /* 0: AB4 quartic path; 1: Boris leapfrog, straight path */
 } DepCtx;
 
 static void path_eval(const double c[5][3], double s, double *r, double *dr)
@@ -324,6 +333,22 @@ static int64_t track_and_deposit(const OMesh *m, int64_t t0, double c[5][3], Dep
  * One time step of particle p: gather, AB4, path, track + deposit into ctx->dg,
  * then the new state.  Returns 0 or a negative status.
  */
+/* Boris: v^{n+1/2} from v^{n-1/2} with the fields E, B at r^n */
+static void boris(double qm, double dt, const double *E, const double *B, const double *v, double *out)
+{
+    double h = 0.5 * qm * dt, t[3], s[3], vm[3], vp[3], c[3];
+    for (int k = 0; k < 3; k++) {
+        t[k] = h * B[k];
+        vm[k] = v[k] + h * E[k];
+    }
+    double tt = dot3(t, t);
+    for (int k = 0; k < 3; k++) s[k] = 2.0 * t[k] / (1.0 + tt);
+    cross3(vm, t, c);
+    for (int k = 0; k < 3; k++) vp[k] = vm[k] + c[k];
+    cross3(vp, s, c);
+    for (int k = 0; k < 3; k++) out[k] = vm[k] + c[k] + h * E[k];
+}
+
 static int step_one(const OMesh *m, const double *e, const double *bv, int64_t p, double *pos, double *vel,
                     double *vh, double *ah, int64_t *tet, double q, double mass, double dt, DepCtx *ctx)
 {
@@ -331,6 +356,29 @@ static int step_one(const OMesh *m, const double *e, const double *bv, int64_t p
     double *r = &pos[3 * p], *v = &vel[3 * p], *VH = &vh[9 * p], *AH = &ah[9 * p];
     double E[3], B[3], vxB[3], a[3];
     gather(m, tet[p], r, e, bv, E, B);
+    if (ctx->pusher == 1) {
+        double vn[3], c[5][3] = {{0}};
+        boris(q / mass, dt, E, B, v, vn);
+        for (int k = 0; k < 3; k++) {
+            c[0][k] = r[k];
+            c[1][k] = dt * vn[k];
+        }
+        int nrefl;
+        int64_t refl_t[ORACLE_MAX_CROSS + 1];
+        int refl_f[ORACLE_MAX_CROSS + 1];
+        int64_t tn = track_and_deposit(m, tet[p], c, ctx, &nrefl, refl_t, refl_f);
+        if (tn == ORACLE_ABSORBED) {
+            path_eval(c, ctx->s_wall, r, NULL);
+            tet[p] = -1;
+            return 0;
+        }
+        if (tn < 0) return (int)tn;
+        path_eval(c, 1.0, r, NULL);
+        for (int i = 0; i < nrefl; i++) reflect(m, refl_t[i], refl_f[i], vn, 0);
+        memcpy(v, vn, 3 * sizeof(double));
+        tet[p] = tn;
+        return 0;
+    }
     cross3(v, B, vxB);
     for (int k = 0; k < 3; k++) a[k] = q / mass * (E[k] + vxB[k]);
     /* path from v^n, v^{n-1}, v^{n-2}, v^{n-3} */
@@ -385,9 +433,9 @@ static int step_one(const OMesh *m, const double *e, const double *bv, int64_t p
  */
 int oracle_step(const OMesh *m, const double *e, const double *bv, int64_t n_p, const int64_t *idx, int64_t n_idx,
                 double *pos, double *vel, double *vh, double *ah, int64_t *tet, double q, double mass, double w,
-                double dt, double *dg, int64_t *counters, int absorb)
+                double dt, double *dg, int64_t *counters, int absorb, int pusher)
 {
-    DepCtx ctx = {q * w, dg, 0, 0, absorb, 0, 0.0, NULL, NULL, 0};
+    DepCtx ctx = {q * w, dg, 0, 0, absorb, 0, 0.0, NULL, NULL, 0, pusher};
     int64_t n = idx ? n_idx : n_p;
     for (int64_t ii = 0; ii < n; ii++) {
         int st = step_one(m, e, bv, idx ? idx[ii] : ii, pos, vel, vh, ah, tet, q, mass, dt, &ctx);
@@ -411,7 +459,7 @@ int oracle_step(const OMesh *m, const double *e, const double *bv, int64_t n_p, 
  */
 int oracle_step_chunked(const OMesh *m, const double *e, const double *bv, int64_t n_p, double *pos, double *vel,
                         double *vh, double *ah, int64_t *tet, double q, double mass, double w, double dt, double *dg,
-                        int64_t n_dg, int64_t *counters, int n_threads, double *work, int absorb)
+                        int64_t n_dg, int64_t *counters, int n_threads, double *work, int absorb, int pusher)
 {
     int status[256];
     int64_t ncr[256], nrf[256], nab[256];
@@ -422,7 +470,7 @@ int oracle_step_chunked(const OMesh *m, const double *e, const double *bv, int64
     for (int c = 0; c < n_threads; c++) {
         double *buf = &work[(int64_t)c * n_dg];
         memset(buf, 0, (size_t)n_dg * sizeof(double));
-        DepCtx ctx = {q * w, buf, 0, 0, absorb, 0, 0.0, NULL, NULL, 0};
+        DepCtx ctx = {q * w, buf, 0, 0, absorb, 0, 0.0, NULL, NULL, 0, pusher};
         int64_t lo = n_p * c / n_threads, hi = n_p * (c + 1) / n_threads;
         status[c] = 0;
         for (int64_t p = lo; p < hi && !status[c]; p++)

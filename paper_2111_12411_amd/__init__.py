@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfempic.so")
 
 FP64, MIXED = 0, 1
 REFLECT, ABSORB = 0, 1
+PUSH_AB4, PUSH_BORIS = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "EOUTSIDE", -5: "ECROSS", -6: "ESOLVE",
           -7: "EDEVICE", -8: "EAGAIN", -9: "EBUSY"}
 
@@ -34,7 +35,7 @@ class MeshInfo(C.Structure):
 class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dt", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32), ("particle_bc", C.c_int32),
-                ("spill_slots", C.c_int32), ("gauss_every", C.c_int32)]
+                ("spill_slots", C.c_int32), ("gauss_every", C.c_int32), ("pusher", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -82,6 +83,7 @@ SYMBOLS = {
     "fempic_fields_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_deposit_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_rho_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "fempic_particles_inject": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_particles_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_history_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_run_save": (C.c_int32, [C.c_void_p, C.c_char_p]),
@@ -173,8 +175,8 @@ class Mesh:
 
 
 def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, gauss_every=0, gamma=0.5, beta=0.25,
-           particle_bc=0):
-    return Params(precision, dt, gamma, beta, pcg_rtol, pcg_maxit, particle_bc, 0, gauss_every)
+           particle_bc=0, pusher=0):
+    return Params(precision, dt, gamma, beta, pcg_rtol, pcg_maxit, particle_bc, 0, gauss_every, pusher)
 
 
 def footprint(order, n_tet, n_particles, precision=FP64):
@@ -231,11 +233,11 @@ class Run:
     """One simulation on the current HIP device."""
 
     def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None, gauss_every=0,
-                 gamma=0.5, beta=0.25, particle_bc=0):
+                 gamma=0.5, beta=0.25, particle_bc=0, pusher=PUSH_AB4):
         self.mesh = mesh
         self.info = mesh.info()
         self.h = C.c_void_p()
-        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every, gamma, beta, particle_bc)
+        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every, gamma, beta, particle_bc, pusher)
         _check(lib().fempic_run_create(mesh.h, C.byref(p), stream, C.byref(self.h)))
         self.n = 0
 
@@ -284,6 +286,13 @@ class Run:
         r0 = np.zeros(self.info["n0"])
         _check(lib().fempic_rho_get(self.h, _p(r), _p(r0), len(r)))
         return r, r0
+
+    def inject(self, pos, vel):
+        """Append particles of the loaded species (fempic_particles_inject)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        _check(lib().fempic_particles_inject(self.h, _p(pos), _p(vel), len(pos)))
+        self.n += len(pos)
 
     def impress(self, B, n1d, constrained=True):
         """Project B sampled at Mesh.impressed_points(n1d) and keep it as the run's impressed

@@ -48,6 +48,7 @@ struct StepParams {
     double dt;
     int32_t tpw;    // tets per workgroup in the particle kernel
     int32_t absorb; // 1: a particle that reaches a wall is removed there (else it reflects)
+    int32_t boris;  // 1: Boris leapfrog with a straight path (no AB4 histories)
 };
 
 // step counters (device int64 each): crossings, reflections, spilled segments,
@@ -145,7 +146,8 @@ struct ParticleArgs {
     unsigned long long *cntb; // [CONT_BLOCKS][NCNT] per-block counters of the continuation kernel
     unsigned long long *perr; // [1] particle-order error flag (launch_place)
 };
-hipError_t launch_particle(int order, bool mixed, const ParticleArgs *dargs, int32_t nt, int32_t tpw, hipStream_t s);
+hipError_t launch_particle(int order, bool mixed, bool boris, const ParticleArgs *dargs, int32_t nt, int32_t tpw,
+                           hipStream_t s);
 // fills cq.idx and *cq.count from cq.flag; tmp: device scratch of at least
 // 2 (np / 4096 + 1) + scan_tmp_entries(np / 4096 + 1) entries
 hipError_t launch_queue_index(const ContQueue &cq, int64_t np, uint32_t *tmp, hipStream_t s);

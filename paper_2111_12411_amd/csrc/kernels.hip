@@ -636,7 +636,7 @@ __device__ inline GPool gview(const SpillPool &p)
 template <typename R, typename GPtr>
 __device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &entry, double (&dp)[4][3],
                                   double (&lam)[4], const GParticles<R> &out, int64_t i, unsigned long long &nrf,
-                                  bool absorb)
+                                  bool absorb, bool hist)
 {
     const int nx = m.nbr[(int64_t)t * 4 + f];
     if (nx >= 0) {
@@ -676,7 +676,7 @@ __device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &en
         out.v[2 * out.cap + i] = x2 - sd * gz;
     }
 #pragma unroll 1
-    for (int h = 0; h < 6; h++) {
+    for (int h = 0; h < (hist ? 6 : 0); h++) {  // no histories with the Boris push
         gptr<R> hp = (h < 3 ? out.vh : out.ah) + (int64_t)(3 * (h % 3)) * out.cap;
         const double x0 = hp[i], x1 = hp[out.cap + i], x2 = hp[2 * out.cap + i];
         const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
@@ -774,7 +774,10 @@ __device__ inline unsigned long long lane_range(int lo, int hi)
 // segment, which lies in the home tet; its current moments are summed per tet
 // in LDS in a fixed order.  A particle whose path leaves the home tet is queued
 // for k_continue.
-template <int K, typename R>
+// BORIS: the Boris leapfrog (the stored velocity is v^{n-1/2}) with a straight
+// path, in place of the AB4 push and its quartic path; no histories are read or
+// written.
+template <int K, typename R, bool BORIS = false>
 __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__restrict__ A)
 {
     const GMesh m = gview(A->m);
@@ -862,10 +865,12 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
             R vh[9], ah[9];
 #pragma unroll
             for (int c = 0; c < 3; c++) vd[c] = in.v[c * in.cap + slot];
+            if constexpr (!BORIS) {
 #pragma unroll
-            for (int c = 0; c < 9; c++) {
-                vh[c] = in.vh[c * in.cap + slot];
-                ah[c] = in.ah[c * in.cap + slot];
+                for (int c = 0; c < 9; c++) {
+                    vh[c] = in.vh[c * in.cap + slot];
+                    ah[c] = in.ah[c * in.cap + slot];
+                }
             }
             const R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
             // fields at r^n (home tet, LDS)
@@ -881,39 +886,69 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
             for (int q = 0; q < 6; q++)
 #pragma unroll
                 for (int c = 0; c < 3; c++) B[c] += cB[q] * s_X[lt][3 * q + c];
-            // Lorentz acceleration (precision R); AB4 velocity increment in R added to the FP64 velocity
-            R vxB[3], a[3];
             double dv[3], vn[3];
-            cross3(v, B, vxB);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                a[c] = qmR * (E[c] + vxB[c]);
-                dv[c] = (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
-                vn[c] = vd[c] + dv[c];
-            }
-            // quartic path r(s) = r^n + sum_{d=1..4} dp_d s^d (FP64 in both modes);
-            // the history holds v^{n-j} - v^n, so in R it is rounded relative to
-            // the change of velocity, not to the velocity
             double dp[4][3];
+            if constexpr (!BORIS) {
+                // Lorentz acceleration (precision R); AB4 velocity increment in R added to the FP64 velocity
+                R vxB[3], a[3];
+                cross3(v, B, vxB);
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const double v0 = vd[c], v1 = vd[c] + (double)vh[c], v2 = vd[c] + (double)vh[3 + c],
-                             v3 = vd[c] + (double)vh[6 + c];
+                for (int c = 0; c < 3; c++) {
+                    a[c] = qmR * (E[c] + vxB[c]);
+                    dv[c] = (double)(dtR / R(24) * (R(55) * a[c] - R(59) * ah[c] + R(37) * ah[3 + c] - R(9) * ah[6 + c]));
+                    vn[c] = vd[c] + dv[c];
+                }
+                // quartic path r(s) = r^n + sum_{d=1..4} dp_d s^d (FP64 in both modes);
+                // the history holds v^{n-j} - v^n, so in R it is rounded relative to
+                // the change of velocity, not to the velocity
 #pragma unroll
-                for (int d = 1; d < 5; d++)
-                    dp[d - 1][c] =
-                        sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
-            }
-            // new velocity and shifted histories, written now (wall reflections patch them)
+                for (int c = 0; c < 3; c++) {
+                    const double v0 = vd[c], v1 = vd[c] + (double)vh[c], v2 = vd[c] + (double)vh[3 + c],
+                                 v3 = vd[c] + (double)vh[6 + c];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                out.v[c * out.cap + i] = vn[c];
-                out.vh[c * out.cap + i] = (R)(-dv[c]);
-                out.vh[(3 + c) * out.cap + i] = (R)((double)vh[c] - dv[c]);
-                out.vh[(6 + c) * out.cap + i] = (R)((double)vh[3 + c] - dv[c]);
-                out.ah[c * out.cap + i] = a[c];
-                out.ah[(3 + c) * out.cap + i] = ah[c];
-                out.ah[(6 + c) * out.cap + i] = ah[3 + c];
+                    for (int d = 1; d < 5; d++)
+                        dp[d - 1][c] =
+                            sp.dt * (LCOEF[0][d] * v0 + LCOEF[1][d] * v1 + LCOEF[2][d] * v2 + LCOEF[3][d] * v3);
+                }
+                // new velocity and shifted histories, written now (wall reflections patch them)
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    out.v[c * out.cap + i] = vn[c];
+                    out.vh[c * out.cap + i] = (R)(-dv[c]);
+                    out.vh[(3 + c) * out.cap + i] = (R)((double)vh[c] - dv[c]);
+                    out.vh[(6 + c) * out.cap + i] = (R)((double)vh[3 + c] - dv[c]);
+                    out.ah[c * out.cap + i] = a[c];
+                    out.ah[(3 + c) * out.cap + i] = ah[c];
+                    out.ah[(6 + c) * out.cap + i] = ah[3 + c];
+                }
+            } else {
+                // Boris: half kick, rotation about B through 2 atan(q |B| dt / 2m), half
+                // kick (precision R); the change of velocity added to the FP64 velocity
+                const R h = R(0.5) * qmR * dtR;
+                R t[3], sv[3], vm[3], vp[3], cr[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    t[c] = h * B[c];
+                    vm[c] = v[c] + h * E[c];
+                }
+                const R f = R(2) / (R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+#pragma unroll
+                for (int c = 0; c < 3; c++) sv[c] = f * t[c];
+                cross3(vm, t, cr);
+#pragma unroll
+                for (int c = 0; c < 3; c++) vp[c] = vm[c] + cr[c];
+                cross3(vp, sv, cr);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    // v^{n+1/2} - v^{n-1/2} = 2 h E + vp x s: formed as the change itself,
+                    // so that in R it is rounded relative to the change, not to v
+                    dv[c] = (double)(R(2) * h * E[c] + cr[c]);
+                    vn[c] = vd[c] + dv[c];
+                    // straight path r(s) = r^n + s dt v^{n+1/2}
+                    dp[0][c] = sp.dt * vn[c];
+                    dp[1][c] = dp[2][c] = dp[3][c] = 0.0;
+                    out.v[c * out.cap + i] = vn[c];
+                }
             }
             out.id[i] = in.id[slot];
             // first segment: in the home tet from s = 0.  A path whose exit
@@ -1048,7 +1083,8 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
             ncross++;
             ncr++;
             const unsigned long long nrf0 = nrf;
-            gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, dp, lam, out, i, nrf, absorb);
+            gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, dp, lam, out, i, nrf, absorb,
+                                 sp.boris == 0);
 #pragma unroll
             for (int c = 0; c < 3; c++) rec->lam[c] = lam[c + 1];
             if (nrf != nrf0) {
@@ -1101,7 +1137,7 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
 #pragma unroll
                         for (int c = 0; c < 3; c++) dq[d][c] = rec->dp[3 * d + c];
                     const unsigned long long nrf0 = nrf;
-                    gone = cross_face<R>(m, G, f_exit, t, entry, dq, le, out, i, nrf, absorb);
+                    gone = cross_face<R>(m, G, f_exit, t, entry, dq, le, out, i, nrf, absorb, sp.boris == 0);
 #pragma unroll
                     for (int c = 0; c < 3; c++) rec->lam[c] = le[c + 1];
                     if (nrf != nrf0) {  // a wall reflection changed the path
@@ -2109,15 +2145,20 @@ hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *o
     return hipGetLastError();
 }
 
-hipError_t launch_particle(int order, bool mixed, const ParticleArgs *A, int32_t nt, int32_t tpw, hipStream_t s)
+hipError_t launch_particle(int order, bool mixed, bool boris, const ParticleArgs *A, int32_t nt, int32_t tpw,
+                           hipStream_t s)
 {
     const unsigned grid = (unsigned)((nt + tpw - 1) / tpw);
-    if (order == 1) {
-        if (mixed) hipLaunchKernelGGL((k_particle<1, float>), dim3(grid), dim3(PBLK), 0, s, A);
-        else hipLaunchKernelGGL((k_particle<1, double>), dim3(grid), dim3(PBLK), 0, s, A);
-    } else {
-        if (mixed) hipLaunchKernelGGL((k_particle<2, float>), dim3(grid), dim3(PBLK), 0, s, A);
-        else hipLaunchKernelGGL((k_particle<2, double>), dim3(grid), dim3(PBLK), 0, s, A);
+    const int v = (order == 1 ? 0 : 4) + (mixed ? 0 : 2) + (boris ? 1 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_particle<1, float, false>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 1: hipLaunchKernelGGL((k_particle<1, float, true>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 2: hipLaunchKernelGGL((k_particle<1, double, false>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 3: hipLaunchKernelGGL((k_particle<1, double, true>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 4: hipLaunchKernelGGL((k_particle<2, float, false>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 5: hipLaunchKernelGGL((k_particle<2, float, true>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    case 6: hipLaunchKernelGGL((k_particle<2, double, false>), dim3(grid), dim3(PBLK), 0, s, A); break;
+    default: hipLaunchKernelGGL((k_particle<2, double, true>), dim3(grid), dim3(PBLK), 0, s, A); break;
     }
     return hipGetLastError();
 }

@@ -407,11 +407,11 @@ size_t Run::particle_bytes(int64_t n) const
     return (size_t)n * (6 * 8 + 18 * rs + 8);
 }
 
-void Run::alloc_particles(int64_t n)
+void Run::alloc_particles(int64_t n, int64_t cap_want)
 {
     np = n;
     np_loaded = n;
-    const int64_t cap = std::max<int64_t>(n, 1);
+    const int64_t cap = std::max<int64_t>({n, cap_want, 1});
     const size_t rs = mixed ? 4 : 8;
     for (int k = 0; k < 2; k++) {
         PBufs &B = pb[k];
@@ -577,9 +577,17 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     }
     // the positions become barycentric coordinates in the located tets
     HIPCHECK(launch_to_bary(dm, n, B.d.cap, (double *)B.lam.p, (const int32_t *)B.tet.p, stream));
-    // AB4 start-up from the current fields
-    HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
-                            (const float *)d_e32.p, (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
+    if (prm.pusher == FEMPIC_PUSH_BORIS) {
+        // the Boris push keeps no history: zero in both buffer sets (checkpoints copy it)
+        for (PBufs *P : {&pb[0], &pb[1]}) {
+            HIPCHECK(hipMemsetAsync(P->vh.p, 0, P->vh.bytes, stream));
+            HIPCHECK(hipMemsetAsync(P->ah.p, 0, P->ah.bytes, stream));
+        }
+    } else {
+        // AB4 start-up from the current fields
+        HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
+                                (const float *)d_e32.p, (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
+    }
     // store the particles in tet order, so the first step reads them like every later one
     {
         const uint32_t *perm = sort_current();
@@ -599,6 +607,118 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     for (double &g : gauss_last) g = 0.0;
     sticky = 0;
     loaded = true;
+}
+
+// Particle injection: the current state is gathered into the next step's order
+// (tet-sorted rows [0, np)), grown into larger buffers when it must be, and the
+// new particles are appended after it, located, given barycentric coordinates
+// and started like loaded ones; the next step sorts the whole set.  Charge
+// enters the run here, not through the deposit, so the Gauss check's reference
+// rho~^0 takes the new particles' nodal charge (like that of the particles
+// present at load): the check then measures the current of every particle since
+// it appeared.
+void Run::inject(const double *pos, const double *vel, int64_t n)
+{
+    sync();
+    AccountScope charge(&acct);
+    if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
+    if (n < 0 || (n > 0 && (!pos || !vel))) throw Error(FEMPIC_EINVAL, "bad particle arrays");
+    if (np_loaded + n >= ((int64_t)1 << 31) / 2) throw Error(FEMPIC_EINVAL, "too many particles");
+    for (int64_t k = 0; k < 3 * n; k++)
+        if (!std::isfinite(pos[k]) || !std::isfinite(vel[k]))
+            throw Error(FEMPIC_EINVAL, "particle " + std::to_string(k / 3) + " has a non-finite position or velocity");
+    if (n == 0) return;
+    const int64_t N0i = std::max<int64_t>(m.N0_int, 1);
+    DevBuf rho_a, rho_b;
+    rho_a.alloc(N0i * 8);
+    rho_b.alloc(N0i * 8);
+    compute_rho((double *)rho_a.p);
+    // the new particles, located on the host side of the upload
+    std::vector<double> xs(3 * n), vs(3 * n);
+    for (int64_t i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+            xs[c * n + i] = pos[3 * i + c];
+            vs[c * n + i] = vel[3 * i + c];
+        }
+    gather_current();
+    cur = 1 - cur;  // the gathered, tet-sorted rows are now the state
+    const int64_t np0 = np, np1 = np0 + n, id0 = np_loaded;
+    const size_t rs = mixed ? 4 : 8;
+    if (np1 > pb[cur].d.cap) {
+        // grow by half again, keeping the gathered rows
+        PBufs old = std::move(pb[cur]);
+        const int64_t oc = old.d.cap;
+        const int64_t nl = np_loaded;
+        alloc_particles(np0, np1 + np1 / 2);
+        np_loaded = nl;
+        const int64_t nc = pb[0].d.cap;
+        auto copy_cols = [&](DevBuf &dst, const DevBuf &src, int cols, size_t es) {
+            for (int c = 0; c < cols; c++)
+                if (np0)
+                    HIPCHECK(hipMemcpyAsync((char *)dst.p + (size_t)c * nc * es, (const char *)src.p + (size_t)c * oc * es,
+                                            (size_t)np0 * es, hipMemcpyDeviceToDevice, stream));
+        };
+        PBufs &B = pb[0];
+        copy_cols(B.lam, old.lam, 3, 8);
+        copy_cols(B.v, old.v, 3, 8);
+        copy_cols(B.vh, old.vh, 9, rs);
+        copy_cols(B.ah, old.ah, 9, rs);
+        copy_cols(B.tet, old.tet, 1, 4);
+        copy_cols(B.id, old.id, 1, 4);
+        HIPCHECK(hipStreamSynchronize(stream));  // old is freed at the end of this block
+        cur = 0;
+        if (prm.pusher == FEMPIC_PUSH_BORIS)
+            for (PBufs *P : {&pb[0], &pb[1]}) {
+                HIPCHECK(hipMemsetAsync(P->vh.p, 0, P->vh.bytes, stream));
+                HIPCHECK(hipMemsetAsync(P->ah.p, 0, P->ah.bytes, stream));
+            }
+    }
+    PBufs &B = pb[cur];
+    const int64_t cap = B.d.cap;
+    for (int c = 0; c < 3; c++) {
+        HIPCHECK(hipMemcpyAsync((double *)B.lam.p + c * cap + np0, &xs[c * n], n * 8, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync((double *)B.v.p + c * cap + np0, &vs[c * n], n * 8, hipMemcpyHostToDevice, stream));
+    }
+    std::vector<int32_t> ids(n);
+    for (int64_t i = 0; i < n; i++) ids[i] = (int32_t)(id0 + i);
+    HIPCHECK(hipMemcpyAsync((int32_t *)B.id.p + np0, ids.data(), n * 4, hipMemcpyHostToDevice, stream));
+    double *xn = (double *)B.lam.p + np0;
+    int32_t *tn = (int32_t *)B.tet.p + np0;
+    if (m.is_cube) {
+        HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
+        HIPCHECK(launch_locate_cube(dm, n, cap, xn, tn, p_small, stream));
+        int32_t err = 0;
+        HIPCHECK(hipMemcpyAsync(&err, p_small, 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        if (err & ERR_OUTSIDE) throw Error(FEMPIC_EOUTSIDE, "an injected particle lies outside the mesh");
+    } else {
+        std::vector<int32_t> tets(n);
+        locate_host(pos, n, tets.data());
+        HIPCHECK(hipMemcpyAsync(tn, tets.data(), n * 4, hipMemcpyHostToDevice, stream));
+    }
+    HIPCHECK(launch_to_bary(dm, n, cap, xn, tn, stream));
+    if (prm.pusher != FEMPIC_PUSH_BORIS) {
+        DevParticles v = B.d;
+        v.lam += np0;
+        v.v = (double *)v.v + np0;
+        v.vh = (char *)v.vh + np0 * rs;
+        v.ah = (char *)v.ah + np0 * rs;
+        v.tet += np0;
+        v.id += np0;
+        HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
+                                (const float *)d_e32.p, (const float *)d_b32.p, v, n, q / mass, prm.dt, stream));
+    }
+    np = np1;
+    np_loaded = id0 + n;
+    perm_valid = false;
+    counts_known = false;
+    // rho~^0 += the new particles' charge (rho~ after minus rho~ before)
+    compute_rho((double *)rho_b.p);
+    HIPCHECK(axpby(m.N0_int, 1.0, (const double *)rho_b.p, -1.0, (const double *)rho_a.p, (double *)rho_b.p,
+                   stream));
+    HIPCHECK(axpby(m.N0_int, 1.0, (const double *)d_rho0.p, 1.0, (const double *)rho_b.p, (double *)d_rho0.p,
+                   stream));
+    HIPCHECK(hipStreamSynchronize(stream));
 }
 
 // uniform-bin point location for meshes that are not Kuhn cubes (host side, at load)
@@ -678,7 +798,8 @@ void Run::particle_phase()
     AccountScope charge(&acct);  // the spill pool may grow
     HIPCHECK(hipEventRecord(ev_a, stream));
     const uint32_t *perm = sort_current();
-    StepParams sp{q / mass, q * w, prm.dt, tpw(), prm.particle_bc == FEMPIC_ABSORB ? 1 : 0};
+    StepParams sp{q / mass, q * w, prm.dt, tpw(), prm.particle_bc == FEMPIC_ABSORB ? 1 : 0,
+                  prm.pusher == FEMPIC_PUSH_BORIS ? 1 : 0};
     // The queue and spill stages run on counts that stay on the device: their
     // launches are sized by bounds from the previous step's counts (the largest
     // possible before the first), and the host reads the counts once, at the end
@@ -712,7 +833,8 @@ void Run::particle_phase()
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipEventRecord(ev_b, stream));
-        HIPCHECK(launch_particle(order, mixed, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw, stream));
+        HIPCHECK(launch_particle(order, mixed, sp.boris != 0, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw,
+                                 stream));
         HIPCHECK(hipEventRecord(ev_c1, stream));
         // compact the queue written by k_particle, then continue the queued paths
         HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
@@ -1270,6 +1392,7 @@ void Run::refresh_gather_b()
 {
     const double *b = (const double *)d_b.p;
     if (has_imp) {
+        if (!d_bimp.p || !d_bg.p) throw Error(FEMPIC_EINVAL, "impressed field without its buffers");
         HIPCHECK(axpby(m.N2, 1.0, b, 1.0, (const double *)d_bimp.p, (double *)d_bg.p, stream));
         b = (const double *)d_bg.p;
     }
@@ -1379,7 +1502,7 @@ void Run::impressed_set(const double *B, int64_t n, int n1d, bool constrained, d
                                                            std::to_string(rel));
         HIPCHECK(spmv(Ka.desc, (const double *)a.p, bi, 1.0, 0.0, nullptr, stream));
     }
-    if (!d_bg.p && !mixed) d_bg.alloc(std::max<int64_t>(N2, 1) * 8);
+    if (!d_bg.p) d_bg.alloc(std::max<int64_t>(N2, 1) * 8);
     has_imp = true;
     refresh_gather_b();
     if (b_out) HIPCHECK(hipMemcpyAsync(b_out, bi, N2 * 8, hipMemcpyDeviceToHost, stream));
@@ -1479,7 +1602,7 @@ struct CkptHeader {
     int32_t particle_bc;
     int64_t np_loaded;   // particles at load (ids are below it; absorbed ones are gone)
     int32_t has_imp;     // an impressed field follows the payload's fields
-    int32_t reserved;
+    int32_t pusher;      // FEMPIC_PUSH_AB4 or FEMPIC_PUSH_BORIS
 };
 
 // 64-bit FNV-1a over the payload taken as a stream of 8-byte words (a last
@@ -1581,6 +1704,7 @@ void Run::save(const char *path)
     h.beta = prm.beta;
     h.have_prev = three_level && have_prev ? 1 : 0;
     h.particle_bc = prm.particle_bc;
+    h.pusher = prm.pusher;
     h.np_loaded = np_loaded;
     h.has_imp = has_imp ? 1 : 0;
     CkptFile F(path, "wb");
@@ -1643,6 +1767,7 @@ void Run::restore(const char *path)
         h.np_loaded >= ((int64_t)1 << 31) / 2)
         throw Error(FEMPIC_EINVAL, "checkpoint header is corrupt");
     if (h.particle_bc != prm.particle_bc) throw Error(FEMPIC_EINVAL, "checkpoint particle wall condition differs");
+    if (h.pusher != prm.pusher) throw Error(FEMPIC_EINVAL, "checkpoint pusher differs");
     if (!(h.mass > 0) || !std::isfinite(h.q) || !std::isfinite(h.w))
         throw Error(FEMPIC_EINVAL, "checkpoint species is corrupt");
     const int64_t n = h.np;
@@ -1739,6 +1864,8 @@ void Run::restore(const char *path)
     for (int c = 0; c < 9; c++) get((char *)B.ah.p + c * cap * rs, &ah[c * n * rs], n * rs);
     get(B.tet.p, tet.data(), n * 4);
     get(B.id.p, id.data(), n * 4);
+    if (prm.pusher == FEMPIC_PUSH_BORIS)  // no history: the other buffer set's stays zero too
+        for (DevBuf *h : {&pb[1].vh, &pb[1].ah}) HIPCHECK(hipMemsetAsync(h->p, 0, h->bytes, stream));
     get(d_e.p, e.data(), e.size() * 8);
     get(d_b.p, b.data(), b.size() * 8);
     get(d_g.p, g.data(), g.size() * 8);
@@ -1756,7 +1883,7 @@ void Run::restore(const char *path)
     has_imp = h.has_imp != 0;
     if (has_imp) {
         if (!d_bimp.p) d_bimp.alloc(std::max<int64_t>(m.N2, 1) * 8);
-        if (!mixed && !d_bg.p) d_bg.alloc(std::max<int64_t>(m.N2, 1) * 8);
+        if (!d_bg.p) d_bg.alloc(std::max<int64_t>(m.N2, 1) * 8);
         get(d_bimp.p, bim.data(), bim.size() * 8);
     }
     np_loaded = h.np_loaded;
@@ -1775,6 +1902,7 @@ void Run::restore(const char *path)
 void Run::history_get(double *vh, double *ah, int64_t n)
 {
     sync();
+    if (prm.pusher == FEMPIC_PUSH_BORIS) throw Error(FEMPIC_EINVAL, "the Boris push keeps no AB4 history");
     if (n < np_loaded) throw Error(FEMPIC_EINVAL, "buffer too short");
     const double nan = std::numeric_limits<double>::quiet_NaN();
     for (int64_t k = 0; k < 9 * np_loaded; k++) {
@@ -1884,6 +2012,7 @@ void check_params(const fempic_params &p)
     if (p.particle_bc != FEMPIC_REFLECT && p.particle_bc != FEMPIC_ABSORB)
         throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
     if (p.gauss_every < 0) throw Error(FEMPIC_EINVAL, "gauss_every must be >= 0");
+    if (p.pusher != FEMPIC_PUSH_AB4 && p.pusher != FEMPIC_PUSH_BORIS) throw Error(FEMPIC_EINVAL, "unknown pusher");
 }
 
 }  // namespace fempic
@@ -2097,6 +2226,14 @@ int32_t fempic_impressed_set(fempic_run run, const double *B, int64_t n, int32_t
     API_BEGIN
     if (!run) throw Error(FEMPIC_EINVAL, "null run");
     run->r->impressed_set(B, n, n1d, constrained != 0, b_out, nb);
+    API_END
+}
+
+int32_t fempic_particles_inject(fempic_run run, const double *pos, const double *vel, int64_t n)
+{
+    API_BEGIN
+    if (!run) throw Error(FEMPIC_EINVAL, "null run");
+    run->r->inject(pos, vel, n);
     API_END
 }
 

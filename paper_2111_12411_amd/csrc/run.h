@@ -76,6 +76,9 @@ class Run {
     Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream_t s, size_t byte_limit = 0);
     ~Run();
     void load(const double *pos, const double *vel, int64_t n, double q, double m, double w);
+    // append n particles of the loaded species (ids after the existing ones),
+    // started like loaded ones; their charge joins the Gauss check's reference
+    void inject(const double *pos, const double *vel, int64_t n);
     void step(int n_steps);
     void sync();
     void gauss(double out[3]);
@@ -125,7 +128,7 @@ class Run {
     void upload_csr(DevCSRBuf &d, const CSR &A, bool want32);
     void zero(DevBuf &b);
     size_t particle_bytes(int64_t n) const;
-    void alloc_particles(int64_t n);
+    void alloc_particles(int64_t n, int64_t cap = 0);
     void alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold);
     void alloc_pool(int64_t cap);
     DevParticles P(int k) const;
@@ -182,8 +185,8 @@ class Run {
     // solver's accumulated solution, *nu u; the three-level scheme's previous
     // increment e^n - e^{n-1} as hi + lo
     DevBuf v_rhs_lo, v_x_lo, v_xs, v_nu, d_dprev, d_dprev_lo;
-    // impressed field (face coefficients, FP64) and, in FP64 runs that have one,
-    // b + it for the gather
+    // impressed field (face coefficients, FP64) and b + it, which the gather reads
+    // (FP64 runs) or which is cast to FP32 for it (mixed runs)
     bool has_imp = false;
     DevBuf d_bimp, d_bg;
     DevBuf f_x, f_r, f_z, f_p, f_q;

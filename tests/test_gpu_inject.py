@@ -1,0 +1,82 @@
+"""GPU parity of particle injection (the beam source of Table III) through the C
+ABI: a beam injected on the wall z = 0 every step into a run with absorbing
+walls, against the oracle doing the same: the deposit of every step DoF by
+DoF, the absorbed counts, the particles in load-and-injection order, fields and
+Gauss residuals.  The particle buffers start at the loaded count, so the first
+injection grows them.  A mixed-precision run with injections resumes bit for
+bit from a checkpoint."""
+import numpy as np
+import pytest
+
+import paper_2111_12411_amd as F
+from paper_2111_12411_amd import workloads as W
+from oracle import core, mesh as omesh
+from parity_util import close
+from test_oracle_pins_inject import beam_source
+
+pytestmark = pytest.mark.gpu
+
+QE, ME = -W.Q_E, W.M_E
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_injected_beam_matches_the_oracle(k):
+    N = 5
+    m = omesh.cube_mesh(N, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    pos, vel = W.particles("thermal", 4000, 31 + k, vth=0.01)
+    w = W.plasma_weight(8000, dt)
+    orc = core.OracleRun(m, dt, ops, absorb=True)
+    orc.load(pos, vel, QE, ME, w)
+    run = F.Run(F.Mesh.cube(N, k), dt, F.FP64, pcg_rtol=1e-15, particle_bc=F.ABSORB)
+    run.load(pos, vel, QE, ME, w)
+    for n in range(15):
+        p, v = beam_source(400, 200 + n)
+        orc.inject(p, v)
+        run.inject(p, v)
+        c0 = orc.counters.copy()
+        orc.step()
+        run.step()
+        close(run.deposit(), orc.last_dg * m.int1, 1e-12)
+        assert run.stats()["absorbed"] == orc.counters[2] - c0[2], n
+    st = run.stats()
+    assert st["n_loaded"] == 4000 + 15 * 400 and st["absorbed_total"] > 0
+    p, v, t = run.particles()
+    alive = orc.tet >= 0
+    assert np.array_equal(t < 0, ~alive)
+    close(p[alive], orc.pos[alive], 1e-13)
+    close(v[alive], orc.vel[alive], 1e-12)
+    e, b = run.fields()
+    close(e, orc.e, 1e-12)
+    close(b, orc.b, 1e-12)
+    rho, rho0 = run.rho()
+    close(rho0, orc.rho0 * m.int0, 1e-12)
+    RG, RC, RS = run.gauss()
+    assert RG < 1e-12 and RC < 1e-12, (RG, RC, RS)
+
+
+def test_injection_resumes_bitwise(tmp_path):
+    N, k = 4, 2
+    mesh = F.Mesh.cube(N, k)
+    dt = 10 * mesh.info()["dt_cfl"]
+    pos, vel = W.particles("thermal", 3000, 41, vth=0.01)
+    w = W.plasma_weight(6000, dt)
+    a = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14, particle_bc=F.ABSORB)
+    a.load(pos, vel, QE, ME, w)
+    for n in range(3):
+        a.inject(*beam_source(300, 300 + n))
+        a.step()
+    path = str(tmp_path / "inj.bin")
+    a.save(path)
+    b = F.Run(mesh, dt, F.MIXED, pcg_rtol=1e-14, particle_bc=F.ABSORB)
+    b.restore(path)
+    for n in range(3):
+        p, v = beam_source(300, 400 + n)
+        a.inject(p, v)
+        b.inject(p, v)
+        a.step()
+        b.step()
+    for x, y in zip(a.fields() + a.particles(), b.fields() + b.particles()):
+        assert np.array_equal(x, y)
+    assert a.gauss()[0] < 1e-12
