@@ -342,8 +342,8 @@ def main():
     ap.add_argument("--largest", action="store_true",
                     help="the largest single run instead: 56^3 cube, order 2, 64M electrons in two streams, mixed")
     ap.add_argument("--gauss-every", type=int, default=0,
-                    help="with --largest: Gauss-law residuals every that many steps, into the --log step log")
-    ap.add_argument("--log", default=None, help="with --largest: append one JSON line per step to this file")
+                    help="Gauss-law residuals every that many steps, into the --log step log")
+    ap.add_argument("--log", default=None, help="append one JSON line per step of the measured run to this file")
     ap.add_argument("--serving", action="store_true",
                     help="measure the submit/poll server on a stream of independent runs instead")
     args = ap.parse_args()
@@ -367,7 +367,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    mix = run_workload(3, F.MIXED, args.steps, args.warmup, n=args.particles, blocks=3)
+    mix = run_workload(3, F.MIXED, args.steps, args.warmup, n=args.particles, blocks=3, gauss_every=args.gauss_every,
+                       log=args.log)
     st = mix["stats"]
     K = args.steps
     n, nt, n1i = mix["n"], mix["info"]["n_tet"], mix["info"]["n1_int"]

@@ -2427,33 +2427,6 @@ __global__ void k_add_comp(int64_t n, double *__restrict__ hi, double *__restric
     lo[i] += e;
 }
 
-// y = A (x_hi + x_lo), one row per thread, Dot2 accumulation; y_hi + y_lo is
-// the result to about twice FP64 (y_lo may be null: y_hi is then the rounded sum)
-__global__ __launch_bounds__(BLK) void k_spmv_dd(int64_t rows, const int64_t *__restrict__ ptr,
-                                                 const int32_t *__restrict__ idx, const double *__restrict__ val,
-                                                 const double *__restrict__ x_hi, const double *__restrict__ x_lo,
-                                                 double *__restrict__ y_hi, double *__restrict__ y_lo)
-{
-#pragma clang fp contract(off)
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    double s = 0.0, c = 0.0;
-    for (int64_t k = ptr[r]; k < ptr[r + 1]; k++) {
-        const double a = val[k];
-        const int32_t j = idx[k];
-        const double p = a * x_hi[j];
-        const double q = fma(a, x_hi[j], -p);
-        double t, e;
-        two_sum(s, p, t, e);
-        s = t;
-        c += q + e + a * x_lo[j];
-    }
-    double h, l;
-    two_sum(s, c, h, l);
-    y_hi[r] = h;
-    if (y_lo) y_lo[r] = l;
-}
-
 hipError_t add_comp(int64_t n, double *hi, double *lo, const double *d, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
@@ -2461,14 +2434,6 @@ hipError_t add_comp(int64_t n, double *hi, double *lo, const double *d, hipStrea
     return hipGetLastError();
 }
 
-hipError_t spmv_dd(const DevCSR &A, const double *x_hi, const double *x_lo, double *y_hi, double *y_lo,
-                   hipStream_t s)
-{
-    if (A.rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_dd, dim3(nblk(A.rows)), dim3(BLK), 0, s, A.rows, A.ptr, A.idx, A.val, x_hi, x_lo,
-                       y_hi, y_lo);
-    return hipGetLastError();
-}
 
 // Linear combination of sparse products and vectors in double-double:
 //   out = a1 (P1 x1) + a2 (P2 (x2 + x2lo)) + c1 v1 + c2 v2
@@ -2569,6 +2534,12 @@ hipError_t combo_dd(int64_t rows, const DevCSR *P1, const double *x1, double a1,
     hipLaunchKernelGGL(k_combo_dd<L>, dim3((unsigned)((threads + BLK - 1) / BLK)), dim3(BLK), 0, s, rows,
                        P1 ? *P1 : none, x1, a1, P2 ? *P2 : none, x2, x2lo, a2, v1, c1, v2, c2, out_hi, out_lo);
     return hipGetLastError();
+}
+
+hipError_t spmv_dd(const DevCSR &A, const double *x_hi, const double *x_lo, double *y_hi, double *y_lo,
+                   hipStream_t s)
+{
+    return combo_dd(A.rows, nullptr, nullptr, 0.0, &A, x_hi, x_lo, 1.0, nullptr, 0.0, nullptr, 0.0, y_hi, y_lo, s);
 }
 
 // x += scale f, compensated: the rounding error of each addition goes to xlo

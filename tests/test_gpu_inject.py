@@ -78,5 +78,5 @@ def test_injection_resumes_bitwise(tmp_path):
         a.step()
         b.step()
     for x, y in zip(a.fields() + a.particles(), b.fields() + b.particles()):
-        assert np.array_equal(x, y)
-    assert a.gauss()[0] < 1e-12
+        assert np.array_equal(x, y, equal_nan=True)  # absorbed particles read back as NaN
+    assert (a.particles()[2] < 0).any() and a.gauss()[0] < 1e-12
