@@ -21,19 +21,36 @@ struct DevMesh {
     double cube_L;
 };
 
-// Particle state, structure of arrays.  The position is held as the particle's
-// barycentric coordinates l_1, l_2, l_3 in its tet (l_0 = 1 - l_1 - l_2 - l_3),
-// FP64 like the velocity in both modes; the AB4 histories are R (double, or
-// float in mixed mode).
+// Particle state.  The position is held as the particle's barycentric
+// coordinates l_1, l_2, l_3 in its tet (l_0 = 1 - l_1 - l_2 - l_3), FP64 like
+// the velocity in both modes; the AB4 histories are R (double, or float in
+// mixed mode): vh = v^{n-1} - v^n, v^{n-2} - v^n, v^{n-3} - v^n and
+// ah = a^{n-1}, a^{n-2}, a^{n-3}, three components each; tet; id (load order).
+//
+// Layout: a particle's state is a row of 4-byte units, packed into 16-byte
+// words, and the words are stored word-major: word k of row s at byte
+// (k cap + s) 16.  Loads of one word by consecutive rows are contiguous, as in
+// a structure of arrays, while one particle's state spans only NW words (8 in
+// mixed mode, 13 in FP64) instead of one line per scalar: a particle read from
+// a slot away from its neighbours (one that changed tet) costs NW lines.
+struct PartLayout {
+    int nw;                      // words per row
+    int lam, tet, id, v, vh, ah; // first unit of each field
+    int hs;                      // units per history value (1: float, 2: double)
+};
+// l_1..l_3, tet, id in words 0-1; v from unit 8; then vh, ah
+constexpr PartLayout PART_MIXED{8, 0, 6, 7, 8, 14, 23, 1};
+constexpr PartLayout PART_FP64{13, 0, 6, 7, 8, 14, 32, 2};
+constexpr const PartLayout &part_layout(bool mixed) { return mixed ? PART_MIXED : PART_FP64; }
+// byte offset of unit u of row s
+constexpr int64_t part_off(int u, int64_t cap, int64_t s) { return ((int64_t)(u >> 2) * cap + s) * 16 + (u & 3) * 4; }
+
 struct DevParticles {
-    double *lam;   // [3][cap]
-    void *v;       // [3][cap]   double
-    void *vh;      // [9][cap]   R: v^{n-1} - v^n, v^{n-2} - v^n, v^{n-3} - v^n
-    void *ah;      // [9][cap]   R: a^{n-1}, a^{n-2}, a^{n-3}
-    int32_t *tet;  // [cap]
-    int32_t *id;   // [cap]  load order
+    void *w;      // [nw][cap] 16-byte words (PartLayout)
     int64_t cap;
 };
+// the rows from s0 on, as a particle set of its own (same cap)
+inline DevParticles part_rows(DevParticles p, int64_t s0) { return DevParticles{(char *)p.w + s0 * 16, p.cap}; }
 
 // particle kernel: threads per block, most tets per block (order 1, 2), and the
 // number of particles a block aims at (tets per block = that / particles per tet)
@@ -95,10 +112,12 @@ struct ContQueue {
 
 
 // x: [3][cap] positions of n particles
-hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
-                              hipStream_t s);
-// positions x ([3][cap], in tet[p]) replaced in place by l_1..l_3 of that tet
-hipError_t launch_to_bary(const DevMesh &m, int64_t n, int64_t cap, double *x, const int32_t *tet, hipStream_t s);
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, DevParticles p, int32_t *err, hipStream_t s);
+// positions (held in the l_1..l_3 units, in the tet of the tet unit) replaced in
+// place by l_1..l_3 of that tet
+hipError_t launch_to_bary(const DevMesh &m, int64_t n, DevParticles p, hipStream_t s);
+// keys[i] = tet of row i, i < n
+hipError_t launch_tet_keys(DevParticles p, int64_t n, uint32_t *keys, hipStream_t s);
 hipError_t launch_startup(int order, bool mixed, const DevMesh &m, const double *e, const double *b, const float *e32,
                           const float *b32, DevParticles p, int64_t n, double qm, double dt, hipStream_t s);
 
@@ -181,8 +200,8 @@ hipError_t launch_place(int64_t np, int32_t nt, int32_t tpw, const int32_t *off,
                         const int32_t *noff, uint32_t *perm, unsigned long long *err, hipStream_t s);
 hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, const double *P, double *out,
                           hipStream_t s);
-hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *lam,
-                          int64_t cap, double qw, double *Pr, hipStream_t s);
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, DevParticles p,
+                          double qw, double *Pr, hipStream_t s);
 
 // linear algebra (FP64 unless noted)
 struct DevCSR {

@@ -64,15 +64,71 @@ namespace {
 // l_0 from the stored l_1..l_3 (always in this order of operations)
 __device__ __forceinline__ double bary0(double l1, double l2, double l3) { return 1.0 - l1 - l2 - l3; }
 
+// global-memory views of the pointers a kernel reads from its argument block:
+// accesses through them compile to global (not flat) memory instructions, so
+// waits on LDS reads do not also wait for outstanding global stores
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p)
+{
+    return (gptr<T>)p;
+}
+
+struct GMesh {
+    gptr<const double> geo;
+    gptr<const int32_t> nbr, map1, map2;
+    int32_t nt;
+};
+__device__ inline GMesh gview(const DevMesh &m)
+{
+    return GMesh{glb(m.geo), glb(m.nbr), glb(m.map1), glb(m.map2), m.nt};
+}
+
+// the fields of row s, in the packed layout of precision R
+template <typename R>
+struct GParticles {
+    static constexpr PartLayout L = sizeof(R) == 4 ? PART_MIXED : PART_FP64;
+    gptr<char> w;
+    int64_t cap;
+    template <typename T>
+    __device__ __forceinline__ gptr<T> at(int u, int64_t s) const
+    {
+        return (gptr<T>)(w + part_off(u, cap, s));
+    }
+    __device__ __forceinline__ gptr<double> lam(int c, int64_t s) const { return at<double>(L.lam + 2 * c, s); }
+    __device__ __forceinline__ gptr<double> v(int c, int64_t s) const { return at<double>(L.v + 2 * c, s); }
+    __device__ __forceinline__ gptr<R> vh(int c, int64_t s) const { return at<R>(L.vh + L.hs * c, s); }
+    __device__ __forceinline__ gptr<R> ah(int c, int64_t s) const { return at<R>(L.ah + L.hs * c, s); }
+    __device__ __forceinline__ gptr<int32_t> tet(int64_t s) const { return at<int32_t>(L.tet, s); }
+    __device__ __forceinline__ gptr<int32_t> id(int64_t s) const { return at<int32_t>(L.id, s); }
+};
+template <typename R>
+__device__ inline GParticles<R> gview(const DevParticles &p)
+{
+    return GParticles<R>{glb((char *)p.w), p.cap};
+}
+
 // ---------------------------------------------------------------- locate
-__global__ void k_locate_cube(DevMesh m, int64_t n, int64_t cap, const double *__restrict__ x,
-                              int32_t *__restrict__ tet, int32_t *__restrict__ err)
+// (the position, the l_1..l_3 units until k_to_bary, and tet share their units in
+// both layouts)
+__device__ __forceinline__ double *prow_lam(const DevParticles &P, int c, int64_t p)
+{
+    return (double *)((char *)P.w + part_off(PART_MIXED.lam + 2 * c, P.cap, p));
+}
+__device__ __forceinline__ int32_t *prow_tet(const DevParticles &P, int64_t p)
+{
+    return (int32_t *)((char *)P.w + part_off(PART_MIXED.tet, P.cap, p));
+}
+static_assert(PART_MIXED.lam == PART_FP64.lam && PART_MIXED.tet == PART_FP64.tet, "shared units");
+
+__global__ void k_locate_cube(DevMesh m, int64_t n, DevParticles P, int32_t *__restrict__ err)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int N = m.cube_N;
     const double L = m.cube_L;
-    double r[3] = {x[p], x[cap + p], x[2 * cap + p]};
+    double r[3] = {*prow_lam(P, 0, p), *prow_lam(P, 1, p), *prow_lam(P, 2, p)};
     const double tol = 1e-12 * L;
     int idx[3];
     bool ok = true;
@@ -98,20 +154,20 @@ __global__ void k_locate_cube(DevMesh m, int64_t n, int64_t cap, const double *_
             bt = (int32_t)t;
         }
     }
-    tet[p] = bt;
+    *prow_tet(P, p) = bt;
     if (!ok || !(best >= -1e-10)) atomicOr(err, (int)ERR_OUTSIDE);
 }
 
 // positions replaced in place by l_1..l_3 of their tets
-__global__ void k_to_bary(DevMesh m, int64_t n, int64_t cap, double *__restrict__ x, const int32_t *__restrict__ tet)
+__global__ void k_to_bary(DevMesh m, int64_t n, DevParticles P)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const double *g = &m.geo[16 * (int64_t)tet[p]];
-    const double r0 = x[p], r1 = x[cap + p], r2 = x[2 * cap + p];
+    const double *g = &m.geo[16 * (int64_t)*prow_tet(P, p)];
+    const double r0 = *prow_lam(P, 0, p), r1 = *prow_lam(P, 1, p), r2 = *prow_lam(P, 2, p);
     double l[3];
     for (int f = 1; f < 4; f++) l[f - 1] = g[4 * f] + g[4 * f + 1] * r0 + g[4 * f + 2] * r1 + g[4 * f + 3] * r2;
-    for (int c = 0; c < 3; c++) x[c * cap + p] = l[c];
+    for (int c = 0; c < 3; c++) *prow_lam(P, c, p) = l[c];
 }
 
 // ------------------------------------------------------------- gather
@@ -173,20 +229,6 @@ __device__ inline void cross3(const R *a, const R *b, R *o)
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-template <typename R>
-__device__ inline void load_vec(const void *base, int64_t cap, int comp, int64_t i, R *o, int n)
-{
-    const R *b = (const R *)base;
-    for (int k = 0; k < n; k++) o[k] = b[(int64_t)(comp + k) * cap + i];
-}
-
-template <typename R>
-__device__ inline void store_vec(void *base, int64_t cap, int comp, int64_t i, const R *v, int n)
-{
-    R *b = (R *)base;
-    for (int k = 0; k < n; k++) b[(int64_t)(comp + k) * cap + i] = v[k];
-}
-
 // ---------------------------------------------------------------- startup
 template <int K, typename R>
 __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restrict__ b, DevParticles P, int64_t n,
@@ -195,9 +237,10 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
     using O = Ord<K>;
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int64_t t = P.tet[p];
+    const GParticles<R> Q = gview<R>(P);
+    const int64_t t = *Q.tet(p);
     const double *g = &m.geo[16 * t];
-    const double l1 = P.lam[p], l2 = P.lam[P.cap + p], l3 = P.lam[2 * P.cap + p];
+    const double l1 = *Q.lam(0, p), l2 = *Q.lam(1, p), l3 = *Q.lam(2, p);
     R lam[4] = {(R)bary0(l1, l2, l3), (R)l1, (R)l2, (R)l3}, gr[4][3];
     for (int f = 0; f < 4; f++)
         for (int k = 0; k < 3; k++) gr[f][k] = (R)g[4 * f + 1 + k];
@@ -214,8 +257,7 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
         cross3(gr[EA[q]], gr[EB[q]], X);
         for (int k = 0; k < 3; k++) B[k] += cB[q] * X[k];
     }
-    double vd[3];
-    load_vec<double>(P.v, P.cap, 0, p, vd, 3);
+    const double vd[3] = {*Q.v(0, p), *Q.v(1, p), *Q.v(2, p)};
     R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]}, vxB[3], a[3];
     cross3(v, B, vxB);
     for (int k = 0; k < 3; k++) a[k] = (R)qm * (E[k] + vxB[k]);
@@ -226,8 +268,10 @@ __global__ void k_startup(DevMesh m, const R *__restrict__ e, const R *__restric
             ah[3 * (j - 1) + k] = a[k];
             vh[3 * (j - 1) + k] = (R)(-j * dt * (double)a[k]);
         }
-    store_vec<R>(P.vh, P.cap, 0, p, vh, 9);
-    store_vec<R>(P.ah, P.cap, 0, p, ah, 9);
+    for (int c = 0; c < 9; c++) {
+        *Q.vh(c, p) = vh[c];
+        *Q.ah(c, p) = ah[c];
+    }
 }
 
 // ------------------------------------------------------------ root finding
@@ -581,40 +625,6 @@ __device__ inline void segment_moments(const double (&lq)[3][5], double h, doubl
     }
 }
 
-// global-memory views of the pointers a kernel reads from its argument block:
-// accesses through them compile to global (not flat) memory instructions, so
-// waits on LDS reads do not also wait for outstanding global stores
-template <typename T>
-using gptr = __attribute__((address_space(1))) T *;
-template <typename T>
-__device__ __forceinline__ gptr<T> glb(T *p)
-{
-    return (gptr<T>)p;
-}
-
-struct GMesh {
-    gptr<const double> geo;
-    gptr<const int32_t> nbr, map1, map2;
-    int32_t nt;
-};
-__device__ inline GMesh gview(const DevMesh &m)
-{
-    return GMesh{glb(m.geo), glb(m.nbr), glb(m.map1), glb(m.map2), m.nt};
-}
-
-template <typename R>
-struct GParticles {
-    gptr<double> lam, v;
-    gptr<R> vh, ah;
-    gptr<int32_t> tet, id;
-    int64_t cap;
-};
-template <typename R>
-__device__ inline GParticles<R> gview(const DevParticles &p)
-{
-    return GParticles<R>{glb(p.lam), glb((double *)p.v), glb((R *)p.vh), glb((R *)p.ah), glb(p.tet), glb(p.id), p.cap};
-}
-
 struct GPool {
     gptr<double> val;
     gptr<int32_t> tet;
@@ -669,20 +679,23 @@ __device__ inline bool cross_face(const GMesh &m, GPtr G, int f, int &t, int &en
         dp[d][2] -= sd * gz;
     }
     {
-        const double x0 = out.v[i], x1 = out.v[out.cap + i], x2 = out.v[2 * out.cap + i];
+        const double x0 = *out.v(0, i), x1 = *out.v(1, i), x2 = *out.v(2, i);
         const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
-        out.v[i] = x0 - sd * gx;
-        out.v[out.cap + i] = x1 - sd * gy;
-        out.v[2 * out.cap + i] = x2 - sd * gz;
+        *out.v(0, i) = x0 - sd * gx;
+        *out.v(1, i) = x1 - sd * gy;
+        *out.v(2, i) = x2 - sd * gz;
     }
 #pragma unroll 1
     for (int h = 0; h < (hist ? 6 : 0); h++) {  // no histories with the Boris push
-        gptr<R> hp = (h < 3 ? out.vh : out.ah) + (int64_t)(3 * (h % 3)) * out.cap;
-        const double x0 = hp[i], x1 = hp[out.cap + i], x2 = hp[2 * out.cap + i];
+        const int c0 = 3 * (h % 3);
+        const gptr<R> h0 = h < 3 ? out.vh(c0, i) : out.ah(c0, i);
+        const gptr<R> h1 = h < 3 ? out.vh(c0 + 1, i) : out.ah(c0 + 1, i);
+        const gptr<R> h2 = h < 3 ? out.vh(c0 + 2, i) : out.ah(c0 + 2, i);
+        const double x0 = *h0, x1 = *h1, x2 = *h2;
         const double sd = (gx * x0 + gy * x1 + gz * x2) * inv;
-        hp[i] = (R)(x0 - sd * gx);
-        hp[out.cap + i] = (R)(x1 - sd * gy);
-        hp[2 * out.cap + i] = (R)(x2 - sd * gz);
+        *h0 = (R)(x0 - sd * gx);
+        *h1 = (R)(x1 - sd * gy);
+        *h2 = (R)(x2 - sd * gz);
     }
     nrf++;
     entry = f;
@@ -857,19 +870,19 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
         const uint32_t slot = min(nslot, (uint32_t)(in.cap - 1));  // perm holds slots < cap
         if (i + PBLK < pend) nslot = perm[i + PBLK];
         if (i < pend) {
-            const int th = in.tet[slot];
+            const int th = *in.tet(slot);
             const int lt = th - T0;
-            const double l1 = in.lam[slot], l2 = in.lam[in.cap + slot], l3 = in.lam[2 * in.cap + slot];
+            const double l1 = *in.lam(0, slot), l2 = *in.lam(1, slot), l3 = *in.lam(2, slot);
             const double ls[4] = {bary0(l1, l2, l3), l1, l2, l3};
             double vd[3];
             R vh[9], ah[9];
 #pragma unroll
-            for (int c = 0; c < 3; c++) vd[c] = in.v[c * in.cap + slot];
+            for (int c = 0; c < 3; c++) vd[c] = *in.v(c, slot);
             if constexpr (!BORIS) {
 #pragma unroll
                 for (int c = 0; c < 9; c++) {
-                    vh[c] = in.vh[c * in.cap + slot];
-                    ah[c] = in.ah[c * in.cap + slot];
+                    vh[c] = *in.vh(c, slot);
+                    ah[c] = *in.ah(c, slot);
                 }
             }
             const R v[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
@@ -913,13 +926,13 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 // new velocity and shifted histories, written now (wall reflections patch them)
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    out.v[c * out.cap + i] = vn[c];
-                    out.vh[c * out.cap + i] = (R)(-dv[c]);
-                    out.vh[(3 + c) * out.cap + i] = (R)((double)vh[c] - dv[c]);
-                    out.vh[(6 + c) * out.cap + i] = (R)((double)vh[3 + c] - dv[c]);
-                    out.ah[c * out.cap + i] = a[c];
-                    out.ah[(3 + c) * out.cap + i] = ah[c];
-                    out.ah[(6 + c) * out.cap + i] = ah[3 + c];
+                    *out.v(c, i) = vn[c];
+                    *out.vh(c, i) = (R)(-dv[c]);
+                    *out.vh(3 + c, i) = (R)((double)vh[c] - dv[c]);
+                    *out.vh(6 + c, i) = (R)((double)vh[3 + c] - dv[c]);
+                    *out.ah(c, i) = a[c];
+                    *out.ah(3 + c, i) = ah[c];
+                    *out.ah(6 + c, i) = ah[3 + c];
                 }
             } else {
                 // Boris: half kick, rotation about B through 2 atan(q |B| dt / 2m), half
@@ -947,10 +960,10 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                     // straight path r(s) = r^n + s dt v^{n+1/2}
                     dp[0][c] = sp.dt * vn[c];
                     dp[1][c] = dp[2][c] = dp[3][c] = 0.0;
-                    out.v[c * out.cap + i] = vn[c];
+                    *out.v(c, i) = vn[c];
                 }
             }
-            out.id[i] = in.id[slot];
+            *out.id(i) = *in.id(slot);
             // first segment: in the home tet from s = 0.  A path whose exit
             // needs the full search is handed whole to k_continue; a path that
             // leaves is handed over at its exit point (the crossing itself is
@@ -997,8 +1010,8 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 for (int c = 0; c < 3; c++) rec->lam[c] = f_exit >= 0 ? horner4(lq[c], s_exit) : ls[c + 1];
             } else {
 #pragma unroll
-                for (int c = 0; c < 3; c++) out.lam[(int64_t)c * out.cap + i] = horner4(lq[c], 1.0);
-                out.tet[i] = th;
+                for (int c = 0; c < 3; c++) *out.lam(c, i) = horner4(lq[c], 1.0);
+                *out.tet(i) = th;
             }
             if (f_exit != -2) {
                 const double s_hi = f_exit < 0 ? 1.0 : s_exit;
@@ -1151,9 +1164,9 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
                 } else {
                     if (f_exit >= 0) errs |= ERR_CROSS;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) out.lam[(int64_t)c * out.cap + i] = le[c + 1];
+                    for (int c = 0; c < 3; c++) *out.lam(c, i) = le[c + 1];
                     if (!(le[1] == le[1] && le[2] == le[2] && le[3] == le[3])) errs |= ERR_NAN;
-                    out.tet[i] = t;
+                    *out.tet(i) = t;
                 }
             }
             asm volatile("" ::: "memory");
@@ -1260,18 +1273,24 @@ __global__ __launch_bounds__(BLK) void k_flag_compact(const uint8_t *__restrict_
 }
 
 // ------------------------------------------------------------ permute
-template <typename R>
+template <int NW>
 __global__ void k_permute(DevParticles in, DevParticles out, const uint32_t *__restrict__ perm, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t j = perm[i];
-    for (int c = 0; c < 3; c++) out.lam[c * out.cap + i] = in.lam[c * in.cap + j];
-    for (int c = 0; c < 3; c++) ((double *)out.v)[c * out.cap + i] = ((const double *)in.v)[c * in.cap + j];
-    for (int c = 0; c < 9; c++) ((R *)out.vh)[c * out.cap + i] = ((const R *)in.vh)[c * in.cap + j];
-    for (int c = 0; c < 9; c++) ((R *)out.ah)[c * out.cap + i] = ((const R *)in.ah)[c * in.cap + j];
-    out.tet[i] = in.tet[j];
-    out.id[i] = in.id[j];
+    typedef unsigned int word __attribute__((ext_vector_type(4)));  // one 16-byte word
+    const gptr<const word> a = glb((const word *)in.w);
+    const gptr<word> b = glb((word *)out.w);
+#pragma unroll
+    for (int k = 0; k < NW; k++) b[k * out.cap + i] = a[k * in.cap + j];
+}
+
+__global__ void k_tet_keys(DevParticles p, int64_t n, uint32_t *__restrict__ keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = (uint32_t)*(const int32_t *)((const char *)p.w + part_off(PART_MIXED.tet, p.cap, i));
 }
 
 // ----------------------------------------------------------- radix sort
@@ -1583,8 +1602,8 @@ __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__rest
 // nodal charge per tet (order-k W0 values times q w), same tiling as k_particle
 template <int K>
 __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__restrict__ perm,
-                                                 const int32_t *__restrict__ off, const double *__restrict__ lam,
-                                                 int64_t cap, double qw, int tpw, double *__restrict__ Pr)
+                                                 const int32_t *__restrict__ off, DevParticles P, double qw, int tpw,
+                                                 double *__restrict__ Pr)
 {
     using O = Ord<K>;
     constexpr int N0 = O::N0;
@@ -1605,9 +1624,9 @@ __global__ __launch_bounds__(BLK) void k_rho_tet(DevMesh m, const uint32_t *__re
         if (i < pend) {
             const uint32_t slot = perm[i];
             double l[4];
-            l[1] = lam[slot];
-            l[2] = lam[cap + slot];
-            l[3] = lam[2 * cap + slot];
+            l[1] = *prow_lam(P, 0, slot);
+            l[2] = *prow_lam(P, 1, slot);
+            l[3] = *prow_lam(P, 2, slot);
             l[0] = bary0(l[1], l[2], l[3]);
             if constexpr (K == 1) {
                 for (int f = 0; f < 4; f++) s_w[f][tid] = qw * l[f];
@@ -2038,18 +2057,17 @@ inline unsigned nblk(int64_t n, int b = BLK) { return (unsigned)((n + b - 1) / b
 }  // namespace
 
 // =================================================================== launchers
-hipError_t launch_locate_cube(const DevMesh &m, int64_t n, int64_t cap, const double *x, int32_t *tet, int32_t *err,
-                              hipStream_t s)
+hipError_t launch_locate_cube(const DevMesh &m, int64_t n, DevParticles p, int32_t *err, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, cap, x, tet, err);
+    hipLaunchKernelGGL(k_locate_cube, dim3(nblk(n)), dim3(BLK), 0, s, m, n, p, err);
     return hipGetLastError();
 }
 
-hipError_t launch_to_bary(const DevMesh &m, int64_t n, int64_t cap, double *x, const int32_t *tet, hipStream_t s)
+hipError_t launch_to_bary(const DevMesh &m, int64_t n, DevParticles p, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_to_bary, dim3(nblk(n)), dim3(BLK), 0, s, m, n, cap, x, tet);
+    hipLaunchKernelGGL(k_to_bary, dim3(nblk(n)), dim3(BLK), 0, s, m, n, p);
     return hipGetLastError();
 }
 
@@ -2132,8 +2150,15 @@ hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const u
                           hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    if (mixed) hipLaunchKernelGGL(k_permute<float>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
-    else hipLaunchKernelGGL(k_permute<double>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
+    if (mixed) hipLaunchKernelGGL(k_permute<PART_MIXED.nw>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
+    else hipLaunchKernelGGL(k_permute<PART_FP64.nw>, dim3(nblk(n)), dim3(BLK), 0, s, in, out, perm, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_keys(DevParticles p, int64_t n, uint32_t *keys, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tet_keys, dim3(nblk(n)), dim3(BLK), 0, s, p, n, keys);
     return hipGetLastError();
 }
 
@@ -2235,15 +2260,15 @@ hipError_t launch_scatter(const int64_t *ptr, const int32_t *idx, int64_t n, con
     return hipGetLastError();
 }
 
-hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, const double *lam,
-                          int64_t cap, double qw, double *Pr, hipStream_t s)
+hipError_t launch_rho_tet(int order, const DevMesh &m, const uint32_t *perm, const int32_t *off, DevParticles p,
+                          double qw, double *Pr, hipStream_t s)
 {
     const int tpw = order == 1 ? 64 : 25;  // BLK / n0
     const unsigned grid = (unsigned)((m.nt + tpw - 1) / tpw);
     if (order == 1)
-        hipLaunchKernelGGL(k_rho_tet<1>, dim3(grid), dim3(BLK), 0, s, m, perm, off, lam, cap, qw, tpw, Pr);
+        hipLaunchKernelGGL(k_rho_tet<1>, dim3(grid), dim3(BLK), 0, s, m, perm, off, p, qw, tpw, Pr);
     else
-        hipLaunchKernelGGL(k_rho_tet<2>, dim3(grid), dim3(BLK), 0, s, m, perm, off, lam, cap, qw, tpw, Pr);
+        hipLaunchKernelGGL(k_rho_tet<2>, dim3(grid), dim3(BLK), 0, s, m, perm, off, p, qw, tpw, Pr);
     return hipGetLastError();
 }
 

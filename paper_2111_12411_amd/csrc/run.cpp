@@ -401,10 +401,58 @@ void Run::sync()
     if (sticky) throw Error(sticky, sticky_msg);
 }
 
-size_t Run::particle_bytes(int64_t n) const
+size_t Run::particle_bytes(int64_t n) const { return (size_t)n * part_layout(mixed).nw * 16; }
+
+namespace {
+// a host image of particle rows: the device layout with the row count in place of cap
+template <typename T>
+T unit_get(const std::vector<char> &img, int64_t n, int u, int64_t s)
 {
-    const size_t rs = mixed ? 4 : 8;
-    return (size_t)n * (6 * 8 + 18 * rs + 8);
+    T x;
+    std::memcpy(&x, img.data() + part_off(u, n, s), sizeof x);
+    return x;
+}
+template <typename T>
+void unit_set(std::vector<char> &img, int64_t n, int u, int64_t s, T x)
+{
+    std::memcpy(img.data() + part_off(u, n, s), &x, sizeof x);
+}
+}  // namespace
+
+std::vector<char> Run::rows_get(const PBufs &B, int64_t s0, int64_t n)
+{
+    const int nw = part_layout(mixed).nw;
+    std::vector<char> img((size_t)std::max<int64_t>(n, 1) * nw * 16);
+    for (int k = 0; k < nw && n > 0; k++)
+        HIPCHECK(hipMemcpyAsync(img.data() + (size_t)k * n * 16, (const char *)B.w.p + ((size_t)k * B.d.cap + s0) * 16,
+                                (size_t)n * 16, hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+    return img;
+}
+
+void Run::rows_put(PBufs &B, int64_t s0, int64_t n, const std::vector<char> &img)
+{
+    const int nw = part_layout(mixed).nw;
+    for (int k = 0; k < nw && n > 0; k++)
+        HIPCHECK(hipMemcpyAsync((char *)B.w.p + ((size_t)k * B.d.cap + s0) * 16, img.data() + (size_t)k * n * 16,
+                                (size_t)n * 16, hipMemcpyHostToDevice, stream));
+    HIPCHECK(hipStreamSynchronize(stream));
+}
+
+// image of n new particles: positions (in the l_1..l_3 units, until they are
+// located), velocities and ids from id0; the rest zero
+std::vector<char> Run::rows_new(const double *pos, const double *vel, int64_t n, int64_t id0) const
+{
+    const PartLayout &L = part_layout(mixed);
+    std::vector<char> img((size_t)std::max<int64_t>(n, 1) * L.nw * 16, 0);
+    for (int64_t i = 0; i < n; i++) {
+        for (int c = 0; c < 3; c++) {
+            unit_set<double>(img, n, L.lam + 2 * c, i, pos[3 * i + c]);
+            unit_set<double>(img, n, L.v + 2 * c, i, vel[3 * i + c]);
+        }
+        unit_set<int32_t>(img, n, L.id, i, (int32_t)(id0 + i));
+    }
+    return img;
 }
 
 void Run::alloc_particles(int64_t n, int64_t cap_want)
@@ -412,21 +460,13 @@ void Run::alloc_particles(int64_t n, int64_t cap_want)
     np = n;
     np_loaded = n;
     const int64_t cap = std::max<int64_t>({n, cap_want, 1});
-    const size_t rs = mixed ? 4 : 8;
     for (int k = 0; k < 2; k++) {
         PBufs &B = pb[k];
-        B.lam.alloc(cap * 3 * 8);
-        B.v.alloc(cap * 3 * 8);
-        B.vh.alloc(cap * 9 * rs);
-        B.ah.alloc(cap * 9 * rs);
-        B.tet.alloc(cap * 4);
-        B.id.alloc(cap * 4);
-        B.d.lam = (double *)B.lam.p;
-        B.d.v = B.v.p;
-        B.d.vh = B.vh.p;
-        B.d.ah = B.ah.p;
-        B.d.tet = (int32_t *)B.tet.p;
-        B.d.id = (int32_t *)B.id.p;
+        B.w.alloc(particle_bytes(cap));
+        // rows start zero: unused units stay defined, and without AB4 (the Boris
+        // push) the histories stay zero in both sets
+        zero(B.w);
+        B.d.w = B.w.p;
         B.d.cap = cap;
     }
     cur = 0;
@@ -502,7 +542,8 @@ const uint32_t *Run::sort_current()
 {
     if (perm_valid) return cur_perm;
     int res = 0;
-    HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream, (const uint32_t *)pb[cur].d.tet));
+    HIPCHECK(launch_tet_keys(pb[cur].d, np, psort.key[0], stream));
+    HIPCHECK(radix_sort(psort, np, key_bits(), true, &res, stream, nullptr));
     HIPCHECK(launch_offsets(psort.key[res], np, (int32_t)m.nt, (int32_t *)d_off.p, stream));
     cur_perm = psort.val[res];
     perm_valid = true;
@@ -547,43 +588,26 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
     w = w_;
     alloc_particles(n);
     PBufs &B = pb[0];
-    std::vector<double> xs(3 * std::max<int64_t>(n, 1));
-    for (int64_t i = 0; i < n; i++)
-        for (int c = 0; c < 3; c++) xs[c * n + i] = pos[3 * i + c];
-    if (n) HIPCHECK(hipMemcpyAsync(B.lam.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
-    HIPCHECK(hipStreamSynchronize(stream));
-    for (int64_t i = 0; i < n; i++)
-        for (int c = 0; c < 3; c++) xs[c * n + i] = vel[3 * i + c];
-    if (n) HIPCHECK(hipMemcpyAsync(B.v.p, xs.data(), 3 * n * 8, hipMemcpyHostToDevice, stream));
-    HIPCHECK(hipStreamSynchronize(stream));
-    std::vector<int32_t> ids(std::max<int64_t>(n, 1));
-    std::iota(ids.begin(), ids.end(), 0);
-    if (n) HIPCHECK(hipMemcpyAsync(B.id.p, ids.data(), n * 4, hipMemcpyHostToDevice, stream));
-    // locate
-    std::vector<int32_t> tets;
+    {
+        std::vector<char> img = rows_new(pos, vel, n, 0);
+        if (!m.is_cube) {
+            std::vector<int32_t> tets(std::max<int64_t>(n, 1));
+            locate_host(pos, n, tets.data());
+            for (int64_t i = 0; i < n; i++) unit_set<int32_t>(img, n, part_layout(mixed).tet, i, tets[i]);
+        }
+        rows_put(B, 0, n, img);
+    }
     if (m.is_cube) {
         HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
-        HIPCHECK(launch_locate_cube(dm, n, B.d.cap, (const double *)B.lam.p, (int32_t *)B.tet.p, p_small,
-                                    stream));
+        HIPCHECK(launch_locate_cube(dm, n, B.d, p_small, stream));
         int32_t err = 0;
         HIPCHECK(hipMemcpyAsync(&err, p_small, 4, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         if (err & ERR_OUTSIDE) throw Error(FEMPIC_EOUTSIDE, "a particle lies outside the mesh");
-    } else {
-        tets.resize(std::max<int64_t>(n, 1));
-        locate_host(pos, n, tets.data());
-        if (n) HIPCHECK(hipMemcpyAsync(B.tet.p, tets.data(), n * 4, hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipStreamSynchronize(stream));
     }
     // the positions become barycentric coordinates in the located tets
-    HIPCHECK(launch_to_bary(dm, n, B.d.cap, (double *)B.lam.p, (const int32_t *)B.tet.p, stream));
-    if (prm.pusher == FEMPIC_PUSH_BORIS) {
-        // the Boris push keeps no history: zero in both buffer sets (checkpoints copy it)
-        for (PBufs *P : {&pb[0], &pb[1]}) {
-            HIPCHECK(hipMemsetAsync(P->vh.p, 0, P->vh.bytes, stream));
-            HIPCHECK(hipMemsetAsync(P->ah.p, 0, P->ah.bytes, stream));
-        }
-    } else {
+    HIPCHECK(launch_to_bary(dm, n, B.d, stream));
+    if (prm.pusher != FEMPIC_PUSH_BORIS) {
         // AB4 start-up from the current fields
         HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
                                 (const float *)d_e32.p, (const float *)d_b32.p, B.d, n, q / mass, prm.dt, stream));
@@ -633,17 +657,9 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
     rho_a.alloc(N0i * 8);
     rho_b.alloc(N0i * 8);
     compute_rho((double *)rho_a.p);
-    // the new particles, located on the host side of the upload
-    std::vector<double> xs(3 * n), vs(3 * n);
-    for (int64_t i = 0; i < n; i++)
-        for (int c = 0; c < 3; c++) {
-            xs[c * n + i] = pos[3 * i + c];
-            vs[c * n + i] = vel[3 * i + c];
-        }
     gather_current();
     cur = 1 - cur;  // the gathered, tet-sorted rows are now the state
     const int64_t np0 = np, np1 = np0 + n, id0 = np_loaded;
-    const size_t rs = mixed ? 4 : 8;
     if (np1 > pb[cur].d.cap) {
         // grow by half again, keeping the gathered rows
         PBufs old = std::move(pb[cur]);
@@ -652,62 +668,36 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
         alloc_particles(np0, np1 + np1 / 2);
         np_loaded = nl;
         const int64_t nc = pb[0].d.cap;
-        auto copy_cols = [&](DevBuf &dst, const DevBuf &src, int cols, size_t es) {
-            for (int c = 0; c < cols; c++)
-                if (np0)
-                    HIPCHECK(hipMemcpyAsync((char *)dst.p + (size_t)c * nc * es, (const char *)src.p + (size_t)c * oc * es,
-                                            (size_t)np0 * es, hipMemcpyDeviceToDevice, stream));
-        };
         PBufs &B = pb[0];
-        copy_cols(B.lam, old.lam, 3, 8);
-        copy_cols(B.v, old.v, 3, 8);
-        copy_cols(B.vh, old.vh, 9, rs);
-        copy_cols(B.ah, old.ah, 9, rs);
-        copy_cols(B.tet, old.tet, 1, 4);
-        copy_cols(B.id, old.id, 1, 4);
+        for (int k = 0; k < part_layout(mixed).nw && np0 > 0; k++)
+            HIPCHECK(hipMemcpyAsync((char *)B.w.p + (size_t)k * nc * 16, (const char *)old.w.p + (size_t)k * oc * 16,
+                                    (size_t)np0 * 16, hipMemcpyDeviceToDevice, stream));
         HIPCHECK(hipStreamSynchronize(stream));  // old is freed at the end of this block
         cur = 0;
-        if (prm.pusher == FEMPIC_PUSH_BORIS)
-            for (PBufs *P : {&pb[0], &pb[1]}) {
-                HIPCHECK(hipMemsetAsync(P->vh.p, 0, P->vh.bytes, stream));
-                HIPCHECK(hipMemsetAsync(P->ah.p, 0, P->ah.bytes, stream));
-            }
     }
     PBufs &B = pb[cur];
-    const int64_t cap = B.d.cap;
-    for (int c = 0; c < 3; c++) {
-        HIPCHECK(hipMemcpyAsync((double *)B.lam.p + c * cap + np0, &xs[c * n], n * 8, hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipMemcpyAsync((double *)B.v.p + c * cap + np0, &vs[c * n], n * 8, hipMemcpyHostToDevice, stream));
+    {
+        std::vector<char> img = rows_new(pos, vel, n, id0);
+        if (!m.is_cube) {
+            std::vector<int32_t> tets(n);
+            locate_host(pos, n, tets.data());
+            for (int64_t i = 0; i < n; i++) unit_set<int32_t>(img, n, part_layout(mixed).tet, i, tets[i]);
+        }
+        rows_put(B, np0, n, img);
     }
-    std::vector<int32_t> ids(n);
-    for (int64_t i = 0; i < n; i++) ids[i] = (int32_t)(id0 + i);
-    HIPCHECK(hipMemcpyAsync((int32_t *)B.id.p + np0, ids.data(), n * 4, hipMemcpyHostToDevice, stream));
-    double *xn = (double *)B.lam.p + np0;
-    int32_t *tn = (int32_t *)B.tet.p + np0;
+    const DevParticles nw = part_rows(B.d, np0);
     if (m.is_cube) {
         HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
-        HIPCHECK(launch_locate_cube(dm, n, cap, xn, tn, p_small, stream));
+        HIPCHECK(launch_locate_cube(dm, n, nw, p_small, stream));
         int32_t err = 0;
         HIPCHECK(hipMemcpyAsync(&err, p_small, 4, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         if (err & ERR_OUTSIDE) throw Error(FEMPIC_EOUTSIDE, "an injected particle lies outside the mesh");
-    } else {
-        std::vector<int32_t> tets(n);
-        locate_host(pos, n, tets.data());
-        HIPCHECK(hipMemcpyAsync(tn, tets.data(), n * 4, hipMemcpyHostToDevice, stream));
     }
-    HIPCHECK(launch_to_bary(dm, n, cap, xn, tn, stream));
-    if (prm.pusher != FEMPIC_PUSH_BORIS) {
-        DevParticles v = B.d;
-        v.lam += np0;
-        v.v = (double *)v.v + np0;
-        v.vh = (char *)v.vh + np0 * rs;
-        v.ah = (char *)v.ah + np0 * rs;
-        v.tet += np0;
-        v.id += np0;
+    HIPCHECK(launch_to_bary(dm, n, nw, stream));
+    if (prm.pusher != FEMPIC_PUSH_BORIS)
         HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
-                                (const float *)d_e32.p, (const float *)d_b32.p, v, n, q / mass, prm.dt, stream));
-    }
+                                (const float *)d_e32.p, (const float *)d_b32.p, nw, n, q / mass, prm.dt, stream));
     np = np1;
     np_loaded = id0 + n;
     perm_valid = false;
@@ -778,7 +768,7 @@ void Run::compute_rho(double *dst, double *Pr)
 {
     if (!Pr) Pr = (double *)d_Pr.p;
     const uint32_t *perm = sort_current();
-    HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d.lam, pb[cur].d.cap, q * w, Pr,
+    HIPCHECK(launch_rho_tet(order, dm, perm, (const int32_t *)d_off.p, pb[cur].d, q * w, Pr,
                             stream));
     HIPCHECK(launch_scatter((const int64_t *)d_inc0_ptr.p, (const int32_t *)d_inc0_idx.p, m.N0_int,
                             (const double *)Pr, dst, stream));
@@ -1554,28 +1544,22 @@ void Run::particles_get(double *pos, double *vel, int64_t *tet, int64_t n)
         if (tet) tet[o] = -1;
     }
     if (!loaded || np == 0) return;
-    const PBufs &B = gather_current();
-    std::vector<double> x(3 * np), v(3 * np);
-    std::vector<int32_t> id(np), tt(np);
-    const int64_t cap = B.d.cap;
-    for (int c = 0; c < 3; c++) {
-        HIPCHECK(hipMemcpy(&x[c * np], (double *)B.lam.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-    }
-    HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
-    HIPCHECK(hipMemcpy(tt.data(), B.tet.p, np * 4, hipMemcpyDeviceToHost));
+    const std::vector<char> img = rows_get(gather_current(), 0, np);
+    const PartLayout &L = part_layout(mixed);
     for (int64_t i = 0; i < np; i++) {
-        const int64_t o = id[i];
+        const int64_t o = unit_get<int32_t>(img, np, L.id, i);
+        const int32_t tt = unit_get<int32_t>(img, np, L.tet, i);
         // position from the barycentric coordinates: x_0 + sum_m l_m (x_m - x_0)
-        const int32_t *tv = &m.tets[4 * (int64_t)tt[i]];
+        const int32_t *tv = &m.tets[4 * (int64_t)tt];
         const double *x0 = &m.xyz[3 * tv[0]];
         for (int c = 0; c < 3; c++) {
             double r = x0[c];
-            for (int k = 1; k < 4; k++) r += x[(k - 1) * np + i] * (m.xyz[3 * tv[k] + c] - x0[c]);
+            for (int k = 1; k < 4; k++)
+                r += unit_get<double>(img, np, L.lam + 2 * (k - 1), i) * (m.xyz[3 * tv[k] + c] - x0[c]);
             if (pos) pos[3 * o + c] = r;
-            if (vel) vel[3 * o + c] = v[c * np + i];
+            if (vel) vel[3 * o + c] = unit_get<double>(img, np, L.v + 2 * c, i);
         }
-        if (tet) tet[o] = tt[i];
+        if (tet) tet[o] = tt;
     }
 }
 
@@ -1715,14 +1699,23 @@ void Run::save(const char *path)
         if (bytes) HIPCHECK(hipMemcpy(stage.data(), d, bytes, hipMemcpyDeviceToHost));
         F.write(stage.data(), bytes);
     };
-    const int64_t cap = S.d.cap;
-    const size_t rs = mixed ? 4 : 8;
-    for (int c = 0; c < 3; c++) put((const double *)S.lam.p + c * cap, np * 8);
-    for (int c = 0; c < 3; c++) put((const double *)S.v.p + c * cap, np * 8);
-    for (int c = 0; c < 9; c++) put((const char *)S.vh.p + c * cap * rs, np * rs);
-    for (int c = 0; c < 9; c++) put((const char *)S.ah.p + c * cap * rs, np * rs);
-    put(S.tet.p, np * 4);
-    put(S.id.p, np * 4);
+    {
+        // the particles field by field (one column per scalar), from a host image of the rows
+        const std::vector<char> img = rows_get(S, 0, np);
+        const PartLayout &L = part_layout(mixed);
+        const int rs = mixed ? 4 : 8;
+        auto col = [&](int u, int bytes) {
+            stage.resize(std::max<size_t>((size_t)np * bytes, 1));
+            for (int64_t i = 0; i < np; i++) std::memcpy(&stage[(size_t)i * bytes], img.data() + part_off(u, np, i), bytes);
+            F.write(stage.data(), (size_t)np * bytes);
+        };
+        for (int c = 0; c < 3; c++) col(L.lam + 2 * c, 8);
+        for (int c = 0; c < 3; c++) col(L.v + 2 * c, 8);
+        for (int c = 0; c < 9; c++) col(L.vh + L.hs * c, rs);
+        for (int c = 0; c < 9; c++) col(L.ah + L.hs * c, rs);
+        col(L.tet, 4);
+        col(L.id, 4);
+    }
     put(d_e.p, m.N1 * 8);
     put(d_b.p, m.N2 * 8);
     put(d_g.p, m.N1_int * 8);
@@ -1853,19 +1846,23 @@ void Run::restore(const char *path)
     mass = h.mass;
     w = h.w;
     alloc_particles(n);
-    PBufs &B = pb[0];
-    const int64_t cap = B.d.cap;
+    {
+        const PartLayout &L = part_layout(mixed);
+        std::vector<char> img((size_t)std::max<int64_t>(n, 1) * L.nw * 16, 0);
+        auto col = [&](int u, const char *src, int bytes) {
+            for (int64_t i = 0; i < n; i++) std::memcpy(img.data() + part_off(u, n, i), src + (size_t)i * bytes, bytes);
+        };
+        for (int c = 0; c < 3; c++) col(L.lam + 2 * c, (const char *)&x[c * n], 8);
+        for (int c = 0; c < 3; c++) col(L.v + 2 * c, (const char *)&v[c * n], 8);
+        for (int c = 0; c < 9; c++) col(L.vh + L.hs * c, &vh[c * n * rs], (int)rs);
+        for (int c = 0; c < 9; c++) col(L.ah + L.hs * c, &ah[c * n * rs], (int)rs);
+        col(L.tet, (const char *)tet.data(), 4);
+        col(L.id, (const char *)id.data(), 4);
+        rows_put(pb[0], 0, n, img);
+    }
     auto get = [&](void *d, const void *src, size_t bytes) {
         if (bytes) HIPCHECK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));
     };
-    for (int c = 0; c < 3; c++) get((double *)B.lam.p + c * cap, &x[c * n], n * 8);
-    for (int c = 0; c < 3; c++) get((double *)B.v.p + c * cap, &v[c * n], n * 8);
-    for (int c = 0; c < 9; c++) get((char *)B.vh.p + c * cap * rs, &vh[c * n * rs], n * rs);
-    for (int c = 0; c < 9; c++) get((char *)B.ah.p + c * cap * rs, &ah[c * n * rs], n * rs);
-    get(B.tet.p, tet.data(), n * 4);
-    get(B.id.p, id.data(), n * 4);
-    if (prm.pusher == FEMPIC_PUSH_BORIS)  // no history: the other buffer set's stays zero too
-        for (DevBuf *h : {&pb[1].vh, &pb[1].ah}) HIPCHECK(hipMemsetAsync(h->p, 0, h->bytes, stream));
     get(d_e.p, e.data(), e.size() * 8);
     get(d_b.p, b.data(), b.size() * 8);
     get(d_g.p, g.data(), g.size() * 8);
@@ -1910,35 +1907,19 @@ void Run::history_get(double *vh, double *ah, int64_t n)
         if (ah) ah[k] = nan;
     }
     if (!loaded || np == 0) return;
-    const PBufs &B = gather_current();
-    const int64_t cap = B.d.cap;
-    std::vector<int32_t> id(np);
-    HIPCHECK(hipMemcpy(id.data(), B.id.p, np * 4, hipMemcpyDeviceToHost));
-    auto fetch = [&](const DevBuf &src, double *dst) {
-        std::vector<double> h(9 * np);
-        if (mixed) {
-            std::vector<float> f(9 * np);
-            for (int c = 0; c < 9; c++)
-                HIPCHECK(hipMemcpy(&f[c * np], (float *)src.p + c * cap, np * 4, hipMemcpyDeviceToHost));
-            for (size_t k = 0; k < f.size(); k++) h[k] = f[k];
-        } else {
-            for (int c = 0; c < 9; c++)
-                HIPCHECK(hipMemcpy(&h[c * np], (double *)src.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-        }
-        for (int64_t i = 0; i < np; i++)
-            for (int c = 0; c < 9; c++) dst[9 * id[i] + c] = h[c * np + i];
+    const std::vector<char> img = rows_get(gather_current(), 0, np);
+    const PartLayout &L = part_layout(mixed);
+    auto hist = [&](int u0, int c, int64_t i) {
+        return mixed ? (double)unit_get<float>(img, np, u0 + c, i) : unit_get<double>(img, np, u0 + 2 * c, i);
     };
-    if (vh) {
-        // the device keeps v^{n-j} - v^n; the caller gets v^{n-j}
-        fetch(B.vh, vh);
-        std::vector<double> v(3 * np);
-        for (int c = 0; c < 3; c++)
-            HIPCHECK(hipMemcpy(&v[c * np], (double *)B.v.p + c * cap, np * 8, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < np; i++)
-            for (int j = 0; j < 3; j++)
-                for (int c = 0; c < 3; c++) vh[9 * id[i] + 3 * j + c] += v[c * np + i];
+    for (int64_t i = 0; i < np; i++) {
+        const int64_t o = unit_get<int32_t>(img, np, L.id, i);
+        for (int c = 0; c < 9; c++) {
+            // the device keeps v^{n-j} - v^n; the caller gets v^{n-j}
+            if (vh) vh[9 * o + c] = hist(L.vh, c, i) + unit_get<double>(img, np, L.v + 2 * (c % 3), i);
+            if (ah) ah[9 * o + c] = hist(L.ah, c, i);
+        }
     }
-    if (ah) fetch(B.ah, ah);
 }
 
 // Mirrors what the constructor, load and the first particle phase allocate.
@@ -1952,7 +1933,6 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
                  N0i = (double)z.n0_int;
     const double nnzA = N1i * (k2 ? 46.0 : 17.0), nnzK = N2 * (k2 ? 13.0 : 3.0), nnzG = N0i * (k2 ? 25.0 : 15.0),
                  nnzNu = N2 * (k2 ? 24.0 : 7.0);
-    const double rs = mixed ? 4 : 8;
     auto csr = [](double rows, double nnz) { return (rows + 1) * 8 + nnz * 12 + 256; };
     // A and *eps, with 2x2 block copies at order 2; K, K^T, *nu, G^T
     double ops = 2 * csr(N1i, nnzA) + (mixed ? nnzA * 4 : 0) + csr(N2, nnzK) + csr(N1i, nnzK) + csr(N2, nnzNu) +
@@ -1967,7 +1947,7 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     vecs += (std::max({N1i, N2, N0i, 1.0}) / 4 + 1024) * 32 + 512;
     const double tets = nt * (n1l + n0l) * 8 + 5 * (nt + 1) * 4 + (double)CONT_BLOCKS * NCNT * 8 + 4096;
     const double cap = (double)std::max<int64_t>(n, 1);
-    const double parts = 2 * cap * (6 * 8 + 18 * rs + 8);
+    const double parts = 2 * cap * part_layout(mixed).nw * 16;
     auto sorts = [&](double c) {
         const double hn = (double)sort_hist_entries((int64_t)c);
         const double tmp = (double)std::max({scan_tmp_entries((int64_t)hn), scan_tmp_entries((int64_t)c),

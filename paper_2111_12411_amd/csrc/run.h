@@ -64,7 +64,7 @@ struct DevCSRBuf {
 };
 
 struct PBufs {
-    DevBuf lam, v, vh, ah, tet, id;
+    DevBuf w;  // the rows' 16-byte words (PartLayout)
     DevParticles d{};
 };
 
@@ -129,6 +129,11 @@ class Run {
     void zero(DevBuf &b);
     size_t particle_bytes(int64_t n) const;
     void alloc_particles(int64_t n, int64_t cap = 0);
+    // rows [s0, s0 + n) of a particle buffer set to / from a host image of them
+    // (the device layout with n in place of cap)
+    std::vector<char> rows_get(const PBufs &B, int64_t s0, int64_t n);
+    void rows_put(PBufs &B, int64_t s0, int64_t n, const std::vector<char> &img);
+    std::vector<char> rows_new(const double *pos, const double *vel, int64_t n, int64_t id0) const;
     void alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold);
     void alloc_pool(int64_t cap);
     DevParticles P(int k) const;
