@@ -319,8 +319,10 @@ typedef struct {
     int64_t absorbed;         /* last step: particles absorbed at a wall */
     int64_t absorbed_total;   /* since load */
     double particle_ms;       /* last call: device time of ordering + particle + deposit reduction, ms */
-    double particle_kernel_ms;/* last call: device time of the particle kernel (gather, push, first segment), ms */
-    double continue_kernel_ms;/* last call: device time of the kernel that tracks paths leaving their tet, ms */
+    double particle_kernel_ms;/* last call: device time of the particle kernel (gather, push, first segment), ms;
+                                 steps whose particle phase replayed a graph do not count (phase_replays) */
+    double continue_kernel_ms;/* last call: device time of the kernel that tracks paths leaving their tet, ms
+                                 (the same steps only) */
     double field_ms;          /* last call: device time of the field update, ms */
     int32_t pcg_iters;        /* last step's PCG iterations (inner iterations in mixed mode) */
     double pcg_relres;        /* last step's final FP64 relative residual */
@@ -332,6 +334,8 @@ typedef struct {
     int64_t a_rows, a_nnz;    /* system matrix A of the field solve: rows (interior W1 DoFs), nonzeros */
     int64_t device_bytes;     /* device memory the run holds now */
     int64_t device_peak_bytes;/* and the most it has held */
+    int64_t phase_replays;    /* last call: steps whose particle phase replayed a captured HIP graph (runs
+                                 of a server, or FEMPIC_PHASE_GRAPHS=1 in the environment) */
 } fempic_stats_t;
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
 
@@ -387,6 +391,7 @@ typedef struct {
     double run_ms;        /* admission -> done */
     const double *step_done_ms; /* [n_steps] completion time of each step, ms since admission */
     int32_t n_steps;
+    const char *message;  /* why the job failed ("" when it did not); owned like the arrays */
 } fempic_job_result;
 
 int32_t fempic_server_create(const fempic_server_params *params, fempic_server *out);

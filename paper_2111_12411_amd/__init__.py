@@ -45,7 +45,7 @@ class Stats(C.Structure):
                 ("pcg_relres", C.c_double), ("crossings", C.c_int64), ("reflections", C.c_int64),
                 ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64),
                 ("a_rows", C.c_int64), ("a_nnz", C.c_int64), ("device_bytes", C.c_int64),
-                ("device_peak_bytes", C.c_int64)]
+                ("device_peak_bytes", C.c_int64), ("phase_replays", C.c_int64)]
 
 
 class ServerParams(C.Structure):
@@ -62,7 +62,8 @@ class JobResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("n1", C.c_int64), ("n2", C.c_int64), ("n", C.c_int64),
                 ("e", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double)), ("pos", C.POINTER(C.c_double)),
                 ("vel", C.POINTER(C.c_double)), ("gauss", C.c_double * 3), ("queue_ms", C.c_double),
-                ("run_ms", C.c_double), ("step_done_ms", C.POINTER(C.c_double)), ("n_steps", C.c_int32)]
+                ("run_ms", C.c_double), ("step_done_ms", C.POINTER(C.c_double)), ("n_steps", C.c_int32),
+                ("message", C.c_char_p)]
 
 
 SYMBOLS = {
@@ -368,7 +369,8 @@ class Server:
         if code == -8:
             return None
         _check(code)
-        out = dict(status=r.status, gauss=list(r.gauss), queue_ms=r.queue_ms, run_ms=r.run_ms)
+        out = dict(status=r.status, gauss=list(r.gauss), queue_ms=r.queue_ms, run_ms=r.run_ms,
+                   message=(r.message or b"").decode(errors="replace"))
         if r.status == 0:
             out["e"] = np.ctypeslib.as_array(r.e, (r.n1,)).copy()
             out["b"] = np.ctypeslib.as_array(r.b, (r.n2,)).copy()

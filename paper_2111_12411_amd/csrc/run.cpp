@@ -69,12 +69,24 @@ thread_local DevAccount *cur_account = nullptr;
 AccountScope::AccountScope(DevAccount *a) : prev(cur_account) { cur_account = a; }
 AccountScope::~AccountScope() { cur_account = prev; }
 
+// HIP calls that act on the whole device (allocation, frees and the device
+// synchronisation before them, stream and pinned-memory creation and
+// destruction, graph instantiation) and stream captures exclude each other
+// across the threads of a process: such a call made while another thread has
+// a capture open on its own stream can invalidate that capture.
+std::mutex &device_mu()
+{
+    static std::mutex mu;
+    return mu;
+}
+
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release()
 {
     if (p && acct) acct->bytes -= bytes;
     acct = nullptr;
     if (p) {
+        std::lock_guard<std::mutex> g(device_mu());
         if (fr) {
             // the caller's allocator may hand the memory out at once, so wait
             // for every queued use first (as hipFree does)
@@ -106,6 +118,7 @@ void DevBuf::alloc(size_t n)
         f = free_fn;
         ctx = alloc_ctx;
     }
+    std::lock_guard<std::mutex> g(device_mu());
     if (a) {
         p = a(n, ctx);
         if (!p) throw Error(FEMPIC_ENOMEM, "the installed allocator failed to provide " + std::to_string(n) + " bytes");
@@ -225,6 +238,7 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
         stream = s;
         own_stream = false;
     } else {
+        std::lock_guard<std::mutex> g(device_mu());
         HIPCHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
         own_stream = true;
     }
@@ -369,12 +383,19 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     p_small = (int32_t *)((char *)d_ctl.p + CTL_SMALL);
     p_perr = (unsigned long long *)((char *)d_ctl.p + CTL_PERR);
     d_cntb.alloc((size_t)CONT_BLOCKS * NCNT * 8);
-    HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
+    {
+        std::lock_guard<std::mutex> g(device_mu());
+        HIPCHECK(hipHostMalloc(&h_pin, 128 + sizeof(ParticleArgs) + 64, hipHostMallocDefault));
+    }
     d_args.alloc(sizeof(ParticleArgs));
     for (auto *ev : {&ev_a, &ev_b, &ev_c1, &ev_c, &ev_d, &ev_e}) HIPCHECK(hipEventCreate(ev));
-    // FEMPIC_GRAPHS=0 launches the PCG batches kernel by kernel instead of replaying graphs
+    // FEMPIC_GRAPHS=0 launches the PCG batches (and the particle phase) kernel by
+    // kernel instead of replaying graphs; FEMPIC_PHASE_GRAPHS=1 replays the
+    // particle phase as graphs (set_phase_graphs; the server's runs always do)
     const char *g = std::getenv("FEMPIC_GRAPHS");
     use_graphs = !(g && std::strcmp(g, "0") == 0);
+    const char *pg = std::getenv("FEMPIC_PHASE_GRAPHS");
+    phase_graphs = pg && std::strcmp(pg, "1") == 0;
     HIPCHECK(hipStreamSynchronize(stream));
 }
 
@@ -382,12 +403,29 @@ Run::~Run()
 {
     if (log) std::fclose(log);
     if (stream) (void)hipStreamSynchronize(stream);
+    clear_phase_graphs();
+    std::lock_guard<std::mutex> g(device_mu());
     for (auto &gx : pcg_graph)
         if (gx) (void)hipGraphExecDestroy(gx);
     for (auto ev : {ev_a, ev_b, ev_c1, ev_c, ev_d, ev_e})
         if (ev) (void)hipEventDestroy(ev);
     if (h_pin) (void)hipHostFree(h_pin);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void Run::clear_phase_graphs()
+{
+    std::lock_guard<std::mutex> g(device_mu());
+    for (auto &kv : phase_graph)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    phase_graph.clear();
+}
+
+void Run::set_phase_graphs(bool on)
+{
+    HIPCHECK(hipStreamSynchronize(stream));
+    phase_graphs = on;
+    if (!on) clear_phase_graphs();
 }
 
 void Run::zero(DevBuf &b)
@@ -457,6 +495,7 @@ std::vector<char> Run::rows_new(const double *pos, const double *vel, int64_t n,
 
 void Run::alloc_particles(int64_t n, int64_t cap_want)
 {
+    clear_phase_graphs();  // they name the old buffers
     np = n;
     np_loaded = n;
     const int64_t cap = std::max<int64_t>({n, cap_want, 1});
@@ -507,6 +546,7 @@ void Run::alloc_sort(SortBuffers &sb, int64_t cap, std::vector<DevBuf> &hold)
 void Run::alloc_pool(int64_t cap)
 {
     if (cap >= (int64_t)SREC_LAST) throw Error(FEMPIC_ENOMEM, "spill pool beyond 2^31 records");
+    clear_phase_graphs();  // they name the old pool
     pool_cap = cap;
     d_pool_val.alloc((size_t)cap * n1l * 8);
     d_pool_pid.alloc((size_t)cap * 4);
@@ -558,7 +598,6 @@ void Run::next_order(int64_t nrec, const uint32_t *srec)
 {
     HIPCHECK(exclusive_scan_u32((const uint32_t *)d_tcnt.p, (uint32_t *)d_noff.p, m.nt, psort.scan_tmp,
                                 (uint32_t *)d_noff.p + m.nt, stream));
-    next_perm = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
     HIPCHECK(launch_place(np, (int32_t)m.nt, tpw(), (const int32_t *)d_off.p, (const uint8_t *)d_moved.p,
                           (const int32_t *)d_soff.p, srec, nrec,
                           (const int32_t *)d_pool_pid.p, pool_cap, (const int32_t *)d_noff.p, next_perm,
@@ -795,10 +834,21 @@ void Run::particle_phase()
     // possible before the first), and the host reads the counts once, at the end
     // of the phase.  A step whose counts exceed the bounds, or that overflows
     // the spill pool, is redone: its input state is untouched until the commit.
-    auto grow = [](int64_t x) { return x + x / 4 + 4096; };
+    // With graphs the bounds are rounded up to at most 4 values per octave, so
+    // that steps with similar counts replay the same graph.
+    auto quant = [](int64_t x) {
+        int e = 0;
+        while ((int64_t)4 << e < x) e++;
+        const int64_t q = std::max<int64_t>((int64_t)1 << e, 1024);
+        return (x + q - 1) / q * q;
+    };
+    const bool graph = phase_graphs && use_graphs && counts_known;
+    auto grow = [&](int64_t x) { return graph ? quant(x + x / 4 + 4096) : x + x / 4 + 4096; };
     int64_t nq_ub = counts_known ? std::min<int64_t>(np, grow(nq_last)) : np;
     int64_t nslot_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nslot_last)) : pool_cap;
     int64_t nrec_ub = counts_known ? std::min<int64_t>(pool_cap, grow(nrec_last)) : pool_cap;
+    const int64_t nq_hint = counts_known ? (graph ? quant(nq_last) : nq_last) : np / 8;
+    next_perm = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
     const int32_t *d_nq = p_small + 6, *d_nrec = p_small + 2;
     for (int attempt = 0;; attempt++) {
         if (attempt == 6) throw Error(FEMPIC_ENOMEM, "spill pool kept overflowing");
@@ -822,31 +872,66 @@ void Run::particle_phase()
         ha->perr = p_perr;
         ha->cntb = (unsigned long long *)d_cntb.p;
         HIPCHECK(hipMemcpyAsync(d_args.p, ha, sizeof(ParticleArgs), hipMemcpyHostToDevice, stream));
-        HIPCHECK(hipEventRecord(ev_b, stream));
-        HIPCHECK(launch_particle(order, mixed, sp.boris != 0, (const ParticleArgs *)d_args.p, (int32_t)m.nt, sp.tpw,
-                                 stream));
-        HIPCHECK(hipEventRecord(ev_c1, stream));
-        // compact the queue written by k_particle, then continue the queued paths
-        HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
-        HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, counts_known ? nq_last : np / 8,
-                                 (unsigned long long *)d_cntb.p, p_cnt, stream));
-        HIPCHECK(hipEventRecord(ev_c, stream));
-        // deterministic reduction of the spill pool: records in canonical order
-        // (queued record, then segment), sorted by tet, summed per tet
-        HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_ub, psort.scan_tmp,
-                                    (uint32_t *)(p_small + 2), stream, d_nq));
-        HIPCHECK(launch_spill_compact(pool(), nslot_ub, d_nq, (const uint32_t *)d_rpos.p, ssort.key[0], ssort.val[0],
-                                      ssort.cap, stream));
-        int res = 0;
-        HIPCHECK(radix_sort(ssort, nrec_ub, key_bits(), false, &res, stream, nullptr, d_nrec));
-        HIPCHECK(launch_offsets(ssort.key[res], nrec_ub, (int32_t)m.nt, (int32_t *)d_soff.p, stream, d_nrec));
-        const uint32_t *srec = ssort.val[res];
-        HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec, (const double *)d_pool_val.p,
-                                     pool_cap, (double *)d_P.p, (const int32_t *)d_nstay.p, (uint32_t *)d_tcnt.p,
-                                     stream));
-        HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int,
-                                (const double *)d_P.p, (double *)d_dg.p, stream));
-        next_order(nrec_ub, srec);
+        // the phase's launches; timed: with events between the particle kernels
+        auto launches = [&](bool timed) {
+            if (timed) HIPCHECK(hipEventRecord(ev_b, stream));
+            HIPCHECK(launch_particle(order, mixed, sp.boris != 0, (const ParticleArgs *)d_args.p, (int32_t)m.nt,
+                                     sp.tpw, stream));
+            if (timed) HIPCHECK(hipEventRecord(ev_c1, stream));
+            // compact the queue written by k_particle, then continue the queued paths
+            HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
+            HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, nq_hint,
+                                     (unsigned long long *)d_cntb.p, p_cnt, stream));
+            if (timed) HIPCHECK(hipEventRecord(ev_c, stream));
+            // deterministic reduction of the spill pool: records in canonical order
+            // (queued record, then segment), sorted by tet, summed per tet
+            HIPCHECK(exclusive_scan_u32((const uint32_t *)d_rcount.p, (uint32_t *)d_rpos.p, nq_ub, psort.scan_tmp,
+                                        (uint32_t *)(p_small + 2), stream, d_nq));
+            HIPCHECK(launch_spill_compact(pool(), nslot_ub, d_nq, (const uint32_t *)d_rpos.p, ssort.key[0],
+                                          ssort.val[0], ssort.cap, stream));
+            int res = 0;
+            HIPCHECK(radix_sort(ssort, nrec_ub, key_bits(), false, &res, stream, nullptr, d_nrec));
+            HIPCHECK(launch_offsets(ssort.key[res], nrec_ub, (int32_t)m.nt, (int32_t *)d_soff.p, stream, d_nrec));
+            const uint32_t *srec = ssort.val[res];
+            HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec,
+                                         (const double *)d_pool_val.p, pool_cap, (double *)d_P.p,
+                                         (const int32_t *)d_nstay.p, (uint32_t *)d_tcnt.p, stream));
+            HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int,
+                                    (const double *)d_P.p, (double *)d_dg.p, stream));
+            next_order(nrec_ub, srec);
+        };
+        phase_timed = !(graph && attempt == 0);
+        if (phase_timed) {
+            launches(true);
+        } else {
+            // kernels only; their launch parameters are all in the key
+            const std::vector<int64_t> key{cur, (int64_t)(uintptr_t)cur_perm, (int64_t)(uintptr_t)next_perm,
+                                           (int64_t)(uintptr_t)d_off.p, (int64_t)(uintptr_t)d_noff.p, nq_ub, nslot_ub,
+                                           nrec_ub, nq_hint, np, sp.tpw, pool_cap};
+            auto it = phase_graph.find(key);
+            if (it == phase_graph.end()) {
+                // keep few: a new set of bounds usually retires the older ones
+                if (phase_graph.size() >= 8) clear_phase_graphs();
+                std::lock_guard<std::mutex> lk(device_mu());  // (see device_mu)
+                hipGraph_t g = nullptr;
+                HIPCHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+                try {
+                    launches(false);
+                } catch (...) {
+                    (void)hipStreamEndCapture(stream, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HIPCHECK(hipStreamEndCapture(stream, &g));
+                hipGraphExec_t gx = nullptr;
+                const hipError_t e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess)
+                    throw Error(FEMPIC_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                it = phase_graph.emplace(key, gx).first;
+            }
+            HIPCHECK(hipGraphLaunch(it->second, stream));
+        }
         HIPCHECK(hipEventRecord(ev_d, stream));
         HIPCHECK(hipMemcpyAsync(h_pin, d_ctl.p, CTL_BYTES, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
@@ -1016,6 +1101,7 @@ void Run::pcg_batch(bool fp32)
     if (!use_graphs) return launch();
     hipGraphExec_t &gx = pcg_graph[fp32 ? 1 : 0];
     if (!gx) {
+        std::lock_guard<std::mutex> g(device_mu());  // (see device_mu)
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         try {
@@ -1179,6 +1265,7 @@ void Run::step(int n_steps)
     if (!loaded) throw Error(FEMPIC_EINVAL, "no particles loaded");
     if (sticky) throw Error(sticky, sticky_msg);
     double pms = 0, kms = 0, cms = 0, fms = 0;
+    int64_t replays = 0;
     try {
         for (int s = 0; s < n_steps; s++) {
             Range rg("fempic step");
@@ -1187,8 +1274,12 @@ void Run::step(int n_steps)
             HIPCHECK(hipEventSynchronize(ev_e));
             float t1 = 0, t2 = 0, t3 = 0, t4 = 0;
             HIPCHECK(hipEventElapsedTime(&t1, ev_a, ev_d));
-            HIPCHECK(hipEventElapsedTime(&t2, ev_b, ev_c1));
-            HIPCHECK(hipEventElapsedTime(&t4, ev_c1, ev_c));
+            if (phase_timed) {  // (a replayed phase graph has no events between its kernels)
+                HIPCHECK(hipEventElapsedTime(&t2, ev_b, ev_c1));
+                HIPCHECK(hipEventElapsedTime(&t4, ev_c1, ev_c));
+            } else {
+                replays++;
+            }
             HIPCHECK(hipEventElapsedTime(&t3, ev_d, ev_e));
             pms += t1;
             kms += t2;
@@ -1207,6 +1298,7 @@ void Run::step(int n_steps)
         throw;
     }
     last_particle_ms = pms;
+    last_phase_replays = replays;
     last_kernel_ms = kms;
     last_continue_ms = cms;
     last_field_ms = fms;
@@ -2298,6 +2390,7 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.a_nnz = r.a_nnz;
     s.device_bytes = (int64_t)r.account().bytes;
     s.device_peak_bytes = (int64_t)r.account().peak;
+    s.phase_replays = r.last_phase_replays;
     *out = s;
     API_END
 }

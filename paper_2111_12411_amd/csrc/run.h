@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -99,6 +100,9 @@ class Run {
     void restore(const char *path);
     void set_log(const char *path);
     static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
+    // replay the particle phase's launches as HIP graphs (see particle_phase);
+    // its per-kernel times are then not measured
+    void set_phase_graphs(bool on);
     // refuse (ENOMEM) any allocation that would take the run's device bytes past `bytes` (0: no cap)
     void set_byte_limit(size_t bytes) { acct.limit = bytes; }
     const DevAccount &account() const { return acct; }
@@ -120,6 +124,7 @@ class Run {
     int64_t last_absorb = 0, absorbed_total = 0;
     double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
+    int64_t last_phase_replays = 0;
     int64_t nnz_total = 0, a_nnz = 0;
     double gauss_last[3] = {0, 0, 0};  // the last evaluation that params.gauss_every asked for
     int64_t gauss_step = 0;
@@ -172,6 +177,12 @@ class Run {
     void pcg_batch(bool fp32);
     bool use_graphs = true;
     hipGraphExec_t pcg_graph[2] = {nullptr, nullptr};
+    // the particle phase's launches, from k_particle to the next order, as graphs
+    // keyed by everything their launch parameters depend on (buffers of the
+    // alternating step parity, launch bounds, counts)
+    bool phase_graphs = false, phase_timed = true;
+    std::map<std::vector<int64_t>, hipGraphExec_t> phase_graph;
+    void clear_phase_graphs();
 
     DevBuf d_geo, d_nbr, d_map1, d_map2, d_map0;
     DevCSRBuf A, Meps, Mnu, K, Kt, Gt;

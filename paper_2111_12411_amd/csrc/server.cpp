@@ -14,6 +14,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -34,6 +35,7 @@ struct Job {
     int32_t status = FEMPIC_EAGAIN;
     bool done = false;
     std::vector<double> e, b, rpos, rvel, step_ms;
+    std::string message;  // why it failed
     double gauss[3] = {0, 0, 0};
 };
 
@@ -65,10 +67,13 @@ struct fempic_server_s {
     {
         (void)hipSetDevice(device);
         int32_t st = FEMPIC_OK;
+        std::string msg;
         try {
             std::shared_ptr<const HostMesh> mesh(build_cube(j->spec.N, j->spec.L, j->spec.order));
             // the run may not grow past what the job was admitted with
             Run run(mesh, j->spec.params, nullptr, j->footprint);
+            // small runs are launch-bound: their particle phases replay graphs
+            run.set_phase_graphs(true);
             run.load(j->pos.data(), j->vel.data(), j->spec.n, j->spec.q, j->spec.m, j->spec.w);
             for (int s = 0; s < j->spec.n_steps; s++) {
                 run.step(1);
@@ -83,11 +88,14 @@ struct fempic_server_s {
             run.particles_get(j->rpos.data(), j->rvel.data(), nullptr, j->spec.n);
         } catch (const Error &e) {
             st = e.code;
+            msg = e.what();
         } catch (...) {
             st = FEMPIC_EDEVICE;
+            msg = "unknown failure";
         }
         std::lock_guard<std::mutex> lk(mu);
         j->status = st;
+        j->message = msg;
         j->t_done = clk::now();
         j->done = true;
         j->pos.clear();
@@ -228,6 +236,7 @@ int32_t fempic_poll(fempic_server s, int64_t ticket, fempic_job_result *out)
     r.run_ms = std::chrono::duration<double, std::milli>(j.t_done - j.t_admit).count();
     r.step_done_ms = j.step_ms.data();
     r.n_steps = (int32_t)j.step_ms.size();
+    r.message = j.message.c_str();
     *out = r;
     return FEMPIC_OK;
     API_CATCH
