@@ -313,6 +313,37 @@ def mass1_tensor(k):
     return C
 
 
+def face_monomial_integral(alpha, o):
+    """int_F l^alpha dS / (2 A) over the face F opposite local vertex o, where l_o = 0:
+    alpha! / (|alpha| + 2)! over the three face coordinates (textbook formula), 0 if alpha_o > 0."""
+    if alpha[o] > 0:
+        return Fraction(0)
+    num = 1
+    for a in alpha:
+        num *= factorial(a)
+    return Fraction(num, factorial(sum(alpha) + 2))
+
+
+@lru_cache(maxsize=None)
+def face_mass1_tensor(k):
+    """F1[o,i,j,m,n] with int_F W1_i . P W1_j dS = 2 A sum_{mn} F1[o,i,j,m,n] (grad l_m . P grad l_n)
+    over the face F opposite local vertex o, for any 3x3 matrix P (the tangential projector
+    I - n n^T gives the surface impedance matrix)."""
+    phis = w1_grad_coeffs(k)
+    n1 = len(phis)
+    C = np.zeros((4, n1, n1, 4, 4))
+    for o in range(4):
+        for i in range(n1):
+            for j in range(n1):
+                for m in range(4):
+                    for n in range(4):
+                        if phis[i][m] and phis[j][n]:
+                            p = _pmul(phis[i][m], phis[j][n])
+                            C[o, i, j, m, n] = float(sum((c * face_monomial_integral(mo, o) for mo, c in p.items()),
+                                                         Fraction(0)))
+    return C
+
+
 @lru_cache(maxsize=None)
 def mass2_tensor(k):
     """C2[l,l',p,q] with int_T W2_l . W2_l' = 6V sum_{pq} C2 * (g_p . g_q), g_p = grad l_m x grad l_n."""

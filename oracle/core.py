@@ -17,7 +17,9 @@ average-acceleration scheme is the trapezoidal rule; eliminating b^{n+1}:
   A (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - (g^{n+1} - g^n),
   A = *eps + dt^2/4 K^T *nu K,
   b^{n+1} = b^n - dt/2 K (e^n + e^{n+1}).
-Only the W1 DoFs off the PEC walls are unknowns (n x E = 0 on the walls).
+Only the W1 DoFs off the PEC walls are unknowns (n x E = 0 on the walls); with
+absorbing walls every W1 DoF is, and the surface impedance matrix enters
+Ampere's law (see OracleRun).
 Gauss's law: with G the local gradient matrix (grad W0 = sum G W1) and K G = 0,
 G^T (*eps e + g) is invariant, and the exact path integral gives
 G^T (g^{n} - g^0) = rho~^n - rho~^0 where rho~_j = q w sum_p W0_j(r_p).
@@ -73,6 +75,36 @@ def assemble(m):
     return ops
 
 
+def surface_impedance(m, Y):
+    """[*I]_ij = Y int_{walls} (n x W1_i) . (n x W1_j) dS (Sec. III-A, surface impedance matrix),
+    natural numbering, n1 x n1.  (n x u) . (n x v) = u . (I - n n^T) v; W1 = sum_m phi^m grad l_m
+    with the face integrals of phi_i^m phi_j^n exact (face_mass1_tensor).  Y is the wall
+    admittance: 1 / eta0 for the first-order absorbing condition."""
+    k = m.order
+    F1 = basis.face_mass1_tensor(k)
+    rows, cols, vals = [], [], []
+    n1l = m.map1.shape[1]
+    for t in range(m.nt):
+        for lf in range(4):
+            if not m.bface[m.tet_face[t, lf]]:
+                continue
+            o = 3 - lf  # the face opposite local vertex o
+            a, b, c = m.tets[t, list(omesh.LOCAL_FACES[lf])]
+            xa, xb, xc = m.xyz[a], m.xyz[b], m.xyz[c]
+            nrm = np.cross(xb - xa, xc - xa)
+            area = 0.5 * np.linalg.norm(nrm)
+            nu = nrm / np.linalg.norm(nrm)
+            P = np.eye(3) - np.outer(nu, nu)
+            gPg = m.grad[t] @ P @ m.grad[t].T  # (4,4): grad l_m . P grad l_n
+            el = Y * 2.0 * area * np.einsum("ijmn,mn->ij", F1[o], gPg)
+            rows.append(np.repeat(m.map1[t], n1l))
+            cols.append(np.tile(m.map1[t], n1l))
+            vals.append(el.ravel())
+    if not rows:
+        return sps.csr_matrix((m.n1, m.n1))
+    return sps.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(m.n1, m.n1))
+
+
 def _assign(loc, rmap, cmap, n_r, n_c):
     """Global matrix whose (rmap[t,i], cmap[t,j]) entry is loc[i,j] for every tet t;
     every tet that touches an entry must give the same value."""
@@ -113,12 +145,18 @@ class OracleRun:
     of the scheme for M dX/dt + S X = F (field_step_newmark)."""
 
     def __init__(self, m, dt, ops=None, particles_only=False, gamma=0.5, beta=0.25, three_level=False,
-                 absorb=False, pusher="ab4"):
+                 absorb=False, pusher="ab4", field_bc="pec"):
         """particles_only: skip the field operators (particle steps with given fields).
         absorb: a particle that reaches a wall deposits its current up to the wall and leaves the
         run (tet -1); otherwise walls reflect.
         pusher: "ab4" (the paper's fourth-order Adams-Bashforth push, quartic path) or "boris"
-        (Boris leapfrog, straight path; the stored velocity is then v^{n-1/2})."""
+        (Boris leapfrog, straight path; the stored velocity is then v^{n-1/2}).
+        field_bc: "pec" (n x E = 0 on the walls: the wall W1 DoFs are not unknowns) or
+        "absorbing": the impedance condition of Sec. II with Psi_I = 0 and the free-space wall
+        admittance Y = 1/eta0 (the first-order absorbing condition); every W1 DoF is an unknown and
+        the surface impedance matrix *I enters Ampere's law as  *eps de/dt + *I e = K^T *nu b - dg/dt
+        (Sec. III-A), trapezoidal in time like the rest:
+          (A + dt/2 *I) (e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n) - dt *I e^n - (g^{n+1} - g^n)."""
         self.m = m
         self.absorb = 1 if absorb else 0
         self.pusher = {"ab4": 0, "boris": 1}[pusher]
@@ -129,12 +167,23 @@ class OracleRun:
         self.three_level = three_level or (gamma, beta) != (0.5, 0.25)
         self.lu3 = None
         self.prev = None  # (b^{n-1}, e^{n-1}, g^{n-1}) of the three-level scheme
+        self.field_bc = field_bc
+        if field_bc not in ("pec", "absorbing"):
+            raise ValueError("field_bc must be 'pec' or 'absorbing'")
+        if field_bc == "absorbing" and self.three_level:
+            raise NotImplementedError("absorbing walls with the two-level trapezoidal scheme only")
         if not particles_only:
             self.ops = ops if ops is not None else assemble(m)
             o = self.ops
-            i1 = o.int1
+            # the unknown W1 DoFs: off the walls (PEC), or all of them (absorbing)
+            self.i1 = o.int1 if field_bc == "pec" else np.arange(m.n1)
+            i1 = self.i1
             self.Ki = o.K[:, i1].tocsr()
             self.A = (o.star_eps[i1][:, i1] + (dt * dt / 4.0) * (self.Ki.T @ o.star_nu @ self.Ki)).tocsc()
+            self.ZI = None
+            if field_bc == "absorbing":
+                self.ZI = surface_impedance(m, np.sqrt(EPS0 / MU0))
+                self.A = (self.A + (dt / 2.0) * self.ZI).tocsc()
         self.tables = basis.c_tables(self.k)
         self.gl = basis.gauss_legendre01(2 * self.k + 2)
         self.cm = cloop.CMesh(m, self.tables, self.gl)
@@ -213,9 +262,11 @@ class OracleRun:
 
     # ---------------------------------------------------------------- fields
     def field_step(self, dg):
-        o, dt, i1 = self.ops, self.dt, self.ops.int1
+        o, dt, i1 = self.ops, self.dt, self.i1
         ei = self.e[i1]
         rhs = dt * (self.Ki.T @ (o.star_nu @ (self.b - 0.5 * dt * (self.Ki @ ei)))) - dg[i1]
+        if self.ZI is not None:
+            rhs = rhs - dt * (self.ZI @ ei)
         if self.lu is None:
             self.lu = spla.splu(self.A)
         d = self.lu.solve(rhs)
