@@ -51,6 +51,15 @@ extern "C" {
 #define FEMPIC_PUSH_BORIS 1 /* Boris leapfrog, straight path (the push is de-linked from
                                the current mapping, Sec. III-B); velocities are v^{n-1/2} */
 
+#define FEMPIC_FIELD_PEC 0    /* walls are perfect conductors: n x E = 0 (Sec. II, Dirichlet
+                                 condition), the wall W1 DoFs are not unknowns */
+#define FEMPIC_FIELD_ABSORB 1 /* first-order absorbing walls: the impedance condition of
+                                 Sec. II with Psi_I = 0 and the free-space admittance
+                                 Y = 1/eta0; every W1 DoF is an unknown and the surface
+                                 impedance matrix of Sec. III-A,
+                                 [*I]_ij = Y int_walls (n x W1_i) . (n x W1_j) dS,
+                                 enters Ampere's law: *eps de/dt + *I e = K^T *nu b - dg/dt */
+
 #define FEMPIC_REFLECT 0 /* particles reflect specularly at PEC walls */
 #define FEMPIC_ABSORB 1  /* a particle that reaches a wall deposits its current up to
                             the wall and leaves the run there */
@@ -95,7 +104,8 @@ int32_t fempic_mesh_destroy(fempic_mesh mesh);
 
 typedef struct {
     int64_t n_vert, n_edge, n_face, n_tet;
-    int64_t n1, n1_int; /* W1 DoFs: all / off the PEC walls (the unknowns)  */
+    int64_t n1, n1_int; /* W1 DoFs: all / off the walls (the unknowns with PEC walls;
+                           with absorbing walls all n1 are)                  */
     int64_t n2;         /* W2 DoFs                                           */
     int64_t n0, n0_int; /* W0 DoFs: all / interior (Gauss-law check rows)    */
     int32_t order, n1_loc, n2_loc, n0_loc;
@@ -145,6 +155,12 @@ typedef struct {
                             loaded velocity is taken as v^{-1/2}, the step moves
                             along the straight path r^n + s dt v^{n+1/2} and deposits
                             its exact path integral, and fempic_history_get is EINVAL */
+    int32_t field_bc;    /* FEMPIC_FIELD_PEC (0) or FEMPIC_FIELD_ABSORB; absorbing walls
+                            need gamma, beta = 1/2, 1/4 (EINVAL otherwise) and are
+                            stepped by the trapezoidal rule like the rest:
+                            (A + dt/2 *I)(e^{n+1} - e^n) = dt K^T *nu (b^n - dt/2 K e^n)
+                            - dt *I e^n - (g^{n+1} - g^n).  Gauss's law on the interior
+                            nodes is unchanged (*I G = 0 there) */
 } fempic_params;
 
 int32_t fempic_run_create(fempic_mesh mesh, const fempic_params *params, void *hip_stream, fempic_run *out);
@@ -210,14 +226,16 @@ int32_t fempic_gauss_residual(fempic_run run, double out[3]);
  * library, 96 MiB on every device it runs on, held until the process ends.
  * Nothing is allocated: no hipMalloc, no installed allocator, no library
  * routine that allocates.  EINVAL when the run's mesh needs more scratch than
- * that (8 n_tet n0_loc + 24 n0_int + 16 n1_int bytes and 64 KiB: up to about the
+ * that (8 n_tet n0_loc + 24 n0_int + 16 n1_int bytes, n1 in place of n1_int
+ * with absorbing walls, and 64 KiB: up to about the
  * 40^3 cube at order 2).  Every call on a device shares that device's array, so
  * calls that overlap on one device (runs on different streams or threads) race
  * and must be serialised by the caller.  Synchronises the run's stream. */
 int32_t fempic_gauss_residual_noalloc(fempic_run run, double out[3]);
 
 /* Copy fields out / in (natural numbering; e has n1 entries, b has n2).
- * fields_set zeroes e on the PEC walls; EINVAL for a non-finite coefficient. */
+ * fields_set zeroes e on PEC walls (absorbing walls keep it); EINVAL for a
+ * non-finite coefficient. */
 int32_t fempic_fields_get(fempic_run run, double *e, int64_t ne, double *b, int64_t nb);
 int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const double *b, int64_t nb);
 
@@ -348,7 +366,10 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
  * fempic_footprint: for a mesh of n_tet tets whose entity counts are those of a
  *   Kuhn cube with 6 N^3 = n_tet (exact for such cubes).  EINVAL for order not
  *   1|2, n_tet < 1, n_particles < 0 or an unknown precision.
- * fempic_footprint_mesh: the same from the counts of a built mesh. */
+ * fempic_footprint_mesh: the same from the counts of a built mesh.
+ * Both assume PEC walls; with absorbing walls (params.field_bc) the wall W1
+ * DoFs are unknowns too and the run holds their solver vectors and the surface
+ * impedance matrix as well (the server budgets that). */
 int32_t fempic_footprint(int32_t order, int64_t n_tet, int64_t n_particles, int32_t precision, size_t *bytes);
 int32_t fempic_footprint_mesh(fempic_mesh mesh, int64_t n_particles, int32_t precision, size_t *bytes);
 

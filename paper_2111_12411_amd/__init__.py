@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfempic.so")
 FP64, MIXED = 0, 1
 REFLECT, ABSORB = 0, 1
 PUSH_AB4, PUSH_BORIS = 0, 1
+FIELD_PEC, FIELD_ABSORB = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "EOUTSIDE", -5: "ECROSS", -6: "ESOLVE",
           -7: "EDEVICE", -8: "EAGAIN", -9: "EBUSY"}
 
@@ -35,7 +36,8 @@ class MeshInfo(C.Structure):
 class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("dt", C.c_double), ("gamma", C.c_double), ("beta", C.c_double),
                 ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32), ("particle_bc", C.c_int32),
-                ("spill_slots", C.c_int32), ("gauss_every", C.c_int32), ("pusher", C.c_int32)]
+                ("spill_slots", C.c_int32), ("gauss_every", C.c_int32), ("pusher", C.c_int32),
+                ("field_bc", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -176,8 +178,8 @@ class Mesh:
 
 
 def params(dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, gauss_every=0, gamma=0.5, beta=0.25,
-           particle_bc=0, pusher=0):
-    return Params(precision, dt, gamma, beta, pcg_rtol, pcg_maxit, particle_bc, 0, gauss_every, pusher)
+           particle_bc=0, pusher=0, field_bc=0):
+    return Params(precision, dt, gamma, beta, pcg_rtol, pcg_maxit, particle_bc, 0, gauss_every, pusher, field_bc)
 
 
 def footprint(order, n_tet, n_particles, precision=FP64):
@@ -234,11 +236,11 @@ class Run:
     """One simulation on the current HIP device."""
 
     def __init__(self, mesh, dt, precision=FP64, pcg_rtol=1e-13, pcg_maxit=20000, stream=None, gauss_every=0,
-                 gamma=0.5, beta=0.25, particle_bc=0, pusher=PUSH_AB4):
+                 gamma=0.5, beta=0.25, particle_bc=0, pusher=PUSH_AB4, field_bc=FIELD_PEC):
         self.mesh = mesh
         self.info = mesh.info()
         self.h = C.c_void_p()
-        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every, gamma, beta, particle_bc, pusher)
+        p = params(dt, precision, pcg_rtol, pcg_maxit, gauss_every, gamma, beta, particle_bc, pusher, field_bc)
         _check(lib().fempic_run_create(mesh.h, C.byref(p), stream, C.byref(self.h)))
         self.n = 0
 

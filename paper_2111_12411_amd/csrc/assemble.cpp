@@ -16,6 +16,7 @@
 #include <functional>
 #include <memory>
 #include <thread>
+#include <tuple>
 
 #include "fempic_impl.h"
 
@@ -286,11 +287,88 @@ double cfl_bound(const HostMesh &m)
     return 2.0 / std::sqrt(lmax);
 }
 
-void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
+// Surface impedance matrix [*I]_ij = Y int_walls (n x W1_i) . (n x W1_j) dS
+// (Sec. III-A) over the first n1s internal W1 DoFs: per wall face of a tet,
+// (n x u) . (n x v) = u . (I - n n^T) v and W1 = sum_m phi^m grad l_m, so the
+// face's element matrix is Y A sum_mn F1[o][i][j][m][n] (grad l_m . P grad l_n)
+// with o the vertex opposite the face and A its area.
+void surface_impedance(const HostMesh &m, const RefElem &R, int64_t n1s, double Y, CSR &Z)
+{
+    const int n1 = R.n1;
+    std::vector<std::tuple<int32_t, int32_t, double>> trip;
+    std::vector<double> el(n1 * n1);
+    for (int64_t t = 0; t < m.nt; t++)
+        for (int lf = 0; lf < 4; lf++) {
+            if (!m.bface[m.tet_face[4 * t + lf]]) continue;
+            const int o = 3 - lf;  // local face lf lies opposite vertex 3 - lf
+            const double *g = &m.geo[16 * t];
+            const double *gn = g + 4 * o + 1;
+            const double gg = gn[0] * gn[0] + gn[1] * gn[1] + gn[2] * gn[2];
+            double e1[3], e2[3], cr[3];
+            const int32_t *tv = &m.tets[4 * t];
+            const int va = tv[LOC_FACE[lf][0]], vb = tv[LOC_FACE[lf][1]], vc = tv[LOC_FACE[lf][2]];
+            for (int c = 0; c < 3; c++) {
+                e1[c] = m.xyz[3 * vb + c] - m.xyz[3 * va + c];
+                e2[c] = m.xyz[3 * vc + c] - m.xyz[3 * va + c];
+            }
+            cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            // grad l_m . P grad l_n with P = I - n n^T, n along grad l_o
+            double gpg[4][4];
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    const double *ga = g + 4 * a + 1, *gb = g + 4 * b + 1;
+                    const double d = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                    const double na = ga[0] * gn[0] + ga[1] * gn[1] + ga[2] * gn[2];
+                    const double nb = gb[0] * gn[0] + gb[1] * gn[1] + gb[2] * gn[2];
+                    gpg[a][b] = d - na * nb / gg;
+                }
+            const double *F = &R.F1[(size_t)o * n1 * n1 * 16];
+            for (int i = 0; i < n1; i++)
+                for (int j = 0; j < n1; j++) {
+                    double v = 0.0;
+                    for (int a = 0; a < 4; a++)
+                        for (int b = 0; b < 4; b++) v += F[((size_t)(i * n1 + j) * 4 + a) * 4 + b] * gpg[a][b];
+                    el[i * n1 + j] = Y * area * v;
+                }
+            for (int i = 0; i < n1; i++) {
+                const int32_t r = m.map1[t * n1 + i];
+                if (r >= n1s) continue;
+                for (int j = 0; j < n1; j++) {
+                    const int32_t c = m.map1[t * n1 + j];
+                    if (c < n1s && el[i * n1 + j] != 0.0) trip.emplace_back(r, c, el[i * n1 + j]);
+                }
+            }
+        }
+    std::sort(trip.begin(), trip.end(), [](const auto &x, const auto &y) {
+        return std::get<0>(x) != std::get<0>(y) ? std::get<0>(x) < std::get<0>(y) : std::get<1>(x) < std::get<1>(y);
+    });
+    Z.rows = Z.cols = n1s;
+    Z.ptr.assign(n1s + 1, 0);
+    Z.idx.clear();
+    Z.val.clear();
+    for (size_t k = 0; k < trip.size(); k++) {
+        const auto [r, c, v] = trip[k];
+        if (!Z.idx.empty() && k > 0 && std::get<0>(trip[k - 1]) == r && Z.idx.back() == c) {
+            Z.val.back() += v;  // faces of a tet share DoFs on their common edge
+        } else {
+            Z.idx.push_back(c);
+            Z.val.push_back(v);
+            Z.ptr[r + 1]++;
+        }
+    }
+    for (int64_t r = 0; r < n1s; r++) Z.ptr[r + 1] += Z.ptr[r];
+}
+
+void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2, bool absorbing)
 {
     const RefElem &R = ref_elem(m.order);
     const int n1 = R.n1, n2 = R.n2, n0 = R.n0;
-    const int64_t N1i = m.N1_int, N0i = m.N0_int, nt = m.nt;
+    // the unknown W1 DoFs (see Operators): the internal numbering puts the wall ones last
+    const int64_t N1i = absorbing ? m.N1 : m.N1_int, N0i = m.N0_int, nt = m.nt;
+    ops.n1s = N1i;
     auto w1int = [&](int64_t t, int i) -> int64_t {
         int32_t d = m.map1[t * n1 + i];
         return d < N1i ? d : -1;
@@ -352,6 +430,19 @@ void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2)
     RowInc r0 = row_incidence(m, N0i, n0, w0int);
     build_csr(r0, N0i, N1i, n0, n1, w1int, Gt.data(), [&](int64_t, int j, int i) { return Gt[j * n1 + i]; }, true,
               ops.Gt);
+    ops.Z = CSR{};
+    if (absorbing) {
+        // wall admittance of free space; the step takes the impedance term at
+        // the half step, as it takes the curl-curl one
+        surface_impedance(m, R, N1i, std::sqrt(EPS0 / MU0), ops.Z);
+        for (int64_t r = 0; r < N1i; r++)
+            for (int64_t k = ops.Z.ptr[r]; k < ops.Z.ptr[r + 1]; k++) {
+                const int32_t *b = ops.A.idx.data() + ops.A.ptr[r], *e = ops.A.idx.data() + ops.A.ptr[r + 1];
+                const int32_t *p = std::lower_bound(b, e, ops.Z.idx[k]);
+                if (p == e || *p != ops.Z.idx[k]) throw Error(FEMPIC_EMESH, "impedance entry outside the field matrix");
+                ops.A.val[p - ops.A.idx.data()] += 0.5 * dt * ops.Z.val[k];
+            }
+    }
     ops.Adiag_inv.assign(N1i, 0.0);
     for (int64_t r = 0; r < N1i; r++) {
         const int32_t *b = ops.A.idx.data() + ops.A.ptr[r], *e = ops.A.idx.data() + ops.A.ptr[r + 1];

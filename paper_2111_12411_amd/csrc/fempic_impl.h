@@ -40,6 +40,7 @@ struct RefElem {
     std::vector<double> K;   // [n2][n1]  curl W1_j = sum_l K[l][j] W2_l
     std::vector<double> C1;  // [n1][n1][4][4] (1/6V) int phi_i^m phi_j^n
     std::vector<double> C2;  // [n2][n2][6][6]
+    std::vector<double> F1;  // [4][n1][n1][4][4] (1/A) int over the face opposite vertex o of phi_i^m phi_j^n
     std::vector<double> glx, glw;  // Gauss-Legendre on [0,1], 2k+2 points
 };
 const RefElem &ref_elem(int order);
@@ -84,18 +85,22 @@ struct CSR {
     int64_t nnz() const { return (int64_t)idx.size(); }
 };
 
+// The unknown W1 DoFs are the first n1s of the internal numbering: those off
+// the walls (N1_int) with PEC walls, all of them (N1) with absorbing walls.
 struct Operators {
-    CSR A;      // *eps + c dt^2 K^T *nu K   (N1_int x N1_int)
-    CSR Meps;   // *eps                      (N1_int x N1_int)
+    int64_t n1s = 0;
+    CSR A;      // *eps + c dt^2 K^T *nu K (+ dt/2 *I)   (n1s x n1s)
+    CSR Meps;   // *eps                      (n1s x n1s)
     CSR Mnu;    // *nu                       (N2 x N2)
-    CSR K;      // curl                      (N2 x N1_int)
-    CSR Kt;     // K^T                       (N1_int x N2)
-    CSR Gt;     // gscale G^T                (N0_int x N1_int)
+    CSR K;      // curl                      (N2 x n1s)
+    CSR Kt;     // K^T                       (n1s x N2)
+    CSR Gt;     // gscale G^T                (N0_int x n1s)
+    CSR Z;      // surface impedance *I      (n1s x n1s; absorbing walls only, else empty)
     // the smallest integer that makes every entry of G an integer (1 at order 1,
     // 3 at order 2): products with gscale G^T are then exact in double-double
     double gscale = 1.0;
     std::vector<double> Adiag_inv;
-    // deposit scatter: for interior W1 DoF j, the (tet*n1l + local) slots in tet order
+    // deposit scatter: for unknown W1 DoF j, the (tet*n1l + local) slots in tet order
     std::vector<int64_t> inc_ptr;
     std::vector<int32_t> inc_idx;
     // nodal scatter for rho~: interior W0 DoF j -> (tet*n0l + local)
@@ -103,8 +108,10 @@ struct Operators {
     std::vector<int32_t> inc0_idx;
 };
 
-// A = *eps + c_dt2 dt^2 K^T *nu K (c_dt2 = (beta / gamma)^2 of the Newmark-beta scheme)
-void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2 = 0.25);
+// A = *eps + c_dt2 dt^2 K^T *nu K (c_dt2 = (beta / gamma)^2 of the Newmark-beta scheme);
+// absorbing: every W1 DoF is an unknown and A gains dt/2 *I (Sec. III-A) with the
+// wall admittance 1/eta0
+void assemble(const HostMesh &m, double dt, Operators &ops, double c_dt2 = 0.25, bool absorbing = false);
 
 // Operators of the impressed-field projection (Sec. III-C): the curl over every
 // W1 DoF, walls included (N2 x N1) and its transpose, and the face DoF ->
@@ -128,6 +135,7 @@ void impressed_rule(int n, std::vector<double> &lam, std::vector<double> &w);
 struct FootprintSizes {
     int order;
     int64_t nt, n1, n1_int, n2, n0_int;
+    bool absorbing = false;  // absorbing walls: all n1 W1 DoFs are unknowns, plus *I
 };
 size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed);
 // sizes of the N^3 Kuhn cube with nt = 6 N^3 tets, N taken real (totals stand in for interior counts)

@@ -303,6 +303,41 @@ RefElem make(int k)
                     for (int r = 0; r < 6; r++)
                         R.C2[((size_t)(i * R.n2 + j) * 6 + p) * 6 + r] += qw[q] * psi[6 * i + p] * psi[6 * j + r];
     }
+    // face tensors: (1/A) int over the face opposite vertex o of phi_i^m phi_j^n,
+    // on a collapsed Gauss rule of the triangle (exact for degree 2k)
+    {
+        std::vector<double> gx, gw;
+        gauss_legendre01(k + 2, gx, gw);
+        R.F1.assign((size_t)4 * R.n1 * R.n1 * 16, 0.0);
+        std::vector<double> phi1(R.n1 * 4);
+        for (int o = 0; o < 4; o++) {
+            int fv[3], c = 0;
+            for (int v = 0; v < 4; v++)
+                if (v != o) fv[c++] = v;
+            double *F = &R.F1[(size_t)o * R.n1 * R.n1 * 16];
+            for (size_t a = 0; a < gx.size(); a++)
+                for (size_t b = 0; b < gx.size(); b++) {
+                    // (u, v) on the square onto the triangle; the average over it has weight 2 (1-u)
+                    const double u = gx[a], v = gx[b], wq = 2.0 * gw[a] * gw[b] * (1.0 - u);
+                    double l[4] = {0, 0, 0, 0};
+                    l[fv[0]] = u;
+                    l[fv[1]] = v * (1.0 - u);
+                    l[fv[2]] = (1.0 - u) * (1.0 - v);
+                    std::fill(phi1.begin(), phi1.end(), 0.0);
+                    for (int i = 0; i < R.n1; i++) {
+                        const W1Fn &f = R.w1[i];
+                        const double Q = qv_of(f.qv, f.qs, f.qc, l);
+                        phi1[4 * i + f.b] += Q * l[f.a];
+                        phi1[4 * i + f.a] -= Q * l[f.b];
+                    }
+                    for (int i = 0; i < R.n1; i++)
+                        for (int j = 0; j < R.n1; j++)
+                            for (int m = 0; m < 4; m++)
+                                for (int n = 0; n < 4; n++)
+                                    F[((size_t)(i * R.n1 + j) * 4 + m) * 4 + n] += wq * phi1[4 * i + m] * phi1[4 * j + n];
+                }
+        }
+    }
     gauss_legendre01(2 * k + 2, R.glx, R.glw);
     return R;
 }

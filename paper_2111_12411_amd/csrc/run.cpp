@@ -284,8 +284,11 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     // operators
     Operators ops;
     three_level = !(p.gamma == 0.5 && p.beta == 0.25);
-    assemble(m, p.dt, ops, (p.beta / p.gamma) * (p.beta / p.gamma));
+    absorbing = p.field_bc == FEMPIC_FIELD_ABSORB;
+    assemble(m, p.dt, ops, (p.beta / p.gamma) * (p.beta / p.gamma), absorbing);
+    n1s = ops.n1s;
     upload_csr(A, ops.A, mixed);
+    if (absorbing) upload_csr(Zi, ops.Z, false);
     upload_csr(Meps, ops.Meps, false);
     upload_csr(Mnu, ops.Mnu, false);
     upload_csr(K, ops.K, false);
@@ -323,7 +326,7 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Mnu.nnz() + ops.K.nnz() + ops.Kt.nnz() + ops.Gt.nnz();
     a_nnz = ops.A.nnz();
     // fields and solver vectors
-    const int64_t N1 = m.N1, N1i = m.N1_int, N2 = m.N2, N0i = m.N0_int;
+    const int64_t N1 = m.N1, N1i = n1s, N2 = m.N2, N0i = m.N0_int;
     d_e.alloc(N1 * 8);
     d_b.alloc(N2 * 8);
     d_g.alloc(std::max<int64_t>(N1i, 1) * 8);
@@ -896,7 +899,7 @@ void Run::particle_phase()
             HIPCHECK(launch_spill_reduce(n1l, (int32_t)m.nt, (const int32_t *)d_soff.p, srec,
                                          (const double *)d_pool_val.p, pool_cap, (double *)d_P.p,
                                          (const int32_t *)d_nstay.p, (uint32_t *)d_tcnt.p, stream));
-            HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, m.N1_int,
+            HIPCHECK(launch_scatter((const int64_t *)d_inc_ptr.p, (const int32_t *)d_inc_idx.p, n1s,
                                     (const double *)d_P.p, (double *)d_dg.p, stream));
             next_order(nrec_ub, srec);
         };
@@ -994,7 +997,7 @@ void Run::particle_phase()
 void Run::field_phase_three_level()
 {
     Range rg("fempic field update, three-level Newmark-beta (a7)");
-    const int64_t N1i = m.N1_int, N2 = m.N2;
+    const int64_t N1i = n1s, N2 = m.N2;
     const double dt = prm.dt, gm = prm.gamma, bt = prm.beta;
     const double an = 0.5 - 2.0 * bt + gm, am = 0.5 + bt - gm;
     const double B0 = an - bt * (1.0 - 2.0 * gm) / gm, B1 = am - bt * (gm - 1.0) / gm;
@@ -1048,7 +1051,7 @@ void Run::field_phase()
 {
     if (three_level) return field_phase_three_level();
     Range rg("fempic field update (a7)");
-    const int64_t N1i = m.N1_int, N2 = m.N2;
+    const int64_t N1i = n1s, N2 = m.N2;
     const double dt = prm.dt;
     double *e = (double *)d_e.p, *b = (double *)d_b.p, *dg = (double *)d_dg.p;
     // g += dg (compensated: d_g_lo keeps the rounding errors for the Gauss check)
@@ -1057,8 +1060,10 @@ void Run::field_phase()
     // (whatever *nu u rounds to, G^T K^T of it is zero)
     HIPCHECK(spmv(K.desc, e, (double *)v_u.p, -0.5 * dt, 1.0, b, stream));
     HIPCHECK(spmv(Mnu.desc, (const double *)v_u.p, (double *)v_nu.p, 1.0, 0.0, nullptr, stream));
-    HIPCHECK(combo_dd(N1i, &Kt.desc, (const double *)v_nu.p, dt, nullptr, nullptr, nullptr, 0.0, dg, -1.0, nullptr,
-                      0.0, (double *)v_rhs.p, (double *)v_rhs_lo.p, stream));
+    // (absorbing walls: - dt *I e as well, e = e + e_lo)
+    HIPCHECK(combo_dd(N1i, &Kt.desc, (const double *)v_nu.p, dt, absorbing ? &Zi.desc : nullptr,
+                      absorbing ? e : nullptr, absorbing ? (const double *)d_e_lo.p : nullptr, absorbing ? -dt : 0.0,
+                      dg, -1.0, nullptr, 0.0, (double *)v_rhs.p, (double *)v_rhs_lo.p, stream));
     // solve A d = rhs (d = v_x + v_x_lo)
     if (mixed) solve_mixed();
     else solve_fp64();
@@ -1086,7 +1091,7 @@ double Run::read_sc(int k)
 // HIP graph and replayed; it holds kernels only.
 void Run::pcg_batch(bool fp32)
 {
-    const int64_t n = m.N1_int;
+    const int64_t n = n1s;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     auto launch = [&]() {
         for (int k = 0; k < 8; k++) {
@@ -1126,7 +1131,7 @@ void Run::pcg_batch(bool fp32)
 // accuracy); returns |r|^2 of the recurrence.  The iterate is v_x.
 double Run::pcg64(const double *b, double tol2, double bb)
 {
-    const int64_t n = m.N1_int;
+    const int64_t n = n1s;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     HIPCHECK(pcg_init(n, b, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
                       (const double *)d_dinv.p, part, sc, A.desc.bptr != nullptr, stream));
@@ -1162,7 +1167,7 @@ double Run::pcg64(const double *b, double tol2, double bb)
 // double-double, rounded into r; returns |r|^2.
 double Run::residual_dd(const double *x, const double *x_lo, double *r)
 {
-    const int64_t n = m.N1_int;
+    const int64_t n = n1s;
     HIPCHECK(combo_dd(n, nullptr, nullptr, 0.0, &A.desc, x, x_lo, -1.0, (const double *)v_rhs.p, 1.0,
                       (const double *)v_rhs_lo.p, 1.0, r, nullptr, stream));
     HIPCHECK(dot_det(n, r, r, (double *)d_partial.p, (double *)d_sc.p + 12, stream));
@@ -1180,7 +1185,7 @@ double Run::solve_target() const { return std::min(prm.pcg_rtol, GAUSS_RTOL); }
 void Run::solve_fp64()
 {
     Range rg("fempic pcg");
-    const int64_t n = m.N1_int;
+    const int64_t n = n1s;
     const double *rhs = (const double *)v_rhs.p;
     double *x = (double *)v_x.p, *xs = (double *)v_xs.p, *xlo = (double *)v_x_lo.p, *rc = (double *)v_tmp.p;
     HIPCHECK(dot_det(n, rhs, rhs, (double *)d_partial.p, (double *)d_sc.p + 12, stream));
@@ -1215,7 +1220,7 @@ void Run::solve_fp64()
 void Run::solve_mixed()
 {
     Range rg("fempic pcg (FP32 inner, FP64 refinement)");
-    const int64_t n = m.N1_int;
+    const int64_t n = n1s;
     double *sc = (double *)d_sc.p, *part = (double *)d_partial.p;
     double *x = (double *)v_x.p, *xlo = (double *)v_x_lo.p, *r = (double *)v_r.p;
     const double *rhs = (const double *)v_rhs.p;
@@ -1364,7 +1369,7 @@ void Run::gauss_noalloc(double out[3])
     void *base = nullptr;
     HIPCHECK(noalloc_scratch(&base));
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t n0 = (size_t)std::max<int64_t>(m.N0_int, 1), n1 = (size_t)std::max<int64_t>(m.N1_int, 1);
+    const size_t n0 = (size_t)std::max<int64_t>(m.N0_int, 1), n1 = (size_t)std::max<int64_t>(n1s, 1);
     const size_t b_pr = al((size_t)m.nt * n0l * 8), b_v0 = al(n0 * 8), b_v1 = al(n1 * 8),
                  b_part = al((size_t)gauss_partial_entries() * 8);
     const size_t need = b_pr + 3 * b_v0 + 2 * b_v1 + b_part + 256;
@@ -1438,7 +1443,7 @@ void Run::fields_set(const double *e, int64_t ne, const double *b, int64_t nb)
         std::vector<double> ei(m.N1, 0.0);
         for (int64_t i = 0; i < m.N1; i++) {
             int64_t k = m.nat2int1[i];
-            if (k < m.N1_int) ei[k] = e[i];
+            if (k < n1s) ei[k] = e[i];
         }
         HIPCHECK(hipMemcpy(d_e.p, ei.data(), m.N1 * 8, hipMemcpyHostToDevice));
         zero(d_e_lo);
@@ -1457,10 +1462,10 @@ void Run::deposit_get(double *dg, int64_t n)
 {
     sync();
     if (n < m.N1) throw Error(FEMPIC_EINVAL, "buffer too short");
-    std::vector<double> d(std::max<int64_t>(m.N1_int, 1));
-    HIPCHECK(hipMemcpy(d.data(), d_dg.p, m.N1_int * 8, hipMemcpyDeviceToHost));
+    std::vector<double> d(std::max<int64_t>(n1s, 1));
+    HIPCHECK(hipMemcpy(d.data(), d_dg.p, n1s * 8, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < m.N1; i++) dg[i] = 0.0;
-    for (int64_t k = 0; k < m.N1_int; k++) dg[m.int2nat1[k]] = d[k];
+    for (int64_t k = 0; k < n1s; k++) dg[m.int2nat1[k]] = d[k];
 }
 
 // ------------------------------------------------------- impressed field
@@ -1767,7 +1772,7 @@ void Run::save(const char *path)
     h.hist_bytes = mixed ? 4 : 8;
     h.nt = m.nt;
     h.n1 = m.N1;
-    h.n1_int = m.N1_int;
+    h.n1_int = n1s;
     h.n2 = m.N2;
     h.n0_int = m.N0_int;
     h.np = np;
@@ -1810,16 +1815,16 @@ void Run::save(const char *path)
     }
     put(d_e.p, m.N1 * 8);
     put(d_b.p, m.N2 * 8);
-    put(d_g.p, m.N1_int * 8);
+    put(d_g.p, n1s * 8);
     put(d_rho0.p, m.N0_int * 8);
-    put(d_e_lo.p, m.N1_int * 8);
-    put(d_g_lo.p, m.N1_int * 8);
+    put(d_e_lo.p, n1s * 8);
+    put(d_g_lo.p, n1s * 8);
     if (h.have_prev) {
-        put(d_eprev.p, m.N1_int * 8);
+        put(d_eprev.p, n1s * 8);
         put(d_bprev.p, m.N2 * 8);
-        put(d_dgprev.p, m.N1_int * 8);
-        put(d_dprev.p, m.N1_int * 8);
-        put(d_dprev_lo.p, m.N1_int * 8);
+        put(d_dgprev.p, n1s * 8);
+        put(d_dprev.p, n1s * 8);
+        put(d_dprev_lo.p, n1s * 8);
     }
     if (h.has_imp) put(d_bimp.p, m.N2 * 8);
     const uint64_t sum = F.hash.value();
@@ -1840,9 +1845,9 @@ void Run::restore(const char *path)
         throw Error(FEMPIC_EINVAL, "not a checkpoint of this library: " + F.path);
     if (h.precision != (mixed ? FEMPIC_MIXED : FEMPIC_FP64) || h.hist_bytes != (mixed ? 4 : 8))
         throw Error(FEMPIC_EINVAL, "checkpoint precision differs from the run's");
-    if (h.order != order || h.nt != m.nt || h.n1 != m.N1 || h.n1_int != m.N1_int || h.n2 != m.N2 ||
+    if (h.order != order || h.nt != m.nt || h.n1 != m.N1 || h.n1_int != n1s || h.n2 != m.N2 ||
         h.n0_int != m.N0_int)
-        throw Error(FEMPIC_EINVAL, "checkpoint is of another mesh or order");
+        throw Error(FEMPIC_EINVAL, "checkpoint is of another mesh, order or field wall condition");
     if (h.dt != prm.dt) throw Error(FEMPIC_EINVAL, "checkpoint time step differs from the run's");
     if (h.gamma != prm.gamma || h.beta != prm.beta)
         throw Error(FEMPIC_EINVAL, "checkpoint Newmark-beta parameters differ from the run's");
@@ -1861,8 +1866,8 @@ void Run::restore(const char *path)
         // the size the header implies, before anything is allocated for it
         const long here = std::ftell(F.f);
         const uint64_t want = (uint64_t)sizeof(CkptHeader) + (uint64_t)n * (6 * 8 + 18 * rs + 8) +
-                              (uint64_t)(m.N1 + m.N2 + 3 * m.N1_int + m.N0_int) * 8 +
-                              (h.have_prev ? (uint64_t)(4 * m.N1_int + m.N2) * 8 : 0) +
+                              (uint64_t)(m.N1 + m.N2 + 3 * n1s + m.N0_int) * 8 +
+                              (h.have_prev ? (uint64_t)(4 * n1s + m.N2) * 8 : 0) +
                               (h.has_imp ? (uint64_t)m.N2 * 8 : 0) + 8;
         if (here < 0 || std::fseek(F.f, 0, SEEK_END) != 0) throw Error(FEMPIC_EINVAL, "cannot read checkpoint " + F.path);
         const long size = std::ftell(F.f);
@@ -1873,7 +1878,7 @@ void Run::restore(const char *path)
     std::vector<double> x(3 * n), v(3 * n);
     std::vector<char> vh(9 * n * rs), ah(9 * n * rs);
     std::vector<int32_t> tet(n), id(n);
-    std::vector<double> e(m.N1), b(m.N2), g(m.N1_int), rho0(m.N0_int), e_lo(m.N1_int), g_lo(m.N1_int);
+    std::vector<double> e(m.N1), b(m.N2), g(n1s), rho0(m.N0_int), e_lo(n1s), g_lo(n1s);
     F.read(x.data(), x.size() * 8);
     F.read(v.data(), v.size() * 8);
     F.read(vh.data(), vh.size());
@@ -1888,11 +1893,11 @@ void Run::restore(const char *path)
     F.read(g_lo.data(), g_lo.size() * 8);
     std::vector<double> ep, bp, dgp, dpv, dpl;
     if (h.have_prev) {
-        ep.resize(m.N1_int);
+        ep.resize(n1s);
         bp.resize(m.N2);
-        dgp.resize(m.N1_int);
-        dpv.resize(m.N1_int);
-        dpl.resize(m.N1_int);
+        dgp.resize(n1s);
+        dpv.resize(n1s);
+        dpl.resize(n1s);
         F.read(ep.data(), ep.size() * 8);
         F.read(bp.data(), bp.size() * 8);
         F.read(dgp.data(), dgp.size() * 8);
@@ -2021,8 +2026,8 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
 {
     const bool k2 = z.order == 2;
     const double n1l = k2 ? 20 : 6, n2l = k2 ? 15 : 4, n0l = k2 ? 10 : 4;
-    const double nt = (double)z.nt, N1 = (double)z.n1, N1i = (double)z.n1_int, N2 = (double)z.n2,
-                 N0i = (double)z.n0_int;
+    const double nt = (double)z.nt, N1 = (double)z.n1, N1i = (double)(z.absorbing ? z.n1 : z.n1_int),
+                 N2 = (double)z.n2, N0i = (double)z.n0_int;
     const double nnzA = N1i * (k2 ? 46.0 : 17.0), nnzK = N2 * (k2 ? 13.0 : 3.0), nnzG = N0i * (k2 ? 25.0 : 15.0),
                  nnzNu = N2 * (k2 ? 24.0 : 7.0);
     auto csr = [](double rows, double nnz) { return (rows + 1) * 8 + nnz * 12 + 256; };
@@ -2030,6 +2035,8 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     double ops = 2 * csr(N1i, nnzA) + (mixed ? nnzA * 4 : 0) + csr(N2, nnzK) + csr(N1i, nnzK) + csr(N2, nnzNu) +
                  csr(N0i, nnzG);
     if (k2) ops += 2 * ((N1i / 2 + 1) * 8 + nnzA * 9 + 256) + (mixed ? nnzA * 4 : 0);
+    // the surface impedance matrix: a wall DoF meets the DoFs of its wall faces
+    if (z.absorbing) ops += csr(N1i, (N1 - (double)z.n1_int) * (k2 ? 16.0 : 5.0));
     const double precond = (k2 ? 2 : 1) * N1i * (8 + (mixed ? 4 : 0));
     const double inc = (N1i + 1) * 8 + nt * n1l * 4 + (N0i + 1) * 8 + nt * n0l * 4;
     const double mesh = nt * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
@@ -2067,9 +2074,9 @@ FootprintSizes kuhn_sizes(int order, double nt)
     return FootprintSizes{order, up(T), up(N1), up(N1), up(N2), up(N0)};
 }
 
-size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed)
+size_t Run::footprint_estimate(const HostMesh &m, int64_t n, bool mixed, bool absorbing)
 {
-    return footprint_bytes(FootprintSizes{m.order, m.nt, m.N1, m.N1_int, m.N2, m.N0_int}, n, mixed);
+    return footprint_bytes(FootprintSizes{m.order, m.nt, m.N1, m.N1_int, m.N2, m.N0_int, absorbing}, n, mixed);
 }
 
 void check_params(const fempic_params &p)
@@ -2085,6 +2092,10 @@ void check_params(const fempic_params &p)
         throw Error(FEMPIC_EINVAL, "unsupported particle boundary condition");
     if (p.gauss_every < 0) throw Error(FEMPIC_EINVAL, "gauss_every must be >= 0");
     if (p.pusher != FEMPIC_PUSH_AB4 && p.pusher != FEMPIC_PUSH_BORIS) throw Error(FEMPIC_EINVAL, "unknown pusher");
+    if (p.field_bc != FEMPIC_FIELD_PEC && p.field_bc != FEMPIC_FIELD_ABSORB)
+        throw Error(FEMPIC_EINVAL, "unknown field boundary condition");
+    if (p.field_bc == FEMPIC_FIELD_ABSORB && !(p.gamma == 0.5 && p.beta == 0.25))
+        throw Error(FEMPIC_EINVAL, "absorbing walls need the trapezoidal scheme (gamma, beta = 1/2, 1/4)");
 }
 
 }  // namespace fempic
@@ -2386,7 +2397,7 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.spills = r.last_spill;
     for (int k = 0; k < 3; k++) s.gauss[k] = r.gauss_last[k];
     s.gauss_step = r.gauss_step;
-    s.a_rows = r.m.N1_int;
+    s.a_rows = r.n1s;
     s.a_nnz = r.a_nnz;
     s.device_bytes = (int64_t)r.account().bytes;
     s.device_peak_bytes = (int64_t)r.account().peak;

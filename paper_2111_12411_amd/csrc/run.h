@@ -99,7 +99,7 @@ class Run {
     void save(const char *path);
     void restore(const char *path);
     void set_log(const char *path);
-    static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed);
+    static size_t footprint_estimate(const HostMesh &m, int64_t n, bool mixed, bool absorbing = false);
     // replay the particle phase's launches as HIP graphs (see particle_phase);
     // its per-kernel times are then not measured
     void set_phase_graphs(bool on);
@@ -116,6 +116,10 @@ class Run {
     int device = 0;  // the HIP device the run was made on
     bool mixed = false;
     int order = 1, n1l = 0, n2l = 0, n0l = 0;
+    // absorbing walls (params.field_bc); n1s: the unknown W1 DoFs, the first n1s of
+    // the internal numbering (N1_int with PEC walls, N1 with absorbing ones)
+    bool absorbing = false;
+    int64_t n1s = 0;
     GLRule gl{};
     DevMesh dm{};
     // statistics
@@ -185,7 +189,7 @@ class Run {
     void clear_phase_graphs();
 
     DevBuf d_geo, d_nbr, d_map1, d_map2, d_map0;
-    DevCSRBuf A, Meps, Mnu, K, Kt, Gt;
+    DevCSRBuf A, Meps, Mnu, K, Kt, Gt, Zi;  // Zi: surface impedance *I (absorbing walls)
     double gscale = 1.0;  // Gt holds gscale G^T
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;

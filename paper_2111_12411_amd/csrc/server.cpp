@@ -40,9 +40,11 @@ struct Job {
 };
 
 // the same estimate as fempic_footprint for the N^3 Kuhn cube
-size_t cube_footprint(int N, int order, int64_t n, bool mixed)
+size_t cube_footprint(int N, int order, int64_t n, bool mixed, bool absorbing)
 {
-    return footprint_bytes(kuhn_sizes(order, 6.0 * N * N * N), n, mixed);
+    FootprintSizes z = kuhn_sizes(order, 6.0 * N * N * N);
+    z.absorbing = absorbing;
+    return footprint_bytes(z, n, mixed);
 }
 
 }  // namespace
@@ -200,7 +202,8 @@ int32_t fempic_submit(fempic_server s, const fempic_job *job, int64_t *ticket)
     j->vel.assign(job->vel, job->vel + 3 * job->n);
     j->spec.pos = nullptr;
     j->spec.vel = nullptr;
-    j->footprint = cube_footprint(job->N, job->order, job->n, job->params.precision == FEMPIC_MIXED);
+    j->footprint = cube_footprint(job->N, job->order, job->n, job->params.precision == FEMPIC_MIXED,
+                                  job->params.field_bc == FEMPIC_FIELD_ABSORB);
     if (j->footprint > s->prm.hbm_budget) throw Error(FEMPIC_ENOMEM, "job can never fit the HBM budget");
     j->t_submit = clk::now();
     std::lock_guard<std::mutex> lk(s->mu);

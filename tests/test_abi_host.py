@@ -80,6 +80,13 @@ def test_run_rejects_bad_params_without_gpu():
         assert "Newmark" in F.lib().fempic_last_error().decode()
     p = F.params(-1.0)
     assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+    # absorbing walls only with the trapezoidal scheme; unknown wall conditions
+    p = F.params(1e-11, gamma=1.5, beta=1.0, field_bc=F.FIELD_ABSORB)
+    assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+    assert "trapezoidal" in F.lib().fempic_last_error().decode()
+    p = F.params(1e-11, field_bc=2)
+    assert F.lib().fempic_run_create(m.h, F.C.byref(p), None, F.C.byref(h)) == -1
+    assert "wall" in F.lib().fempic_last_error().decode() or "boundary" in F.lib().fempic_last_error().decode()
 
 
 def test_run_rejects_negative_gauss_cadence_without_gpu():
