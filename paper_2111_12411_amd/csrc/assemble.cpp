@@ -333,6 +333,9 @@ void surface_impedance(const HostMesh &m, const RefElem &R, int64_t n1s, double 
                         for (int b = 0; b < 4; b++) v += F[((size_t)(i * n1 + j) * 4 + a) * 4 + b] * gpg[a][b];
                     el[i * n1 + j] = Y * area * v;
                 }
+            // symmetric as the exact matrix is (the two sums round in different orders)
+            for (int i = 0; i < n1; i++)
+                for (int j = i + 1; j < n1; j++) el[i * n1 + j] = el[j * n1 + i] = 0.5 * (el[i * n1 + j] + el[j * n1 + i]);
             for (int i = 0; i < n1; i++) {
                 const int32_t r = m.map1[t * n1 + i];
                 if (r >= n1s) continue;

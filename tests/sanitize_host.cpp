@@ -2,6 +2,7 @@
 // g++ under AddressSanitizer and UndefinedBehaviorSanitizer by
 // tests/test_host_sanitizers.py (no GPU code is involved).  Exits non-zero on a
 // failed check; the sanitizers abort on a memory error or undefined behaviour.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <memory>
@@ -59,6 +60,31 @@ int main()
             CHECK((int64_t)ops.inc0_ptr.size() == m->N0_int + 1);
             for (int32_t s : ops.inc_idx) CHECK(s >= 0 && s < m->nt * m->n1l);
             for (int32_t s : ops.inc0_idx) CHECK(s >= 0 && s < m->nt * m->n0l);
+            CHECK(ops.n1s == m->N1_int && ops.Z.nnz() == 0);
+            // absorbing walls: every W1 DoF an unknown, the surface impedance matrix
+            // symmetric, on the wall DoFs only, and inside A's pattern
+            Operators ab;
+            assemble(*m, 5 * m->dt_cfl, ab, 0.25, true);
+            CHECK(ab.n1s == m->N1);
+            check_csr(ab.A, m->N1, m->N1);
+            check_csr(ab.Z, m->N1, m->N1);
+            check_csr(ab.Gt, m->N0_int, m->N1);
+            CHECK((int64_t)ab.inc_ptr.size() == m->N1 + 1);
+            CHECK(ab.Z.nnz() > 0);
+            double zmax = 0.0;
+            for (double v : ab.Z.val) zmax = std::max(zmax, std::fabs(v));
+            for (int64_t r = 0; r < ab.Z.rows; r++)
+                for (int64_t q = ab.Z.ptr[r]; q < ab.Z.ptr[r + 1]; q++) {
+                    const int32_t c = ab.Z.idx[q];
+                    CHECK(r >= m->N1_int && c >= m->N1_int);
+                    const int32_t *b = ab.Z.idx.data() + ab.Z.ptr[c], *e = ab.Z.idx.data() + ab.Z.ptr[c + 1];
+                    const int32_t *f = std::lower_bound(b, e, (int32_t)r);
+                    CHECK(f != e && *f == r);
+                    if (f != e && *f == r) {
+                        const double vt = ab.Z.val[f - ab.Z.idx.data()];
+                        CHECK(std::fabs(vt - ab.Z.val[q]) <= 1e-14 * zmax);
+                    }
+                }
             // the generic path: the same cube with vertex ids permuted and tet corners unsorted
             const int64_t nv = m->nv, nt = m->nt;
             std::vector<int64_t> perm(nv);
