@@ -173,8 +173,8 @@ hipError_t launch_queue_index(const ContQueue &cq, int64_t np, uint32_t *tmp, hi
 // blocks of the continuation kernel (one counter slot each in cntb)
 constexpr int CONT_BLOCKS = 65536;
 // nq_hint: expected queue length (sizes the grid; any length is processed)
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *dargs, int64_t nq_hint, unsigned long long *cntb,
-                           unsigned long long *cnt, hipStream_t s);
+hipError_t launch_continue(int order, bool mixed, bool boris, const ParticleArgs *dargs, int64_t nq_hint,
+                           unsigned long long *cntb, unsigned long long *cnt, hipStream_t s);
 // spill records in canonical order (queued record, then segment): key = tet,
 // val = slot (| SREC_LAST); nslots: launch size, nq: device count of queued
 // records (the slots in use are 2 nq plus the pool's appended count); kcap:

@@ -578,22 +578,40 @@ __device__ inline int fast_exit(GPtr G, const double (&dp)[4][3], const double (
 // l_0' = -(l_1' + l_2' + l_3'); Gauss-Legendre nodes on [0, h].  Only the
 // local DoFs C0 <= i < C1 are accumulated (a caller short of registers takes
 // the DoFs in two passes).
-template <int K, int C0 = 0, int C1 = Ord<K>::N1>
+// LINE: the path is straight (the Boris push), so the coordinates are linear in
+// u and the integrand has degree k: ceil((k+1)/2) Gauss-Legendre points are
+// exact (1 at order 1, 2 at order 2) instead of the 2k+2 of the quartic path.
+template <bool LINE>
+struct SegRule;
+template <>
+struct SegRule<true> {
+    // Gauss-Legendre on [0, 1]: 1 point (x = 1/2) and 2 points (x = 1/2 -+ 1/(2 sqrt 3))
+    static constexpr double X2 = 0.5 / 1.7320508075688772935;
+    __device__ static double x(int n, int g) { return n == 1 ? 0.5 : (g == 0 ? 0.5 - X2 : 0.5 + X2); }
+    __device__ static double w(int n, int) { return n == 1 ? 1.0 : 0.5; }
+};
+template <int K, int C0 = 0, int C1 = Ord<K>::N1, bool LINE = false>
 __device__ inline void segment_moments(const double (&lq)[3][5], double h, double qw, const GLRule &gl, double *dep)
 {
     using O = Ord<K>;
+    constexpr int NG = LINE ? (K + 2) / 2 : O::NG;
 #pragma unroll
     for (int c = C0; c < C1; c++) dep[c] = 0.0;
     const double qwh = qw * h;
 #pragma unroll
-    for (int g = 0; g < O::NG; g++) {
-        const double u = h * gl.x[g];
-        const double wg = qwh * gl.w[g];
+    for (int g = 0; g < NG; g++) {
+        const double u = h * (LINE ? SegRule<true>::x(NG, g) : gl.x[g]);
+        const double wg = qwh * (LINE ? SegRule<true>::w(NG, g) : gl.w[g]);
         double lam[4], dl[4];  // dl carries the quadrature weight
 #pragma unroll
         for (int m = 1; m < 4; m++) {
-            lam[m] = horner4(lq[m - 1], u);
-            dl[m] = wg * dhorner4(lq[m - 1], u);
+            if constexpr (LINE) {
+                lam[m] = fma(lq[m - 1][1], u, lq[m - 1][0]);
+                dl[m] = wg * lq[m - 1][1];
+            } else {
+                lam[m] = horner4(lq[m - 1], u);
+                dl[m] = wg * dhorner4(lq[m - 1], u);
+            }
         }
         lam[0] = 1.0 - lam[1] - lam[2] - lam[3];
         dl[0] = -(dl[1] + dl[2] + dl[3]);
@@ -1017,7 +1035,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                 const double s_hi = f_exit < 0 ? 1.0 : s_exit;
                 if (s_hi > 0.0) {
                     double dep[N1];
-                    segment_moments<K>(lq, s_hi, sp.qw, gl, dep);
+                    segment_moments<K, 0, N1, BORIS>(lq, s_hi, sp.qw, gl, dep);
 #pragma unroll
                     for (int c = 0; c < N1; c++) s_hc[c][tid] = dep[c];
                 }
@@ -1059,7 +1077,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
 // Kernel 2: the rest of the paths of queued particles, segment by segment;
 // every segment's current moments go to the spill pool tagged with
 // (sorted particle, segment), so their reduction order is canonical.
-template <int K, typename R>
+template <int K, typename R, bool BORIS = false>
 __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restrict__ A)
 {
     const GMesh m = gview(A->m);
@@ -1097,7 +1115,7 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
             ncr++;
             const unsigned long long nrf0 = nrf;
             gone = cross_face<R>(m, m.geo + (int64_t)t * 16, pending, t, entry, dp, lam, out, i, nrf, absorb,
-                                 sp.boris == 0);
+                                 !BORIS);
 #pragma unroll
             for (int c = 0; c < 3; c++) rec->lam[c] = lam[c + 1];
             if (nrf != nrf0) {
@@ -1150,7 +1168,7 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
 #pragma unroll
                         for (int c = 0; c < 3; c++) dq[d][c] = rec->dp[3 * d + c];
                     const unsigned long long nrf0 = nrf;
-                    gone = cross_face<R>(m, G, f_exit, t, entry, dq, le, out, i, nrf, absorb, sp.boris == 0);
+                    gone = cross_face<R>(m, G, f_exit, t, entry, dq, le, out, i, nrf, absorb, !BORIS);
 #pragma unroll
                     for (int c = 0; c < 3; c++) rec->lam[c] = le[c + 1];
                     if (nrf != nrf0) {  // a wall reflection changed the path
@@ -1178,7 +1196,7 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
                 const int64_t slot = spill_slot(pool, r, nq, t_seg, last, i, nsp_i, errs);
                 if (slot >= 0) {
                     double dep[N1];
-                    segment_moments<K>(lq, fmax(s_hi - s_lo, 0.0), sp.qw, gl, dep);
+                    segment_moments<K, 0, N1, BORIS>(lq, fmax(s_hi - s_lo, 0.0), sp.qw, gl, dep);
                     const gptr<double> dst = pool.val + slot * N1;
 #pragma unroll
                     for (int c = 0; c < N1; c++) dst[c] = dep[c];
@@ -2200,18 +2218,28 @@ hipError_t launch_queue_index(const ContQueue &cq, int64_t np, uint32_t *tmp, hi
     return hipGetLastError();
 }
 
-hipError_t launch_continue(int order, bool mixed, const ParticleArgs *A, int64_t nq_hint, unsigned long long *cntb,
-                           unsigned long long *cnt, hipStream_t s)
+hipError_t launch_continue(int order, bool mixed, bool boris, const ParticleArgs *A, int64_t nq_hint,
+                           unsigned long long *cntb, unsigned long long *cnt, hipStream_t s)
 {
     // about one queued path per thread (a grid-stride loop covers a longer queue)
     const int64_t want = (nq_hint + nq_hint / 8 + BLK - 1) / BLK + 16;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(CONT_BLOCKS, want));
     if (order == 1) {
-        if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, A);
-        else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, A);
+        if (boris) {
+            if (mixed) hipLaunchKernelGGL((k_continue<1, float, true>), dim3(grid), dim3(BLK), 0, s, A);
+            else hipLaunchKernelGGL((k_continue<1, double, true>), dim3(grid), dim3(BLK), 0, s, A);
+        } else {
+            if (mixed) hipLaunchKernelGGL((k_continue<1, float>), dim3(grid), dim3(BLK), 0, s, A);
+            else hipLaunchKernelGGL((k_continue<1, double>), dim3(grid), dim3(BLK), 0, s, A);
+        }
     } else {
-        if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, A);
-        else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, A);
+        if (boris) {
+            if (mixed) hipLaunchKernelGGL((k_continue<2, float, true>), dim3(grid), dim3(BLK), 0, s, A);
+            else hipLaunchKernelGGL((k_continue<2, double, true>), dim3(grid), dim3(BLK), 0, s, A);
+        } else {
+            if (mixed) hipLaunchKernelGGL((k_continue<2, float>), dim3(grid), dim3(BLK), 0, s, A);
+            else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, A);
+        }
     }
     hipLaunchKernelGGL(k_counters, dim3(1), dim3(BLK), 0, s, cntb, (int)grid, cnt);
     return hipGetLastError();

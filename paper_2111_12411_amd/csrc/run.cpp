@@ -883,7 +883,7 @@ void Run::particle_phase()
             if (timed) HIPCHECK(hipEventRecord(ev_c1, stream));
             // compact the queue written by k_particle, then continue the queued paths
             HIPCHECK(launch_queue_index(ha->cq, np, (uint32_t *)d_qtmp.p, stream));
-            HIPCHECK(launch_continue(order, mixed, (const ParticleArgs *)d_args.p, nq_hint,
+            HIPCHECK(launch_continue(order, mixed, sp.boris != 0, (const ParticleArgs *)d_args.p, nq_hint,
                                      (unsigned long long *)d_cntb.p, p_cnt, stream));
             if (timed) HIPCHECK(hipEventRecord(ev_c, stream));
             // deterministic reduction of the spill pool: records in canonical order
