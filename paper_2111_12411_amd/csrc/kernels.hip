@@ -832,6 +832,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
     __shared__ R s_b[TM][N2];
     __shared__ int32_t s_off[TM + 1];
     __shared__ int32_t s_nstay[TM];  // particles of each tet that are not queued
+    __shared__ int32_t s_nbr[TM][4];
     __shared__ double s_hc[N1][PBLK + 1];
 
     const int tid = threadIdx.x;
@@ -845,6 +846,7 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
     uint32_t nslot = pbeg + tid < pend ? perm[pbeg + tid] : 0u;
     for (int k = tid; k < ntl * 16; k += PBLK) s_geo[k / 16][k % 16] = m.geo[(int64_t)T0 * 16 + k];
     for (int k = tid; k <= ntl; k += PBLK) s_off[k] = off[T0 + k];
+    for (int k = tid; k < ntl * 4; k += PBLK) s_nbr[k / 4][k % 4] = m.nbr[(int64_t)T0 * 4 + k];
     for (int k = tid; k < TM; k += PBLK) s_nstay[k] = 0;
     // the step's counters, which later kernels of the step accumulate into
     if (blockIdx.x == 0 && tid < NCNT) glb(A->cnt)[tid] = 0ull;
@@ -1011,10 +1013,13 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
                     for (int c = 0; c < 3; c++) rec->dp[3 * d + c] = dp[d][c];
                 rec->s_lo = f_exit >= 0 ? s_exit : 0.0;
                 rec->i = i;
-                rec->t = th;
-                rec->entry = -1;
-                rec->ncross = 0;
-                rec->pending = f_exit >= 0 ? f_exit : -1;
+                // an exit into a neighbour is crossed here (below), one into a wall
+                // is left pending to k_continue
+                const int nx = f_exit >= 0 ? s_nbr[lt][f_exit] : -1;
+                rec->t = nx >= 0 ? nx >> 2 : th;
+                rec->entry = nx >= 0 ? nx & 3 : -1;
+                rec->ncross = nx >= 0 ? 1 : 0;
+                rec->pending = f_exit >= 0 && nx < 0 ? f_exit : -1;
             }
             double lq[3][5];  // l_1..l_3 along the path in the home tet
             if (f_exit != -2) {
@@ -1024,8 +1029,25 @@ __global__ __launch_bounds__(PBLK, 3) void k_particle(const ParticleArgs *__rest
             if (f_exit != -1) {
                 // coordinates where k_continue takes the path up: the exit point, or
                 // the start for a path handed over whole
+                double le[4];
 #pragma unroll
-                for (int c = 0; c < 3; c++) rec->lam[c] = f_exit >= 0 ? horner4(lq[c], s_exit) : ls[c + 1];
+                for (int c = 0; c < 3; c++) le[c + 1] = f_exit >= 0 ? horner4(lq[c], s_exit) : ls[c + 1];
+                const int nx = f_exit >= 0 ? s_nbr[lt][f_exit] : -1;
+                if (nx >= 0) {
+                    // the crossing into the neighbour: the three shared vertices keep
+                    // their coordinates, listed in the same order in both tets, and
+                    // the neighbour's vertex across the face starts at 0
+                    le[0] = bary0(le[1], le[2], le[3]);
+                    const int e = nx & 3;
+                    const double s0 = f_exit == 0 ? le[1] : le[0];
+                    const double s1 = f_exit <= 1 ? le[2] : le[1];
+                    const double s2 = f_exit <= 2 ? le[3] : le[2];
+                    le[1] = e == 0 ? s0 : (e == 1 ? 0.0 : s1);
+                    le[2] = e <= 1 ? s1 : (e == 2 ? 0.0 : s2);
+                    le[3] = e <= 2 ? s2 : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < 3; c++) rec->lam[c] = le[c + 1];
             } else {
 #pragma unroll
                 for (int c = 0; c < 3; c++) *out.lam(c, i) = horner4(lq[c], 1.0);
@@ -1099,6 +1121,7 @@ __global__ __launch_bounds__(BLK, 2) void k_continue(const ParticleArgs *__restr
         const int64_t i = rec->i;
         int t = rec->t, entry = rec->entry, ncross = rec->ncross, nsp_i = 0;
         const int pending = rec->pending;
+        ncr += ncross;  // a crossing into a neighbour that k_particle made
         bool gone = false;  // absorbed at a wall
         if (pending >= 0) {
             // the exit found in the home tet: cross it now
