@@ -140,6 +140,13 @@ hipError_t radix_sort(SortBuffers &sb, int64_t n, int bits, bool vals_are_iota, 
 // out[i] = in[perm[i]] for every particle array
 hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const uint32_t *perm, int64_t n,
                           hipStream_t s);
+// order of np0 present and n new particles: next_perm[p + noff_new[t]] = perm[p]
+// for present sorted position p in tet t (off[t] <= p < off[t+1]), and
+// next_perm[off[t+1] + q] = slot0 + nval[q] for the q-th new particle in tet
+// order (nkey = its tet); next_off[t] = off[t] + noff_new[t], t in [0, nt]
+hipError_t launch_merge_order(int64_t np0, int64_t n, int32_t nt, const int32_t *off, const int32_t *noff_new,
+                              const uint32_t *perm, const uint32_t *nkey, const uint32_t *nval, uint32_t slot0,
+                              int32_t *next_off, uint32_t *next_perm, hipStream_t s);
 // bucket offsets off[t] = first index with key >= t, for t in [0, nt]
 hipError_t launch_offsets(const uint32_t *sorted_key, int64_t n, int32_t nt, int32_t *off, hipStream_t s,
                           const int32_t *dn = nullptr);

@@ -2196,6 +2196,40 @@ hipError_t launch_permute(bool mixed, DevParticles in, DevParticles out, const u
     return hipGetLastError();
 }
 
+__global__ void k_merge_order(int64_t np0, int64_t n, int32_t nt, const int32_t *__restrict__ off,
+                              const int32_t *__restrict__ noff_new, const uint32_t *__restrict__ perm,
+                              const uint32_t *__restrict__ nkey, const uint32_t *__restrict__ nval, uint32_t slot0,
+                              int32_t *__restrict__ next_off, uint32_t *__restrict__ next_perm)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < np0) {
+        // the present particle's tet: the last one whose range starts at or before it
+        int lo = 0, hi = nt;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        next_perm[g + noff_new[lo]] = perm[g];
+    } else if (g < np0 + n) {
+        const int64_t q = g - np0;
+        next_perm[off[nkey[q] + 1] + q] = slot0 + nval[q];
+    } else if (g <= np0 + n + nt) {
+        const int64_t t = g - np0 - n;
+        next_off[t] = off[t] + noff_new[t];
+    }
+}
+
+hipError_t launch_merge_order(int64_t np0, int64_t n, int32_t nt, const int32_t *off, const int32_t *noff_new,
+                              const uint32_t *perm, const uint32_t *nkey, const uint32_t *nval, uint32_t slot0,
+                              int32_t *next_off, uint32_t *next_perm, hipStream_t s)
+{
+    const int64_t w = np0 + n + nt + 1;
+    hipLaunchKernelGGL(k_merge_order, dim3(nblk(w)), dim3(BLK), 0, s, np0, n, nt, off, noff_new, perm, nkey, nval,
+                       slot0, next_off, next_perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_tet_keys(DevParticles p, int64_t n, uint32_t *keys, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

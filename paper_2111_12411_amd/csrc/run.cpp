@@ -512,6 +512,7 @@ void Run::alloc_particles(int64_t n, int64_t cap_want)
         B.d.cap = cap;
     }
     cur = 0;
+    rows_used = n;
     perm_valid = false;
     counts_known = false;
     // particle sort
@@ -607,6 +608,24 @@ void Run::next_order(int64_t nrec, const uint32_t *srec)
                           p_perr, stream));
 }
 
+// The new rows [base, base + n) of the current buffer set join the current order
+// of its np0 particles:
+// each tet keeps its particles in their order and takes its new ones after
+// them, in row order (what a stable sort of the appended state by tet gives).
+// The keys of the new rows are sorted with the spill-record sort buffers.
+void Run::merge_order(int64_t np0, int64_t base, int64_t n)
+{
+    sort_current();
+    HIPCHECK(launch_tet_keys(part_rows(pb[cur].d, base), n, ssort.key[0], stream));
+    int res = 0;
+    HIPCHECK(radix_sort(ssort, n, key_bits(), true, &res, stream, nullptr));
+    HIPCHECK(launch_offsets(ssort.key[res], n, (int32_t)m.nt, (int32_t *)d_soff.p, stream));
+    next_perm = cur_perm == psort.val[0] ? psort.val[1] : psort.val[0];
+    HIPCHECK(launch_merge_order(np0, n, (int32_t)m.nt, (const int32_t *)d_off.p, (const int32_t *)d_soff.p, cur_perm,
+                                ssort.key[res], ssort.val[res], (uint32_t)base, (int32_t *)d_noff.p, next_perm, stream));
+    commit_order();
+}
+
 void Run::commit_order()
 {
     std::swap(d_off.p, d_noff.p);
@@ -659,6 +678,7 @@ void Run::load(const double *pos, const double *vel, int64_t n, double q_, doubl
         const uint32_t *perm = sort_current();
         HIPCHECK(launch_permute(mixed, pb[0].d, pb[1].d, perm, n, stream));
         cur = 1;
+        rows_used = n;
         perm_valid = false;
     }
     // Gauss reference charge
@@ -699,10 +719,20 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
     rho_a.alloc(N0i * 8);
     rho_b.alloc(N0i * 8);
     compute_rho((double *)rho_a.p);
-    gather_current();
-    cur = 1 - cur;  // the gathered, tet-sorted rows are now the state
     const int64_t np0 = np, np1 = np0 + n, id0 = np_loaded;
-    if (np1 > pb[cur].d.cap) {
+    // With room in the current buffer set the new rows go after every row that may
+    // hold a particle (the last step wrote rows [0, rows_used); the particles it
+    // absorbed left holes there) and are merged into the current particle order
+    // (below); otherwise the state is gathered into tet order, grown, and the
+    // next step sorts the whole set.
+    int64_t base = rows_used;
+    const bool room = base + n <= pb[cur].d.cap;
+    if (!room) {
+        gather_current();
+        cur = 1 - cur;  // the gathered, tet-sorted rows are now the state
+        base = np0;
+    }
+    if (!room) {
         // grow by half again, keeping the gathered rows
         PBufs old = std::move(pb[cur]);
         const int64_t oc = old.d.cap;
@@ -725,9 +755,9 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
             locate_host(pos, n, tets.data());
             for (int64_t i = 0; i < n; i++) unit_set<int32_t>(img, n, part_layout(mixed).tet, i, tets[i]);
         }
-        rows_put(B, np0, n, img);
+        rows_put(B, base, n, img);
     }
-    const DevParticles nw = part_rows(B.d, np0);
+    const DevParticles nw = part_rows(B.d, base);
     if (m.is_cube) {
         HIPCHECK(hipMemsetAsync(p_small, 0, 4, stream));
         HIPCHECK(launch_locate_cube(dm, n, nw, p_small, stream));
@@ -740,9 +770,11 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
     if (prm.pusher != FEMPIC_PUSH_BORIS)
         HIPCHECK(launch_startup(order, mixed, dm, (const double *)d_e.p, (const double *)gather_b(),
                                 (const float *)d_e32.p, (const float *)d_b32.p, nw, n, q / mass, prm.dt, stream));
+    if (room) merge_order(np0, base, n);
+    rows_used = base + n;
     np = np1;
     np_loaded = id0 + n;
-    perm_valid = false;
+    if (!room) perm_valid = false;
     counts_known = false;
     // rho~^0 += the new particles' charge (rho~ after minus rho~ before)
     compute_rho((double *)rho_b.p);
@@ -976,6 +1008,7 @@ void Run::particle_phase()
     }
     commit_order();
     cur = 1 - cur;
+    rows_used = np;  // the step wrote rows [0, np) (holes where particles left)
     // particles absorbed at a wall are not in the new order
     np -= last_absorb;
     absorbed_total += last_absorb;
@@ -1956,6 +1989,7 @@ void Run::restore(const char *path)
         col(L.tet, (const char *)tet.data(), 4);
         col(L.id, (const char *)id.data(), 4);
         rows_put(pb[0], 0, n, img);
+        rows_used = n;
     }
     auto get = [&](void *d, const void *src, size_t bytes) {
         if (bytes) HIPCHECK(hipMemcpy(d, src, bytes, hipMemcpyHostToDevice));

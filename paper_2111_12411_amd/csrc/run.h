@@ -158,6 +158,9 @@ class Run {
     void particle_phase();
     void next_order(int64_t nrec, const uint32_t *srec);
     void commit_order();
+    void merge_order(int64_t np0, int64_t base, int64_t n);
+    // rows of the current buffer set that may hold a particle: [0, rows_used)
+    int64_t rows_used = 0;
     void field_phase();
     void field_phase_three_level();
     void solve_fp64();
