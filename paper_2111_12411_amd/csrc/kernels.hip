@@ -2237,8 +2237,30 @@ hipError_t launch_tet_keys(DevParticles p, int64_t n, uint32_t *keys, hipStream_
     return hipGetLastError();
 }
 
+// the same offsets for few keys over many buckets (a host count below nt): one
+// thread per bucket finds its first key by bisection, so that no thread walks a
+// long run of empty buckets
+__global__ void k_offsets_sparse(const uint32_t *__restrict__ key, int64_t n, int32_t nt, int32_t *__restrict__ off,
+                                 const int32_t *__restrict__ dn)
+{
+    n = dev_count(n, dn);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > nt) return;
+    int64_t lo = 0, hi = n;  // first index whose key (clamped to nt) is >= t
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (min((int64_t)key[mid], (int64_t)nt) < t) lo = mid + 1;
+        else hi = mid;
+    }
+    off[t] = (int32_t)lo;
+}
+
 hipError_t launch_offsets(const uint32_t *key, int64_t n, int32_t nt, int32_t *off, hipStream_t s, const int32_t *dn)
 {
+    if (n < (int64_t)nt) {
+        hipLaunchKernelGGL(k_offsets_sparse, dim3(nblk((int64_t)nt + 1)), dim3(BLK), 0, s, key, n, nt, off, dn);
+        return hipGetLastError();
+    }
     // with a device count, n may come out as 0: then nt + 1 threads clear off
     const int64_t w = dn ? std::max<int64_t>(n, (int64_t)nt + 1) : (n > 0 ? n : (int64_t)nt + 1);
     hipLaunchKernelGGL(k_offsets, dim3(nblk(w)), dim3(BLK), 0, s, key, n, nt, off, dn);

@@ -714,10 +714,8 @@ void Run::inject(const double *pos, const double *vel, int64_t n)
         if (!std::isfinite(pos[k]) || !std::isfinite(vel[k]))
             throw Error(FEMPIC_EINVAL, "particle " + std::to_string(k / 3) + " has a non-finite position or velocity");
     if (n == 0) return;
-    const int64_t N0i = std::max<int64_t>(m.N0_int, 1);
-    DevBuf rho_a, rho_b;
-    rho_a.alloc(N0i * 8);
-    rho_b.alloc(N0i * 8);
+    // rho~ before and after, in the Gauss check's scratch vectors (N0_int each)
+    DevBuf &rho_a = d_GtDe, &rho_b = d_Gtg;
     compute_rho((double *)rho_a.p);
     const int64_t np0 = np, np1 = np0 + n, id0 = np_loaded;
     // With room in the current buffer set the new rows go after every row that may

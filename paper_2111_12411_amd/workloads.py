@@ -37,6 +37,22 @@ def _clip(x):
     return np.clip(x, _EDGE, 1.0 - _EDGE)
 
 
+def wall_beam(n, seed, L=1.0, vz=0.167, rb=0.4, vth=0.005):
+    """A beam entering through the wall z = 0 (the shape of the paper's beam source, Table III:
+    v0/c = 0.167, beam radius 0.4 of the half width): positions uniform over the disc of radius
+    rb L / 2 about the wall's centre, on z = 0; velocities vz c along z plus a thermal spread,
+    the z component kept positive."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = 0.5 * rb * L * np.sqrt(rng.random(n))
+    phi = 2.0 * np.pi * rng.random(n)
+    pos = np.zeros((n, 3))
+    pos[:, 0] = 0.5 * L + r * np.cos(phi)
+    pos[:, 1] = 0.5 * L + r * np.sin(phi)
+    vel = rng.normal(0.0, vth * C_LIGHT, (n, 3))
+    vel[:, 2] = vz * C_LIGHT + np.abs(vel[:, 2])
+    return pos, vel
+
+
 def particles(kind, n, seed, L=1.0, vth=0.01, drift=0.1):
     """Positions (n,3) and velocities (n,3) in SI units."""
     rng = np.random.Generator(np.random.PCG64(seed))
