@@ -243,6 +243,23 @@ int32_t fempic_fields_set(fempic_run run, const double *e, int64_t ne, const dou
  * n1 entries; zero on the walls). */
 int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n);
 
+/* The matrix of the implicit field update (Sec. III-A, eq. (maxwell_semi), in
+ * the Newmark-beta form of Sec. III-B: A = *eps + (beta/gamma)^2 dt^2 K^T *nu K,
+ * plus dt/2 *I with absorbing walls) applied to W1 coefficients: y = A x over
+ * the unknown W1 DoFs.
+ * x and y have n >= n1 entries in the natural numbering (as fields_get's e);
+ * entries of x on PEC walls are ignored and those of y are set to 0.
+ * form: FEMPIC_OP_ASSEMBLED, the assembled FP64 matrix (the one the solve's
+ * residuals use), or FEMPIC_OP_ITERATION, the form its PCG iterations apply:
+ * in the iterations' precision (FP32 for the inner solve of mixed precision)
+ * and, with PEC walls, tet by tet from the geometry instead of the assembled
+ * matrix (unless FEMPIC_MATFREE=0 was set when the run was made).  Host
+ * buffers; synchronous.  EINVAL for a short buffer, a non-finite x or an
+ * unknown form. */
+#define FEMPIC_OP_ASSEMBLED 0
+#define FEMPIC_OP_ITERATION 1
+int32_t fempic_field_matvec(fempic_run run, const double *x, double *y, int64_t n, int32_t form);
+
 /* Nodal charge measured with the order-k W0 functions (Sec. III-A: charge on
  * the primal nodes; Sec. IV-D, the Gauss check): rho[j] = q w sum_p W0_j(r_p)
  * at the current positions, and rho0 the reference taken at load (natural W0

@@ -16,6 +16,7 @@ FP64, MIXED = 0, 1
 REFLECT, ABSORB = 0, 1
 PUSH_AB4, PUSH_BORIS = 0, 1
 FIELD_PEC, FIELD_ABSORB = 0, 1
+OP_ASSEMBLED, OP_ITERATION = 0, 1
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EMESH", -4: "EOUTSIDE", -5: "ECROSS", -6: "ESOLVE",
           -7: "EDEVICE", -8: "EAGAIN", -9: "EBUSY"}
 
@@ -85,6 +86,7 @@ SYMBOLS = {
     "fempic_fields_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_fields_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "fempic_deposit_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "fempic_field_matvec": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32]),
     "fempic_rho_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_particles_inject": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "fempic_particles_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
@@ -282,6 +284,16 @@ class Run:
         d = np.zeros(self.info["n1"])
         _check(lib().fempic_deposit_get(self.h, _p(d), len(d)))
         return d
+
+    def field_matvec(self, x, form=None):
+        """y = A x with the field update's matrix (fempic_field_matvec), natural W1 numbering;
+        form OP_ASSEMBLED (default) or OP_ITERATION."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.info["n1"])
+        if len(x) < len(y):
+            raise ValueError("x needs n1 entries")
+        _check(lib().fempic_field_matvec(self.h, _p(x), _p(y), len(y), OP_ASSEMBLED if form is None else form))
+        return y
 
     def rho(self):
         """Nodal charge now and at load (fempic_rho_get), natural W0 numbering."""

@@ -226,6 +226,23 @@ struct DevCSR {
     const double *bval;
     const float *bval32;
 };
+// The field system's operator with PEC walls, A = eps0 M1 + c S / mu0, applied
+// tet by tet without the assembled matrix: each tet's product from its gradients
+// and volume (k_mf_elem), then each unknown DoF sums its tets' products in tet
+// order (k_mf_sum).  The operands and geo/pe are in one precision (FP64 for
+// mf_apply, FP32 for mf_apply32).
+struct DevMF {
+    int order;            // 1 or 2; 0: not in use (the assembled matrix is)
+    int64_t nt, n1s;      // tets; unknown W1 DoFs (the internal ids below n1s)
+    const int32_t *map1;  // [nt][n1l] internal W1 ids
+    const void *geo;      // [nt][16]: grad l_0..l_3 (x, y, z), the volume, 3 unused
+    const int64_t *ptr;   // per unknown DoF i: its incidences t n1l + l in [ptr[i], ptr[i+1]), tet-ascending
+    const int32_t *idx;
+    void *pe;             // [nt][n1l] the tets' products
+    double kM, kC;        // eps0 and c / mu0 (c: the curl-curl term's coefficient times dt^2)
+};
+hipError_t mf_apply(const DevMF &mf, const double *x, double *y, hipStream_t s);
+hipError_t mf_apply32(const DevMF &mf, const float *x, float *y, hipStream_t s);
 hipError_t spmv(const DevCSR &A, const double *x, double *y, double alpha, double beta, const double *z,
                 hipStream_t s);  // y = alpha A x + beta z (z may alias y or be null when beta == 0)
 hipError_t spmv32(const DevCSR &A, const float *x, float *y, hipStream_t s);
@@ -239,13 +256,14 @@ hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y
 enum { SC_RZ = 0, SC_PQ = 1, SC_RR = 4, SC_BB = 5 };
 hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
                     double *partial, double *scalars, bool block, hipStream_t s);
-hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
-                    const double *dinv, double *partial, double *scalars, int par, hipStream_t s);
+// mf (nullable): apply A tet by tet instead of the assembled matrix when mf->order != 0
+hipError_t pcg_iter(const DevCSR &A, const DevMF *mf, int64_t n, double *x, double *r, double *z, double *p,
+                    double *q, const double *dinv, double *partial, double *scalars, int par, hipStream_t s);
 // FP32 inner PCG (mixed mode); vectors float, scalars double
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
                       double *partial, double *scalars, bool block, hipStream_t s);
-hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
-                      double *partial, double *scalars, int par, hipStream_t s);
+hipError_t pcg32_iter(const DevCSR &A, const DevMF *mf, int64_t n, float *x, float *r, float *z, float *p, float *q,
+                      const float *dinv, double *partial, double *scalars, int par, hipStream_t s);
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s);
 hipError_t add_f2d(int64_t n, const float *in, double scale, double *out, hipStream_t s);
 

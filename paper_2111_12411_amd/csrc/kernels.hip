@@ -1874,6 +1874,285 @@ __global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__r
     }
 }
 
+// ------------------------------------------------ system operator, tet by tet
+// A = eps0 M1 + c S / mu0 applied without the assembled matrix.  In a tet,
+// E = sum_j x_j W1_j = sum_m P_m(l) grad l_m, with P_m a homogeneous polynomial
+// of degree K in the barycentric coordinates (every W1_j is (qc + qs l_v) times
+// l_a grad l_b - l_b grad l_a, and l_a = l_a (l_0 + ... + l_3)).  Then
+//   int_T E.E' = sum_{m,n} (grad l_m . grad l_n) int_T P_m P'_n,
+//   curl E = sum_{n<m} (dP_m/dl_n - dP_n/dl_m) grad l_n x grad l_m,
+// and the monomial integrals are exact: (1/V) int_T l^a = 6 a! / (|a| + 3)!
+// (a! = a_0! a_1! a_2! a_3!).  The product A x is the derivative of the
+// tet's energy, so it takes the transposes of the same linear maps.
+
+// monomials of degree 2: (a, b), a <= b, in the order 00 01 02 03 11 12 13 22 23 33
+__host__ __device__ constexpr int mono2(int a, int b)
+{
+    return a <= b ? a * 4 - a * (a - 1) / 2 + (b - a) : b * 4 - b * (b - 1) / 2 + (a - b);
+}
+__host__ __device__ constexpr int mono2_a(int u) { return u < 4 ? 0 : (u < 7 ? 1 : (u < 9 ? 2 : 3)); }
+__host__ __device__ constexpr int mono2_b(int u) { return u < 4 ? u : (u < 7 ? u - 3 : (u < 9 ? u - 5 : 3)); }
+// local edges (a, b) and faces as compile-time functions (the same numbering as
+// EA, EB and FV): face f is opposite vertex 3 - f
+__host__ __device__ constexpr int ea_(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
+__host__ __device__ constexpr int eb_(int p) { return p < 3 ? p + 1 : (p < 5 ? p - 1 : 3); }
+__host__ __device__ constexpr int fv_(int f, int i) { return i < 3 - f ? i : i + 1; }
+static_assert(ea_(0) == 0 && eb_(0) == 1 && ea_(3) == 1 && eb_(3) == 2 && ea_(4) == 1 && eb_(4) == 3 &&
+                  ea_(5) == 2 && eb_(5) == 3,
+              "local edges");
+static_assert(fv_(0, 2) == 2 && fv_(1, 2) == 3 && fv_(2, 1) == 2 && fv_(3, 0) == 1, "local faces");
+static_assert(mono2(0, 3) == 3 && mono2(1, 1) == 4 && mono2(3, 2) == 8 && mono2_a(7) == 2 && mono2_b(6) == 3,
+              "degree-2 monomials");
+__host__ __device__ constexpr int fact(int n) { return n <= 1 ? 1 : n * fact(n - 1); }
+// (1/V) int_T of l_i l_j l_k l_l (degree 4) and of l_i l_j (degree 2)
+__host__ __device__ constexpr double gram4(int i, int j, int k, int l)
+{
+    int a[4] = {0, 0, 0, 0};
+    a[i]++;
+    a[j]++;
+    a[k]++;
+    a[l]++;
+    return 6.0 * fact(a[0]) * fact(a[1]) * fact(a[2]) * fact(a[3]) / fact(7);
+}
+__host__ __device__ constexpr double gram2(int i, int j) { return i == j ? 0.1 : 0.05; }
+
+template <int K>
+struct MonoN;
+template <>
+struct MonoN<1> {
+    static constexpr int NM = 4, NS = 1;
+};
+template <>
+struct MonoN<2> {
+    static constexpr int NM = 10, NS = 4;
+};
+
+// the coefficients of the P_m as linear maps of the tet's W1 coefficients:
+// f(j, m, u, c) for every term "P_m contains c x_j times monomial u"
+template <int K, typename F>
+__device__ __forceinline__ void w1_terms(F &&f)
+{
+    if constexpr (K == 1) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            f(e, eb_(e), ea_(e), 1.0f);   // l_a grad l_b
+            f(e, ea_(e), eb_(e), -1.0f);  // - l_b grad l_a
+        }
+    } else {
+        // l_a as the sum over n of l_a l_n
+        auto lin = [&](int j, int m, int a, float c) {
+#pragma unroll
+            for (int n = 0; n < 4; n++) f(j, m, mono2(a, n), c);
+        };
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int a = ea_(e), b = eb_(e);
+            // DoF 2e: (3 l_a - 1) W_ab ; DoF 2e+1: (3 l_b - 1) W_ab
+            f(2 * e, b, mono2(a, a), 3.0f);
+            lin(2 * e, b, a, -1.0f);
+            f(2 * e, a, mono2(a, b), -3.0f);
+            lin(2 * e, a, b, 1.0f);
+            f(2 * e + 1, b, mono2(a, b), 3.0f);
+            lin(2 * e + 1, b, a, -1.0f);
+            f(2 * e + 1, a, mono2(b, b), -3.0f);
+            lin(2 * e + 1, a, b, 1.0f);
+        }
+#pragma unroll
+        for (int fc = 0; fc < 4; fc++) {
+            const int a = fv_(fc, 0), b = fv_(fc, 1), c = fv_(fc, 2);
+            // DoF 12+2f: 3 l_c W_ab ; DoF 13+2f: 3 l_b W_ac
+            f(12 + 2 * fc, b, mono2(a, c), 3.0f);
+            f(12 + 2 * fc, a, mono2(b, c), -3.0f);
+            f(13 + 2 * fc, c, mono2(a, b), 3.0f);
+            f(13 + 2 * fc, a, mono2(b, c), -3.0f);
+        }
+    }
+}
+
+// coefficient of monomial v (degree K-1) in dP/dl_i for the monomial u of P
+// (degree K): d(l_a l_b)/dl_i over the degree-1 monomials; degree 1: d l_a / dl_i
+template <int K>
+__device__ __forceinline__ constexpr float dmono(int u, int i, int v)
+{
+    if constexpr (K == 1) {
+        return u == i ? 1.0f : 0.0f;
+    } else {
+        const int a = mono2_a(u), b = mono2_b(u);
+        if (a == b) return (a == i && v == a) ? 2.0f : 0.0f;
+        return (a == i && v == b) || (b == i && v == a) ? 1.0f : 0.0f;
+    }
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__restrict__ map1, int64_t n1s,
+                                                 const T *__restrict__ geo, const T *__restrict__ x, T kM, T kC,
+                                                 T *__restrict__ pe)
+{
+    constexpr int N1 = Ord<K>::N1, NM = MonoN<K>::NM, NS = MonoN<K>::NS;
+    const int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    if (t >= nt) return;
+    const gptr<const T> gg = glb(geo) + t * 16;
+    T gl[4][3];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) gl[m][c] = gg[3 * m + c];
+    const T vol = gg[12];
+    T xl[N1];
+    {
+        const gptr<const int32_t> mp = glb(map1) + t * N1;
+        int32_t d[N1];
+#pragma unroll
+        for (int j = 0; j < N1; j++) d[j] = mp[j];
+#pragma unroll
+        for (int j = 0; j < N1; j++) xl[j] = d[j] < n1s ? x[d[j]] : T(0);
+    }
+    // P_m coefficients
+    T C[4][NM];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int u = 0; u < NM; u++) C[m][u] = T(0);
+    w1_terms<K>([&](int j, int m, int u, float c) { C[m][u] += T(c) * xl[j]; });
+    // grad l_m . grad l_n and (grad l_a x grad l_b) . (grad l_c x grad l_d)
+    T g[4][4], X[6][3], G2[6][6];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int n = m; n < 4; n++) g[m][n] = g[n][m] = gl[m][0] * gl[n][0] + gl[m][1] * gl[n][1] + gl[m][2] * gl[n][2];
+#pragma unroll
+    for (int p = 0; p < 6; p++) cross3(gl[ea_(p)], gl[eb_(p)], X[p]);
+#pragma unroll
+    for (int p = 0; p < 6; p++)
+#pragma unroll
+        for (int q = p; q < 6; q++) G2[p][q] = G2[q][p] = X[p][0] * X[q][0] + X[p][1] * X[q][1] + X[p][2] * X[q][2];
+    // curl: S_p = dP_m/dl_n - dP_n/dl_m for the pair p = (n, m), n < m
+    T S[6][NS];
+#pragma unroll
+    for (int p = 0; p < 6; p++) {
+        const int n = ea_(p), m = eb_(p);
+#pragma unroll
+        for (int v = 0; v < NS; v++) {
+            T s = T(0);
+#pragma unroll
+            for (int u = 0; u < NM; u++) {
+                const float d1 = dmono<K>(u, n, v), d2 = dmono<K>(u, m, v);
+                if (d1 != 0.0f) s += T(d1) * C[m][u];
+                if (d2 != 0.0f) s -= T(d2) * C[n][u];
+            }
+            S[p][v] = s;
+        }
+    }
+    // mass: D[m] = kM V sum_n g[m][n] H C[n], H the degree-K Gram matrix
+    T D[4][NM];
+    {
+        T h[4][NM];
+#pragma unroll
+        for (int n = 0; n < 4; n++)
+#pragma unroll
+            for (int u = 0; u < NM; u++) {
+                T s = T(0);
+#pragma unroll
+                for (int w = 0; w < NM; w++) {
+                    if constexpr (K == 1) s += T(gram2(u, w)) * C[n][w];
+                    else s += T(gram4(mono2_a(u), mono2_b(u), mono2_a(w), mono2_b(w))) * C[n][w];
+                }
+                h[n][u] = s;
+            }
+        const T sm = kM * vol;
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+#pragma unroll
+            for (int u = 0; u < NM; u++)
+                D[m][u] = sm * (g[m][0] * h[0][u] + g[m][1] * h[1][u] + g[m][2] * h[2][u] + g[m][3] * h[3][u]);
+    }
+    // curl: dS[p] = kC V sum_q G2[p][q] H' S[q] (H' the degree-(K-1) Gram matrix), then
+    // the transpose of the map C -> S into D
+    {
+        T hs[6][NS];
+#pragma unroll
+        for (int q = 0; q < 6; q++)
+#pragma unroll
+            for (int v = 0; v < NS; v++) {
+                if constexpr (K == 1) {
+                    hs[q][v] = S[q][v];
+                } else {
+                    T s = T(0);
+#pragma unroll
+                    for (int w = 0; w < NS; w++) s += T(gram2(v, w)) * S[q][w];
+                    hs[q][v] = s;
+                }
+            }
+        const T sc = kC * vol;
+#pragma unroll
+        for (int p = 0; p < 6; p++) {
+            const int n = ea_(p), m = eb_(p);
+#pragma unroll
+            for (int v = 0; v < NS; v++) {
+                T ds = T(0);
+#pragma unroll
+                for (int q = 0; q < 6; q++) ds += G2[p][q] * hs[q][v];
+                ds *= sc;
+#pragma unroll
+                for (int u = 0; u < NM; u++) {
+                    const float d1 = dmono<K>(u, n, v), d2 = dmono<K>(u, m, v);
+                    if (d1 != 0.0f) D[m][u] += T(d1) * ds;
+                    if (d2 != 0.0f) D[n][u] -= T(d2) * ds;
+                }
+            }
+        }
+    }
+    T yl[N1];
+#pragma unroll
+    for (int j = 0; j < N1; j++) yl[j] = T(0);
+    w1_terms<K>([&](int j, int m, int u, float c) { yl[j] += T(c) * D[m][u]; });
+    const gptr<T> po = glb(pe) + t * N1;
+#pragma unroll
+    for (int j = 0; j < N1; j++) po[j] = yl[j];
+}
+
+// y_i = sum of the tets' products over the incidences of unknown DoF i, in tet
+// order; optional fused partial dot(dotv, y) per workgroup (fixed order)
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_mf_sum(int64_t n, const int64_t *__restrict__ ptr,
+                                                const int32_t *__restrict__ idx, const T *__restrict__ pe,
+                                                T *__restrict__ y, const T *__restrict__ dotv,
+                                                double *__restrict__ partial)
+{
+    __shared__ double s_red[BLK];
+    constexpr int U = 8;
+    const int tid = threadIdx.x;
+    double d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BLK + tid; i < n; i += (int64_t)gridDim.x * BLK) {
+        const int64_t kb = ptr[i], ke = ptr[i + 1];
+        const T w = dotv ? dotv[i] : T(0);
+        T s = T(0);
+        for (int64_t k = kb; k < ke; k += U) {
+            // entries past the row's end load its last one again and are not added
+            int32_t ix[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) ix[u] = idx[min(k + u, ke - 1)];
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) v[u] = pe[ix[u]];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (k + u < ke) s += v[u];
+        }
+        y[i] = s;
+        d += (double)w * (double)s;
+    }
+    if (partial) {
+        s_red[tid] = d;
+        __syncthreads();
+        for (int o = BLK / 2; o > 0; o >>= 1) {
+            if (tid < o) s_red[tid] += s_red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) partial[blockIdx.x] = s_red[0];
+    }
+}
+
 // fixed-order sum of n partials (one block of 1024 threads), k values interleaved
 __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ partial, int64_t n, int k,
                                                  double *__restrict__ out)
@@ -2453,11 +2732,32 @@ hipError_t pcg_init_t(int64_t n, const T *b, T *x, T *r, T *z, T *p, const T *di
 }
 
 template <typename T>
-hipError_t pcg_iter_t(const DevCSR &A, const T *val, int64_t n, T *x, T *r, T *z, T *p, T *q, const T *dinv,
-                      double *partial, double *sc, int par, hipStream_t s)
+hipError_t mf_apply_t(const DevMF &mf, const T *x, T *y, const T *dotv, double *partial, unsigned &grid,
+                      hipStream_t s)
+{
+    grid = red_grid(mf.n1s, BLK);
+    if (mf.nt > 0) {
+        const unsigned ge = (unsigned)((mf.nt + BLK - 1) / BLK);
+        if (mf.order == 1)
+            hipLaunchKernelGGL((k_mf_elem<1, T>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+        else
+            hipLaunchKernelGGL((k_mf_elem<2, T>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+    }
+    if (mf.n1s > 0)
+        hipLaunchKernelGGL(k_mf_sum<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s, mf.ptr, mf.idx, (const T *)mf.pe, y,
+                           dotv, partial);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_iter_t(const DevCSR &A, const T *val, const DevMF *mf, int64_t n, T *x, T *r, T *z, T *p, T *q,
+                      const T *dinv, double *partial, double *sc, int par, hipStream_t s)
 {
     unsigned g1;
-    hipError_t err = spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, g1, s);
+    hipError_t err = mf && mf->order ? mf_apply_t<T>(*mf, p, q, p, partial, g1, s)
+                                     : spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, g1, s);
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g1, 1, sc + SC_PQ);
     const bool block = A.bptr != nullptr;
@@ -2478,10 +2778,22 @@ hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z,
     return pcg_init_t<double>(n, b, x, r, z, p, dinv, partial, sc, block, s);
 }
 
-hipError_t pcg_iter(const DevCSR &A, int64_t n, double *x, double *r, double *z, double *p, double *q,
-                    const double *dinv, double *partial, double *sc, int par, hipStream_t s)
+hipError_t pcg_iter(const DevCSR &A, const DevMF *mf, int64_t n, double *x, double *r, double *z, double *p,
+                    double *q, const double *dinv, double *partial, double *sc, int par, hipStream_t s)
 {
-    return pcg_iter_t<double>(A, A.val, n, x, r, z, p, q, dinv, partial, sc, par, s);
+    return pcg_iter_t<double>(A, A.val, mf, n, x, r, z, p, q, dinv, partial, sc, par, s);
+}
+
+hipError_t mf_apply(const DevMF &mf, const double *x, double *y, hipStream_t s)
+{
+    unsigned g;
+    return mf_apply_t<double>(mf, x, y, nullptr, nullptr, g, s);
+}
+
+hipError_t mf_apply32(const DevMF &mf, const float *x, float *y, hipStream_t s)
+{
+    unsigned g;
+    return mf_apply_t<float>(mf, x, y, nullptr, nullptr, g, s);
 }
 
 hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, float *p, const float *dinv,
@@ -2490,10 +2802,10 @@ hipError_t pcg32_init(int64_t n, const float *b, float *x, float *r, float *z, f
     return pcg_init_t<float>(n, b, x, r, z, p, dinv, partial, sc, block, s);
 }
 
-hipError_t pcg32_iter(const DevCSR &A, int64_t n, float *x, float *r, float *z, float *p, float *q, const float *dinv,
-                      double *partial, double *sc, int par, hipStream_t s)
+hipError_t pcg32_iter(const DevCSR &A, const DevMF *mf, int64_t n, float *x, float *r, float *z, float *p, float *q,
+                      const float *dinv, double *partial, double *sc, int par, hipStream_t s)
 {
-    return pcg_iter_t<float>(A, A.val32, n, x, r, z, p, q, dinv, partial, sc, par, s);
+    return pcg_iter_t<float>(A, A.val32, mf, n, x, r, z, p, q, dinv, partial, sc, par, s);
 }
 
 hipError_t cast_d2f(int64_t n, const double *in, float *out, double scale, hipStream_t s)

@@ -323,6 +323,36 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
     upload(d_inc_idx, ops.inc_idx, stream);
     upload(d_inc0_ptr, ops.inc0_ptr, stream);
     upload(d_inc0_idx, ops.inc0_idx, stream);
+    // the PCG iterations apply A tet by tet (PEC walls; FEMPIC_MATFREE=0 keeps the
+    // assembled matrix): per tet the gradients of l_0..l_3 and the volume, in the
+    // precision of the iterations (FP32 inner solve in mixed precision)
+    {
+        const char *mfe = std::getenv("FEMPIC_MATFREE");
+        const bool mf_on = !absorbing && !(mfe && std::strcmp(mfe, "0") == 0);
+        mf = DevMF{};
+        if (mf_on) {
+            const int64_t nt = m.nt;
+            std::vector<double> g64((size_t)nt * 16, 0.0);
+            for (int64_t t = 0; t < nt; t++) {
+                for (int v = 0; v < 4; v++)
+                    for (int c = 0; c < 3; c++) g64[16 * t + 3 * v + c] = m.geo[16 * t + 4 * v + 1 + c];
+                g64[16 * t + 12] = m.vol[t];
+            }
+            if (mixed) {
+                std::vector<float> g32(g64.begin(), g64.end());
+                upload(d_mfgeo, g32, stream);
+                HIPCHECK(hipStreamSynchronize(stream));
+                d_mfpe.alloc((size_t)nt * n1l * 4);
+            } else {
+                upload(d_mfgeo, g64, stream);
+                HIPCHECK(hipStreamSynchronize(stream));
+                d_mfpe.alloc((size_t)nt * n1l * 8);
+            }
+            const double c_dt2 = (p.beta / p.gamma) * (p.beta / p.gamma);
+            mf = DevMF{order, nt, n1s, (const int32_t *)d_map1.p, d_mfgeo.p, (const int64_t *)d_inc_ptr.p,
+                       (const int32_t *)d_inc_idx.p, d_mfpe.p, EPS0, c_dt2 * p.dt * p.dt / MU0};
+        }
+    }
     nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Mnu.nnz() + ops.K.nnz() + ops.Kt.nnz() + ops.Gt.nnz();
     a_nnz = ops.A.nnz();
     // fields and solver vectors
@@ -1127,10 +1157,10 @@ void Run::pcg_batch(bool fp32)
     auto launch = [&]() {
         for (int k = 0; k < 8; k++) {
             if (fp32)
-                HIPCHECK(pcg32_iter(A.desc, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
+                HIPCHECK(pcg32_iter(A.desc, &mf, n, (float *)f_x.p, (float *)f_r.p, (float *)f_z.p, (float *)f_p.p,
                                     (float *)f_q.p, (const float *)d_dinv32.p, part, sc, k & 1, stream));
             else
-                HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                HIPCHECK(pcg_iter(A.desc, &mf, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
                                   (double *)v_q.p, (const double *)d_dinv.p, part, sc, k & 1, stream));
         }
     };
@@ -1175,7 +1205,7 @@ double Run::pcg64(const double *b, double tol2, double bb)
             it += 8;
         } else {
             for (; it < prm.pcg_maxit; it++)
-                HIPCHECK(pcg_iter(A.desc, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
+                HIPCHECK(pcg_iter(A.desc, &mf, n, (double *)v_x.p, (double *)v_r.p, (double *)v_z.p, (double *)v_p.p,
                                   (double *)v_q.p, (const double *)d_dinv.p, part, sc, it & 1, stream));
         }
         rr = read_sc(SC_RR);
@@ -1497,6 +1527,38 @@ void Run::deposit_get(double *dg, int64_t n)
     HIPCHECK(hipMemcpy(d.data(), d_dg.p, n1s * 8, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < m.N1; i++) dg[i] = 0.0;
     for (int64_t k = 0; k < n1s; k++) dg[m.int2nat1[k]] = d[k];
+}
+
+void Run::field_matvec(const double *x, double *y, int64_t n, int form)
+{
+    sync();
+    if (n < m.N1) throw Error(FEMPIC_EINVAL, "buffer too short");
+    if (form != FEMPIC_OP_ASSEMBLED && form != FEMPIC_OP_ITERATION) throw Error(FEMPIC_EINVAL, "unknown operator form");
+    std::vector<double> xi(std::max<int64_t>(n1s, 1), 0.0);
+    for (int64_t i = 0; i < m.N1; i++) {
+        if (!std::isfinite(x[i])) throw Error(FEMPIC_EINVAL, "non-finite x");
+        const int64_t k = m.nat2int1[i];
+        if (k < n1s) xi[k] = x[i];
+    }
+    // the solver's search-direction vectors hold nothing between steps
+    std::vector<double> yi(xi.size(), 0.0);
+    if (form == FEMPIC_OP_ITERATION && mixed) {
+        std::vector<float> xf(xi.begin(), xi.end()), yf(xi.size());
+        HIPCHECK(hipMemcpyAsync(f_p.p, xf.data(), n1s * 4, hipMemcpyHostToDevice, stream));
+        if (mf.order) HIPCHECK(mf_apply32(mf, (const float *)f_p.p, (float *)f_q.p, stream));
+        else HIPCHECK(spmv32(A.desc, (const float *)f_p.p, (float *)f_q.p, stream));
+        HIPCHECK(hipMemcpyAsync(yf.data(), f_q.p, n1s * 4, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (int64_t k = 0; k < n1s; k++) yi[k] = yf[k];
+    } else {
+        HIPCHECK(hipMemcpyAsync(v_p.p, xi.data(), n1s * 8, hipMemcpyHostToDevice, stream));
+        if (form == FEMPIC_OP_ITERATION && mf.order) HIPCHECK(mf_apply(mf, (const double *)v_p.p, (double *)v_q.p, stream));
+        else HIPCHECK(spmv(A.desc, (const double *)v_p.p, (double *)v_q.p, 1.0, 0.0, nullptr, stream));
+        HIPCHECK(hipMemcpyAsync(yi.data(), v_q.p, n1s * 8, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+    for (int64_t i = 0; i < m.N1; i++) y[i] = 0.0;
+    for (int64_t k = 0; k < n1s; k++) y[m.int2nat1[k]] = yi[k];
 }
 
 // ------------------------------------------------------- impressed field
@@ -2072,6 +2134,8 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     const double precond = (k2 ? 2 : 1) * N1i * (8 + (mixed ? 4 : 0));
     const double inc = (N1i + 1) * 8 + nt * n1l * 4 + (N0i + 1) * 8 + nt * n0l * 4;
     const double mesh = nt * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
+    // the operator applied tet by tet (PEC walls): geometry and per-tet products
+    const double matfree = z.absorbing ? 0.0 : nt * (16 + n1l) * (mixed ? 4 : 8);
     double vecs = (N1 + N2) * 8 + 5 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
                   (mixed ? 5 * N1i * 4 : 0) + N2 * 8 + 4 * N0i * 8;
     vecs += 5 * N1i * 8 + N2 * 8;  // double-double halves, *nu u, the previous increment
@@ -2091,7 +2155,7 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
                          (2 * (cap / 4096 + 1) + (double)scan_tmp_entries((int64_t)(cap / 4096 + 1))) * 4 + 64;
     // every buffer is at least 16 bytes; a generous allowance for the few dozen small ones
     const double small = 64 * 1024;
-    return (size_t)(ops + precond + inc + mesh + vecs + tets + parts + sorts(cap) + pool + queue + small);
+    return (size_t)(ops + precond + inc + mesh + matfree + vecs + tets + parts + sorts(cap) + pool + queue + small);
 }
 
 FootprintSizes kuhn_sizes(int order, double nt)
@@ -2310,6 +2374,14 @@ int32_t fempic_deposit_get(fempic_run run, double *dg, int64_t n)
     API_BEGIN
     if (!run || !dg) throw Error(FEMPIC_EINVAL, "null argument");
     run->r->deposit_get(dg, n);
+    API_END
+}
+
+int32_t fempic_field_matvec(fempic_run run, const double *x, double *y, int64_t n, int32_t form)
+{
+    API_BEGIN
+    if (!run || !x || !y) throw Error(FEMPIC_EINVAL, "null argument");
+    run->r->field_matvec(x, y, n, form);
     API_END
 }
 

@@ -89,6 +89,8 @@ class Run {
     void fields_get(double *e, int64_t ne, double *b, int64_t nb);
     void fields_set(const double *e, int64_t ne, const double *b, int64_t nb);
     void deposit_get(double *dg, int64_t n);
+    // y = A x (natural W1 numbering): the assembled FP64 matrix or the PCG iterations' form
+    void field_matvec(const double *x, double *y, int64_t n, int form);
     void rho_get(double *rho, double *rho0, int64_t n);
     // impressed magnetic flux density: B sampled at the points of the n1d^3 rule
     // of every tet, projected (constrained: onto the divergence-free faces) and
@@ -195,6 +197,9 @@ class Run {
     DevCSRBuf A, Meps, Mnu, K, Kt, Gt, Zi;  // Zi: surface impedance *I (absorbing walls)
     double gscale = 1.0;  // Gt holds gscale G^T
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
+    // A applied tet by tet in the PCG iterations (order 0: the assembled matrix)
+    DevBuf d_mfgeo, d_mfpe;
+    DevMF mf{};
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
     // rounding errors of the running sums e and g (compensated summation), and
     // the low half of *eps e in the Gauss check
