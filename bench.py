@@ -83,13 +83,25 @@ def copy_bandwidth(gib=2, reps=5):
     return 2.0 * n * 4 / best / 1e9
 
 
-def pcg_bytes_per_iter(order, precision, rows, nnz):
+def pcg_bytes_per_iter(order, precision, rows, nnz, field_op=0, nt=0, inc=0):
     """Bytes one inner PCG iteration must move: q = A p with the fused dot(p, q); x, r and the
-    preconditioned residual z updated with dot(r, z); p = z + beta p.  Order 2 stores A in 2x2
-    blocks with one int32 column per block and a 2x2 block-Jacobi preconditioner, order 1 in CSR
-    with Jacobi.  Inner vectors and values are FP32 in mixed precision, FP64 otherwise."""
+    preconditioned residual z updated with dot(r, z); p = z + beta p.  Inner vectors and values are
+    FP32 in mixed precision, FP64 otherwise; order 2 has a 2x2 block-Jacobi preconditioner, order 1
+    Jacobi.
+    field_op 0: A assembled, at order 2 in 2x2 blocks with one int32 column per block, at order 1
+    in CSR.  field_op 1 or 2: A applied tet by tet (nt tets): per tet its local W1 ids (int32; one
+    per DoF pair with field_op 2) and 16 geometry words read, p read once, the n1l products written;
+    then per row of A its inc incidences (an int32 each, one per pair with field_op 2; int64 row
+    pointers) and their products read, q written and p read again for the dot."""
     vs = 4 if precision == F.MIXED else 8
-    if order == 2:
+    if field_op:
+        n1l = 20 if order == 2 else 6
+        per = 2 if field_op == 2 else 1
+        elem = nt * (n1l // per) * 4 + nt * 16 * vs + rows * vs + nt * n1l * vs
+        sums = (rows // per + 1) * 8 + (inc // per) * 4 + inc * vs + 2 * rows * vs
+        spmv = elem + sums
+        precond = (rows // 2) * 4 * vs if order == 2 else rows * vs
+    elif order == 2:
         blocks, brows = nnz // 4, rows // 2
         spmv = blocks * (4 * vs + 4) + brows * (8 + 3 * 2 * vs)  # values, column; row pointer, x, y, dot pairs
         precond = brows * 4 * vs
@@ -423,7 +435,7 @@ def main():
     achieved = alg / kernel_s / 1e9
     traffic = profiled_traffic() if args.particles is None else None
     it = max(st["pcg_iters"], 1)
-    pcg_b = pcg_bytes_per_iter(cfg["order"], F.MIXED, st["a_rows"], st["a_nnz"])
+    pcg_b = pcg_bytes_per_iter(cfg["order"], F.MIXED, st["a_rows"], st["a_nnz"], st["field_op"], nt, st["a_inc"])
     # the field phase per step divided by its inner iterations: it also holds the right-hand
     # side, the Faraday update and the FP64 refinement residuals, so the rate is a lower bound
     pcg_ms = st["field_ms"] / K / it
@@ -450,7 +462,7 @@ def main():
         "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2],
                            "ms": mix["gauss_ms"]},
         "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"], "a_rows": st["a_rows"],
-                "a_nnz": st["a_nnz"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
+                "a_nnz": st["a_nnz"], "field_op": st["field_op"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
                 "gb_s": pcg_b / (pcg_ms / 1e3) / 1e9},
         "crossings_per_particle_step": st["crossings"] / n,
         "spills_per_particle_step": st["spills"] / n,

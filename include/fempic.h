@@ -371,6 +371,10 @@ typedef struct {
     int64_t device_peak_bytes;/* and the most it has held */
     int64_t phase_replays;    /* last call: steps whose particle phase replayed a captured HIP graph (runs
                                  of a server, or FEMPIC_PHASE_GRAPHS=1 in the environment) */
+    int32_t field_op;         /* the operator the PCG iterations apply: 0 the assembled matrix, 1 tet by
+                                 tet, 2 tet by tet with the two DoFs of each edge and face taken together */
+    int64_t a_inc;            /* (tet, local position) incidences of A's rows: the products that the
+                                 tet-by-tet operator sums */
 } fempic_stats_t;
 int32_t fempic_stats(fempic_run run, fempic_stats_t *out);
 

@@ -48,7 +48,8 @@ class Stats(C.Structure):
                 ("pcg_relres", C.c_double), ("crossings", C.c_int64), ("reflections", C.c_int64),
                 ("spills", C.c_int64), ("gauss", C.c_double * 3), ("gauss_step", C.c_int64),
                 ("a_rows", C.c_int64), ("a_nnz", C.c_int64), ("device_bytes", C.c_int64),
-                ("device_peak_bytes", C.c_int64), ("phase_replays", C.c_int64)]
+                ("device_peak_bytes", C.c_int64), ("phase_replays", C.c_int64), ("field_op", C.c_int32),
+                ("a_inc", C.c_int64)]
 
 
 class ServerParams(C.Structure):

@@ -240,6 +240,13 @@ struct DevMF {
     const int32_t *idx;
     void *pe;             // [nt][n1l] the tets' products
     double kM, kC;        // eps0 and c / mu0 (c: the curl-curl term's coefficient times dt^2)
+    // optional (order 2), used when map1p is set: the two DoFs of an edge or face are
+    // the unknowns 2j, 2j+1 at local positions 2i, 2i+1 of every tet they meet.
+    // map1p [nt][n1l/2]: j of local pair i, -1 when not unknowns; ptr2/idx2: per pair
+    // j its incidences t n1l + 2i, tet-ascending
+    const int32_t *map1p;
+    const int64_t *ptr2;
+    const int32_t *idx2;
 };
 hipError_t mf_apply(const DevMF &mf, const double *x, double *y, hipStream_t s);
 hipError_t mf_apply32(const DevMF &mf, const float *x, float *y, hipStream_t s);

@@ -1983,7 +1983,10 @@ __device__ __forceinline__ constexpr float dmono(int u, int i, int v)
     }
 }
 
-template <int K, typename T>
+// PAIRS (order 2): map1 holds per tet the N1/2 pair ids j of its DoF pairs
+// (local 2i, 2i+1 are the unknowns 2j, 2j+1; -1 when they are not unknowns),
+// and x is read a pair at a time
+template <int K, typename T, bool PAIRS>
 __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__restrict__ map1, int64_t n1s,
                                                  const T *__restrict__ geo, const T *__restrict__ x, T kM, T kC,
                                                  T *__restrict__ pe)
@@ -1999,7 +2002,20 @@ __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__re
         for (int c = 0; c < 3; c++) gl[m][c] = gg[3 * m + c];
     const T vol = gg[12];
     T xl[N1];
-    {
+    if constexpr (PAIRS) {
+        static_assert(N1 % 2 == 0, "pairs");
+        using T2 = T __attribute__((ext_vector_type(2)));
+        const gptr<const int32_t> mp = glb(map1) + t * (N1 / 2);
+        int32_t d[N1 / 2];
+#pragma unroll
+        for (int j = 0; j < N1 / 2; j++) d[j] = mp[j];
+#pragma unroll
+        for (int j = 0; j < N1 / 2; j++) {
+            const T2 v = d[j] >= 0 ? *(glb((const T2 *)x) + d[j]) : T2{T(0), T(0)};
+            xl[2 * j] = v.x;
+            xl[2 * j + 1] = v.y;
+        }
+    } else {
         const gptr<const int32_t> mp = glb(map1) + t * N1;
         int32_t d[N1];
 #pragma unroll
@@ -2109,6 +2125,53 @@ __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__re
     const gptr<T> po = glb(pe) + t * N1;
 #pragma unroll
     for (int j = 0; j < N1; j++) po[j] = yl[j];
+}
+
+// the same sums a pair of DoFs (2j, 2j+1) at a time: they meet the same tets, at
+// adjacent local positions, so one incidence list (the even position) serves both
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_mf_sum2(int64_t npair, const int64_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ idx, const T *__restrict__ pe,
+                                                 T *__restrict__ y, const T *__restrict__ dotv,
+                                                 double *__restrict__ partial)
+{
+    using T2 = T __attribute__((ext_vector_type(2)));
+    __shared__ double s_red[BLK];
+    constexpr int U = 8;
+    const int tid = threadIdx.x;
+    const gptr<const T2> pe2 = glb((const T2 *)pe);
+    double d = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * BLK + tid; j < npair; j += (int64_t)gridDim.x * BLK) {
+        const int64_t kb = ptr[j], ke = ptr[j + 1];
+        const T2 w = dotv ? *(glb((const T2 *)dotv) + j) : T2{T(0), T(0)};
+        T s0 = T(0), s1 = T(0);
+        for (int64_t k = kb; k < ke; k += U) {
+            // entries past the row's end load its last one again and are not added
+            int32_t ix[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) ix[u] = idx[min(k + u, ke - 1)];
+            T2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) v[u] = pe2[ix[u] >> 1];
+#pragma unroll
+            for (int u = 0; u < U; u++)
+                if (k + u < ke) {
+                    s0 += v[u].x;
+                    s1 += v[u].y;
+                }
+        }
+        *(glb((T2 *)y) + j) = T2{s0, s1};
+        d += (double)w.x * (double)s0 + (double)w.y * (double)s1;
+    }
+    if (partial) {
+        s_red[tid] = d;
+        __syncthreads();
+        for (int o = BLK / 2; o > 0; o >>= 1) {
+            if (tid < o) s_red[tid] += s_red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) partial[blockIdx.x] = s_red[0];
+    }
 }
 
 // y_i = sum of the tets' products over the incidences of unknown DoF i, in tet
@@ -2735,19 +2798,28 @@ template <typename T>
 hipError_t mf_apply_t(const DevMF &mf, const T *x, T *y, const T *dotv, double *partial, unsigned &grid,
                       hipStream_t s)
 {
-    grid = red_grid(mf.n1s, BLK);
+    const bool pairs = mf.map1p != nullptr;
+    grid = red_grid(pairs ? mf.n1s / 2 : mf.n1s, BLK);
     if (mf.nt > 0) {
         const unsigned ge = (unsigned)((mf.nt + BLK - 1) / BLK);
         if (mf.order == 1)
-            hipLaunchKernelGGL((k_mf_elem<1, T>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+            hipLaunchKernelGGL((k_mf_elem<1, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+        else if (pairs)
+            hipLaunchKernelGGL((k_mf_elem<2, T, true>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1p, mf.n1s,
                                (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
         else
-            hipLaunchKernelGGL((k_mf_elem<2, T>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+            hipLaunchKernelGGL((k_mf_elem<2, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
                                (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
     }
-    if (mf.n1s > 0)
-        hipLaunchKernelGGL(k_mf_sum<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s, mf.ptr, mf.idx, (const T *)mf.pe, y,
-                           dotv, partial);
+    if (mf.n1s > 0) {
+        if (pairs)
+            hipLaunchKernelGGL(k_mf_sum2<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s / 2, mf.ptr2, mf.idx2,
+                               (const T *)mf.pe, y, dotv, partial);
+        else
+            hipLaunchKernelGGL(k_mf_sum<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s, mf.ptr, mf.idx, (const T *)mf.pe,
+                               y, dotv, partial);
+    }
     return hipGetLastError();
 }
 

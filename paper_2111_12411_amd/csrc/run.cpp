@@ -350,11 +350,55 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
             }
             const double c_dt2 = (p.beta / p.gamma) * (p.beta / p.gamma);
             mf = DevMF{order, nt, n1s, (const int32_t *)d_map1.p, d_mfgeo.p, (const int64_t *)d_inc_ptr.p,
-                       (const int32_t *)d_inc_idx.p, d_mfpe.p, EPS0, c_dt2 * p.dt * p.dt / MU0};
+                       (const int32_t *)d_inc_idx.p, d_mfpe.p, EPS0, c_dt2 * p.dt * p.dt / MU0,
+                       nullptr, nullptr, nullptr};
+            // order 2: pair the two DoFs of each edge and face when every tet lists
+            // them as adjacent unknowns 2j, 2j+1 (the internal numbering does)
+            if (order == 2 && n1s % 2 == 0) {
+                const int np = n1l / 2;
+                std::vector<int32_t> mp((size_t)nt * np);
+                bool ok = true;
+                for (int64_t t = 0; t < nt && ok; t++)
+                    for (int i = 0; i < np; i++) {
+                        const int32_t a = m.map1[(size_t)t * n1l + 2 * i], b = m.map1[(size_t)t * n1l + 2 * i + 1];
+                        if (a < n1s || b < n1s) {
+                            ok = ok && a % 2 == 0 && b == a + 1 && b < n1s;
+                            mp[(size_t)t * np + i] = a / 2;
+                        } else {
+                            mp[(size_t)t * np + i] = -1;
+                        }
+                    }
+                // per pair the incidences of its even DoF; the odd one's must be the next positions
+                std::vector<int64_t> p2((size_t)n1s / 2 + 1, 0);
+                std::vector<int32_t> i2;
+                if (ok) {
+                    i2.reserve(ops.inc_idx.size() / 2);
+                    for (int64_t j = 0; j < n1s / 2 && ok; j++) {
+                        const int64_t a0 = ops.inc_ptr[2 * j], a1 = ops.inc_ptr[2 * j + 1], b1 = ops.inc_ptr[2 * j + 2];
+                        ok = a1 - a0 == b1 - a1;
+                        for (int64_t q = 0; ok && q < a1 - a0; q++) {
+                            const int32_t e = ops.inc_idx[a0 + q];
+                            ok = e % 2 == 0 && ops.inc_idx[a1 + q] == e + 1;
+                            i2.push_back(e);
+                        }
+                        p2[j + 1] = (int64_t)i2.size();
+                    }
+                }
+                if (ok) {
+                    upload(d_mfmap, mp, stream);
+                    upload(d_mfptr2, p2, stream);
+                    upload(d_mfidx2, i2, stream);
+                    HIPCHECK(hipStreamSynchronize(stream));
+                    mf.map1p = (const int32_t *)d_mfmap.p;
+                    mf.ptr2 = (const int64_t *)d_mfptr2.p;
+                    mf.idx2 = (const int32_t *)d_mfidx2.p;
+                }
+            }
         }
     }
     nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Mnu.nnz() + ops.K.nnz() + ops.Kt.nnz() + ops.Gt.nnz();
     a_nnz = ops.A.nnz();
+    a_inc = (int64_t)ops.inc_idx.size();
     // fields and solver vectors
     const int64_t N1 = m.N1, N1i = n1s, N2 = m.N2, N0i = m.N0_int;
     d_e.alloc(N1 * 8);
@@ -2135,7 +2179,9 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     const double inc = (N1i + 1) * 8 + nt * n1l * 4 + (N0i + 1) * 8 + nt * n0l * 4;
     const double mesh = nt * (16 * 8 + 16 + (n1l + n2l + n0l) * 4);
     // the operator applied tet by tet (PEC walls): geometry and per-tet products
-    const double matfree = z.absorbing ? 0.0 : nt * (16 + n1l) * (mixed ? 4 : 8);
+    const double matfree = z.absorbing ? 0.0
+                                       : nt * (16 + n1l) * (mixed ? 4 : 8) +
+                                             (k2 ? nt * n1l / 2 * 4 + (N1i / 2 + 1) * 8 + nt * n1l / 2 * 4 : 0);
     double vecs = (N1 + N2) * 8 + 5 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
                   (mixed ? 5 * N1i * 4 : 0) + N2 * 8 + 4 * N0i * 8;
     vecs += 5 * N1i * 8 + N2 * 8;  // double-double halves, *nu u, the previous increment
@@ -2506,6 +2552,8 @@ int32_t fempic_stats(fempic_run run, fempic_stats_t *out)
     s.device_bytes = (int64_t)r.account().bytes;
     s.device_peak_bytes = (int64_t)r.account().peak;
     s.phase_replays = r.last_phase_replays;
+    s.field_op = r.field_op();
+    s.a_inc = r.a_inc;
     *out = s;
     API_END
 }

@@ -108,6 +108,8 @@ class Run {
     // refuse (ENOMEM) any allocation that would take the run's device bytes past `bytes` (0: no cap)
     void set_byte_limit(size_t bytes) { acct.limit = bytes; }
     const DevAccount &account() const { return acct; }
+    // the operator of the PCG iterations: 0 assembled, 1 tet by tet, 2 tet by tet in DoF pairs
+    int field_op() const { return mf.order == 0 ? 0 : (mf.map1p ? 2 : 1); }
 
     DevAccount acct;  // before every buffer member: destroyed after them
     std::shared_ptr<const HostMesh> mesh_hold;
@@ -131,7 +133,7 @@ class Run {
     double last_particle_ms = 0, last_kernel_ms = 0, last_continue_ms = 0, last_field_ms = 0, last_relres = 0;
     int32_t last_iters = 0;
     int64_t last_phase_replays = 0;
-    int64_t nnz_total = 0, a_nnz = 0;
+    int64_t nnz_total = 0, a_nnz = 0, a_inc = 0;
     double gauss_last[3] = {0, 0, 0};  // the last evaluation that params.gauss_every asked for
     int64_t gauss_step = 0;
 
@@ -198,7 +200,7 @@ class Run {
     double gscale = 1.0;  // Gt holds gscale G^T
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
     // A applied tet by tet in the PCG iterations (order 0: the assembled matrix)
-    DevBuf d_mfgeo, d_mfpe;
+    DevBuf d_mfgeo, d_mfpe, d_mfmap, d_mfptr2, d_mfidx2;
     DevMF mf{};
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
     // rounding errors of the running sums e and g (compensated summation), and

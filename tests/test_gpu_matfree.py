@@ -58,6 +58,8 @@ def test_operator_matches_the_oracle(k, prec, scheme):
     dt = 10 * core.cfl_dt(m, ops)
     A, i1 = oracle_matrix(m, ops, dt, gamma, beta)
     run = make_run(N, k, dt, prec, gamma=gamma, beta=beta)
+    # order 2 takes the two DoFs of each edge and face together
+    assert run.stats()["field_op"] == (2 if k == 2 else 1)
     rng = np.random.Generator(np.random.PCG64(70 + 2 * k + prec))
     for trial in range(2):
         x = rng.normal(size=m.n1)
@@ -89,6 +91,7 @@ def test_assembled_form_when_switched_off_or_absorbing(k):
     x = rng.normal(size=m.n1)
     for kw, mf in (({}, False), ({"field_bc": F.FIELD_ABSORB}, True)):
         run = make_run(N, k, dt, F.MIXED, matfree=mf, **kw)
+        assert run.stats()["field_op"] == 0
         ya = run.field_matvec(x, F.OP_ASSEMBLED)
         close(run.field_matvec(x, F.OP_ITERATION), ya, 1e-6)
         run.close()
