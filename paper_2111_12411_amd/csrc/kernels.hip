@@ -2242,15 +2242,50 @@ __global__ __launch_bounds__(1024) void k_finish(const double *__restrict__ part
 // the preconditioner: Jacobi (dinv[i] = 1 / A_ii), or with BLOCK 2x2 block
 // Jacobi (dinv[4j..4j+3] = inverse of the diagonal block of rows 2j, 2j+1,
 // row-major); with BLOCK a thread handles one pair of rows
+// sums over i < n of v[2 i + q] (q = 0, 1; two = false: of v[i] alone) in one fixed
+// order, the same in every workgroup: strided entries per thread, then a tree
+// in LDS (blockDim.x == BLK)
+template <bool TWO>
+__device__ __forceinline__ void block_totals(const double *__restrict__ v, int64_t n, double *s0, double *s1,
+                                             double &t0, double &t1)
+{
+    const int tid = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t i = tid; i < n; i += BLK) {
+        if constexpr (TWO) {
+            a0 += v[2 * i];
+            a1 += v[2 * i + 1];
+        } else {
+            a0 += v[i];
+        }
+    }
+    s0[tid] = a0;
+    if constexpr (TWO) s1[tid] = a1;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            s0[tid] += s0[tid + o];
+            if constexpr (TWO) s1[tid] += s1[tid + o];
+        }
+        __syncthreads();
+    }
+    t0 = s0[0];
+    t1 = TWO ? s1[0] : 0.0;
+    __syncthreads();
+}
+
+// pq: the npq workgroup partials of p.q, summed here by every workgroup
 template <typename T, bool BLOCK>
 __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z,
                                                    const T *__restrict__ p, const T *__restrict__ q,
                                                    const T *__restrict__ dinv, const double *__restrict__ sc, int par,
+                                                   const double *__restrict__ pqpart, int64_t npq,
                                                    double *__restrict__ partial)
 {
     __shared__ double s0[BLK], s1[BLK];
     const int tid = threadIdx.x;
-    const double pq = sc[SC_PQ];
+    double pq, unused;
+    block_totals<false>(pqpart, npq, s0, s1, pq, unused);
     const double a = pq != 0.0 ? sc[SC_RZ + 10 * par] / pq : 0.0;
     double rz = 0, rr = 0;
     if constexpr (BLOCK) {
@@ -2296,16 +2331,22 @@ __global__ __launch_bounds__(BLK) void k_update_xr(int64_t n, T *__restrict__ x,
     }
 }
 
-// p = z + b p with b = rz_new / rz_old; keeps r.z for the next iteration in
-// the other parity slot (no other thread reads that slot in this launch)
+// p = z + b p with b = rz_new / rz_old, rz_new and r.r summed by every workgroup
+// from the nrz (r.z, r.r) partials; keeps r.z for the next iteration in the
+// other parity slot (no other thread reads that slot in this launch) and r.r
 template <typename T>
-__global__ void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z, double *__restrict__ sc, int par)
+__global__ __launch_bounds__(BLK) void k_update_p(int64_t n, T *__restrict__ p, const T *__restrict__ z,
+                                                  double *__restrict__ sc, int par, const double *__restrict__ rzpart,
+                                                  int64_t nrz)
 {
+    __shared__ double s0[BLK], s1[BLK];
+    double rzn, rrn;
+    block_totals<true>(rzpart, nrz, s0, s1, rzn, rrn);
     const double rzo = sc[SC_RZ + 10 * par];
-    const double bt = rzo != 0.0 ? sc[8] / rzo : 0.0;
+    const double bt = rzo != 0.0 ? rzn / rzo : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc[SC_RZ + 10 * (1 - par)] = sc[8];
-        sc[SC_RR] = sc[9];
+        sc[SC_RZ + 10 * (1 - par)] = rzn;
+        sc[SC_RR] = rrn;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = (T)((double)z[i] + bt * (double)p[i]);
@@ -2831,15 +2872,18 @@ hipError_t pcg_iter_t(const DevCSR &A, const T *val, const DevMF *mf, int64_t n,
     hipError_t err = mf && mf->order ? mf_apply_t<T>(*mf, p, q, p, partial, g1, s)
                                      : spmv_t<T>(A, val, p, q, 1.0, 0.0, (const T *)nullptr, p, partial, g1, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g1, 1, sc + SC_PQ);
+    // the product's partials of p.q at partial[0, g1), the update's (r.z, r.r) ones
+    // after them; each consumer sums the partials itself
+    double *part2 = partial + RED_BLOCKS;
     const bool block = A.bptr != nullptr;
     const unsigned g2 = red_grid(block ? (n + 1) / 2 : n, BLK);
     if (block)
-        hipLaunchKernelGGL((k_update_xr<T, true>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
+        hipLaunchKernelGGL((k_update_xr<T, true>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par,
+                           partial, (int64_t)g1, part2);
     else
-        hipLaunchKernelGGL((k_update_xr<T, false>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par, partial);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, partial, (int64_t)g2, 2, sc + 8);
-    hipLaunchKernelGGL(k_update_p<T>, dim3(g2), dim3(BLK), 0, s, n, p, z, sc, par);
+        hipLaunchKernelGGL((k_update_xr<T, false>), dim3(g2), dim3(BLK), 0, s, n, x, r, z, p, q, dinv, sc, par,
+                           partial, (int64_t)g1, part2);
+    hipLaunchKernelGGL(k_update_p<T>, dim3(g2), dim3(BLK), 0, s, n, p, z, sc, par, part2, (int64_t)g2);
     return hipGetLastError();
 }
 }  // namespace
