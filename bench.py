@@ -462,7 +462,8 @@ def main():
         "gauss_residual": {"R_G": mix["gauss"][0], "R_C": mix["gauss"][1], "R_S": mix["gauss"][2],
                            "ms": mix["gauss_ms"]},
         "pcg": {"iters_last_step": st["pcg_iters"], "relres": st["pcg_relres"], "a_rows": st["a_rows"],
-                "a_nnz": st["a_nnz"], "field_op": st["field_op"], "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
+                "a_nnz": st["a_nnz"], "field_op": st["field_op"], "a_inc": st["a_inc"],
+                "alg_bytes_per_iter": pcg_b, "ms_per_iter": pcg_ms,
                 "gb_s": pcg_b / (pcg_ms / 1e3) / 1e9},
         "crossings_per_particle_step": st["crossings"] / n,
         "spills_per_particle_step": st["spills"] / n,
