@@ -89,16 +89,20 @@ def pcg_bytes_per_iter(order, precision, rows, nnz, field_op=0, nt=0, inc=0):
     FP32 in mixed precision, FP64 otherwise; order 2 has a 2x2 block-Jacobi preconditioner, order 1
     Jacobi.
     field_op 0: A assembled, at order 2 in 2x2 blocks with one int32 column per block, at order 1
-    in CSR.  field_op 1 or 2: A applied tet by tet (nt tets): per tet its local W1 ids (int32; one
-    per DoF pair with field_op 2) and 16 geometry words read, p read once, the n1l products written;
-    then per row of A its inc incidences (an int32 each, one per pair with field_op 2; int64 row
-    pointers) and their products read, q written and p read again for the dot."""
+    in CSR.  field_op 1: A applied tet by tet (nt tets): per tet its n1l local W1 ids (int32) and 16
+    geometry words read, p read once, the n1l products written; then per row of A (int64 row
+    pointers) its inc incidences (int32) and their products read, q written and p read again for
+    the dot.  field_op 2 (order 2, DoF pairs): per tet one id and one product position (int32) per
+    pair; the inc products of the rows written in row order and read contiguously, no incidences."""
     vs = 4 if precision == F.MIXED else 8
     if field_op:
         n1l = 20 if order == 2 else 6
-        per = 2 if field_op == 2 else 1
-        elem = nt * (n1l // per) * 4 + nt * 16 * vs + rows * vs + nt * n1l * vs
-        sums = (rows // per + 1) * 8 + (inc // per) * 4 + inc * vs + 2 * rows * vs
+        if field_op == 2:
+            elem = nt * (n1l // 2) * 4 * 2 + nt * 16 * vs + rows * vs + inc * vs
+            sums = (rows // 2 + 1) * 8 + inc * vs + 2 * rows * vs
+        else:
+            elem = nt * n1l * 4 + nt * 16 * vs + rows * vs + nt * n1l * vs
+            sums = (rows + 1) * 8 + inc * 4 + inc * vs + 2 * rows * vs
         spmv = elem + sums
         precond = (rows // 2) * 4 * vs if order == 2 else rows * vs
     elif order == 2:

@@ -242,11 +242,12 @@ struct DevMF {
     double kM, kC;        // eps0 and c / mu0 (c: the curl-curl term's coefficient times dt^2)
     // optional (order 2), used when map1p is set: the two DoFs of an edge or face are
     // the unknowns 2j, 2j+1 at local positions 2i, 2i+1 of every tet they meet.
-    // map1p [nt][n1l/2]: j of local pair i, -1 when not unknowns; ptr2/idx2: per pair
-    // j its incidences t n1l + 2i, tet-ascending
+    // map1p [nt][n1l/2]: j of local pair i, -1 when not unknowns; ptr2: per pair j
+    // the range [ptr2[j], ptr2[j+1]) of its tets (tet-ascending) in pe, which then
+    // holds pairs of products; slot2 [nt][n1l/2]: where in pe the tet's pair i goes
     const int32_t *map1p;
     const int64_t *ptr2;
-    const int32_t *idx2;
+    const int32_t *slot2;
 };
 hipError_t mf_apply(const DevMF &mf, const double *x, double *y, hipStream_t s);
 hipError_t mf_apply32(const DevMF &mf, const float *x, float *y, hipStream_t s);

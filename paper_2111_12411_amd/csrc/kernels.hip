@@ -1986,10 +1986,13 @@ __device__ __forceinline__ constexpr float dmono(int u, int i, int v)
 // PAIRS (order 2): map1 holds per tet the N1/2 pair ids j of its DoF pairs
 // (local 2i, 2i+1 are the unknowns 2j, 2j+1; -1 when they are not unknowns),
 // and x is read a pair at a time
+// With PAIRS the products of pair i go to position slot[t][i] of the pairs'
+// incidence lists (pe then holds T pairs in incidence order; -1: not unknowns),
+// so that the row sums read them contiguously.
 template <int K, typename T, bool PAIRS>
 __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__restrict__ map1, int64_t n1s,
                                                  const T *__restrict__ geo, const T *__restrict__ x, T kM, T kC,
-                                                 T *__restrict__ pe)
+                                                 T *__restrict__ pe, const int32_t *__restrict__ slot)
 {
     constexpr int N1 = Ord<K>::N1, NM = MonoN<K>::NM, NS = MonoN<K>::NS;
     const int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x;
@@ -2122,18 +2125,29 @@ __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__re
 #pragma unroll
     for (int j = 0; j < N1; j++) yl[j] = T(0);
     w1_terms<K>([&](int j, int m, int u, float c) { yl[j] += T(c) * D[m][u]; });
-    const gptr<T> po = glb(pe) + t * N1;
+    if constexpr (PAIRS) {
+        using T2 = T __attribute__((ext_vector_type(2)));
+        const gptr<const int32_t> sl = glb(slot) + t * (N1 / 2);
+        const gptr<T2> po = glb((T2 *)pe);
 #pragma unroll
-    for (int j = 0; j < N1; j++) po[j] = yl[j];
+        for (int j = 0; j < N1 / 2; j++) {
+            const int32_t s = sl[j];
+            if (s >= 0) po[s] = T2{yl[2 * j], yl[2 * j + 1]};
+        }
+    } else {
+        const gptr<T> po = glb(pe) + t * N1;
+#pragma unroll
+        for (int j = 0; j < N1; j++) po[j] = yl[j];
+    }
 }
 
 // the same sums a pair of DoFs (2j, 2j+1) at a time: they meet the same tets, at
-// adjacent local positions, so one incidence list (the even position) serves both
+// adjacent local positions, and k_mf_elem has put their products at positions
+// [ptr[j], ptr[j+1]) of pe, in tet order
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_mf_sum2(int64_t npair, const int64_t *__restrict__ ptr,
-                                                 const int32_t *__restrict__ idx, const T *__restrict__ pe,
-                                                 T *__restrict__ y, const T *__restrict__ dotv,
-                                                 double *__restrict__ partial)
+                                                 const T *__restrict__ pe, T *__restrict__ y,
+                                                 const T *__restrict__ dotv, double *__restrict__ partial)
 {
     using T2 = T __attribute__((ext_vector_type(2)));
     __shared__ double s_red[BLK];
@@ -2147,12 +2161,9 @@ __global__ __launch_bounds__(BLK) void k_mf_sum2(int64_t npair, const int64_t *_
         T s0 = T(0), s1 = T(0);
         for (int64_t k = kb; k < ke; k += U) {
             // entries past the row's end load its last one again and are not added
-            int32_t ix[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) ix[u] = idx[min(k + u, ke - 1)];
             T2 v[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) v[u] = pe2[ix[u] >> 1];
+            for (int u = 0; u < U; u++) v[u] = pe2[min(k + u, ke - 1)];
 #pragma unroll
             for (int u = 0; u < U; u++)
                 if (k + u < ke) {
@@ -2845,18 +2856,18 @@ hipError_t mf_apply_t(const DevMF &mf, const T *x, T *y, const T *dotv, double *
         const unsigned ge = (unsigned)((mf.nt + BLK - 1) / BLK);
         if (mf.order == 1)
             hipLaunchKernelGGL((k_mf_elem<1, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
-                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, (const int32_t *)nullptr);
         else if (pairs)
             hipLaunchKernelGGL((k_mf_elem<2, T, true>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1p, mf.n1s,
-                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, mf.slot2);
         else
             hipLaunchKernelGGL((k_mf_elem<2, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
-                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe);
+                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, (const int32_t *)nullptr);
     }
     if (mf.n1s > 0) {
         if (pairs)
-            hipLaunchKernelGGL(k_mf_sum2<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s / 2, mf.ptr2, mf.idx2,
-                               (const T *)mf.pe, y, dotv, partial);
+            hipLaunchKernelGGL(k_mf_sum2<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s / 2, mf.ptr2, (const T *)mf.pe, y,
+                               dotv, partial);
         else
             hipLaunchKernelGGL(k_mf_sum<T>, dim3(grid), dim3(BLK), 0, s, mf.n1s, mf.ptr, mf.idx, (const T *)mf.pe,
                                y, dotv, partial);

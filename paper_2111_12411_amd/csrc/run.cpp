@@ -368,30 +368,33 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
                             mp[(size_t)t * np + i] = -1;
                         }
                     }
-                // per pair the incidences of its even DoF; the odd one's must be the next positions
+                // per pair the incidences of its even DoF (the odd one's must be the next
+                // positions), numbered in order: the position of each (tet, pair) in pe
                 std::vector<int64_t> p2((size_t)n1s / 2 + 1, 0);
-                std::vector<int32_t> i2;
+                std::vector<int32_t> sl((size_t)nt * np, -1);
                 if (ok) {
-                    i2.reserve(ops.inc_idx.size() / 2);
+                    int64_t pos = 0;
                     for (int64_t j = 0; j < n1s / 2 && ok; j++) {
                         const int64_t a0 = ops.inc_ptr[2 * j], a1 = ops.inc_ptr[2 * j + 1], b1 = ops.inc_ptr[2 * j + 2];
                         ok = a1 - a0 == b1 - a1;
                         for (int64_t q = 0; ok && q < a1 - a0; q++) {
-                            const int32_t e = ops.inc_idx[a0 + q];
-                            ok = e % 2 == 0 && ops.inc_idx[a1 + q] == e + 1;
-                            i2.push_back(e);
+                            const int32_t e = ops.inc_idx[a0 + q];  // t n1l + local
+                            ok = e % 2 == 0 && ops.inc_idx[a1 + q] == e + 1 && sl[e / 2] < 0;
+                            sl[e / 2] = (int32_t)pos++;
                         }
-                        p2[j + 1] = (int64_t)i2.size();
+                        p2[j + 1] = pos;
                     }
+                    for (int64_t t = 0; t < nt && ok; t++)
+                        for (int i = 0; i < np; i++) ok = ok && (mp[(size_t)t * np + i] < 0) == (sl[(size_t)t * np + i] < 0);
                 }
                 if (ok) {
                     upload(d_mfmap, mp, stream);
                     upload(d_mfptr2, p2, stream);
-                    upload(d_mfidx2, i2, stream);
+                    upload(d_mfslot, sl, stream);
                     HIPCHECK(hipStreamSynchronize(stream));
                     mf.map1p = (const int32_t *)d_mfmap.p;
                     mf.ptr2 = (const int64_t *)d_mfptr2.p;
-                    mf.idx2 = (const int32_t *)d_mfidx2.p;
+                    mf.slot2 = (const int32_t *)d_mfslot.p;
                 }
             }
         }
@@ -2181,7 +2184,7 @@ size_t footprint_bytes(const FootprintSizes &z, int64_t n, bool mixed)
     // the operator applied tet by tet (PEC walls): geometry and per-tet products
     const double matfree = z.absorbing ? 0.0
                                        : nt * (16 + n1l) * (mixed ? 4 : 8) +
-                                             (k2 ? nt * n1l / 2 * 4 + (N1i / 2 + 1) * 8 + nt * n1l / 2 * 4 : 0);
+                                             (k2 ? 2 * nt * n1l / 2 * 4 + (N1i / 2 + 1) * 8 : 0);
     double vecs = (N1 + N2) * 8 + 5 * N1i * 8 + (mixed ? (N1 + N2) * 4 : 0) + 8 * N1i * 8 +
                   (mixed ? 5 * N1i * 4 : 0) + N2 * 8 + 4 * N0i * 8;
     vecs += 5 * N1i * 8 + N2 * 8;  // double-double halves, *nu u, the previous increment

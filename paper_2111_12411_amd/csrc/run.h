@@ -200,7 +200,7 @@ class Run {
     double gscale = 1.0;  // Gt holds gscale G^T
     DevBuf d_dinv, d_dinv32, d_inc_ptr, d_inc_idx, d_inc0_ptr, d_inc0_idx;
     // A applied tet by tet in the PCG iterations (order 0: the assembled matrix)
-    DevBuf d_mfgeo, d_mfpe, d_mfmap, d_mfptr2, d_mfidx2;
+    DevBuf d_mfgeo, d_mfpe, d_mfmap, d_mfptr2, d_mfslot;
     DevMF mf{};
     DevBuf d_e, d_b, d_g, d_dg, d_e32, d_b32;
     // rounding errors of the running sums e and g (compensated summation), and

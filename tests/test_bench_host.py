@@ -72,9 +72,10 @@ def test_pcg_bytes_per_iteration():
     # the benchmark system: 2 384 240 rows, 25 457 008 blocks -> 0.662 GB per iteration
     assert abs(bench.pcg_bytes_per_iter(2, F.MIXED, 2_384_240, 4 * 25_457_008) / 1e9 - 0.6617) < 1e-3
     # tet by tet, order 2 in pairs, mixed: one tet whose 20 DoFs are the 20 rows (10 pairs), 20
-    # incidences: 10 pair ids x 4 + 16 x 4 geometry + 20 x 4 p + 20 x 4 products; 11 row pointers
-    # x 8 + 10 x 4 indices + 20 x 4 products + 2 x 20 x 4; block-Jacobi 10 x 16; 7 x 80; 3 x 80
-    assert bench.pcg_bytes_per_iter(2, F.MIXED, 20, 0, 2, 1, 20) == (40 + 64 + 80 + 80) + (88 + 40 + 80 + 160) \
+    # incidences: 10 pair ids and 10 product positions x 4 + 16 x 4 geometry + 20 x 4 p + 20 x 4
+    # products; 11 row pointers x 8 + 20 x 4 products + 2 x 20 x 4; block-Jacobi 10 x 16; 7 x 80;
+    # 3 x 80
+    assert bench.pcg_bytes_per_iter(2, F.MIXED, 20, 0, 2, 1, 20) == (80 + 64 + 80 + 80) + (88 + 80 + 160) \
         + 160 + 560 + 240
     # order 1, FP64, one DoF per row (field_op 1): 6 ids x 4 + 16 x 8 + 6 x 8 + 6 x 8; 7 x 8 + 6 x 4
     # + 6 x 8 + 2 x 6 x 8; Jacobi 6 x 8; 7 x 48; 3 x 48
