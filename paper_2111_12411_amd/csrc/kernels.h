@@ -240,8 +240,8 @@ struct DevMF {
     const int32_t *idx;
     void *pe;             // [nt][n1l] the tets' products
     double kM, kC;        // eps0 and c / mu0 (c: the curl-curl term's coefficient times dt^2)
-    // optional (order 2), used when map1p is set: the two DoFs of an edge or face are
-    // the unknowns 2j, 2j+1 at local positions 2i, 2i+1 of every tet they meet.
+    // order 2 (required there; order 1 uses map1, ptr and idx): the two DoFs of an edge or
+    // face are the unknowns 2j, 2j+1 at local positions 2i, 2i+1 of every tet they meet.
     // map1p [nt][n1l/2]: j of local pair i, -1 when not unknowns; ptr2: per pair j
     // the range [ptr2[j], ptr2[j+1]) of its tets (tet-ascending) in pe, which then
     // holds pairs of products; slot2 [nt][n1l/2]: where in pe the tet's pair i goes

@@ -2850,18 +2850,17 @@ template <typename T>
 hipError_t mf_apply_t(const DevMF &mf, const T *x, T *y, const T *dotv, double *partial, unsigned &grid,
                       hipStream_t s)
 {
-    const bool pairs = mf.map1p != nullptr;
+    // order 2 is applied in DoF pairs only (the set-up uses the assembled matrix otherwise)
+    const bool pairs = mf.order == 2;
+    if (pairs && !mf.map1p) return hipErrorInvalidValue;
     grid = red_grid(pairs ? mf.n1s / 2 : mf.n1s, BLK);
     if (mf.nt > 0) {
         const unsigned ge = (unsigned)((mf.nt + BLK - 1) / BLK);
-        if (mf.order == 1)
-            hipLaunchKernelGGL((k_mf_elem<1, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
-                               (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, (const int32_t *)nullptr);
-        else if (pairs)
+        if (pairs)
             hipLaunchKernelGGL((k_mf_elem<2, T, true>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1p, mf.n1s,
                                (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, mf.slot2);
         else
-            hipLaunchKernelGGL((k_mf_elem<2, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
+            hipLaunchKernelGGL((k_mf_elem<1, T, false>), dim3(ge), dim3(BLK), 0, s, mf.nt, mf.map1, mf.n1s,
                                (const T *)mf.geo, x, (T)mf.kM, (T)mf.kC, (T *)mf.pe, (const int32_t *)nullptr);
     }
     if (mf.n1s > 0) {

@@ -397,6 +397,12 @@ Run::Run(std::shared_ptr<const HostMesh> mesh, const fempic_params &p, hipStream
                     mf.slot2 = (const int32_t *)d_mfslot.p;
                 }
             }
+            // order 2 is applied in pairs only: without them the iterations keep the assembled matrix
+            if (order == 2 && !mf.map1p) {
+                mf = DevMF{};
+                d_mfgeo.release();
+                d_mfpe.release();
+            }
         }
     }
     nnz_total = ops.A.nnz() + ops.Meps.nnz() + ops.Mnu.nnz() + ops.K.nnz() + ops.Kt.nnz() + ops.Gt.nnz();
