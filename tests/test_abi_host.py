@@ -133,6 +133,7 @@ def test_null_handles_are_einval_without_gpu():
         lambda: L.fempic_fields_get(None, buf, 1, buf, 1),
         lambda: L.fempic_fields_set(None, buf, 1, buf, 1),
         lambda: L.fempic_deposit_get(None, buf, 1),
+        lambda: L.fempic_field_matvec(None, buf, buf, 1, 0),
         lambda: L.fempic_particles_get(None, buf, buf, None, 1),
         lambda: L.fempic_rho_get(None, buf, buf, 1),
         lambda: L.fempic_history_get(None, buf, buf, 1),
