@@ -126,3 +126,24 @@ def test_runs_agree_with_the_assembled_iterations(k, prec):
     assert max(rg) < 1e-12, rg
     for r in runs:
         r.close()
+
+
+def test_matvec_rejects_bad_arguments():
+    """EINVAL for an unknown form, a short buffer and a non-finite x; the run stays usable."""
+    N, k = 3, 2
+    m = omesh.cube_mesh(N, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    run = make_run(N, k, dt, F.MIXED)
+    x = np.ones(m.n1)
+    for bad in (lambda: run.field_matvec(x, 7),
+                lambda: F._check(F.lib().fempic_field_matvec(run.h, F._p(x), F._p(np.zeros(m.n1)), m.n1 - 1, 0)),
+                lambda: run.field_matvec(np.full(m.n1, np.nan))):
+        with pytest.raises(F.FempicError) as ei:
+            bad()
+        assert ei.value.code == -1
+    A, i1 = oracle_matrix(m, ops, dt)
+    y = np.zeros(m.n1)
+    y[i1] = A @ x[i1]
+    close(run.field_matvec(x), y, 1e-12)
+    run.close()
