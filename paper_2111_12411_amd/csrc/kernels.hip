@@ -10,6 +10,8 @@
 //                         fixed order, other segments appended to a spill pool
 //  * k_spill_*            deterministic reduction of the spill pool per tet
 //  * k_scatter            per-tet partials -> DoF current moments (fixed order)
+//  * k_mf_elem, k_mf_sum*  the field system's matrix applied tet by tet (the
+//                         PCG iterations' product)
 //  * SpMV / PCG / norms   field update, deterministic reductions
 //
 // No floating-point atomics anywhere: every floating-point sum is taken in a
@@ -1875,7 +1877,8 @@ __global__ __launch_bounds__(BLK) void k_bspmv(int64_t brows, const int64_t *__r
 }
 
 // ------------------------------------------------ system operator, tet by tet
-// A = eps0 M1 + c S / mu0 applied without the assembled matrix.  In a tet,
+// The matrix of the implicit update (Sec. III-A, eq. (maxwell_semi); Sec. III-B),
+// A = eps0 M1 + c S / mu0, applied without the assembled matrix.  In a tet,
 // E = sum_j x_j W1_j = sum_m P_m(l) grad l_m, with P_m a homogeneous polynomial
 // of degree K in the barycentric coordinates (every W1_j is (qc + qs l_v) times
 // l_a grad l_b - l_b grad l_a, and l_a = l_a (l_0 + ... + l_3)).  Then
