@@ -1416,6 +1416,9 @@ __global__ __launch_bounds__(BLK) void k_rs_scatter(const uint32_t *__restrict__
 constexpr int SC_THREADS = 1024;
 constexpr int SC_ITEMS = 4;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+// up to this many tiles a scan adds the tile sums per tile directly (each
+// workgroup reads at most this many sums) instead of scanning them first
+constexpr int64_t SCAN_DIRECT_TILES = 4096;
 
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_w, uint32_t &total)
 {
@@ -1468,6 +1471,30 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_tile(const uint32_t *__rest
     if (threadIdx.x == 0 && sums) sums[blockIdx.x] = tot;
 }
 
+// a single-tile scan that also writes the total
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tile1(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                           int64_t n, uint32_t *__restrict__ total,
+                                                           const int32_t *__restrict__ dn)
+{
+    __shared__ uint32_t s_w[SC_THREADS / 64];
+    n = dev_count(n, dn);
+    const int64_t base = (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t v[SC_ITEMS], s = 0;
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; k++) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(s, s_w, tot);
+#pragma unroll
+    for (int k = 0; k < SC_ITEMS; k++) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
 __global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t *__restrict__ sums,
                            const int32_t *__restrict__ dn)
 {
@@ -1476,6 +1503,24 @@ __global__ void k_scan_add(uint32_t *__restrict__ out, int64_t n, const uint32_t
     const uint32_t add = sums[blockIdx.x];
     for (int k = threadIdx.x; k < SC_TILE; k += blockDim.x)
         if (base + k < n) out[base + k] += add;
+}
+
+// the same for few tiles, without a scan of the tile sums: each workgroup adds
+// up the sums of the tiles before it; the last one also writes the total
+__global__ __launch_bounds__(BLK) void k_scan_add_direct(uint32_t *__restrict__ out, int64_t n,
+                                                         const uint32_t *__restrict__ sums,
+                                                         uint32_t *__restrict__ total, const int32_t *__restrict__ dn)
+{
+    __shared__ uint32_t s_w[BLK / 64];
+    n = dev_count(n, dn);
+    uint32_t a = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += BLK) a += sums[k];
+    uint32_t add;
+    (void)block_exclusive_scan(a, s_w, add);
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+    for (int k = threadIdx.x; k < SC_TILE; k += BLK)
+        if (base + k < n) out[base + k] += add;
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = add + sums[blockIdx.x];
 }
 
 __global__ void k_scan_total(const uint32_t *__restrict__ in, const uint32_t *__restrict__ out, int64_t n,
@@ -2546,8 +2591,17 @@ hipError_t exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint
     }
     const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_tile, dim3(1), dim3(SC_THREADS), 0, s, in, out, n, (uint32_t *)nullptr, dn);
-    } else {
+        hipLaunchKernelGGL(k_scan_tile1, dim3(1), dim3(SC_THREADS), 0, s, in, out, n, total, dn);
+        return hipGetLastError();
+    }
+    if (nb <= SCAN_DIRECT_TILES) {
+        // two launches: tile scans, then each tile adds the sums before it (and the total)
+        uint32_t *sums = tmp;
+        hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, out, n, sums, dn);
+        hipLaunchKernelGGL(k_scan_add_direct, dim3((unsigned)nb), dim3(BLK), 0, s, out, n, sums, total, dn);
+        return hipGetLastError();
+    }
+    {
         uint32_t *sums = tmp;
         uint32_t *sums_scan = tmp + nb;
         hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nb), dim3(SC_THREADS), 0, s, in, out, n, sums, dn);
