@@ -264,7 +264,9 @@ hipError_t axpby(int64_t n, double a, const double *x, double b, const double *y
 enum { SC_RZ = 0, SC_PQ = 1, SC_RR = 4, SC_BB = 5 };
 hipError_t pcg_init(int64_t n, const double *b, double *x, double *r, double *z, double *p, const double *dinv,
                     double *partial, double *scalars, bool block, hipStream_t s);
-// mf (nullable): apply A tet by tet instead of the assembled matrix when mf->order != 0
+// mf (nullable): apply A tet by tet instead of the assembled matrix when mf->order != 0.
+// partial: the product's dot partials at [0, 2048), the update's (r.z, r.r) pairs
+// after them: at least 2048 + 2 ceil(n / 256) doubles.
 hipError_t pcg_iter(const DevCSR &A, const DevMF *mf, int64_t n, double *x, double *r, double *z, double *p,
                     double *q, const double *dinv, double *partial, double *scalars, int par, hipStream_t s);
 // FP32 inner PCG (mixed mode); vectors float, scalars double
