@@ -147,3 +147,44 @@ def test_matvec_rejects_bad_arguments():
     y[i1] = A @ x[i1]
     close(run.field_matvec(x), y, 1e-12)
     run.close()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("prec", [F.FP64, F.MIXED])
+def test_operator_on_a_jittered_relabelled_mesh(k, prec):
+    """A general mesh: the 4^3 Kuhn cube with its inner vertices moved at random (tets of unequal
+    shapes), its vertices relabelled and its tets and their vertex lists shuffled, so that the DoF
+    numbering and the per-tet DoF pairs come out of the general mesh builder.  The iterations'
+    form against the oracle's operators on the same arrays."""
+    N = 4
+    xyz, tets = omesh.kuhn_cube(N)
+    rng = np.random.Generator(np.random.PCG64(300 + 2 * k + prec))
+    inner = np.all((xyz > 1e-9) & (xyz < 1 - 1e-9), axis=1)
+    xyz = xyz.copy()
+    xyz[inner] += rng.uniform(-0.15, 0.15, size=(inner.sum(), 3)) / N
+    relabel = rng.permutation(len(xyz))
+    xyz2 = np.empty_like(xyz)
+    xyz2[relabel] = xyz
+    tets2 = relabel[np.asarray(tets)]
+    tets2 = tets2[rng.permutation(len(tets2))]
+    tets2 = np.array([rng.permutation(t) for t in tets2])
+    m = omesh.build(xyz2, tets2, k)
+    ops = core.assemble(m)
+    dt = 10 * core.cfl_dt(m, ops)
+    A, i1 = oracle_matrix(m, ops, dt)
+    old = os.environ.get("FEMPIC_MATFREE")
+    os.environ["FEMPIC_MATFREE"] = "1"
+    try:
+        run = F.Run(F.Mesh.from_arrays(xyz2, tets2, k), dt, prec)
+    finally:
+        if old is None:
+            del os.environ["FEMPIC_MATFREE"]
+        else:
+            os.environ["FEMPIC_MATFREE"] = old
+    assert run.stats()["field_op"] == (2 if k == 2 else 1)
+    x = rng.normal(size=m.n1)
+    y = np.zeros(m.n1)
+    y[i1] = A @ x[i1]
+    close(run.field_matvec(x, F.OP_ASSEMBLED), y, 1e-12)
+    close(run.field_matvec(x, F.OP_ITERATION), y, TOL[prec])
+    run.close()
