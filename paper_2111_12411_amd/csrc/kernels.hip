@@ -2043,7 +2043,15 @@ __global__ __launch_bounds__(BLK) void k_mf_elem(int64_t nt, const int32_t *__re
                                                  T *__restrict__ pe, const int32_t *__restrict__ slot)
 {
     constexpr int N1 = Ord<K>::N1, NM = MonoN<K>::NM, NS = MonoN<K>::NS;
-    const int64_t t = (int64_t)blockIdx.x * BLK + threadIdx.x;
+    // workgroups go round-robin to the 8 XCDs; each XCD takes one contiguous
+    // eighth of the tets, so that neighbouring tets' parts of the same rows meet
+    // in one L2 before they are written back
+    // (XCD x = b % 8 holds the q + (x < r) workgroups b = x, x + 8, ..., with q, r =
+    // G / 8, G % 8 for G workgroups, and takes the range starting at x q + min(x, r):
+    // a bijection of [0, G))
+    const int64_t ng = gridDim.x, bk = blockIdx.x, q = ng / 8, r = ng % 8, xc = bk % 8;
+    const int64_t wb = xc * q + (xc < r ? xc : r) + bk / 8;
+    const int64_t t = wb * BLK + threadIdx.x;
     if (t >= nt) return;
     const gptr<const T> gg = glb(geo) + t * 16;
     T gl[4][3];
