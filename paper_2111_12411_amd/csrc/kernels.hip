@@ -3111,7 +3111,31 @@ __device__ inline DD row_dot_dd(const int64_t *__restrict__ ptr, const int32_t *
 {
 #pragma clang fp contract(off)
     DD a;
-    for (int64_t k = ptr[r] + lane; k < ptr[r + 1]; k += L) {
+    const int64_t e = ptr[r + 1];
+    int64_t k = ptr[r] + lane;
+    // four of the lane's entries at a time: their loads are issued together, and
+    // they are added in the same order as one at a time
+    constexpr int U = 4;
+    for (; k + (U - 1) * L < e; k += U * L) {
+        double v[U], xv[U], xl[U];
+        int32_t j[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            v[u] = val[k + u * L];
+            j[u] = idx[k + u * L];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            xv[u] = x[j[u]];
+            xl[u] = xlo ? xlo[j[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            dd_fma(a, v[u], xv[u]);
+            if (xlo) a.c += v[u] * xl[u];
+        }
+    }
+    for (; k < e; k += L) {
         const double v = val[k];
         const int32_t j = idx[k];
         dd_fma(a, v, x[j]);
