@@ -1246,7 +1246,7 @@ __global__ __launch_bounds__(BLK) void k_counters(const unsigned long long *__re
 {
     __shared__ unsigned long long s_v[NCNT][BLK];
     unsigned long long v[NCNT] = {};
-    for (int b = threadIdx.x; b < nb; b += BLK)
+    for (int b = blockIdx.x * BLK + threadIdx.x; b < nb; b += gridDim.x * BLK)
         for (int k = 0; k < NCNT; k++)
             v[k] = k == CNT_ERR ? (v[k] | cntb[b * NCNT + k]) : v[k] + cntb[b * NCNT + k];
     for (int k = 0; k < NCNT; k++) s_v[k][threadIdx.x] = v[k];
@@ -1258,9 +1258,12 @@ __global__ __launch_bounds__(BLK) void k_counters(const unsigned long long *__re
                                                    : s_v[k][threadIdx.x] + s_v[k][threadIdx.x + h];
         __syncthreads();
     }
+    // integer sums (and the error bits' or): exact in any order, so the
+    // workgroups add theirs atomically
     if (threadIdx.x < NCNT) {
         const int k = threadIdx.x;
-        cnt[k] = k == CNT_ERR ? (cnt[k] | s_v[k][0]) : cnt[k] + s_v[k][0];
+        if (k == CNT_ERR) atomicOr(&cnt[k], s_v[k][0]);
+        else atomicAdd(&cnt[k], s_v[k][0]);
     }
 }
 
@@ -1683,7 +1686,20 @@ __global__ void k_scatter(const int64_t *__restrict__ ptr, const int32_t *__rest
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double s = 0.0;
-    for (int64_t k = ptr[j]; k < ptr[j + 1]; k++) s += P[idx[k]];
+    const int64_t e = ptr[j + 1];
+    int64_t k = ptr[j];
+    // four entries' loads issued together, added in the same order as one at a time
+    for (; k + 3 < e; k += 4) {
+        int32_t i4[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) i4[u] = idx[k + u];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = P[i4[u]];
+#pragma unroll
+        for (int u = 0; u < 4; u++) s += v[u];
+    }
+    for (; k < e; k++) s += P[idx[k]];
     out[j] = s;
 }
 
@@ -2779,7 +2795,8 @@ hipError_t launch_continue(int order, bool mixed, bool boris, const ParticleArgs
             else hipLaunchKernelGGL((k_continue<2, double>), dim3(grid), dim3(BLK), 0, s, A);
         }
     }
-    hipLaunchKernelGGL(k_counters, dim3(1), dim3(BLK), 0, s, cntb, (int)grid, cnt);
+    hipLaunchKernelGGL(k_counters, dim3(std::min<unsigned>(64u, (grid + BLK - 1) / BLK)), dim3(BLK), 0, s, cntb,
+                       (int)grid, cnt);
     return hipGetLastError();
 }
 
